@@ -1,0 +1,174 @@
+"""FP64 CPU oracle for the SSLBM SEIRD step and the BGK comparison step.
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package. The product path (the
+HIP library and its binding in ``paper_2603_19789_amd``) never imports it, and
+the two share no code.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, compiled with gcc without
+FMA contraction). This module only marshals NumPy arrays through ctypes and
+builds the library with gcc when it is missing.
+
+Parameters are passed as any object with attributes ``beta, alpha, gamma, phi``
+(the paper's rates, Sec. II.A), ``d`` (five diffusivities, length^2/time),
+``dx`` and ``dt``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+HERE = Path(__file__).resolve().parent
+SOURCE = HERE / "oracle.c"
+LIBRARY = HERE / "liboracle.so"
+
+PERIODIC = 0
+NOFLUX = 1
+_BC = {"periodic": PERIODIC, "noflux": NOFLUX, PERIODIC: PERIODIC, NOFLUX: NOFLUX}
+
+
+def compile_library(source: Path = SOURCE, output: Path = LIBRARY, defines=()) -> Path:
+    """Compile the oracle with gcc: -O2, IEEE FP64, no FMA contraction, OpenMP."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-o", str(output), str(source), "-lm"]
+    cmd[1:1] = [f"-D{d}" for d in defines]
+    subprocess.run(cmd, check=True)
+    return output
+
+
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    out = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and out.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {out.shape}")
+    return out
+
+
+class Oracle:
+    """ctypes view of one compiled copy of ``oracle.c``."""
+
+    def __init__(self, path: Path | str = LIBRARY):
+        self.path = Path(path)
+        lib = ctypes.CDLL(str(self.path))
+        i, d, ll = ctypes.c_int, ctypes.c_double, ctypes.c_longlong
+        lib.oracle_sslbm_step.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, i]
+        lib.oracle_sslbm_run.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, ll, i]
+        lib.oracle_bgk_init.argtypes = [i, i, _DP, _DP, _DP]
+        lib.oracle_bgk_density.argtypes = [i, i, _DP, _DP, _DP]
+        lib.oracle_bgk_step.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, _DP, _DP, i]
+        lib.oracle_bgk_run.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, _DP, _DP, ll, i]
+        for f in ("oracle_sslbm_step", "oracle_sslbm_run", "oracle_bgk_init",
+                  "oracle_bgk_density", "oracle_bgk_step", "oracle_bgk_run"):
+            getattr(lib, f).restype = ctypes.c_int
+        self.lib = lib
+
+    @staticmethod
+    def _params(p):
+        rates = np.array([p.beta, p.alpha, p.gamma, p.phi], dtype=np.float64)
+        d = _f64(p.d, (5,)).copy()
+        return rates, d, float(p.dx), float(p.dt)
+
+    @staticmethod
+    def _check(rc: int, what: str):
+        if rc != 0:
+            raise ValueError(f"{what}: oracle rejected the arguments (code {rc})")
+
+    # ------------------------------------------------------------- SSLBM --
+    def sslbm_step(self, rho, p, bc="periodic", threads: int = 1) -> np.ndarray:
+        """One step, Eq. (sslbm_final_clean); rho has shape (5, ny, nx)."""
+        rho = _f64(rho)
+        _, ny, nx = rho.shape
+        out = np.empty_like(rho)
+        rates, d, dx, dt = self._params(p)
+        rc = self.lib.oracle_sslbm_step(nx, ny, _BC[bc], _ptr(rates), _ptr(d), dx, dt,
+                                        _ptr(rho), _ptr(out), threads)
+        self._check(rc, "sslbm_step")
+        return out
+
+    def sslbm_run(self, rho, p, nsteps: int, bc="periodic", threads: int = 1) -> np.ndarray:
+        rho = _f64(rho).copy()
+        _, ny, nx = rho.shape
+        work = np.empty_like(rho)
+        rates, d, dx, dt = self._params(p)
+        rc = self.lib.oracle_sslbm_run(nx, ny, _BC[bc], _ptr(rates), _ptr(d), dx, dt,
+                                       _ptr(rho), _ptr(work), int(nsteps), threads)
+        self._check(rc, "sslbm_run")
+        return rho
+
+    # --------------------------------------------------------------- BGK --
+    def bgk_init(self, rho):
+        """Equilibrium populations: returns f (4, 5, ny, nx) and rhoD (ny, nx)."""
+        rho = _f64(rho)
+        _, ny, nx = rho.shape
+        f = np.empty((4, 5, ny, nx))
+        rd = np.empty((ny, nx))
+        self._check(self.lib.oracle_bgk_init(nx, ny, _ptr(rho), _ptr(f), _ptr(rd)), "bgk_init")
+        return f, rd
+
+    def bgk_density(self, f, rhoD) -> np.ndarray:
+        f = _f64(f)
+        ny, nx = f.shape[2:]
+        rhoD = _f64(rhoD, (ny, nx))
+        rho = np.empty((5, ny, nx))
+        self._check(self.lib.oracle_bgk_density(nx, ny, _ptr(f), _ptr(rhoD), _ptr(rho)),
+                    "bgk_density")
+        return rho
+
+    def bgk_step(self, f, rhoD, p, bc="periodic", threads: int = 1):
+        f = _f64(f)
+        ny, nx = f.shape[2:]
+        rhoD = _f64(rhoD, (ny, nx))
+        fo, do = np.empty_like(f), np.empty_like(rhoD)
+        rates, d, dx, dt = self._params(p)
+        rc = self.lib.oracle_bgk_step(nx, ny, _BC[bc], _ptr(rates), _ptr(d), dx, dt, _ptr(f),
+                                      _ptr(rhoD), _ptr(fo), _ptr(do), threads)
+        self._check(rc, "bgk_step")
+        return fo, do
+
+    def bgk_run(self, f, rhoD, p, nsteps: int, bc="periodic", threads: int = 1):
+        f = _f64(f).copy()
+        ny, nx = f.shape[2:]
+        rhoD = _f64(rhoD, (ny, nx)).copy()
+        fw, dw = np.empty_like(f), np.empty_like(rhoD)
+        rates, d, dx, dt = self._params(p)
+        rc = self.lib.oracle_bgk_run(nx, ny, _BC[bc], _ptr(rates), _ptr(d), dx, dt, _ptr(f),
+                                     _ptr(rhoD), _ptr(fw), _ptr(dw), int(nsteps), threads)
+        self._check(rc, "bgk_run")
+        return f, rhoD
+
+    def bgk_run_density(self, rho0, p, nsteps: int, bc="periodic", threads: int = 1):
+        """Equilibrium start from rho0, nsteps BGK steps, densities out."""
+        f, rd = self.bgk_init(rho0)
+        f, rd = self.bgk_run(f, rd, p, nsteps, bc, threads)
+        return self.bgk_density(f, rd)
+
+
+_DEFAULT: Oracle | None = None
+
+
+def load() -> Oracle:
+    """The oracle built from ``oracle.c`` (compiled with gcc only if no build exists)."""
+    global _DEFAULT
+    if _DEFAULT is None:
+        if not LIBRARY.exists():
+            compile_library()
+        _DEFAULT = Oracle(LIBRARY)
+    return _DEFAULT
+
+
+def host_threads() -> int:
+    """Threads the oracle may use on this host (OMP_NUM_THREADS if set)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return os.cpu_count() or 1

@@ -1,0 +1,318 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for the SSLBM SEIRD time step and for the
+ * BGK lattice Boltzmann step it is compared with.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library. The product path (the
+ * HIP library and its Python binding) never calls it, and this file shares no
+ * code, header, table or constant with that path.
+ *
+ * Source: De Rosis, "A distribution-free lattice Boltzmann method for
+ * compartmental reaction-diffusion systems with application to epidemic
+ * modelling" (arXiv 2603.19789).
+ *
+ * Everything here is written for a reader checking it against the paper by
+ * eye: literal formulas, one cell at a time, no blocking, no fusion, no
+ * algebraic simplification. The only liberty is an OpenMP loop over rows,
+ * which does not change any arithmetic (every output cell is computed by
+ * exactly the same expression whatever the thread count).
+ *
+ * Notation (paper, Sec. II.A and Table "Table_params"):
+ *   compartments C = S, E, I, R, D stored as rho[C][y][x], x fastest;
+ *   rates beta (contact), alpha (1/incubation), gamma (removal), phi (fatality
+ *   ratio); diffusivities d[C] in length^2/time; lattice spacing dx, step dt.
+ *
+ * Readings of points the paper leaves open (each one also listed in the
+ * design notes of the repository):
+ *   - the relaxation time follows Eq. (diffusivity) written in lattice units:
+ *     d_lu = d*dt/dx^2 and tau = 1/2 + d_lu/c_s^2;
+ *   - the force of infection is taken as zero where the contact-eligible
+ *     population N_c <= 0 (the paper never divides by an empty cell);
+ *   - no-flux boundary: a neighbour outside the domain takes the value of the
+ *     centre cell (homogeneous Neumann, so the stencil difference across the
+ *     wall is zero); BGK uses half-way bounce-back;
+ *   - the deceased compartment does not diffuse in the paper (Sec. II.A) and
+ *     follows the ODE of Eq. (rhoD), advanced by forward Euler with I at time
+ *     t; if a caller gives D a nonzero diffusivity it is treated as a fifth
+ *     mobile compartment with the SSLBM update;
+ *   - BGK starts from equilibrium populations f_i = w_i rho.
+ *
+ * Parity: pinned by tests (closed forms, invariants, the paper's fourth-order
+ * finite-difference reference, special cases, and planted-mistake tests).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_E_ARG (-1)
+
+#define BC_PERIODIC 0
+#define BC_NOFLUX 1
+
+enum { CS = 0, CE = 1, CI = 2, CR = 3, CD = 4 };
+
+/* D2Q5 lattice, Sec. II.B: link vectors c_i = (c_ix, c_iy) and weights. */
+static const int CX[5] = {0, 1, 0, -1, 0};
+static const int CY[5] = {0, 0, 1, 0, -1};
+static const double W[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+/* direction opposite to i: c_opp(i) = -c_i (used by bounce-back only) */
+static const int OPP[5] = {0, 3, 4, 1, 2};
+/* lattice speed of sound squared, c_s = 1/sqrt(3) (Sec. II.B) */
+static const double CS2 = 1.0 / 3.0;
+
+/* rates[] layout: beta, alpha, gamma, phi */
+typedef struct {
+    double beta, alpha, gamma, phi;
+} seird_rates;
+
+static seird_rates unpack_rates(const double *r)
+{
+    seird_rates k;
+    k.beta = r[0];
+    k.alpha = r[1];
+    k.gamma = r[2];
+    k.phi = r[3];
+    return k;
+}
+
+/* Relaxation time of compartment C from its diffusivity, Eq. (diffusivity):
+ * d = c_s^2 (tau - 1/2) in lattice units, lattice diffusivity d*dt/dx^2. */
+static double relaxation_time(double d, double dx, double dt)
+{
+    double d_lattice = d * dt / (dx * dx);
+    return 0.5 + d_lattice / CS2;
+}
+
+/* Value of one field at lattice node (x, y); (xc, yc) is the centre node of
+ * the stencil being evaluated, used by the no-flux rule. */
+static double node_value(const double *field, int nx, int ny, int bc, int x, int y,
+                         int xc, int yc)
+{
+    if (x < 0 || x >= nx || y < 0 || y >= ny) {
+        if (bc == BC_PERIODIC) {
+            x = ((x % nx) + nx) % nx;
+            y = ((y % ny) + ny) % ny;
+        } else {
+            return field[(size_t)yc * nx + xc];
+        }
+    }
+    return field[(size_t)y * nx + x];
+}
+
+/* SEIRD reaction sources, Eq. (sources) for S, E, I, R and Eq. (rhoD) for D,
+ * all evaluated from the densities of one node at time t. */
+static void seird_sources(const double rho[5], seird_rates k, double psi[5])
+{
+    double S = rho[CS], E = rho[CE], I = rho[CI], R = rho[CR];
+    double Nc = S + E + I + R; /* contact-eligible population (excludes D) */
+    double force = 0.0;
+    if (Nc > 0.0)
+        force = k.beta * S * I / Nc;
+    psi[CS] = -force;
+    psi[CE] = force - k.alpha * E;
+    psi[CI] = k.alpha * E - k.gamma * I;
+    psi[CR] = (1.0 - k.phi) * k.gamma * I;
+    psi[CD] = k.phi * k.gamma * I;
+}
+
+static int valid_grid(int nx, int ny, int bc)
+{
+    return nx >= 1 && ny >= 1 && (bc == BC_PERIODIC || bc == BC_NOFLUX);
+}
+
+/*
+ * One SSLBM step for all five compartments, out of place.
+ * Eq. (sslbm_final_clean) with rho_f, rho_b, rho_c from Eqs. (rhof), (rhob),
+ * (rhoc), for the mobile compartments; Eq. (rhoD) by forward Euler for D when
+ * it does not diffuse.
+ */
+int oracle_sslbm_step(int nx, int ny, int bc, const double *rates, const double *d,
+                      double dx, double dt, const double *in, double *out, int nthreads)
+{
+    if (!valid_grid(nx, ny, bc) || !rates || !d || !in || !out || in == out)
+        return ORACLE_E_ARG;
+    seird_rates k = unpack_rates(rates);
+    double tau[5];
+    for (int c = 0; c < 5; ++c)
+        tau[c] = relaxation_time(d[c], dx, dt);
+    size_t plane = (size_t)nx * ny;
+    if (nthreads <= 0)
+        nthreads = 1;
+
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            size_t cell = (size_t)y * nx + x;
+            double centre[5], psi[5];
+            for (int c = 0; c < 5; ++c)
+                centre[c] = in[c * plane + cell];
+            seird_sources(centre, k, psi);
+
+            for (int c = 0; c < 5; ++c) {
+                const double *field = in + c * plane;
+                if (c == CD && d[CD] == 0.0) {
+                    /* deceased: d rho^D / dt = phi gamma rho^I, Eq. (rhoD) */
+                    out[c * plane + cell] = centre[CD] + psi[CD] * dt;
+                    continue;
+                }
+                double rho_f = 0.0, rho_b = 0.0;
+                for (int i = 0; i < 5; ++i) {
+                    rho_f += W[i] * node_value(field, nx, ny, bc, x + CX[i], y + CY[i], x, y);
+                    rho_b += W[i] * node_value(field, nx, ny, bc, x - CX[i], y - CY[i], x, y);
+                }
+                double rho_c = centre[c];
+                out[c * plane + cell] =
+                    rho_b + (tau[c] - 1.0) * (rho_f - 2.0 * rho_c + rho_b) + psi[c] * dt;
+            }
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* nsteps SSLBM steps; result left in rho, work is a buffer of the same size. */
+int oracle_sslbm_run(int nx, int ny, int bc, const double *rates, const double *d,
+                     double dx, double dt, double *rho, double *work, long long nsteps,
+                     int nthreads)
+{
+    if (!valid_grid(nx, ny, bc) || !rho || !work || rho == work || nsteps < 0)
+        return ORACLE_E_ARG;
+    double *a = rho, *b = work;
+    for (long long n = 0; n < nsteps; ++n) {
+        int rc = oracle_sslbm_step(nx, ny, bc, rates, d, dx, dt, a, b, nthreads);
+        if (rc)
+            return rc;
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != rho)
+        memcpy(rho, a, sizeof(double) * 5 * (size_t)nx * ny);
+    return ORACLE_OK;
+}
+
+/* ---------------------------------------------------------------- BGK --- */
+/* Populations f[C][i][y][x] for the four mobile compartments C = S, E, I, R,
+ * directions i = 0..4; the deceased are carried as a density (Sec. II.B: the
+ * BGK storage holds five populations for four mobile groups plus rho^D). */
+
+static size_t fidx(int c, int i, size_t plane) { return ((size_t)c * 5 + i) * plane; }
+
+/* Equilibrium start, f_i = w_i rho (reading: the paper does not state it). */
+int oracle_bgk_init(int nx, int ny, const double *rho, double *f, double *rhoD)
+{
+    if (nx < 1 || ny < 1 || !rho || !f || !rhoD)
+        return ORACLE_E_ARG;
+    size_t plane = (size_t)nx * ny;
+    for (int c = 0; c < 4; ++c)
+        for (int i = 0; i < 5; ++i)
+            for (size_t p = 0; p < plane; ++p)
+                f[fidx(c, i, plane) + p] = W[i] * rho[c * plane + p];
+    for (size_t p = 0; p < plane; ++p)
+        rhoD[p] = rho[CD * plane + p];
+    return ORACLE_OK;
+}
+
+/* Macroscopic densities rho^C = sum_i f_i^C (Sec. II.B), plus rho^D. */
+int oracle_bgk_density(int nx, int ny, const double *f, const double *rhoD, double *rho)
+{
+    if (nx < 1 || ny < 1 || !rho || !f || !rhoD)
+        return ORACLE_E_ARG;
+    size_t plane = (size_t)nx * ny;
+    for (int c = 0; c < 4; ++c)
+        for (size_t p = 0; p < plane; ++p) {
+            double s = 0.0;
+            for (int i = 0; i < 5; ++i)
+                s += f[fidx(c, i, plane) + p];
+            rho[c * plane + p] = s;
+        }
+    for (size_t p = 0; p < plane; ++p)
+        rho[CD * plane + p] = rhoD[p];
+    return ORACLE_OK;
+}
+
+/*
+ * One BGK step, Eq. (pdf): collide with f^eq = w_i rho and the source w_i Psi dt,
+ * then stream to x + c_i. Periodic wrap or half-way bounce-back. rho^D follows
+ * Eq. (rhoD) by forward Euler. The deceased must not diffuse here.
+ */
+int oracle_bgk_step(int nx, int ny, int bc, const double *rates, const double *d,
+                    double dx, double dt, const double *f_in, const double *rhoD_in,
+                    double *f_out, double *rhoD_out, int nthreads)
+{
+    if (!valid_grid(nx, ny, bc) || !rates || !d || !f_in || !rhoD_in || !f_out ||
+        !rhoD_out || f_in == f_out || rhoD_in == rhoD_out || d[CD] != 0.0)
+        return ORACLE_E_ARG;
+    seird_rates k = unpack_rates(rates);
+    double tau[4];
+    for (int c = 0; c < 4; ++c)
+        tau[c] = relaxation_time(d[c], dx, dt);
+    size_t plane = (size_t)nx * ny;
+    if (nthreads <= 0)
+        nthreads = 1;
+
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            size_t cell = (size_t)y * nx + x;
+            double rho[5], psi[5];
+            for (int c = 0; c < 4; ++c) {
+                double s = 0.0;
+                for (int i = 0; i < 5; ++i)
+                    s += f_in[fidx(c, i, plane) + cell];
+                rho[c] = s;
+            }
+            rho[CD] = rhoD_in[cell];
+            seird_sources(rho, k, psi);
+
+            for (int c = 0; c < 4; ++c) {
+                for (int i = 0; i < 5; ++i) {
+                    double f = f_in[fidx(c, i, plane) + cell];
+                    double feq = W[i] * rho[c];
+                    double fstar = f + (feq - f) / tau[c] + W[i] * psi[c] * dt;
+                    int xd = x + CX[i], yd = y + CY[i];
+                    if (xd < 0 || xd >= nx || yd < 0 || yd >= ny) {
+                        if (bc == BC_PERIODIC) {
+                            xd = (xd + nx) % nx;
+                            yd = (yd + ny) % ny;
+                        } else {
+                            /* half-way bounce-back: returns reversed to this node */
+                            f_out[fidx(c, OPP[i], plane) + cell] = fstar;
+                            continue;
+                        }
+                    }
+                    f_out[fidx(c, i, plane) + (size_t)yd * nx + xd] = fstar;
+                }
+            }
+            rhoD_out[cell] = rho[CD] + psi[CD] * dt;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* nsteps BGK steps; results in f, rhoD; f_work, rhoD_work have the same sizes. */
+int oracle_bgk_run(int nx, int ny, int bc, const double *rates, const double *d, double dx,
+                   double dt, double *f, double *rhoD, double *f_work, double *rhoD_work,
+                   long long nsteps, int nthreads)
+{
+    if (!f || !rhoD || !f_work || !rhoD_work || nsteps < 0)
+        return ORACLE_E_ARG;
+    double *fa = f, *fb = f_work, *da = rhoD, *db = rhoD_work;
+    for (long long n = 0; n < nsteps; ++n) {
+        int rc = oracle_bgk_step(nx, ny, bc, rates, d, dx, dt, fa, da, fb, db, nthreads);
+        if (rc)
+            return rc;
+        double *t = fa;
+        fa = fb;
+        fb = t;
+        t = da;
+        da = db;
+        db = t;
+    }
+    size_t plane = (size_t)nx * ny;
+    if (fa != f) {
+        memcpy(f, fa, sizeof(double) * 20 * plane);
+        memcpy(rhoD, da, sizeof(double) * plane);
+    }
+    return ORACLE_OK;
+}

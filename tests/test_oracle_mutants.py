@@ -1,0 +1,64 @@
+"""Planted mistakes: each one is a plausible slip in the oracle (a dropped term,
+a wrong sign, weight or index), planted in a temporary copy of ``oracle.c``
+on the CPU. The pins must catch every one of them, otherwise they are not
+strong enough to trust the oracle.
+"""
+import pytest
+
+import oracle
+import pins
+
+MUTANTS = {
+    "rest weight": ("W[5] = {1.0 / 3.0, 1.0 / 6.0,", "W[5] = {1.0 / 6.0, 1.0 / 6.0,"),
+    "one link weight": ("1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};", "1.0 / 6.0, 1.0 / 6.0, 1.0 / 3.0};"),
+    "tau without c_s^2": ("return 0.5 + d_lattice / CS2;", "return 0.5 + d_lattice;"),
+    "relaxation factor tau-1/2": ("(tau[c] - 1.0) * (rho_f", "(tau[c] - 0.5) * (rho_f"),
+    "centre weight in the bracket": ("rho_f - 2.0 * rho_c + rho_b", "rho_f - rho_c + rho_b"),
+    "start from centre not rho_b": ("rho_b + (tau[c] - 1.0)", "rho_c + (tau[c] - 1.0)"),
+    "N instead of N_c": ("double Nc = S + E + I + R;", "double Nc = S + E + I + R + rho[CD];"),
+    "no incubation outflow": ("psi[CE] = force - k.alpha * E;", "psi[CE] = force;"),
+    "removal scaled by phi": ("psi[CI] = k.alpha * E - k.gamma * I;",
+                              "psi[CI] = k.alpha * E - k.gamma * k.phi * I;"),
+    "recovery uses phi": ("psi[CR] = (1.0 - k.phi) * k.gamma * I;",
+                          "psi[CR] = k.phi * k.gamma * I;"),
+    "deaths from E": ("psi[CD] = k.phi * k.gamma * I;", "psi[CD] = k.phi * k.gamma * E;"),
+    "force not divided by N_c": ("force = k.beta * S * I / Nc;", "force = k.beta * S * I;"),
+    "force uses E": ("force = k.beta * S * I / Nc;", "force = k.beta * S * E / Nc;"),
+    "no-flux ghost zero": ("return field[(size_t)yc * nx + xc];", "return 0.0;"),
+    "periodic wrap off by one": ("x = ((x % nx) + nx) % nx;", "x = ((x % nx) + nx + 1) % nx;"),
+    "source without dt": ("+ psi[c] * dt;", "+ psi[c];"),
+    "deceased ODE from wrong source": ("centre[CD] + psi[CD] * dt;", "centre[CD] + psi[CI] * dt;"),
+    "wrong link vector": ("CY[5] = {0, 0, 1, 0, -1};", "CY[5] = {0, 0, 1, 0, 1};"),
+    "BGK relaxation times tau": ("f + (feq - f) / tau[c] +", "f + (feq - f) * tau[c] +"),
+    "BGK source without weight": ("+ W[i] * psi[c] * dt;", "+ psi[c] * dt;"),
+    "BGK bounce-back same direction": ("f_out[fidx(c, OPP[i], plane) + cell] = fstar;",
+                                       "f_out[fidx(c, i, plane) + cell] = fstar;"),
+    "BGK density drops a population": ("s += f_in[fidx(c, i, plane) + cell];",
+                                       "s += (i < 4) ? f_in[fidx(c, i, plane) + cell] : 0.0;"),
+    "BGK deceased frozen": ("rhoD_out[cell] = rho[CD] + psi[CD] * dt;",
+                            "rhoD_out[cell] = rho[CD];"),
+    "BGK equilibrium from f": ("double feq = W[i] * rho[c];", "double feq = W[i] * f;"),
+    "BGK opposite table": ("OPP[5] = {0, 3, 4, 1, 2};", "OPP[5] = {0, 4, 3, 2, 1};"),
+}
+
+
+def _caught(orc) -> list:
+    failures = []
+    for check in pins.FAST_SSLBM_CHECKS + pins.FAST_BGK_CHECKS:
+        try:
+            check(orc)
+        except (AssertionError, ValueError, FloatingPointError) as exc:
+            failures.append(f"{check.__name__}: {str(exc)[:80]}")
+    return failures
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    original, mutated = MUTANTS[name]
+    source = oracle.SOURCE.read_text()
+    assert source.count(original) == 1, f"mutation site for '{name}' not unique in oracle.c"
+    src = tmp_path / "oracle_mutant.c"
+    src.write_text(source.replace(original, mutated))
+    lib = oracle.compile_library(src, tmp_path / "liboracle_mutant.so")
+    failures = _caught(oracle.Oracle(lib))
+    assert failures, f"planted mistake '{name}' passed every pin"
