@@ -1,0 +1,240 @@
+"""Throughput of the SSLBM SEIRD step on one MI355X.
+
+Workload: a 4096 x 4096 periodic grid with 64 seeded infected foci (width 2
+cells), R0 swept over {1.5, 3, 5} through beta, lattice diffusivities drawn
+log-uniform in [1e-4, 1e-2], dt = 0.01, SSLBM and BGK side by side in FP32 and
+FP64. One "step" is one time step of the whole grid. The headline number is
+the SSLBM in FP32 at R0 = 3, in giga lattice-node updates per second (GLUPS);
+the other eleven runs are reported under "variants".
+
+Prints one JSON line (rank 0, N = 1 only):
+  value / ms_per_step       headline run, inputs resident in HBM, HIP events on
+                            the launch stream around exactly --steps steps
+  roofline                  dominant kernel (the SSLBM pass kernel): algorithmic
+                            HBM bytes per launch / average launch time vs 8 TB/s
+  cpu_baseline              the FP64 CPU oracle on a bounded sample of the same
+                            workload, on the host cores
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+if str(ROOT) not in sys.path:
+    sys.path.insert(0, str(ROOT))
+
+import numpy as np  # noqa: E402
+
+PEAK_HBM_GBPS = 8000.0
+NX = NY = 4096
+HEADLINE = ("sslbm", "f32", 3.0)
+KERNEL_SOURCES = ["paper_2603_19789_amd/csrc/sslbm_kernels.hip",
+                  "paper_2603_19789_amd/csrc/seird_device.h"]
+TRAFFIC_FILE = ROOT / "profiles" / "sslbm_march_f32_4096_traffic.md"
+
+# algorithmic HBM bytes per node and step at one step per pass
+SSLBM_BYTES = {"f32": 40, "f64": 80}      # 5 fields read + 5 written
+BGK_BYTES = {"f32": 168, "f64": 336}      # 20 populations + rhoD, read + written
+
+
+def parse_args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--only", default="", help="comma list of scheme:dtype:R0 to run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the CPU oracle sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        h.update((ROOT / rel).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the headline kernel, from the committed counter
+    summary, if it was taken on the current kernel source."""
+    if not TRAFFIC_FILE.exists():
+        return None
+    text = TRAFFIC_FILE.read_text()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]{16})", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK):
+    params = inputs.c2_params(r0)
+    rho0 = inputs.c2_state(NX, NY)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    stream = torch.cuda.current_stream()
+    if scheme == "sslbm":
+        solver = Solver(NX, NY, params, dtype=dtype)
+        rho = torch.tensor(rho0, dtype=tdt, device="cuda")
+        scratch = torch.empty_like(rho)
+        solver.run(rho, warmup, scratch)
+        blocking = solver.blocking
+
+        def timed():
+            solver.run(rho, steps, scratch)
+        launches = -(-steps // blocking)
+        if launches % 2 == 1 and steps >= 2:
+            launches += 1
+    else:
+        solver = BGK(NX, NY, params, dtype=dtype)
+        f, rd = solver.init(torch.tensor(rho0, dtype=tdt, device="cuda"))
+        fs, ds = torch.empty_like(f), torch.empty_like(rd)
+        solver.run(f, rd, warmup, fs, ds)
+        blocking = 1
+
+        def timed():
+            solver.run(f, rd, steps, fs, ds)
+        launches = steps
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    timed()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    cells = NX * NY
+    glups = cells * steps / (ms * 1e-3) / 1e9
+    per_step = SSLBM_BYTES[dtype] if scheme == "sslbm" else BGK_BYTES[dtype]
+    bytes_per_launch = per_step * cells if scheme == "sslbm" else per_step * cells
+    out = {
+        "scheme": scheme, "dtype": dtype, "R0": r0, "steps": steps, "ms": ms,
+        "ms_per_step": ms / steps, "glups": glups, "steps_per_pass": blocking,
+        "launches": launches, "avg_launch_ms": ms / launches,
+        "algorithmic_bytes_per_launch": bytes_per_launch,
+        "achieved_gbps": bytes_per_launch / (ms / launches * 1e-3) / 1e9,
+        "effective_gbps": glups * per_step,  # node-updates/s x bytes at one step per pass
+    }
+    if scheme == "sslbm":
+        tot = solver.total(rho)
+        out["total_population"] = sum(tot)
+    del solver
+    return out
+
+
+def copy_probe(torch):
+    """One plain device-to-device copy of 1 GiB, for scaling HBM counters."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def cpu_baseline(inputs, target_seconds: float):
+    """The FP64 CPU oracle on the headline workload: as many whole steps of the
+    4096 x 4096 grid as fit in about target_seconds."""
+    import oracle
+    orc = oracle.load()
+    threads = oracle.host_threads()
+    params = inputs.c2_params(HEADLINE[2])
+    rho = inputs.c2_state(NX, NY)
+    t = time.perf_counter()
+    rho = orc.sslbm_run(rho, params, 1, threads=threads)
+    one = time.perf_counter() - t
+    n = max(1, int(target_seconds / max(one, 1e-6)) - 1)
+    t = time.perf_counter()
+    orc.sslbm_run(rho, params, n, threads=threads)
+    el = time.perf_counter() - t
+    return {
+        "value": NX * NY * n / el / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+        "sample": f"{NX}x{NY} headline workload (R0=3, periodic), {n} FP64 steps, "
+                  f"{el:.1f} s on {threads} host threads",
+    }
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(domain decomposition is a design note, not code). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_19789_amd import BGK, Solver, inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    variants = [(s, d, r) for s in ("sslbm", "bgk") for d in ("f32", "f64")
+                for r in inputs.C2_R0]
+    if args.only:
+        keep = []
+        for item in args.only.split(","):
+            s, d, r = item.split(":")
+            keep.append((s, d, float(r)))
+        variants = [v for v in variants if v in keep]
+    if HEADLINE not in variants:
+        variants.insert(0, HEADLINE)
+    else:
+        variants.remove(HEADLINE)
+        variants.insert(0, HEADLINE)
+
+    results = []
+    for s, d, r in variants:
+        # BGK is 4x the traffic per step: keep its timed work comparable
+        steps = args.steps if s == "sslbm" else max(1, args.steps // 4)
+        warm = args.warmup if s == "sslbm" else max(1, args.warmup // 4)
+        res = run_variant(torch, s, d, r, steps, warm, inputs, Solver, BGK)
+        results.append(res)
+        print(f"# {s} {d} R0={r:g}: {res['glups']:.1f} GLUPS, {res['steps_per_pass']} steps/pass, "
+              f"{res['achieved_gbps']:.0f} GB/s per launch", file=sys.stderr, flush=True)
+    if args.copy_probe:
+        copy_probe(torch)
+
+    head = results[0]
+    traffic = recorded_traffic()
+    roof = {
+        "kernel": "sslbm_march_kernel<float,K>",
+        "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBPS,
+        "achieved": round(head["achieved_gbps"], 1),
+        "frac": round(head["achieved_gbps"] / PEAK_HBM_GBPS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
+        "avg_launch_ms": round(head["avg_launch_ms"], 5),
+        "steps_per_pass": head["steps_per_pass"],
+        "effective_frac": round(head["effective_gbps"] / PEAK_HBM_GBPS, 4),
+    }
+    line = {
+        "metric": "SSLBM GLUPS & %HBM peak", "value": round(head["glups"], 2), "unit": "GLUPS",
+        "n_gpus": 1, "steps": head["steps"], "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sslbm-seird-{NX}x{NY}-64foci", "nx": NX, "ny": NY,
+                   "R0": HEADLINE[2], "bc": "periodic", "dt": 0.01,
+                   "steps_per_pass": head["steps_per_pass"], "parallelism": "single-gpu"},
+        "roofline": roof,
+        "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                     for r in results],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(inputs, args.cpu_seconds)
+        line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

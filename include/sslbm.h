@@ -1,0 +1,172 @@
+/*
+ * sslbm.h -- C ABI of libsslbm.so: the single-step simplified lattice
+ * Boltzmann method (SSLBM) for the spatial SEIRD epidemic model, and the BGK
+ * lattice Boltzmann step it is compared with, on AMD MI355X (gfx950).
+ *
+ * Paper: A. De Rosis, "A distribution-free lattice Boltzmann method for
+ * compartmental reaction-diffusion systems with application to epidemic
+ * modelling", arXiv 2603.19789.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status (sslbm_status); SSLBM_OK is 0.
+ * - Arguments are validated on the host before any HIP call: a rejected call
+ *   enqueues nothing, touches no device memory and works without a GPU.
+ * - Device buffers are plain device pointers allocated and owned by the
+ *   caller (hipMalloc, or torch tensors on the GPU). The library never frees
+ *   them and never keeps them after the call returns.
+ * - Work is enqueued on `hip_stream`, a hipStream_t passed as void* (NULL is
+ *   the default stream). Only sslbm_total waits for the stream.
+ * - A context holds host-side constants only (lattice diffusivities, rates
+ *   times dt, launch shape). It is not thread-safe; distinct contexts are
+ *   independent.
+ *
+ * Data layouts (x fastest, row-major, no padding; element type from dtype)
+ * ------------------------------------------------------------------------
+ * - rho  : [5][ny][nx], compartments in the order S, E, I, R, D.
+ * - f    : [4][5][ny][nx], BGK populations of the mobile compartments
+ *          C = S, E, I, R (outer index), directions i = 0..4 of the D2Q5
+ *          lattice with c_i = (0,0), (1,0), (0,1), (-1,0), (0,-1) (Sec. II.B).
+ * - rhoD : [ny][nx], the deceased density carried next to the BGK populations
+ *          (Sec. II.B storage count).
+ * x + 1 is the next element of a row and y + 1 the next row.
+ */
+#ifndef SSLBM_H
+#define SSLBM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSLBM_OK = 0,
+    SSLBM_E_ARG = -1,         /* null pointer, bad size, negative rate/diffusivity, dx or dt <= 0 */
+    SSLBM_E_UNSTABLE = -2,    /* parameters outside the linear stability region (see sslbm_init) */
+    SSLBM_E_UNSUPPORTED = -3, /* valid request this build does not serve (e.g. BGK with d[4] != 0) */
+    SSLBM_E_ALIAS = -4,       /* input and output buffers overlap */
+    SSLBM_E_HIP = -5,         /* a HIP call or kernel launch failed; see sslbm_last_hip_error */
+    SSLBM_E_NOMEM = -6        /* host allocation of the context failed */
+} sslbm_status;
+
+typedef enum { SSLBM_F32 = 0, SSLBM_F64 = 1 } sslbm_dtype;     /* storage and arithmetic type */
+typedef enum { SSLBM_PERIODIC = 0, SSLBM_NOFLUX = 1 } sslbm_bc;
+
+/*
+ * Model parameters, in the paper's notation (Sec. II.A, Table "Table_params"):
+ *   beta  contact rate, alpha inverse incubation period, gamma removal rate,
+ *   phi   infection fatality ratio (0 <= phi <= 1), all rates per unit time;
+ *   d[C]  diffusivity of S, E, I, R, D in length^2 / time (the paper keeps
+ *         D at rest, d[4] = 0; a nonzero d[4] makes D a fifth mobile
+ *         compartment under the same update);
+ *   dx    lattice spacing, dt time step.
+ * The lattice diffusivity is d_lu = d dt / dx^2 and the relaxation time
+ * tau = 1/2 + 3 d_lu, Eq. (diffusivity) with c_s^2 = 1/3.
+ * Workloads stated with (beta, sigma, gamma, mu) map to alpha = sigma,
+ * gamma_paper = gamma + mu, phi = mu / (gamma + mu).
+ */
+typedef struct {
+    double beta, alpha, gamma, phi;
+    double d[5];
+    double dx, dt;
+} sslbm_params;
+
+typedef struct sslbm_ctx sslbm_ctx;
+
+/*
+ * Create a context for an nx-by-ny grid.
+ * dtype: SSLBM_F32 or SSLBM_F64 (element type of every buffer, and the
+ *        arithmetic precision). bc: SSLBM_PERIODIC or SSLBM_NOFLUX.
+ * Validation (no GPU needed):
+ *   SSLBM_E_ARG      out or p null; nx, ny < 1 or above 1<<20; unknown dtype or
+ *                    bc; any rate or d negative or not finite; phi > 1;
+ *                    dx or dt not > 0.
+ *   SSLBM_E_UNSTABLE some d_lu > 1/4 (the diffusion amplification factor
+ *                    G(k) = 1 - 2 d_lu (2 - cos kx - cos ky) leaves [-1, 1];
+ *                    Sec. II.C.2, stability of the purely diffusive case), or
+ *                    dt |lambda_2| + 8 max(d_lu^E, d_lu^I) > 2, where
+ *                    lambda_2 is the negative eigenvalue of the E-I block at
+ *                    the disease-free equilibrium, Eq. (eigenvalues): the
+ *                    decaying mode of the linearised update would oscillate
+ *                    with growing amplitude.
+ * On success *out owns host memory released by sslbm_destroy.
+ */
+int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_params *p);
+
+/* Replace the parameters (same validation as sslbm_init); grid, dtype and bc stay. */
+int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p);
+
+/*
+ * Blocking depth: the number of time steps sslbm_run advances per pass over
+ * HBM (each pass reads and writes the five fields once). 0 restores the
+ * automatic choice. Allowed range 0..SSLBM_MAX_BLOCKING; results are bit for
+ * bit the same for every depth.
+ */
+#define SSLBM_MAX_BLOCKING 8
+int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass);
+int sslbm_get_blocking(const sslbm_ctx *c);
+
+/*
+ * One SSLBM time step for all five compartments, Eq. (sslbm_final_clean)
+ * with rho_f, rho_b, rho_c of Eqs. (rhof), (rhob), (rhoc) for the mobile
+ * compartments, the sources of Eq. (sources) and forward Euler for D,
+ * Eq. (rhoD); every source term uses the densities at time t of the same node.
+ * On the D2Q5 lattice rho_f and rho_b hold the same five values with the
+ * same weights, so the update is computed as
+ *   rho(t+dt) = rho + d_lu ((rho_N + rho_S) + (rho_E + rho_W) - 4 rho) + Psi dt.
+ * Boundaries: periodic wrap, or no-flux (a neighbour outside the domain takes
+ * the centre value, so nothing crosses the wall; Sec. II.C.2, mass
+ * conservation).
+ * rho_in, rho_out: device, layout rho, must not overlap (SSLBM_E_ALIAS).
+ * The force of infection is zero where S + E + I + R <= 0.
+ */
+int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream);
+
+/*
+ * nsteps SSLBM steps, several per HBM pass (see sslbm_set_blocking). The
+ * result is left in rho; scratch is a device buffer of the same size whose
+ * contents are undefined afterwards. Bit for bit equal to nsteps calls of
+ * sslbm_step. nsteps = 0 leaves rho unchanged. rho and scratch must not overlap.
+ */
+int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream);
+
+/*
+ * BGK comparison scheme, Eq. (pdf) with f^eq = w_i rho, the source w_i Psi dt
+ * and tau from Eq. (diffusivity); collide then stream to x + c_i (periodic
+ * wrap, or half-way bounce-back at no-flux walls). rho^D follows Eq. (rhoD)
+ * by forward Euler. The paper's BGK carries D as a density, so every bgk_*
+ * call returns SSLBM_E_UNSUPPORTED when d[4] != 0.
+ *   bgk_init:    f_i = w_i rho (equilibrium start), rhoD = rho[D].
+ *   bgk_step:    one step, f_in/rhoD_in -> f_out/rhoD_out (no overlap).
+ *   bgk_run:     nsteps steps in place in f/rhoD, using same-size scratch.
+ *   bgk_density: rho[C] = sum_i f_i for S, E, I, R and rho[D] = rhoD.
+ */
+int bgk_init(sslbm_ctx *c, const void *rho, void *f, void *rhoD, void *hip_stream);
+int bgk_step(sslbm_ctx *c, const void *f_in, const void *rhoD_in, void *f_out, void *rhoD_out,
+             void *hip_stream);
+int bgk_run(sslbm_ctx *c, void *f, void *rhoD, void *f_scratch, void *rhoD_scratch,
+            long long nsteps, void *hip_stream);
+int bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho, void *hip_stream);
+
+/*
+ * Total population per compartment, out_totals[C] = sum_x rho[C](x) in FP64,
+ * the quantity conserved by Eq. (mass_conservation) when summed over C.
+ * Deterministic (fixed reduction order). Waits for the stream. The first
+ * call allocates a small device buffer (5 doubles per block) kept by the
+ * context until sslbm_destroy.
+ */
+int sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_stream);
+
+/* Release a context (NULL is allowed). */
+void sslbm_destroy(sslbm_ctx *c);
+
+/* Static description of a status code. */
+const char *sslbm_strerror(int status);
+
+/* hipError_t of the last failed HIP call made for this context (0 if none). */
+int sslbm_last_hip_error(const sslbm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSLBM_H */

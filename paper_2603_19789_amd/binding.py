@@ -1,0 +1,264 @@
+"""ctypes binding of libsslbm.so (argument marshalling only).
+
+Every step of the solver runs in the HIP kernels of ``libsslbm.so``; this
+module checks tensors, passes raw device pointers and the current HIP stream,
+and turns status codes into ``SSLBMError``. There is no other code path: if
+the library is missing, every call raises.
+
+Tensors are torch tensors on the GPU, contiguous, float32 or float64:
+  rho  (5, ny, nx)      densities S, E, I, R, D
+  f    (4, 5, ny, nx)   BGK populations of S, E, I, R over the D2Q5 links
+  rhoD (ny, nx)         deceased density of the BGK state
+Parameters are any object with attributes beta, alpha, gamma, phi, d (5
+values), dx, dt (see ``inputs.Params``).
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+LIBRARY = Path(__file__).resolve().parent / "libsslbm.so"
+HEADER = Path(__file__).resolve().parent.parent / "include" / "sslbm.h"
+
+OK, E_ARG, E_UNSTABLE, E_UNSUPPORTED, E_ALIAS, E_HIP, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
+F32, F64 = 0, 1
+PERIODIC, NOFLUX = 0, 1
+MAX_BLOCKING = 8
+_BC = {"periodic": PERIODIC, "noflux": NOFLUX, PERIODIC: PERIODIC, NOFLUX: NOFLUX}
+
+
+class SSLBMError(RuntimeError):
+    def __init__(self, status: int, what: str, hip_error: int = 0):
+        self.status = status
+        self.hip_error = hip_error
+        msg = f"{what}: {_strerror(status)} (status {status}"
+        msg += f", hipError {hip_error})" if hip_error else ")"
+        super().__init__(msg)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("phi", ctypes.c_double),
+                ("d", ctypes.c_double * 5), ("dx", ctypes.c_double), ("dt", ctypes.c_double)]
+
+    @classmethod
+    def of(cls, p) -> "Params":
+        return cls(float(p.beta), float(p.alpha), float(p.gamma), float(p.phi),
+                   (ctypes.c_double * 5)(*[float(v) for v in p.d]), float(p.dx), float(p.dt))
+
+
+_LIB = None
+
+
+def library() -> ctypes.CDLL:
+    """The loaded libsslbm.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not LIBRARY.exists():
+            raise RuntimeError(
+                f"{LIBRARY} is missing: build it with `python -m paper_2603_19789_amd.build` "
+                "(or __graft_entry__.build()); there is no fallback path")
+        lib = ctypes.CDLL(str(LIBRARY))
+        vp, i, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong
+        pp = ctypes.POINTER(Params)
+        sig = {
+            "sslbm_init": [ctypes.POINTER(vp), i, i, i, i, pp],
+            "sslbm_set_params": [vp, pp],
+            "sslbm_set_blocking": [vp, i],
+            "sslbm_get_blocking": [vp],
+            "sslbm_step": [vp, vp, vp, vp],
+            "sslbm_run": [vp, vp, vp, ll, vp],
+            "bgk_init": [vp, vp, vp, vp, vp],
+            "bgk_step": [vp, vp, vp, vp, vp, vp],
+            "bgk_run": [vp, vp, vp, vp, vp, ll, vp],
+            "bgk_density": [vp, vp, vp, vp, vp],
+            "sslbm_total": [vp, vp, ctypes.POINTER(ctypes.c_double), vp],
+            "sslbm_strerror": [i],
+            "sslbm_last_hip_error": [vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.sslbm_strerror.restype = ctypes.c_char_p
+        lib.sslbm_destroy.argtypes = [vp]
+        lib.sslbm_destroy.restype = None
+        _LIB = lib
+    return _LIB
+
+
+def _strerror(status: int) -> str:
+    try:
+        return library().sslbm_strerror(status).decode()
+    except Exception:  # library unavailable while formatting an error
+        return "error"
+
+
+# --------------------------------------------------------------- tensors --
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class _Context:
+    def __init__(self, nx: int, ny: int, params, dtype, bc):
+        torch = _torch()
+        if dtype in (torch.float32, "f32", "float32", F32):
+            self.dtype, self.code = torch.float32, F32
+        elif dtype in (torch.float64, "f64", "float64", F64):
+            self.dtype, self.code = torch.float64, F64
+        else:
+            raise ValueError(f"unsupported dtype {dtype!r}")
+        if bc not in _BC:
+            raise ValueError(f"unknown boundary condition {bc!r}")
+        self.nx, self.ny, self.bc = int(nx), int(ny), bc
+        self.lib = library()
+        h = ctypes.c_void_p()
+        st = self.lib.sslbm_init(ctypes.byref(h), self.nx, self.ny, self.code, _BC[bc],
+                                 ctypes.byref(Params.of(params)))
+        if st != OK:
+            raise SSLBMError(st, "sslbm_init")
+        self.handle = h
+        self.params = params
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.sslbm_destroy(h)
+            self.handle = None
+
+    def _check(self, st: int, what: str):
+        if st != OK:
+            raise SSLBMError(st, what, self.lib.sslbm_last_hip_error(self.handle))
+
+    def _tensor(self, t, shape, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be on the GPU")
+        if t.dtype != self.dtype:
+            raise ValueError(f"{name} must be {self.dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self, *shape):
+        return _torch().empty(shape, dtype=self.dtype, device="cuda")
+
+    def set_params(self, params):
+        self._check(self.lib.sslbm_set_params(self.handle, ctypes.byref(Params.of(params))),
+                    "sslbm_set_params")
+        self.params = params
+
+
+class Solver(_Context):
+    """SSLBM SEIRD solver on an nx-by-ny grid (HIP kernels, one GPU)."""
+
+    def __init__(self, nx, ny, params, dtype="f64", bc="periodic", blocking: int = 0):
+        super().__init__(nx, ny, params, dtype, bc)
+        if blocking:
+            self.set_blocking(blocking)
+
+    @property
+    def shape(self):
+        return (5, self.ny, self.nx)
+
+    def set_blocking(self, steps_per_pass: int):
+        self._check(self.lib.sslbm_set_blocking(self.handle, int(steps_per_pass)),
+                    "sslbm_set_blocking")
+
+    @property
+    def blocking(self) -> int:
+        return self.lib.sslbm_get_blocking(self.handle)
+
+    def step(self, rho_in, rho_out=None, stream=None):
+        """One time step rho_in -> rho_out (allocated when not given)."""
+        if rho_out is None:
+            rho_out = self.empty(*self.shape)
+        a = self._tensor(rho_in, self.shape, "rho_in")
+        b = self._tensor(rho_out, self.shape, "rho_out")
+        self._check(self.lib.sslbm_step(self.handle, a, b, _stream(stream)), "sslbm_step")
+        return rho_out
+
+    def run(self, rho, nsteps: int, scratch=None, stream=None):
+        """nsteps time steps in place in rho; scratch (same shape) is clobbered."""
+        if scratch is None:
+            scratch = self.empty(*self.shape)
+        a = self._tensor(rho, self.shape, "rho")
+        b = self._tensor(scratch, self.shape, "scratch")
+        self._check(self.lib.sslbm_run(self.handle, a, b, int(nsteps), _stream(stream)),
+                    "sslbm_run")
+        return rho
+
+    def total(self, rho, stream=None):
+        """Per-compartment totals (5 floats, FP64 sums); waits for the stream."""
+        out = (ctypes.c_double * 5)()
+        a = self._tensor(rho, self.shape, "rho")
+        self._check(self.lib.sslbm_total(self.handle, a, out, _stream(stream)), "sslbm_total")
+        return [out[i] for i in range(5)]
+
+
+class BGK(_Context):
+    """BGK lattice Boltzmann comparison scheme on the same grid (HIP kernels)."""
+
+    def __init__(self, nx, ny, params, dtype="f64", bc="periodic"):
+        super().__init__(nx, ny, params, dtype, bc)
+
+    @property
+    def f_shape(self):
+        return (4, 5, self.ny, self.nx)
+
+    def init(self, rho, stream=None):
+        f = self.empty(*self.f_shape)
+        rd = self.empty(self.ny, self.nx)
+        self._check(self.lib.bgk_init(self.handle, self._tensor(rho, (5, self.ny, self.nx), "rho"),
+                                      self._tensor(f, self.f_shape, "f"),
+                                      self._tensor(rd, (self.ny, self.nx), "rhoD"),
+                                      _stream(stream)), "bgk_init")
+        return f, rd
+
+    def step(self, f, rhoD, f_out=None, rhoD_out=None, stream=None):
+        if f_out is None:
+            f_out = self.empty(*self.f_shape)
+        if rhoD_out is None:
+            rhoD_out = self.empty(self.ny, self.nx)
+        plane = (self.ny, self.nx)
+        self._check(self.lib.bgk_step(self.handle, self._tensor(f, self.f_shape, "f"),
+                                      self._tensor(rhoD, plane, "rhoD"),
+                                      self._tensor(f_out, self.f_shape, "f_out"),
+                                      self._tensor(rhoD_out, plane, "rhoD_out"),
+                                      _stream(stream)), "bgk_step")
+        return f_out, rhoD_out
+
+    def run(self, f, rhoD, nsteps: int, f_scratch=None, rhoD_scratch=None, stream=None):
+        if f_scratch is None:
+            f_scratch = self.empty(*self.f_shape)
+        if rhoD_scratch is None:
+            rhoD_scratch = self.empty(self.ny, self.nx)
+        plane = (self.ny, self.nx)
+        self._check(self.lib.bgk_run(self.handle, self._tensor(f, self.f_shape, "f"),
+                                     self._tensor(rhoD, plane, "rhoD"),
+                                     self._tensor(f_scratch, self.f_shape, "f_scratch"),
+                                     self._tensor(rhoD_scratch, plane, "rhoD_scratch"),
+                                     int(nsteps), _stream(stream)), "bgk_run")
+        return f, rhoD
+
+    def density(self, f, rhoD, rho=None, stream=None):
+        if rho is None:
+            rho = self.empty(5, self.ny, self.nx)
+        plane = (self.ny, self.nx)
+        self._check(self.lib.bgk_density(self.handle, self._tensor(f, self.f_shape, "f"),
+                                         self._tensor(rhoD, plane, "rhoD"),
+                                         self._tensor(rho, (5, self.ny, self.nx), "rho"),
+                                         _stream(stream)), "bgk_density")
+        return rho

@@ -1,0 +1,382 @@
+// sslbm_api.cpp -- host side of libsslbm.so: argument validation, derived
+// constants, launch planning and the extern "C" entry points of sslbm.h.
+// Every check runs before the first HIP call, so rejected calls need no GPU.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <new>
+#include <vector>
+
+#include "sslbm.h"
+#include "sslbm_internal.h"
+
+struct sslbm_ctx {
+    int nx = 0, ny = 0, dtype = 0, bc = 0;
+    sslbm_params p{};
+    sslbm::StepCoef coef{};
+    int blocking = 0;       // steps per HBM pass for sslbm_run; 0 = automatic
+    int rows_per_wave = 0;  // 0 = automatic
+    int last_hip = 0;
+    double *partials = nullptr;  // device buffer of sslbm_total
+    int partial_blocks = 0;
+    int partial_device = -1;
+};
+
+namespace {
+
+constexpr int MAX_SIDE = 1 << 20;
+constexpr long long MAX_CELLS = 1ll << 33;
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+// Validation of sslbm_params and the derived per-step constants.
+int derive(const sslbm_params *p, sslbm::StepCoef *k) {
+    if (!p)
+        return SSLBM_E_ARG;
+    if (!finite_nonneg(p->beta) || !finite_nonneg(p->alpha) || !finite_nonneg(p->gamma) ||
+        !finite_nonneg(p->phi) || p->phi > 1.0)
+        return SSLBM_E_ARG;
+    if (!(std::isfinite(p->dx) && p->dx > 0.0) || !(std::isfinite(p->dt) && p->dt > 0.0))
+        return SSLBM_E_ARG;
+    for (int c = 0; c < 5; ++c)
+        if (!finite_nonneg(p->d[c]))
+            return SSLBM_E_ARG;
+
+    sslbm::StepCoef out{};
+    const double scale = p->dt / (p->dx * p->dx);
+    for (int c = 0; c < 5; ++c) {
+        out.dl[c] = p->d[c] * scale;
+        // |G(k)| <= 1 for every k iff 0 <= d_lu <= 1/4 (G = 1 - 2 d_lu (2 - cos kx - cos ky))
+        if (!(out.dl[c] <= 0.25))
+            return SSLBM_E_UNSTABLE;
+    }
+    // Linearisation at the disease-free equilibrium, Eq. (eigenvalues): the
+    // decaying E-I eigenvalue lambda_2 plus the most negative diffusion factor
+    // must stay >= -1, i.e. dt |lambda_2| + 8 max(d_lu^E, d_lu^I) <= 2.
+    const double a = p->alpha, g = p->gamma, b = p->beta;
+    const double lambda2 = 0.5 * (-(a + g) - std::sqrt((a - g) * (a - g) + 4.0 * a * b));
+    const double dmax = out.dl[1] > out.dl[2] ? out.dl[1] : out.dl[2];
+    if (p->dt * std::fabs(lambda2) + 8.0 * dmax > 2.0)
+        return SSLBM_E_UNSTABLE;
+
+    out.bdt = p->beta * p->dt;
+    out.kE = p->alpha * p->dt;
+    out.kI = p->gamma * p->dt;
+    out.kR = (1.0 - p->phi) * p->gamma * p->dt;
+    out.kD = p->phi * p->gamma * p->dt;
+    for (int c = 0; c < 4; ++c)
+        out.omega[c] = 1.0 / (0.5 + 3.0 * out.dl[c]);
+    out.diffuse_d = p->d[4] != 0.0;
+    *k = out;
+    return SSLBM_OK;
+}
+
+size_t elem_size(const sslbm_ctx *c) { return c->dtype == SSLBM_F32 ? 4 : 8; }
+size_t plane_elems(const sslbm_ctx *c) { return (size_t)c->nx * (size_t)c->ny; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+sslbm::GridDesc grid_of(const sslbm_ctx *c) {
+    sslbm::GridDesc g;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.plane = (long long)c->nx * c->ny;
+    g.bc = c->bc;
+    return g;
+}
+
+int hip_status(sslbm_ctx *c, hipError_t e) {
+    if (e == hipSuccess)
+        return SSLBM_OK;
+    c->last_hip = (int)e;
+    return SSLBM_E_HIP;
+}
+
+// Steps per pass when the caller has not fixed it.
+int auto_blocking(const sslbm_ctx *c) { return c->dtype == SSLBM_F32 ? 4 : 4; }
+
+sslbm::MarchShape shape_for(const sslbm_ctx *c, int K) {
+    sslbm::MarchShape s;
+    if (c->rows_per_wave > 0) {
+        s.rows_per_wave = c->rows_per_wave;
+        return s;
+    }
+    // enough wavefronts to fill 256 CUs several times over, chunks no shorter
+    // than 16 rows (the 2K halo rows are recomputed per chunk)
+    const int strips = (c->nx + (64 - 2 * K) - 1) / (64 - 2 * K);
+    long long h = (long long)c->ny * strips / 4096;
+    if (h < 16)
+        h = 16;
+    if (h > 64)
+        h = 64;
+    s.rows_per_wave = (int)h;
+    return s;
+}
+
+// Split nsteps into passes of at most K steps, with an even number of passes
+// whenever nsteps >= 2 so that the ping-pong ends in the caller's buffer.
+std::vector<int> plan_passes(long long nsteps, int K) {
+    std::vector<int> passes;
+    for (long long left = nsteps; left > 0;) {
+        const int k = left >= K ? K : (int)left;
+        passes.push_back(k);
+        left -= k;
+    }
+    if (passes.size() % 2 == 1 && nsteps >= 2) {
+        for (size_t i = 0; i < passes.size(); ++i) {
+            if (passes[i] >= 2) {
+                const int a = passes[i] / 2, b = passes[i] - a;
+                passes[i] = a;
+                passes.insert(passes.begin() + (long)i + 1, b);
+                break;
+            }
+        }
+    }
+    return passes;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_params *p) {
+    if (!out || !p)
+        return SSLBM_E_ARG;
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nx > MAX_SIDE || ny > MAX_SIDE || (long long)nx * ny > MAX_CELLS)
+        return SSLBM_E_ARG;
+    if (dtype != SSLBM_F32 && dtype != SSLBM_F64)
+        return SSLBM_E_ARG;
+    if (bc != SSLBM_PERIODIC && bc != SSLBM_NOFLUX)
+        return SSLBM_E_ARG;
+    sslbm::StepCoef k;
+    const int st = derive(p, &k);
+    if (st != SSLBM_OK)
+        return st;
+    sslbm_ctx *c = new (std::nothrow) sslbm_ctx();
+    if (!c)
+        return SSLBM_E_NOMEM;
+    c->nx = nx;
+    c->ny = ny;
+    c->dtype = dtype;
+    c->bc = bc;
+    c->p = *p;
+    c->coef = k;
+    *out = c;
+    return SSLBM_OK;
+}
+
+int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p) {
+    if (!c)
+        return SSLBM_E_ARG;
+    sslbm::StepCoef k;
+    const int st = derive(p, &k);
+    if (st != SSLBM_OK)
+        return st;
+    c->p = *p;
+    c->coef = k;
+    return SSLBM_OK;
+}
+
+int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass) {
+    if (!c || steps_per_pass < 0 || steps_per_pass > SSLBM_MAX_BLOCKING)
+        return SSLBM_E_ARG;
+    c->blocking = steps_per_pass;
+    return SSLBM_OK;
+}
+
+int sslbm_get_blocking(const sslbm_ctx *c) {
+    if (!c)
+        return SSLBM_E_ARG;
+    return c->blocking > 0 ? c->blocking : auto_blocking(c);
+}
+
+int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream) {
+    if (!c || !rho_in || !rho_out)
+        return SSLBM_E_ARG;
+    const size_t bytes = 5 * plane_elems(c) * elem_size(c);
+    if (overlap(rho_in, bytes, rho_out, bytes))
+        return SSLBM_E_ALIAS;
+    return hip_status(c, sslbm::launch_march(c->dtype, rho_in, rho_out, grid_of(c), c->coef, 1,
+                                             shape_for(c, 1), (hipStream_t)hip_stream));
+}
+
+int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream) {
+    if (!c || !rho || !scratch || nsteps < 0)
+        return SSLBM_E_ARG;
+    const size_t bytes = 5 * plane_elems(c) * elem_size(c);
+    if (overlap(rho, bytes, scratch, bytes))
+        return SSLBM_E_ALIAS;
+    if (nsteps == 0)
+        return SSLBM_OK;
+    const int K = sslbm_get_blocking(c);
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const sslbm::GridDesc g = grid_of(c);
+    void *src = rho, *dst = scratch;
+    for (int k : plan_passes(nsteps, K)) {
+        const int st =
+            hip_status(c, sslbm::launch_march(c->dtype, src, dst, g, c->coef, k, shape_for(c, k), s));
+        if (st != SSLBM_OK)
+            return st;
+        void *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != rho)
+        return hip_status(c, hipMemcpyAsync(rho, src, bytes, hipMemcpyDeviceToDevice, s));
+    return SSLBM_OK;
+}
+
+static int bgk_check(const sslbm_ctx *c) {
+    if (!c)
+        return SSLBM_E_ARG;
+    if (c->p.d[4] != 0.0)
+        return SSLBM_E_UNSUPPORTED;
+    return SSLBM_OK;
+}
+
+int bgk_init(sslbm_ctx *c, const void *rho, void *f, void *rhoD, void *hip_stream) {
+    int st = bgk_check(c);
+    if (st != SSLBM_OK)
+        return st;
+    if (!rho || !f || !rhoD)
+        return SSLBM_E_ARG;
+    const size_t pb = plane_elems(c) * elem_size(c);
+    if (overlap(rho, 5 * pb, f, 20 * pb) || overlap(rho, 5 * pb, rhoD, pb) ||
+        overlap(f, 20 * pb, rhoD, pb))
+        return SSLBM_E_ALIAS;
+    return hip_status(c, sslbm::launch_bgk_init(c->dtype, rho, f, rhoD, grid_of(c),
+                                                (hipStream_t)hip_stream));
+}
+
+int bgk_step(sslbm_ctx *c, const void *f_in, const void *rhoD_in, void *f_out, void *rhoD_out,
+             void *hip_stream) {
+    int st = bgk_check(c);
+    if (st != SSLBM_OK)
+        return st;
+    if (!f_in || !rhoD_in || !f_out || !rhoD_out)
+        return SSLBM_E_ARG;
+    const size_t pb = plane_elems(c) * elem_size(c);
+    const void *ins[2] = {f_in, rhoD_in};
+    const void *outs[2] = {f_out, rhoD_out};
+    const size_t sz[2] = {20 * pb, pb};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (overlap(ins[i], sz[i], outs[j], sz[j]))
+                return SSLBM_E_ALIAS;
+    if (overlap(f_out, 20 * pb, rhoD_out, pb))
+        return SSLBM_E_ALIAS;
+    return hip_status(c, sslbm::launch_bgk_step(c->dtype, f_in, rhoD_in, f_out, rhoD_out,
+                                                grid_of(c), c->coef, (hipStream_t)hip_stream));
+}
+
+int bgk_run(sslbm_ctx *c, void *f, void *rhoD, void *f_scratch, void *rhoD_scratch,
+            long long nsteps, void *hip_stream) {
+    int st = bgk_check(c);
+    if (st != SSLBM_OK)
+        return st;
+    if (!f || !rhoD || !f_scratch || !rhoD_scratch || nsteps < 0)
+        return SSLBM_E_ARG;
+    const size_t pb = plane_elems(c) * elem_size(c);
+    void *bufs[4] = {f, rhoD, f_scratch, rhoD_scratch};
+    const size_t sz[4] = {20 * pb, pb, 20 * pb, pb};
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j)
+            if (overlap(bufs[i], sz[i], bufs[j], sz[j]))
+                return SSLBM_E_ALIAS;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    const sslbm::GridDesc g = grid_of(c);
+    void *fa = f, *da = rhoD, *fb = f_scratch, *db = rhoD_scratch;
+    for (long long n = 0; n < nsteps; ++n) {
+        st = hip_status(c, sslbm::launch_bgk_step(c->dtype, fa, da, fb, db, g, c->coef, s));
+        if (st != SSLBM_OK)
+            return st;
+        void *t = fa;
+        fa = fb;
+        fb = t;
+        t = da;
+        da = db;
+        db = t;
+    }
+    if (fa != f) {
+        st = hip_status(c, hipMemcpyAsync(f, fa, 20 * pb, hipMemcpyDeviceToDevice, s));
+        if (st != SSLBM_OK)
+            return st;
+        return hip_status(c, hipMemcpyAsync(rhoD, da, pb, hipMemcpyDeviceToDevice, s));
+    }
+    return SSLBM_OK;
+}
+
+int bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho, void *hip_stream) {
+    int st = bgk_check(c);
+    if (st != SSLBM_OK)
+        return st;
+    if (!f || !rhoD || !rho)
+        return SSLBM_E_ARG;
+    const size_t pb = plane_elems(c) * elem_size(c);
+    if (overlap(rho, 5 * pb, f, 20 * pb) || overlap(rho, 5 * pb, rhoD, pb))
+        return SSLBM_E_ALIAS;
+    return hip_status(c, sslbm::launch_bgk_density(c->dtype, f, rhoD, rho, grid_of(c),
+                                                   (hipStream_t)hip_stream));
+}
+
+int sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_stream) {
+    if (!c || !rho || !out_totals)
+        return SSLBM_E_ARG;
+    const sslbm::GridDesc g = grid_of(c);
+    const int blocks = sslbm::total_blocks(g);
+    int dev = 0;
+    int st = hip_status(c, hipGetDevice(&dev));
+    if (st != SSLBM_OK)
+        return st;
+    if (!c->partials || c->partial_blocks < blocks || c->partial_device != dev) {
+        if (c->partials)
+            (void)hipFree(c->partials);
+        c->partials = nullptr;
+        st = hip_status(c, hipMalloc((void **)&c->partials, sizeof(double) * (5 * blocks + 5)));
+        if (st != SSLBM_OK)
+            return st;
+        c->partial_blocks = blocks;
+        c->partial_device = dev;
+    }
+    const hipStream_t s = (hipStream_t)hip_stream;
+    double *out_dev = c->partials + 5 * c->partial_blocks;
+    st = hip_status(c, sslbm::launch_total(c->dtype, rho, g, c->partials, blocks, out_dev, s));
+    if (st != SSLBM_OK)
+        return st;
+    st = hip_status(c, hipMemcpyAsync(out_totals, out_dev, 5 * sizeof(double),
+                                      hipMemcpyDeviceToHost, s));
+    if (st != SSLBM_OK)
+        return st;
+    return hip_status(c, hipStreamSynchronize(s));
+}
+
+void sslbm_destroy(sslbm_ctx *c) {
+    if (!c)
+        return;
+    if (c->partials)
+        (void)hipFree(c->partials);
+    delete c;
+}
+
+const char *sslbm_strerror(int status) {
+    switch (status) {
+    case SSLBM_OK: return "success";
+    case SSLBM_E_ARG: return "invalid argument";
+    case SSLBM_E_UNSTABLE: return "parameters outside the linear stability region";
+    case SSLBM_E_UNSUPPORTED: return "unsupported request";
+    case SSLBM_E_ALIAS: return "input and output buffers overlap";
+    case SSLBM_E_HIP: return "HIP runtime error";
+    case SSLBM_E_NOMEM: return "out of host memory";
+    default: return "unknown status";
+    }
+}
+
+int sslbm_last_hip_error(const sslbm_ctx *c) { return c ? c->last_hip : 0; }
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// sslbm_internal.h -- declarations shared by the host API and the kernel
+// translation units of libsslbm.so (not installed, not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "sslbm.h"
+
+namespace sslbm {
+
+// Grid description passed by value to every kernel.
+struct GridDesc {
+    int nx, ny;
+    long long plane;  // nx * ny
+    int bc;           // SSLBM_PERIODIC or SSLBM_NOFLUX
+};
+
+// Per-step constants, derived once on the host in FP64 and rounded to the
+// arithmetic type at launch:
+//   dl[C] = d[C] dt / dx^2 (lattice diffusivity, tau = 1/2 + 3 dl),
+//   bdt = beta dt, kE = alpha dt, kI = gamma dt,
+//   kR = (1 - phi) gamma dt, kD = phi gamma dt   (Eq. sources, Eq. rhoD),
+//   omega[C] = 1 / tau[C] (BGK collision frequency).
+struct StepCoef {
+    double dl[5];
+    double bdt, kE, kI, kR, kD;
+    double omega[4];
+    bool diffuse_d;  // d[4] != 0
+};
+
+// Launch shape of the y-marching kernel.
+struct MarchShape {
+    int rows_per_wave;  // H: output rows each wavefront produces
+};
+
+// ---- launchers (sslbm_kernels.hip) --------------------------------------
+// K steps in one pass: in -> out (no overlap). K in 1..SSLBM_MAX_BLOCKING.
+hipError_t launch_march(int dtype, const void *in, void *out, const GridDesc &g,
+                        const StepCoef &k, int K, const MarchShape &shape, hipStream_t s);
+
+// ---- launchers (bgk_kernels.hip) ----------------------------------------
+hipError_t launch_bgk_init(int dtype, const void *rho, void *f, void *rhoD, const GridDesc &g,
+                           hipStream_t s);
+hipError_t launch_bgk_step(int dtype, const void *f_in, const void *rhoD_in, void *f_out,
+                           void *rhoD_out, const GridDesc &g, const StepCoef &k, hipStream_t s);
+hipError_t launch_bgk_density(int dtype, const void *f, const void *rhoD, void *rho,
+                              const GridDesc &g, hipStream_t s);
+
+// ---- launchers (reduce_kernels.hip) -------------------------------------
+// Number of partial blocks the total reduction uses (partials: blocks x 5 doubles).
+int total_blocks(const GridDesc &g);
+hipError_t launch_total(int dtype, const void *rho, const GridDesc &g, double *partials,
+                        int blocks, double *out5_device, hipStream_t s);
+
+}  // namespace sslbm

@@ -1,0 +1,164 @@
+"""The C-ABI library on the CPU: it loads, exports what include/sslbm.h
+declares, and rejects bad arguments on the host before any HIP call."""
+import ctypes
+import math
+import re
+
+import pytest
+
+from paper_2603_19789_amd import binding
+from paper_2603_19789_amd.binding import Params
+from paper_2603_19789_amd.inputs import c1_params
+
+SIG_RE = re.compile(r"^\s*(?:int|void|const\s+char\s*\*)\s*\**\s*(\w+)\s*\(", re.M)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return binding.library()
+
+
+def declared_functions():
+    text = binding.HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(SIG_RE.findall(text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ("sslbm_init", "sslbm_step", "sslbm_run", "bgk_step", "bgk_init",
+                     "bgk_run", "bgk_density", "sslbm_total", "sslbm_destroy",
+                     "sslbm_set_params", "sslbm_set_blocking", "sslbm_get_blocking",
+                     "sslbm_strerror", "sslbm_last_hip_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _init(lib, nx=8, ny=8, dtype=binding.F64, bc=binding.PERIODIC, p=None):
+    h = ctypes.c_void_p()
+    params = Params.of(p if p is not None else c1_params())
+    st = lib.sslbm_init(ctypes.byref(h), nx, ny, dtype, bc, ctypes.byref(params))
+    return st, h
+
+
+def test_valid_init_and_destroy(lib):
+    st, h = _init(lib)
+    assert st == binding.OK and h.value
+    assert lib.sslbm_get_blocking(h) >= 1
+    assert lib.sslbm_last_hip_error(h) == 0
+    lib.sslbm_destroy(h)
+    lib.sslbm_destroy(None)
+
+
+@pytest.mark.parametrize("nx,ny,dtype,bc", [
+    (0, 8, binding.F64, binding.PERIODIC), (8, -1, binding.F64, binding.PERIODIC),
+    ((1 << 20) + 1, 8, binding.F64, binding.PERIODIC), (8, 8, 2, binding.PERIODIC),
+    (8, 8, binding.F32, 7),
+])
+def test_init_rejects_bad_grid(lib, nx, ny, dtype, bc):
+    st, h = _init(lib, nx, ny, dtype, bc)
+    assert st == binding.E_ARG and not h.value
+
+
+def test_init_rejects_null(lib):
+    h = ctypes.c_void_p()
+    assert lib.sslbm_init(ctypes.byref(h), 8, 8, 0, 0, None) == binding.E_ARG
+    assert lib.sslbm_init(None, 8, 8, 0, 0, ctypes.byref(Params.of(c1_params()))) == binding.E_ARG
+
+
+@pytest.mark.parametrize("change", [
+    dict(beta=-0.1), dict(alpha=math.nan), dict(gamma=math.inf), dict(phi=1.5), dict(phi=-0.1),
+    dict(dx=0.0), dict(dt=-0.01), dict(dt=math.nan), dict(d=(0.1, -1e-3, 0.1, 0.1, 0.0)),
+    dict(d=(0.1, 0.1, math.nan, 0.1, 0.0)),
+])
+def test_init_rejects_bad_parameters(lib, change):
+    st, _ = _init(lib, p=c1_params().with_(**change))
+    assert st == binding.E_ARG
+
+
+def test_diffusion_stability_limit(lib):
+    """d_lu = d dt / dx^2 must stay in [0, 1/4]."""
+    p = c1_params()
+    ok = p.with_(d=(25.0, 0.0, 0.0, 0.0, 0.0))          # d_lu = 0.25
+    bad = p.with_(d=(25.01, 0.0, 0.0, 0.0, 0.0))        # d_lu > 0.25
+    assert _init(lib, p=ok)[0] == binding.OK
+    assert _init(lib, p=bad)[0] == binding.E_UNSTABLE
+
+
+def test_reaction_stability_limit(lib):
+    """dt |lambda_2| + 8 max(d_lu^E, d_lu^I) <= 2, lambda_2 from Eq. (eigenvalues)."""
+    p = c1_params().with_(d=(0.0,) * 5)
+    a, g, b = p.alpha, p.gamma, p.beta
+    lam2 = abs(0.5 * (-(a + g) - math.sqrt((a - g) ** 2 + 4 * a * b)))
+    assert _init(lib, p=p.with_(dt=1.99 / lam2))[0] == binding.OK
+    assert _init(lib, p=p.with_(dt=2.01 / lam2))[0] == binding.E_UNSTABLE
+    # with diffusion of E the margin shrinks by 8 d_lu
+    dt = 1.0 / lam2
+    d_e = 0.13 / dt  # d_lu^E = 0.13 -> 1 + 1.04 > 2
+    assert _init(lib, p=p.with_(dt=dt, d=(0.0, d_e, 0.0, 0.0, 0.0)))[0] == binding.E_UNSTABLE
+
+
+def test_aliasing_and_argument_errors_before_any_gpu_call(lib):
+    st, h = _init(lib, 16, 8)
+    assert st == binding.OK
+    nbytes = 5 * 16 * 8 * 8
+    a = ctypes.c_void_p(0x100000)
+    b = ctypes.c_void_p(0x100000 + nbytes - 8)       # overlaps a
+    c = ctypes.c_void_p(0x100000 + nbytes)           # adjacent, no overlap
+    assert lib.sslbm_step(h, a, b, None) == binding.E_ALIAS
+    assert lib.sslbm_step(h, a, None, None) == binding.E_ARG
+    assert lib.sslbm_run(h, a, b, 5, None) == binding.E_ALIAS
+    assert lib.sslbm_run(h, a, c, -1, None) == binding.E_ARG
+    assert lib.sslbm_run(h, a, c, 0, None) == binding.OK   # nothing to do, no HIP call
+    out = (ctypes.c_double * 5)()
+    assert lib.sslbm_total(h, None, out, None) == binding.E_ARG
+    assert lib.sslbm_set_blocking(h, -1) == binding.E_ARG
+    assert lib.sslbm_set_blocking(h, binding.MAX_BLOCKING + 1) == binding.E_ARG
+    assert lib.sslbm_set_blocking(h, 3) == binding.OK
+    assert lib.sslbm_get_blocking(h) == 3
+    assert lib.sslbm_set_blocking(h, 0) == binding.OK
+    lib.sslbm_destroy(h)
+
+
+def test_bgk_rejects_diffusing_deceased(lib):
+    p = c1_params().with_(d=(0.1, 0.1, 0.1, 0.1, 0.1))
+    st, h = _init(lib, p=p)
+    assert st == binding.OK  # the SSLBM supports a diffusing D
+    a, b = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x900000)
+    assert lib.bgk_step(h, a, b, a, b, None) == binding.E_UNSUPPORTED
+    assert lib.bgk_init(h, a, b, a, None) == binding.E_UNSUPPORTED
+    lib.sslbm_destroy(h)
+
+
+def test_bgk_aliasing(lib):
+    st, h = _init(lib, 8, 8)
+    pb = 8 * 8 * 8
+    f_in, d_in = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x100000 + 20 * pb)
+    f_out = ctypes.c_void_p(0x100000 + 10 * pb)  # overlaps f_in
+    d_out = ctypes.c_void_p(0x900000)
+    assert lib.bgk_step(h, f_in, d_in, f_out, d_out, None) == binding.E_ALIAS
+    assert lib.bgk_run(h, f_in, d_in, f_out, d_out, 3, None) == binding.E_ALIAS
+    lib.sslbm_destroy(h)
+
+
+def test_set_params_revalidates(lib):
+    st, h = _init(lib)
+    assert lib.sslbm_set_params(h, ctypes.byref(Params.of(c1_params().with_(beta=-1.0)))) \
+        == binding.E_ARG
+    assert lib.sslbm_set_params(h, ctypes.byref(Params.of(c1_params()))) == binding.OK
+    lib.sslbm_destroy(h)
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6, 42):
+        assert lib.sslbm_strerror(code)
+
+
+def test_python_solver_raises_on_bad_parameters():
+    with pytest.raises(binding.SSLBMError) as exc:
+        binding.Solver(8, 8, c1_params().with_(d=(100.0,) * 5))
+    assert exc.value.status == binding.E_UNSTABLE

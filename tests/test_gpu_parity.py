@@ -1,0 +1,224 @@
+"""HIP path against the FP64 CPU oracle, element by element, through the C ABI.
+
+Tolerances (relative L2 per compartment): FP64 1e-12, FP32 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import TOL, max_rel_l2, sample_nodes, to_gpu, to_np, windowed_oracle
+from paper_2603_19789_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2603_19789_amd import BGK, Solver  # noqa: E402
+
+RATES = inputs.c1_params()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def params_for(d_lattice=(0.03, 0.015, 0.005, 0.02, 0.0)):
+    return RATES.with_(d=inputs.lattice_to_physical(d_lattice, RATES.dx, RATES.dt))
+
+
+def test_c1_fp64_1000_steps(orc):
+    """128x128 periodic, 1000 steps, one Gaussian focus: FP64 within 1e-12."""
+    w = inputs.c1_workload()
+    s = Solver(w.nx, w.ny, w.params, dtype="f64")
+    rho = to_gpu(w.rho0, "f64")
+    s.run(rho, w.nsteps)
+    want = orc.sslbm_run(w.rho0, w.params, w.nsteps, threads=oracle.host_threads())
+    err = max_rel_l2(to_np(rho), want)
+    print(f"C1 f64 err {err:.3e}")
+    assert err <= TOL["f64"]
+
+
+def test_c1_fp32_1000_steps(orc):
+    w = inputs.c1_workload()
+    s = Solver(w.nx, w.ny, w.params, dtype="f32")
+    rho = to_gpu(w.rho0, "f32")
+    s.run(rho, w.nsteps)
+    want = orc.sslbm_run(w.rho0, w.params, w.nsteps, threads=oracle.host_threads())
+    err = max_rel_l2(to_np(rho), want)
+    print(f"C1 f32 err {err:.3e}")
+    assert err <= TOL["f32"]
+
+
+SHAPES = [(1, 1), (2, 3), (3, 3), (5, 2), (17, 9), (63, 65), (64, 64), (130, 71), (201, 129)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_random_state_shapes(orc, nx, ny, bc, dtype):
+    """Ragged and tiny grids, both walls, single steps and blocked runs."""
+    p = params_for()
+    rho0 = inputs.random_state(nx, ny, seed=nx * 1000 + ny)
+    s = Solver(nx, ny, p, dtype=dtype, bc=bc)
+    one = to_np(s.step(to_gpu(rho0, dtype)))
+    assert max_rel_l2(one, orc.sslbm_step(rho0, p, bc=bc)) <= TOL[dtype]
+    rho = to_gpu(rho0, dtype)
+    s.run(rho, 13)
+    assert max_rel_l2(to_np(rho), orc.sslbm_run(rho0, p, 13, bc=bc)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+def test_diffusing_deceased(orc, dtype, bc):
+    """d[4] != 0 makes D a fifth mobile compartment."""
+    p = params_for((0.03, 0.015, 0.005, 0.02, 0.04))
+    rho0 = inputs.random_state(77, 41, seed=5)
+    s = Solver(77, 41, p, dtype=dtype, bc=bc)
+    rho = to_gpu(rho0, dtype)
+    s.run(rho, 20)
+    assert max_rel_l2(to_np(rho), orc.sslbm_run(rho0, p, 20, bc=bc)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+def test_blocking_depth_is_bitwise_invisible(dtype, bc):
+    """K steps per pass give the same bits as K single steps, for every K."""
+    nx, ny = 131, 77
+    p = params_for()
+    rho0 = to_gpu(inputs.random_state(nx, ny, seed=9), dtype)
+    s = Solver(nx, ny, p, dtype=dtype, bc=bc)
+    ref_t = rho0.clone()
+    tmp = torch.empty_like(ref_t)
+    for _ in range(17):
+        s.step(ref_t, tmp)
+        ref_t, tmp = tmp, ref_t
+    for K in range(1, 9):
+        s.set_blocking(K)
+        rho = rho0.clone()
+        s.run(rho, 17)
+        assert torch.equal(rho, ref_t), f"K={K}"
+
+
+def test_run_is_resumable_bitwise():
+    """run(a) then run(b) equals run(a + b), bit for bit."""
+    p = params_for()
+    s = Solver(96, 80, p, dtype="f32")
+    rho0 = to_gpu(inputs.random_state(96, 80, seed=2), "f32")
+    a = rho0.clone()
+    s.run(a, 11)
+    s.run(a, 30)
+    b = rho0.clone()
+    s.run(b, 41)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_translation_and_symmetry_bitwise(dtype):
+    """Periodic grid: shifting the start shifts the result exactly; transposing
+    or mirroring a square grid transposes or mirrors the result exactly."""
+    n = 72
+    p = params_for()
+    rho0 = inputs.random_state(n, n, seed=4)
+    s = Solver(n, n, p, dtype=dtype)
+
+    def run(a):
+        t = to_gpu(a, dtype)
+        s.run(t, 9)
+        return t.cpu()
+
+    base = run(rho0)
+    shifted = run(np.roll(rho0, (5, -7), axis=(1, 2)))
+    assert torch.equal(shifted, torch.roll(base, (5, -7), dims=(1, 2)))
+    transposed = run(np.ascontiguousarray(np.transpose(rho0, (0, 2, 1))))
+    assert torch.equal(transposed, base.transpose(1, 2))
+    mirrored = run(np.ascontiguousarray(rho0[:, :, ::-1]))
+    assert torch.equal(mirrored, torch.flip(base, dims=(2,)))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+def test_totals_and_conservation(orc, dtype, bc):
+    p = params_for()
+    rho0 = inputs.random_state(150, 97, seed=8)
+    s = Solver(150, 97, p, dtype=dtype, bc=bc)
+    rho = to_gpu(rho0, dtype)
+    t0 = s.total(rho)
+    assert np.allclose(t0, rho0.reshape(5, -1).sum(axis=1), rtol=1e-12 if dtype == "f64" else 1e-6)
+    s.run(rho, 200)
+    t1 = s.total(rho)
+    want = orc.sslbm_run(rho0, p, 200, bc=bc).reshape(5, -1).sum(axis=1)
+    assert np.allclose(t1, want, rtol=1e-11 if dtype == "f64" else 1e-5)
+    drift = abs(sum(t1) - sum(t0)) / sum(t0)
+    assert drift < (1e-13 if dtype == "f64" else 1e-5)
+    assert s.total(rho) == t1  # deterministic
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (3, 2), (33, 17), (300, 7)])
+def test_bgk_against_oracle(orc, nx, ny, bc, dtype):
+    p = params_for()
+    rho0 = inputs.random_state(nx, ny, seed=3 * nx + ny)
+    b = BGK(nx, ny, p, dtype=dtype, bc=bc)
+    f, rd = b.init(to_gpu(rho0, dtype))
+    fo, do = orc.bgk_init(rho0)
+    assert max_rel_l2(to_np(f).reshape(20, ny, nx), fo.reshape(20, ny, nx)) <= TOL[dtype]
+    f1, d1 = b.step(f, rd)
+    fo1, do1 = orc.bgk_step(fo, do, p, bc=bc)
+    assert max_rel_l2(to_np(f1).reshape(20, ny, nx), fo1.reshape(20, ny, nx)) <= TOL[dtype]
+    assert max_rel_l2(to_np(d1)[None], do1[None]) <= TOL[dtype]
+    b.run(f, rd, 15)
+    got = to_np(b.density(f, rd))
+    assert max_rel_l2(got, orc.bgk_run_density(rho0, p, 15, bc=bc)) <= TOL[dtype]
+
+
+def test_bgk_c1_1000_steps(orc):
+    w = inputs.c1_workload()
+    b = BGK(w.nx, w.ny, w.params, dtype="f64")
+    f, rd = b.init(to_gpu(w.rho0, "f64"))
+    b.run(f, rd, w.nsteps)
+    want = orc.bgk_run_density(w.rho0, w.params, w.nsteps, threads=oracle.host_threads())
+    assert max_rel_l2(to_np(b.density(f, rd)), want) <= TOL["f64"]
+
+
+def test_errors_surface_as_exceptions():
+    from paper_2603_19789_amd.binding import SSLBMError
+    s = Solver(8, 8, params_for(), dtype="f64")
+    a = to_gpu(inputs.random_state(8, 8, 1), "f64")
+    with pytest.raises(SSLBMError):
+        s.step(a, a)          # aliasing
+    with pytest.raises(ValueError):
+        s.step(a.float())     # wrong dtype
+    with pytest.raises(ValueError):
+        s.step(a[:, :, :4])   # wrong shape
+
+
+# --------------------------------------------------- full-size workload ---
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+def test_full_size_4096_sampled(orc, dtype, bc):
+    """4096x4096, 64 foci, R0 = 5, launched as the benchmark launches it
+    (sslbm_run, automatic blocking): sampled nodes against the oracle run on
+    each node's dependence cone, plus conservation of the whole grid."""
+    nsteps = 24
+    w = inputs.c2_workload(r0=5.0, nsteps=nsteps)
+    rho0 = w.rho0.copy()
+    # make the early dynamics visible: every cell gets some exposed/infected
+    rng = np.random.default_rng(12)
+    rho0[1] = rng.uniform(0, 0.02, size=rho0[1].shape)
+    rho0[0] = 1.0 - rho0[1] - rho0[2]
+    s = Solver(w.nx, w.ny, w.params, dtype=dtype, bc=bc)
+    rho = to_gpu(rho0, dtype)
+    t0 = sum(s.total(rho))
+    s.run(rho, nsteps)
+    torch.cuda.synchronize()
+    nodes = sample_nodes(w.nx, w.ny, 120, seed=3)
+    want = windowed_oracle(orc, rho0, w.params, nsteps, bc, nodes)
+    xs = torch.tensor([x for x, _ in nodes], device="cuda")
+    ys = torch.tensor([y for _, y in nodes], device="cuda")
+    got = rho[:, ys, xs].T.cpu().double().numpy()
+    err = np.linalg.norm(got - want, axis=0) / np.linalg.norm(want, axis=0)
+    assert np.all(err <= TOL[dtype]), err
+    drift = abs(sum(s.total(rho)) - t0) / t0
+    assert drift < (1e-12 if dtype == "f64" else 1e-5)
