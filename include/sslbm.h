@@ -99,11 +99,29 @@ int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p);
  * Blocking depth: the number of time steps sslbm_run advances per pass over
  * HBM (each pass reads and writes the five fields once). 0 restores the
  * automatic choice. Allowed range 0..SSLBM_MAX_BLOCKING; results are bit for
- * bit the same for every depth.
+ * bit the same for every depth. Shorthand for the steps_per_pass field of
+ * sslbm_set_launch below.
  */
 #define SSLBM_MAX_BLOCKING 8
 int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass);
 int sslbm_get_blocking(const sslbm_ctx *c);
+
+/*
+ * Launch shape of the pass kernel used by sslbm_run (sslbm_step always takes
+ * one step per pass). Each wavefront owns a strip of 64 - 2 * steps_per_pass
+ * output columns and marches down rows_per_wave output rows. Zero in a field
+ * selects the automatic value. Shapes change speed only, never results (bit
+ * for bit). Valid: steps_per_pass 0..SSLBM_MAX_BLOCKING, rows_per_wave
+ * 0..65536. A depth whose register footprint does not fit one wavefront
+ * (above 6 in FP64) returns SSLBM_E_UNSUPPORTED.
+ * sslbm_get_launch reports the shape sslbm_run uses (automatic fields resolved).
+ */
+typedef struct {
+    int steps_per_pass;
+    int rows_per_wave;
+} sslbm_launch;
+int sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape);
+int sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape);
 
 /*
  * One SSLBM time step for all five compartments, Eq. (sslbm_final_clean)

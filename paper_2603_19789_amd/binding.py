@@ -47,6 +47,14 @@ class Params(ctypes.Structure):
                    (ctypes.c_double * 5)(*[float(v) for v in p.d]), float(p.dx), float(p.dt))
 
 
+class Launch(ctypes.Structure):
+    """Pass shape (zero = automatic): steps per HBM pass, output rows per wavefront."""
+    _fields_ = [("steps_per_pass", ctypes.c_int), ("rows_per_wave", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _LIB = None
 
 
@@ -66,6 +74,8 @@ def library() -> ctypes.CDLL:
             "sslbm_set_params": [vp, pp],
             "sslbm_set_blocking": [vp, i],
             "sslbm_get_blocking": [vp],
+            "sslbm_set_launch": [vp, ctypes.POINTER(Launch)],
+            "sslbm_get_launch": [vp, ctypes.POINTER(Launch)],
             "sslbm_step": [vp, vp, vp, vp],
             "sslbm_run": [vp, vp, vp, ll, vp],
             "bgk_init": [vp, vp, vp, vp, vp],
@@ -180,6 +190,19 @@ class Solver(_Context):
     @property
     def blocking(self) -> int:
         return self.lib.sslbm_get_blocking(self.handle)
+
+    def set_launch(self, steps_per_pass=0, rows_per_wave=0):
+        """Pass shape (0 = automatic); changes speed, never results."""
+        shape = Launch(int(steps_per_pass), int(rows_per_wave))
+        self._check(self.lib.sslbm_set_launch(self.handle, ctypes.byref(shape)),
+                    "sslbm_set_launch")
+
+    def launch(self) -> dict:
+        """The pass shape sslbm_run uses, automatic fields resolved."""
+        shape = Launch()
+        self._check(self.lib.sslbm_get_launch(self.handle, ctypes.byref(shape)),
+                    "sslbm_get_launch")
+        return shape.as_dict()
 
     def step(self, rho_in, rho_out=None, stream=None):
         """One time step rho_in -> rho_out (allocated when not given)."""

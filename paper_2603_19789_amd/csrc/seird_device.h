@@ -16,6 +16,14 @@ struct Coef {
 };
 
 // ---------------------------------------------------------------------------
+// a / b. FP64 divides with IEEE rounding; FP32 multiplies by the hardware
+// reciprocal (v_rcp_f32, within 1 ulp), which is far inside the FP32
+// tolerance and a fifth of the cost of the rounded division.
+__device__ __forceinline__ float quotient(float a, float b) {
+    return a * __builtin_amdgcn_rcpf(b);
+}
+__device__ __forceinline__ double quotient(double a, double b) { return a / b; }
+
 // SEIRD source increments Psi^C dt of one node, Eq. (sources) and Eq. (rhoD),
 // from the node's densities at time t. The force of infection is zero where
 // the contact-eligible population S + E + I + R is not positive.
@@ -23,7 +31,7 @@ template <typename T>
 __device__ __forceinline__ void seird_increments(T S, T E, T I, T R, const Coef<T> &k, T &fdt,
                                                  T &rE, T &rI) {
     const T nc = (S + E) + (I + R);
-    const T q = (k.bdt * S) * I / nc;
+    const T q = quotient((k.bdt * S) * I, nc);
     fdt = nc > T(0) ? q : T(0);
     rE = k.kE * E;
     rI = k.kI * I;
@@ -42,11 +50,12 @@ __device__ __forceinline__ void seird_update(const T c[5], const T nb[5], const 
                                              T out[5]) {
     T fdt, rE, rI;
     seird_increments(c[0], c[1], c[2], c[3], k, fdt, rE, rI);
+    // nb - 4c with one rounding (4c is exact, so this equals nb - (4c))
     T diff[5];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        diff[q] = fma(k.dl[q], nb[q] - T(4) * c[q], c[q]);
-    diff[4] = DIFFUSE_D ? fma(k.dl[4], nb[4] - T(4) * c[4], c[4]) : c[4];
+        diff[q] = fma(k.dl[q], fma(T(-4), c[q], nb[q]), c[q]);
+    diff[4] = DIFFUSE_D ? fma(k.dl[4], fma(T(-4), c[4], nb[4]), c[4]) : c[4];
     out[0] = diff[0] - fdt;
     out[1] = diff[1] + (fdt - rE);
     out[2] = diff[2] + (rE - rI);
@@ -87,13 +96,14 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // ---------------------------------------------------------------------------
 // Whole-wavefront lane shifts by one (DPP wave_shr:1 / wave_shl:1). Lane 0
-// (resp. 63) receives its own value; those edge lanes are halo lanes whose
-// results are never stored.
+// (resp. 63) receives zero; those edge lanes are halo lanes whose results are
+// never stored. With a zero fill the shift needs no copy of an old value and
+// folds into the add that consumes it.
 __device__ __forceinline__ int lane_from_left_i(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true);
 }
 __device__ __forceinline__ int lane_from_right_i(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
 }
 __device__ __forceinline__ float lane_from_left(float v) {
     return __int_as_float(lane_from_left_i(__float_as_int(v)));

@@ -16,8 +16,7 @@ struct sslbm_ctx {
     int nx = 0, ny = 0, dtype = 0, bc = 0;
     sslbm_params p{};
     sslbm::StepCoef coef{};
-    int blocking = 0;       // steps per HBM pass for sslbm_run; 0 = automatic
-    int rows_per_wave = 0;  // 0 = automatic
+    sslbm_launch launch{};  // requested pass shape; zero fields = automatic
     int last_hip = 0;
     double *partials = nullptr;  // device buffer of sslbm_total
     int partial_blocks = 0;
@@ -97,24 +96,25 @@ int hip_status(sslbm_ctx *c, hipError_t e) {
     return SSLBM_E_HIP;
 }
 
-// Steps per pass when the caller has not fixed it.
-int auto_blocking(const sslbm_ctx *c) { return c->dtype == SSLBM_F32 ? 4 : 4; }
-
-sslbm::MarchShape shape_for(const sslbm_ctx *c, int K) {
-    sslbm::MarchShape s;
-    if (c->rows_per_wave > 0) {
-        s.rows_per_wave = c->rows_per_wave;
-        return s;
+// Pass shape actually used: requested fields, automatic ones filled in.
+sslbm_launch resolve(const sslbm_ctx *c) {
+    sslbm_launch r = c->launch;
+    if (r.steps_per_pass == 0)
+        r.steps_per_pass = 4;
+    if (r.rows_per_wave == 0) {
+        // enough wavefronts to fill 256 CUs several times over, chunks no
+        // shorter than 16 rows (2K halo rows are recomputed per chunk)
+        const int w = sslbm::strip_width(r.steps_per_pass);
+        const long long strips = (c->nx + w - 1) / w;
+        long long h = (long long)c->ny * strips / 4096;
+        r.rows_per_wave = (int)(h < 16 ? 16 : (h > 64 ? 64 : h));
     }
-    // enough wavefronts to fill 256 CUs several times over, chunks no shorter
-    // than 16 rows (the 2K halo rows are recomputed per chunk)
-    const int strips = (c->nx + (64 - 2 * K) - 1) / (64 - 2 * K);
-    long long h = (long long)c->ny * strips / 4096;
-    if (h < 16)
-        h = 16;
-    if (h > 64)
-        h = 64;
-    s.rows_per_wave = (int)h;
+    return r;
+}
+
+sslbm::MarchShape shape_for(const sslbm_ctx *c) {
+    sslbm::MarchShape s;
+    s.rows_per_wave = resolve(c).rows_per_wave;
     return s;
 }
 
@@ -183,17 +183,38 @@ int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p) {
     return SSLBM_OK;
 }
 
-int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass) {
-    if (!c || steps_per_pass < 0 || steps_per_pass > SSLBM_MAX_BLOCKING)
+int sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape) {
+    if (!c || !shape)
         return SSLBM_E_ARG;
-    c->blocking = steps_per_pass;
+    const sslbm_launch &r = *shape;
+    if (r.steps_per_pass < 0 || r.steps_per_pass > SSLBM_MAX_BLOCKING || r.rows_per_wave < 0 ||
+        r.rows_per_wave > 65536)
+        return SSLBM_E_ARG;
+    if (r.steps_per_pass > sslbm::march_max_depth(c->dtype))
+        return SSLBM_E_UNSUPPORTED;
+    c->launch = r;
     return SSLBM_OK;
+}
+
+int sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape) {
+    if (!c || !shape)
+        return SSLBM_E_ARG;
+    *shape = resolve(c);
+    return SSLBM_OK;
+}
+
+int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass) {
+    if (!c)
+        return SSLBM_E_ARG;
+    sslbm_launch r = c->launch;
+    r.steps_per_pass = steps_per_pass;
+    return sslbm_set_launch(c, &r);
 }
 
 int sslbm_get_blocking(const sslbm_ctx *c) {
     if (!c)
         return SSLBM_E_ARG;
-    return c->blocking > 0 ? c->blocking : auto_blocking(c);
+    return resolve(c).steps_per_pass;
 }
 
 int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream) {
@@ -203,7 +224,7 @@ int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream
     if (overlap(rho_in, bytes, rho_out, bytes))
         return SSLBM_E_ALIAS;
     return hip_status(c, sslbm::launch_march(c->dtype, rho_in, rho_out, grid_of(c), c->coef, 1,
-                                             shape_for(c, 1), (hipStream_t)hip_stream));
+                                             shape_for(c), (hipStream_t)hip_stream));
 }
 
 int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream) {
@@ -214,13 +235,13 @@ int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hi
         return SSLBM_E_ALIAS;
     if (nsteps == 0)
         return SSLBM_OK;
-    const int K = sslbm_get_blocking(c);
+    const int K = resolve(c).steps_per_pass;
     const hipStream_t s = (hipStream_t)hip_stream;
     const sslbm::GridDesc g = grid_of(c);
     void *src = rho, *dst = scratch;
     for (int k : plan_passes(nsteps, K)) {
         const int st =
-            hip_status(c, sslbm::launch_march(c->dtype, src, dst, g, c->coef, k, shape_for(c, k), s));
+            hip_status(c, sslbm::launch_march(c->dtype, src, dst, g, c->coef, k, shape_for(c), s));
         if (st != SSLBM_OK)
             return st;
         void *t = src;

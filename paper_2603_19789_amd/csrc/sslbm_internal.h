@@ -30,13 +30,17 @@ struct StepCoef {
 
 // Launch shape of the y-marching kernel.
 struct MarchShape {
-    int rows_per_wave;  // H: output rows each wavefront produces
+    int rows_per_wave;  // output rows each wavefront produces
 };
 
 // ---- launchers (sslbm_kernels.hip) --------------------------------------
 // K steps in one pass: in -> out (no overlap). K in 1..SSLBM_MAX_BLOCKING.
 hipError_t launch_march(int dtype, const void *in, void *out, const GridDesc &g,
                         const StepCoef &k, int K, const MarchShape &shape, hipStream_t s);
+// Largest steps-per-pass whose kernel fits the register budget (8 FP32, 6 FP64).
+int march_max_depth(int dtype);
+// Output columns of one wavefront strip at K steps per pass.
+int strip_width(int K);
 
 // ---- launchers (bgk_kernels.hip) ----------------------------------------
 hipError_t launch_bgk_init(int dtype, const void *rho, void *f, void *rhoD, const GridDesc &g,

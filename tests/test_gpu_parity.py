@@ -79,24 +79,55 @@ def test_diffusing_deceased(orc, dtype, bc):
     assert max_rel_l2(to_np(rho), orc.sslbm_run(rho0, p, 20, bc=bc)) <= TOL[dtype]
 
 
+def _reference_steps(s, rho0, n):
+    ref_t = rho0.clone()
+    tmp = torch.empty_like(ref_t)
+    for _ in range(n):
+        s.step(ref_t, tmp)
+        ref_t, tmp = tmp, ref_t
+    return ref_t
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("bc", ["periodic", "noflux"])
-def test_blocking_depth_is_bitwise_invisible(dtype, bc):
-    """K steps per pass give the same bits as K single steps, for every K."""
-    nx, ny = 131, 77
+@pytest.mark.parametrize("nx,ny", [(131, 77), (130, 64)])
+def test_launch_shape_is_bitwise_invisible(dtype, bc, nx, ny):
+    """Every pass shape (steps per pass, rows per wavefront) gives the same
+    bits as single steps."""
     p = params_for()
     rho0 = to_gpu(inputs.random_state(nx, ny, seed=9), dtype)
     s = Solver(nx, ny, p, dtype=dtype, bc=bc)
-    ref_t = rho0.clone()
-    tmp = torch.empty_like(ref_t)
-    for _ in range(17):
-        s.step(ref_t, tmp)
-        ref_t, tmp = tmp, ref_t
+    ref_t = _reference_steps(s, rho0, 17)
+    from paper_2603_19789_amd.binding import SSLBMError
+    tried = 0
     for K in range(1, 9):
-        s.set_blocking(K)
-        rho = rho0.clone()
-        s.run(rho, 17)
-        assert torch.equal(rho, ref_t), f"K={K}"
+        for H in (0, 1, 5, 16, 200):
+            try:
+                s.set_launch(K, H)
+            except SSLBMError:
+                continue  # beyond the register budget for this dtype
+            rho = rho0.clone()
+            s.run(rho, 17)
+            assert torch.equal(rho, ref_t), f"K={K} H={H}"
+            tried += 1
+    assert tried >= 30
+
+
+def test_unaligned_buffers_bitwise():
+    """Buffers at any element offset give the same bits (no alignment needs)."""
+    nx, ny = 96, 40
+    p = params_for()
+    s = Solver(nx, ny, p, dtype="f32")
+    rho0 = to_gpu(inputs.random_state(nx, ny, seed=10), "f32")
+    ref_t = _reference_steps(s, rho0, 9)
+    s.set_launch(3, 0)
+    n = 5 * ny * nx
+    buf = torch.empty(n + 1, dtype=torch.float32, device="cuda")
+    rho = buf[1:].view(5, ny, nx)
+    rho.copy_(rho0)
+    sbuf = torch.empty(n + 1, dtype=torch.float32, device="cuda")
+    s.run(rho, 9, scratch=sbuf[1:].view(5, ny, nx))
+    assert torch.equal(rho, ref_t)
 
 
 def test_run_is_resumable_bitwise():
