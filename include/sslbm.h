@@ -108,17 +108,21 @@ int sslbm_get_blocking(const sslbm_ctx *c);
 
 /*
  * Launch shape of the pass kernel used by sslbm_run (sslbm_step always takes
- * one step per pass). Each wavefront owns a strip of 64 - 2 * steps_per_pass
- * output columns and marches down rows_per_wave output rows. Zero in a field
- * selects the automatic value. Shapes change speed only, never results (bit
- * for bit). Valid: steps_per_pass 0..SSLBM_MAX_BLOCKING, rows_per_wave
- * 0..65536. A depth whose register footprint does not fit one wavefront
- * (above 6 in FP64) returns SSLBM_E_UNSUPPORTED.
+ * one step per pass). Each wavefront owns a strip of 64 * cols_per_lane
+ * columns, of which 64 * cols_per_lane - 2 * steps_per_pass (the halo rounded
+ * up to a multiple of cols_per_lane) are output, and marches down
+ * rows_per_wave output rows. Zero in a field selects the automatic value.
+ * Shapes change speed only, never results (bit for bit). Valid:
+ * steps_per_pass 0..SSLBM_MAX_BLOCKING, rows_per_wave 0..65536,
+ * cols_per_lane 0..2. A combination whose register footprint does not fit one
+ * wavefront (FP32 above 6 steps with two columns per lane; FP64 above 5 with
+ * one, above 2 with two) returns SSLBM_E_UNSUPPORTED.
  * sslbm_get_launch reports the shape sslbm_run uses (automatic fields resolved).
  */
 typedef struct {
     int steps_per_pass;
     int rows_per_wave;
+    int cols_per_lane;
 } sslbm_launch;
 int sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape);
 int sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape);

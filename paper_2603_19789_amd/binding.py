@@ -48,8 +48,10 @@ class Params(ctypes.Structure):
 
 
 class Launch(ctypes.Structure):
-    """Pass shape (zero = automatic): steps per HBM pass, output rows per wavefront."""
-    _fields_ = [("steps_per_pass", ctypes.c_int), ("rows_per_wave", ctypes.c_int)]
+    """Pass shape (zero = automatic): steps per HBM pass, output rows per
+    wavefront, adjacent columns per lane."""
+    _fields_ = [("steps_per_pass", ctypes.c_int), ("rows_per_wave", ctypes.c_int),
+                ("cols_per_lane", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -191,9 +193,9 @@ class Solver(_Context):
     def blocking(self) -> int:
         return self.lib.sslbm_get_blocking(self.handle)
 
-    def set_launch(self, steps_per_pass=0, rows_per_wave=0):
+    def set_launch(self, steps_per_pass=0, rows_per_wave=0, cols_per_lane=0):
         """Pass shape (0 = automatic); changes speed, never results."""
-        shape = Launch(int(steps_per_pass), int(rows_per_wave))
+        shape = Launch(int(steps_per_pass), int(rows_per_wave), int(cols_per_lane))
         self._check(self.lib.sslbm_set_launch(self.handle, ctypes.byref(shape)),
                     "sslbm_set_launch")
 

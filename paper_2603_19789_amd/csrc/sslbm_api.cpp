@@ -96,25 +96,59 @@ int hip_status(sslbm_ctx *c, hipError_t e) {
     return SSLBM_E_HIP;
 }
 
+// Steps per pass and columns per lane when the caller has not chosen: the
+// fastest shapes measured on MI355X for large grids (the pass turns from
+// HBM-bound to ALU-bound around there).
+int auto_depth(const sslbm_ctx *c) { return c->dtype == SSLBM_F32 ? 6 : 5; }
+int auto_cols(const sslbm_ctx *c) { return c->dtype == SSLBM_F32 ? 2 : 1; }
+
+// Rows per wavefront when the caller has not chosen: the shortest chunks for
+// which all wavefronts of the pass are resident at once (one round, no tail),
+// but at least 2K rows so the halo rows stay a minority. Without a device to
+// query, a fixed estimate of three resident wavefronts per SIMD is used.
+int auto_rows(const sslbm_ctx *c, int K, int V) {
+    const int w = sslbm::strip_width(K, V);
+    const long long strips = (c->nx + w - 1) / w;
+    long long resident = sslbm::march_resident_waves(c->dtype, K, V, c->coef.diffuse_d);
+    if (resident <= 0)
+        resident = 3 * 4 * 256;
+    long long chunks = resident / strips;
+    if (chunks < 1)
+        chunks = 1;
+    long long h = (c->ny + chunks - 1) / chunks;
+    if (h < 2 * K)
+        h = 2 * K;
+    if (h > 65536)
+        h = 65536;
+    return (int)h;
+}
+
 // Pass shape actually used: requested fields, automatic ones filled in.
 sslbm_launch resolve(const sslbm_ctx *c) {
     sslbm_launch r = c->launch;
     if (r.steps_per_pass == 0)
-        r.steps_per_pass = 4;
-    if (r.rows_per_wave == 0) {
-        // enough wavefronts to fill 256 CUs several times over, chunks no
-        // shorter than 16 rows (2K halo rows are recomputed per chunk)
-        const int w = sslbm::strip_width(r.steps_per_pass);
-        const long long strips = (c->nx + w - 1) / w;
-        long long h = (long long)c->ny * strips / 4096;
-        r.rows_per_wave = (int)(h < 16 ? 16 : (h > 64 ? 64 : h));
-    }
+        r.steps_per_pass = auto_depth(c);
+    if (r.cols_per_lane == 0)
+        r.cols_per_lane = auto_cols(c);
+    if (r.rows_per_wave == 0)
+        r.rows_per_wave = auto_rows(c, r.steps_per_pass, r.cols_per_lane);
     return r;
 }
 
-sslbm::MarchShape shape_for(const sslbm_ctx *c) {
+// Shape of one pass of k steps (the last pass of a run may be shorter). Two
+// columns per lane read and write aligned element pairs: that needs an even
+// row length and pair-aligned buffers, else the pass takes one column per lane.
+sslbm::MarchShape shape_for(const sslbm_ctx *c, int k, const void *in, const void *out) {
+    const sslbm_launch r = resolve(c);
     sslbm::MarchShape s;
-    s.rows_per_wave = resolve(c).rows_per_wave;
+    s.cols_per_lane = r.cols_per_lane;
+    const uintptr_t pair = 2 * elem_size(c);
+    if (s.cols_per_lane == 2 &&
+        (c->nx % 2 != 0 || (uintptr_t)in % pair != 0 || (uintptr_t)out % pair != 0 ||
+         k > sslbm::march_max_depth(c->dtype, 2)))
+        s.cols_per_lane = 1;
+    s.rows_per_wave =
+        c->launch.rows_per_wave > 0 ? c->launch.rows_per_wave : auto_rows(c, k, s.cols_per_lane);
     return s;
 }
 
@@ -188,9 +222,13 @@ int sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape) {
         return SSLBM_E_ARG;
     const sslbm_launch &r = *shape;
     if (r.steps_per_pass < 0 || r.steps_per_pass > SSLBM_MAX_BLOCKING || r.rows_per_wave < 0 ||
-        r.rows_per_wave > 65536)
+        r.rows_per_wave > 65536 || r.cols_per_lane < 0 || r.cols_per_lane > 2)
         return SSLBM_E_ARG;
-    if (r.steps_per_pass > sslbm::march_max_depth(c->dtype))
+    sslbm_ctx probe = *c;
+    probe.partials = nullptr;
+    probe.launch = r;
+    const sslbm_launch full = resolve(&probe);
+    if (full.steps_per_pass > sslbm::march_max_depth(c->dtype, full.cols_per_lane))
         return SSLBM_E_UNSUPPORTED;
     c->launch = r;
     return SSLBM_OK;
@@ -224,7 +262,8 @@ int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream
     if (overlap(rho_in, bytes, rho_out, bytes))
         return SSLBM_E_ALIAS;
     return hip_status(c, sslbm::launch_march(c->dtype, rho_in, rho_out, grid_of(c), c->coef, 1,
-                                             shape_for(c), (hipStream_t)hip_stream));
+                                             shape_for(c, 1, rho_in, rho_out),
+                                             (hipStream_t)hip_stream));
 }
 
 int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream) {
@@ -241,7 +280,8 @@ int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hi
     void *src = rho, *dst = scratch;
     for (int k : plan_passes(nsteps, K)) {
         const int st =
-            hip_status(c, sslbm::launch_march(c->dtype, src, dst, g, c->coef, k, shape_for(c), s));
+            hip_status(c, sslbm::launch_march(c->dtype, src, dst, g, c->coef, k,
+                                              shape_for(c, k, src, dst), s));
         if (st != SSLBM_OK)
             return st;
         void *t = src;

@@ -31,16 +31,20 @@ struct StepCoef {
 // Launch shape of the y-marching kernel.
 struct MarchShape {
     int rows_per_wave;  // output rows each wavefront produces
+    int cols_per_lane;  // adjacent columns per lane: 1 or 2
 };
 
 // ---- launchers (sslbm_kernels.hip) --------------------------------------
 // K steps in one pass: in -> out (no overlap). K in 1..SSLBM_MAX_BLOCKING.
 hipError_t launch_march(int dtype, const void *in, void *out, const GridDesc &g,
                         const StepCoef &k, int K, const MarchShape &shape, hipStream_t s);
-// Largest steps-per-pass whose kernel fits the register budget (8 FP32, 6 FP64).
-int march_max_depth(int dtype);
+// Largest steps-per-pass whose kernel fits the register budget.
+int march_max_depth(int dtype, int cols_per_lane);
 // Output columns of one wavefront strip at K steps per pass.
-int strip_width(int K);
+int strip_width(int K, int cols_per_lane);
+// Wavefronts of the K-step pass kernel resident on the current device at
+// once (occupancy x CUs), 0 when no device can be queried.
+int march_resident_waves(int dtype, int K, int cols_per_lane, bool diffuse_d);
 
 // ---- launchers (bgk_kernels.hip) ----------------------------------------
 hipError_t launch_bgk_init(int dtype, const void *rho, void *f, void *rhoD, const GridDesc &g,

@@ -39,12 +39,23 @@ constexpr int BLOCK_THREADS = 64 * WAVES_PER_BLOCK;
 constexpr int RING = 4;  // row slots per level: 3 in use + 1 being loaded
 
 // Register budget: the rows a wavefront keeps live (3 per level plus the one
-// in flight, 5 fields) must fit in 256 VGPRs with room for the arithmetic;
-// larger depths are not instantiated.
-template <typename T, int K>
+// in flight, 5 fields, V columns) plus the arithmetic's temporaries must fit
+// in 256 VGPRs (two wavefronts per SIMD); larger combinations would spill and
+// are not instantiated.
+template <typename T, int K, int V>
 constexpr bool march_fits() {
-    return (3 * K + 1) * 5 * (int)(sizeof(T) / 4) + 48 <= 256;
+    constexpr int words = (int)(sizeof(T) / 4);
+    return (3 * K + 1) * 5 * V * words + 48 * words <= 256;
 }
+
+// Strip geometry: 64 lanes x V columns, of which HX on each side are halo
+// (K rounded up to a multiple of V so that every strip starts at an even
+// column for V = 2).
+template <int K, int V>
+struct Strip {
+    static constexpr int HX = (K + V - 1) / V * V;
+    static constexpr int WU = 64 * V - 2 * HX;  // output columns
+};
 
 // Row access through buffer instructions: the resource (base address and
 // byte length of one row) is wavefront-uniform and lives in scalar
@@ -66,6 +77,9 @@ __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off
 __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+// Stores go through L2 with the default policy: strips are not aligned to
+// 128-byte lines, and L2 merges the partial lines that neighbouring strips
+// write (streaming them past the cache measured slower).
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
 }
@@ -74,106 +88,190 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U2, v), r, off, 0, 0);
 }
 
-template <typename T, int K>
+// Two consecutive elements at an aligned byte offset, one vector access.
+// The loaded vector is reinterpreted as one wide integer and split with
+// shifts: taking its elements one by one lets this compiler narrow the load
+// to half its width (the upper half is then never read).
+__device__ __forceinline__ void buf_load_pair(__amdgpu_buffer_rsrc_t r, unsigned off, float &a,
+                                              float &b) {
+    const unsigned long long w = __builtin_bit_cast(
+        unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    a = __builtin_bit_cast(float, (unsigned)w);
+    b = __builtin_bit_cast(float, (unsigned)(w >> 32));
+}
+__device__ __forceinline__ void buf_load_pair(__amdgpu_buffer_rsrc_t r, unsigned off, double &a,
+                                              double &b) {
+    const unsigned __int128 w = __builtin_bit_cast(
+        unsigned __int128, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    a = __builtin_bit_cast(double, (unsigned long long)w);
+    b = __builtin_bit_cast(double, (unsigned long long)(w >> 64));
+}
+__device__ __forceinline__ void buf_store_pair(__amdgpu_buffer_rsrc_t r, unsigned off, float a,
+                                               float b) {
+    using U2 = unsigned __attribute__((ext_vector_type(2)));
+    const U2 w = {__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b)};
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store_pair(__amdgpu_buffer_rsrc_t r, unsigned off, double a,
+                                               double b) {
+    using U4 = unsigned __attribute__((ext_vector_type(4)));
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, a);
+    const unsigned long long y = __builtin_bit_cast(unsigned long long, b);
+    const U4 w = {(unsigned)x, (unsigned)(x >> 32), (unsigned)y, (unsigned)(y >> 32)};
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, off, 0, 0);
+}
+
+template <typename T, int K, int V>
 struct MarchState {
-    T ring[K][RING][5];  // [level][slot][compartment]
+    T ring[K][RING][5][V];  // [level][slot][compartment][column of the lane]
 };
 
-template <typename T>
+template <typename T, int V>
 struct MarchArgs {
     const T *__restrict__ in;
     T *__restrict__ out;
     GridDesc g;
     Coef<T> k;
-    unsigned xoff;  // byte offset of this lane's memory column within a row
-    int xl;         // logical column of this lane
-    bool out_lane;  // lane holds an output column of the strip
-    int y0;         // first output row of the chunk
-    int j0;         // first level-0 row (y0 - K)
-    int tend;       // number of level-0 rows
+    unsigned xoff[V];  // byte offsets of this lane's memory columns within a row
+    bool swap;         // V = 2: the lane's pair lies reversed in memory (mirror image)
+    int xl;            // logical column of this lane's first column
+    bool out_col[V];   // the column is an output column of the strip
+    int y0;            // first output row of the chunk
+    int j0;            // first level-0 row (y0 - K)
+    int tend;          // number of level-0 rows
 };
 
 // Level-0 row j0 + t into its ring slot SL. Rows past the chunk are still
 // in range (the index map folds every integer into the grid), so the fetch
 // needs no guard.
-template <typename T, int K, int SL>
-__device__ __forceinline__ void fetch_row(MarchState<T, K> &st, const MarchArgs<T> &a, int t) {
+template <typename T, int K, int V, int SL>
+__device__ __forceinline__ void fetch_row(MarchState<T, K, V> &st, const MarchArgs<T, V> &a,
+                                          int t) {
     const long long row = (long long)map_index(a.j0 + t, a.g.ny, a.g.bc) * a.g.nx;
 #pragma unroll
-    for (int c = 0; c < 5; ++c)
-        st.ring[0][SL][c] = buf_load(row_resource(a.in + (c * a.g.plane + row), a.g.nx), a.xoff,
-                                     T(0));
+    for (int c = 0; c < 5; ++c) {
+        const __amdgpu_buffer_rsrc_t r = row_resource(a.in + (c * a.g.plane + row), a.g.nx);
+        if constexpr (V == 1) {
+            st.ring[0][SL][c][0] = buf_load(r, a.xoff[0], T(0));
+        } else {
+            // the pair is one aligned vector in memory, possibly mirrored
+            T lo, hi;
+            buf_load_pair(r, a.xoff[0], lo, hi);
+            st.ring[0][SL][c][0] = a.swap ? hi : lo;
+            st.ring[0][SL][c][1] = a.swap ? lo : hi;
+        }
+    }
+}
+
+// East + west neighbours of column v of this lane at level-(L-1) slot S:
+// the adjacent column inside the lane, or the next lane's edge column
+// through a DPP wave shift.
+template <typename T, int V, typename Row>
+__device__ __forceinline__ T east_west(const Row &m, int v) {
+    if constexpr (V == 1) {
+        return lane_from_right(m[0]) + lane_from_left(m[0]);
+    } else {
+        if (v == 0)
+            return m[1] + lane_from_left(m[V - 1]);
+        if (v == V - 1)
+            return lane_from_right(m[0]) + m[V - 2];
+        return m[v + 1] + m[v - 1];
+    }
 }
 
 // Level l (1..K) at phase P: the row j - l from rows j-l-1, j-l, j-l+1 of
 // level l-1 (slots (P-l-1), (P-l), (P-l+1) mod RING); the result goes to slot
 // (P-l) mod RING of level l, or to HBM for l = K (output row j - K).
-template <typename T, int K, bool DIFFUSE_D, int P, int L>
-__device__ __forceinline__ void level(MarchState<T, K> &st, const MarchArgs<T> &a, int t) {
+template <typename T, int K, bool DIFFUSE_D, int V, int P, int L>
+__device__ __forceinline__ void level(MarchState<T, K, V> &st, const MarchArgs<T, V> &a, int t) {
     constexpr int s_up = ((P - L - 1) % RING + RING) % RING;
     constexpr int s_mid = ((P - L) % RING + RING) % RING;
     constexpr int s_dn = ((P - L + 1) % RING + RING) % RING;
-    T cen[5], nb[5], res[5];
+    T res[5][V];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        cen[c] = st.ring[L - 1][s_mid][c];
-        if (c < 4 || DIFFUSE_D) {
-            const T ew = lane_from_right(cen[c]) + lane_from_left(cen[c]);
-            nb[c] = (st.ring[L - 1][s_up][c] + st.ring[L - 1][s_dn][c]) + ew;
-        } else {
-            nb[c] = T(0);
+    for (int v = 0; v < V; ++v) {
+        T cen[5], nb[5], o[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            cen[c] = st.ring[L - 1][s_mid][c][v];
+            if (c < 4 || DIFFUSE_D) {
+                const T ew = east_west<T, V>(st.ring[L - 1][s_mid][c], v);
+                nb[c] = (st.ring[L - 1][s_up][c][v] + st.ring[L - 1][s_dn][c][v]) + ew;
+            } else {
+                nb[c] = T(0);
+            }
         }
+        seird_update<T, DIFFUSE_D>(cen, nb, a.k, o);
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+            res[c][v] = o[c];
     }
-    seird_update<T, DIFFUSE_D>(cen, nb, a.k, res);
     if constexpr (L < K) {
 #pragma unroll
         for (int c = 0; c < 5; ++c)
-            st.ring[L][s_mid][c] = res[c];
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                st.ring[L][s_mid][c][v] = res[c][v];
     } else {
         const long long row = (long long)(a.j0 + t - K) * a.g.nx;
         const unsigned xo = (unsigned)a.xl * (unsigned)sizeof(T);
-        if (a.out_lane) {
+        if constexpr (V == 1) {
+            if (a.out_col[0]) {
 #pragma unroll
-            for (int c = 0; c < 5; ++c)
-                buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), xo, res[c]);
+                for (int c = 0; c < 5; ++c)
+                    buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), xo, res[c][0]);
+            }
+        } else {
+            // strips start at even columns and nx is even, so a pair is either
+            // entirely output or entirely halo
+            if (a.out_col[0]) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c)
+                    buf_store_pair(row_resource(a.out + (c * a.g.plane + row), a.g.nx), xo,
+                                   res[c][0], res[c][1]);
+            }
         }
     }
 }
 
 // Levels L..LMAX at phase P.
-template <typename T, int K, bool DIFFUSE_D, int P, int L, int LMAX>
-__device__ __forceinline__ void levels(MarchState<T, K> &st, const MarchArgs<T> &a, int t) {
+template <typename T, int K, bool DIFFUSE_D, int V, int P, int L, int LMAX>
+__device__ __forceinline__ void levels(MarchState<T, K, V> &st, const MarchArgs<T, V> &a, int t) {
     if constexpr (L <= LMAX) {
-        level<T, K, DIFFUSE_D, P, L>(st, a, t);
-        levels<T, K, DIFFUSE_D, P, L + 1, LMAX>(st, a, t);
+        level<T, K, DIFFUSE_D, V, P, L>(st, a, t);
+        levels<T, K, DIFFUSE_D, V, P, L + 1, LMAX>(st, a, t);
     }
 }
 
 // Warm-up rows t = TC < 2K (compile time): fetch row t + 1, then the levels
 // that already have three rows below them (l <= t/2). Nothing is stored yet.
-template <typename T, int K, bool DIFFUSE_D, int TC>
-__device__ __forceinline__ void warm_up(MarchState<T, K> &st, const MarchArgs<T> &a) {
+template <typename T, int K, bool DIFFUSE_D, int V, int TC>
+__device__ __forceinline__ void warm_up(MarchState<T, K, V> &st, const MarchArgs<T, V> &a) {
     if constexpr (TC < 2 * K) {
-        fetch_row<T, K, (TC + 1) % RING>(st, a, TC + 1);
-        levels<T, K, DIFFUSE_D, TC % RING, 1, TC / 2>(st, a, TC);
-        warm_up<T, K, DIFFUSE_D, TC + 1>(st, a);
+        fetch_row<T, K, V, (TC + 1) % RING>(st, a, TC + 1);
+        levels<T, K, DIFFUSE_D, V, TC % RING, 1, TC / 2>(st, a, TC);
+        warm_up<T, K, DIFFUSE_D, V, TC + 1>(st, a);
     }
 }
 
 // Steady-state row t (phase P): fetch row t + 1, all K levels, one output row.
 // Straight-line code, so the memory counters stay exact and the wait for row
 // t's data lets the row t + 1 loads stay in flight.
-template <typename T, int K, bool DIFFUSE_D, int P>
-__device__ __forceinline__ void steady_row(MarchState<T, K> &st, const MarchArgs<T> &a, int t) {
-    fetch_row<T, K, (P + 1) % RING>(st, a, t + 1);
-    levels<T, K, DIFFUSE_D, P, 1, K>(st, a, t);
+template <typename T, int K, bool DIFFUSE_D, int V, int P>
+__device__ __forceinline__ void steady_row(MarchState<T, K, V> &st, const MarchArgs<T, V> &a,
+                                           int t) {
+    fetch_row<T, K, V, (P + 1) % RING>(st, a, t + 1);
+    levels<T, K, DIFFUSE_D, V, P, 1, K>(st, a, t);
 }
 
-template <typename T, int K, bool DIFFUSE_D>
-__global__ __launch_bounds__(BLOCK_THREADS) void sslbm_march_kernel(
+// At least two wavefronts per SIMD (at most 256 VGPRs each): with one, a
+// SIMD idles whenever its only wavefront waits for memory.
+template <typename T, int K, bool DIFFUSE_D, int V>
+__global__ __launch_bounds__(BLOCK_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+void sslbm_march_kernel(
     const T *__restrict__ in, T *__restrict__ out, GridDesc g, Coef<T> k, int rows_per_wave,
     int strips, int total_waves) {
-    constexpr int WU = 64 - 2 * K;  // output columns per strip
+    using Geo = Strip<K, V>;
     const int lane = threadIdx.x & 63;
     // wavefront-uniform from here on: keep it in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(
@@ -183,7 +281,7 @@ __global__ __launch_bounds__(BLOCK_THREADS) void sslbm_march_kernel(
     const int strip = wave % strips;
     const int chunk = wave / strips;
 
-    MarchArgs<T> a;
+    MarchArgs<T, V> a;
     a.in = in;
     a.out = out;
     a.g = g;
@@ -192,37 +290,51 @@ __global__ __launch_bounds__(BLOCK_THREADS) void sslbm_march_kernel(
     const int y1 = min(a.y0 + rows_per_wave, g.ny);  // output rows [y0, y1)
     a.j0 = a.y0 - K;
     a.tend = y1 - a.y0 + 2 * K;
-    a.xl = strip * WU - K + lane;
-    a.xoff = (unsigned)map_index(a.xl, g.nx, g.bc) * (unsigned)sizeof(T);
-    a.out_lane = lane >= K && lane < 64 - K && a.xl < g.nx;
+    a.xl = strip * Geo::WU - Geo::HX + lane * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        a.xoff[v] = (unsigned)map_index(a.xl + v, g.nx, g.bc) * (unsigned)sizeof(T);
+        const int pos = lane * V + v;
+        a.out_col[v] = pos >= Geo::HX && pos < Geo::HX + Geo::WU && a.xl + v < g.nx;
+    }
+    a.swap = false;
+    if constexpr (V == 2) {
+        // xl is even and nx is even, so the pair maps onto one aligned pair of
+        // memory columns, in order or (across a mirror) reversed
+        a.swap = a.xoff[1] < a.xoff[0];
+        if (a.swap)
+            a.xoff[0] = a.xoff[1];
+    }
 
-    MarchState<T, K> st;
+    MarchState<T, K, V> st;
 #pragma unroll
     for (int l = 0; l < K; ++l)
 #pragma unroll
         for (int r = 0; r < RING; ++r)
 #pragma unroll
             for (int c = 0; c < 5; ++c)
-                st.ring[l][r][c] = T(0);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    st.ring[l][r][c][v] = T(0);
 
     // rows 0 .. 2K-1: fill the levels; from row 2K on every row yields output
-    fetch_row<T, K, 0>(st, a, 0);
-    warm_up<T, K, DIFFUSE_D, 0>(st, a);
+    fetch_row<T, K, V, 0>(st, a, 0);
+    warm_up<T, K, DIFFUSE_D, V, 0>(st, a);
     constexpr int P0 = (2 * K) % RING;
     int t = 2 * K;
     for (; t + RING <= a.tend; t += RING) {
-        steady_row<T, K, DIFFUSE_D, P0>(st, a, t);
-        steady_row<T, K, DIFFUSE_D, (P0 + 1) % RING>(st, a, t + 1);
-        steady_row<T, K, DIFFUSE_D, (P0 + 2) % RING>(st, a, t + 2);
-        steady_row<T, K, DIFFUSE_D, (P0 + 3) % RING>(st, a, t + 3);
+        steady_row<T, K, DIFFUSE_D, V, P0>(st, a, t);
+        steady_row<T, K, DIFFUSE_D, V, (P0 + 1) % RING>(st, a, t + 1);
+        steady_row<T, K, DIFFUSE_D, V, (P0 + 2) % RING>(st, a, t + 2);
+        steady_row<T, K, DIFFUSE_D, V, (P0 + 3) % RING>(st, a, t + 3);
     }
     // last partial group of rows (only when the chunk height is not a multiple of 4)
     if (t < a.tend)
-        steady_row<T, K, DIFFUSE_D, P0>(st, a, t);
+        steady_row<T, K, DIFFUSE_D, V, P0>(st, a, t);
     if (t + 1 < a.tend)
-        steady_row<T, K, DIFFUSE_D, (P0 + 1) % RING>(st, a, t + 1);
+        steady_row<T, K, DIFFUSE_D, V, (P0 + 1) % RING>(st, a, t + 1);
     if (t + 2 < a.tend)
-        steady_row<T, K, DIFFUSE_D, (P0 + 2) % RING>(st, a, t + 2);
+        steady_row<T, K, DIFFUSE_D, V, (P0 + 2) % RING>(st, a, t + 2);
 }
 
 template <typename T>
@@ -238,20 +350,20 @@ static Coef<T> cast_coef(const StepCoef &s) {
     return k;
 }
 
-template <typename T, int K, bool DD>
+template <typename T, int K, bool DD, int V>
 static hipError_t launch_k(const void *in, void *out, const GridDesc &g, const StepCoef &s,
                            const MarchShape &shape, hipStream_t st) {
-    if constexpr (!march_fits<T, K>()) {
+    if constexpr (!march_fits<T, K, V>()) {
         return hipErrorInvalidValue;
     } else {
-        constexpr int WU = 64 - 2 * K;
+        constexpr int WU = Strip<K, V>::WU;
         const int strips = (g.nx + WU - 1) / WU;
         const int chunks = (g.ny + shape.rows_per_wave - 1) / shape.rows_per_wave;
         const long long waves = (long long)strips * chunks;
         const long long blocks = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
         if (waves > 0x7fffffffll)
             return hipErrorInvalidConfiguration;
-        hipLaunchKernelGGL((sslbm_march_kernel<T, K, DD>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((sslbm_march_kernel<T, K, DD, V>), dim3((unsigned)blocks),
                            dim3(BLOCK_THREADS), 0, st, static_cast<const T *>(in),
                            static_cast<T *>(out), g, cast_coef<T>(s), shape.rows_per_wave,
                            strips, (int)waves);
@@ -259,49 +371,116 @@ static hipError_t launch_k(const void *in, void *out, const GridDesc &g, const S
     }
 }
 
-template <typename T, bool DD>
+template <typename T, bool DD, int V>
 static hipError_t dispatch_k(const void *in, void *out, const GridDesc &g, const StepCoef &s,
                              int K, const MarchShape &shape, hipStream_t st) {
     switch (K) {
-    case 1: return launch_k<T, 1, DD>(in, out, g, s, shape, st);
-    case 2: return launch_k<T, 2, DD>(in, out, g, s, shape, st);
-    case 3: return launch_k<T, 3, DD>(in, out, g, s, shape, st);
-    case 4: return launch_k<T, 4, DD>(in, out, g, s, shape, st);
-    case 5: return launch_k<T, 5, DD>(in, out, g, s, shape, st);
-    case 6: return launch_k<T, 6, DD>(in, out, g, s, shape, st);
-    case 7: return launch_k<T, 7, DD>(in, out, g, s, shape, st);
-    case 8: return launch_k<T, 8, DD>(in, out, g, s, shape, st);
+    case 1: return launch_k<T, 1, DD, V>(in, out, g, s, shape, st);
+    case 2: return launch_k<T, 2, DD, V>(in, out, g, s, shape, st);
+    case 3: return launch_k<T, 3, DD, V>(in, out, g, s, shape, st);
+    case 4: return launch_k<T, 4, DD, V>(in, out, g, s, shape, st);
+    case 5: return launch_k<T, 5, DD, V>(in, out, g, s, shape, st);
+    case 6: return launch_k<T, 6, DD, V>(in, out, g, s, shape, st);
+    case 7: return launch_k<T, 7, DD, V>(in, out, g, s, shape, st);
+    case 8: return launch_k<T, 8, DD, V>(in, out, g, s, shape, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T, bool DD>
+static hipError_t dispatch_v(const void *in, void *out, const GridDesc &g, const StepCoef &s,
+                             int K, const MarchShape &shape, hipStream_t st) {
+    if (shape.cols_per_lane == 2)
+        return dispatch_k<T, DD, 2>(in, out, g, s, K, shape, st);
+    return dispatch_k<T, DD, 1>(in, out, g, s, K, shape, st);
 }
 
 hipError_t launch_march(int dtype, const void *in, void *out, const GridDesc &g,
                         const StepCoef &k, int K, const MarchShape &shape, hipStream_t s) {
     if (dtype == SSLBM_F32)
-        return k.diffuse_d ? dispatch_k<float, true>(in, out, g, k, K, shape, s)
-                           : dispatch_k<float, false>(in, out, g, k, K, shape, s);
-    return k.diffuse_d ? dispatch_k<double, true>(in, out, g, k, K, shape, s)
-                       : dispatch_k<double, false>(in, out, g, k, K, shape, s);
+        return k.diffuse_d ? dispatch_v<float, true>(in, out, g, k, K, shape, s)
+                           : dispatch_v<float, false>(in, out, g, k, K, shape, s);
+    return k.diffuse_d ? dispatch_v<double, true>(in, out, g, k, K, shape, s)
+                       : dispatch_v<double, false>(in, out, g, k, K, shape, s);
 }
 
-int strip_width(int K) { return 64 - 2 * K; }
+int strip_width(int K, int cols_per_lane) {
+    const int hx = (K + cols_per_lane - 1) / cols_per_lane * cols_per_lane;
+    return 64 * cols_per_lane - 2 * hx;
+}
 
-template <typename T>
+template <typename T, bool DD, int V>
+static const void *kernel_of(int K) {
+    const void *f = nullptr;
+    if constexpr (march_fits<T, 1, V>()) if (K == 1) f = (const void *)sslbm_march_kernel<T, 1, DD, V>;
+    if constexpr (march_fits<T, 2, V>()) if (K == 2) f = (const void *)sslbm_march_kernel<T, 2, DD, V>;
+    if constexpr (march_fits<T, 3, V>()) if (K == 3) f = (const void *)sslbm_march_kernel<T, 3, DD, V>;
+    if constexpr (march_fits<T, 4, V>()) if (K == 4) f = (const void *)sslbm_march_kernel<T, 4, DD, V>;
+    if constexpr (march_fits<T, 5, V>()) if (K == 5) f = (const void *)sslbm_march_kernel<T, 5, DD, V>;
+    if constexpr (march_fits<T, 6, V>()) if (K == 6) f = (const void *)sslbm_march_kernel<T, 6, DD, V>;
+    if constexpr (march_fits<T, 7, V>()) if (K == 7) f = (const void *)sslbm_march_kernel<T, 7, DD, V>;
+    if constexpr (march_fits<T, 8, V>()) if (K == 8) f = (const void *)sslbm_march_kernel<T, 8, DD, V>;
+    return f;
+}
+
+template <typename T, bool DD>
+static const void *kernel_of_v(int K, int V) {
+    return V == 2 ? kernel_of<T, DD, 2>(K) : kernel_of<T, DD, 1>(K);
+}
+
+int march_resident_waves(int dtype, int K, int cols_per_lane, bool diffuse_d) {
+    // cached per (device, dtype, V, K, diffuse_d)
+    static int cache[16][2][2][SSLBM_MAX_BLOCKING + 1][2] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16 || K < 1 ||
+        K > SSLBM_MAX_BLOCKING || cols_per_lane < 1 || cols_per_lane > 2)
+        return 0;
+    int &slot = cache[dev][dtype == SSLBM_F64][cols_per_lane - 1][K][diffuse_d ? 1 : 0];
+    if (slot)
+        return slot;
+    const void *f =
+        dtype == SSLBM_F32
+            ? (diffuse_d ? kernel_of_v<float, true>(K, cols_per_lane)
+                         : kernel_of_v<float, false>(K, cols_per_lane))
+            : (diffuse_d ? kernel_of_v<double, true>(K, cols_per_lane)
+                         : kernel_of_v<double, false>(K, cols_per_lane));
+    // occupancy from the kernel's register count: 512 VGPRs per SIMD lane,
+    // allocated in granules of 8, at most 8 wavefronts per SIMD
+    hipFuncAttributes attr;
+    int cus = 0;
+    if (!f || hipFuncGetAttributes(&attr, f) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int regs = (attr.numRegs + 7) / 8 * 8;
+    int per_simd = regs > 0 ? 512 / regs : 8;
+    if (per_simd > 8)
+        per_simd = 8;
+    if (per_simd < 1)
+        per_simd = 1;
+    slot = per_simd * 4 * cus;
+    return slot;
+}
+
+template <typename T, int V>
 static int max_depth() {
     int K = 0;
-    if (march_fits<T, 1>()) K = 1;
-    if (march_fits<T, 2>()) K = 2;
-    if (march_fits<T, 3>()) K = 3;
-    if (march_fits<T, 4>()) K = 4;
-    if (march_fits<T, 5>()) K = 5;
-    if (march_fits<T, 6>()) K = 6;
-    if (march_fits<T, 7>()) K = 7;
-    if (march_fits<T, 8>()) K = 8;
+    if (march_fits<T, 1, V>()) K = 1;
+    if (march_fits<T, 2, V>()) K = 2;
+    if (march_fits<T, 3, V>()) K = 3;
+    if (march_fits<T, 4, V>()) K = 4;
+    if (march_fits<T, 5, V>()) K = 5;
+    if (march_fits<T, 6, V>()) K = 6;
+    if (march_fits<T, 7, V>()) K = 7;
+    if (march_fits<T, 8, V>()) K = 8;
     return K;
 }
 
-int march_max_depth(int dtype) {
-    return dtype == SSLBM_F32 ? max_depth<float>() : max_depth<double>();
+int march_max_depth(int dtype, int cols_per_lane) {
+    if (cols_per_lane == 2)
+        return dtype == SSLBM_F32 ? max_depth<float, 2>() : max_depth<double, 2>();
+    return dtype == SSLBM_F32 ? max_depth<float, 1>() : max_depth<double, 1>();
 }
 
 }  // namespace sslbm

@@ -123,18 +123,19 @@ def test_aliasing_and_argument_errors_before_any_gpu_call(lib):
     assert lib.sslbm_get_blocking(h) == 3
     assert lib.sslbm_set_blocking(h, 0) == binding.OK
     L = binding.Launch
-    for bad in (L(0, -1), L(0, 65537), L(-1, 0), L(9, 0)):
+    for bad in (L(0, -1, 0), L(0, 65537, 0), L(-1, 0, 0), L(9, 0, 0), L(0, 0, 3), L(0, 0, -1)):
         assert lib.sslbm_set_launch(h, ctypes.byref(bad)) == binding.E_ARG
-    assert lib.sslbm_set_launch(h, ctypes.byref(L(2, 40))) == binding.OK
+    assert lib.sslbm_set_launch(h, ctypes.byref(L(2, 40, 2))) == binding.OK
     got = L()
     assert lib.sslbm_get_launch(h, ctypes.byref(got)) == binding.OK
-    assert got.as_dict() == L(2, 40).as_dict()
-    # FP64 with 8 steps per pass exceeds the register budget of one wavefront
-    assert lib.sslbm_set_launch(h, ctypes.byref(L(8, 0))) == binding.E_UNSUPPORTED
-    assert lib.sslbm_set_launch(h, ctypes.byref(L(6, 0))) == binding.OK
-    assert lib.sslbm_set_launch(h, ctypes.byref(L(0, 0))) == binding.OK
+    assert got.as_dict() == L(2, 40, 2).as_dict()
+    # FP64 beyond the register budget of one wavefront
+    assert lib.sslbm_set_launch(h, ctypes.byref(L(6, 0, 1))) == binding.E_UNSUPPORTED
+    assert lib.sslbm_set_launch(h, ctypes.byref(L(3, 0, 2))) == binding.E_UNSUPPORTED
+    assert lib.sslbm_set_launch(h, ctypes.byref(L(5, 0, 1))) == binding.OK
+    assert lib.sslbm_set_launch(h, ctypes.byref(L(0, 0, 0))) == binding.OK
     assert lib.sslbm_get_launch(h, ctypes.byref(got)) == binding.OK
-    assert got.steps_per_pass >= 1 and got.rows_per_wave >= 1
+    assert got.steps_per_pass >= 1 and got.rows_per_wave >= 1 and got.cols_per_lane in (1, 2)
     lib.sslbm_destroy(h)
 
 

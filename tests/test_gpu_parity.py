@@ -101,15 +101,16 @@ def test_launch_shape_is_bitwise_invisible(dtype, bc, nx, ny):
     from paper_2603_19789_amd.binding import SSLBMError
     tried = 0
     for K in range(1, 9):
-        for H in (0, 1, 5, 16, 200):
-            try:
-                s.set_launch(K, H)
-            except SSLBMError:
-                continue  # beyond the register budget for this dtype
-            rho = rho0.clone()
-            s.run(rho, 17)
-            assert torch.equal(rho, ref_t), f"K={K} H={H}"
-            tried += 1
+        for V in (1, 2):
+            for H in (0, 1, 5, 16, 200):
+                try:
+                    s.set_launch(K, H, V)
+                except SSLBMError:
+                    continue  # beyond the register budget for this dtype
+                rho = rho0.clone()
+                s.run(rho, 17)
+                assert torch.equal(rho, ref_t), f"K={K} V={V} H={H}"
+                tried += 1
     assert tried >= 30
 
 
@@ -120,7 +121,7 @@ def test_unaligned_buffers_bitwise():
     s = Solver(nx, ny, p, dtype="f32")
     rho0 = to_gpu(inputs.random_state(nx, ny, seed=10), "f32")
     ref_t = _reference_steps(s, rho0, 9)
-    s.set_launch(3, 0)
+    s.set_launch(3, 0, 2)
     n = 5 * ny * nx
     buf = torch.empty(n + 1, dtype=torch.float32, device="cuda")
     rho = buf[1:].view(5, ny, nx)
