@@ -98,7 +98,8 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK):
         rho = torch.tensor(rho0, dtype=tdt, device="cuda")
         scratch = torch.empty_like(rho)
         solver.run(rho, warmup, scratch)
-        blocking = solver.blocking
+        shape = solver.launch()
+        blocking = shape["steps_per_pass"]
 
         def timed():
             solver.run(rho, steps, scratch)
@@ -111,6 +112,7 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK):
         fs, ds = torch.empty_like(f), torch.empty_like(rd)
         solver.run(f, rd, warmup, fs, ds)
         blocking = 1
+        shape = {"steps_per_pass": 1}
 
         def timed():
             solver.run(f, rd, steps, fs, ds)
@@ -129,7 +131,7 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK):
     bytes_per_launch = per_step * cells
     out = {
         "scheme": scheme, "dtype": dtype, "R0": r0, "steps": steps, "ms": ms,
-        "ms_per_step": ms / steps, "glups": glups, "steps_per_pass": blocking,
+        "ms_per_step": ms / steps, "glups": glups, "steps_per_pass": blocking, "launch": shape,
         "launches": launches, "avg_launch_ms": ms / launches,
         "algorithmic_bytes_per_launch": bytes_per_launch,
         "achieved_gbps": bytes_per_launch / (ms / launches * 1e-3) / 1e9,
@@ -163,20 +165,22 @@ def copy_probe(torch, reps: int = 1):
 
 
 def cpu_baseline(inputs, target_seconds: float):
-    """The FP64 CPU oracle on the headline workload: as many whole steps of the
-    4096 x 4096 grid as fit in about target_seconds."""
+    """The FP64 CPU oracle on the headline workload: whole steps of the
+    4096 x 4096 grid, in groups of 4, until about target_seconds have passed
+    (one untimed step first, so thread start-up is not counted)."""
     import oracle
     orc = oracle.load()
     threads = oracle.host_threads()
     params = inputs.c2_params(HEADLINE[2])
-    rho = inputs.c2_state(NX, NY)
+    rho = orc.sslbm_run(inputs.c2_state(NX, NY), params, 1, threads=threads)
+    n = 0
     t = time.perf_counter()
-    rho = orc.sslbm_run(rho, params, 1, threads=threads)
-    one = time.perf_counter() - t
-    n = max(1, int(target_seconds / max(one, 1e-6)) - 1)
-    t = time.perf_counter()
-    orc.sslbm_run(rho, params, n, threads=threads)
-    el = time.perf_counter() - t
+    while True:
+        rho = orc.sslbm_run(rho, params, 4, threads=threads)
+        n += 4
+        el = time.perf_counter() - t
+        if el >= target_seconds:
+            break
     return {
         "value": NX * NY * n / el / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
         "sample": f"{NX}x{NY} headline workload (R0=3, periodic), {n} FP64 steps, "
@@ -242,7 +246,7 @@ def main():
                 "achieved": hbm["achieved"], "frac": hbm["frac"]}
     roof.update({
         "traffic": traffic,
-        "kernel": f"sslbm_march_kernel<float,{k}>",
+        "kernel": f"sslbm_march_kernel<float, {k}, false, {head['launch'].get('cols_per_lane', 1)}>",
         "steps_per_pass": k,
         "flops_per_update": FLOPS_PER_UPDATE,
         "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
@@ -258,7 +262,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"sslbm-seird-{NX}x{NY}-64foci", "nx": NX, "ny": NY,
                    "R0": HEADLINE[2], "bc": "periodic", "dt": 0.01,
-                   "steps_per_pass": head["steps_per_pass"], "parallelism": "single-gpu"},
+                   "launch": head["launch"], "parallelism": "single-gpu"},
         "roofline": roof,
         "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                      for r in results],

@@ -4,8 +4,9 @@
 // post-collision population to x + c_i (periodic wrap, or half-way
 // bounce-back at a no-flux wall). One thread per node, rows of the grid on
 // blockIdx.y, so every population plane is read and written in coalesced
-// 256-node row segments (the pushed ones shifted by one node). Stores are
-// non-temporal: nothing is read back within the step.
+// 256-node row segments (the pushed ones shifted by one node). Stores keep
+// the default cache policy: the pushed rows are shifted by one node, and L2
+// merges the partial lines (non-temporal stores measured 5% slower).
 #include <hip/hip_runtime.h>
 
 #include "seird_device.h"
@@ -84,10 +85,10 @@ __global__ __launch_bounds__(BGK_THREADS) void bgk_step_kernel(const T *__restri
         for (int i = 0; i < 5; ++i) {
             const T w = weight<T>(i);
             const T fs = f[c][i] + (w * rho[c] - f[c][i]) * k.omega[c] + w * src[c];
-            __builtin_nontemporal_store(fs, &f_out[(c * 5 + dir[i]) * plane + dest[i]]);
+            f_out[(c * 5 + dir[i]) * plane + dest[i]] = fs;
         }
     }
-    __builtin_nontemporal_store(fma(k.k.kD, rho[2], dead), &d_out[cell]);
+    d_out[cell] = fma(k.k.kD, rho[2], dead);
 }
 
 template <typename T>
