@@ -46,6 +46,7 @@ FLOPS_PER_UPDATE = 46
 NX = NY = 4096
 HEADLINE = ("sslbm", "f32", 3.0)
 KERNEL_SOURCES = ["paper_2603_19789_amd/csrc/sslbm_kernels.hip",
+                  "paper_2603_19789_amd/csrc/march_core.h",
                   "paper_2603_19789_amd/csrc/seird_device.h"]
 TRAFFIC_FILE = ROOT / "profiles" / "sslbm_march_f32_4096_traffic.md"
 
@@ -64,7 +65,9 @@ def parse_args():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run one plain 1 GiB device copy (counter calibration)")
+                    help="time a single 1 GiB device copy (counter calibration runs)")
+    ap.add_argument("--ensemble-steps", type=int, default=2000,
+                    help="steps of the uneven 512-instance ensemble (0 skips it)")
     return ap.parse_args()
 
 
@@ -145,6 +148,34 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK):
     return out
 
 
+def run_ensemble(torch, inputs, Ensemble, steps):
+    """The uneven ensemble (512 square grids, sides from {64, 128, 256, 512},
+    sampled R0 and diffusivities, FP32): tuned pass shape, then `steps` steps
+    of every instance as one HIP graph launch, timed with HIP events."""
+    w = inputs.ensemble_workload(nsteps=steps)
+    ens = Ensemble(w.sizes, w.params, dtype="f32")
+    flat = ens.empty()
+    for v, s in zip(ens.views(flat), w.states()):
+        v.copy_(torch.tensor(s, dtype=torch.float32, device="cuda"))
+    scratch = ens.empty()
+    t0 = time.perf_counter()
+    shape = ens.tune(flat, scratch)
+    tune_s = time.perf_counter() - t0
+    ens.run(flat, steps, scratch, graph=True)  # capture and first replay
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    ens.run(flat, steps, scratch, graph=True)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    cells = sum(nx * ny for nx, ny in w.sizes)
+    return {"workload": w.name, "instances": len(w.sizes), "cells": cells, "steps": steps,
+            "ms": round(ms, 3), "glups": round(cells * steps / (ms * 1e-3) / 1e9, 2),
+            "launch": shape, "tune_s": round(tune_s, 3), "graph": True, "dtype": "f32"}
+
+
 def copy_probe(torch, reps: int = 1):
     """Plain device-to-device copies of 1 GiB: the practical HBM ceiling of
     this GPU (read + write GB/s), and a transfer of known size for scaling HBM
@@ -198,7 +229,7 @@ def main():
 
     import torch
 
-    from paper_2603_19789_amd import BGK, Solver, inputs
+    from paper_2603_19789_amd import BGK, Ensemble, Solver, inputs
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -228,6 +259,11 @@ def main():
         print(f"# {s} {d} R0={r:g}: {res['glups']:.1f} GLUPS, {res['steps_per_pass']} steps/pass, "
               f"{res['achieved_gbps']:.0f} GB/s per launch", file=sys.stderr, flush=True)
     copy_gbps = copy_probe(torch, 1 if args.copy_probe else 5)
+    ensemble = None
+    if args.ensemble_steps > 0:
+        ensemble = run_ensemble(torch, inputs, Ensemble, args.ensemble_steps)
+        print(f"# ensemble: {ensemble['glups']:.1f} GLUPS over {ensemble['instances']} grids, "
+              f"shape {ensemble['launch']}", file=sys.stderr, flush=True)
 
     head = results[0]
     traffic = recorded_traffic()
@@ -267,6 +303,8 @@ def main():
         "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                      for r in results],
     }
+    if ensemble is not None:
+        line["ensemble"] = ensemble
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs, args.cpu_seconds)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)

@@ -181,6 +181,49 @@ int sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_s
 /* Release a context (NULL is allowed). */
 void sslbm_destroy(sslbm_ctx *c);
 
+/*
+ * Ensembles: many independent SSLBM grids of different sizes and parameters
+ * advanced together, one launch per pass covering every instance (each
+ * instance gets exactly the bits sslbm_run would give it alone).
+ *
+ * State layout: one device buffer holds all instances; instance i is a
+ * [5][ny_i][nx_i] block at element offset sslbm_ensemble_offset(e, i)
+ * (offsets are multiples of 4 elements; gaps between blocks are unused).
+ * sslbm_ensemble_elements(e) is the buffer length in elements.
+ *
+ *   sslbm_ensemble_create: count >= 1 instances; nx, ny: host arrays of
+ *       count grid sizes (1 .. 65536 each); params: host array of count
+ *       parameter sets (each validated as in sslbm_init); dtype and bc as in
+ *       sslbm_init, shared by all instances. Host memory only; device tables
+ *       are built on first use. Errors: SSLBM_E_ARG, SSLBM_E_UNSTABLE (with
+ *       the failing instance index in *bad_instance if not NULL).
+ *   sslbm_ensemble_set_launch / get_launch: pass shape shared by all
+ *       instances, as sslbm_set_launch (zero = automatic).
+ *   sslbm_ensemble_tune: times candidate pass shapes on the current state
+ *       (reads rho, writes only scratch), keeps the fastest, reports it in
+ *       *best if not NULL. Waits for the stream.
+ *   sslbm_ensemble_run: nsteps steps of every instance, result in rho,
+ *       scratch clobbered. With SSLBM_RUN_GRAPH in flags the passes are
+ *       captured once into a HIP graph (cached for the same nsteps, buffers
+ *       and shape) and replayed as one launch; the graph runs on a stream of
+ *       the ensemble that is ordered after, and before, hip_stream. The first
+ *       call with a new shape uploads tables (synchronous).
+ */
+#define SSLBM_RUN_GRAPH 1
+typedef struct sslbm_ensemble sslbm_ensemble;
+int sslbm_ensemble_create(sslbm_ensemble **out, int count, const int *nx, const int *ny,
+                          int dtype, int bc, const sslbm_params *params, int *bad_instance);
+long long sslbm_ensemble_offset(const sslbm_ensemble *e, int instance);
+long long sslbm_ensemble_elements(const sslbm_ensemble *e);
+int sslbm_ensemble_set_launch(sslbm_ensemble *e, const sslbm_launch *shape);
+int sslbm_ensemble_get_launch(const sslbm_ensemble *e, sslbm_launch *shape);
+int sslbm_ensemble_tune(sslbm_ensemble *e, const void *rho, void *scratch, void *hip_stream,
+                        sslbm_launch *best);
+int sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps, int flags,
+                       void *hip_stream);
+int sslbm_ensemble_last_hip_error(const sslbm_ensemble *e);
+void sslbm_ensemble_destroy(sslbm_ensemble *e);
+
 /* Static description of a status code. */
 const char *sslbm_strerror(int status);
 

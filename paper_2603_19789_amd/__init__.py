@@ -7,11 +7,11 @@ package loads nothing: the library is opened on first use of ``Solver``,
 """
 from __future__ import annotations
 
-__all__ = ["Solver", "BGK", "SSLBMError", "library"]
+__all__ = ["Solver", "BGK", "Ensemble", "SSLBMError", "library"]
 
 
 def __getattr__(name):
-    if name in ("Solver", "BGK", "SSLBMError", "library"):
+    if name in ("Solver", "BGK", "Ensemble", "SSLBMError", "library"):
         from . import binding
         return getattr(binding, name)
     raise AttributeError(name)

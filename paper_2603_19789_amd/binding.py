@@ -87,6 +87,13 @@ def library() -> ctypes.CDLL:
             "sslbm_total": [vp, vp, ctypes.POINTER(ctypes.c_double), vp],
             "sslbm_strerror": [i],
             "sslbm_last_hip_error": [vp],
+            "sslbm_ensemble_create": [ctypes.POINTER(vp), i, ctypes.POINTER(i),
+                                      ctypes.POINTER(i), i, i, pp, ctypes.POINTER(i)],
+            "sslbm_ensemble_set_launch": [vp, ctypes.POINTER(Launch)],
+            "sslbm_ensemble_get_launch": [vp, ctypes.POINTER(Launch)],
+            "sslbm_ensemble_tune": [vp, vp, vp, vp, ctypes.POINTER(Launch)],
+            "sslbm_ensemble_run": [vp, vp, vp, ll, i, vp],
+            "sslbm_ensemble_last_hip_error": [vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -95,6 +102,12 @@ def library() -> ctypes.CDLL:
         lib.sslbm_strerror.restype = ctypes.c_char_p
         lib.sslbm_destroy.argtypes = [vp]
         lib.sslbm_destroy.restype = None
+        lib.sslbm_ensemble_destroy.argtypes = [vp]
+        lib.sslbm_ensemble_destroy.restype = None
+        for name in ("sslbm_ensemble_offset", "sslbm_ensemble_elements"):
+            getattr(lib, name).restype = ll
+        lib.sslbm_ensemble_offset.argtypes = [vp, i]
+        lib.sslbm_ensemble_elements.argtypes = [vp]
         _LIB = lib
     return _LIB
 
@@ -287,3 +300,101 @@ class BGK(_Context):
                                          self._tensor(rho, (5, self.ny, self.nx), "rho"),
                                          _stream(stream)), "bgk_density")
         return rho
+
+
+RUN_GRAPH = 1
+
+
+class Ensemble:
+    """Many independent SSLBM grids of different sizes and parameters,
+    advanced together (one launch per pass, optionally one HIP graph per run).
+
+    The state is one flat tensor of ``elements`` values; ``views(state)``
+    gives the (5, ny_i, nx_i) block of every instance."""
+
+    def __init__(self, sizes, params, dtype="f32", bc="periodic"):
+        torch = _torch()
+        if dtype in (torch.float32, "f32", "float32", F32):
+            self.dtype, self.code = torch.float32, F32
+        elif dtype in (torch.float64, "f64", "float64", F64):
+            self.dtype, self.code = torch.float64, F64
+        else:
+            raise ValueError(f"unsupported dtype {dtype!r}")
+        if bc not in _BC:
+            raise ValueError(f"unknown boundary condition {bc!r}")
+        sizes = [(int(nx), int(ny)) for nx, ny in sizes]
+        params = list(params)
+        if len(sizes) != len(params) or not sizes:
+            raise ValueError("need one parameter set per instance")
+        n = len(sizes)
+        self.lib = library()
+        nx = (ctypes.c_int * n)(*[s[0] for s in sizes])
+        ny = (ctypes.c_int * n)(*[s[1] for s in sizes])
+        ps = (Params * n)(*[Params.of(p) for p in params])
+        bad = ctypes.c_int(-1)
+        h = ctypes.c_void_p()
+        st = self.lib.sslbm_ensemble_create(ctypes.byref(h), n, nx, ny, self.code, _BC[bc], ps,
+                                            ctypes.byref(bad))
+        if st != OK:
+            raise SSLBMError(st, f"sslbm_ensemble_create (instance {bad.value})")
+        self.handle = h
+        self.sizes = sizes
+        self.params = params
+        self.bc = bc
+        self.offsets = [self.lib.sslbm_ensemble_offset(h, i) for i in range(n)]
+        self.elements = self.lib.sslbm_ensemble_elements(h)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.sslbm_ensemble_destroy(h)
+            self.handle = None
+
+    def _check(self, st, what):
+        if st != OK:
+            raise SSLBMError(st, what, self.lib.sslbm_ensemble_last_hip_error(self.handle))
+
+    def empty(self):
+        return _torch().empty(self.elements, dtype=self.dtype, device="cuda")
+
+    def views(self, state):
+        return [state[o:o + 5 * ny * nx].view(5, ny, nx)
+                for o, (nx, ny) in zip(self.offsets, self.sizes)]
+
+    def _flat(self, t, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != self.dtype:
+            raise ValueError(f"{name} must be a {self.dtype} tensor on the GPU")
+        if t.numel() != self.elements or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with {self.elements} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_launch(self, steps_per_pass=0, rows_per_wave=0, cols_per_lane=0):
+        shape = Launch(int(steps_per_pass), int(rows_per_wave), int(cols_per_lane))
+        self._check(self.lib.sslbm_ensemble_set_launch(self.handle, ctypes.byref(shape)),
+                    "sslbm_ensemble_set_launch")
+
+    def launch(self) -> dict:
+        shape = Launch()
+        self._check(self.lib.sslbm_ensemble_get_launch(self.handle, ctypes.byref(shape)),
+                    "sslbm_ensemble_get_launch")
+        return shape.as_dict()
+
+    def tune(self, state, scratch=None, stream=None) -> dict:
+        """Time candidate pass shapes on `state` (unchanged), keep the fastest."""
+        if scratch is None:
+            scratch = self.empty()
+        best = Launch()
+        self._check(self.lib.sslbm_ensemble_tune(self.handle, self._flat(state, "state"),
+                                                 self._flat(scratch, "scratch"), _stream(stream),
+                                                 ctypes.byref(best)), "sslbm_ensemble_tune")
+        return best.as_dict()
+
+    def run(self, state, nsteps: int, scratch=None, graph: bool = False, stream=None):
+        if scratch is None:
+            scratch = self.empty()
+        flags = RUN_GRAPH if graph else 0
+        self._check(self.lib.sslbm_ensemble_run(self.handle, self._flat(state, "state"),
+                                                self._flat(scratch, "scratch"), int(nsteps),
+                                                flags, _stream(stream)), "sslbm_ensemble_run")
+        return state

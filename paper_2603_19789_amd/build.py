@@ -7,6 +7,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
@@ -16,7 +17,8 @@ INCLUDE = ROOT / "include"
 LIBRARY = PKG / "libsslbm.so"
 ARCH = "gfx950"
 
-SOURCES = ["sslbm_api.cpp", "sslbm_kernels.hip", "bgk_kernels.hip", "reduce_kernels.hip"]
+SOURCES = ["sslbm_api.cpp", "ensemble_api.cpp", "sslbm_kernels.hip", "ensemble_kernels.hip",
+           "bgk_kernels.hip", "reduce_kernels.hip"]
 
 # -ffp-contract=off: only the fma() calls written in the kernels fuse, so every
 # launch shape and blocking depth rounds identically.
@@ -49,16 +51,19 @@ def build(verbose: bool = False) -> Path:
     """Compile every source and link the shared library (always rebuilds)."""
     objdir = PKG / "_build"
     objdir.mkdir(exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for name in SOURCES:
         src = CSRC / name
         obj = objdir / (src.stem + ".o")
-        cmd = [hipcc(), *FLAGS, "-x", "hip", f"-I{INCLUDE}", f"-I{CSRC}", "-c", str(src), "-o",
-               str(obj)]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        _run(cmd)
+        cmds.append([hipcc(), *FLAGS, "-x", "hip", f"-I{INCLUDE}", f"-I{CSRC}", "-c", str(src),
+                     "-o", str(obj)])
         objs.append(str(obj))
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as pool:
+        list(pool.map(_run, cmds))
     tmp = LIBRARY.with_suffix(".so.tmp")
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *objs]
     if verbose:

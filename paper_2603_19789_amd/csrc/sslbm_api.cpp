@@ -28,50 +28,6 @@ namespace {
 constexpr int MAX_SIDE = 1 << 20;
 constexpr long long MAX_CELLS = 1ll << 33;
 
-bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
-
-// Validation of sslbm_params and the derived per-step constants.
-int derive(const sslbm_params *p, sslbm::StepCoef *k) {
-    if (!p)
-        return SSLBM_E_ARG;
-    if (!finite_nonneg(p->beta) || !finite_nonneg(p->alpha) || !finite_nonneg(p->gamma) ||
-        !finite_nonneg(p->phi) || p->phi > 1.0)
-        return SSLBM_E_ARG;
-    if (!(std::isfinite(p->dx) && p->dx > 0.0) || !(std::isfinite(p->dt) && p->dt > 0.0))
-        return SSLBM_E_ARG;
-    for (int c = 0; c < 5; ++c)
-        if (!finite_nonneg(p->d[c]))
-            return SSLBM_E_ARG;
-
-    sslbm::StepCoef out{};
-    const double scale = p->dt / (p->dx * p->dx);
-    for (int c = 0; c < 5; ++c) {
-        out.dl[c] = p->d[c] * scale;
-        // |G(k)| <= 1 for every k iff 0 <= d_lu <= 1/4 (G = 1 - 2 d_lu (2 - cos kx - cos ky))
-        if (!(out.dl[c] <= 0.25))
-            return SSLBM_E_UNSTABLE;
-    }
-    // Linearisation at the disease-free equilibrium, Eq. (eigenvalues): the
-    // decaying E-I eigenvalue lambda_2 plus the most negative diffusion factor
-    // must stay >= -1, i.e. dt |lambda_2| + 8 max(d_lu^E, d_lu^I) <= 2.
-    const double a = p->alpha, g = p->gamma, b = p->beta;
-    const double lambda2 = 0.5 * (-(a + g) - std::sqrt((a - g) * (a - g) + 4.0 * a * b));
-    const double dmax = out.dl[1] > out.dl[2] ? out.dl[1] : out.dl[2];
-    if (p->dt * std::fabs(lambda2) + 8.0 * dmax > 2.0)
-        return SSLBM_E_UNSTABLE;
-
-    out.bdt = p->beta * p->dt;
-    out.kE = p->alpha * p->dt;
-    out.kI = p->gamma * p->dt;
-    out.kR = (1.0 - p->phi) * p->gamma * p->dt;
-    out.kD = p->phi * p->gamma * p->dt;
-    for (int c = 0; c < 4; ++c)
-        out.omega[c] = 1.0 / (0.5 + 3.0 * out.dl[c]);
-    out.diffuse_d = p->d[4] != 0.0;
-    *k = out;
-    return SSLBM_OK;
-}
-
 size_t elem_size(const sslbm_ctx *c) { return c->dtype == SSLBM_F32 ? 4 : 8; }
 size_t plane_elems(const sslbm_ctx *c) { return (size_t)c->nx * (size_t)c->ny; }
 
@@ -152,6 +108,54 @@ sslbm::MarchShape shape_for(const sslbm_ctx *c, int k, const void *in, const voi
     return s;
 }
 
+}  // namespace
+
+namespace sslbm {
+
+static bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+// Validation of sslbm_params and the derived per-step constants.
+int derive_coef(const sslbm_params *p, StepCoef *k) {
+    if (!p)
+        return SSLBM_E_ARG;
+    if (!finite_nonneg(p->beta) || !finite_nonneg(p->alpha) || !finite_nonneg(p->gamma) ||
+        !finite_nonneg(p->phi) || p->phi > 1.0)
+        return SSLBM_E_ARG;
+    if (!(std::isfinite(p->dx) && p->dx > 0.0) || !(std::isfinite(p->dt) && p->dt > 0.0))
+        return SSLBM_E_ARG;
+    for (int c = 0; c < 5; ++c)
+        if (!finite_nonneg(p->d[c]))
+            return SSLBM_E_ARG;
+
+    StepCoef out{};
+    const double scale = p->dt / (p->dx * p->dx);
+    for (int c = 0; c < 5; ++c) {
+        out.dl[c] = p->d[c] * scale;
+        // |G(k)| <= 1 for every k iff 0 <= d_lu <= 1/4 (G = 1 - 2 d_lu (2 - cos kx - cos ky))
+        if (!(out.dl[c] <= 0.25))
+            return SSLBM_E_UNSTABLE;
+    }
+    // Linearisation at the disease-free equilibrium, Eq. (eigenvalues): the
+    // decaying E-I eigenvalue lambda_2 plus the most negative diffusion factor
+    // must stay >= -1, i.e. dt |lambda_2| + 8 max(d_lu^E, d_lu^I) <= 2.
+    const double a = p->alpha, g = p->gamma, b = p->beta;
+    const double lambda2 = 0.5 * (-(a + g) - std::sqrt((a - g) * (a - g) + 4.0 * a * b));
+    const double dmax = out.dl[1] > out.dl[2] ? out.dl[1] : out.dl[2];
+    if (p->dt * std::fabs(lambda2) + 8.0 * dmax > 2.0)
+        return SSLBM_E_UNSTABLE;
+
+    out.bdt = p->beta * p->dt;
+    out.kE = p->alpha * p->dt;
+    out.kI = p->gamma * p->dt;
+    out.kR = (1.0 - p->phi) * p->gamma * p->dt;
+    out.kD = p->phi * p->gamma * p->dt;
+    for (int c = 0; c < 4; ++c)
+        out.omega[c] = 1.0 / (0.5 + 3.0 * out.dl[c]);
+    out.diffuse_d = p->d[4] != 0.0;
+    *k = out;
+    return SSLBM_OK;
+}
+
 // Split nsteps into passes of at most K steps, with an even number of passes
 // whenever nsteps >= 2 so that the ping-pong ends in the caller's buffer.
 std::vector<int> plan_passes(long long nsteps, int K) {
@@ -174,7 +178,7 @@ std::vector<int> plan_passes(long long nsteps, int K) {
     return passes;
 }
 
-}  // namespace
+}  // namespace sslbm
 
 extern "C" {
 
@@ -189,7 +193,7 @@ int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_p
     if (bc != SSLBM_PERIODIC && bc != SSLBM_NOFLUX)
         return SSLBM_E_ARG;
     sslbm::StepCoef k;
-    const int st = derive(p, &k);
+    const int st = sslbm::derive_coef(p, &k);
     if (st != SSLBM_OK)
         return st;
     sslbm_ctx *c = new (std::nothrow) sslbm_ctx();
@@ -209,7 +213,7 @@ int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p) {
     if (!c)
         return SSLBM_E_ARG;
     sslbm::StepCoef k;
-    const int st = derive(p, &k);
+    const int st = sslbm::derive_coef(p, &k);
     if (st != SSLBM_OK)
         return st;
     c->p = *p;
@@ -278,7 +282,7 @@ int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hi
     const hipStream_t s = (hipStream_t)hip_stream;
     const sslbm::GridDesc g = grid_of(c);
     void *src = rho, *dst = scratch;
-    for (int k : plan_passes(nsteps, K)) {
+    for (int k : sslbm::plan_passes(nsteps, K)) {
         const int st =
             hip_status(c, sslbm::launch_march(c->dtype, src, dst, g, c->coef, k,
                                               shape_for(c, k, src, dst), s));

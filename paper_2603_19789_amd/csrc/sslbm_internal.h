@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <vector>
+
 #include "sslbm.h"
 
 namespace sslbm {
@@ -33,6 +35,13 @@ struct MarchShape {
     int rows_per_wave;  // output rows each wavefront produces
     int cols_per_lane;  // adjacent columns per lane: 1 or 2
 };
+
+// ---- host helpers (sslbm_api.cpp) ---------------------------------------
+// Validate parameters and derive the per-step constants (SSLBM status code).
+int derive_coef(const sslbm_params *p, StepCoef *k);
+// Split nsteps into passes of at most K steps, an even number of passes
+// whenever nsteps >= 2 (so that ping-pong buffers end where they started).
+std::vector<int> plan_passes(long long nsteps, int K);
 
 // ---- launchers (sslbm_kernels.hip) --------------------------------------
 // K steps in one pass: in -> out (no overlap). K in 1..SSLBM_MAX_BLOCKING.

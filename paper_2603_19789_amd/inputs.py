@@ -162,3 +162,44 @@ def paper_test_case(nx: int, ny: int, chi: float, r0: float, seed: int, eps: flo
     rho[1] = exposed
     rho[0] = density - exposed
     return p, rho
+
+
+# ------------------------------------------------------------- ensembles --
+
+@dataclass(frozen=True)
+class EnsembleWorkload:
+    name: str
+    sizes: list = field(repr=False)      # (nx, ny) per instance
+    params: list = field(repr=False)     # Params per instance
+    nsteps: int = 2000
+    bc: str = "periodic"
+
+    def states(self):
+        """Initial state of every instance (generated on demand: 512 of them
+        take ~0.9 GB in FP64)."""
+        rng = np.random.default_rng(self._seed + 77)
+        for nx, ny in self.sizes:
+            foci = int(rng.integers(1, 9))
+            centres = list(zip(rng.integers(0, nx, foci).tolist(), rng.integers(0, ny, foci).tolist()))
+            yield gaussian_foci_state(nx, ny, centres, amplitude=0.01, width=4.0)
+
+    _seed: int = 3
+
+
+def ensemble_workload(count: int = 512, seed: int = 3, nsteps: int = 2000,
+                      sides=(64, 128, 256, 512)) -> EnsembleWorkload:
+    """Uneven ensemble: square grids with sides drawn uniformly from `sides`,
+    R0 uniform in [1.5, 5] through beta = R0 (gamma + mu), lattice
+    diffusivities of S, E, I, R log-uniform in [1e-4, 1e-2] (D at rest),
+    sigma = 0.2, gamma = 0.1, mu = 0.01, and 1 to 8 Gaussian foci of width 4
+    cells and amplitude 0.01 per instance."""
+    rng = np.random.default_rng(seed)
+    n = rng.choice(np.asarray(sides), size=count)
+    r0 = rng.uniform(1.5, 5.0, size=count)
+    dl = np.exp(rng.uniform(np.log(1e-4), np.log(1e-2), size=(count, 4)))
+    gamma, mu = 0.1, 0.01
+    params = [from_sigma_mu(r0[i] * (gamma + mu), 0.2, gamma, mu, tuple(dl[i]) + (0.0,))
+              for i in range(count)]
+    sizes = [(int(v), int(v)) for v in n]
+    return EnsembleWorkload(f"sslbm-ensemble-{count}-uneven", sizes, params, nsteps,
+                            _seed=seed)
