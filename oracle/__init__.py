@@ -67,8 +67,10 @@ class Oracle:
         lib.oracle_bgk_density.argtypes = [i, i, _DP, _DP, _DP]
         lib.oracle_bgk_step.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, _DP, _DP, i]
         lib.oracle_bgk_run.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, _DP, _DP, ll, i]
+        lib.oracle_sslbm_adjoint_step.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, _DP, _DP]
         for f in ("oracle_sslbm_step", "oracle_sslbm_run", "oracle_bgk_init",
-                  "oracle_bgk_density", "oracle_bgk_step", "oracle_bgk_run"):
+                  "oracle_bgk_density", "oracle_bgk_step", "oracle_bgk_run",
+                  "oracle_sslbm_adjoint_step"):
             getattr(lib, f).restype = ctypes.c_int
         self.lib = lib
 
@@ -104,6 +106,34 @@ class Oracle:
                                        _ptr(rho), _ptr(work), int(nsteps), threads)
         self._check(rc, "sslbm_run")
         return rho
+
+    # ------------------------------------------------------------ adjoint --
+    def sslbm_adjoint_step(self, rho, lam_next, p, bc="periodic"):
+        """Reverse of one step at state rho (time t): returns dJ/d rho(t) and the
+        step's dJ/d(beta, alpha, gamma, phi, d[0..4]) given dJ/d rho(t+dt)."""
+        rho = _f64(rho)
+        lam_next = _f64(lam_next, rho.shape)
+        _, ny, nx = rho.shape
+        lam = np.empty_like(rho)
+        grad = np.zeros(9)
+        rates, d, dx, dt = self._params(p)
+        rc = self.lib.oracle_sslbm_adjoint_step(nx, ny, _BC[bc], _ptr(rates), _ptr(d), dx, dt,
+                                                _ptr(rho), _ptr(lam_next), _ptr(lam), _ptr(grad))
+        self._check(rc, "sslbm_adjoint_step")
+        return lam, grad
+
+    def sslbm_adjoint_run(self, rho0, p, nsteps: int, lam_final, bc="periodic"):
+        """Whole-run reverse sweep: forward storing every state, then the
+        adjoint steps back to t = 0. Returns dJ/d rho0 and dJ/d params (9)."""
+        states = [_f64(rho0).copy()]
+        for _ in range(nsteps):
+            states.append(self.sslbm_step(states[-1], p, bc=bc))
+        lam = _f64(lam_final).copy()
+        grad = np.zeros(9)
+        for n in range(nsteps - 1, -1, -1):
+            lam, g = self.sslbm_adjoint_step(states[n], lam, p, bc=bc)
+            grad += g
+        return lam, grad
 
     # --------------------------------------------------------------- BGK --
     def bgk_init(self, rho):

@@ -39,6 +39,9 @@
  *
  * Parity: pinned by tests (closed forms, invariants, the paper's fourth-order
  * finite-difference reference, special cases, and planted-mistake tests).
+ * The adjoint (reverse) step at the end of this file is pinned to the forward
+ * step: the transpose identity <lam, A rho> = <A^T lam, rho> of the linear
+ * case, self-adjointness of pure diffusion, and central finite differences.
  */
 #include <math.h>
 #include <stddef.h>
@@ -313,6 +316,105 @@ int oracle_bgk_run(int nx, int ny, int bc, const double *rates, const double *d,
     if (fa != f) {
         memcpy(f, fa, sizeof(double) * 20 * plane);
         memcpy(rhoD, da, sizeof(double) * plane);
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------ adjoint --- */
+/*
+ * Reverse step of oracle_sslbm_step: given lam_next = dJ/d rho(t+dt), return
+ * lam_out = dJ/d rho(t) and add dJ/d(beta, alpha, gamma, phi, d[0..4]) of
+ * this step to grad[9]. Written as the exact transpose of the literal update
+ * above: every term w_i rho(x -/+ c_i) of rho_b / rho_f hands its weight back
+ * to the node it read (the centre itself for a no-flux ghost), and every
+ * source term hands back its partial derivatives at (x, t).
+ */
+int oracle_sslbm_adjoint_step(int nx, int ny, int bc, const double *rates, const double *d,
+                              double dx, double dt, const double *rho, const double *lam_next,
+                              double *lam_out, double *grad)
+{
+    if (!valid_grid(nx, ny, bc) || !rates || !d || !rho || !lam_next || !lam_out || !grad ||
+        lam_out == lam_next)
+        return ORACLE_E_ARG;
+    seird_rates k = unpack_rates(rates);
+    double tau[5];
+    for (int c = 0; c < 5; ++c)
+        tau[c] = relaxation_time(d[c], dx, dt);
+    size_t plane = (size_t)nx * ny;
+    memset(lam_out, 0, sizeof(double) * 5 * plane);
+
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            size_t cell = (size_t)y * nx + x;
+            double centre[5], lam[5];
+            for (int c = 0; c < 5; ++c) {
+                centre[c] = rho[c * plane + cell];
+                lam[c] = lam_next[c * plane + cell];
+            }
+            /* transport part, compartment by compartment */
+            for (int c = 0; c < 5; ++c) {
+                const double *field = rho + c * plane;
+                double *back = lam_out + c * plane;
+                /* A deceased compartment at rest moves by forward Euler only:
+                 * D(t+dt) = D(t) + phi gamma I dt, so its transport is the
+                 * identity. Its d-gradient is still the one-sided derivative of
+                 * the SSLBM update at d = 0, which coincides with that update. */
+                int at_rest = (c == CD && d[CD] == 0.0);
+                double rho_f = 0.0, rho_b = 0.0;
+                for (int i = 0; i < 5; ++i) {
+                    /* rho_b reads x - c_i with weight w_i (1 + (tau - 1)) = w_i tau */
+                    int xb = x - CX[i], yb = y - CY[i];
+                    /* rho_f reads x + c_i with weight w_i (tau - 1) */
+                    int xf = x + CX[i], yf = y + CY[i];
+                    size_t nb_b = cell, nb_f = cell;
+                    if (xb >= 0 && xb < nx && yb >= 0 && yb < ny)
+                        nb_b = (size_t)yb * nx + xb;
+                    else if (bc == BC_PERIODIC)
+                        nb_b = (size_t)(((yb % ny) + ny) % ny) * nx + ((xb % nx) + nx) % nx;
+                    if (xf >= 0 && xf < nx && yf >= 0 && yf < ny)
+                        nb_f = (size_t)yf * nx + xf;
+                    else if (bc == BC_PERIODIC)
+                        nb_f = (size_t)(((yf % ny) + ny) % ny) * nx + ((xf % nx) + nx) % nx;
+                    if (!at_rest) {
+                        back[nb_b] += lam[c] * W[i] * tau[c];
+                        back[nb_f] += lam[c] * W[i] * (tau[c] - 1.0);
+                    }
+                    rho_b += W[i] * field[nb_b];
+                    rho_f += W[i] * field[nb_f];
+                }
+                if (at_rest)
+                    back[cell] += lam[c];
+                else
+                    back[cell] += lam[c] * (-2.0) * (tau[c] - 1.0);
+                /* d out / d tau = rho_f - 2 rho_c + rho_b; tau = 1/2 + 3 d dt / dx^2 */
+                grad[4 + c] += lam[c] * (rho_f - 2.0 * centre[c] + rho_b) * 3.0 * dt / (dx * dx);
+            }
+            /* source part: out += Psi(rho(x, t)) dt */
+            double S = centre[CS], E = centre[CE], I = centre[CI], R = centre[CR];
+            double Nc = centre[CS] + centre[CE] + centre[CI] + centre[CR];
+            double lS = lam[CS], lE = lam[CE], lI = lam[CI], lR = lam[CR], lD = lam[CD];
+            if (Nc > 0.0) {
+                double F = k.beta * S * I / Nc; /* force of infection */
+                /* dF/dS, dF/dE, dF/dI, dF/dR */
+                double fS = k.beta * I / Nc - F / Nc;
+                double fE = -F / Nc;
+                double fI = k.beta * S / Nc - F / Nc;
+                double fR = -F / Nc;
+                double g = (lE - lS) * dt; /* F enters S with -1 and E with +1 */
+                lam_out[CS * plane + cell] += g * fS;
+                lam_out[CE * plane + cell] += g * fE;
+                lam_out[CI * plane + cell] += g * fI;
+                lam_out[CR * plane + cell] += g * fR;
+                grad[0] += (lE - lS) * dt * S * I / Nc;
+            }
+            /* alpha E moves E -> I; gamma I leaves I, (1 - phi) to R, phi to D */
+            lam_out[CE * plane + cell] += (lI - lE) * k.alpha * dt;
+            lam_out[CI * plane + cell] +=
+                (-lI + (1.0 - k.phi) * lR + k.phi * lD) * k.gamma * dt;
+            grad[1] += (lI - lE) * E * dt;
+            grad[2] += (-lI + (1.0 - k.phi) * lR + k.phi * lD) * I * dt;
+            grad[3] += (lD - lR) * k.gamma * I * dt;
+        }
     }
     return ORACLE_OK;
 }

@@ -5,6 +5,7 @@ strong enough to trust the oracle.
 """
 import pytest
 
+import adjoint_pins
 import oracle
 import pins
 
@@ -39,12 +40,34 @@ MUTANTS = {
                             "rhoD_out[cell] = rho[CD];"),
     "BGK equilibrium from f": ("double feq = W[i] * rho[c];", "double feq = W[i] * f;"),
     "BGK opposite table": ("OPP[5] = {0, 3, 4, 1, 2};", "OPP[5] = {0, 4, 3, 2, 1};"),
+    "adjoint back-read weight": ("back[nb_b] += lam[c] * W[i] * tau[c];",
+                                 "back[nb_b] += lam[c] * W[i] * (tau[c] - 0.5);"),
+    "adjoint centre sign": ("lam[c] * (-2.0) * (tau[c] - 1.0)", "lam[c] * 2.0 * (tau[c] - 1.0)"),
+    "adjoint resting deceased dropped": ("back[cell] += lam[c];\n", "back[cell] += 0.0;\n"),
+    "adjoint no-flux ghost to node 0": ("size_t nb_b = cell, nb_f = cell;",
+                                        "size_t nb_b = 0, nb_f = 0;"),
+    "adjoint periodic wrap": ("nb_f = (size_t)(((yf % ny) + ny) % ny) * nx + ((xf % nx) + nx) % nx;",
+                              "nb_f = (size_t)(((yf % ny) + ny) % ny) * nx + ((xf % nx) + nx + 1) % nx;"),
+    "adjoint dF/dS without -F/N": ("double fS = k.beta * I / Nc - F / Nc;",
+                                   "double fS = k.beta * I / Nc;"),
+    "adjoint dF/dE zero": ("double fE = -F / Nc;", "double fE = 0.0;"),
+    "adjoint dF/dR zero": ("double fR = -F / Nc;", "double fR = 0.0;"),
+    "adjoint incubation sign": ("(lI - lE) * k.alpha * dt;", "(lE - lI) * k.alpha * dt;"),
+    "adjoint deaths without phi": ("k.phi * lD) * k.gamma * dt;", "lD) * k.gamma * dt;"),
+    "adjoint beta gradient not over N_c": ("grad[0] += (lE - lS) * dt * S * I / Nc;",
+                                           "grad[0] += (lE - lS) * dt * S * I;"),
+    "adjoint alpha gradient from I": ("grad[1] += (lI - lE) * E * dt;",
+                                      "grad[1] += (lI - lE) * I * dt;"),
+    "adjoint gamma gradient from E": ("k.phi * lD) * I * dt;", "k.phi * lD) * E * dt;"),
+    "adjoint phi gradient sign": ("grad[3] += (lD - lR) * k.gamma * I * dt;",
+                                  "grad[3] += (lR - lD) * k.gamma * I * dt;"),
+    "adjoint d gradient without c_s^2": ("* 3.0 * dt / (dx * dx);", "* dt / (dx * dx);"),
 }
 
 
 def _caught(orc) -> list:
     failures = []
-    for check in pins.FAST_SSLBM_CHECKS + pins.FAST_BGK_CHECKS:
+    for check in pins.FAST_SSLBM_CHECKS + pins.FAST_BGK_CHECKS + adjoint_pins.FAST_ADJOINT_CHECKS:
         try:
             check(orc)
         except (AssertionError, ValueError, FloatingPointError) as exc:
