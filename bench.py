@@ -66,6 +66,8 @@ def parse_args():
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a single 1 GiB device copy (counter calibration runs)")
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="steps of the 1024x1024 FP64 adjoint gradient run (0 skips it)")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the uneven 512-instance ensemble (0 skips it)")
     return ap.parse_args()
@@ -176,6 +178,63 @@ def run_ensemble(torch, inputs, Ensemble, steps):
             "launch": shape, "tune_s": round(tune_s, 3), "graph": True, "dtype": "f32"}
 
 
+def run_adjoint(torch, inputs, Solver, steps, every=100):
+    """One gradient of the 1024 x 1024 FP64 fitting problem (16 foci, all five
+    compartments diffusing, J = 1/2 |I_T - I*|^2 + 1/2 |D_T - D*|^2 against a
+    target made with perturbed rates): the checkpointed forward run, then the
+    reverse sweep (segment recomputation + adjoint steps), timed with HIP
+    events; plus the adjoint step alone, for its bandwidth."""
+    w = inputs.c4_workload(nsteps=steps)
+    s = Solver(w.nx, w.ny, inputs.c4_target_params(), dtype="f64")
+    rho0 = torch.tensor(w.rho0, dtype=torch.float64, device="cuda")
+    target = rho0.clone()
+    s.run(target, steps)
+    s.set_params(w.params)
+    count = s.checkpoint_count(steps, every)
+    cps = torch.empty((count, 5, w.ny, w.nx), dtype=torch.float64, device="cuda")
+    ws = torch.empty(s.adjoint_workspace_bytes(every), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for rep in range(2):  # the first pass warms up; the second is timed
+        rho = rho0.clone()
+        lam = torch.zeros_like(rho)
+        grad = torch.zeros(9, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        s.run_checkpointed(rho, steps, every, checkpoints=cps)
+        ev[1].record(stream)
+        lam[2] = rho[2] - target[2]
+        lam[4] = rho[4] - target[4]
+        s.adjoint_run(cps, steps, every, lam, grad=grad, workspace=ws)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+    fwd_ms, rev_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    # the adjoint step alone (adjoint kernel + the one-block gradient sum)
+    reps = 200
+    a, b = lam.clone(), torch.empty_like(lam)
+    g = torch.zeros(9, dtype=torch.float64, device="cuda")
+    s.adjoint_step(rho0, a, b, g)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(reps):
+        s.adjoint_step(rho0, a, b, g)
+        a, b = b, a
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    step_ms = ev[0].elapsed_time(ev[1]) / reps
+    nodes = w.nx * w.ny
+    bytes_per_step = 15 * 8 * nodes  # lam and rho read, new lam written, 5 fields each
+    out = {"workload": w.name, "nx": w.nx, "ny": w.ny, "steps": steps, "checkpoint_every": every,
+           "dtype": "f64", "forward_ms": round(fwd_ms, 3), "reverse_ms": round(rev_ms, 3),
+           "gradient_ms": round(fwd_ms + rev_ms, 3),
+           "adjoint_step_ms": round(step_ms, 5),
+           "adjoint_step_gbps": round(bytes_per_step / (step_ms * 1e-3) / 1e9, 1),
+           "adjoint_bytes_per_node": 120,
+           "grad": [float(x) for x in grad.cpu().tolist()]}
+    del s
+    return out
+
+
 def copy_probe(torch, reps: int = 1):
     """Plain device-to-device copies of 1 GiB: the practical HBM ceiling of
     this GPU (read + write GB/s), and a transfer of known size for scaling HBM
@@ -265,6 +324,14 @@ def main():
         print(f"# ensemble: {ensemble['glups']:.1f} GLUPS over {ensemble['instances']} grids, "
               f"shape {ensemble['launch']}", file=sys.stderr, flush=True)
 
+    adjoint_res = None
+    if args.adjoint_steps > 0:
+        adjoint_res = run_adjoint(torch, inputs, Solver, args.adjoint_steps)
+        print(f"# adjoint: gradient in {adjoint_res['gradient_ms']:.1f} ms "
+              f"(forward {adjoint_res['forward_ms']:.1f}, reverse {adjoint_res['reverse_ms']:.1f}); "
+              f"adjoint step {adjoint_res['adjoint_step_gbps']:.0f} GB/s",
+              file=sys.stderr, flush=True)
+
     head = results[0]
     traffic = recorded_traffic()
     k = head["steps_per_pass"]
@@ -305,6 +372,8 @@ def main():
     }
     if ensemble is not None:
         line["ensemble"] = ensemble
+    if adjoint_res is not None:
+        line["adjoint"] = adjoint_res
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs, args.cpu_seconds)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)

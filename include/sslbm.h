@@ -34,6 +34,8 @@
 #ifndef SSLBM_H
 #define SSLBM_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -180,6 +182,50 @@ int sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_s
 
 /* Release a context (NULL is allowed). */
 void sslbm_destroy(sslbm_ctx *c);
+
+/*
+ * Reverse mode (adjoint). For a loss J of the state at the end of a run,
+ * lam(t) = dJ/d rho(t) satisfies lam(t) = A(rho(t))^T lam(t + dt), A the
+ * Jacobian of one step of Eq. (sslbm_final_clean) with the sources of
+ * Eq. (sources) and Eq. (rhoD) (the deceased at rest follow forward Euler).
+ * The gradient of J with respect to the parameters is the sum over steps of
+ * each step's partial derivatives contracted with lam(t + dt). Gradients are
+ * packed as grad[9] = dJ/d(beta, alpha, gamma, phi, d[0], ..., d[4]) with the
+ * physical diffusivities of sslbm_params; dJ/d d[4] at d[4] = 0 is the
+ * one-sided derivative for d[4] >= 0. All sums are deterministic.
+ *
+ *   sslbm_adjoint_step: lam_out = A(rho)^T lam_next for the state rho at time
+ *       t and lam_next = dJ/d rho(t + dt) (device buffers, layout of rho);
+ *       the step's parameter gradient is ADDED to grad, a device array of 9
+ *       doubles. lam_out may not overlap rho, lam_next or grad. The first
+ *       call allocates a small device buffer kept by the context.
+ *   sslbm_checkpoint_count: ceil(nsteps / every), the number of states
+ *       sslbm_run_checkpointed stores; -1 for nsteps < 0 or every < 1.
+ *   sslbm_run_checkpointed: as sslbm_run (result in rho, scratch clobbered),
+ *       and stores the state at steps 0, every, 2 every, ... into
+ *       checkpoints, a device buffer of sslbm_checkpoint_count states.
+ *   sslbm_adjoint_workspace_bytes: bytes of device workspace the reverse
+ *       sweep needs for this context and checkpoint interval (every states
+ *       plus 128 bytes per wavefront of the adjoint kernel); 0 for a bad
+ *       argument.
+ *   sslbm_adjoint_run: the reverse sweep of a run of nsteps steps recorded
+ *       by sslbm_run_checkpointed with the same every and parameters. On
+ *       entry lam holds dJ/d rho(T); on return dJ/d rho(0). The run's
+ *       parameter gradient is ADDED to grad (device, 9 doubles). Each segment
+ *       of `every` steps is recomputed from its checkpoint into the workspace
+ *       (never read before it is written; clobbered). Buffers may not overlap.
+ * Errors: SSLBM_E_ARG (NULL pointer, nsteps < 0, every < 1), SSLBM_E_ALIAS,
+ * SSLBM_E_HIP.
+ */
+#define SSLBM_GRAD_COUNT 9
+int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
+                       double *grad, void *hip_stream);
+long long sslbm_checkpoint_count(long long nsteps, int every);
+int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, int every,
+                           void *checkpoints, void *hip_stream);
+size_t sslbm_adjoint_workspace_bytes(const sslbm_ctx *c, int every);
+int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, int every,
+                      void *lam, double *grad, void *workspace, void *hip_stream);
 
 /*
  * Ensembles: many independent SSLBM grids of different sizes and parameters

@@ -22,6 +22,7 @@ HEADER = Path(__file__).resolve().parent.parent / "include" / "sslbm.h"
 
 OK, E_ARG, E_UNSTABLE, E_UNSUPPORTED, E_ALIAS, E_HIP, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
 F32, F64 = 0, 1
+GRAD_COUNT = 9  # dJ/d(beta, alpha, gamma, phi, d[0..4])
 PERIODIC, NOFLUX = 0, 1
 MAX_BLOCKING = 8
 _BC = {"periodic": PERIODIC, "noflux": NOFLUX, PERIODIC: PERIODIC, NOFLUX: NOFLUX}
@@ -94,6 +95,9 @@ def library() -> ctypes.CDLL:
             "sslbm_ensemble_tune": [vp, vp, vp, vp, ctypes.POINTER(Launch)],
             "sslbm_ensemble_run": [vp, vp, vp, ll, i, vp],
             "sslbm_ensemble_last_hip_error": [vp],
+            "sslbm_adjoint_step": [vp, vp, vp, vp, vp, vp],
+            "sslbm_run_checkpointed": [vp, vp, vp, ll, i, vp, vp],
+            "sslbm_adjoint_run": [vp, vp, ll, i, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -108,6 +112,10 @@ def library() -> ctypes.CDLL:
             getattr(lib, name).restype = ll
         lib.sslbm_ensemble_offset.argtypes = [vp, i]
         lib.sslbm_ensemble_elements.argtypes = [vp]
+        lib.sslbm_checkpoint_count.argtypes = [ll, i]
+        lib.sslbm_checkpoint_count.restype = ll
+        lib.sslbm_adjoint_workspace_bytes.argtypes = [vp, i]
+        lib.sslbm_adjoint_workspace_bytes.restype = ctypes.c_size_t
         _LIB = lib
     return _LIB
 
@@ -244,6 +252,88 @@ class Solver(_Context):
         a = self._tensor(rho, self.shape, "rho")
         self._check(self.lib.sslbm_total(self.handle, a, out, _stream(stream)), "sslbm_total")
         return [out[i] for i in range(5)]
+
+    # ------------------------------------------------------------ adjoint --
+    def _grad(self, grad):
+        torch = _torch()
+        if grad is None:
+            grad = torch.zeros(GRAD_COUNT, dtype=torch.float64, device="cuda")
+        if (not isinstance(grad, torch.Tensor) or grad.device.type != "cuda"
+                or grad.dtype != torch.float64 or tuple(grad.shape) != (GRAD_COUNT,)
+                or not grad.is_contiguous()):
+            raise ValueError("grad must be a contiguous float64 GPU tensor of 9 elements")
+        return grad
+
+    def adjoint_step(self, rho, lam_next, lam_out=None, grad=None, stream=None):
+        """One reverse step at state rho: returns (lam_out, grad) with
+        lam_out = dJ/d rho(t) and the step's dJ/d(beta, alpha, gamma, phi,
+        d[0..4]) added to grad (float64, 9, zeros when not given)."""
+        if lam_out is None:
+            lam_out = self.empty(*self.shape)
+        grad = self._grad(grad)
+        a = self._tensor(rho, self.shape, "rho")
+        b = self._tensor(lam_next, self.shape, "lam_next")
+        c = self._tensor(lam_out, self.shape, "lam_out")
+        self._check(self.lib.sslbm_adjoint_step(self.handle, a, b, c,
+                                                ctypes.c_void_p(grad.data_ptr()),
+                                                _stream(stream)), "sslbm_adjoint_step")
+        return lam_out, grad
+
+    def checkpoint_count(self, nsteps: int, every: int) -> int:
+        n = self.lib.sslbm_checkpoint_count(int(nsteps), int(every))
+        if n < 0:
+            raise ValueError("nsteps must be >= 0 and every >= 1")
+        return n
+
+    def run_checkpointed(self, rho, nsteps: int, every: int, checkpoints=None, scratch=None,
+                         stream=None):
+        """nsteps steps in place in rho, storing the state every `every` steps
+        (steps 0, every, ...). Returns the checkpoints tensor."""
+        count = self.checkpoint_count(nsteps, every)
+        if checkpoints is None:
+            checkpoints = self.empty(max(count, 1), *self.shape)
+        if scratch is None:
+            scratch = self.empty(*self.shape)
+        a = self._tensor(rho, self.shape, "rho")
+        b = self._tensor(scratch, self.shape, "scratch")
+        if (tuple(checkpoints.shape[1:]) != self.shape or checkpoints.shape[0] < count
+                or checkpoints.dtype != self.dtype or not checkpoints.is_contiguous()
+                or checkpoints.device.type != "cuda"):
+            raise ValueError(f"checkpoints must be a contiguous GPU tensor of >= {count} states")
+        self._check(self.lib.sslbm_run_checkpointed(
+            self.handle, a, b, int(nsteps), int(every), ctypes.c_void_p(checkpoints.data_ptr()),
+            _stream(stream)), "sslbm_run_checkpointed")
+        return checkpoints
+
+    def adjoint_workspace_bytes(self, every: int) -> int:
+        n = self.lib.sslbm_adjoint_workspace_bytes(self.handle, int(every))
+        if n == 0:
+            raise ValueError("every must be >= 1")
+        return n
+
+    def adjoint_run(self, checkpoints, nsteps: int, every: int, lam, grad=None, workspace=None,
+                    stream=None):
+        """Reverse sweep of a run recorded by run_checkpointed: lam holds
+        dJ/d rho(T) on entry and dJ/d rho(0) on return; the parameter gradient
+        is added to grad. Returns (lam, grad)."""
+        torch = _torch()
+        count = self.checkpoint_count(nsteps, every)
+        if (checkpoints.shape[0] < count or tuple(checkpoints.shape[1:]) != self.shape
+                or checkpoints.dtype != self.dtype or not checkpoints.is_contiguous()
+                or checkpoints.device.type != "cuda"):
+            raise ValueError(f"checkpoints must hold >= {count} states of shape {self.shape}")
+        need = self.adjoint_workspace_bytes(every)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+        if workspace.numel() * workspace.element_size() < need or workspace.device.type != "cuda":
+            raise ValueError(f"workspace must be a GPU tensor of at least {need} bytes")
+        grad = self._grad(grad)
+        a = self._tensor(lam, self.shape, "lam")
+        self._check(self.lib.sslbm_adjoint_run(
+            self.handle, ctypes.c_void_p(checkpoints.data_ptr()), int(nsteps), int(every), a,
+            ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+            _stream(stream)), "sslbm_adjoint_run")
+        return lam, grad
 
 
 class BGK(_Context):

@@ -1,0 +1,193 @@
+// adjoint_api.cpp -- host side of the reverse-mode entry points of sslbm.h:
+// one adjoint step, a forward run that stores checkpoints, and the
+// checkpointed reverse sweep over a whole run.
+//
+// Reverse sweep. The forward run stores the state every `every` steps. The
+// sweep takes the segments from the last to the first: it recomputes the
+// states of a segment from its checkpoint with single forward steps (each
+// state is needed by one adjoint step), then runs the segment's adjoint
+// steps backwards. Work: about two forward steps and one adjoint step per
+// step of the run; memory: the checkpoints plus one segment of states.
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "adjoint_internal.h"
+#include "sslbm.h"
+#include "sslbm_internal.h"
+
+namespace {
+
+size_t elem_size(const sslbm_ctx *c) { return c->dtype == SSLBM_F32 ? 4 : 8; }
+size_t state_bytes(const sslbm_ctx *c) {
+    return 5 * (size_t)c->nx * (size_t)c->ny * elem_size(c);
+}
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return na && nb && x < y + nb && y < x + na;
+}
+
+int hip_status(sslbm_ctx *c, hipError_t e) {
+    if (e == hipSuccess)
+        return SSLBM_OK;
+    c->last_hip = (int)e;
+    return SSLBM_E_HIP;
+}
+
+sslbm::GridDesc grid_of(const sslbm_ctx *c) {
+    sslbm::GridDesc g;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.plane = (long long)c->nx * c->ny;
+    g.bc = c->bc;
+    return g;
+}
+
+sslbm::AdjFactors factors_of(const sslbm_ctx *c) {
+    sslbm::AdjFactors f;
+    f.dt = c->p.dt;
+    f.gamma_dt = c->p.gamma * c->p.dt;
+    f.phi = c->p.phi;
+    f.dt_dx2 = c->p.dt / (c->p.dx * c->p.dx);
+    return f;
+}
+
+size_t partials_bytes(const sslbm::AdjShape &s) {
+    return (size_t)s.slots() * sslbm::ADJ_SLOT * sizeof(double);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
+                       double *grad, void *hip_stream) {
+    if (!c || !rho || !lam_next || !lam_out || !grad)
+        return SSLBM_E_ARG;
+    const size_t bytes = state_bytes(c);
+    if (overlap(lam_out, bytes, lam_next, bytes) || overlap(lam_out, bytes, rho, bytes) ||
+        overlap(grad, 9 * sizeof(double), lam_out, bytes))
+        return SSLBM_E_ALIAS;
+    const sslbm::AdjShape shape = sslbm::adjoint_shape(c->nx, c->ny);
+    int dev = 0;
+    int st = hip_status(c, hipGetDevice(&dev));
+    if (st != SSLBM_OK)
+        return st;
+    if (!c->adj_partials || c->adj_slots < shape.slots() || c->adj_device != dev) {
+        if (c->adj_partials)
+            (void)hipFree(c->adj_partials);
+        c->adj_partials = nullptr;
+        st = hip_status(c, hipMalloc((void **)&c->adj_partials, partials_bytes(shape)));
+        if (st != SSLBM_OK)
+            return st;
+        c->adj_slots = shape.slots();
+        c->adj_device = dev;
+    }
+    const hipStream_t s = (hipStream_t)hip_stream;
+    st = hip_status(c, sslbm::launch_adjoint(c->dtype, rho, lam_next, lam_out, grid_of(c),
+                                             c->coef, shape, c->adj_partials, true, s));
+    if (st != SSLBM_OK)
+        return st;
+    return hip_status(c, sslbm::launch_adjoint_finish(c->adj_partials, (int)shape.slots(),
+                                                      factors_of(c), grad, s));
+}
+
+long long sslbm_checkpoint_count(long long nsteps, int every) {
+    if (nsteps < 0 || every < 1)
+        return -1;
+    return (nsteps + every - 1) / every;
+}
+
+int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, int every,
+                           void *checkpoints, void *hip_stream) {
+    if (!c || !rho || !scratch || !checkpoints || nsteps < 0 || every < 1)
+        return SSLBM_E_ARG;
+    const size_t bytes = state_bytes(c);
+    const long long count = sslbm_checkpoint_count(nsteps, every);
+    const size_t cp_bytes = (size_t)count * bytes;
+    if (overlap(checkpoints, cp_bytes, rho, bytes) || overlap(checkpoints, cp_bytes, scratch, bytes) ||
+        overlap(rho, bytes, scratch, bytes))
+        return SSLBM_E_ALIAS;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    for (long long k = 0; k < count; ++k) {
+        char *slot = static_cast<char *>(checkpoints) + (size_t)k * bytes;
+        int st = hip_status(c, hipMemcpyAsync(slot, rho, bytes, hipMemcpyDeviceToDevice, s));
+        if (st != SSLBM_OK)
+            return st;
+        const long long n = nsteps - k * every < every ? nsteps - k * every : every;
+        st = sslbm_run(c, rho, scratch, n, hip_stream);
+        if (st != SSLBM_OK)
+            return st;
+    }
+    return SSLBM_OK;
+}
+
+size_t sslbm_adjoint_workspace_bytes(const sslbm_ctx *c, int every) {
+    if (!c || every < 1)
+        return 0;
+    // states 1 .. every-1 of a segment, one adjoint field, the partials slots
+    return align256((size_t)every * state_bytes(c)) +
+           align256(partials_bytes(sslbm::adjoint_shape(c->nx, c->ny)));
+}
+
+int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, int every,
+                      void *lam, double *grad, void *workspace, void *hip_stream) {
+    if (!c || !checkpoints || !lam || !grad || !workspace || nsteps < 0 || every < 1)
+        return SSLBM_E_ARG;
+    const size_t bytes = state_bytes(c);
+    const long long count = sslbm_checkpoint_count(nsteps, every);
+    const size_t cp_bytes = (size_t)count * bytes;
+    const size_t ws_bytes = sslbm_adjoint_workspace_bytes(c, every);
+    if (overlap(lam, bytes, checkpoints, cp_bytes) || overlap(lam, bytes, workspace, ws_bytes) ||
+        overlap(checkpoints, cp_bytes, workspace, ws_bytes) ||
+        overlap(grad, 9 * sizeof(double), lam, bytes) ||
+        overlap(grad, 9 * sizeof(double), workspace, ws_bytes))
+        return SSLBM_E_ALIAS;
+    if (nsteps == 0)
+        return SSLBM_OK;
+
+    char *ws = static_cast<char *>(workspace);
+    // segment state i (1 <= i < every) at ws + (i - 1) * bytes; the second
+    // adjoint buffer after them; the partials at the end
+    char *lam_alt = ws + (size_t)(every - 1) * bytes;
+    double *partials = reinterpret_cast<double *>(ws + align256((size_t)every * bytes));
+    const sslbm::AdjShape shape = sslbm::adjoint_shape(c->nx, c->ny);
+    const sslbm::GridDesc g = grid_of(c);
+    const hipStream_t s = (hipStream_t)hip_stream;
+
+    void *cur = lam, *nxt = lam_alt;
+    bool first = true;
+    for (long long k = count - 1; k >= 0; --k) {
+        const char *cp = static_cast<const char *>(checkpoints) + (size_t)k * bytes;
+        const long long len = nsteps - k * every < every ? nsteps - k * every : every;
+        auto state = [&](long long i) -> const void * {
+            return i == 0 ? (const void *)cp : (const void *)(ws + (size_t)(i - 1) * bytes);
+        };
+        for (long long i = 1; i < len; ++i) {
+            const int st = sslbm_step(c, state(i - 1), ws + (size_t)(i - 1) * bytes, hip_stream);
+            if (st != SSLBM_OK)
+                return st;
+        }
+        for (long long i = len - 1; i >= 0; --i) {
+            const int st = hip_status(c, sslbm::launch_adjoint(c->dtype, state(i), cur, nxt, g,
+                                                               c->coef, shape, partials, first, s));
+            if (st != SSLBM_OK)
+                return st;
+            first = false;
+            void *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+    }
+    if (cur != lam) {
+        const int st = hip_status(c, hipMemcpyAsync(lam, cur, bytes, hipMemcpyDeviceToDevice, s));
+        if (st != SSLBM_OK)
+            return st;
+    }
+    return hip_status(c, sslbm::launch_adjoint_finish(partials, (int)shape.slots(), factors_of(c),
+                                                      grad, s));
+}
+
+}  // extern "C"

@@ -1,0 +1,302 @@
+// adjoint_kernels.hip -- reverse (adjoint) SSLBM step on gfx950.
+//
+// For a loss J of the state at the end of a run, the adjoint field
+// lam(t) = dJ/d rho(t) obeys lam(t) = A(rho(t))^T lam(t + dt), A the Jacobian
+// of one step (Eq. sslbm_final_clean with the sources of Eq. (sources) and
+// Eq. (rhoD)). On D2Q5 the transport part of the step is c + dl L c, L the
+// five-point Laplacian with periodic wrap or mirror (no-flux) ghosts; L is
+// symmetric on both, so its transpose is the same stencil applied to lam.
+// The source part is pointwise: its transpose multiplies lam(x) by the
+// transposed 5x5 Jacobian of Psi dt at rho(x, t).
+//
+// Parameter gradients of one step, summed over the grid (dt and the factors
+// that do not vary in space are applied once, at the end of a run):
+//   dJ/dbeta  += dt sum (lamE - lamS) S I / Nc
+//   dJ/dalpha += dt sum (lamI - lamE) E
+//   dJ/dgamma += dt sum (-lamI + (1 - phi) lamR + phi lamD) I
+//   dJ/dphi   += gamma dt sum (lamD - lamR) I
+//   dJ/dd^C   += dt/dx^2 sum lam^C L rho^C = dt/dx^2 sum rho^C L lam^C
+// (the last by the symmetry of L: the kernel needs rho only at the node).
+//
+// Layout and traversal are those of the forward pass at one step per pass:
+// one wavefront per strip of 64 columns (62 output columns and one halo
+// column on each side) walking down a chunk of rows; lam rows sit in a
+// 4-slot register ring unrolled so that slots are compile-time constants,
+// east/west neighbours come through DPP lane shifts, rows are addressed by
+// buffer descriptors. Per output row the wavefront reads one row of lam and
+// one row of rho (5 fields each) and writes one row of the new lam.
+//
+// The nine sums are kept per lane in FP64, reduced across the wavefront at
+// the end of its chunk and added to the wavefront's own slot of a partials
+// buffer; the same wavefront owns the same slot at every step, so a run's
+// sums are deterministic. A final one-block kernel adds the slots in a fixed
+// order and applies the factors.
+#include <hip/hip_runtime.h>
+
+#include "adjoint_internal.h"
+#include "march_core.h"
+
+namespace sslbm {
+
+namespace {
+
+constexpr int ADJ_HX = 1;                 // halo columns per strip side
+constexpr int ADJ_WU = 64 - 2 * ADJ_HX;   // output columns per strip
+
+template <typename T>
+struct AdjState {
+    T lam[RING][5];  // lam(t + dt) rows, ring slot = row mod 4
+    T rho[2][5];     // rho(t) of the output row (and of the next one, in flight)
+};
+
+template <typename T>
+struct AdjArgs {
+    const T *__restrict__ rho;
+    const T *__restrict__ lam;
+    T *__restrict__ out;
+    GridDesc g;
+    Coef<T> k;
+    unsigned xoff;  // byte offset of the lane's memory column within a row
+    unsigned xo;    // byte offset of the lane's output column
+    bool out_col;   // the lane's column is an output column
+    int j0;         // first lam row read (one above the first output row)
+};
+
+template <typename T, int SL>
+__device__ __forceinline__ void fetch_lam(AdjState<T> &st, const AdjArgs<T> &a, int t) {
+    const long long row = (long long)map_index(a.j0 + t, a.g.ny, a.g.bc) * a.g.nx;
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        st.lam[SL][c] =
+            buf_load(row_resource(a.lam + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
+}
+
+template <typename T, int SR>
+__device__ __forceinline__ void fetch_rho(AdjState<T> &st, const AdjArgs<T> &a, int y) {
+    const long long row = (long long)map_index(y, a.g.ny, a.g.bc) * a.g.nx;
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        st.rho[SR][c] =
+            buf_load(row_resource(a.rho + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
+}
+
+// Output row j0 + t - 1 at phase P = t mod 4: lam rows t-2, t-1, t are in
+// slots P-2, P-1, P; rho of the row is in slot P mod 2.
+template <typename T, bool DIFFUSE_D, int P>
+__device__ __forceinline__ void adjoint_row(AdjState<T> &st, const AdjArgs<T> &a, int t,
+                                            double acc[ADJ_SUMS]) {
+    constexpr int su = (P + 2) % RING, sm = (P + 3) % RING, sd = P % RING, sr = P % 2;
+    const Coef<T> &k = a.k;
+    T lc[5], lap[5], o[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        lc[c] = st.lam[sm][c];
+        const T nb = (st.lam[su][c] + st.lam[sd][c]) +
+                     (lane_from_right(lc[c]) + lane_from_left(lc[c]));
+        lap[c] = fma(T(-4), lc[c], nb);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        o[c] = fma(k.dl[c], lap[c], lc[c]);
+    o[4] = DIFFUSE_D ? fma(k.dl[4], lap[4], lc[4]) : lc[4];
+
+    const T S = st.rho[sr][0], E = st.rho[sr][1], I = st.rho[sr][2], R = st.rho[sr][3];
+    const T nc = (S + E) + (I + R);
+    const bool live = nc > T(0);
+    const T r = live ? quotient(T(1), nc) : T(0);  // 1 / Nc, or 0 where F = 0
+    const T sir = (S * I) * r;                     // S I / Nc = F / beta
+    const T qi = k.bdt * (I * r);                  // dt dF/dS + dt F/Nc
+    const T qs = k.bdt * (S * r);                  // dt dF/dI + dt F/Nc
+    const T w = k.bdt * (sir * r);                 // dt F / Nc
+    const T g = lc[1] - lc[0];                     // F moves S -> E
+    const T de = lc[2] - lc[1];                    // alpha E moves E -> I
+    o[0] = fma(g, qi - w, o[0]);
+    o[1] = fma(de, k.kE, fma(-g, w, o[1]));
+    o[2] = fma(g, qs - w, o[2]) + (fma(lc[3], k.kR, lc[4] * k.kD) - lc[2] * k.kI);
+    o[3] = fma(-g, w, o[3]);
+
+    if (a.out_col) {
+        const long long row = (long long)(a.j0 + t - 1) * a.g.nx;
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+            buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), a.xo, o[c]);
+        acc[0] += (double)(g * sir);
+        acc[1] += (double)(de * E);
+        acc[2] += (double)(lc[2] * I);
+        acc[3] += (double)(lc[3] * I);
+        acc[4] += (double)(lc[4] * I);
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+            acc[5 + c] += (double)(st.rho[sr][c] * lap[c]);
+    }
+}
+
+// Steady row t at phase P: fetch lam row t + 1 and the rho row of the next
+// output row, then the output row of t.
+template <typename T, bool DIFFUSE_D, int P>
+__device__ __forceinline__ void adjoint_steady(AdjState<T> &st, const AdjArgs<T> &a, int t,
+                                               double acc[ADJ_SUMS]) {
+    fetch_lam<T, (P + 1) % RING>(st, a, t + 1);
+    fetch_rho<T, (P + 1) % 2>(st, a, a.j0 + t);
+    adjoint_row<T, DIFFUSE_D, P>(st, a, t, acc);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+template <typename T, bool DIFFUSE_D>
+__global__ __launch_bounds__(BLOCK_THREADS) void adjoint_kernel(
+    const T *__restrict__ rho, const T *__restrict__ lam, T *__restrict__ out, GridDesc g,
+    Coef<T> k, int strips, int chunks, int rows, double *__restrict__ partials, int first) {
+    const int wave = __builtin_amdgcn_readfirstlane(
+        xcd_tile(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    if (wave >= strips * chunks)
+        return;  // whole wavefront leaves together
+    const int strip = wave / chunks, chunk = wave - strip * chunks;
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, g.ny);
+    const int lane = threadIdx.x & 63;
+    const int xl = strip * ADJ_WU - ADJ_HX + lane;
+
+    AdjArgs<T> a;
+    a.rho = rho;
+    a.lam = lam;
+    a.out = out;
+    a.g = g;
+    a.k = k;
+    a.xoff = (unsigned)map_index(xl, g.nx, g.bc) * (unsigned)sizeof(T);
+    a.xo = (unsigned)xl * (unsigned)sizeof(T);
+    a.out_col = lane >= ADJ_HX && lane < ADJ_HX + ADJ_WU && xl < g.nx;
+    a.j0 = y0 - 1;
+
+    AdjState<T> st;
+#pragma unroll
+    for (int s = 0; s < RING; ++s)
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+            st.lam[s][c] = T(0);
+    double acc[ADJ_SUMS];
+#pragma unroll
+    for (int j = 0; j < ADJ_SUMS; ++j)
+        acc[j] = 0.0;
+
+    // lam rows j0 .. y1 (t = 0 .. tend); the output row of t is j0 + t - 1
+    const int tend = y1 - y0 + 2;
+    fetch_lam<T, 0>(st, a, 0);
+    fetch_lam<T, 1>(st, a, 1);
+    fetch_lam<T, 2>(st, a, 2);
+    fetch_rho<T, 0>(st, a, y0);
+    int t = 2;
+    for (; t + RING <= tend; t += RING) {
+        adjoint_steady<T, DIFFUSE_D, 2>(st, a, t, acc);
+        adjoint_steady<T, DIFFUSE_D, 3>(st, a, t + 1, acc);
+        adjoint_steady<T, DIFFUSE_D, 0>(st, a, t + 2, acc);
+        adjoint_steady<T, DIFFUSE_D, 1>(st, a, t + 3, acc);
+    }
+    if (t < tend)
+        adjoint_steady<T, DIFFUSE_D, 2>(st, a, t, acc);
+    if (t + 1 < tend)
+        adjoint_steady<T, DIFFUSE_D, 3>(st, a, t + 1, acc);
+    if (t + 2 < tend)
+        adjoint_steady<T, DIFFUSE_D, 0>(st, a, t + 2, acc);
+
+#pragma unroll
+    for (int j = 0; j < ADJ_SUMS; ++j)
+        acc[j] = wave_sum(acc[j]);
+    if (lane == 0) {
+        double *slot = partials + (long long)wave * ADJ_SLOT;
+#pragma unroll
+        for (int j = 0; j < ADJ_SUMS; ++j)
+            slot[j] = first ? acc[j] : slot[j] + acc[j];
+    }
+}
+
+// Sum of the slots in a fixed order (strided per thread, then a fixed tree),
+// scaled into the nine parameter gradients and added to grad.
+__global__ __launch_bounds__(256) void adjoint_finish_kernel(const double *__restrict__ partials,
+                                                             int slots, AdjFactors f,
+                                                             double *__restrict__ grad) {
+    __shared__ double part[ADJ_SUMS][256];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < ADJ_SUMS; ++j) {
+        double s = 0.0;
+        for (int i = tid; i < slots; i += 256)
+            s += partials[(long long)i * ADJ_SLOT + j];
+        part[j][tid] = s;
+    }
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (tid < h) {
+#pragma unroll
+            for (int j = 0; j < ADJ_SUMS; ++j)
+                part[j][tid] += part[j][tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid < 9) {
+        double v;
+        switch (tid) {
+        case 0: v = f.dt * part[0][0]; break;
+        case 1: v = f.dt * part[1][0]; break;
+        case 2: v = f.dt * ((1.0 - f.phi) * part[3][0] + f.phi * part[4][0] - part[2][0]); break;
+        case 3: v = f.gamma_dt * (part[4][0] - part[3][0]); break;
+        default: v = f.dt_dx2 * part[5 + (tid - 4)][0]; break;
+        }
+        grad[tid] += v;
+    }
+}
+
+template <typename T, bool DD>
+hipError_t launch_t(const void *rho, const void *lam, void *out, const GridDesc &g,
+                    const StepCoef &k, const AdjShape &s, double *partials, bool first,
+                    hipStream_t st) {
+    const int waves = s.strips * s.chunks;
+    const int blocks = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    hipLaunchKernelGGL((adjoint_kernel<T, DD>), dim3((unsigned)blocks), dim3(BLOCK_THREADS), 0,
+                       st, static_cast<const T *>(rho), static_cast<const T *>(lam),
+                       static_cast<T *>(out), g, cast_coef<T>(k), s.strips, s.chunks, s.rows,
+                       partials, first ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+AdjShape adjoint_shape(int nx, int ny) {
+    AdjShape s;
+    s.strips = (nx + ADJ_WU - 1) / ADJ_WU;
+    // chunks of at least 8 rows (halo rows below 25 % of the lam reads), and
+    // no more wavefronts than about two rounds of resident ones need
+    const long long target = 4096;
+    long long rows = ((long long)ny * s.strips + target - 1) / target;
+    if (rows < 8)
+        rows = 8;
+    if (rows > ny)
+        rows = ny;
+    s.rows = (int)rows;
+    s.chunks = (int)((ny + rows - 1) / rows);
+    return s;
+}
+
+hipError_t launch_adjoint(int dtype, const void *rho, const void *lam, void *out,
+                          const GridDesc &g, const StepCoef &k, const AdjShape &s,
+                          double *partials, bool first, hipStream_t st) {
+    if (dtype == SSLBM_F32)
+        return k.diffuse_d ? launch_t<float, true>(rho, lam, out, g, k, s, partials, first, st)
+                           : launch_t<float, false>(rho, lam, out, g, k, s, partials, first, st);
+    return k.diffuse_d ? launch_t<double, true>(rho, lam, out, g, k, s, partials, first, st)
+                       : launch_t<double, false>(rho, lam, out, g, k, s, partials, first, st);
+}
+
+hipError_t launch_adjoint_finish(const double *partials, int slots, const AdjFactors &f,
+                                 double *grad, hipStream_t st) {
+    hipLaunchKernelGGL(adjoint_finish_kernel, dim3(1), dim3(256), 0, st, partials, slots, f,
+                       grad);
+    return hipGetLastError();
+}
+
+}  // namespace sslbm

@@ -12,17 +12,6 @@
 #include "sslbm.h"
 #include "sslbm_internal.h"
 
-struct sslbm_ctx {
-    int nx = 0, ny = 0, dtype = 0, bc = 0;
-    sslbm_params p{};
-    sslbm::StepCoef coef{};
-    sslbm_launch launch{};  // requested pass shape; zero fields = automatic
-    int last_hip = 0;
-    double *partials = nullptr;  // device buffer of sslbm_total
-    int partial_blocks = 0;
-    int partial_device = -1;
-};
-
 namespace {
 
 constexpr int MAX_SIDE = 1 << 20;
@@ -426,6 +415,8 @@ void sslbm_destroy(sslbm_ctx *c) {
         return;
     if (c->partials)
         (void)hipFree(c->partials);
+    if (c->adj_partials)
+        (void)hipFree(c->adj_partials);
     delete c;
 }
 

@@ -70,3 +70,18 @@ hipError_t launch_total(int dtype, const void *rho, const GridDesc &g, double *p
                         int blocks, double *out5_device, hipStream_t s);
 
 }  // namespace sslbm
+
+// The state behind the opaque sslbm_ctx handle.
+struct sslbm_ctx {
+    int nx = 0, ny = 0, dtype = 0, bc = 0;
+    sslbm_params p{};
+    sslbm::StepCoef coef{};
+    sslbm_launch launch{};  // requested pass shape; zero fields = automatic
+    int last_hip = 0;
+    double *partials = nullptr;  // device buffer of sslbm_total
+    int partial_blocks = 0;
+    int partial_device = -1;
+    double *adj_partials = nullptr;  // device slots of sslbm_adjoint_step
+    long long adj_slots = 0;
+    int adj_device = -1;
+};

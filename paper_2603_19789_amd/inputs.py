@@ -203,3 +203,36 @@ def ensemble_workload(count: int = 512, seed: int = 3, nsteps: int = 2000,
     sizes = [(int(v), int(v)) for v in n]
     return EnsembleWorkload(f"sslbm-ensemble-{count}-uneven", sizes, params, nsteps,
                             _seed=seed)
+
+
+# --------------------------------------------------------------- adjoint --
+
+def c4_params() -> Params:
+    """Rates beta=0.5, sigma=0.2, gamma=0.1, mu=0.01 and lattice diffusivity
+    1e-3 for all five compartments (D included, so that central differences in
+    every diffusivity stay inside d >= 0); dx = 1, dt = 0.01."""
+    return from_sigma_mu(0.5, 0.2, 0.1, 0.01, (1e-3,) * 5)
+
+
+C4_SIGMA_MU = (0.5, 0.2, 0.1, 0.01)
+
+
+def c4_perturbed_sigma_mu(seed: int = 4) -> tuple:
+    """(beta, sigma, gamma, mu) of the fitting target: each rate of C4
+    multiplied by 1 + 0.05 N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    return tuple(float(v * (1.0 + 0.05 * z)) for v, z in zip(C4_SIGMA_MU, rng.normal(size=4)))
+
+
+def c4_target_params(seed: int = 4) -> Params:
+    return from_sigma_mu(*c4_perturbed_sigma_mu(seed), (1e-3,) * 5)
+
+
+def c4_state(nx: int = 1024, ny: int = 1024, seed: int = 4) -> np.ndarray:
+    """16 seeded Gaussian foci of infected, amplitude 0.01, width 8 cells."""
+    return gaussian_foci_state(nx, ny, seeded_centres(nx, ny, 16, seed), 0.01, 8.0)
+
+
+def c4_workload(nx: int = 1024, ny: int = 1024, seed: int = 4, nsteps: int = 2000) -> Workload:
+    return Workload(f"sslbm-adjoint-{nx}x{ny}-fp64", nx, ny, c4_params(), c4_state(nx, ny, seed),
+                    nsteps)

@@ -10,7 +10,8 @@ from paper_2603_19789_amd import binding
 from paper_2603_19789_amd.binding import Params
 from paper_2603_19789_amd.inputs import c1_params
 
-SIG_RE = re.compile(r"^\s*(?:int|void|const\s+char\s*\*)\s*\**\s*(\w+)\s*\(", re.M)
+SIG_RE = re.compile(r"^\s*(?:int|void|long\s+long|size_t|const\s+char\s*\*)\s*\**\s*(\w+)\s*\(",
+                    re.M)
 
 
 @pytest.fixture(scope="module")
@@ -30,7 +31,9 @@ def test_header_declares_the_entry_points():
                      "bgk_run", "bgk_density", "sslbm_total", "sslbm_destroy",
                      "sslbm_set_params", "sslbm_set_blocking", "sslbm_get_blocking",
                      "sslbm_set_launch", "sslbm_get_launch",
-                     "sslbm_strerror", "sslbm_last_hip_error"):
+                     "sslbm_strerror", "sslbm_last_hip_error", "sslbm_adjoint_step",
+                     "sslbm_run_checkpointed", "sslbm_adjoint_run", "sslbm_checkpoint_count",
+                     "sslbm_adjoint_workspace_bytes", "sslbm_ensemble_run"):
         assert required in names
 
 
@@ -177,3 +180,37 @@ def test_python_solver_raises_on_bad_parameters():
     with pytest.raises(binding.SSLBMError) as exc:
         binding.Solver(8, 8, c1_params().with_(d=(100.0,) * 5))
     assert exc.value.status == binding.E_UNSTABLE
+
+
+def test_adjoint_host_checks(lib):
+    """Reverse-mode entry points: counts, workspace size and argument errors,
+    all decided on the host."""
+    assert lib.sslbm_checkpoint_count(0, 100) == 0
+    assert lib.sslbm_checkpoint_count(2000, 100) == 20
+    assert lib.sslbm_checkpoint_count(2001, 100) == 21
+    assert lib.sslbm_checkpoint_count(5, 0) == -1
+    assert lib.sslbm_checkpoint_count(-1, 3) == -1
+    st, h = _init(lib, 130, 45, binding.F64)
+    assert st == binding.OK
+    state = 5 * 130 * 45 * 8
+    ws = lib.sslbm_adjoint_workspace_bytes(h, 10)
+    assert ws >= 10 * state and ws % 256 == 0
+    assert lib.sslbm_adjoint_workspace_bytes(h, 0) == 0
+    assert lib.sslbm_adjoint_workspace_bytes(None, 10) == 0
+    vp = ctypes.c_void_p
+    a, b, c, g, w = (vp(0x100000000 * k) for k in (1, 2, 3, 4, 5))
+    assert lib.sslbm_adjoint_step(h, None, b, c, g, None) == binding.E_ARG
+    assert lib.sslbm_adjoint_step(h, a, b, c, None, None) == binding.E_ARG
+    assert lib.sslbm_adjoint_step(h, a, b, b, g, None) == binding.E_ALIAS
+    assert lib.sslbm_adjoint_step(h, a, b, a, g, None) == binding.E_ALIAS
+    assert lib.sslbm_adjoint_step(h, a, b, c, vp(c.value + 8), None) == binding.E_ALIAS
+    assert lib.sslbm_run_checkpointed(h, a, b, 10, 0, c, None) == binding.E_ARG
+    assert lib.sslbm_run_checkpointed(h, a, b, -1, 5, c, None) == binding.E_ARG
+    assert lib.sslbm_run_checkpointed(h, a, b, 30, 10, vp(a.value - state), None) == binding.E_ALIAS
+    assert lib.sslbm_adjoint_run(h, a, 10, 0, b, g, w, None) == binding.E_ARG
+    assert lib.sslbm_adjoint_run(h, a, 10, 5, b, g, None, None) == binding.E_ARG
+    assert lib.sslbm_adjoint_run(h, a, 10, 5, vp(w.value + 64), g, w, None) == binding.E_ALIAS
+    assert lib.sslbm_adjoint_run(h, a, 10, 5, b, vp(w.value + 8), w, None) == binding.E_ALIAS
+    # nothing to do for a run of zero steps: no GPU call is made
+    assert lib.sslbm_adjoint_run(h, a, 0, 5, b, g, w, None) == binding.OK
+    lib.sslbm_destroy(h)

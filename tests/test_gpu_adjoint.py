@@ -1,0 +1,260 @@
+"""Adjoint (reverse) SSLBM step on the GPU against the FP64 CPU oracle's
+adjoint, and the checkpointed reverse sweep against central differences of
+the forward run (through the C ABI).
+
+Tolerances. The adjoint field: relative L2 per compartment 1e-12 (FP64) and
+1e-5 (FP32), as for the forward step. Parameter gradients are sums over every
+node and step taken in another order than the oracle's (and, for the
+diffusivities, through the equal sum of rho L lam instead of lam L rho): the
+gradient vector must agree to 1e-10 (FP64) and 1e-4 (FP32) of its norm.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import TOL, max_rel_l2, to_gpu, to_np
+from paper_2603_19789_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2603_19789_amd import Solver  # noqa: E402
+from paper_2603_19789_amd import adjoint  # noqa: E402
+
+GRAD_TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def rough_params(d_dead):
+    """Rates and lattice diffusivities large enough that every adjoint term
+    matters in one step."""
+    return inputs.Params(beta=0.9, alpha=0.6, gamma=0.45, phi=0.3,
+                         d=tuple(v * 0.25 / 0.1 for v in (0.11, 0.05, 0.17, 0.08, d_dead)),
+                         dx=0.5, dt=0.1)
+
+
+def grad_err(got, want) -> float:
+    return float(np.linalg.norm(got - want) / max(np.linalg.norm(want), 1e-300))
+
+
+SHAPES = [(1, 1), (5, 2), (62, 8), (63, 9), (130, 45), (201, 67)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("d_dead", [0.0, 0.07])
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_adjoint_step(orc, nx, ny, bc, d_dead, dtype):
+    """One reverse step on random states and adjoint fields, tiny to several
+    strips and chunks with ragged edges."""
+    print(f"adjoint step {nx}x{ny} {bc} d_D={d_dead} {dtype}", flush=True)
+    p = rough_params(d_dead)
+    rng = np.random.default_rng(nx * 1000 + ny)
+    rho = inputs.random_state(nx, ny, seed=nx + ny, infected_scale=0.4)
+    lam = rng.normal(size=rho.shape)
+    if dtype == "f32":  # the oracle sees exactly the FP32 inputs
+        rho, lam = rho.astype(np.float32).astype(np.float64), lam.astype(np.float32).astype(np.float64)
+    want_lam, want_grad = orc.sslbm_adjoint_step(rho, lam, p, bc=bc)
+    s = Solver(nx, ny, p, dtype=dtype, bc=bc)
+    got_lam, got_grad = s.adjoint_step(to_gpu(rho, dtype), to_gpu(lam, dtype))
+    torch.cuda.synchronize()
+    err = max_rel_l2(to_np(got_lam), want_lam)
+    gerr = grad_err(to_np(got_grad), want_grad)
+    print(f"  lam err {err:.3e} grad err {gerr:.3e}")
+    assert err <= TOL[dtype]
+    assert gerr <= GRAD_TOL[dtype]
+
+
+def test_adjoint_step_accumulates_into_grad(orc):
+    """grad is added to, not overwritten."""
+    p = rough_params(0.07)
+    rho = inputs.random_state(40, 30, seed=3)
+    lam = np.random.default_rng(3).normal(size=rho.shape)
+    s = Solver(40, 30, p, dtype="f64")
+    start = torch.arange(9, dtype=torch.float64, device="cuda")
+    _, g = s.adjoint_step(to_gpu(rho, "f64"), to_gpu(lam, "f64"), grad=start.clone())
+    _, want = orc.sslbm_adjoint_step(rho, lam, p)
+    assert grad_err(to_np(g) - np.arange(9), want) <= 1e-10
+
+
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("nsteps,every", [(37, 10), (20, 20), (9, 4), (1, 100)])
+def test_adjoint_run_matches_oracle(orc, bc, nsteps, every):
+    """Checkpointed reverse sweep (ragged last segment, one segment, one
+    step) against the oracle's sweep over stored states, FP64."""
+    print(f"adjoint run {bc} n={nsteps} every={every}", flush=True)
+    nx, ny = 70, 52
+    p = rough_params(0.07).with_(dt=0.05, d=tuple(v * 0.5 for v in rough_params(0.07).d))
+    rho0 = inputs.random_state(nx, ny, seed=nsteps, infected_scale=0.4)
+    weight = np.random.default_rng(every).normal(size=rho0.shape)
+    want_lam, want_grad = orc.sslbm_adjoint_run(rho0, p, nsteps, weight, bc=bc)
+    s = Solver(nx, ny, p, dtype="f64", bc=bc)
+    rho = to_gpu(rho0, "f64")
+    cps = s.run_checkpointed(rho, nsteps, every)
+    lam, grad = s.adjoint_run(cps, nsteps, every, to_gpu(weight, "f64"))
+    torch.cuda.synchronize()
+    err = max_rel_l2(to_np(lam), want_lam)
+    gerr = grad_err(to_np(grad), want_grad)
+    print(f"  lam0 err {err:.3e} grad err {gerr:.3e}")
+    assert err <= TOL["f64"]
+    assert gerr <= GRAD_TOL["f64"]
+
+
+def test_checkpoints_are_the_states():
+    """run_checkpointed ends where run ends, and checkpoint k is the state
+    after k * every steps, bit for bit."""
+    p = inputs.c1_params()
+    rho0 = inputs.random_state(96, 80, seed=5)
+    s = Solver(96, 80, p, dtype="f32")
+    a = to_gpu(rho0, "f32")
+    cps = s.run_checkpointed(a, 53, 10)
+    b = to_gpu(rho0, "f32")
+    s.run(b, 53)
+    assert torch.equal(a, b)
+    for k in range(6):
+        c = to_gpu(rho0, "f32")
+        s.run(c, 10 * k)
+        assert torch.equal(cps[k], c), k
+
+
+def test_adjoint_run_is_deterministic():
+    p = rough_params(0.07)
+    s = Solver(150, 90, p, dtype="f64")
+    rho0 = to_gpu(inputs.random_state(150, 90, seed=8), "f64")
+    lam0 = torch.randn(5, 90, 150, dtype=torch.float64, device="cuda",
+                       generator=torch.Generator("cuda").manual_seed(1))
+    outs = []
+    for _ in range(2):
+        rho = rho0.clone()
+        cps = s.run_checkpointed(rho, 30, 7)
+        outs.append(s.adjoint_run(cps, 30, 7, lam0.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def _c4_loss_fn(solver, rho0, target, nsteps):
+    """J = 1/2 |I_T - I*|^2 + 1/2 |D_T - D*|^2 from the forward run alone."""
+    def loss(params):
+        solver.set_params(params)
+        rho = rho0.clone()
+        solver.run(rho, nsteps)
+        return 0.5 * float(((rho[2] - target[0]) ** 2).sum() + ((rho[4] - target[1]) ** 2).sum())
+    return loss
+
+
+def _c4_setup(nx, ny, nsteps):
+    w = inputs.c4_workload(nx, ny, nsteps=nsteps)
+    s = Solver(nx, ny, w.params, dtype="f64")
+    rho0 = to_gpu(w.rho0, "f64")
+    tgt = rho0.clone()
+    s.set_params(inputs.c4_target_params())
+    s.run(tgt, nsteps)
+    s.set_params(w.params)
+    return w, s, rho0, torch.stack([tgt[2], tgt[4]]).contiguous()
+
+
+def test_c4_oracle_adjoint_small(orc):
+    """C4-shaped problem (16 foci, five diffusing compartments, I and D
+    misfit) on 128x128 over 200 steps: the GPU sweep against the FP64 CPU
+    adjoint, field and gradients. The target comes from the oracle here."""
+    nx = ny = 128
+    nsteps, every = 200, 50
+    w = inputs.c4_workload(nx, ny, nsteps=nsteps)
+    target = orc.sslbm_run(w.rho0, inputs.c4_target_params(), nsteps)
+    final = orc.sslbm_run(w.rho0, w.params, nsteps)
+    lam_t = np.zeros_like(final)
+    lam_t[2], lam_t[4] = final[2] - target[2], final[4] - target[4]
+    want_lam, want_grad = orc.sslbm_adjoint_run(w.rho0, w.params, nsteps, lam_t)
+    s = Solver(nx, ny, w.params, dtype="f64")
+    rho = to_gpu(w.rho0, "f64")
+    cps = s.run_checkpointed(rho, nsteps, every)
+    lam = torch.zeros_like(rho)
+    lam[2], lam[4] = rho[2] - to_gpu(target[2], "f64"), rho[4] - to_gpu(target[4], "f64")
+    lam, grad = s.adjoint_run(cps, nsteps, every, lam)
+    torch.cuda.synchronize()
+    err = max_rel_l2(to_np(lam), want_lam)
+    gerr = grad_err(to_np(grad), want_grad)
+    print(f"C4-small lam0 err {err:.3e} grad err {gerr:.3e}")
+    assert err <= TOL["f64"]
+    assert gerr <= GRAD_TOL["f64"]
+
+
+def test_c4_full_gradient_against_central_differences():
+    """C4 at full size: 1024x1024, FP64, 2000 steps, checkpoints every 100.
+    Each of the nine parameter gradients against central differences of the
+    forward run with a relative step of 1e-6. The differences carry rounding
+    of order 1e-16 |J| / h and a truncation error of order h^2; they agree
+    with the adjoint to 1e-6 of the gradient's norm."""
+    nx = ny = 1024
+    nsteps, every = 2000, 100
+    w, s, rho0, target = _c4_setup(nx, ny, nsteps)
+    rho = rho0.clone()
+    cps = s.run_checkpointed(rho, nsteps, every)
+    lam = torch.zeros_like(rho)
+    lam[2], lam[4] = rho[2] - target[0], rho[4] - target[1]
+    _, grad = s.adjoint_run(cps, nsteps, every, lam)
+    grad = to_np(grad)
+    loss = _c4_loss_fn(s, rho0, target, nsteps)
+    base = adjoint.theta_of(w.params).numpy()
+    fd = np.empty(9)
+    for j in range(9):
+        h = 1e-6 * abs(base[j])
+        up, down = base.copy(), base.copy()
+        up[j] += h
+        down[j] -= h
+        fd[j] = (loss(adjoint.params_of(torch.tensor(up), w.params.dx, w.params.dt))
+                 - loss(adjoint.params_of(torch.tensor(down), w.params.dx, w.params.dt))) / (2 * h)
+        print(f"  {adjoint.PARAM_NAMES[j]:6s} adjoint {grad[j]: .10e}  fd {fd[j]: .10e}")
+    s.set_params(w.params)
+    err = float(np.linalg.norm(grad - fd) / np.linalg.norm(fd))
+    print(f"C4 full: gradient vs central differences {err:.3e}")
+    assert err <= 1e-6
+    for j in range(9):
+        assert abs(grad[j] - fd[j]) <= 1e-5 * abs(fd[j]) + 1e-7 * np.linalg.norm(fd), j
+
+
+def test_autograd_function_sigma_mu():
+    """torch.autograd through the reverse sweep: gradients with respect to
+    (beta, sigma, gamma, mu) and rho0 equal the sweep's gradients pushed
+    through the chain rule, and sigma's against a central difference."""
+    nx, ny, nsteps, every = 96, 96, 120, 25
+    w, s, rho0, target = _c4_setup(nx, ny, nsteps)
+    rates = torch.tensor(inputs.C4_SIGMA_MU, dtype=torch.float64, requires_grad=True)
+    d = torch.tensor(w.params.d, dtype=torch.float64, requires_grad=True)
+    r0 = rho0.clone().requires_grad_(True)
+
+    def objective(rates_, d_):
+        theta = adjoint.theta_from_sigma_mu(rates_[0], rates_[1], rates_[2], rates_[3], d_)
+        out = adjoint.sslbm_run(r0, theta, s, nsteps, every)
+        return 0.5 * (((out[2] - target[0]) ** 2).sum() + ((out[4] - target[1]) ** 2).sum())
+
+    j = objective(rates, d)
+    j.backward()
+    assert r0.grad is not None and r0.grad.shape == rho0.shape
+    # sigma (alpha in the paper's notation) enters theta directly
+    h = 1e-6 * inputs.C4_SIGMA_MU[1]
+    with torch.no_grad():
+        up = rates.detach().clone()
+        up[1] += h
+        dn = rates.detach().clone()
+        dn[1] -= h
+        fd = (float(objective(up, d.detach())) - float(objective(dn, d.detach()))) / (2 * h)
+    print(f"dJ/dsigma autograd {float(rates.grad[1]):.10e} fd {fd:.10e}")
+    assert abs(float(rates.grad[1]) - fd) <= 1e-5 * abs(fd)
+    # mu through gamma_p = gamma + mu and phi = mu / (gamma + mu)
+    theta = adjoint.theta_from_sigma_mu(*[torch.tensor(v, dtype=torch.float64)
+                                          for v in inputs.C4_SIGMA_MU], d.detach())
+    s.set_params(adjoint.params_of(theta, w.params.dx, w.params.dt))
+    rho = rho0.clone()
+    cps = s.run_checkpointed(rho, nsteps, every)
+    lam = torch.zeros_like(rho)
+    lam[2], lam[4] = rho[2] - target[0], rho[4] - target[1]
+    _, g = s.adjoint_run(cps, nsteps, every, lam)
+    g = to_np(g)
+    gam, mu = inputs.C4_SIGMA_MU[2], inputs.C4_SIGMA_MU[3]
+    dmu = g[2] + g[3] * gam / (gam + mu) ** 2
+    assert abs(float(rates.grad[3]) - dmu) <= 1e-12 * abs(dmu)
+    assert np.allclose(d.grad.numpy(), g[4:], rtol=1e-12, atol=0)
