@@ -317,7 +317,6 @@ def main():
         results.append(res)
         print(f"# {s} {d} R0={r:g}: {res['glups']:.1f} GLUPS, {res['steps_per_pass']} steps/pass, "
               f"{res['achieved_gbps']:.0f} GB/s per launch", file=sys.stderr, flush=True)
-    copy_gbps = copy_probe(torch, 1 if args.copy_probe else 5)
     ensemble = None
     if args.ensemble_steps > 0:
         ensemble = run_ensemble(torch, inputs, Ensemble, args.ensemble_steps)
@@ -331,6 +330,10 @@ def main():
               f"(forward {adjoint_res['forward_ms']:.1f}, reverse {adjoint_res['reverse_ms']:.1f}); "
               f"adjoint step {adjoint_res['adjoint_step_gbps']:.0f} GB/s",
               file=sys.stderr, flush=True)
+
+    # last, so that the 1 GiB copy is the final copy dispatch of the run (the
+    # transfer of known size that HBM counters are scaled by)
+    copy_gbps = copy_probe(torch, 1 if args.copy_probe else 5)
 
     head = results[0]
     traffic = recorded_traffic()

@@ -234,7 +234,8 @@ int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, i
  *
  * State layout: one device buffer holds all instances; instance i is a
  * [5][ny_i][nx_i] block at element offset sslbm_ensemble_offset(e, i)
- * (offsets are multiples of 4 elements; gaps between blocks are unused).
+ * (offsets are multiples of 4 elements; gaps between blocks hold no data and
+ * their contents after a run are unspecified).
  * sslbm_ensemble_elements(e) is the buffer length in elements.
  *
  *   sslbm_ensemble_create: count >= 1 instances; nx, ny: host arrays of

@@ -22,6 +22,12 @@ def _params(i):
     return base.with_(beta=0.3 + 0.1 * i, d=inputs.lattice_to_physical(dl, base.dx, base.dt))
 
 
+def _same(ens, a, b) -> bool:
+    """Bitwise equality of every instance (the gaps between instance blocks
+    hold no data and are not compared)."""
+    return all(torch.equal(x, y) for x, y in zip(ens.views(a), ens.views(b)))
+
+
 def _load(ens, states, dtype):
     flat = ens.empty()
     flat.zero_()
@@ -69,7 +75,7 @@ def test_every_shape_gives_the_same_bits(dtype):
                     continue
                 got = start.clone()
                 ens.run(got, 11)
-                assert torch.equal(got, ref), f"K={K} V={V} H={H}"
+                assert _same(ens, got, ref), f"K={K} V={V} H={H}"
                 tried += 1
     assert tried >= 8
 
@@ -88,7 +94,7 @@ def test_graph_replays_match_eager_runs():
         got = start.clone()
         ens.run(got, 9, scratch, graph=True)
         torch.cuda.synchronize()
-        assert torch.equal(got, eager), f"replay {rep}"
+        assert _same(ens, got, eager), f"replay {rep}"
         # eager work between replays, on the same buffers
         tmp = start.clone()
         ens.run(tmp, 3, scratch)
@@ -96,7 +102,7 @@ def test_graph_replays_match_eager_runs():
     # a graph on other buffers is a different graph
     other = start.clone()
     ens.run(other, 9, graph=True)
-    assert torch.equal(other, eager)
+    assert _same(ens, other, eager)
 
 
 def test_tuner_keeps_state_and_results():
@@ -109,11 +115,11 @@ def test_tuner_keeps_state_and_results():
     ens.run(ref, 10)
     state = start.clone()
     best = ens.tune(state)
-    assert torch.equal(state, start)
+    assert torch.equal(state, start)  # the tuner writes nothing, gaps included
     assert best == ens.launch()
     assert best["steps_per_pass"] >= 2
     ens.run(state, 10)
-    assert torch.equal(state, ref)
+    assert _same(ens, state, ref)
 
 
 def test_uneven_512_ensemble_sampled():
