@@ -215,22 +215,30 @@ __global__ __launch_bounds__(BLOCK_THREADS) void adjoint_kernel(
     }
 }
 
-// Sum of the slots in a fixed order (strided per thread, then a fixed tree),
-// scaled into the nine parameter gradients and added to grad.
-__global__ __launch_bounds__(256) void adjoint_finish_kernel(const double *__restrict__ partials,
-                                                             int slots, AdjFactors f,
-                                                             double *__restrict__ grad) {
-    __shared__ double part[ADJ_SUMS][256];
+// Sum of the slots in a fixed order (slot-strided per thread, then a fixed
+// tree), scaled into the nine parameter gradients and added to grad. Each
+// thread reads whole slots, so its loads are independent and contiguous.
+constexpr int FINISH_THREADS = 512;
+
+__global__ __launch_bounds__(FINISH_THREADS) void adjoint_finish_kernel(
+    const double *__restrict__ partials, int slots, AdjFactors f, double *__restrict__ grad) {
+    __shared__ double part[ADJ_SUMS][FINISH_THREADS];
     const int tid = threadIdx.x;
+    double s[ADJ_SUMS];
 #pragma unroll
-    for (int j = 0; j < ADJ_SUMS; ++j) {
-        double s = 0.0;
-        for (int i = tid; i < slots; i += 256)
-            s += partials[(long long)i * ADJ_SLOT + j];
-        part[j][tid] = s;
+    for (int j = 0; j < ADJ_SUMS; ++j)
+        s[j] = 0.0;
+    for (int i = tid; i < slots; i += FINISH_THREADS) {
+        const double *slot = partials + (long long)i * ADJ_SLOT;
+#pragma unroll
+        for (int j = 0; j < ADJ_SUMS; ++j)
+            s[j] += slot[j];
     }
+#pragma unroll
+    for (int j = 0; j < ADJ_SUMS; ++j)
+        part[j][tid] = s[j];
     __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
+    for (int h = FINISH_THREADS / 2; h >= 1; h >>= 1) {
         if (tid < h) {
 #pragma unroll
             for (int j = 0; j < ADJ_SUMS; ++j)
@@ -269,10 +277,17 @@ hipError_t launch_t(const void *rho, const void *lam, void *out, const GridDesc 
 AdjShape adjoint_shape(int nx, int ny) {
     AdjShape s;
     s.strips = (nx + ADJ_WU - 1) / ADJ_WU;
-    // chunks of at least 8 rows (halo rows below 25 % of the lam reads), and
-    // no more wavefronts than about two rounds of resident ones need
-    const long long target = 4096;
-    long long rows = ((long long)ny * s.strips + target - 1) / target;
+    // The shortest chunks (at least 8 rows) for which the grid fits in one
+    // workgroup of 4 wavefronts per CU of the 256 of an MI355X: measured at
+    // 1024 x 1024 in FP64, one wavefront per SIMD on long chunks beats more
+    // wavefronts on short ones (25.5 us per step at 24 rows, 31 us at 16 rows
+    // when 16 CUs get a second workgroup, 29 us at 3 rows), since every chunk
+    // re-reads two halo rows and restarts its row pipeline.
+    const long long target = 256 * WAVES_PER_BLOCK;
+    long long chunks = target / s.strips;
+    if (chunks < 1)
+        chunks = 1;
+    long long rows = (ny + chunks - 1) / chunks;
     if (rows < 8)
         rows = 8;
     if (rows > ny)
@@ -294,8 +309,8 @@ hipError_t launch_adjoint(int dtype, const void *rho, const void *lam, void *out
 
 hipError_t launch_adjoint_finish(const double *partials, int slots, const AdjFactors &f,
                                  double *grad, hipStream_t st) {
-    hipLaunchKernelGGL(adjoint_finish_kernel, dim3(1), dim3(256), 0, st, partials, slots, f,
-                       grad);
+    hipLaunchKernelGGL(adjoint_finish_kernel, dim3(1), dim3(FINISH_THREADS), 0, st, partials,
+                       slots, f, grad);
     return hipGetLastError();
 }
 
