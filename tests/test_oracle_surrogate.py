@@ -1,0 +1,148 @@
+"""The surrogate's FP64 oracle operations against independent definitions
+(CPU only): FFT circular convolution, shifted identities, adjoint
+(inner-product) identities, finite differences and Adam's closed form."""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+
+RNG = np.random.default_rng(7)
+
+
+def _inner(a, b):
+    return float(np.sum(np.asarray(a) * np.asarray(b)))
+
+
+def test_conv_matches_fft_circular_correlation():
+    """Each (out, in) channel pair is a circular cross-correlation with the
+    3x3 kernel embedded in an H x W image: IFFT(conj(FFT(k)) FFT(x))."""
+    n, h, w, ci, co = 2, 9, 12, 3, 4
+    x = RNG.normal(size=(n, h, w, ci))
+    wt = RNG.normal(size=(co, 9, ci))
+    b = RNG.normal(size=co)
+    got = S.conv3x3(x, wt, b)
+    for o in range(co):
+        want = np.full((n, h, w), b[o])
+        for i in range(ci):
+            k = np.zeros((h, w))
+            for t, (dy, dx) in enumerate(S.TAPS):
+                k[dy % h, dx % w] = wt[o, t, i]
+            kf = np.conj(np.fft.fft2(k))
+            for m in range(n):
+                want[m] += np.real(np.fft.ifft2(kf * np.fft.fft2(x[m, :, :, i])))
+        assert np.max(np.abs(got[..., o] - want)) < 1e-12
+
+
+def test_conv_centre_and_shift_taps():
+    x = RNG.normal(size=(1, 5, 7, 3))
+    w = np.zeros((3, 9, 3))
+    w[:, 4, :] = np.eye(3)  # centre tap, identity
+    assert np.array_equal(S.conv3x3(x, w), x)
+    w = np.zeros((3, 9, 3))
+    w[:, 5, :] = np.eye(3)  # tap (dy, dx) = (0, +1): reads the east neighbour
+    assert np.array_equal(S.conv3x3(x, w)[0, 2, 3], x[0, 2, 4])
+    assert np.array_equal(S.conv3x3(x, w)[0, 2, 6], x[0, 2, 0])  # periodic wrap
+    w = np.zeros((3, 9, 3))
+    w[:, 1, :] = np.eye(3)  # tap (-1, 0): reads the row above
+    assert np.array_equal(S.conv3x3(x, w)[0, 0, 3], x[0, 4, 3])
+
+
+def test_conv_adjoint_identities():
+    """<dZ, conv(X, W)> = <bwd_data(dZ, W), X> = <bwd_weight(X, dZ), W>,
+    and <dZ, b> summed = <db, b>."""
+    n, h, w, ci, co = 2, 6, 8, 5, 3
+    x = RNG.normal(size=(n, h, w, ci))
+    wt = RNG.normal(size=(co, 9, ci))
+    dz = RNG.normal(size=(n, h, w, co))
+    b = RNG.normal(size=co)
+    lhs = _inner(dz, S.conv3x3(x, wt))
+    assert abs(lhs - _inner(S.conv3x3_bwd_data(dz, wt), x)) < 1e-10 * abs(lhs) + 1e-10
+    dw, db = S.conv3x3_bwd_weight(x, dz)
+    assert abs(lhs - _inner(dw, wt)) < 1e-10 * abs(lhs) + 1e-10
+    bias_part = _inner(dz, S.conv3x3(x, wt, b)) - lhs
+    assert abs(bias_part - _inner(db, b)) < 1e-10 * (abs(bias_part) + 1)
+
+
+def test_pool_and_upsample_adjoints():
+    a = RNG.normal(size=(2, 4, 6, 3))
+    big = RNG.normal(size=(2, 8, 12, 3))
+    assert abs(_inner(S.up2(a), big) - _inner(a, S.up2_bwd(big))) < 1e-12
+    assert abs(_inner(S.pool2(big), a) - _inner(big, S.pool2_bwd(a))) < 1e-12
+    assert np.allclose(S.pool2(S.up2(a)), a, rtol=0, atol=1e-15)
+    assert S.pool2(np.arange(16.0).reshape(1, 4, 4, 1))[0, 0, 0, 0] == (0 + 1 + 4 + 5) / 4
+
+
+def test_leaky_derivative_fd():
+    z = RNG.normal(size=200)
+    z = z[np.abs(z) > 1e-3]
+    c = RNG.normal(size=z.size)
+    h = 1e-7
+    fd = (S.leaky(z + h, 0.1) - S.leaky(z - h, 0.1)) / (2 * h) * c
+    assert np.allclose(S.leaky_bwd(c, S.leaky(z, 0.1), 0.1), fd, rtol=1e-7, atol=1e-9)
+
+
+def test_adam_constant_gradient_closed_form():
+    """For a constant gradient g the bias-corrected moments are exactly g and
+    g^2, so every step moves theta by lr g / (|g| + eps)."""
+    g = np.array([0.3, -2.0, 1e-3])
+    theta, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 26):
+        theta, m, v = S.adam(theta, g, m, v, t, lr=0.01)
+    assert np.allclose(theta, -25 * 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_unet_shapes_and_parameter_count():
+    spec = S.unet_spec(levels=4, base=32, cin=16, cout=16)
+    convs = [op for op in spec if op[0] == "conv"]
+    assert len(convs) == 15
+    params = sum(9 * ci * co + co for _, ci, co, _ in convs)
+    assert 1.9e6 < params < 2.0e6
+    assert convs[8][1:3] == (256 + 128, 128)  # first decoder conv: upsampled + skip
+
+
+@pytest.mark.parametrize("slope", [0.1])
+def test_unet_gradient_fd(slope):
+    """Whole-network gradients (a small U-Net) against central differences
+    of the forward pass, for the input and for weights of every layer."""
+    spec = S.unet_spec(levels=3, base=4, cin=3, cout=2)
+    rng = np.random.default_rng(11)
+    weights = []
+    for op in spec:
+        if op[0] == "conv":
+            _, ci, co, _ = op
+            weights.append((rng.normal(size=(co, 9, ci)) / np.sqrt(9 * ci), rng.normal(size=co) * 0.1))
+    x = rng.normal(size=(2, 8, 8, 3))
+    target = rng.normal(size=(2, 8, 8, 2))
+
+    def loss(ws, xx):
+        out, _ = S.unet_forward(xx, ws, spec, slope)
+        return 0.5 * np.sum((out - target) ** 2)
+
+    out, tape = S.unet_forward(x, weights, spec, slope)
+    grads, dx = S.unet_backward(out - target, weights, tape, slope)
+    h = 1e-6
+    for k in range(len(weights)):
+        w, b = weights[k]
+        for _ in range(2):
+            idx = tuple(rng.integers(0, s) for s in w.shape)
+            wp, wm = w.copy(), w.copy()
+            wp[idx] += h
+            wm[idx] -= h
+            up = [(wp, b) if j == k else weights[j] for j in range(len(weights))]
+            dn = [(wm, b) if j == k else weights[j] for j in range(len(weights))]
+            fd = (loss(up, x) - loss(dn, x)) / (2 * h)
+            assert abs(grads[k][0][idx] - fd) <= 1e-5 * max(1.0, abs(fd)), (k, idx)
+        o = rng.integers(0, b.size)
+        bp, bm = b.copy(), b.copy()
+        bp[o] += h
+        bm[o] -= h
+        fd = (loss([(w, bp) if j == k else weights[j] for j in range(len(weights))], x)
+              - loss([(w, bm) if j == k else weights[j] for j in range(len(weights))], x)) / (2 * h)
+        assert abs(grads[k][1][o] - fd) <= 1e-5 * max(1.0, abs(fd)), (k, "bias")
+    for _ in range(4):
+        idx = tuple(rng.integers(0, s) for s in x.shape)
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (loss(weights, xp) - loss(weights, xm)) / (2 * h)
+        assert abs(dx[idx] - fd) <= 1e-5 * max(1.0, abs(fd)), idx
