@@ -1,0 +1,124 @@
+/*
+ * surrogate.h -- C ABI of the learned surrogate's operations in libsslbm.so:
+ * a convolutional network that advances the SEIRD state of the SSLBM
+ * (arXiv 2603.19789, Eq. (sslbm_final_clean)) by a fixed number of steps,
+ * trained on the GPU on states produced by the SSLBM itself. The paper has
+ * no surrogate; these are standard deep-learning operations, on BF16 MFMA
+ * with FP32 accumulation.
+ *
+ * Conventions (as sslbm.h): int status codes from sslbm.h, host-side
+ * validation before any HIP call, caller-owned device buffers, work enqueued
+ * on hip_stream (a hipStream_t as void*, NULL = default stream).
+ *
+ * Tensors
+ * -------
+ * - Activation views: BF16 (stored as uint16), NHWC. Element (n, y, x, c) of a
+ *   view is at p[((n h + y) w + x) pitch + c]. pitch >= channels; channels,
+ *   pitch and the view's start (in elements from a 16-byte aligned buffer)
+ *   are multiples of 8, and the pointer itself is 16-byte aligned. A view
+ *   may be a channel slice of a wider buffer (pitch > channels).
+ * - Weights: BF16 [cout][9][cin], tap = 3 (dy + 1) + (dx + 1) for the
+ *   neighbour (y + dy, x + dx); bias FP32 [cout].
+ * - Convolutions are 3x3 cross-correlations with periodic padding:
+ *   y[n,y,x,o] = b[o] + sum_{dy,dx,i} W[o,tap,i] x[n,(y+dy) mod h,(x+dx) mod w,i].
+ * - Densities: FP32 [batch][5][h][w] (the SSLBM layout, S E I R D).
+ * Errors: SSLBM_E_ARG (NULL pointer, size <= 0, a channel count, pitch or
+ * pointer not meeting the alignment above, odd h or w where halving is
+ * needed, w not a multiple of 8 for the weight gradient, workspace too
+ * small), SSLBM_E_HIP.
+ */
+#ifndef SSLBM_SURROGATE_H
+#define SSLBM_SURROGATE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SUR_LEAKY 1   /* apply y = z > 0 ? z : slope z after the bias */
+#define SUR_OUT_F32 2 /* write the output view in FP32 instead of BF16 */
+
+/* Forward convolution (see above); y may not overlap x. */
+int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
+                        const void *weight, const float *bias, void *y, int y_pitch, int cout,
+                        int flags, float slope, void *hip_stream);
+
+/* dx = d(sum dz * conv(x)) / dx for weight [cout][9][cin]: the convolution
+ * of dz with the weights flipped in space and transposed in channels, built
+ * in `flip_scratch` (device, >= 18 cout cin bytes). dx is overwritten. */
+int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
+                              const void *weight, int cin, void *dx, int dx_pitch,
+                              void *flip_scratch, void *hip_stream);
+
+/* Workspace bytes of sur_conv3x3_backward_weight for these sizes (0 if invalid). */
+size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int cout);
+
+/* dweight[o][tap][i] = sum_{n,y,x} dz[n,y,x,o] x[n,y+dy,x+dx,i] and
+ * dbias[o] = sum dz[..., o] (FP32, overwritten; dbias may be NULL).
+ * Deterministic: FP32 partial sums over pixel ranges added in a fixed order. */
+int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int dz_pitch, int n,
+                                int h, int w, int cin, int cout, float *dweight, float *dbias,
+                                void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* dz = y > 0 ? dy : slope dy over `pixels` pixels of c channels (y is the
+ * activation's output). dz may alias dy. */
+int sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,
+                       int dz_pitch, long long pixels, int c, float slope, void *hip_stream);
+
+/* 2x2 average pooling of x (n, h, w, c) into y (n, h/2, w/2, c), and its
+ * adjoint: dx (n, h, w) = dy / 4 broadcast over each window, added to dx
+ * when accumulate != 0. */
+int sur_pool2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
+              void *hip_stream);
+int sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                       int dx_pitch, int accumulate, void *hip_stream);
+
+/* 2x nearest-neighbour upsampling of x (n, h, w, c) into y (n, 2h, 2w, c),
+ * and its adjoint: dx (n, h, w) = sum of dy over each 2x2 window. */
+int sur_up2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
+            void *hip_stream);
+int sur_up2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                     int dx_pitch, void *hip_stream);
+
+/* Network input from densities: x (BF16 NHWC, 16 channels, pitch 16) holds
+ * rho_c / scale_in[c] for c < 5, then planes[b][0..8] (FP32 device
+ * [batch][9], the normalised rates and diffusivities) on every pixel, then
+ * two zero channels. scale_in: host array of 5 positive floats. */
+int sur_pack_input(const float *rho, int batch, int h, int w, const float *planes,
+                   const float *scale_in, void *x, void *hip_stream);
+
+/* rho_next = rho + scale_out[c] * out[..., c] for c < 5; out is FP32 NHWC
+ * with 16 channels (the network's last layer). rho_next may alias rho. */
+int sur_apply_output(const float *rho, const float *out, int batch, int h, int w,
+                     const float *scale_out, float *rho_next, void *hip_stream);
+
+/* Training loss: the mean over (b, y, x, c < 5) of
+ * (out[..., c] - (target - rho)_c / scale_out[c])^2 into *loss (device
+ * double), and its gradient dout (BF16 NHWC, 16 channels, zero for c >= 5).
+ * partials: device scratch of 1024 doubles. */
+int sur_mse_loss(const float *out, const float *rho, const float *target, int batch, int h,
+                 int w, const float *scale_out, void *dout, double *partials, double *loss,
+                 void *hip_stream);
+
+/* One Adam step (Kingma and Ba, 2015) over count FP32 parameters; step
+ * counts from 1. theta_bf16 (may be NULL) receives the rounded parameters. */
+int sur_adam(float *theta, void *theta_bf16, const float *grad, float *m, float *v,
+             long long count, int step, float lr, float beta1, float beta2, float eps,
+             void *hip_stream);
+
+/* Periodic crop of a density state: dst[c][j][i] = rho[c][(y0 + j) mod h]
+ * [(x0 + i) mod w] for the 5 compartments, j < ch, i < cw (FP32; any integer
+ * y0, x0). Used to recompute SSLBM steps on sub-tiles when judging the
+ * surrogate. */
+int sur_crop_periodic(const float *rho, int h, int w, int y0, int x0, int ch, int cw, float *dst,
+                      void *hip_stream);
+
+/* dst = round-to-nearest-even BF16 of src (count values). */
+int sur_to_bf16(const float *src, void *dst, long long count, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSLBM_SURROGATE_H */

@@ -111,6 +111,54 @@ def adam(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
 
 
+# ------------------------------------------------------ input and output --
+
+def pack_input(rho, planes, scale_in):
+    """Network input [b, h, w, 16] from densities rho [b, 5, h, w]: rho_c /
+    scale_in[c], then the 9 parameter values of each instance, then zeros."""
+    rho = np.asarray(rho, np.float64)
+    b, _, h, w = rho.shape
+    x = np.zeros((b, h, w, 16))
+    for c in range(5):
+        x[..., c] = rho[:, c] / scale_in[c]
+    for k in range(9):
+        x[..., 5 + k] = np.asarray(planes, np.float64)[:, k][:, None, None]
+    return x
+
+
+def apply_output(rho, out, scale_out):
+    """rho + scale_out[c] out[..., c] for the five compartments."""
+    rho = np.asarray(rho, np.float64)
+    nxt = rho.copy()
+    for c in range(5):
+        nxt[:, c] += scale_out[c] * np.asarray(out, np.float64)[..., c]
+    return nxt
+
+
+def mse_loss(out, rho, target, scale_out):
+    """Mean over (b, y, x, c < 5) of (out_c - (target - rho)_c / scale_out[c])^2
+    and its gradient with respect to out (zero for channels >= 5)."""
+    out = np.asarray(out, np.float64)
+    d = np.zeros_like(out)
+    for c in range(5):
+        d[..., c] = out[..., c] - (np.asarray(target, np.float64)[:, c]
+                                   - np.asarray(rho, np.float64)[:, c]) / scale_out[c]
+    count = out.shape[0] * out.shape[1] * out.shape[2] * 5
+    return float(np.sum(d * d) / count), 2.0 * d / count
+
+
+# ------------------------------------------------------ storage precision --
+
+def bf16_round(a):
+    """Round to the nearest BF16 value, ties to even: BF16 keeps the upper 16
+    bits of the IEEE binary32 encoding (sign, 8 exponent bits, 7 fraction
+    bits). Input is first rounded to binary32. Finite values only."""
+    a32 = np.asarray(a, np.float64).astype(np.float32)
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
 # ---------------------------------------------------------------- network --
 
 def unet_spec(levels: int = 4, base: int = 32, cin: int = 16, cout: int = 16):
@@ -140,24 +188,35 @@ def unet_spec(levels: int = 4, base: int = 32, cin: int = 16, cout: int = 16):
     return spec
 
 
-def unet_forward(x, weights, spec, slope):
+def _exact(a):
+    return np.asarray(a, np.float64)
+
+
+def unet_forward(x, weights, spec, slope, store=_exact):
     """Forward pass; weights is a list of (W, b) per conv in spec order.
-    Returns the output and the tape of activations for unet_backward."""
+    Returns the output and the tape of activations for unet_backward.
+    `store` is applied to every tensor a layer hands on (each activated
+    convolution output and each pooled tensor; the last convolution's
+    output is kept exact): identity by default, bf16_round to model a
+    network whose activations are stored in BF16."""
     tape = []
     saved = {}
     k = 0
     h = np.asarray(x, np.float64)
+    n_conv = sum(1 for op in spec if op[0] == "conv")
     for op in spec:
         if op[0] == "conv":
             w, b = weights[k]
             k += 1
             z = conv3x3(h, w, b)
             y = leaky(z, slope) if op[3] else z
+            if k < n_conv:
+                y = store(y)
             tape.append(("conv", h, y, op[3]))
             h = y
         elif op[0] == "pool":
             tape.append(("pool", h.shape))
-            h = pool2(h)
+            h = store(pool2(h))
         elif op[0] == "up":
             tape.append(("up",))
             h = up2(h)
@@ -171,28 +230,31 @@ def unet_forward(x, weights, spec, slope):
     return h, tape
 
 
-def unet_backward(dout, weights, tape, slope):
-    """Gradients (dW, db) per conv, in spec order, and dX of the input."""
+def unet_backward(dout, weights, tape, slope, store=_exact):
+    """Gradients (dW, db) per conv, in spec order, and dX of the input.
+    `store` is applied where a gradient tensor is handed on: dZ after the
+    activation, dX of each convolution, the upsampling adjoint, and an
+    encoder output's gradient after the skip and pooled parts are added."""
     grads = [None] * len(weights)
     k = len(weights)
     skip_grad = {}
-    g = np.asarray(dout, np.float64)
+    g = store(dout)
     for entry in reversed(tape):
         if entry[0] == "conv":
             k -= 1
             _, x_in, y, act = entry
-            dz = leaky_bwd(g, y, slope) if act else g
+            dz = store(leaky_bwd(g, y, slope)) if act else g
             grads[k] = conv3x3_bwd_weight(x_in, dz)
-            g = conv3x3_bwd_data(dz, weights[k][0])
+            g = store(conv3x3_bwd_data(dz, weights[k][0]))
         elif entry[0] == "pool":
             g = pool2_bwd(g)
         elif entry[0] == "up":
-            g = up2_bwd(g)
+            g = store(up2_bwd(g))
         elif entry[0] == "cat":
             _, level, c_up = entry
             skip_grad[level] = g[..., c_up:]
             g = g[..., :c_up]
         elif entry[0] == "save":
             if entry[1] in skip_grad:
-                g = g + skip_grad.pop(entry[1])
+                g = store(g + skip_grad.pop(entry[1]))
     return grads, g

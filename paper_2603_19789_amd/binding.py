@@ -71,6 +71,7 @@ def library() -> ctypes.CDLL:
                 "(or __graft_entry__.build()); there is no fallback path")
         lib = ctypes.CDLL(str(LIBRARY))
         vp, i, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong
+        f, sz, fp = ctypes.c_float, ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)
         pp = ctypes.POINTER(Params)
         sig = {
             "sslbm_init": [ctypes.POINTER(vp), i, i, i, i, pp],
@@ -98,6 +99,21 @@ def library() -> ctypes.CDLL:
             "sslbm_adjoint_step": [vp, vp, vp, vp, vp, vp],
             "sslbm_run_checkpointed": [vp, vp, vp, ll, i, vp, vp],
             "sslbm_adjoint_run": [vp, vp, ll, i, vp, vp, vp, vp],
+            # surrogate.h
+            "sur_conv3x3_forward": [vp, i, i, i, i, i, vp, vp, vp, i, i, i, f, vp],
+            "sur_conv3x3_backward_data": [vp, i, i, i, i, i, vp, i, vp, i, vp, vp],
+            "sur_conv3x3_backward_weight": [vp, i, vp, i, i, i, i, i, i, vp, vp, vp, sz, vp],
+            "sur_leaky_backward": [vp, i, vp, i, vp, i, ll, i, f, vp],
+            "sur_pool2": [vp, i, i, i, i, i, vp, i, vp],
+            "sur_pool2_backward": [vp, i, i, i, i, i, vp, i, i, vp],
+            "sur_up2": [vp, i, i, i, i, i, vp, i, vp],
+            "sur_up2_backward": [vp, i, i, i, i, i, vp, i, vp],
+            "sur_pack_input": [vp, i, i, i, vp, fp, vp, vp],
+            "sur_apply_output": [vp, vp, i, i, i, fp, vp, vp],
+            "sur_mse_loss": [vp, vp, vp, i, i, i, fp, vp, vp, vp, vp],
+            "sur_adam": [vp, vp, vp, vp, vp, ll, i, f, f, f, f, vp],
+            "sur_to_bf16": [vp, vp, ll, vp],
+            "sur_crop_periodic": [vp, i, i, i, i, i, i, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -116,6 +132,8 @@ def library() -> ctypes.CDLL:
         lib.sslbm_checkpoint_count.restype = ll
         lib.sslbm_adjoint_workspace_bytes.argtypes = [vp, i]
         lib.sslbm_adjoint_workspace_bytes.restype = ctypes.c_size_t
+        lib.sur_conv3x3_backward_weight_workspace.argtypes = [i, i, i, i, i]
+        lib.sur_conv3x3_backward_weight_workspace.restype = ctypes.c_size_t
         _LIB = lib
     return _LIB
 

@@ -1,0 +1,224 @@
+// surrogate_api.cpp -- host side of surrogate.h: argument validation (before
+// any HIP call) and dispatch to the surrogate kernels.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "sslbm.h"
+#include "surrogate.h"
+#include "surrogate_internal.h"
+
+namespace {
+
+constexpr int MAX_SIDE = 1 << 16;
+constexpr int MAX_CHANNELS = 4096;
+
+int status(hipError_t e) { return e == hipSuccess ? SSLBM_OK : SSLBM_E_HIP; }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// A BF16 NHWC view of c channels with the given pitch.
+bool view_ok(const void *p, int pitch, int c) {
+    return p && aligned16(p) && c > 0 && c <= MAX_CHANNELS && c % 8 == 0 && pitch >= c &&
+           pitch % 8 == 0;
+}
+
+bool dims_ok(int n, int h, int w) {
+    return n > 0 && h > 0 && w > 0 && h <= MAX_SIDE && w <= MAX_SIDE &&
+           (long long)n * h * w <= (1ll << 34);
+}
+
+bool scales_ok(const float *s) {
+    if (!s)
+        return false;
+    for (int c = 0; c < 5; ++c)
+        if (!(std::isfinite(s[c]) && s[c] > 0.f))
+            return false;
+    return true;
+}
+
+sslbm::IoScales make_scales(const float *in, const float *out) {
+    sslbm::IoScales sc{};
+    for (int c = 0; c < 5; ++c) {
+        sc.inv_in[c] = in ? 1.f / in[c] : 1.f;
+        sc.out[c] = out ? out[c] : 1.f;
+        sc.inv_out[c] = out ? 1.f / out[c] : 1.f;
+    }
+    return sc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
+                        const void *weight, const float *bias, void *y, int y_pitch, int cout,
+                        int flags, float slope, void *hip_stream) {
+    if (!view_ok(x, x_pitch, cin) || !dims_ok(n, h, w) || !weight || !aligned16(weight) || !y ||
+        (flags & ~(SUR_LEAKY | SUR_OUT_F32)) || cout <= 0 || cout > MAX_CHANNELS ||
+        y_pitch < cout || !std::isfinite(slope))
+        return SSLBM_E_ARG;
+    if (!(flags & SUR_OUT_F32) && !view_ok(y, y_pitch, cout))
+        return SSLBM_E_ARG;
+    if ((flags & SUR_OUT_F32) && (cout % 4 != 0 || y_pitch % 4 != 0 || !aligned16(y)))
+        return SSLBM_E_ARG;
+    sslbm::ConvArgs a;
+    a.x = x;
+    a.x_pitch = x_pitch;
+    a.n = n;
+    a.h = h;
+    a.w = w;
+    a.cin = cin;
+    a.wt = weight;
+    a.bias = bias;
+    a.y = y;
+    a.y_pitch = y_pitch;
+    a.cout = cout;
+    a.slope = slope;
+    return status(sslbm::launch_conv_fwd(a, flags & SUR_LEAKY, flags & SUR_OUT_F32,
+                                         (hipStream_t)hip_stream));
+}
+
+int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
+                              const void *weight, int cin, void *dx, int dx_pitch,
+                              void *flip_scratch, void *hip_stream) {
+    if (!view_ok(dz, dz_pitch, cout) || !view_ok(dx, dx_pitch, cin) || !dims_ok(n, h, w) ||
+        !weight || !flip_scratch || !aligned16(flip_scratch))
+        return SSLBM_E_ARG;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    int st = status(sslbm::launch_flip(weight, cout, cin, flip_scratch, s));
+    if (st != SSLBM_OK)
+        return st;
+    sslbm::ConvArgs a;
+    a.x = dz;
+    a.x_pitch = dz_pitch;
+    a.n = n;
+    a.h = h;
+    a.w = w;
+    a.cin = cout;
+    a.wt = flip_scratch;
+    a.bias = nullptr;
+    a.y = dx;
+    a.y_pitch = dx_pitch;
+    a.cout = cin;
+    a.slope = 0.f;
+    return status(sslbm::launch_conv_fwd(a, false, false, s));
+}
+
+size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int cout) {
+    if (!dims_ok(n, h, w) || cin <= 0 || cin % 8 || cout <= 0 || cout % 8 ||
+        cin > MAX_CHANNELS || cout > MAX_CHANNELS || w % 8)
+        return 0;
+    return sslbm::wgrad_plan(n, h, w, cin, cout).bytes();
+}
+
+int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int dz_pitch, int n,
+                                int h, int w, int cin, int cout, float *dweight, float *dbias,
+                                void *workspace, size_t workspace_bytes, void *hip_stream) {
+    if (!view_ok(x, x_pitch, cin) || !view_ok(dz, dz_pitch, cout) || !dims_ok(n, h, w) ||
+        w % 8 || !dweight || !workspace || !aligned16(workspace))
+        return SSLBM_E_ARG;
+    if (workspace_bytes < sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_wgrad(x, x_pitch, dz, dz_pitch, n, h, w, cin, cout, dweight,
+                                      dbias, workspace, (hipStream_t)hip_stream));
+}
+
+int sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,
+                       int dz_pitch, long long pixels, int c, float slope, void *hip_stream) {
+    if (!view_ok(dy, dy_pitch, c) || !view_ok(y, y_pitch, c) || !view_ok(dz, dz_pitch, c) ||
+        pixels <= 0 || !std::isfinite(slope))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_leaky_bwd(dy, dy_pitch, y, y_pitch, dz, dz_pitch, pixels, c, slope,
+                                          (hipStream_t)hip_stream));
+}
+
+int sur_pool2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
+              void *hip_stream) {
+    if (!view_ok(x, x_pitch, c) || !view_ok(y, y_pitch, c) || !dims_ok(n, h, w) || h % 2 || w % 2)
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_pool2(x, x_pitch, n, h, w, c, y, y_pitch, (hipStream_t)hip_stream));
+}
+
+int sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                       int dx_pitch, int accumulate, void *hip_stream) {
+    if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, h, w) || h % 2 ||
+        w % 2)
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_pool2_bwd(dy, dy_pitch, n, h, w, c, dx, dx_pitch, accumulate != 0,
+                                          (hipStream_t)hip_stream));
+}
+
+int sur_up2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
+            void *hip_stream) {
+    if (!view_ok(x, x_pitch, c) || !view_ok(y, y_pitch, c) || !dims_ok(n, 2 * h, 2 * w))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_up2(x, x_pitch, n, h, w, c, y, y_pitch, (hipStream_t)hip_stream));
+}
+
+int sur_up2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                     int dx_pitch, void *hip_stream) {
+    if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, 2 * h, 2 * w))
+        return SSLBM_E_ARG;
+    return status(
+        sslbm::launch_up2_bwd(dy, dy_pitch, n, h, w, c, dx, dx_pitch, (hipStream_t)hip_stream));
+}
+
+int sur_pack_input(const float *rho, int batch, int h, int w, const float *planes,
+                   const float *scale_in, void *x, void *hip_stream) {
+    if (!rho || !planes || !x || !aligned16(x) || !dims_ok(batch, h, w) || !scales_ok(scale_in))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_pack_input(rho, batch, h, w, planes, make_scales(scale_in, nullptr),
+                                           x, (hipStream_t)hip_stream));
+}
+
+int sur_apply_output(const float *rho, const float *out, int batch, int h, int w,
+                     const float *scale_out, float *rho_next, void *hip_stream) {
+    if (!rho || !out || !rho_next || !dims_ok(batch, h, w) || !scales_ok(scale_out))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_apply_output(rho, out, batch, h, w, make_scales(nullptr, scale_out),
+                                             rho_next, (hipStream_t)hip_stream));
+}
+
+int sur_mse_loss(const float *out, const float *rho, const float *target, int batch, int h,
+                 int w, const float *scale_out, void *dout, double *partials, double *loss,
+                 void *hip_stream) {
+    if (!out || !rho || !target || !dout || !aligned16(dout) || !partials || !loss ||
+        !dims_ok(batch, h, w) || !scales_ok(scale_out))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_mse(out, rho, target, batch, h, w, make_scales(nullptr, scale_out),
+                                    dout, partials, loss, (hipStream_t)hip_stream));
+}
+
+int sur_adam(float *theta, void *theta_bf16, const float *grad, float *m, float *v,
+             long long count, int step, float lr, float beta1, float beta2, float eps,
+             void *hip_stream) {
+    if (!theta || !grad || !m || !v || count <= 0 || step < 1 || !(lr >= 0.f) ||
+        !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return SSLBM_E_ARG;
+    sslbm::AdamArgs a;
+    a.lr = lr;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    a.inv_bc1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+    a.inv_bc2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+    return status(sslbm::launch_adam(theta, theta_bf16, grad, m, v, count, a,
+                                     (hipStream_t)hip_stream));
+}
+
+int sur_crop_periodic(const float *rho, int h, int w, int y0, int x0, int ch, int cw, float *dst,
+                      void *hip_stream) {
+    if (!rho || !dst || !dims_ok(1, h, w) || !dims_ok(1, ch, cw))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_crop(rho, h, w, y0, x0, ch, cw, dst, (hipStream_t)hip_stream));
+}
+
+int sur_to_bf16(const float *src, void *dst, long long count, void *hip_stream) {
+    if (!src || !dst || count <= 0)
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_to_bf16(src, dst, count, (hipStream_t)hip_stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// surrogate_internal.h -- declarations shared by the surrogate's host entry
+// points and its kernels (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+
+namespace sslbm {
+
+constexpr int SUR_IN_CHANNELS = 16;   // 5 densities, 9 parameter planes, 2 zero
+constexpr int SUR_OUT_CHANNELS = 16;  // 5 predicted increments, 11 unused
+constexpr int SUR_LOSS_BLOCKS = 1024;
+
+inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+struct ConvArgs {
+    const void *x;      // BF16 NHWC view
+    int x_pitch;
+    int n, h, w, cin;
+    const void *wt;     // BF16 [cout][9][cin]
+    const float *bias;  // may be null
+    void *y;            // BF16 or FP32 NHWC view
+    int y_pitch;
+    int cout;
+    float slope;
+};
+
+struct WgradArgs {
+    const uint16_t *dz_t, *xs;
+    float *part;
+    int n, h, w, cin, cout;
+    long long P, Pp, chunk;
+    int splits;
+};
+
+struct WgradPlan {
+    long long P, Pp, chunk, waves;
+    int splits, ni;
+    size_t dz_t_bytes, xs_bytes, part_bytes;
+    size_t bytes() const { return align256(dz_t_bytes) + align256(xs_bytes) + align256(part_bytes); }
+};
+
+struct IoScales {
+    float inv_in[5];   // input density channel = rho / scale_in
+    float out[5];      // increment = scale_out * network output
+    float inv_out[5];  // 1 / scale_out
+};
+
+struct AdamArgs {
+    float lr, beta1, beta2, eps, inv_bc1, inv_bc2;  // inv_bc = 1 / (1 - beta^step)
+};
+
+hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s);
+hipError_t launch_flip(const void *w, int cout, int cin, void *wf, hipStream_t s);
+WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout);
+hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, int h, int w,
+                        int cin, int cout, float *dw, float *db, void *ws, hipStream_t s);
+hipError_t launch_leaky_bwd(const void *dy, int dyp, const void *y, int yp, void *dz, int dzp,
+                            long long pixels, int c, float slope, hipStream_t s);
+hipError_t launch_pool2(const void *x, int xp, int n, int h, int w, int c, void *y, int yp,
+                        hipStream_t s);
+hipError_t launch_pool2_bwd(const void *dy, int dyp, int n, int h, int w, int c, void *dx,
+                            int dxp, bool accumulate, hipStream_t s);
+hipError_t launch_up2(const void *x, int xp, int n, int h, int w, int c, void *y, int yp,
+                      hipStream_t s);
+hipError_t launch_up2_bwd(const void *dy, int dyp, int n, int h, int w, int c, void *dx, int dxp,
+                          hipStream_t s);
+hipError_t launch_pack_input(const float *rho, int batch, int h, int w, const float *planes,
+                             const IoScales &sc, void *x, hipStream_t s);
+hipError_t launch_apply_output(const float *rho, const float *out, int batch, int h, int w,
+                               const IoScales &sc, float *next, hipStream_t s);
+hipError_t launch_mse(const float *out, const float *rho, const float *target, int batch, int h,
+                      int w, const IoScales &sc, void *dout, double *partials, double *loss,
+                      hipStream_t s);
+hipError_t launch_adam(float *theta, void *theta_bf16, const float *grad, float *m, float *v,
+                       long long count, const AdamArgs &a, hipStream_t s);
+hipError_t launch_to_bf16(const float *src, void *dst, long long count, hipStream_t s);
+hipError_t launch_crop(const float *rho, int h, int w, int y0, int x0, int ch, int cw, float *dst,
+                       hipStream_t s);
+
+}  // namespace sslbm

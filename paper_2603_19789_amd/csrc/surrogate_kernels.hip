@@ -1,0 +1,777 @@
+// surrogate_kernels.hip -- the operations of the learned surrogate on gfx950:
+// periodic 3x3 convolutions on BF16 MFMA with FP32 accumulation (forward,
+// and the two backward passes), pooling, upsampling, activation, the
+// surrogate's input/output/loss maps and the Adam update.
+//
+// Activations are NHWC BF16 views: element (n, y, x, c) of a view lives at
+// ptr[((n H + y) W + x) pitch + c]; a view's channels are a slice of a wider
+// buffer when pitch > channels (that is how skip connections concatenate
+// without copies). Channel counts, pitches and slice offsets are multiples of
+// 8, so one lane moves 8 channels (16 bytes) per access. Weights are BF16
+// [out][tap][in], tap = 3 (dy + 1) + (dx + 1), with FP32 master copies.
+//
+// Convolution as implicit GEMM on V_MFMA_F32_16X16X32_BF16. Lane l of a
+// wavefront holds row l % 16 of A and column l % 16 of B, each with the 8
+// consecutive k values 8 (l / 16) .. 8 (l / 16) + 7, and receives rows
+// 4 (l / 16) + i, i = 0..3, of column l % 16 of the 16 x 16 FP32 result
+// (layout checked on the device).
+//   forward:  rows = output pixels, columns = output channels,
+//             k = (tap, input channel): both fragments are 16-byte loads of
+//             8 consecutive channels (NHWC activations, [out][tap][in] weights).
+//   backward data: the forward kernel on dZ with the weights flipped in
+//             space and transposed in channels (periodic padding makes the
+//             adjoint of a correlation the correlation with the flipped kernel).
+//   backward weights: rows = output channels, columns = input channels,
+//             k = pixels. dZ and X are first transposed to channel-major
+//             planes (X in three copies shifted by dx = -1, 0, +1), so a
+//             fragment is again 8 consecutive values; dy moves whole rows.
+//             Pixels are split across wavefronts; FP32 partial sums are added
+//             in a fixed order by a second kernel, so results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "surrogate_internal.h"
+
+namespace sslbm {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int THREADS = 256;
+
+// FP32 -> BF16 with round-to-nearest-even (finite inputs; NaN stays NaN).
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7f800000u) == 0x7f800000u)
+        return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) {
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(p));
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Eight BF16 values as one 16-byte vector (element 0 in the low half-word).
+__device__ __forceinline__ uint4 pack8(const uint16_t *v) {
+    return make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
+                      v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
+}
+
+// ------------------------------------------------------------- forward conv
+// One wavefront: 64 consecutive output pixels x (16 NT) output channels.
+template <int NT, bool F32OUT, bool LEAKY>
+__global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
+    const int wave = blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6);
+    const int groups = (a.cout + 16 * NT - 1) / (16 * NT);
+    const long long P = (long long)a.n * a.h * a.w;
+    const long long tile = wave / groups;
+    const int cg = wave - (int)(tile * groups);
+    if (tile * 64 >= P)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, g = lane >> 4;
+    const uint16_t *x = static_cast<const uint16_t *>(a.x);
+    const uint16_t *wt = static_cast<const uint16_t *>(a.wt);
+
+    int pn[4], py[4], px[4];
+#pragma unroll
+    for (int ms = 0; ms < 4; ++ms) {
+        long long q = tile * 64 + 16 * ms + m;
+        if (q >= P)
+            q = P - 1;  // a clamped duplicate; its result is never stored
+        const long long hw = (long long)a.h * a.w;
+        pn[ms] = (int)(q / hw);
+        const int r = (int)(q - (long long)pn[ms] * hw);
+        py[ms] = r / a.w;
+        px[ms] = r - py[ms] * a.w;
+    }
+    int co[NT];
+#pragma unroll
+    for (int ns = 0; ns < NT; ++ns) {
+        const int c = cg * 16 * NT + 16 * ns + m;
+        co[ns] = c < a.cout ? c : a.cout - 1;
+    }
+
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int ms = 0; ms < 4; ++ms)
+#pragma unroll
+        for (int ns = 0; ns < NT; ++ns)
+            acc[ms][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const uint16_t *arow[4];
+#pragma unroll
+        for (int ms = 0; ms < 4; ++ms) {
+            const int yy = wrap(py[ms] + dy, a.h), xx = wrap(px[ms] + dx, a.w);
+            arow[ms] = x + (((long long)pn[ms] * a.h + yy) * a.w + xx) * a.x_pitch;
+        }
+        for (int c0 = 0; c0 < a.cin; c0 += 32) {
+            const int cc = c0 + 8 * g;
+            const bool live = cc < a.cin;
+            bf16x8 A[4], B[NT];
+#pragma unroll
+            for (int ms = 0; ms < 4; ++ms)
+                A[ms] = live ? load8(arow[ms] + cc) : zero8();
+#pragma unroll
+            for (int ns = 0; ns < NT; ++ns)
+                B[ns] = live ? load8(wt + ((long long)co[ns] * 9 + t) * a.cin + cc) : zero8();
+#pragma unroll
+            for (int ms = 0; ms < 4; ++ms)
+#pragma unroll
+                for (int ns = 0; ns < NT; ++ns)
+                    acc[ms][ns] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ms], B[ns], acc[ms][ns], 0, 0, 0);
+        }
+    }
+
+#pragma unroll
+    for (int ns = 0; ns < NT; ++ns) {
+        const int c = cg * 16 * NT + 16 * ns + m;
+        if (c >= a.cout)
+            continue;
+        const float b = a.bias ? a.bias[c] : 0.f;
+#pragma unroll
+        for (int ms = 0; ms < 4; ++ms)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long long q = tile * 64 + 16 * ms + 4 * g + i;
+                if (q >= P)
+                    continue;
+                float v = acc[ms][ns][i] + b;
+                if (LEAKY)
+                    v = v > 0.f ? v : a.slope * v;
+                if (F32OUT)
+                    static_cast<float *>(a.y)[q * a.y_pitch + c] = v;
+                else
+                    static_cast<uint16_t *>(a.y)[q * a.y_pitch + c] = to_bf16(v);
+            }
+    }
+}
+
+// W'[i][t'][o] = W[o][8 - t][i]: the kernel of the backward-data pass.
+__global__ __launch_bounds__(THREADS) void flip_kernel(const uint16_t *__restrict__ w, int cout,
+                                                       int cin, uint16_t *__restrict__ wf) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    const long long total = (long long)cout * 9 * cin;
+    if (e >= total)
+        return;
+    const int i = (int)(e % cin);
+    const int t = (int)((e / cin) % 9);
+    const int o = (int)(e / (9ll * cin));
+    wf[((long long)i * 9 + (8 - t)) * cout + o] = w[e];
+}
+
+// ------------------------------------------------------- backward weights
+// Channel-major copies: dz_t[o][q] = dZ[q][o]; xs[s][i][q] = X[shift(q, dx =
+// s - 1)][i]. q runs over P pixels padded with zeros to a multiple of 32.
+__global__ __launch_bounds__(THREADS) void transpose_dz_kernel(const uint16_t *__restrict__ dz,
+                                                               int pitch, long long P, long long Pp,
+                                                               int c, uint16_t *__restrict__ out) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= Pp * c)
+        return;
+    const long long q = e % Pp;
+    const int ch = (int)(e / Pp);
+    out[e] = q < P ? dz[q * pitch + ch] : (uint16_t)0;
+}
+
+__global__ __launch_bounds__(THREADS) void transpose_shift_kernel(
+    const uint16_t *__restrict__ x, int pitch, int n, int h, int w, long long Pp, int c,
+    uint16_t *__restrict__ out) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= 3 * Pp * c)
+        return;
+    const long long q = e % Pp;
+    const long long rest = e / Pp;
+    const int ch = (int)(rest % c);
+    const int s = (int)(rest / c);
+    const long long P = (long long)n * h * w;
+    uint16_t v = 0;
+    if (q < P) {
+        const long long row = q / w;  // n * h + y
+        const int xx = wrap((int)(q - row * w) + s - 1, w);
+        v = x[(row * w + xx) * pitch + ch];
+    }
+    out[e] = v;
+}
+
+// One wavefront: 32 output channels x (16 NI) input channels of one tap,
+// over the pixel range of its split; FP32 partial sums to part[split].
+template <int NI>
+__global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
+    const int wave = blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6);
+    const int ot = (a.cout + 31) / 32, it = (a.cin + 16 * NI - 1) / (16 * NI);
+    const int per_split = ot * it * 9;
+    const int split = wave / per_split;
+    if (split >= a.splits)
+        return;
+    int r = wave - split * per_split;
+    const int tap = r % 9;
+    r /= 9;
+    const int ib = r % it, ob = r / it;
+    const int dy = tap / 3 - 1, s = tap % 3;
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, g = lane >> 4;
+
+    int o[2], i[NI];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = ob * 32 + 16 * u + m;
+        o[u] = c < a.cout ? c : a.cout - 1;
+    }
+#pragma unroll
+    for (int u = 0; u < NI; ++u) {
+        const int c = ib * 16 * NI + 16 * u + m;
+        i[u] = c < a.cin ? c : a.cin - 1;
+    }
+    const uint16_t *dz = a.dz_t;
+    const uint16_t *xs = a.xs + (long long)s * a.cin * a.Pp;
+
+    f32x4 acc[2][NI];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < NI; ++v)
+            acc[u][v] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const long long k0 = (long long)split * a.chunk;
+    long long k1 = k0 + a.chunk;
+    if (k1 > a.Pp)
+        k1 = a.Pp;
+    const long long hw = (long long)a.h * a.w;
+    for (long long q0 = k0; q0 < k1; q0 += 32) {
+        const long long q = q0 + 8 * g;  // 8 pixels of one row (w % 8 == 0)
+        long long qs = q;
+        if (q < a.P) {
+            const long long nn = q / hw;
+            const int rr = (int)(q - nn * hw);
+            const int yy = wrap(rr / a.w + dy, a.h);
+            qs = (nn * a.h + yy) * a.w + (rr - (rr / a.w) * a.w);
+        }
+        bf16x8 A[2], B[NI];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            A[u] = load8(dz + (long long)o[u] * a.Pp + q);
+#pragma unroll
+        for (int v = 0; v < NI; ++v)
+            B[v] = load8(xs + (long long)i[v] * a.Pp + qs);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < NI; ++v)
+                acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[u], B[v], acc[u][v], 0, 0, 0);
+    }
+    // result rows (output channels) 4 g + j of subtile u, column m of subtile v
+    float *part = a.part + (long long)split * a.cout * 9 * a.cin;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < NI; ++v) {
+            const int ic = ib * 16 * NI + 16 * v + m;
+            if (ic >= a.cin)
+                continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int oc = ob * 32 + 16 * u + 4 * g + j;
+                if (oc < a.cout)
+                    part[((long long)oc * 9 + tap) * a.cin + ic] = acc[u][v][j];
+            }
+        }
+}
+
+// dW = sum over splits (fixed order); db[o] = sum over pixels of dz_t[o][:].
+__global__ __launch_bounds__(THREADS) void wgrad_reduce_kernel(const float *__restrict__ part,
+                                                               int splits, long long count,
+                                                               float *__restrict__ dw) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= count)
+        return;
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k)
+        s += part[k * count + e];
+    dw[e] = s;
+}
+
+__global__ __launch_bounds__(THREADS) void bias_grad_kernel(const uint16_t *__restrict__ dz_t,
+                                                            long long Pp, float *__restrict__ db) {
+    __shared__ float red[THREADS];
+    const uint16_t *row = dz_t + (long long)blockIdx.x * Pp;
+    float s = 0.f;
+    for (long long q = threadIdx.x; q < Pp; q += THREADS)
+        s += from_bf16(row[q]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = THREADS / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        db[blockIdx.x] = red[0];
+}
+
+// --------------------------------------------------------- elementwise ops
+// Each thread handles 8 channels of one pixel.
+__global__ __launch_bounds__(THREADS) void leaky_bwd_kernel(const uint16_t *__restrict__ dy,
+                                                            int dyp, const uint16_t *__restrict__ y,
+                                                            int yp, uint16_t *__restrict__ dz,
+                                                            int dzp, long long pixels, int c,
+                                                            float slope) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    const int c8 = c / 8;
+    if (e >= pixels * c8)
+        return;
+    const long long q = e / c8;
+    const int ch = (int)(e - q * c8) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float d = from_bf16(dy[q * dyp + ch + j]);
+        const float v = from_bf16(y[q * yp + ch + j]);
+        dz[q * dzp + ch + j] = to_bf16(v > 0.f ? d : slope * d);
+    }
+}
+
+// y (n, h/2, w/2) = mean of 2x2 windows of x (n, h, w)
+__global__ __launch_bounds__(THREADS) void pool2_kernel(const uint16_t *__restrict__ x, int xp,
+                                                        int n, int h, int w, int c,
+                                                        uint16_t *__restrict__ y, int yp) {
+    const int ho = h / 2, wo = w / 2, c8 = c / 8;
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= (long long)n * ho * wo * c8)
+        return;
+    const long long q = e / c8;
+    const int ch = (int)(e - q * c8) * 8;
+    const int xo = (int)(q % wo);
+    const long long r = q / wo;
+    const int yo = (int)(r % ho);
+    const int nn = (int)(r / ho);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float s = 0.f;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                s += from_bf16(x[(((long long)nn * h + 2 * yo + a) * w + 2 * xo + b) * xp + ch + j]);
+        y[q * yp + ch + j] = to_bf16(0.25f * s);
+    }
+}
+
+// dx (n, h, w) (+)= dy (n, h/2, w/2) / 4 at the window's four inputs
+__global__ __launch_bounds__(THREADS) void pool2_bwd_kernel(const uint16_t *__restrict__ dy,
+                                                            int dyp, int n, int h, int w, int c,
+                                                            uint16_t *__restrict__ dx, int dxp,
+                                                            int accumulate) {
+    const int c8 = c / 8;
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= (long long)n * h * w * c8)
+        return;
+    const long long q = e / c8;
+    const int ch = (int)(e - q * c8) * 8;
+    const int xx = (int)(q % w);
+    const long long r = q / w;
+    const int yy = (int)(r % h);
+    const int nn = (int)(r / h);
+    const long long qo = ((long long)nn * (h / 2) + yy / 2) * (w / 2) + xx / 2;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float v = 0.25f * from_bf16(dy[qo * dyp + ch + j]);
+        if (accumulate)
+            v += from_bf16(dx[q * dxp + ch + j]);
+        dx[q * dxp + ch + j] = to_bf16(v);
+    }
+}
+
+// y (n, 2h, 2w) = x (n, h, w) repeated over 2x2 windows
+__global__ __launch_bounds__(THREADS) void up2_kernel(const uint16_t *__restrict__ x, int xp,
+                                                      int n, int h, int w, int c,
+                                                      uint16_t *__restrict__ y, int yp) {
+    const int c8 = c / 8, H = 2 * h, W = 2 * w;
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= (long long)n * H * W * c8)
+        return;
+    const long long q = e / c8;
+    const int ch = (int)(e - q * c8) * 8;
+    const int xx = (int)(q % W);
+    const long long r = q / W;
+    const int yy = (int)(r % H);
+    const int nn = (int)(r / H);
+    const long long qi = ((long long)nn * h + yy / 2) * w + xx / 2;
+    *reinterpret_cast<uint4 *>(y + q * yp + ch) = *reinterpret_cast<const uint4 *>(x + qi * xp + ch);
+}
+
+// dx (n, h, w) = sum of dy (n, 2h, 2w) over each 2x2 window
+__global__ __launch_bounds__(THREADS) void up2_bwd_kernel(const uint16_t *__restrict__ dy,
+                                                          int dyp, int n, int h, int w, int c,
+                                                          uint16_t *__restrict__ dx, int dxp) {
+    const int c8 = c / 8;
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= (long long)n * h * w * c8)
+        return;
+    const long long q = e / c8;
+    const int ch = (int)(e - q * c8) * 8;
+    const int xx = (int)(q % w);
+    const long long r = q / w;
+    const int yy = (int)(r % h);
+    const int nn = (int)(r / h);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float s = 0.f;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                s += from_bf16(
+                    dy[(((long long)nn * 2 * h + 2 * yy + a) * 2 * w + 2 * xx + b) * dyp + ch + j]);
+        dx[q * dxp + ch + j] = to_bf16(s);
+    }
+}
+
+// ------------------------------------------------- surrogate input / output
+// x[b, y, x, :] = (rho_c / scale_c for c < 5, the 9 parameter values, 0, 0)
+__global__ __launch_bounds__(THREADS) void pack_input_kernel(const float *__restrict__ rho,
+                                                             int batch, int h, int w,
+                                                             const float *__restrict__ planes,
+                                                             IoScales s,
+                                                             uint16_t *__restrict__ x) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    const long long hw = (long long)h * w;
+    if (e >= batch * hw)
+        return;
+    const long long b = e / hw, p = e - b * hw;
+    uint16_t v[SUR_IN_CHANNELS];
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        v[c] = to_bf16(rho[(b * 5 + c) * hw + p] * s.inv_in[c]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        v[5 + k] = to_bf16(planes[b * 9 + k]);
+    v[14] = v[15] = 0;
+    uint4 *dst = reinterpret_cast<uint4 *>(x + e * SUR_IN_CHANNELS);
+    dst[0] = pack8(v);
+    dst[1] = pack8(v + 8);
+}
+
+// rho_next[b, c] = rho[b, c] + scale_out_c * out[b, y, x, c] for c < 5
+__global__ __launch_bounds__(THREADS) void apply_output_kernel(const float *__restrict__ rho,
+                                                               const float *__restrict__ out,
+                                                               int batch, int h, int w,
+                                                               IoScales s,
+                                                               float *__restrict__ next) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    const long long hw = (long long)h * w;
+    if (e >= batch * hw * 5)
+        return;
+    const long long p = e % hw;
+    const long long bc = e / hw;
+    const int c = (int)(bc % 5);
+    const long long b = bc / 5;
+    next[e] = rho[e] + s.out[c] * out[(b * hw + p) * SUR_OUT_CHANNELS + c];
+}
+
+// Loss = mean over (b, y, x, c < 5) of (out - (target - rho) / scale_out)^2;
+// dout = its gradient (BF16, channels >= 5 zero); per-block FP64 partials.
+__global__ __launch_bounds__(THREADS) void mse_kernel(const float *__restrict__ out,
+                                                      const float *__restrict__ rho,
+                                                      const float *__restrict__ target, int batch,
+                                                      int h, int w, IoScales s,
+                                                      uint16_t *__restrict__ dout,
+                                                      double *__restrict__ partials) {
+    __shared__ double red[THREADS];
+    const long long hw = (long long)h * w;
+    const long long pixels = batch * hw;
+    const double inv_count = 1.0 / (double)(pixels * 5);
+    double acc = 0.0;
+    for (long long q = (long long)blockIdx.x * THREADS + threadIdx.x; q < pixels;
+         q += (long long)gridDim.x * THREADS) {
+        const long long b = q / hw, p = q - b * hw;
+        uint16_t gv[SUR_OUT_CHANNELS];
+#pragma unroll
+        for (int c = 0; c < SUR_OUT_CHANNELS; ++c)
+            gv[c] = 0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const long long k = (b * 5 + c) * hw + p;
+            const float r = (target[k] - rho[k]) * s.inv_out[c];
+            const float d = out[q * SUR_OUT_CHANNELS + c] - r;
+            acc += (double)d * (double)d;
+            gv[c] = to_bf16((float)(2.0 * inv_count) * d);
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(dout + q * SUR_OUT_CHANNELS);
+        dst[0] = pack8(gv);
+        dst[1] = pack8(gv + 8);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = THREADS / 2; k >= 1; k >>= 1) {
+        if ((int)threadIdx.x < k)
+            red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = red[0] * inv_count;
+}
+
+__global__ __launch_bounds__(THREADS) void sum_partials_kernel(const double *__restrict__ p,
+                                                               int count,
+                                                               double *__restrict__ out) {
+    __shared__ double red[THREADS];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += THREADS)
+        s += p[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = THREADS / 2; k >= 1; k >>= 1) {
+        if ((int)threadIdx.x < k)
+            red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *out = red[0];
+}
+
+// ------------------------------------------------------------------- Adam
+__global__ __launch_bounds__(THREADS) void adam_kernel(float *__restrict__ theta,
+                                                       uint16_t *__restrict__ theta_bf16,
+                                                       const float *__restrict__ grad,
+                                                       float *__restrict__ m,
+                                                       float *__restrict__ v, long long count,
+                                                       AdamArgs a) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= count)
+        return;
+    const float gr = grad[e];
+    const float mm = a.beta1 * m[e] + (1.f - a.beta1) * gr;
+    const float vv = a.beta2 * v[e] + (1.f - a.beta2) * gr * gr;
+    m[e] = mm;
+    v[e] = vv;
+    const float t = theta[e] - a.lr * (mm * a.inv_bc1) / (sqrtf(vv * a.inv_bc2) + a.eps);
+    theta[e] = t;
+    if (theta_bf16)
+        theta_bf16[e] = to_bf16(t);
+}
+
+__global__ __launch_bounds__(THREADS) void to_bf16_kernel(const float *__restrict__ src,
+                                                          uint16_t *__restrict__ dst,
+                                                          long long count) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e < count)
+        dst[e] = to_bf16(src[e]);
+}
+
+__global__ __launch_bounds__(THREADS) void crop_kernel(const float *__restrict__ rho, int h, int w,
+                                                       int y0, int x0, int ch, int cw,
+                                                       float *__restrict__ dst) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    const long long area = (long long)ch * cw;
+    if (e >= 5 * area)
+        return;
+    const int c = (int)(e / area);
+    const long long r = e - c * area;
+    const int j = (int)(r / cw), i = (int)(r - (long long)j * cw);
+    int y = (y0 + j) % h, x = (x0 + i) % w;
+    if (y < 0)
+        y += h;
+    if (x < 0)
+        x += w;
+    dst[e] = rho[((long long)c * h + y) * w + x];
+}
+
+unsigned blocks_for(long long work) { return (unsigned)((work + THREADS - 1) / THREADS); }
+
+}  // namespace
+
+hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
+    const long long P = (long long)a.n * a.h * a.w;
+    const bool two = a.cout > 16;
+    const long long groups = two ? (a.cout + 31) / 32 : 1;
+    const long long waves = (P + 63) / 64 * groups;
+    const dim3 grid((unsigned)((waves + 3) / 4)), block(THREADS);
+#define SUR_FWD(NT, F, L) hipLaunchKernelGGL((conv_fwd_kernel<NT, F, L>), grid, block, 0, s, a)
+    if (two && f32out && leaky)
+        SUR_FWD(2, true, true);
+    else if (two && f32out)
+        SUR_FWD(2, true, false);
+    else if (two && leaky)
+        SUR_FWD(2, false, true);
+    else if (two)
+        SUR_FWD(2, false, false);
+    else if (f32out && leaky)
+        SUR_FWD(1, true, true);
+    else if (f32out)
+        SUR_FWD(1, true, false);
+    else if (leaky)
+        SUR_FWD(1, false, true);
+    else
+        SUR_FWD(1, false, false);
+#undef SUR_FWD
+    return hipGetLastError();
+}
+
+hipError_t launch_flip(const void *w, int cout, int cin, void *wf, hipStream_t s) {
+    hipLaunchKernelGGL(flip_kernel, dim3(blocks_for((long long)cout * 9 * cin)), dim3(THREADS), 0,
+                       s, static_cast<const uint16_t *>(w), cout, cin,
+                       static_cast<uint16_t *>(wf));
+    return hipGetLastError();
+}
+
+WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
+    WgradPlan p;
+    p.P = (long long)n * h * w;
+    p.Pp = (p.P + 31) / 32 * 32;
+    p.ni = cin > 16 ? 2 : 1;
+    const long long tiles = (long long)((cout + 31) / 32) * ((cin + 16 * p.ni - 1) / (16 * p.ni)) * 9;
+    long long splits = 4096 / tiles;  // about 4096 wavefronts in all
+    if (splits < 1)
+        splits = 1;
+    const long long max_splits = p.Pp / 256;  // at least 256 pixels each
+    if (splits > max_splits)
+        splits = max_splits > 0 ? max_splits : 1;
+    long long chunk = (p.Pp + splits - 1) / splits;
+    chunk = (chunk + 31) / 32 * 32;
+    p.splits = (int)((p.Pp + chunk - 1) / chunk);
+    p.chunk = chunk;
+    p.waves = tiles * p.splits;
+    // workspace: dz_t (cout x Pp), xs (3 x cin x Pp) BF16, partials FP32
+    p.dz_t_bytes = (size_t)cout * p.Pp * 2;
+    p.xs_bytes = (size_t)3 * cin * p.Pp * 2;
+    p.part_bytes = (size_t)p.splits * cout * 9 * cin * 4;
+    return p;
+}
+
+hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, int h, int w,
+                        int cin, int cout, float *dw, float *db, void *ws, hipStream_t s) {
+    const WgradPlan p = wgrad_plan(n, h, w, cin, cout);
+    uint16_t *dz_t = static_cast<uint16_t *>(ws);
+    uint16_t *xs = reinterpret_cast<uint16_t *>(static_cast<char *>(ws) + align256(p.dz_t_bytes));
+    float *part = reinterpret_cast<float *>(static_cast<char *>(ws) + align256(p.dz_t_bytes) +
+                                            align256(p.xs_bytes));
+    hipLaunchKernelGGL(transpose_dz_kernel, dim3(blocks_for(p.Pp * cout)), dim3(THREADS), 0, s,
+                       static_cast<const uint16_t *>(dz), dzp, p.P, p.Pp, cout, dz_t);
+    hipLaunchKernelGGL(transpose_shift_kernel, dim3(blocks_for(3 * p.Pp * cin)), dim3(THREADS), 0,
+                       s, static_cast<const uint16_t *>(x), xp, n, h, w, p.Pp, cin, xs);
+    WgradArgs a;
+    a.dz_t = dz_t;
+    a.xs = xs;
+    a.part = part;
+    a.n = n;
+    a.h = h;
+    a.w = w;
+    a.cin = cin;
+    a.cout = cout;
+    a.P = p.P;
+    a.Pp = p.Pp;
+    a.chunk = p.chunk;
+    a.splits = p.splits;
+    const dim3 grid((unsigned)((p.waves + 3) / 4));
+    if (p.ni == 2)
+        hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(THREADS), 0, s, a);
+    const long long count = (long long)cout * 9 * cin;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for(count)), dim3(THREADS), 0, s, part,
+                       p.splits, count, dw);
+    if (db)
+        hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)cout), dim3(THREADS), 0, s, dz_t, p.Pp,
+                           db);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaky_bwd(const void *dy, int dyp, const void *y, int yp, void *dz, int dzp,
+                            long long pixels, int c, float slope, hipStream_t s) {
+    hipLaunchKernelGGL(leaky_bwd_kernel, dim3(blocks_for(pixels * (c / 8))), dim3(THREADS), 0, s,
+                       static_cast<const uint16_t *>(dy), dyp, static_cast<const uint16_t *>(y),
+                       yp, static_cast<uint16_t *>(dz), dzp, pixels, c, slope);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool2(const void *x, int xp, int n, int h, int w, int c, void *y, int yp,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(pool2_kernel, dim3(blocks_for((long long)n * (h / 2) * (w / 2) * (c / 8))),
+                       dim3(THREADS), 0, s, static_cast<const uint16_t *>(x), xp, n, h, w, c,
+                       static_cast<uint16_t *>(y), yp);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool2_bwd(const void *dy, int dyp, int n, int h, int w, int c, void *dx,
+                            int dxp, bool accumulate, hipStream_t s) {
+    hipLaunchKernelGGL(pool2_bwd_kernel, dim3(blocks_for((long long)n * h * w * (c / 8))),
+                       dim3(THREADS), 0, s, static_cast<const uint16_t *>(dy), dyp, n, h, w, c,
+                       static_cast<uint16_t *>(dx), dxp, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_up2(const void *x, int xp, int n, int h, int w, int c, void *y, int yp,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(up2_kernel, dim3(blocks_for((long long)n * 4 * h * w * (c / 8))),
+                       dim3(THREADS), 0, s, static_cast<const uint16_t *>(x), xp, n, h, w, c,
+                       static_cast<uint16_t *>(y), yp);
+    return hipGetLastError();
+}
+
+hipError_t launch_up2_bwd(const void *dy, int dyp, int n, int h, int w, int c, void *dx, int dxp,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(up2_bwd_kernel, dim3(blocks_for((long long)n * h * w * (c / 8))),
+                       dim3(THREADS), 0, s, static_cast<const uint16_t *>(dy), dyp, n, h, w, c,
+                       static_cast<uint16_t *>(dx), dxp);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input(const float *rho, int batch, int h, int w, const float *planes,
+                             const IoScales &sc, void *x, hipStream_t s) {
+    hipLaunchKernelGGL(pack_input_kernel, dim3(blocks_for((long long)batch * h * w)),
+                       dim3(THREADS), 0, s, rho, batch, h, w, planes, sc,
+                       static_cast<uint16_t *>(x));
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_output(const float *rho, const float *out, int batch, int h, int w,
+                               const IoScales &sc, float *next, hipStream_t s) {
+    hipLaunchKernelGGL(apply_output_kernel, dim3(blocks_for((long long)batch * h * w * 5)),
+                       dim3(THREADS), 0, s, rho, out, batch, h, w, sc, next);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse(const float *out, const float *rho, const float *target, int batch, int h,
+                      int w, const IoScales &sc, void *dout, double *partials, double *loss,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(mse_kernel, dim3(SUR_LOSS_BLOCKS), dim3(THREADS), 0, s, out, rho, target,
+                       batch, h, w, sc, static_cast<uint16_t *>(dout), partials);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(THREADS), 0, s, partials,
+                       SUR_LOSS_BLOCKS, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *theta, void *theta_bf16, const float *grad, float *m, float *v,
+                       long long count, const AdamArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(count)), dim3(THREADS), 0, s, theta,
+                       static_cast<uint16_t *>(theta_bf16), grad, m, v, count, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_crop(const float *rho, int h, int w, int y0, int x0, int ch, int cw, float *dst,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(crop_kernel, dim3(blocks_for(5ll * ch * cw)), dim3(THREADS), 0, s, rho, h,
+                       w, y0 % h, x0 % w, ch, cw, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *src, void *dst, long long count, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(count)), dim3(THREADS), 0, s, src,
+                       static_cast<uint16_t *>(dst), count);
+    return hipGetLastError();
+}
+
+}  // namespace sslbm

@@ -1,0 +1,555 @@
+"""Learned surrogate of the SSLBM: a periodic 3x3-convolution U-Net on BF16
+MFMA (FP32 accumulation) that advances the five SEIRD densities by a fixed
+number of SSLBM steps in one evaluation, trained on the GPU on states the
+SSLBM itself produces, with plain SSLBM as its fallback and error judge.
+
+Every operation runs in the library's HIP kernels (include/surrogate.h);
+this module allocates the buffers (torch, device memory only) and calls the
+kernels in order: it is the network's layer plan and the training and
+rollout loops.
+
+Network (levels L, base width C, channels C_l = C 2^l):
+  encoder level l: a_l = act(conv(in_l)), e_l = act(conv(a_l)),
+                   in_0 = packed input (16 channels), in_l = pool(e_{l-1});
+  decoder level l (L-2 .. 0): cat_l = [up(h_{l+1}), e_l],
+                   b_l = act(conv(cat_l)), h_l = act(conv(b_l)), h_{L-1} = e_{L-1};
+  output: conv(h_0) -> 16 FP32 channels, of which the first 5 are the
+  increments of S, E, I, R, D in units of per-compartment scales.
+The prediction is rho + scale_out * out (the network learns the increment).
+e_l lives inside cat_l (channel offset C_{l+1}), so the skip connection
+needs no copy.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from .binding import OK, SSLBMError, library
+
+LEAKY, OUT_F32 = 1, 2
+IN_CHANNELS = OUT_CHANNELS = 16
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, offset_elems: int = 0):
+    return ctypes.c_void_p(t.data_ptr() + offset_elems * t.element_size())
+
+
+def _check(st, what):
+    if st != OK:
+        raise SSLBMError(st, what)
+
+
+def _floats(v):
+    return (ctypes.c_float * len(v))(*[float(x) for x in v])
+
+
+class _View:
+    """A BF16 NHWC view: buffer, channel offset, channels (pitch = buffer's)."""
+
+    def __init__(self, buf, offset: int, channels: int):
+        self.buf, self.offset, self.c = buf, offset, channels
+
+    @property
+    def pitch(self):
+        return self.buf.shape[-1]
+
+    @property
+    def ptr(self):
+        return _ptr(self.buf, self.offset)
+
+
+@dataclass
+class _Conv:
+    cin: int
+    cout: int
+    act: bool
+    w_off: int = 0  # offset of W [cout][9][cin] in the flat parameter vector
+    b_off: int = 0  # offset of b [cout]
+
+
+class UNet:
+    """The surrogate network: parameters (FP32 master, BF16 copy), Adam
+    state, and the forward and backward passes over a batch."""
+
+    def __init__(self, levels: int = 4, base: int = 32, slope: float = 0.1, seed: int = 0):
+        torch = _torch()
+        self.lib = library()
+        self.levels, self.base, self.slope = levels, base, slope
+        self.ch = [base * 2 ** l for l in range(levels)]
+        convs = []
+        c = IN_CHANNELS
+        for l in range(levels):
+            convs += [_Conv(c, self.ch[l], True), _Conv(self.ch[l], self.ch[l], True)]
+            c = self.ch[l]
+        for l in range(levels - 2, -1, -1):
+            convs += [_Conv(self.ch[l + 1] + self.ch[l], self.ch[l], True),
+                      _Conv(self.ch[l], self.ch[l], True)]
+        convs.append(_Conv(self.ch[0], OUT_CHANNELS, False))
+        off = 0
+        for cv in convs:
+            cv.w_off = off
+            off += cv.cout * 9 * cv.cin
+            off = (off + 7) // 8 * 8  # keep every weight block 16-byte aligned in BF16
+            cv.b_off = off
+            off += (cv.cout + 7) // 8 * 8
+        self.convs, self.count = convs, off
+        # He initialisation for the activated layers; a small last layer, so
+        # the untrained network predicts increments near zero
+        rng = np.random.default_rng(seed)
+        theta = np.zeros(off, np.float32)
+        for k, cv in enumerate(convs):
+            std = math.sqrt(2.0 / (9 * cv.cin)) * (1.0 if cv.act else 0.1)
+            theta[cv.w_off:cv.w_off + cv.cout * 9 * cv.cin] = rng.normal(
+                0.0, std, cv.cout * 9 * cv.cin)
+        self.theta = torch.tensor(theta, device="cuda")
+        self.theta_bf16 = torch.empty(off, dtype=torch.bfloat16, device="cuda")
+        self.grad = torch.zeros_like(self.theta)
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.step_count = 0
+        _check(self.lib.sur_to_bf16(_ptr(self.theta), _ptr(self.theta_bf16), off, None),
+               "sur_to_bf16")
+        self._shape = None
+
+    @property
+    def parameters(self) -> int:
+        return sum(cv.cout * 9 * cv.cin + cv.cout for cv in self.convs)
+
+    def flops(self, batch: int, h: int, w: int) -> float:
+        """Multiply-add flops (x2) of one forward pass."""
+        total = 0.0
+        for k, cv in enumerate(self._levels_of_convs()):
+            hh, ww = h >> cv[1], w >> cv[1]
+            total += 2.0 * batch * hh * ww * 9 * cv[0].cin * cv[0].cout
+        return total
+
+    def _levels_of_convs(self):
+        L = self.levels
+        lv = []
+        for l in range(L):
+            lv += [l, l]
+        for l in range(L - 2, -1, -1):
+            lv += [l, l]
+        lv.append(0)
+        return list(zip(self.convs, lv))
+
+    # ------------------------------------------------------------ buffers --
+    def _buffers(self, n, h, w):
+        if self._shape == (n, h, w):
+            return
+        torch = _torch()
+        bf = torch.bfloat16
+        L, ch = self.levels, self.ch
+        if h % (1 << (L - 1)) or w % (8 << (L - 1)):
+            raise ValueError(f"grid {h}x{w} must be divisible by {1 << (L - 1)} (rows) and "
+                             f"{8 << (L - 1)} (columns)")
+        dims = [(h >> l, w >> l) for l in range(L)]
+        mk = lambda l, c: torch.empty((n, dims[l][0], dims[l][1], c), dtype=bf, device="cuda")
+        self.x0 = torch.empty((n, h, w, IN_CHANNELS), dtype=bf, device="cuda")
+        self.a = [mk(l, ch[l]) for l in range(L)]
+        self.pool = [None] + [mk(l, ch[l - 1]) for l in range(1, L)]
+        self.cat = [mk(l, ch[l + 1] + ch[l]) for l in range(L - 1)]
+        self.e_last = mk(L - 1, ch[L - 1])
+        self.b = [mk(l, ch[l]) for l in range(L - 1)]
+        self.hdec = [mk(l, ch[l]) for l in range(L - 1)]
+        self.out = torch.empty((n, h, w, OUT_CHANNELS), dtype=torch.float32, device="cuda")
+        # gradients
+        self.g_cat = [mk(l, ch[l + 1] + ch[l]) for l in range(L - 1)]
+        self.g_l = [mk(l, ch[l]) for l in range(L)]      # gradient of a level's C_l tensors
+        self.g_l2 = [mk(l, ch[l]) for l in range(L)]
+        self.g_pool = [None] + [mk(l, ch[l - 1]) for l in range(1, L)]
+        self.g_e_last = mk(L - 1, ch[L - 1])
+        self.dout = torch.empty((n, h, w, OUT_CHANNELS), dtype=bf, device="cuda")
+        ws = 0
+        for cv, l in self._levels_of_convs():
+            ws = max(ws, self.lib.sur_conv3x3_backward_weight_workspace(
+                n, dims[l][0], dims[l][1], cv.cin, cv.cout))
+        self.wgrad_ws = torch.empty(ws, dtype=torch.uint8, device="cuda")
+        self.flip = torch.empty(max(cv.cout * 9 * cv.cin for cv in self.convs) + 64, dtype=bf,
+                                device="cuda")
+        self.dims = dims
+        self._shape = (n, h, w)
+
+    def e_view(self, l):
+        """View of encoder output e_l (inside cat_l, or its own buffer)."""
+        if l == self.levels - 1:
+            return _View(self.e_last, 0, self.ch[l])
+        return _View(self.cat[l], self.ch[l + 1], self.ch[l])
+
+    # ------------------------------------------------------------ forward --
+    def _conv(self, k, src: _View, dst, l, f32=False):
+        cv = self.convs[k]
+        n = self._shape[0]
+        hh, ww = self.dims[l]
+        flags = (LEAKY if cv.act else 0) | (OUT_F32 if f32 else 0)
+        dptr = dst.ptr if isinstance(dst, _View) else _ptr(dst)
+        dpitch = dst.pitch if isinstance(dst, _View) else dst.shape[-1]
+        _check(self.lib.sur_conv3x3_forward(
+            src.ptr, src.pitch, n, hh, ww, cv.cin, _ptr(self.theta_bf16, cv.w_off),
+            _ptr(self.theta, cv.b_off), dptr, dpitch, cv.cout, flags, self.slope, None),
+            "sur_conv3x3_forward")
+
+    def forward_packed(self):
+        """Network pass on self.x0 into self.out (FP32 NHWC, 16 channels)."""
+        L, ch, lib = self.levels, self.ch, self.lib
+        n = self._shape[0]
+        k = 0
+        for l in range(L):
+            src = _View(self.x0, 0, IN_CHANNELS) if l == 0 else _View(self.pool[l], 0, ch[l - 1])
+            self._conv(k, src, _View(self.a[l], 0, ch[l]), l)
+            self._conv(k + 1, _View(self.a[l], 0, ch[l]), self.e_view(l), l)
+            k += 2
+            if l + 1 < L:
+                e = self.e_view(l)
+                hh, ww = self.dims[l]
+                _check(lib.sur_pool2(e.ptr, e.pitch, n, hh, ww, ch[l], _ptr(self.pool[l + 1]),
+                                     ch[l], None), "sur_pool2")
+        h_view = self.e_view(L - 1)
+        for l in range(L - 2, -1, -1):
+            hh, ww = self.dims[l + 1]
+            _check(lib.sur_up2(h_view.ptr, h_view.pitch, n, hh, ww, ch[l + 1], _ptr(self.cat[l]),
+                               self.cat[l].shape[-1], None), "sur_up2")
+            self._conv(k, _View(self.cat[l], 0, ch[l + 1] + ch[l]), _View(self.b[l], 0, ch[l]), l)
+            self._conv(k + 1, _View(self.b[l], 0, ch[l]), _View(self.hdec[l], 0, ch[l]), l)
+            k += 2
+            h_view = _View(self.hdec[l], 0, ch[l])
+        self._conv(k, h_view, self.out, 0, f32=True)
+        return self.out
+
+    # ----------------------------------------------------------- backward --
+    def _conv_backward(self, k, x: _View, y: _View, gy: _View, gx, l):
+        """Gradients of conv k (input x, output y, output gradient gy, which
+        is turned into dZ in place); dX into view gx unless gx is None."""
+        cv = self.convs[k]
+        lib = self.lib
+        n = self._shape[0]
+        hh, ww = self.dims[l]
+        if cv.act:
+            _check(lib.sur_leaky_backward(gy.ptr, gy.pitch, y.ptr, y.pitch, gy.ptr, gy.pitch,
+                                          n * hh * ww, cv.cout, self.slope, None),
+                   "sur_leaky_backward")
+        ws = self.wgrad_ws
+        _check(lib.sur_conv3x3_backward_weight(
+            x.ptr, x.pitch, gy.ptr, gy.pitch, n, hh, ww, cv.cin, cv.cout,
+            _ptr(self.grad, cv.w_off), _ptr(self.grad, cv.b_off), _ptr(ws), ws.numel(), None),
+            "sur_conv3x3_backward_weight")
+        if gx is not None:
+            _check(lib.sur_conv3x3_backward_data(
+                gy.ptr, gy.pitch, n, hh, ww, cv.cout, _ptr(self.theta_bf16, cv.w_off), cv.cin,
+                gx.ptr, gx.pitch, _ptr(self.flip), None), "sur_conv3x3_backward_data")
+
+    def backward_packed(self):
+        """Parameter gradients (into self.grad) from self.dout (BF16 NHWC,
+        the loss gradient of self.out)."""
+        L, ch, lib = self.levels, self.ch, self.lib
+        n = self._shape[0]
+        k = len(self.convs) - 1
+        h_in = _View(self.hdec[0], 0, ch[0]) if L > 1 else self.e_view(0)
+        g_h = _View(self.g_l[0], 0, ch[0])
+        # output layer (no activation: dZ = dout)
+        self._conv_backward(k, h_in, None, _View(self.dout, 0, OUT_CHANNELS), g_h, 0)
+        k -= 1
+        # decoder, from the top level down
+        for l in range(0, L - 1):
+            k_first = len(self.convs) - 1 - 2 * (l + 1)
+            b = _View(self.b[l], 0, ch[l])
+            hdec = _View(self.hdec[l], 0, ch[l])
+            g_b = _View(self.g_l2[l], 0, ch[l])
+            self._conv_backward(k_first + 1, b, hdec, _View(self.g_l[l], 0, ch[l]), g_b, l)
+            cat = _View(self.cat[l], 0, ch[l + 1] + ch[l])
+            g_cat = _View(self.g_cat[l], 0, ch[l + 1] + ch[l])
+            self._conv_backward(k_first, cat, b, g_b, g_cat, l)
+            # gradient of the upsampled input -> the level below's output
+            below = (_View(self.g_l[l + 1], 0, ch[l + 1]) if l + 1 < L - 1
+                     else _View(self.g_e_last, 0, ch[L - 1]))
+            hh, ww = self.dims[l + 1]
+            _check(lib.sur_up2_backward(_ptr(self.g_cat[l]), self.g_cat[l].shape[-1], n, hh, ww,
+                                        ch[l + 1], below.ptr, below.pitch, None),
+                   "sur_up2_backward")
+        # encoder, from the bottleneck up
+        for l in range(L - 1, -1, -1):
+            k1 = 2 * l
+            if l == L - 1:
+                g_e = _View(self.g_e_last, 0, ch[l])
+            else:
+                g_e = _View(self.g_cat[l], ch[l + 1], ch[l])  # skip gradient already there
+                hh, ww = self.dims[l]
+                _check(lib.sur_pool2_backward(_ptr(self.g_pool[l + 1]), ch[l], n, hh, ww, ch[l],
+                                              g_e.ptr, g_e.pitch, 1, None), "sur_pool2_backward")
+            a = _View(self.a[l], 0, ch[l])
+            g_a = _View(self.g_l2[l], 0, ch[l])
+            self._conv_backward(k1 + 1, a, self.e_view(l), g_e, g_a, l)
+            src = _View(self.x0, 0, IN_CHANNELS) if l == 0 else _View(self.pool[l], 0, ch[l - 1])
+            g_src = None if l == 0 else _View(self.g_pool[l], 0, ch[l - 1])
+            self._conv_backward(k1, src, a, g_a, g_src, l)
+
+    def adam(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        _check(self.lib.sur_adam(_ptr(self.theta), _ptr(self.theta_bf16), _ptr(self.grad),
+                                 _ptr(self.m), _ptr(self.v), self.count, self.step_count,
+                                 lr, beta1, beta2, eps, None), "sur_adam")
+
+    def copy_from(self, other: "UNet"):
+        self.theta.copy_(other.theta)
+        _check(self.lib.sur_to_bf16(_ptr(self.theta), _ptr(self.theta_bf16), self.count, None),
+               "sur_to_bf16")
+
+    def weights_numpy(self):
+        """(W [cout][9][cin], b) per conv as the BF16 values the kernels use,
+        in FP64 (for checks against a reference implementation)."""
+        wb = self.theta_bf16.float().cpu().numpy().astype(np.float64)
+        th = self.theta.cpu().numpy().astype(np.float64)
+        out = []
+        for cv in self.convs:
+            w = wb[cv.w_off:cv.w_off + cv.cout * 9 * cv.cin].reshape(cv.cout, 9, cv.cin)
+            out.append((w, th[cv.b_off:cv.b_off + cv.cout]))
+        return out
+
+    def grads_numpy(self):
+        g = self.grad.cpu().numpy().astype(np.float64)
+        return [(g[cv.w_off:cv.w_off + cv.cout * 9 * cv.cin].reshape(cv.cout, 9, cv.cin),
+                 g[cv.b_off:cv.b_off + cv.cout]) for cv in self.convs]
+
+
+# ------------------------------------------------------------- the model --
+
+def param_planes(params_list):
+    """The 9 constant input planes of each instance: rates relative to the
+    workloads' typical values and log10 lattice diffusivities (0 for a
+    compartment at rest)."""
+    rows = []
+    for p in params_list:
+        dl = [d * p.dt / (p.dx * p.dx) for d in p.d]
+        rows.append([p.beta / 0.3 - 1.0, p.alpha / 0.2 - 1.0, p.gamma / 0.11 - 1.0,
+                     p.phi / 0.09 - 1.0] + [(math.log10(v) + 3.0) if v > 0 else 0.0 for v in dl])
+    return rows
+
+
+class Surrogate:
+    """A trained network plus its input/output scales: advances FP32 states
+    [batch][5][h][w] by `jump` SSLBM steps per evaluation."""
+
+    def __init__(self, net: UNet, jump: int, scale_in, scale_out):
+        self.net, self.jump = net, int(jump)
+        self.scale_in = [float(v) for v in scale_in]
+        self.scale_out = [float(v) for v in scale_out]
+        self.lib = library()
+
+    def predict(self, rho, planes, out=None):
+        torch = _torch()
+        b, _, h, w = rho.shape
+        self.net._buffers(b, h, w)
+        pl = torch.tensor(planes, dtype=torch.float32, device="cuda").contiguous()
+        _check(self.lib.sur_pack_input(_ptr(rho), b, h, w, _ptr(pl), _floats(self.scale_in),
+                                       _ptr(self.net.x0), None), "sur_pack_input")
+        self.net.forward_packed()
+        if out is None:
+            out = torch.empty_like(rho)
+        _check(self.lib.sur_apply_output(_ptr(rho), _ptr(self.net.out), b, h, w,
+                                         _floats(self.scale_out), _ptr(out), None),
+               "sur_apply_output")
+        return out
+
+
+def _ensemble_batch(params_list, h, w, seed, warm, jump):
+    """States (x_t, x_{t+jump}) of a batch of equal grids from 1-8 seeded
+    Gaussian foci after `warm` SSLBM steps, advanced together by the
+    library's ensemble kernel (FP32)."""
+    torch = _torch()
+    from .binding import Ensemble
+    from .inputs import gaussian_foci_state
+    rng = np.random.default_rng(seed)
+    ens = Ensemble([(w, h)] * len(params_list), params_list, dtype="f32")
+    flat = ens.empty()
+    states = []
+    for v in ens.views(flat):
+        foci = int(rng.integers(1, 9))
+        centres = list(zip(rng.integers(0, w, foci).tolist(), rng.integers(0, h, foci).tolist()))
+        amp = float(rng.uniform(0.005, 0.05))
+        v.copy_(torch.tensor(gaussian_foci_state(w, h, centres, amp, float(rng.uniform(3, 8))),
+                             dtype=torch.float32, device="cuda"))
+    scratch = ens.empty()
+    if warm:
+        ens.run(flat, warm, scratch)
+    b = len(params_list)
+    x_t = flat.view(b, 5, h, w).clone()  # instance blocks are contiguous (5 h w % 4 == 0)
+    ens.run(flat, jump, scratch)
+    x_next = flat.view(b, 5, h, w).clone()
+    return x_t, x_next
+
+
+def sample_params(rng, count):
+    """Rates and diffusivities of the training distribution: R0 uniform in
+    [1.5, 5] through beta = R0 (gamma + mu), sigma = 0.2, gamma = 0.1,
+    mu = 0.01, lattice diffusivities of S, E, I, R log-uniform in
+    [1e-4, 1e-2], D at rest."""
+    from .inputs import from_sigma_mu
+    out = []
+    for _ in range(count):
+        r0 = rng.uniform(1.5, 5.0)
+        dl = tuple(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2), 4)).tolist()) + (0.0,)
+        out.append(from_sigma_mu(r0 * 0.11, 0.2, 0.1, 0.01, dl))
+    return out
+
+
+@dataclass
+class TrainReport:
+    steps: int
+    batch: int
+    seconds: float
+    first_loss: float
+    last_loss: float
+    samples: int
+    conv_tflops: float
+
+
+def train(net: UNet, *, steps=300, batch=16, size=256, jump=50, lr=1e-3, seed=0,
+          max_warm=1500, log=None):
+    """Train on freshly generated SSLBM pairs; returns (Surrogate, TrainReport)."""
+    torch = _torch()
+    lib = library()
+    rng = np.random.default_rng(seed)
+    # scales from probe batches spread over the warm-up range: RMS of each
+    # density and of its increment over `jump` steps (with floors, so a
+    # compartment that is still empty does not get a vanishing scale)
+    sq_in, sq_out = np.zeros(5), np.zeros(5)
+    probes = 4
+    for j in range(probes):
+        plist = sample_params(rng, batch)
+        x_t, x_n = _ensemble_batch(plist, size, size, int(rng.integers(1 << 30)),
+                                   (j * max_warm) // max(probes - 1, 1), jump)
+        for c in range(5):
+            sq_in[c] += float(torch.mean(x_t[:, c].double() ** 2)) / probes
+            sq_out[c] += float(torch.mean((x_n[:, c] - x_t[:, c]).double() ** 2)) / probes
+    scale_in = [max(math.sqrt(v), 1e-3) for v in sq_in]
+    scale_out = [max(math.sqrt(v), 1e-5) for v in sq_out]
+    sur = Surrogate(net, jump, scale_in, scale_out)
+    partials = torch.empty(1024, dtype=torch.float64, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        plist = sample_params(rng, batch)
+        x_t, x_n = _ensemble_batch(plist, size, size, int(rng.integers(1 << 30)),
+                                   int(rng.integers(0, max_warm + 1)), jump)
+        net._buffers(batch, size, size)
+        pl = torch.tensor(param_planes(plist), dtype=torch.float32, device="cuda")
+        _check(lib.sur_pack_input(_ptr(x_t), batch, size, size, _ptr(pl), _floats(scale_in),
+                                  _ptr(net.x0), None), "sur_pack_input")
+        net.forward_packed()
+        _check(lib.sur_mse_loss(_ptr(net.out), _ptr(x_t), _ptr(x_n), batch, size, size,
+                                _floats(scale_out), _ptr(net.dout), _ptr(partials), _ptr(loss),
+                                None), "sur_mse_loss")
+        net.backward_packed()
+        # cosine decay of the learning rate
+        net.adam(lr * 0.5 * (1.0 + math.cos(math.pi * it / max(steps, 1))))
+        if it == 0 or it == steps - 1 or (log and it % 50 == 0):
+            losses.append((it, float(loss)))
+            if log:
+                log(f"train step {it}: loss {float(loss):.4e}")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    flops = 3.0 * net.flops(batch, size, size) * steps
+    rep = TrainReport(steps, batch, secs, losses[0][1], losses[-1][1], steps * batch,
+                      flops / secs / 1e12)
+    return sur, rep
+
+
+# --------------------------------------------------------------- rollout --
+
+@dataclass
+class RolloutReport:
+    jumps: int
+    accepted: int
+    fallbacks: int
+    seconds: float
+    max_check_error: float
+    min_check_error: float
+
+
+def _rel_l2_max(a, b):
+    """Largest per-compartment relative L2 difference of [.., 5, h, w] states."""
+    torch = _torch()
+    worst = 0.0
+    for c in range(5):
+        num = torch.linalg.vector_norm((a[..., c, :, :] - b[..., c, :, :]).double())
+        den = torch.linalg.vector_norm(b[..., c, :, :].double())
+        worst = max(worst, float(num / den) if float(den) > 0 else float(num))
+    return worst
+
+
+class Rollout:
+    """Advance one grid to step T in jumps of the surrogate, each judged by
+    plain SSLBM recomputed on seeded sub-tiles: a tile of side `tile` is
+    cropped with a halo of `jump` cells (the dependence cone of `jump`
+    steps), advanced `jump` steps, and its centre compared with the
+    surrogate's prediction. A jump whose largest per-compartment relative L2
+    error exceeds `threshold` is redone by plain SSLBM from the same state."""
+
+    def __init__(self, sur: Surrogate, params, h: int, w: int, *, tiles=4, tile=64,
+                 threshold=1e-3, seed=0):
+        from .binding import Ensemble, Solver
+        torch = _torch()
+        self.sur, self.params, self.h, self.w = sur, params, h, w
+        self.tiles, self.tile, self.threshold = tiles, tile, threshold
+        self.rng = np.random.default_rng(seed)
+        self.solver = Solver(w, h, params, dtype="f32")
+        self.scratch = torch.empty((5, h, w), dtype=torch.float32, device="cuda")
+        side = tile + 2 * sur.jump
+        self.ens = Ensemble([(side, side)] * tiles, [params] * tiles, dtype="f32")
+        self.crops = self.ens.empty()
+        self.crop_scratch = self.ens.empty()
+        self.pred_crops = torch.empty((tiles, 5, tile, tile), dtype=torch.float32, device="cuda")
+        self.planes = param_planes([params])
+        self.lib = library()
+
+    def _judge(self, state, pred):
+        jump, tile = self.sur.jump, self.tile
+        side = tile + 2 * jump
+        views = self.ens.views(self.crops)
+        corners = [(int(self.rng.integers(0, self.h)), int(self.rng.integers(0, self.w)))
+                   for _ in range(self.tiles)]
+        for (y0, x0), v, pc in zip(corners, views, self.pred_crops):
+            _check(self.lib.sur_crop_periodic(_ptr(state), self.h, self.w, y0 - jump, x0 - jump,
+                                              side, side, _ptr(v), None), "sur_crop_periodic")
+            _check(self.lib.sur_crop_periodic(_ptr(pred), self.h, self.w, y0, x0, tile, tile,
+                                              _ptr(pc), None), "sur_crop_periodic")
+        self.ens.run(self.crops, jump, self.crop_scratch)
+        ref = _torch().stack([v[:, jump:jump + tile, jump:jump + tile] for v in views])
+        return _rel_l2_max(self.pred_crops, ref)
+
+    def run(self, rho0, T: int):
+        """Returns (state at T, RolloutReport); T a multiple of the jump."""
+        torch = _torch()
+        jump = self.sur.jump
+        if T % jump:
+            raise ValueError(f"T must be a multiple of {jump}")
+        state = rho0.clone()
+        pred = torch.empty_like(state)
+        accepted = fallbacks = 0
+        errs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(T // jump):
+            self.sur.predict(state[None], self.planes, out=pred[None])
+            err = self._judge(state, pred)
+            errs.append(err)
+            if err <= self.threshold:
+                state, pred = pred, state
+                accepted += 1
+            else:
+                self.solver.run(state, jump, self.scratch)
+                fallbacks += 1
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        return state, RolloutReport(T // jump, accepted, fallbacks, secs, max(errs), min(errs))

@@ -214,3 +214,33 @@ def test_adjoint_host_checks(lib):
     # nothing to do for a run of zero steps: no GPU call is made
     assert lib.sslbm_adjoint_run(h, a, 0, 5, b, g, w, None) == binding.OK
     lib.sslbm_destroy(h)
+
+
+def test_surrogate_header_exports_and_host_checks(lib):
+    """surrogate.h: every declared function is exported, and bad arguments
+    are rejected on the host (no GPU call is made for them)."""
+    text = re.sub(r"/\*.*?\*/", "", (binding.HEADER.parent / "surrogate.h").read_text(), flags=re.S)
+    names = sorted(set(SIG_RE.findall(text)))
+    assert "sur_conv3x3_forward" in names and "sur_adam" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    vp = ctypes.c_void_p
+    a, b, c = vp(0x100000000), vp(0x200000000), vp(0x300000000)
+    fwd = lib.sur_conv3x3_forward
+    assert fwd(a, 16, 1, 8, 8, 16, b, None, c, 16, 32, 0, 0.1, None) == binding.E_ARG  # pitch < cout
+    assert fwd(vp(a.value + 2), 16, 1, 8, 8, 16, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG
+    assert fwd(a, 16, 1, 8, 8, 12, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG  # cin % 8
+    assert fwd(a, 16, 0, 8, 8, 16, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG
+    assert fwd(a, 16, 1, 8, 8, 16, b, None, c, 32, 32, 4, 0.1, None) == binding.E_ARG  # flags
+    assert lib.sur_conv3x3_backward_weight_workspace(1, 8, 12, 16, 16) == 0  # w % 8
+    assert lib.sur_conv3x3_backward_weight_workspace(1, 8, 16, 16, 16) > 0
+    ws = lib.sur_conv3x3_backward_weight_workspace(2, 8, 16, 32, 64)
+    assert lib.sur_conv3x3_backward_weight(a, 32, b, 64, 2, 8, 16, 32, 64, c, None, vp(0x400000000),
+                                           ws - 1, None) == binding.E_ARG
+    assert lib.sur_pool2(a, 16, 1, 7, 8, 16, b, 16, None) == binding.E_ARG  # odd height
+    bad = (ctypes.c_float * 5)(1, 1, 0, 1, 1)
+    assert lib.sur_pack_input(a, 1, 8, 8, b, bad, c, None) == binding.E_ARG
+    assert lib.sur_adam(a, None, b, c, vp(0x500000000), 10, 0, 1e-3, 0.9, 0.999, 1e-8,
+                        None) == binding.E_ARG  # step 0
+    assert lib.sur_adam(a, None, b, c, vp(0x500000000), 10, 1, 1e-3, 1.0, 0.999, 1e-8,
+                        None) == binding.E_ARG  # beta1 = 1

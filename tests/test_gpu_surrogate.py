@@ -1,0 +1,288 @@
+"""Surrogate kernels (BF16 MFMA convolutions and the rest) against the FP64
+oracle of oracle/surrogate.py, through the C ABI; then the assembled U-Net,
+training, and the rollout's fallback.
+
+Tolerances. Inputs are BF16 values, which the oracle receives exactly. An
+FP32-accumulated dot product of K terms is within about K 2^-24 of the sum
+of |terms| (in practice far less); we allow 1e-5 of that sum. A BF16 output
+adds one rounding, at most 2^-9 of the value (allowed: 2^-8).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import surrogate as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2603_19789_amd import binding  # noqa: E402
+from paper_2603_19789_amd import surrogate as S  # noqa: E402
+
+RNG = np.random.default_rng(5)
+BF = torch.bfloat16
+
+
+def lib():
+    return binding.library()
+
+
+def p(t, off=0):
+    return ctypes.c_void_p(t.data_ptr() + off * t.element_size())
+
+
+def bf16_array(shape, scale=1.0):
+    """A BF16 GPU tensor and its exact FP64 values."""
+    t = torch.tensor(RNG.normal(scale=scale, size=shape), dtype=torch.float32).to(BF).cuda()
+    return t, t.float().cpu().numpy().astype(np.float64)
+
+
+def check_close(got, want, scale, rtol, what):
+    err = np.abs(got - want)
+    bound = rtol * np.abs(want) + 1e-5 * scale + 1e-30
+    worst = float(np.max(err / bound))
+    print(f"{what}: worst error / allowed = {worst:.3f}")
+    assert worst <= 1.0, what
+
+
+CONV_CASES = [
+    # n, h, w, cin, cout
+    (1, 8, 8, 16, 16), (2, 16, 24, 16, 32), (1, 32, 32, 32, 32), (2, 8, 16, 64, 128),
+    (1, 16, 16, 96, 32), (1, 9, 7, 24, 48), (1, 5, 13, 8, 40), (3, 4, 8, 384, 128),
+]
+
+
+@pytest.mark.parametrize("flags", [0, S.LEAKY, S.OUT_F32])
+@pytest.mark.parametrize("n,h,w,cin,cout", CONV_CASES)
+def test_conv_forward(n, h, w, cin, cout, flags):
+    print(f"conv fwd n={n} {h}x{w} {cin}->{cout} flags={flags}", flush=True)
+    # input as a channel slice of a wider buffer (pitch > channels, offset 8)
+    pitch = cin + 16
+    buf, bufv = bf16_array((n, h, w, pitch))
+    xv = bufv[..., 8:8 + cin]
+    wt, wv = bf16_array((cout, 9, cin), scale=1.0 / np.sqrt(9 * cin))
+    bias = torch.tensor(RNG.normal(size=cout), dtype=torch.float32).cuda()
+    f32 = bool(flags & S.OUT_F32)
+    y = torch.zeros((n, h, w, cout), dtype=torch.float32 if f32 else BF, device="cuda")
+    st = lib().sur_conv3x3_forward(p(buf, 8), pitch, n, h, w, cin, p(wt), p(bias), p(y), cout,
+                                   cout, flags, 0.1, None)
+    assert st == binding.OK
+    torch.cuda.synchronize()
+    want = O.conv3x3(xv, wv, bias.cpu().numpy())
+    if flags & S.LEAKY:
+        want = O.leaky(want, 0.1)
+    scale = O.conv3x3(np.abs(xv), np.abs(wv), np.abs(bias.cpu().numpy()))
+    check_close(y.float().cpu().numpy(), want, scale, 1e-6 if f32 else 2 ** -8, "forward")
+
+
+@pytest.mark.parametrize("n,h,w,cin,cout", CONV_CASES[:6])
+def test_conv_backward_data(n, h, w, cin, cout):
+    print(f"conv bwd-data n={n} {h}x{w} {cin}->{cout}", flush=True)
+    dz, dzv = bf16_array((n, h, w, cout))
+    wt, wv = bf16_array((cout, 9, cin), scale=1.0 / np.sqrt(9 * cin))
+    dx = torch.empty((n, h, w, cin), dtype=BF, device="cuda")
+    flip = torch.empty(cout * 9 * cin + 64, dtype=BF, device="cuda")
+    st = lib().sur_conv3x3_backward_data(p(dz), cout, n, h, w, cout, p(wt), cin, p(dx), cin,
+                                         p(flip), None)
+    assert st == binding.OK
+    torch.cuda.synchronize()
+    want = O.conv3x3_bwd_data(dzv, wv)
+    scale = O.conv3x3_bwd_data(np.abs(dzv), np.abs(wv))
+    check_close(dx.float().cpu().numpy(), want, scale, 2 ** -8, "backward data")
+
+
+WGRAD_CASES = [(1, 8, 8, 16, 16), (2, 16, 24, 16, 32), (2, 8, 16, 64, 128), (1, 16, 16, 96, 32),
+               (3, 4, 8, 384, 128), (1, 5, 8, 8, 40), (4, 32, 32, 32, 64)]
+
+
+@pytest.mark.parametrize("n,h,w,cin,cout", WGRAD_CASES)
+def test_conv_backward_weight(n, h, w, cin, cout):
+    print(f"conv bwd-weight n={n} {h}x{w} {cin}->{cout}", flush=True)
+    pitch = cin + 8
+    buf, bufv = bf16_array((n, h, w, pitch))
+    xv = bufv[..., :cin]
+    dz, dzv = bf16_array((n, h, w, cout))
+    dw = torch.empty((cout, 9, cin), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    ws_bytes = lib().sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout)
+    assert ws_bytes > 0
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    st = lib().sur_conv3x3_backward_weight(p(buf), pitch, p(dz), cout, n, h, w, cin, cout, p(dw),
+                                           p(db), p(ws), ws_bytes, None)
+    assert st == binding.OK
+    torch.cuda.synchronize()
+    want_w, want_b = O.conv3x3_bwd_weight(xv, dzv)
+    scale_w, scale_b = O.conv3x3_bwd_weight(np.abs(xv), np.abs(dzv))
+    check_close(dw.cpu().numpy(), want_w, scale_w, 1e-6, "backward weight")
+    check_close(db.cpu().numpy(), want_b, scale_b, 1e-6, "bias gradient")
+    # deterministic
+    dw2 = torch.empty_like(dw)
+    lib().sur_conv3x3_backward_weight(p(buf), pitch, p(dz), cout, n, h, w, cin, cout, p(dw2),
+                                      None, p(ws), ws_bytes, None)
+    assert torch.equal(dw, dw2)
+
+
+def test_pool_up_leaky():
+    n, h, w, c = 2, 8, 12, 24
+    x, xv = bf16_array((n, h, w, c))
+    y = torch.empty((n, h // 2, w // 2, c), dtype=BF, device="cuda")
+    L = lib()
+    assert L.sur_pool2(p(x), c, n, h, w, c, p(y), c, None) == binding.OK
+    check_close(y.float().cpu().numpy(), O.pool2(xv), 0, 2 ** -8, "pool2")
+    dy, dyv = bf16_array((n, h // 2, w // 2, c))
+    dx, dxv = bf16_array((n, h, w, c))
+    assert L.sur_pool2_backward(p(dy), c, n, h, w, c, p(dx), c, 1, None) == binding.OK
+    check_close(dx.float().cpu().numpy(), dxv + O.pool2_bwd(dyv), 0, 2 ** -8, "pool2 backward")
+    u = torch.empty((n, 2 * h, 2 * w, c), dtype=BF, device="cuda")
+    assert L.sur_up2(p(x), c, n, h, w, c, p(u), c, None) == binding.OK
+    assert np.array_equal(u.float().cpu().numpy(), O.up2(xv))
+    du, duv = bf16_array((n, 2 * h, 2 * w, c))
+    g = torch.empty((n, h, w, c), dtype=BF, device="cuda")
+    assert L.sur_up2_backward(p(du), c, n, h, w, c, p(g), c, None) == binding.OK
+    check_close(g.float().cpu().numpy(), O.up2_bwd(duv), 0, 2 ** -8, "up2 backward")
+    z = torch.empty_like(x)
+    assert L.sur_leaky_backward(p(dx), c, p(x), c, p(z), c, n * h * w, c, 0.1, None) == binding.OK
+    check_close(z.float().cpu().numpy(), O.leaky_bwd(dx.float().cpu().numpy(), xv, 0.1), 0,
+                2 ** -8, "leaky backward")
+
+
+def test_adam_matches_oracle():
+    count = 5000
+    theta0 = RNG.normal(size=count).astype(np.float32)
+    th = torch.tensor(theta0).cuda()
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    tb = torch.empty(count, dtype=BF, device="cuda")
+    ot, om, ov = theta0.astype(np.float64), np.zeros(count), np.zeros(count)
+    for step in range(1, 6):
+        g = RNG.normal(size=count).astype(np.float32)
+        gt = torch.tensor(g).cuda()
+        assert lib().sur_adam(p(th), p(tb), p(gt), p(m), p(v), count, step, 1e-2, 0.9, 0.999,
+                              1e-8, None) == binding.OK
+        ot, om, ov = O.adam(ot, g.astype(np.float64), om, ov, step, 1e-2)
+    got = th.cpu().numpy()
+    assert np.max(np.abs(got - ot)) < 1e-5
+    assert torch.equal(tb, th.to(BF))  # the BF16 copy is the round-to-nearest-even of theta
+
+
+def test_io_kernels_and_crop():
+    b, h, w = 2, 8, 16
+    rho = torch.tensor(RNG.uniform(0, 1, size=(b, 5, h, w)), dtype=torch.float32).cuda()
+    planes = RNG.normal(size=(b, 9))
+    scale_in, scale_out = [1.0, 0.05, 0.05, 0.5, 0.02], [0.01, 0.002, 0.003, 0.004, 1e-4]
+    fl = lambda v: (ctypes.c_float * 5)(*v)
+    x = torch.empty((b, h, w, 16), dtype=BF, device="cuda")
+    pl = torch.tensor(planes, dtype=torch.float32).cuda()
+    L = lib()
+    assert L.sur_pack_input(p(rho), b, h, w, p(pl), fl(scale_in), p(x), None) == binding.OK
+    rho_np = rho.cpu().numpy().astype(np.float64)
+    want = O.pack_input(rho_np, pl.cpu().numpy(), np.float32(scale_in))
+    check_close(x.float().cpu().numpy(), want, 0, 2 ** -8, "pack input")
+    out = torch.tensor(RNG.normal(size=(b, h, w, 16)), dtype=torch.float32).cuda()
+    nxt = torch.empty_like(rho)
+    assert L.sur_apply_output(p(rho), p(out), b, h, w, fl(scale_out), p(nxt), None) == binding.OK
+    want = O.apply_output(rho_np, out.cpu().numpy(), np.float32(scale_out))
+    assert np.max(np.abs(nxt.cpu().numpy() - want)) < 1e-6
+    target = rho + 0.01 * torch.randn_like(rho)
+    dout = torch.empty((b, h, w, 16), dtype=BF, device="cuda")
+    part = torch.empty(1024, dtype=torch.float64, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    assert L.sur_mse_loss(p(out), p(rho), p(target), b, h, w, fl(scale_out), p(dout), p(part),
+                          p(loss), None) == binding.OK
+    wl, wg = O.mse_loss(out.cpu().numpy(), rho_np, target.cpu().numpy().astype(np.float64),
+                        [float(np.float32(1 / s)) ** -1 for s in scale_out])
+    assert abs(float(loss) - wl) <= 1e-5 * wl
+    check_close(dout.float().cpu().numpy(), wg, np.max(np.abs(wg)), 2 ** -8, "loss gradient")
+    # periodic crop, negative corner
+    H, W = 20, 24
+    state = torch.tensor(RNG.normal(size=(5, H, W)), dtype=torch.float32).cuda()
+    dst = torch.empty((5, 9, 30), dtype=torch.float32, device="cuda")
+    assert L.sur_crop_periodic(p(state), H, W, -3, 17, 9, 30, p(dst), None) == binding.OK
+    ys = np.mod(np.arange(-3, 6), H)
+    xs = np.mod(np.arange(17, 47), W)
+    assert np.array_equal(dst.cpu().numpy(), state.cpu().numpy()[:, ys][:, :, xs])
+
+
+def _small_net():
+    return S.UNet(levels=3, base=16, slope=0.1, seed=3)
+
+
+def test_unet_forward_backward_against_oracle():
+    """The assembled network (3 levels, base 16, batch 2, 64x64) against the
+    oracle's U-Net with the same BF16 weights, once with the oracle storing
+    activations and gradients in BF16 where the kernels do (close agreement:
+    only FP32-versus-FP64 sums and the roundings they flip differ), and once
+    in plain FP64 (the BF16 storage itself moves the first layers' weight
+    gradients by several per cent; a miswired buffer would leave them
+    uncorrelated, so the direction is checked there). With random weights
+    and data the backward chain amplifies single roundings: the BF16 model
+    itself is 5-15 % from FP64 in the deep layers, and the kernels, whose
+    FP32 sums flip some of its roundings, are within a few per cent of it."""
+    net = _small_net()
+    n, h, w = 2, 64, 64
+    net._buffers(n, h, w)
+    x = torch.tensor(RNG.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF).cuda()
+    net.x0.copy_(x)
+    out = net.forward_packed().clone()
+    weights = net.weights_numpy()
+    spec = O.unet_spec(levels=3, base=16, cin=16, cout=16)
+    xv = x.float().cpu().numpy()
+    want16, tape16 = O.unet_forward(xv, weights, spec, 0.1, store=O.bf16_round)
+    want, tape = O.unet_forward(xv, weights, spec, 0.1)
+    got = out.cpu().numpy()
+    err16 = np.linalg.norm(got - want16) / np.linalg.norm(want16)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(f"U-Net forward rel L2: {err16:.3e} (BF16 storage model), {err:.3e} (FP64)")
+    assert err16 < 5e-3 and err < 2e-2
+    dout = torch.tensor(RNG.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF).cuda()
+    net.dout.copy_(dout)
+    net.backward_packed()
+    grads = net.grads_numpy()
+    dv = dout.float().cpu().numpy()
+    want_g16, _ = O.unet_backward(dv, weights, tape16, 0.1, store=O.bf16_round)
+    want_g, _ = O.unet_backward(dv, weights, tape, 0.1)
+    cos = lambda a, b: float(np.sum(a * b) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    for k, ((gw, gb), (ww, wb), (fw, fb)) in enumerate(zip(grads, want_g16, want_g)):
+        print(f"  layer {k}: weight gradient rel L2 {rel(gw, ww):.3e} (BF16 model), "
+              f"{rel(gw, fw):.3e} (FP64, cos {cos(gw, fw):.5f}); bias {rel(gb, wb):.3e}, "
+              f"{rel(gb, fb):.3e}")
+        assert rel(gw, ww) < 6e-2 and rel(gb, wb) < 6e-2, k
+        assert cos(gw, fw) > 0.98, k
+
+
+def test_training_learns_and_beats_persistence():
+    """A short training run on SSLBM pairs (64x64, jump of 20 steps): the
+    loss falls, and on held-out pairs the trained network's increment error
+    is well below that of predicting no change."""
+    net = _small_net()
+    sur, rep = S.train(net, steps=120, batch=8, size=64, jump=20, lr=2e-3, seed=1, max_warm=400)
+    print(f"train: loss {rep.first_loss:.3e} -> {rep.last_loss:.3e} in {rep.seconds:.1f} s")
+    assert rep.last_loss < 0.3 * rep.first_loss
+    rng = np.random.default_rng(99)
+    plist = S.sample_params(rng, 8)
+    x_t, x_n = S._ensemble_batch(plist, 64, 64, 1234, 300, 20)
+    pred = sur.predict(x_t, S.param_planes(plist))
+    err_net = float(torch.linalg.vector_norm((pred - x_n).double()))
+    err_still = float(torch.linalg.vector_norm((x_t - x_n).double()))
+    print(f"held-out: network {err_net:.3e}, no change {err_still:.3e}")
+    assert err_net < 0.5 * err_still
+
+
+def test_rollout_with_broken_network_falls_back_to_sslbm():
+    """A network with zeroed weights predicts no change; the sub-tile judge
+    rejects every jump and the rollout is plain SSLBM, bit for bit."""
+    from paper_2603_19789_amd import Solver, inputs
+    net = _small_net()
+    net.theta.zero_()
+    net.copy_from(net)
+    sur = S.Surrogate(net, 20, [1.0] * 5, [1e-3] * 5)
+    prm = inputs.c1_params()
+    rho0 = torch.tensor(inputs.c1_workload(64, 64).rho0, dtype=torch.float32).cuda()
+    roll = S.Rollout(sur, prm, 64, 64, tiles=2, tile=16, threshold=1e-3, seed=2)
+    state, rep = roll.run(rho0, 100)
+    assert rep.fallbacks == rep.jumps == 5 and rep.accepted == 0
+    ref = rho0.clone()
+    Solver(64, 64, prm, dtype="f32").run(ref, 100)
+    assert torch.equal(state, ref)

@@ -146,3 +146,63 @@ def test_unet_gradient_fd(slope):
         xm[idx] -= h
         fd = (loss(weights, xp) - loss(weights, xm)) / (2 * h)
         assert abs(dx[idx] - fd) <= 1e-5 * max(1.0, abs(fd)), idx
+
+
+def test_loss_gradient_fd_and_io_roundtrip():
+    rng = np.random.default_rng(3)
+    rho = rng.uniform(0, 1, size=(2, 5, 4, 6))
+    target = rho + rng.normal(scale=0.01, size=rho.shape)
+    scale = [0.5, 0.01, 0.02, 0.03, 0.001]
+    out = rng.normal(size=(2, 4, 6, 16))
+    loss, grad = S.mse_loss(out, rho, target, scale)
+    assert np.all(grad[..., 5:] == 0)
+    for _ in range(5):
+        idx = (int(rng.integers(2)), int(rng.integers(4)), int(rng.integers(6)), int(rng.integers(5)))
+        h = 1e-6
+        op, om = out.copy(), out.copy()
+        op[idx] += h
+        om[idx] -= h
+        fd = (S.mse_loss(op, rho, target, scale)[0] - S.mse_loss(om, rho, target, scale)[0]) / (2 * h)
+        assert abs(grad[idx] - fd) < 1e-7
+    # the output that makes the loss zero reproduces the target exactly
+    exact = np.zeros_like(out)
+    for c in range(5):
+        exact[..., c] = (target[:, c] - rho[:, c]) / scale[c]
+    assert S.mse_loss(exact, rho, target, scale)[0] < 1e-28
+    assert np.allclose(S.apply_output(rho, exact, scale), target, rtol=0, atol=1e-15)
+    x = S.pack_input(rho, rng.normal(size=(2, 9)), [1, 2, 3, 4, 5])
+    assert np.allclose(x[1, 2, 3, 4], rho[1, 4, 2, 3] / 5) and np.all(x[..., 14:] == 0)
+
+
+def test_bf16_round_definition():
+    """Ties go to the even neighbour, 8 significant bits, and the result is
+    the nearest BF16 value (checked by brute force against the two BF16
+    neighbours built from the bit pattern)."""
+    assert S.bf16_round(1.0) == 1.0
+    assert S.bf16_round(1.0 + 2.0 ** -8) == 1.0            # tie -> even (1.0)
+    assert S.bf16_round(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6  # tie -> even
+    assert S.bf16_round(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert S.bf16_round(-3.0) == -3.0
+    vals = np.random.default_rng(1).normal(size=2000) * 10.0 ** np.random.default_rng(2).integers(-5, 5, 2000)
+    got = S.bf16_round(vals)
+    f32 = vals.astype(np.float32)
+    lo = (f32.view(np.uint32) & 0xFFFF0000).view(np.float32).astype(np.float64)
+    hi = ((f32.view(np.uint32) & 0xFFFF0000) + 0x10000).view(np.float32).astype(np.float64)
+    best = np.where(np.abs(f32 - lo) <= np.abs(hi - f32), lo, hi)
+    tie = np.abs(f32 - lo) == np.abs(hi - f32)
+    assert np.array_equal(got[~tie], best[~tie])
+
+
+def test_unet_storage_hook_changes_only_rounding():
+    spec = S.unet_spec(levels=2, base=8, cin=8, cout=8)
+    rng = np.random.default_rng(4)
+    weights = [(rng.normal(size=(op[2], 9, op[1])) * 0.2, rng.normal(size=op[2]) * 0.1)
+               for op in spec if op[0] == "conv"]
+    x = rng.normal(size=(1, 8, 8, 8))
+    exact, tape = S.unet_forward(x, weights, spec, 0.1)
+    rounded, tape16 = S.unet_forward(x, weights, spec, 0.1, store=S.bf16_round)
+    assert np.linalg.norm(rounded - exact) / np.linalg.norm(exact) < 2e-2
+    g, _ = S.unet_backward(exact, weights, tape, 0.1)
+    g16, _ = S.unet_backward(exact, weights, tape16, 0.1, store=S.bf16_round)
+    for (a, _), (b, _) in zip(g, g16):
+        assert np.linalg.norm(a - b) / np.linalg.norm(a) < 0.2
