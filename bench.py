@@ -68,6 +68,9 @@ def parse_args():
                     help="time a single 1 GiB device copy (counter calibration runs)")
     ap.add_argument("--adjoint-steps", type=int, default=2000,
                     help="steps of the 1024x1024 FP64 adjoint gradient run (0 skips it)")
+    ap.add_argument("--surrogate-steps", type=int, default=1250,
+                    help="training steps (batch 16 at 256x256) of the surrogate before its "
+                         "1024x1024 rollout to 5000 steps (0 skips it)")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the uneven 512-instance ensemble (0 skips it)")
     return ap.parse_args()
@@ -235,6 +238,77 @@ def run_adjoint(torch, inputs, Solver, steps, every=100):
     return out
 
 
+def run_surrogate(torch, inputs, Solver, train_steps):
+    """The learned surrogate: a 4-level, base-32 U-Net (BF16 MFMA, FP32
+    accumulation) trained on `train_steps` batches of 16 SSLBM pairs at
+    256 x 256 (sampled R0 and diffusivities, 50-step jumps); inference at
+    batch 64 on 256 x 256; then time-to-T on a 1024 x 1024 grid to T = 5000:
+    plain FP32 SSLBM against 100 surrogate jumps judged on SSLBM sub-tiles
+    with fallback at 1e-3, both scored against the FP64 SSLBM trajectory."""
+    from paper_2603_19789_amd import surrogate as S
+    net = S.UNet(levels=4, base=32, seed=0)
+    sur, rep = S.train(net, steps=train_steps, batch=16, size=256, jump=50, lr=1e-3, seed=0)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    # inference throughput, batch 64 at 256 x 256 (network pass only)
+    net._buffers(64, 256, 256)
+    net.x0.normal_()
+    net.forward_packed()
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(10):
+        net.forward_packed()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    infer_ms = ev[0].elapsed_time(ev[1]) / 10
+    infer_tflops = net.flops(64, 256, 256) / (infer_ms * 1e-3) / 1e12
+    # time to T
+    w = inputs.c5_rollout_workload()
+    T = w.nsteps
+    rho0 = torch.tensor(w.rho0, dtype=torch.float32, device="cuda")
+    ref = torch.tensor(w.rho0, dtype=torch.float64, device="cuda")
+    Solver(w.nx, w.ny, w.params, dtype="f64").run(ref, T)
+    plain = Solver(w.nx, w.ny, w.params, dtype="f32")
+    st = rho0.clone()
+    scratch = torch.empty_like(st)
+    plain.run(st, T, scratch)  # warm-up
+    st = rho0.clone()
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    plain.run(st, T, scratch)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    plain_ms = ev[0].elapsed_time(ev[1])
+    plain_err = S.relative_l2(st, ref)
+    roll = S.Rollout(sur, w.params, w.ny, w.nx, tiles=4, tile=64, target=1e-3, seed=0)
+    roll.run(rho0, 100)  # warm-up (buffers, tables)
+    final, rr = roll.run(rho0, T)
+    roll_err = S.relative_l2(final, ref)
+    # the surrogate alone: every jump accepted (still judged, for the error record)
+    free = S.Rollout(sur, w.params, w.ny, w.nx, tiles=4, tile=64, threshold=1e30, seed=0)
+    free_state, fr = free.run(rho0, T)
+    free_err = S.relative_l2(free_state, ref)
+    bare = S.Rollout(sur, w.params, w.ny, w.nx, threshold=float("inf"), seed=0)
+    _, br = bare.run(rho0, T)
+    return {"workload": w.name, "T": T, "jump": sur.jump, "parameters": net.parameters,
+            "train": {"steps": rep.steps, "batch": rep.batch, "size": 256, "samples": rep.samples,
+                      "seconds": round(rep.seconds, 2), "first_loss": rep.first_loss,
+                      "last_loss": rep.last_loss, "tflops": round(rep.conv_tflops, 1)},
+            "inference_batch64_256_ms": round(infer_ms, 3),
+            "inference_tflops": round(infer_tflops, 1),
+            "plain_ms": round(plain_ms, 3), "plain_rel_l2_vs_fp64": plain_err,
+            "rollout_ms": round(rr.seconds * 1e3, 3), "rollout_rel_l2_vs_fp64": roll_err,
+            "accepted_jumps": rr.accepted, "fallback_jumps": rr.fallbacks,
+            "target": 1e-3, "per_jump_threshold": rr.threshold,
+            "speedup_at_1e-3": round(plain_ms / (rr.seconds * 1e3), 4),
+            "surrogate_only_ms": round(br.seconds * 1e3, 3),
+            "surrogate_only_rel_l2_vs_fp64": free_err,
+            "surrogate_only_speedup": round(plain_ms / (br.seconds * 1e3), 4),
+            "jump_error_estimate": {"min": fr.min_check_error, "median": fr.median_check_error,
+                                    "max": fr.max_check_error},
+            "dtype": "bf16 network, f32 state"}
+
+
 def copy_probe(torch, reps: int = 1):
     """Plain device-to-device copies of 1 GiB: the practical HBM ceiling of
     this GPU (read + write GB/s), and a transfer of known size for scaling HBM
@@ -331,6 +405,17 @@ def main():
               f"adjoint step {adjoint_res['adjoint_step_gbps']:.0f} GB/s",
               file=sys.stderr, flush=True)
 
+    surrogate_res = None
+    if args.surrogate_steps > 0:
+        surrogate_res = run_surrogate(torch, inputs, Solver, args.surrogate_steps)
+        print(f"# surrogate: trained {surrogate_res['train']['steps']} steps in "
+              f"{surrogate_res['train']['seconds']:.1f} s (loss {surrogate_res['train']['last_loss']:.2e}); "
+              f"time to T plain {surrogate_res['plain_ms']:.1f} ms, rollout "
+              f"{surrogate_res['rollout_ms']:.1f} ms ({surrogate_res['accepted_jumps']} of "
+              f"{surrogate_res['accepted_jumps'] + surrogate_res['fallback_jumps']} jumps accepted), "
+              f"error {surrogate_res['rollout_rel_l2_vs_fp64']:.2e}",
+              file=sys.stderr, flush=True)
+
     # last, so that the 1 GiB copy is the final copy dispatch of the run (the
     # transfer of known size that HBM counters are scaled by)
     copy_gbps = copy_probe(torch, 1 if args.copy_probe else 5)
@@ -377,6 +462,8 @@ def main():
         line["ensemble"] = ensemble
     if adjoint_res is not None:
         line["adjoint"] = adjoint_res
+    if surrogate_res is not None:
+        line["surrogate"] = surrogate_res
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs, args.cpu_seconds)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)

@@ -174,37 +174,91 @@ __global__ __launch_bounds__(THREADS) void flip_kernel(const uint16_t *__restric
 }
 
 // ------------------------------------------------------- backward weights
-// Channel-major copies: dz_t[o][q] = dZ[q][o]; xs[s][i][q] = X[shift(q, dx =
-// s - 1)][i]. q runs over P pixels padded with zeros to a multiple of 32.
-__global__ __launch_bounds__(THREADS) void transpose_dz_kernel(const uint16_t *__restrict__ dz,
-                                                               int pitch, long long P, long long Pp,
-                                                               int c, uint16_t *__restrict__ out) {
-    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
-    if (e >= Pp * c)
-        return;
-    const long long q = e % Pp;
-    const int ch = (int)(e / Pp);
-    out[e] = q < P ? dz[q * pitch + ch] : (uint16_t)0;
+// Channel-major copies through LDS tiles of 64 pixels x 64 channels:
+// out[ch][q] = X[src(q)][ch], src(q) the pixel dx columns east of q in its
+// row (wrapped), zero for the padding pixels q >= P. Loads read 8 channels
+// of a pixel (16 bytes), stores write 8 pixels of a channel.
+constexpr int TT = 64;
+
+__global__ __launch_bounds__(THREADS) void transpose_kernel(const uint16_t *__restrict__ x,
+                                                            int pitch, int c, long long P,
+                                                            long long Pp, int w, int dx,
+                                                            uint16_t *__restrict__ out) {
+    __shared__ uint16_t tile[TT][TT + 8];
+    const long long q0 = (long long)blockIdx.x * TT;
+    const int c0 = blockIdx.y * TT;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int idx = threadIdx.x + THREADS * k;
+        const int px = idx >> 3, chunk = idx & 7;
+        const long long q = q0 + px;
+        const int ch = c0 + 8 * chunk;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (q < P && ch < c) {
+            const long long row = q / w;
+            const int xx = wrap((int)(q - row * w) + dx, w);
+            v = *reinterpret_cast<const uint4 *>(x + (row * w + xx) * pitch + ch);
+        }
+        const uint32_t words[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            tile[8 * chunk + 2 * j][px] = (uint16_t)(words[j] & 0xffffu);
+            tile[8 * chunk + 2 * j + 1][px] = (uint16_t)(words[j] >> 16);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int idx = threadIdx.x + THREADS * k;
+        const int row = idx >> 3, seg = idx & 7;
+        const int ch = c0 + row;
+        const long long q = q0 + 8 * seg;
+        if (ch < c && q < Pp) {
+            uint16_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                v[j] = tile[row][8 * seg + j];
+            *reinterpret_cast<uint4 *>(out + (long long)ch * Pp + q) = pack8(v);
+        }
+    }
 }
 
-__global__ __launch_bounds__(THREADS) void transpose_shift_kernel(
-    const uint16_t *__restrict__ x, int pitch, int n, int h, int w, long long Pp, int c,
-    uint16_t *__restrict__ out) {
-    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
-    if (e >= 3 * Pp * c)
-        return;
-    const long long q = e % Pp;
-    const long long rest = e / Pp;
-    const int ch = (int)(rest % c);
-    const int s = (int)(rest / c);
-    const long long P = (long long)n * h * w;
-    uint16_t v = 0;
-    if (q < P) {
-        const long long row = q / w;  // n * h + y
-        const int xx = wrap((int)(q - row * w) + s - 1, w);
-        v = x[(row * w + xx) * pitch + ch];
+// Bias gradient, deterministic: block (o, k) sums slice k of row o of dz_t,
+// then one thread per channel adds the slices in order.
+constexpr int BIAS_SLICES = 32;
+
+__global__ __launch_bounds__(THREADS) void bias_partial_kernel(const uint16_t *__restrict__ dz_t,
+                                                               long long Pp,
+                                                               float *__restrict__ part) {
+    __shared__ float red[THREADS];
+    const int o = blockIdx.x, k = blockIdx.y;
+    const long long len = (Pp + BIAS_SLICES - 1) / BIAS_SLICES;
+    const long long a = k * len;
+    const long long b = a + len < Pp ? a + len : Pp;
+    const uint16_t *row = dz_t + (long long)o * Pp;
+    float s = 0.f;
+    for (long long q = a + threadIdx.x; q < b; q += THREADS)
+        s += from_bf16(row[q]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = THREADS / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
     }
-    out[e] = v;
+    if (threadIdx.x == 0)
+        part[(long long)o * BIAS_SLICES + k] = red[0];
+}
+
+__global__ __launch_bounds__(THREADS) void bias_sum_kernel(const float *__restrict__ part,
+                                                           int cout, float *__restrict__ db) {
+    const int o = blockIdx.x * THREADS + threadIdx.x;
+    if (o >= cout)
+        return;
+    float s = 0.f;
+    for (int k = 0; k < BIAS_SLICES; ++k)
+        s += part[(long long)o * BIAS_SLICES + k];
+    db[o] = s;
 }
 
 // One wavefront: 32 output channels x (16 NI) input channels of one tap,
@@ -302,24 +356,6 @@ __global__ __launch_bounds__(THREADS) void wgrad_reduce_kernel(const float *__re
     for (int k = 0; k < splits; ++k)
         s += part[k * count + e];
     dw[e] = s;
-}
-
-__global__ __launch_bounds__(THREADS) void bias_grad_kernel(const uint16_t *__restrict__ dz_t,
-                                                            long long Pp, float *__restrict__ db) {
-    __shared__ float red[THREADS];
-    const uint16_t *row = dz_t + (long long)blockIdx.x * Pp;
-    float s = 0.f;
-    for (long long q = threadIdx.x; q < Pp; q += THREADS)
-        s += from_bf16(row[q]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = THREADS / 2; h >= 1; h >>= 1) {
-        if ((int)threadIdx.x < h)
-            red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        db[blockIdx.x] = red[0];
 }
 
 // --------------------------------------------------------- elementwise ops
@@ -647,7 +683,10 @@ WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
     // workspace: dz_t (cout x Pp), xs (3 x cin x Pp) BF16, partials FP32
     p.dz_t_bytes = (size_t)cout * p.Pp * 2;
     p.xs_bytes = (size_t)3 * cin * p.Pp * 2;
-    p.part_bytes = (size_t)p.splits * cout * 9 * cin * 4;
+    // FP32 partials of dW per split; afterwards the bias partials reuse them
+    const size_t part_elems = (size_t)p.splits * cout * 9 * cin;
+    const size_t bias_elems = (size_t)cout * BIAS_SLICES;
+    p.part_bytes = (part_elems > bias_elems ? part_elems : bias_elems) * 4;
     return p;
 }
 
@@ -658,10 +697,16 @@ hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, i
     uint16_t *xs = reinterpret_cast<uint16_t *>(static_cast<char *>(ws) + align256(p.dz_t_bytes));
     float *part = reinterpret_cast<float *>(static_cast<char *>(ws) + align256(p.dz_t_bytes) +
                                             align256(p.xs_bytes));
-    hipLaunchKernelGGL(transpose_dz_kernel, dim3(blocks_for(p.Pp * cout)), dim3(THREADS), 0, s,
-                       static_cast<const uint16_t *>(dz), dzp, p.P, p.Pp, cout, dz_t);
-    hipLaunchKernelGGL(transpose_shift_kernel, dim3(blocks_for(3 * p.Pp * cin)), dim3(THREADS), 0,
-                       s, static_cast<const uint16_t *>(x), xp, n, h, w, p.Pp, cin, xs);
+    {
+        const dim3 tb(THREADS);
+        const unsigned qt = (unsigned)((p.Pp + TT - 1) / TT);
+        hipLaunchKernelGGL(transpose_kernel, dim3(qt, (unsigned)((cout + TT - 1) / TT)), tb, 0, s,
+                           static_cast<const uint16_t *>(dz), dzp, cout, p.P, p.Pp, w, 0, dz_t);
+        for (int sh = 0; sh < 3; ++sh)
+            hipLaunchKernelGGL(transpose_kernel, dim3(qt, (unsigned)((cin + TT - 1) / TT)), tb, 0,
+                               s, static_cast<const uint16_t *>(x), xp, cin, p.P, p.Pp, w, sh - 1,
+                               xs + (long long)sh * cin * p.Pp);
+    }
     WgradArgs a;
     a.dz_t = dz_t;
     a.xs = xs;
@@ -683,9 +728,13 @@ hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, i
     const long long count = (long long)cout * 9 * cin;
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for(count)), dim3(THREADS), 0, s, part,
                        p.splits, count, dw);
-    if (db)
-        hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)cout), dim3(THREADS), 0, s, dz_t, p.Pp,
-                           db);
+    if (db) {
+        // the bias partials reuse the start of the (already reduced) partials buffer
+        hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)cout, BIAS_SLICES), dim3(THREADS), 0,
+                           s, dz_t, p.Pp, part);
+        hipLaunchKernelGGL(bias_sum_kernel, dim3((unsigned)((cout + THREADS - 1) / THREADS)),
+                           dim3(THREADS), 0, s, part, cout, db);
+    }
     return hipGetLastError();
 }
 

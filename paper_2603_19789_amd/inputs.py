@@ -236,3 +236,14 @@ def c4_state(nx: int = 1024, ny: int = 1024, seed: int = 4) -> np.ndarray:
 def c4_workload(nx: int = 1024, ny: int = 1024, seed: int = 4, nsteps: int = 2000) -> Workload:
     return Workload(f"sslbm-adjoint-{nx}x{ny}-fp64", nx, ny, c4_params(), c4_state(nx, ny, seed),
                     nsteps)
+
+
+# ------------------------------------------------------------- surrogate --
+
+def c5_rollout_workload(n: int = 1024, seed: int = 5, nsteps: int = 5000) -> Workload:
+    """Surrogate rollout: n x n periodic grid, R0 = 3 through beta, lattice
+    diffusivities of S, E, I, R log-uniform in [1e-4, 1e-2] (seeded), D at
+    rest, 16 seeded Gaussian foci of amplitude 0.01 and width 8, 5000 steps
+    (100 surrogate jumps of 50 steps)."""
+    return Workload(f"sslbm-surrogate-rollout-{n}x{n}", n, n, c2_params(3.0, seed),
+                    gaussian_foci_state(n, n, seeded_centres(n, n, 16, seed), 0.01, 8.0), nsteps)

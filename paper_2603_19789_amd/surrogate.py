@@ -475,16 +475,26 @@ class RolloutReport:
     seconds: float
     max_check_error: float
     min_check_error: float
+    median_check_error: float
+    threshold: float
 
 
-def _rel_l2_max(a, b):
-    """Largest per-compartment relative L2 difference of [.., 5, h, w] states."""
+def _rms(t):
+    """Root mean square of each compartment of [.., 5, h, w] (FP64, 5 values)."""
+    torch = _torch()
+    dims = [d for d in range(t.dim()) if d != t.dim() - 3]
+    return torch.sqrt(torch.mean(t.double() ** 2, dim=dims))
+
+
+def relative_l2(a, b):
+    """Largest per-compartment relative L2 difference ||a_c - b_c|| / ||b_c||
+    of [.., 5, h, w] states (absolute where b_c is zero)."""
     torch = _torch()
     worst = 0.0
     for c in range(5):
-        num = torch.linalg.vector_norm((a[..., c, :, :] - b[..., c, :, :]).double())
-        den = torch.linalg.vector_norm(b[..., c, :, :].double())
-        worst = max(worst, float(num / den) if float(den) > 0 else float(num))
+        num = float(torch.linalg.vector_norm((a[..., c, :, :] - b[..., c, :, :]).double()))
+        den = float(torch.linalg.vector_norm(b[..., c, :, :].double()))
+        worst = max(worst, num / den if den > 0 else num)
     return worst
 
 
@@ -493,15 +503,24 @@ class Rollout:
     plain SSLBM recomputed on seeded sub-tiles: a tile of side `tile` is
     cropped with a halo of `jump` cells (the dependence cone of `jump`
     steps), advanced `jump` steps, and its centre compared with the
-    surrogate's prediction. A jump whose largest per-compartment relative L2
-    error exceeds `threshold` is redone by plain SSLBM from the same state."""
+    surrogate's prediction. The error estimate of a compartment is the RMS
+    difference over the tiles divided by the compartment's RMS over the
+    whole grid (the larger of the state's and the recomputed tiles'), an
+    estimate of the grid-wide relative L2 error of the jump that stays
+    defined where a tile holds none of a compartment. A jump whose largest
+    estimate exceeds the jump's share of the error budget is redone by plain
+    SSLBM from the same state. The budget is `target`, the relative L2 error
+    allowed at T; accepted errors can add up, so each of the T / jump jumps
+    may spend target / (T / jump). A fixed `threshold` replaces that share
+    (an infinite one runs the surrogate alone, unjudged)."""
 
     def __init__(self, sur: Surrogate, params, h: int, w: int, *, tiles=4, tile=64,
-                 threshold=1e-3, seed=0):
+                 target=1e-3, threshold=None, seed=0):
         from .binding import Ensemble, Solver
         torch = _torch()
         self.sur, self.params, self.h, self.w = sur, params, h, w
-        self.tiles, self.tile, self.threshold = tiles, tile, threshold
+        self.tiles, self.tile = tiles, tile
+        self.target, self.threshold = target, threshold
         self.rng = np.random.default_rng(seed)
         self.solver = Solver(w, h, params, dtype="f32")
         self.scratch = torch.empty((5, h, w), dtype=torch.float32, device="cuda")
@@ -525,8 +544,12 @@ class Rollout:
             _check(self.lib.sur_crop_periodic(_ptr(pred), self.h, self.w, y0, x0, tile, tile,
                                               _ptr(pc), None), "sur_crop_periodic")
         self.ens.run(self.crops, jump, self.crop_scratch)
-        ref = _torch().stack([v[:, jump:jump + tile, jump:jump + tile] for v in views])
-        return _rel_l2_max(self.pred_crops, ref)
+        torch = _torch()
+        ref = torch.stack([v[:, jump:jump + tile, jump:jump + tile] for v in views])
+        scale = torch.maximum(_rms(state), _rms(ref))
+        err = _rms(self.pred_crops - ref) / scale
+        err = torch.where(scale > 0, err, _rms(self.pred_crops - ref))
+        return float(torch.max(err))
 
     def run(self, rho0, T: int):
         """Returns (state at T, RolloutReport); T a multiple of the jump."""
@@ -540,11 +563,13 @@ class Rollout:
         errs = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        share = self.threshold if self.threshold is not None else self.target / (T // jump)
+        judged = math.isfinite(share)
         for _ in range(T // jump):
             self.sur.predict(state[None], self.planes, out=pred[None])
-            err = self._judge(state, pred)
+            err = self._judge(state, pred) if judged else 0.0
             errs.append(err)
-            if err <= self.threshold:
+            if err <= share:
                 state, pred = pred, state
                 accepted += 1
             else:
@@ -552,4 +577,5 @@ class Rollout:
                 fallbacks += 1
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
-        return state, RolloutReport(T // jump, accepted, fallbacks, secs, max(errs), min(errs))
+        return state, RolloutReport(T // jump, accepted, fallbacks, secs, max(errs), min(errs),
+                                    float(np.median(errs)), share)

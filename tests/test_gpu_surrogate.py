@@ -280,7 +280,7 @@ def test_rollout_with_broken_network_falls_back_to_sslbm():
     sur = S.Surrogate(net, 20, [1.0] * 5, [1e-3] * 5)
     prm = inputs.c1_params()
     rho0 = torch.tensor(inputs.c1_workload(64, 64).rho0, dtype=torch.float32).cuda()
-    roll = S.Rollout(sur, prm, 64, 64, tiles=2, tile=16, threshold=1e-3, seed=2)
+    roll = S.Rollout(sur, prm, 64, 64, tiles=2, tile=16, target=1e-3, seed=2)
     state, rep = roll.run(rho0, 100)
     assert rep.fallbacks == rep.jumps == 5 and rep.accepted == 0
     ref = rho0.clone()
