@@ -68,9 +68,12 @@ class Oracle:
         lib.oracle_bgk_step.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, _DP, _DP, i]
         lib.oracle_bgk_run.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, _DP, _DP, ll, i]
         lib.oracle_sslbm_adjoint_step.argtypes = [i, i, i, _DP, _DP, d, d, _DP, _DP, _DP, _DP]
+        _IP = ctypes.POINTER(ctypes.c_int)
+        lib.oracle_generic_step.argtypes = [i, i, i, i, i, _DP, d, d, i, _IP, _IP, _IP, _IP, _DP,
+                                            _IP, _DP, _DP]
         for f in ("oracle_sslbm_step", "oracle_sslbm_run", "oracle_bgk_init",
                   "oracle_bgk_density", "oracle_bgk_step", "oracle_bgk_run",
-                  "oracle_sslbm_adjoint_step"):
+                  "oracle_sslbm_adjoint_step", "oracle_generic_step"):
             getattr(lib, f).restype = ctypes.c_int
         self.lib = lib
 
@@ -134,6 +137,28 @@ class Oracle:
             lam, g = self.sslbm_adjoint_step(states[n], lam, p, bc=bc)
             grad += g
         return lam, grad
+
+    # ------------------------------------------------------ generic models --
+    def generic_step(self, rho, model, bc="periodic"):
+        """One step of a generic compartmental model (see GenericModel)."""
+        rho = _f64(rho)
+        m, ny, nx = rho.shape
+        out = np.empty_like(rho)
+        ip = lambda v: (ctypes.c_int * max(len(v), 1))(*[int(x) for x in v])
+        dp = lambda v: (ctypes.c_double * max(len(v), 1))(*[float(x) for x in v])
+        t = model.transitions
+        rc = self.lib.oracle_generic_step(
+            nx, ny, _BC[bc], model.lattice, m, dp(model.d), model.dx, model.dt, len(t),
+            ip([x[0] for x in t]), ip([x[1] for x in t]), ip([x[2] for x in t]),
+            ip([x[4] for x in t]), dp([x[3] for x in t]), ip(model.counted), _ptr(rho), _ptr(out))
+        self._check(rc, "generic_step")
+        return out
+
+    def generic_run(self, rho, model, nsteps: int, bc="periodic"):
+        rho = _f64(rho).copy()
+        for _ in range(nsteps):
+            rho = self.generic_step(rho, model, bc=bc)
+        return rho
 
     # --------------------------------------------------------------- BGK --
     def bgk_init(self, rho):

@@ -418,3 +418,112 @@ int oracle_sslbm_adjoint_step(int nx, int ny, int bc, const double *rates, const
     }
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------ generic models --- */
+/*
+ * Generic compartmental model, Eq. (generic_pde): d_t C = Psi^C + d^C lap C
+ * for M compartments, advanced by Eq. (sslbm_final_clean) on the D2Q5 or the
+ * D2Q9 lattice (Sec. II.C.2, anisotropy paragraph: D2Q9 with rest weight
+ * 4/9, axis weights 1/9 and diagonal weights 1/36). The source is a list of
+ * transitions; transition r moves the flow
+ *     f_r = rate_r * C[src_r] * (cat_r >= 0 ? C[cat_r] : 1) / (freq_r ? N : 1)
+ * out of compartment src_r and into dst_r (dst_r < 0: out of the system),
+ * with N the sum of the compartments flagged in `counted` (f_r = 0 where a
+ * frequency-dependent transition sees N <= 0). The SEIRD sources of
+ * Eq. (sources) and Eq. (rhoD) are the transitions S->E (rate beta, catalyst
+ * I, frequency-dependent, N = S+E+I+R), E->I (alpha), I->R ((1-phi) gamma)
+ * and I->D (phi gamma).
+ * A compartment with d = 0 uses the same update (tau = 1/2), which leaves
+ * only the source term: forward Euler, as Eq. (rhoD) for the deceased.
+ * No-flux walls: the centre value on D2Q5 (as oracle_sslbm_step), the mirror
+ * image on D2Q9 (node_value_mirror).
+ */
+static const int CX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double W9[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+#define GENERIC_MAX_COMPARTMENTS 8
+
+/* No-flux wall on D2Q9: the field is extended by its mirror image about the
+ * wall (homogeneous Neumann), coordinate by coordinate, so a diagonal ghost
+ * across a wall takes the value of the node it mirrors. On D2Q5 this is the
+ * same as taking the centre value (node_value). */
+static double node_value_mirror(const double *field, int nx, int ny, int bc, int x, int y)
+{
+    if (bc == BC_PERIODIC) {
+        x = (x + nx) % nx; /* |offset| <= 1 */
+        y = (y + ny) % ny;
+    } else {
+        if (x < 0)
+            x = -1 - x;
+        if (x >= nx)
+            x = 2 * nx - 1 - x;
+        if (y < 0)
+            y = -1 - y;
+        if (y >= ny)
+            y = 2 * ny - 1 - y;
+    }
+    return field[(size_t)y * nx + x];
+}
+
+int oracle_generic_step(int nx, int ny, int bc, int lattice, int m, const double *d, double dx,
+                        double dt, int ntrans, const int *src, const int *dst, const int *cat,
+                        const int *freq, const double *rate, const int *counted,
+                        const double *in, double *out)
+{
+    if (!valid_grid(nx, ny, bc) || (lattice != 5 && lattice != 9) || m < 1 ||
+        m > GENERIC_MAX_COMPARTMENTS || !d || ntrans < 0 || (ntrans && (!src || !dst || !cat ||
+        !freq || !rate)) || !counted || !in || !out || in == out)
+        return ORACLE_E_ARG;
+    for (int r = 0; r < ntrans; ++r)
+        if (src[r] < 0 || src[r] >= m || dst[r] >= m || cat[r] >= m)
+            return ORACLE_E_ARG;
+    const int *cx = lattice == 5 ? CX : CX9;
+    const int *cy = lattice == 5 ? CY : CY9;
+    const double *w = lattice == 5 ? W : W9;
+    double tau[GENERIC_MAX_COMPARTMENTS];
+    for (int c = 0; c < m; ++c)
+        tau[c] = relaxation_time(d[c], dx, dt);
+    size_t plane = (size_t)nx * ny;
+
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            size_t cell = (size_t)y * nx + x;
+            double centre[GENERIC_MAX_COMPARTMENTS], psi[GENERIC_MAX_COMPARTMENTS];
+            double total = 0.0;
+            for (int c = 0; c < m; ++c) {
+                centre[c] = in[c * plane + cell];
+                psi[c] = 0.0;
+                if (counted[c])
+                    total += centre[c];
+            }
+            for (int r = 0; r < ntrans; ++r) {
+                double flow = rate[r] * centre[src[r]];
+                if (cat[r] >= 0)
+                    flow *= centre[cat[r]];
+                if (freq[r])
+                    flow = total > 0.0 ? flow / total : 0.0;
+                psi[src[r]] -= flow;
+                if (dst[r] >= 0)
+                    psi[dst[r]] += flow;
+            }
+            for (int c = 0; c < m; ++c) {
+                const double *field = in + c * plane;
+                double rho_f = 0.0, rho_b = 0.0;
+                for (int i = 0; i < lattice; ++i) {
+                    if (lattice == 5) {
+                        rho_f += w[i] * node_value(field, nx, ny, bc, x + cx[i], y + cy[i], x, y);
+                        rho_b += w[i] * node_value(field, nx, ny, bc, x - cx[i], y - cy[i], x, y);
+                    } else {
+                        rho_f += w[i] * node_value_mirror(field, nx, ny, bc, x + cx[i], y + cy[i]);
+                        rho_b += w[i] * node_value_mirror(field, nx, ny, bc, x - cx[i], y - cy[i]);
+                    }
+                }
+                double bracket = rho_f - 2.0 * centre[c] + rho_b;
+                out[c * plane + cell] = (tau[c] - 1.0) * bracket + rho_b + dt * psi[c];
+            }
+        }
+    }
+    return ORACLE_OK;
+}

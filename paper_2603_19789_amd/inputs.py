@@ -247,3 +247,44 @@ def c5_rollout_workload(n: int = 1024, seed: int = 5, nsteps: int = 5000) -> Wor
     (100 surrogate jumps of 50 steps)."""
     return Workload(f"sslbm-surrogate-rollout-{n}x{n}", n, n, c2_params(3.0, seed),
                     gaussian_foci_state(n, n, seeded_centres(n, n, 16, seed), 0.01, 8.0), nsteps)
+
+
+# --------------------------------------------------------- generic models --
+
+@dataclass(frozen=True)
+class GenericModel:
+    """A compartmental model d_t C = Psi^C + d^C lap C (Eq. (generic_pde)).
+    transitions: (src, dst, catalyst, rate, frequency) tuples; transition r
+    moves rate * C[src] * C[catalyst] (1 when catalyst < 0), divided by the
+    sum of the `counted` compartments when frequency is 1, from src to dst
+    (dst < 0: out of the system). d: physical diffusivities; lattice 5 or 9."""
+    names: tuple
+    d: tuple
+    transitions: tuple
+    counted: tuple
+    lattice: int = 5
+    dx: float = 1.0
+    dt: float = 0.01
+
+
+def seirvd_model(lattice: int = 9, dt: float = 0.01) -> GenericModel:
+    """A richer model than SEIRD: vaccinated V (rate nu from S, leaky
+    protection: V infected at 30 % of the susceptible rate) and waning
+    immunity (R -> S at rate omega). Compartments S, E, I, R, D, V; D at
+    rest; lattice diffusivities 2e-3 (S, E, R, V) and 5e-4 (I)."""
+    beta, sigma, gamma, mu, nu, omega, leak = 0.5, 0.2, 0.1, 0.01, 0.02, 0.005, 0.3
+    d_lu = (2e-3, 2e-3, 5e-4, 2e-3, 0.0, 2e-3)
+    S, E, I, R, D, V = range(6)
+    transitions = ((S, E, I, beta, 1), (V, E, I, leak * beta, 1), (E, I, -1, sigma, 0),
+                   (I, R, -1, gamma, 0), (I, D, -1, mu, 0), (S, V, -1, nu, 0),
+                   (R, S, -1, omega, 0))
+    return GenericModel(("S", "E", "I", "R", "D", "V"), lattice_to_physical(d_lu, 1.0, dt),
+                        transitions, (1, 1, 1, 1, 0, 1), lattice, 1.0, dt)
+
+
+def seirvd_state(nx: int, ny: int, seed: int = 6, foci: int = 8) -> np.ndarray:
+    """S = 1 - I, 8 seeded infected foci (amplitude 0.02, width 4), others 0."""
+    base = gaussian_foci_state(nx, ny, seeded_centres(nx, ny, foci, seed), 0.02, 4.0)
+    rho = np.zeros((6, ny, nx))
+    rho[:5] = base
+    return rho

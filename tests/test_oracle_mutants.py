@@ -6,6 +6,7 @@ strong enough to trust the oracle.
 import pytest
 
 import adjoint_pins
+import generic_pins
 import oracle
 import pins
 
@@ -62,12 +63,25 @@ MUTANTS = {
     "adjoint phi gradient sign": ("grad[3] += (lD - lR) * k.gamma * I * dt;",
                                   "grad[3] += (lR - lD) * k.gamma * I * dt;"),
     "adjoint d gradient without c_s^2": ("* 3.0 * dt / (dx * dx);", "* dt / (dx * dx);"),
+    "D2Q9 diagonal weight": ("1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};",
+                             "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 18.0};"),
+    "D2Q9 diagonal vector": ("CX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};",
+                             "CX9[9] = {0, 1, 0, -1, 0, 1, 1, -1, 1};"),
+    "generic catalyst ignored": ("                    flow *= centre[cat[r]];",
+                                 "                    flow *= 1.0;"),
+    "generic frequency ignored": ("                if (freq[r])\n", "                if (0)\n"),
+    "generic half outflow": ("psi[src[r]] -= flow;", "psi[src[r]] -= 0.5 * flow;"),
+    "generic counts every compartment": ("                if (counted[c])\n",
+                                         "                if (1)\n"),
+    "D2Q9 mirror off by one": ("x = 2 * nx - 1 - x;", "x = 2 * nx - 2 - x;"),
+    "D2Q9 mirror of y": ("y = -1 - y;", "y = -y;"),
 }
 
 
 def _caught(orc) -> list:
     failures = []
-    for check in pins.FAST_SSLBM_CHECKS + pins.FAST_BGK_CHECKS + adjoint_pins.FAST_ADJOINT_CHECKS:
+    for check in (pins.FAST_SSLBM_CHECKS + pins.FAST_BGK_CHECKS + adjoint_pins.FAST_ADJOINT_CHECKS
+                  + generic_pins.FAST_GENERIC_CHECKS):
         try:
             check(orc)
         except (AssertionError, ValueError, FloatingPointError) as exc:
