@@ -271,6 +271,48 @@ int sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long ns
 int sslbm_ensemble_last_hip_error(const sslbm_ensemble *e);
 void sslbm_ensemble_destroy(sslbm_ensemble *e);
 
+/*
+ * Generic compartmental models, Eq. (generic_pde): d_t C = Psi^C + d^C lap C
+ * for 1..SSLBM_MAX_COMPARTMENTS compartments, one SSLBM step per launch
+ * (Eq. (sslbm_final_clean)) on the D2Q5 lattice (lattice = 5) or the D2Q9
+ * lattice (lattice = 9: rest weight 4/9, axes 1/9, diagonals 1/36; its
+ * symbol is 4/9 + (2/9)(cos kx + cos ky) + (1/9) cos kx cos ky, isotropic
+ * to fourth order as the anisotropy analysis of Sec. II.C.2 states).
+ * Layout: rho[compartments][ny][nx]. No-flux walls are mirror images (the
+ * centre value on D2Q5, as sslbm_step); periodic walls wrap.
+ *
+ * Sources: transition r moves
+ *     rate * C[src] * (catalyst >= 0 ? C[catalyst] : 1) / (frequency ? N : 1)
+ * per unit time out of src into dst (dst = -1: out of the system), N being
+ * the sum of the compartments with counted[c] != 0 (the flow is 0 where a
+ * frequency-dependent transition sees N <= 0). The SEIRD model of Eq. (sources)
+ * and Eq. (rhoD) is S->E (beta, catalyst I, frequency), E->I (alpha),
+ * I->R ((1 - phi) gamma), I->D (phi gamma) with N = S + E + I + R.
+ *
+ *   sslbm_model_create: d (physical diffusivities, >= 0) and counted are host
+ *       arrays of `compartments` entries; transitions: host array. Rejects
+ *       (SSLBM_E_ARG) bad sizes, indices (src == dst, out of range), negative
+ *       or non-finite rates; (SSLBM_E_UNSTABLE) any compartment with
+ *       s * d_lu + dt * outflow > 2, s = 8 (D2Q5) or 16/3 (D2Q9), outflow the
+ *       sum of its transitions' rates (density-dependent catalysis, whose
+ *       flow has no bound, is left out). Host memory only.
+ *   sslbm_model_step / sslbm_model_run: as sslbm_step / sslbm_run.
+ */
+#define SSLBM_MAX_COMPARTMENTS 8
+#define SSLBM_MAX_TRANSITIONS 16
+typedef struct {
+    int src, dst, catalyst, frequency;
+    double rate;
+} sslbm_transition;
+typedef struct sslbm_model sslbm_model;
+int sslbm_model_create(sslbm_model **out, int nx, int ny, int dtype, int bc, int lattice,
+                       int compartments, const double *d, const int *counted, double dx,
+                       double dt, int ntransitions, const sslbm_transition *transitions);
+int sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hip_stream);
+int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps, void *hip_stream);
+int sslbm_model_last_hip_error(const sslbm_model *m);
+void sslbm_model_destroy(sslbm_model *m);
+
 /* Static description of a status code. */
 const char *sslbm_strerror(int status);
 

@@ -48,6 +48,11 @@ class Params(ctypes.Structure):
                    (ctypes.c_double * 5)(*[float(v) for v in p.d]), float(p.dx), float(p.dt))
 
 
+class Transition(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int), ("dst", ctypes.c_int), ("catalyst", ctypes.c_int),
+                ("frequency", ctypes.c_int), ("rate", ctypes.c_double)]
+
+
 class Launch(ctypes.Structure):
     """Pass shape (zero = automatic): steps per HBM pass, output rows per
     wavefront, adjacent columns per lane."""
@@ -99,6 +104,13 @@ def library() -> ctypes.CDLL:
             "sslbm_adjoint_step": [vp, vp, vp, vp, vp, vp],
             "sslbm_run_checkpointed": [vp, vp, vp, ll, i, vp, vp],
             "sslbm_adjoint_run": [vp, vp, ll, i, vp, vp, vp, vp],
+            "sslbm_model_create": [ctypes.POINTER(vp), i, i, i, i, i, i,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i),
+                                   ctypes.c_double, ctypes.c_double, i,
+                                   ctypes.POINTER(Transition)],
+            "sslbm_model_step": [vp, vp, vp, vp],
+            "sslbm_model_run": [vp, vp, vp, ll, vp],
+            "sslbm_model_last_hip_error": [vp],
             # surrogate.h
             "sur_conv3x3_forward": [vp, i, i, i, i, i, vp, vp, vp, i, i, i, f, vp],
             "sur_conv3x3_backward_data": [vp, i, i, i, i, i, vp, i, vp, i, vp, vp],
@@ -124,6 +136,8 @@ def library() -> ctypes.CDLL:
         lib.sslbm_destroy.restype = None
         lib.sslbm_ensemble_destroy.argtypes = [vp]
         lib.sslbm_ensemble_destroy.restype = None
+        lib.sslbm_model_destroy.argtypes = [vp]
+        lib.sslbm_model_destroy.restype = None
         for name in ("sslbm_ensemble_offset", "sslbm_ensemble_elements"):
             getattr(lib, name).restype = ll
         lib.sslbm_ensemble_offset.argtypes = [vp, i]
@@ -506,3 +520,74 @@ class Ensemble:
                                                 self._flat(scratch, "scratch"), int(nsteps),
                                                 flags, _stream(stream)), "sslbm_ensemble_run")
         return state
+
+
+class Model:
+    """A generic compartmental model (inputs.GenericModel) on an nx-by-ny
+    grid: D2Q5 or D2Q9, up to 8 compartments, transition-list sources."""
+
+    def __init__(self, nx, ny, model, dtype="f64", bc="periodic"):
+        torch = _torch()
+        self.lib = library()
+        if dtype in (torch.float32, "f32", "float32", F32):
+            self.dtype, self.code = torch.float32, F32
+        elif dtype in (torch.float64, "f64", "float64", F64):
+            self.dtype, self.code = torch.float64, F64
+        else:
+            raise ValueError(f"unsupported dtype {dtype!r}")
+        if bc not in _BC:
+            raise ValueError(f"unknown boundary condition {bc!r}")
+        self.nx, self.ny, self.model = int(nx), int(ny), model
+        m = len(model.d)
+        d = (ctypes.c_double * m)(*model.d)
+        counted = (ctypes.c_int * m)(*[int(v) for v in model.counted])
+        tr = (Transition * max(len(model.transitions), 1))(
+            *[Transition(int(t[0]), int(t[1]), int(t[2]), int(t[4]), float(t[3]))
+              for t in model.transitions])
+        h = ctypes.c_void_p()
+        st = self.lib.sslbm_model_create(ctypes.byref(h), self.nx, self.ny, self.code, _BC[bc],
+                                         int(model.lattice), m, d, counted, float(model.dx),
+                                         float(model.dt), len(model.transitions), tr)
+        if st != OK:
+            raise SSLBMError(st, "sslbm_model_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.sslbm_model_destroy(h)
+            self.handle = None
+
+    @property
+    def shape(self):
+        return (len(self.model.d), self.ny, self.nx)
+
+    def _check(self, st, what):
+        if st != OK:
+            raise SSLBMError(st, what, self.lib.sslbm_model_last_hip_error(self.handle))
+
+    def _t(self, t, name):
+        torch = _torch()
+        if (not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != self.dtype
+                or tuple(t.shape) != self.shape or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {self.dtype} GPU tensor of shape "
+                             f"{self.shape}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def step(self, rho_in, rho_out=None, stream=None):
+        torch = _torch()
+        if rho_out is None:
+            rho_out = torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        self._check(self.lib.sslbm_model_step(self.handle, self._t(rho_in, "rho_in"),
+                                              self._t(rho_out, "rho_out"), _stream(stream)),
+                    "sslbm_model_step")
+        return rho_out
+
+    def run(self, rho, nsteps: int, scratch=None, stream=None):
+        torch = _torch()
+        if scratch is None:
+            scratch = torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        self._check(self.lib.sslbm_model_run(self.handle, self._t(rho, "rho"),
+                                             self._t(scratch, "scratch"), int(nsteps),
+                                             _stream(stream)), "sslbm_model_run")
+        return rho

@@ -18,8 +18,8 @@ LIBRARY = PKG / "libsslbm.so"
 ARCH = "gfx950"
 
 SOURCES = ["sslbm_api.cpp", "ensemble_api.cpp", "adjoint_api.cpp", "surrogate_api.cpp",
-           "sslbm_kernels.hip", "ensemble_kernels.hip", "adjoint_kernels.hip",
-           "surrogate_kernels.hip", "bgk_kernels.hip", "reduce_kernels.hip"]
+           "model_api.cpp", "sslbm_kernels.hip", "ensemble_kernels.hip", "adjoint_kernels.hip",
+           "surrogate_kernels.hip", "model_kernels.hip", "bgk_kernels.hip", "reduce_kernels.hip"]
 
 # -ffp-contract=off: only the fma() calls written in the kernels fuse, so every
 # launch shape and blocking depth rounds identically.

@@ -1,0 +1,150 @@
+// model_api.cpp -- host side of the generic-model entry points of sslbm.h:
+// validation of the model (lattice, compartments, transitions, stability)
+// before any HIP call, derived constants, and the step and run loops.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdint>
+#include <new>
+
+#include "model_internal.h"
+#include "sslbm.h"
+
+struct sslbm_model {
+    int nx = 0, ny = 0, dtype = 0, bc = 0, lattice = 5;
+    sslbm::ModelCoefHost coef{};
+    int last_hip = 0;
+};
+
+namespace {
+
+constexpr int MAX_SIDE = 1 << 20;
+
+int hip_status(sslbm_model *m, hipError_t e) {
+    if (e == hipSuccess)
+        return SSLBM_OK;
+    m->last_hip = (int)e;
+    return SSLBM_E_HIP;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+size_t state_bytes(const sslbm_model *m) {
+    return (size_t)m->coef.m * m->nx * m->ny * (m->dtype == SSLBM_F32 ? 4 : 8);
+}
+
+sslbm::GridDesc grid_of(const sslbm_model *m) {
+    sslbm::GridDesc g;
+    g.nx = m->nx;
+    g.ny = m->ny;
+    g.plane = (long long)m->nx * m->ny;
+    g.bc = m->bc;
+    return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sslbm_model_create(sslbm_model **out, int nx, int ny, int dtype, int bc, int lattice,
+                       int compartments, const double *d, const int *counted, double dx,
+                       double dt, int ntransitions, const sslbm_transition *t) {
+    if (!out)
+        return SSLBM_E_ARG;
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nx > MAX_SIDE || ny > MAX_SIDE || (long long)nx * ny > (1ll << 33) ||
+        (dtype != SSLBM_F32 && dtype != SSLBM_F64) || (bc != SSLBM_PERIODIC && bc != SSLBM_NOFLUX) ||
+        (lattice != 5 && lattice != 9) || compartments < 1 ||
+        compartments > SSLBM_MAX_COMPARTMENTS || !d || !counted || ntransitions < 0 ||
+        ntransitions > SSLBM_MAX_TRANSITIONS || (ntransitions && !t) || !std::isfinite(dx) ||
+        !std::isfinite(dt) || dx <= 0.0 || dt <= 0.0)
+        return SSLBM_E_ARG;
+    sslbm::ModelCoefHost k{};
+    k.m = compartments;
+    k.ntrans = ntransitions;
+    double outflow[SSLBM_MAX_COMPARTMENTS] = {};
+    for (int c = 0; c < compartments; ++c) {
+        if (!std::isfinite(d[c]) || d[c] < 0.0)
+            return SSLBM_E_ARG;
+        k.dl[c] = d[c] * dt / (dx * dx);
+        if (counted[c])
+            k.counted |= 1u << c;
+    }
+    for (int r = 0; r < ntransitions; ++r) {
+        const sslbm_transition &x = t[r];
+        if (x.src < 0 || x.src >= compartments || x.dst < -1 || x.dst >= compartments ||
+            x.dst == x.src || x.catalyst < -1 || x.catalyst >= compartments ||
+            (x.frequency != 0 && x.frequency != 1) || !std::isfinite(x.rate) || x.rate < 0.0)
+            return SSLBM_E_ARG;
+        k.src[r] = x.src;
+        k.dst[r] = x.dst;
+        k.cat[r] = x.catalyst;
+        k.freq[r] = x.frequency;
+        k.rate_dt[r] = x.rate * dt;
+        // per-node outflow rate of src: bounded by rate when the catalyst is
+        // absent, or is a counted compartment of a frequency-dependent term
+        // (C_cat / N <= 1); density-dependent catalysis is left unbounded
+        if (x.catalyst < 0 || (x.frequency && counted[x.catalyst]))
+            outflow[x.src] += x.rate;
+    }
+    // linear stability of the explicit update, as for the SEIRD step:
+    // (2 tau - 1) max(1 - Lambda) + dt * outflow <= 2, with
+    // max(1 - Lambda) = 4/3 on D2Q5 and 8/9 on D2Q9, 2 tau - 1 = 6 dl
+    const double spread = lattice == 5 ? 8.0 : 16.0 / 3.0;
+    for (int c = 0; c < compartments; ++c)
+        if (spread * k.dl[c] + dt * outflow[c] > 2.0 * (1.0 + 1e-12))
+            return SSLBM_E_UNSTABLE;
+    sslbm_model *m = new (std::nothrow) sslbm_model();
+    if (!m)
+        return SSLBM_E_NOMEM;
+    m->nx = nx;
+    m->ny = ny;
+    m->dtype = dtype;
+    m->bc = bc;
+    m->lattice = lattice;
+    m->coef = k;
+    *out = m;
+    return SSLBM_OK;
+}
+
+int sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hip_stream) {
+    if (!m || !rho_in || !rho_out)
+        return SSLBM_E_ARG;
+    const size_t bytes = state_bytes(m);
+    if (overlap(rho_in, bytes, rho_out, bytes))
+        return SSLBM_E_ALIAS;
+    return hip_status(m, sslbm::launch_model(m->dtype, m->lattice, rho_in, rho_out, grid_of(m),
+                                             m->coef, (hipStream_t)hip_stream));
+}
+
+int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
+                    void *hip_stream) {
+    if (!m || !rho || !scratch || nsteps < 0)
+        return SSLBM_E_ARG;
+    const size_t bytes = state_bytes(m);
+    if (overlap(rho, bytes, scratch, bytes))
+        return SSLBM_E_ALIAS;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    void *src = rho, *dst = scratch;
+    for (long long n = 0; n < nsteps; ++n) {
+        const int st = hip_status(m, sslbm::launch_model(m->dtype, m->lattice, src, dst,
+                                                         grid_of(m), m->coef, s));
+        if (st != SSLBM_OK)
+            return st;
+        void *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    if (src != rho)
+        return hip_status(m, hipMemcpyAsync(rho, src, bytes, hipMemcpyDeviceToDevice, s));
+    return SSLBM_OK;
+}
+
+int sslbm_model_last_hip_error(const sslbm_model *m) { return m ? m->last_hip : 0; }
+
+void sslbm_model_destroy(sslbm_model *m) { delete m; }
+
+}  // extern "C"

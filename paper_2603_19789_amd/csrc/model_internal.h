@@ -1,0 +1,43 @@
+// model_internal.h -- declarations shared by the generic-model entry points
+// and kernels (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "sslbm_internal.h"
+
+namespace sslbm {
+
+constexpr int MODEL_MAX_C = SSLBM_MAX_COMPARTMENTS;
+constexpr int MODEL_MAX_T = SSLBM_MAX_TRANSITIONS;
+
+// Per-step constants in the arithmetic type: dl = d dt / dx^2 (divided by 6
+// on D2Q9), rate = rate dt; the transition table; counted = bit mask of the
+// compartments summed into N.
+template <typename T>
+struct ModelCoef {
+    T dl[MODEL_MAX_C];
+    T rate[MODEL_MAX_T];
+    int src[MODEL_MAX_T], dst[MODEL_MAX_T], cat[MODEL_MAX_T], freq[MODEL_MAX_T];
+    int m, ntrans;
+    unsigned counted;
+};
+
+// The same in FP64, derived once on the host.
+struct ModelCoefHost {
+    double dl[MODEL_MAX_C];
+    double rate_dt[MODEL_MAX_T];
+    int src[MODEL_MAX_T], dst[MODEL_MAX_T], cat[MODEL_MAX_T], freq[MODEL_MAX_T];
+    int m, ntrans;
+    unsigned counted;
+};
+
+struct ModelShape {
+    int strips, chunks, rows;
+};
+
+ModelShape model_shape(int nx, int ny);
+hipError_t launch_model(int dtype, int lattice, const void *in, void *out, const GridDesc &g,
+                        const ModelCoefHost &h, hipStream_t s);
+
+}  // namespace sslbm

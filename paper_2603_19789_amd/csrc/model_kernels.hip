@@ -1,0 +1,243 @@
+// model_kernels.hip -- one SSLBM step of a generic compartmental model
+// (Eq. (generic_pde)) on the D2Q5 or the D2Q9 lattice, for up to 8
+// compartments whose sources are a list of transitions.
+//
+// Update. Eq. (sslbm_final_clean) with rho_f = rho_b = sum_i w_i rho(x + c_i)
+// (both lattices are symmetric) reduces to rho + (2 tau - 1)(sum_i w_i
+// rho(x + c_i) - rho) + Psi dt:
+//   D2Q5: rho + dl L5,        L5 = (N + S + E + W) - 4 rho
+//   D2Q9: rho + (dl / 6) L9,  L9 = 4 (N + S + E + W) + (NE + NW + SE + SW) - 20 rho
+// with dl = d dt / dx^2 (weights 1/3, 1/6 on D2Q5; 4/9, 1/9, 1/36 on D2Q9).
+// No-flux walls are mirror images (map_index), periodic walls wrap.
+//
+// Sources. Transition r moves rate_r dt C[src] (C[cat] if cat >= 0)
+// (/ N if frequency-dependent, 0 where N <= 0) from src to dst (dst < 0:
+// out of the system); N sums the compartments flagged as counted. The table
+// is the same for every node (kernel arguments), so every compartment
+// lookup is a wavefront-uniform branch, not a per-lane select.
+//
+// Traversal: the y-march of the single-step kernels (one wavefront per strip
+// of 62 output columns plus one halo column per side, rows in a 4-slot
+// register ring with compile-time slots, east/west through DPP). Per output
+// row: one row of every compartment read, one written.
+#include <hip/hip_runtime.h>
+
+#include "march_core.h"
+#include "model_internal.h"
+
+namespace sslbm {
+
+namespace {
+
+constexpr int MHX = 1, MWU = 64 - 2 * MHX;
+
+template <typename T>
+struct ModelRows {
+    T ring[RING][MODEL_MAX_C];
+};
+
+template <typename T>
+__device__ __forceinline__ T pick(const T v[MODEL_MAX_C], int c) {
+    switch (c) {
+    case 0: return v[0];
+    case 1: return v[1];
+    case 2: return v[2];
+    case 3: return v[3];
+    case 4: return v[4];
+    case 5: return v[5];
+    case 6: return v[6];
+    default: return v[7];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void add_to(T v[MODEL_MAX_C], int c, T x) {
+    switch (c) {
+    case 0: v[0] += x; break;
+    case 1: v[1] += x; break;
+    case 2: v[2] += x; break;
+    case 3: v[3] += x; break;
+    case 4: v[4] += x; break;
+    case 5: v[5] += x; break;
+    case 6: v[6] += x; break;
+    case 7: v[7] += x; break;
+    default: break;
+    }
+}
+
+template <typename T>
+struct ModelArgs {
+    const T *__restrict__ in;
+    T *__restrict__ out;
+    GridDesc g;
+    unsigned xoff, xo;
+    bool out_col;
+    int j0;
+};
+
+template <typename T, int SL>
+__device__ __forceinline__ void fetch_rows(ModelRows<T> &st, const ModelArgs<T> &a,
+                                           const ModelCoef<T> &k, int t) {
+    const long long row = (long long)map_index(a.j0 + t, a.g.ny, a.g.bc) * a.g.nx;
+#pragma unroll
+    for (int c = 0; c < MODEL_MAX_C; ++c)
+        if (c < k.m)
+            st.ring[SL][c] =
+                buf_load(row_resource(a.in + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
+}
+
+template <typename T, int Q, int P>
+__device__ __forceinline__ void model_row(ModelRows<T> &st, const ModelArgs<T> &a,
+                                          const ModelCoef<T> &k, int t) {
+    constexpr int su = (P + 2) % RING, sm = (P + 3) % RING, sd = P % RING;
+    T cen[MODEL_MAX_C], out[MODEL_MAX_C];
+    T total = T(0);
+#pragma unroll
+    for (int c = 0; c < MODEL_MAX_C; ++c) {
+        cen[c] = st.ring[sm][c];
+        out[c] = T(0);
+        if (c < k.m) {
+            const T up = st.ring[su][c], dn = st.ring[sd][c];
+            const T axis = (up + dn) + (lane_from_right(cen[c]) + lane_from_left(cen[c]));
+            if constexpr (Q == 5) {
+                out[c] = fma(k.dl[c], fma(T(-4), cen[c], axis), cen[c]);
+            } else {
+                const T diag = (lane_from_right(up) + lane_from_left(up)) +
+                               (lane_from_right(dn) + lane_from_left(dn));
+                out[c] = fma(k.dl[c], fma(T(-20), cen[c], fma(T(4), axis, diag)), cen[c]);
+            }
+            if ((k.counted >> c) & 1u)
+                total += cen[c];
+        }
+    }
+    for (int r = 0; r < k.ntrans; ++r) {
+        T flow = k.rate[r] * pick(cen, k.src[r]);
+        if (k.cat[r] >= 0)
+            flow *= pick(cen, k.cat[r]);
+        if (k.freq[r]) {
+            const T q = quotient(flow, total);
+            flow = total > T(0) ? q : T(0);
+        }
+        add_to(out, k.src[r], -flow);
+        if (k.dst[r] >= 0)
+            add_to(out, k.dst[r], flow);
+    }
+    if (a.out_col) {
+        const long long row = (long long)(a.j0 + t - 1) * a.g.nx;
+#pragma unroll
+        for (int c = 0; c < MODEL_MAX_C; ++c)
+            if (c < k.m)
+                buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), a.xo, out[c]);
+    }
+}
+
+template <typename T, int Q, int P>
+__device__ __forceinline__ void model_steady(ModelRows<T> &st, const ModelArgs<T> &a,
+                                             const ModelCoef<T> &k, int t) {
+    fetch_rows<T, (P + 1) % RING>(st, a, k, t + 1);
+    model_row<T, Q, P>(st, a, k, t);
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(BLOCK_THREADS) void model_kernel(const T *__restrict__ in,
+                                                              T *__restrict__ out, GridDesc g,
+                                                              ModelCoef<T> k, int strips,
+                                                              int chunks, int rows) {
+    const int wave = __builtin_amdgcn_readfirstlane(
+        xcd_tile(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    if (wave >= strips * chunks)
+        return;  // whole wavefront leaves together
+    const int strip = wave / chunks, chunk = wave - strip * chunks;
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, g.ny);
+    const int lane = threadIdx.x & 63;
+    const int xl = strip * MWU - MHX + lane;
+    ModelArgs<T> a;
+    a.in = in;
+    a.out = out;
+    a.g = g;
+    a.xoff = (unsigned)map_index(xl, g.nx, g.bc) * (unsigned)sizeof(T);
+    a.xo = (unsigned)xl * (unsigned)sizeof(T);
+    a.out_col = lane >= MHX && lane < MHX + MWU && xl < g.nx;
+    a.j0 = y0 - 1;
+
+    ModelRows<T> st;
+#pragma unroll
+    for (int s = 0; s < RING; ++s)
+#pragma unroll
+        for (int c = 0; c < MODEL_MAX_C; ++c)
+            st.ring[s][c] = T(0);
+    // rows j0 .. y1 (t = 0 .. tend); the output row of t is j0 + t - 1
+    const int tend = y1 - y0 + 2;
+    fetch_rows<T, 0>(st, a, k, 0);
+    fetch_rows<T, 1>(st, a, k, 1);
+    fetch_rows<T, 2>(st, a, k, 2);
+    int t = 2;
+    for (; t + RING <= tend; t += RING) {
+        model_steady<T, Q, 2>(st, a, k, t);
+        model_steady<T, Q, 3>(st, a, k, t + 1);
+        model_steady<T, Q, 0>(st, a, k, t + 2);
+        model_steady<T, Q, 1>(st, a, k, t + 3);
+    }
+    if (t < tend)
+        model_steady<T, Q, 2>(st, a, k, t);
+    if (t + 1 < tend)
+        model_steady<T, Q, 3>(st, a, k, t + 1);
+    if (t + 2 < tend)
+        model_steady<T, Q, 0>(st, a, k, t + 2);
+}
+
+template <typename T, int Q>
+hipError_t launch_t(const void *in, void *out, const GridDesc &g, const ModelCoefHost &h,
+                    hipStream_t s) {
+    ModelCoef<T> k;
+    k.m = h.m;
+    k.ntrans = h.ntrans;
+    k.counted = h.counted;
+    for (int c = 0; c < MODEL_MAX_C; ++c)
+        k.dl[c] = (T)(Q == 5 ? h.dl[c] : h.dl[c] / 6.0);
+    for (int r = 0; r < MODEL_MAX_T; ++r) {
+        k.rate[r] = (T)h.rate_dt[r];
+        k.src[r] = h.src[r];
+        k.dst[r] = h.dst[r];
+        k.cat[r] = h.cat[r];
+        k.freq[r] = h.freq[r];
+    }
+    const ModelShape sh = model_shape(g.nx, g.ny);
+    const int waves = sh.strips * sh.chunks;
+    hipLaunchKernelGGL((model_kernel<T, Q>), dim3((unsigned)((waves + 3) / 4)),
+                       dim3(BLOCK_THREADS), 0, s, static_cast<const T *>(in),
+                       static_cast<T *>(out), g, k, sh.strips, sh.chunks, sh.rows);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+ModelShape model_shape(int nx, int ny) {
+    // as the other single-step kernels: one workgroup of four wavefronts per
+    // CU on chunks of at least 8 rows
+    ModelShape s;
+    s.strips = (nx + MWU - 1) / MWU;
+    long long chunks = (256 * WAVES_PER_BLOCK) / s.strips;
+    if (chunks < 1)
+        chunks = 1;
+    long long rows = (ny + chunks - 1) / chunks;
+    if (rows < 8)
+        rows = 8;
+    if (rows > ny)
+        rows = ny;
+    s.rows = (int)rows;
+    s.chunks = (int)((ny + rows - 1) / rows);
+    return s;
+}
+
+hipError_t launch_model(int dtype, int lattice, const void *in, void *out, const GridDesc &g,
+                        const ModelCoefHost &h, hipStream_t s) {
+    if (dtype == SSLBM_F32)
+        return lattice == 9 ? launch_t<float, 9>(in, out, g, h, s)
+                            : launch_t<float, 5>(in, out, g, h, s);
+    return lattice == 9 ? launch_t<double, 9>(in, out, g, h, s)
+                        : launch_t<double, 5>(in, out, g, h, s);
+}
+
+}  // namespace sslbm

@@ -244,3 +244,41 @@ def test_surrogate_header_exports_and_host_checks(lib):
                         None) == binding.E_ARG  # step 0
     assert lib.sur_adam(a, None, b, c, vp(0x500000000), 10, 1, 1e-3, 1.0, 0.999, 1e-8,
                         None) == binding.E_ARG  # beta1 = 1
+
+
+def test_generic_model_host_checks(lib):
+    """sslbm_model_create validates the model on the host."""
+    from paper_2603_19789_amd.binding import Transition
+    D = ctypes.c_double
+    d = (D * 3)(0.1, 0.1, 0.0)
+    counted = (ctypes.c_int * 3)(1, 1, 0)
+
+    def create(lattice=9, m=3, trans=((0, 1, -1, 0, 0.5),), dd=d, dt=0.01, nx=16):
+        arr = (Transition * max(len(trans), 1))(*[Transition(*t) for t in trans])
+        h = ctypes.c_void_p()
+        st = lib.sslbm_model_create(ctypes.byref(h), nx, 8, binding.F64, binding.PERIODIC,
+                                    lattice, m, dd, counted, 1.0, dt, len(trans), arr)
+        if h.value:
+            lib.sslbm_model_destroy(h)
+        return st
+
+    assert create() == binding.OK
+    assert create(lattice=5) == binding.OK
+    assert create(lattice=7) == binding.E_ARG
+    assert create(m=0) == binding.E_ARG
+    assert create(m=9) == binding.E_ARG
+    assert create(trans=((0, 0, -1, 0, 0.5),)) == binding.E_ARG      # src == dst
+    assert create(trans=((3, 1, -1, 0, 0.5),)) == binding.E_ARG      # src out of range
+    assert create(trans=((0, 1, 5, 1, 0.5),)) == binding.E_ARG       # catalyst out of range
+    assert create(trans=((0, 1, -1, 2, 0.5),)) == binding.E_ARG      # frequency flag
+    assert create(trans=((0, 1, -1, 0, -0.5),)) == binding.E_ARG     # negative rate
+    assert create(trans=((0, -1, -1, 0, 0.5),)) == binding.OK        # sink
+    # stability: D2Q5 allows d_lu <= 1/4, D2Q9 d_lu <= 3/8 (no sources)
+    assert create(lattice=5, trans=(), dd=(D * 3)(30.0, 0, 0), dt=0.01) == binding.E_UNSTABLE
+    assert create(lattice=9, trans=(), dd=(D * 3)(30.0, 0, 0), dt=0.01) == binding.OK
+    assert create(lattice=9, trans=(), dd=(D * 3)(38.0, 0, 0), dt=0.01) == binding.E_UNSTABLE
+    assert create(trans=((0, 1, -1, 0, 250.0),)) == binding.E_UNSTABLE  # dt * outflow > 2
+    h = ctypes.c_void_p()
+    assert lib.sslbm_model_create(None, 8, 8, 0, 0, 5, 1, d, counted, 1.0, 0.01, 0,
+                                  None) == binding.E_ARG
+    assert lib.sslbm_model_step(None, h, h, None) == binding.E_ARG

@@ -1,0 +1,89 @@
+"""Generic compartmental models (D2Q5 and D2Q9, transition-list sources) on
+the GPU against the FP64 oracle's generic step, through the C ABI.
+Tolerances as the SEIRD step: relative L2 per compartment 1e-12 (FP64),
+1e-5 (FP32)."""
+import numpy as np
+import pytest
+
+import generic_pins
+import oracle
+from gpu_util import TOL, max_rel_l2, to_gpu, to_np
+from paper_2603_19789_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2603_19789_amd import Model, Solver  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+SHAPES = [(1, 1), (3, 2), (62, 9), (63, 17), (130, 45), (201, 67)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("lattice", [5, 9])
+@pytest.mark.parametrize("nx,ny", SHAPES)
+def test_seirvd_steps(orc, nx, ny, lattice, bc, dtype):
+    """The six-compartment vaccination / waning model, 7 steps, random state."""
+    print(f"model {nx}x{ny} D2Q{lattice} {bc} {dtype}", flush=True)
+    m = inputs.seirvd_model(lattice=lattice, dt=0.05)
+    rng = np.random.default_rng(nx * 7 + ny)
+    rho0 = rng.uniform(0.0, 0.3, size=(6, ny, nx))
+    rho0[0] += 0.5
+    if dtype == "f32":
+        rho0 = rho0.astype(np.float32).astype(np.float64)
+    want = orc.generic_run(rho0, m, 7, bc=bc)
+    g = Model(nx, ny, m, dtype=dtype, bc=bc)
+    rho = to_gpu(rho0, dtype)
+    g.run(rho, 7)
+    err = max_rel_l2(to_np(rho), want)
+    print(f"  err {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+def test_seird_as_transitions_matches_the_seird_kernel():
+    """SEIRD written as transitions on D2Q5 agrees with the SEIRD pass kernel
+    (different rounding order: within the FP64 tolerance)."""
+    p = inputs.c1_params()
+    w = inputs.c1_workload(96, 80, nsteps=300)
+    m = generic_pins.seird_as_transitions(p, lattice=5)
+    a = to_gpu(w.rho0, "f64")
+    Model(96, 80, m, dtype="f64").run(a, 300)
+    b = to_gpu(w.rho0, "f64")
+    Solver(96, 80, p, dtype="f64").run(b, 300)
+    err = max_rel_l2(to_np(a), to_np(b))
+    print(f"SEIRD via transitions vs SEIRD kernel: {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_d2q9_long_run_and_conservation(orc):
+    """A 128x96 run of 200 steps on D2Q9 against the oracle, and the total
+    population (no sinks: vaccination and waning only move people)."""
+    m = inputs.seirvd_model(lattice=9)
+    rho0 = inputs.seirvd_state(128, 96)
+    want = orc.generic_run(rho0, m, 200)
+    for bc in ("periodic", "noflux"):
+        want = orc.generic_run(rho0, m, 200, bc=bc)
+        rho = to_gpu(rho0, "f64")
+        Model(128, 96, m, dtype="f64", bc=bc).run(rho, 200)
+        got = to_np(rho)
+        assert max_rel_l2(got, want) <= TOL["f64"]
+        assert abs(got.sum() - rho0.sum()) <= 1e-12 * rho0.sum()
+
+
+def test_model_errors():
+    from paper_2603_19789_amd import SSLBMError
+    m = inputs.seirvd_model(lattice=9)
+    g = Model(32, 16, m, dtype="f32")
+    with pytest.raises(ValueError):
+        g.step(torch.zeros((5, 16, 32), dtype=torch.float32, device="cuda"))
+    rho = torch.zeros(g.shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(SSLBMError):
+        g.step(rho, rho)  # in place: the step is out of place
+    with pytest.raises(SSLBMError):
+        Model(32, 16, inputs.GenericModel(("a",), (100.0,), (), (1,), 5, 1.0, 0.01))
