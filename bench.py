@@ -71,6 +71,9 @@ def parse_args():
     ap.add_argument("--surrogate-steps", type=int, default=1250,
                     help="training steps (batch 16 at 256x256) of the surrogate before its "
                          "1024x1024 rollout to 5000 steps (0 skips it)")
+    ap.add_argument("--generic-steps", type=int, default=200,
+                    help="steps of the generic six-compartment model on D2Q5 and D2Q9 "
+                         "(0 skips it)")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the uneven 512-instance ensemble (0 skips it)")
     return ap.parse_args()
@@ -309,6 +312,32 @@ def run_surrogate(torch, inputs, Solver, train_steps):
             "dtype": "bf16 network, f32 state"}
 
 
+def run_generic(torch, inputs, Model, steps):
+    """The six-compartment vaccination / waning model (generic transition
+    sources) on a 4096 x 4096 periodic grid, D2Q5 and D2Q9, FP32, one step
+    per launch: GLUPS and HBM GB/s (6 fields read and written per node)."""
+    out = []
+    rho0 = torch.tensor(inputs.seirvd_state(NX, NY), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for lattice in (5, 9):
+        m = Model(NX, NY, inputs.seirvd_model(lattice=lattice), dtype="f32")
+        rho = rho0.clone()
+        scratch = torch.empty_like(rho)
+        m.run(rho, 10, scratch)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        m.run(rho, steps, scratch)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out.append({"lattice": f"D2Q{lattice}", "compartments": 6, "transitions": 7,
+                    "ms_per_step": round(ms, 5),
+                    "glups": round(NX * NY / (ms * 1e-3) / 1e9, 2),
+                    "gbps": round(48 * NX * NY / (ms * 1e-3) / 1e9, 1)})
+    return {"workload": f"seirvd-{NX}x{NY}-f32", "steps": steps, "runs": out}
+
+
 def copy_probe(torch, reps: int = 1):
     """Plain device-to-device copies of 1 GiB: the practical HBM ceiling of
     this GPU (read + write GB/s), and a transfer of known size for scaling HBM
@@ -362,7 +391,7 @@ def main():
 
     import torch
 
-    from paper_2603_19789_amd import BGK, Ensemble, Solver, inputs
+    from paper_2603_19789_amd import BGK, Ensemble, Model, Solver, inputs
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -403,6 +432,13 @@ def main():
         print(f"# adjoint: gradient in {adjoint_res['gradient_ms']:.1f} ms "
               f"(forward {adjoint_res['forward_ms']:.1f}, reverse {adjoint_res['reverse_ms']:.1f}); "
               f"adjoint step {adjoint_res['adjoint_step_gbps']:.0f} GB/s",
+              file=sys.stderr, flush=True)
+
+    generic_res = None
+    if args.generic_steps > 0:
+        generic_res = run_generic(torch, inputs, Model, args.generic_steps)
+        print("# generic model: " + ", ".join(f"{r['lattice']} {r['glups']:.1f} GLUPS "
+                                              f"{r['gbps']:.0f} GB/s" for r in generic_res["runs"]),
               file=sys.stderr, flush=True)
 
     surrogate_res = None
@@ -464,6 +500,8 @@ def main():
         line["adjoint"] = adjoint_res
     if surrogate_res is not None:
         line["surrogate"] = surrogate_res
+    if generic_res is not None:
+        line["generic"] = generic_res
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs, args.cpu_seconds)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)
