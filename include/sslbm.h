@@ -296,7 +296,10 @@ void sslbm_ensemble_destroy(sslbm_ensemble *e);
  *       s * d_lu + dt * outflow > 2, s = 8 (D2Q5) or 16/3 (D2Q9), outflow the
  *       sum of its transitions' rates (density-dependent catalysis, whose
  *       flow has no bound, is left out). Host memory only.
- *   sslbm_model_step / sslbm_model_run: as sslbm_step / sslbm_run.
+ *   sslbm_model_step / sslbm_model_run: as sslbm_step / sslbm_run. The
+ *       first call uploads a small transition table to the current device
+ *       (synchronous); the model then stays on that device
+ *       (SSLBM_E_UNSUPPORTED elsewhere).
  */
 #define SSLBM_MAX_COMPARTMENTS 8
 #define SSLBM_MAX_TRANSITIONS 16

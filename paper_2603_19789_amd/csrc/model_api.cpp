@@ -14,6 +14,8 @@ struct sslbm_model {
     int nx = 0, ny = 0, dtype = 0, bc = 0, lattice = 5;
     sslbm::ModelCoefHost coef{};
     int last_hip = 0;
+    void *table = nullptr;  // device transition table, uploaded on first use
+    int table_device = -1;
 };
 
 namespace {
@@ -34,6 +36,32 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 size_t state_bytes(const sslbm_model *m) {
     return (size_t)m->coef.m * m->nx * m->ny * (m->dtype == SSLBM_F32 ? 4 : 8);
+}
+
+// The device transition table on the current device (uploaded once; a
+// model stays on the device it first ran on).
+int ensure_table(sslbm_model *m) {
+    int dev = 0;
+    int st = hip_status(m, hipGetDevice(&dev));
+    if (st != SSLBM_OK)
+        return st;
+    if (m->table)
+        return m->table_device == dev ? SSLBM_OK : SSLBM_E_UNSUPPORTED;
+    const size_t elem = m->dtype == SSLBM_F32 ? 4 : 8;
+    const size_t bytes = (size_t)sslbm::MODEL_MAX_T * sslbm::MODEL_TAB_STRIDE * elem;
+    unsigned char host[sslbm::MODEL_MAX_T * sslbm::MODEL_TAB_STRIDE * 8] = {};
+    sslbm::model_table(m->coef, m->dtype, host);
+    st = hip_status(m, hipMalloc(&m->table, bytes));
+    if (st != SSLBM_OK)
+        return st;
+    st = hip_status(m, hipMemcpy(m->table, host, bytes, hipMemcpyHostToDevice));
+    if (st != SSLBM_OK) {
+        (void)hipFree(m->table);
+        m->table = nullptr;
+        return st;
+    }
+    m->table_device = dev;
+    return SSLBM_OK;
 }
 
 sslbm::GridDesc grid_of(const sslbm_model *m) {
@@ -116,8 +144,11 @@ int sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hi
     const size_t bytes = state_bytes(m);
     if (overlap(rho_in, bytes, rho_out, bytes))
         return SSLBM_E_ALIAS;
+    const int st = ensure_table(m);
+    if (st != SSLBM_OK)
+        return st;
     return hip_status(m, sslbm::launch_model(m->dtype, m->lattice, rho_in, rho_out, grid_of(m),
-                                             m->coef, (hipStream_t)hip_stream));
+                                             m->coef, m->table, (hipStream_t)hip_stream));
 }
 
 int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
@@ -127,11 +158,16 @@ int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
     const size_t bytes = state_bytes(m);
     if (overlap(rho, bytes, scratch, bytes))
         return SSLBM_E_ALIAS;
+    if (nsteps == 0)
+        return SSLBM_OK;
+    const int tst = ensure_table(m);
+    if (tst != SSLBM_OK)
+        return tst;
     const hipStream_t s = (hipStream_t)hip_stream;
     void *src = rho, *dst = scratch;
     for (long long n = 0; n < nsteps; ++n) {
         const int st = hip_status(m, sslbm::launch_model(m->dtype, m->lattice, src, dst,
-                                                         grid_of(m), m->coef, s));
+                                                         grid_of(m), m->coef, m->table, s));
         if (st != SSLBM_OK)
             return st;
         void *tmp = src;
@@ -145,6 +181,12 @@ int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
 
 int sslbm_model_last_hip_error(const sslbm_model *m) { return m ? m->last_hip : 0; }
 
-void sslbm_model_destroy(sslbm_model *m) { delete m; }
+void sslbm_model_destroy(sslbm_model *m) {
+    if (!m)
+        return;
+    if (m->table)
+        (void)hipFree(m->table);
+    delete m;
+}
 
 }  // extern "C"

@@ -10,15 +10,16 @@ namespace sslbm {
 
 constexpr int MODEL_MAX_C = SSLBM_MAX_COMPARTMENTS;
 constexpr int MODEL_MAX_T = SSLBM_MAX_TRANSITIONS;
+// one transition in the device table: src one-hot, catalyst one-hot, the
+// constant term, the frequency flag, rate dt (delta_dst - delta_src)
+constexpr int MODEL_TAB_STRIDE = 3 * MODEL_MAX_C + 2;
 
-// Per-step constants in the arithmetic type: dl = d dt / dx^2 (divided by 6
-// on D2Q9), rate = rate dt; the transition table; counted = bit mask of the
-// compartments summed into N.
+// Per-step constants passed to the kernel in the arithmetic type: dl =
+// d dt / dx^2 (divided by 6 on D2Q9); counted = bit mask of the compartments
+// summed into N. The transitions travel in a device table (model_table).
 template <typename T>
 struct ModelCoef {
     T dl[MODEL_MAX_C];
-    T rate[MODEL_MAX_T];
-    int src[MODEL_MAX_T], dst[MODEL_MAX_T], cat[MODEL_MAX_T], freq[MODEL_MAX_T];
     int m, ntrans;
     unsigned counted;
 };
@@ -38,6 +39,9 @@ struct ModelShape {
 
 ModelShape model_shape(int nx, int ny);
 hipError_t launch_model(int dtype, int lattice, const void *in, void *out, const GridDesc &g,
-                        const ModelCoefHost &h, hipStream_t s);
+                        const ModelCoefHost &h, const void *table, hipStream_t s);
+// The device table (MODEL_TAB_STRIDE values per transition, in the
+// arithmetic type) written into host memory dst.
+void model_table(const ModelCoefHost &h, int dtype, void *dst);
 
 }  // namespace sslbm

@@ -13,8 +13,8 @@
 // Sources. Transition r moves rate_r dt C[src] (C[cat] if cat >= 0)
 // (/ N if frequency-dependent, 0 where N <= 0) from src to dst (dst < 0:
 // out of the system); N sums the compartments flagged as counted. The table
-// is the same for every node (kernel arguments), so every compartment
-// lookup is a wavefront-uniform branch, not a per-lane select.
+// is the same for every node (kernel arguments): its loop is unrolled and
+// every lookup is a select on a scalar condition.
 //
 // Traversal: the y-march of the single-step kernels (one wavefront per strip
 // of 62 output columns plus one halo column per side, rows in a 4-slot
@@ -37,35 +37,6 @@ struct ModelRows {
 };
 
 template <typename T>
-__device__ __forceinline__ T pick(const T v[MODEL_MAX_C], int c) {
-    switch (c) {
-    case 0: return v[0];
-    case 1: return v[1];
-    case 2: return v[2];
-    case 3: return v[3];
-    case 4: return v[4];
-    case 5: return v[5];
-    case 6: return v[6];
-    default: return v[7];
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void add_to(T v[MODEL_MAX_C], int c, T x) {
-    switch (c) {
-    case 0: v[0] += x; break;
-    case 1: v[1] += x; break;
-    case 2: v[2] += x; break;
-    case 3: v[3] += x; break;
-    case 4: v[4] += x; break;
-    case 5: v[5] += x; break;
-    case 6: v[6] += x; break;
-    case 7: v[7] += x; break;
-    default: break;
-    }
-}
-
-template <typename T>
 struct ModelArgs {
     const T *__restrict__ in;
     T *__restrict__ out;
@@ -75,28 +46,29 @@ struct ModelArgs {
     int j0;
 };
 
-template <typename T, int SL>
-__device__ __forceinline__ void fetch_rows(ModelRows<T> &st, const ModelArgs<T> &a,
-                                           const ModelCoef<T> &k, int t) {
+// The compartment count is a template parameter, so every load is
+// unconditional straight-line code and the next row's loads stay in flight
+// while the current row is computed.
+template <typename T, int M, int SL>
+__device__ __forceinline__ void fetch_rows(ModelRows<T> &st, const ModelArgs<T> &a, int t) {
     const long long row = (long long)map_index(a.j0 + t, a.g.ny, a.g.bc) * a.g.nx;
 #pragma unroll
-    for (int c = 0; c < MODEL_MAX_C; ++c)
-        if (c < k.m)
-            st.ring[SL][c] =
-                buf_load(row_resource(a.in + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
+    for (int c = 0; c < M; ++c)
+        st.ring[SL][c] =
+            buf_load(row_resource(a.in + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
 }
 
-template <typename T, int Q, int P>
+template <typename T, int Q, int M, int P>
 __device__ __forceinline__ void model_row(ModelRows<T> &st, const ModelArgs<T> &a,
-                                          const ModelCoef<T> &k, int t) {
+                                          const ModelCoef<T> &k, const T *tab, int t) {
     constexpr int su = (P + 2) % RING, sm = (P + 3) % RING, sd = P % RING;
     T cen[MODEL_MAX_C], out[MODEL_MAX_C];
     T total = T(0);
 #pragma unroll
     for (int c = 0; c < MODEL_MAX_C; ++c) {
-        cen[c] = st.ring[sm][c];
+        cen[c] = c < M ? st.ring[sm][c] : T(0);
         out[c] = T(0);
-        if (c < k.m) {
+        if (c < M) {
             const T up = st.ring[su][c], dn = st.ring[sd][c];
             const T axis = (up + dn) + (lane_from_right(cen[c]) + lane_from_left(cen[c]));
             if constexpr (Q == 5) {
@@ -106,43 +78,52 @@ __device__ __forceinline__ void model_row(ModelRows<T> &st, const ModelArgs<T> &
                                (lane_from_right(dn) + lane_from_left(dn));
                 out[c] = fma(k.dl[c], fma(T(-20), cen[c], fma(T(4), axis, diag)), cen[c]);
             }
-            if ((k.counted >> c) & 1u)
-                total += cen[c];
+            total += ((k.counted >> c) & 1u) ? cen[c] : T(0);
         }
     }
+    // transitions, from the table in LDS (uniform addresses: broadcasts)
     for (int r = 0; r < k.ntrans; ++r) {
-        T flow = k.rate[r] * pick(cen, k.src[r]);
-        if (k.cat[r] >= 0)
-            flow *= pick(cen, k.cat[r]);
-        if (k.freq[r]) {
-            const T q = quotient(flow, total);
-            flow = total > T(0) ? q : T(0);
+        const T *e = tab + r * MODEL_TAB_STRIDE;
+        T src = T(0), cat = e[2 * MODEL_MAX_C];  // the constant term: 1 without catalyst
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            src = fma(e[c], cen[c], src);
+            cat = fma(e[MODEL_MAX_C + c], cen[c], cat);
         }
-        add_to(out, k.src[r], -flow);
-        if (k.dst[r] >= 0)
-            add_to(out, k.dst[r], flow);
+        T flow = src * cat;
+        const T q = quotient(flow, total);
+        flow = e[2 * MODEL_MAX_C + 1] != T(0) ? (total > T(0) ? q : T(0)) : flow;
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            out[c] = fma(e[2 * MODEL_MAX_C + 2 + c], flow, out[c]);
     }
     if (a.out_col) {
         const long long row = (long long)(a.j0 + t - 1) * a.g.nx;
 #pragma unroll
-        for (int c = 0; c < MODEL_MAX_C; ++c)
-            if (c < k.m)
-                buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), a.xo, out[c]);
+        for (int c = 0; c < M; ++c)
+            buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), a.xo, out[c]);
     }
 }
 
-template <typename T, int Q, int P>
+template <typename T, int Q, int M, int P>
 __device__ __forceinline__ void model_steady(ModelRows<T> &st, const ModelArgs<T> &a,
-                                             const ModelCoef<T> &k, int t) {
-    fetch_rows<T, (P + 1) % RING>(st, a, k, t + 1);
-    model_row<T, Q, P>(st, a, k, t);
+                                             const ModelCoef<T> &k, const T *tab, int t) {
+    fetch_rows<T, M, (P + 1) % RING>(st, a, t + 1);
+    model_row<T, Q, M, P>(st, a, k, tab, t);
 }
 
-template <typename T, int Q>
+template <typename T, int Q, int M>
 __global__ __launch_bounds__(BLOCK_THREADS) void model_kernel(const T *__restrict__ in,
                                                               T *__restrict__ out, GridDesc g,
-                                                              ModelCoef<T> k, int strips,
-                                                              int chunks, int rows) {
+                                                              ModelCoef<T> k,
+                                                              const T *__restrict__ table,
+                                                              int strips, int chunks, int rows) {
+    // the transition table, copied to LDS by the whole workgroup before any
+    // wavefront may leave
+    __shared__ T tab[MODEL_MAX_T * MODEL_TAB_STRIDE];
+    for (int i = threadIdx.x; i < k.ntrans * MODEL_TAB_STRIDE; i += BLOCK_THREADS)
+        tab[i] = table[i];
+    __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(
         xcd_tile(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (threadIdx.x >> 6));
     if (wave >= strips * chunks)
@@ -169,46 +150,56 @@ __global__ __launch_bounds__(BLOCK_THREADS) void model_kernel(const T *__restric
             st.ring[s][c] = T(0);
     // rows j0 .. y1 (t = 0 .. tend); the output row of t is j0 + t - 1
     const int tend = y1 - y0 + 2;
-    fetch_rows<T, 0>(st, a, k, 0);
-    fetch_rows<T, 1>(st, a, k, 1);
-    fetch_rows<T, 2>(st, a, k, 2);
+    fetch_rows<T, M, 0>(st, a, 0);
+    fetch_rows<T, M, 1>(st, a, 1);
+    fetch_rows<T, M, 2>(st, a, 2);
     int t = 2;
     for (; t + RING <= tend; t += RING) {
-        model_steady<T, Q, 2>(st, a, k, t);
-        model_steady<T, Q, 3>(st, a, k, t + 1);
-        model_steady<T, Q, 0>(st, a, k, t + 2);
-        model_steady<T, Q, 1>(st, a, k, t + 3);
+        model_steady<T, Q, M, 2>(st, a, k, tab, t);
+        model_steady<T, Q, M, 3>(st, a, k, tab, t + 1);
+        model_steady<T, Q, M, 0>(st, a, k, tab, t + 2);
+        model_steady<T, Q, M, 1>(st, a, k, tab, t + 3);
     }
     if (t < tend)
-        model_steady<T, Q, 2>(st, a, k, t);
+        model_steady<T, Q, M, 2>(st, a, k, tab, t);
     if (t + 1 < tend)
-        model_steady<T, Q, 3>(st, a, k, t + 1);
+        model_steady<T, Q, M, 3>(st, a, k, tab, t + 1);
     if (t + 2 < tend)
-        model_steady<T, Q, 0>(st, a, k, t + 2);
+        model_steady<T, Q, M, 0>(st, a, k, tab, t + 2);
+}
+
+template <typename T, int Q, int M>
+hipError_t launch_m(const void *in, void *out, const GridDesc &g, const ModelCoef<T> &k,
+                    const void *table, hipStream_t s) {
+    const ModelShape sh = model_shape(g.nx, g.ny);
+    const int waves = sh.strips * sh.chunks;
+    hipLaunchKernelGGL((model_kernel<T, Q, M>), dim3((unsigned)((waves + 3) / 4)),
+                       dim3(BLOCK_THREADS), 0, s, static_cast<const T *>(in),
+                       static_cast<T *>(out), g, k, static_cast<const T *>(table), sh.strips,
+                       sh.chunks, sh.rows);
+    return hipGetLastError();
 }
 
 template <typename T, int Q>
 hipError_t launch_t(const void *in, void *out, const GridDesc &g, const ModelCoefHost &h,
-                    hipStream_t s) {
+                    const void *table, hipStream_t s) {
     ModelCoef<T> k;
     k.m = h.m;
     k.ntrans = h.ntrans;
     k.counted = h.counted;
     for (int c = 0; c < MODEL_MAX_C; ++c)
         k.dl[c] = (T)(Q == 5 ? h.dl[c] : h.dl[c] / 6.0);
-    for (int r = 0; r < MODEL_MAX_T; ++r) {
-        k.rate[r] = (T)h.rate_dt[r];
-        k.src[r] = h.src[r];
-        k.dst[r] = h.dst[r];
-        k.cat[r] = h.cat[r];
-        k.freq[r] = h.freq[r];
+    switch (h.m) {
+    case 1: return launch_m<T, Q, 1>(in, out, g, k, table, s);
+    case 2: return launch_m<T, Q, 2>(in, out, g, k, table, s);
+    case 3: return launch_m<T, Q, 3>(in, out, g, k, table, s);
+    case 4: return launch_m<T, Q, 4>(in, out, g, k, table, s);
+    case 5: return launch_m<T, Q, 5>(in, out, g, k, table, s);
+    case 6: return launch_m<T, Q, 6>(in, out, g, k, table, s);
+    case 7: return launch_m<T, Q, 7>(in, out, g, k, table, s);
+    case 8: return launch_m<T, Q, 8>(in, out, g, k, table, s);
+    default: return hipErrorInvalidValue;
     }
-    const ModelShape sh = model_shape(g.nx, g.ny);
-    const int waves = sh.strips * sh.chunks;
-    hipLaunchKernelGGL((model_kernel<T, Q>), dim3((unsigned)((waves + 3) / 4)),
-                       dim3(BLOCK_THREADS), 0, s, static_cast<const T *>(in),
-                       static_cast<T *>(out), g, k, sh.strips, sh.chunks, sh.rows);
-    return hipGetLastError();
 }
 
 }  // namespace
@@ -232,12 +223,38 @@ ModelShape model_shape(int nx, int ny) {
 }
 
 hipError_t launch_model(int dtype, int lattice, const void *in, void *out, const GridDesc &g,
-                        const ModelCoefHost &h, hipStream_t s) {
+                        const ModelCoefHost &h, const void *table, hipStream_t s) {
     if (dtype == SSLBM_F32)
-        return lattice == 9 ? launch_t<float, 9>(in, out, g, h, s)
-                            : launch_t<float, 5>(in, out, g, h, s);
-    return lattice == 9 ? launch_t<double, 9>(in, out, g, h, s)
-                        : launch_t<double, 5>(in, out, g, h, s);
+        return lattice == 9 ? launch_t<float, 9>(in, out, g, h, table, s)
+                            : launch_t<float, 5>(in, out, g, h, table, s);
+    return lattice == 9 ? launch_t<double, 9>(in, out, g, h, table, s)
+                        : launch_t<double, 5>(in, out, g, h, table, s);
+}
+
+void model_table(const ModelCoefHost &h, int dtype, void *dst) {
+    // per transition: one-hot row of src (MODEL_MAX_C), one-hot row of the
+    // catalyst (MODEL_MAX_C) and the constant 1 when there is none, the
+    // frequency flag, then rate dt (delta_dst - delta_src) per compartment
+    double row[MODEL_TAB_STRIDE];
+    for (int r = 0; r < h.ntrans; ++r) {
+        for (int i = 0; i < MODEL_TAB_STRIDE; ++i)
+            row[i] = 0.0;
+        row[h.src[r]] = 1.0;
+        if (h.cat[r] >= 0)
+            row[MODEL_MAX_C + h.cat[r]] = 1.0;
+        else
+            row[2 * MODEL_MAX_C] = 1.0;
+        row[2 * MODEL_MAX_C + 1] = h.freq[r] ? 1.0 : 0.0;
+        row[2 * MODEL_MAX_C + 2 + h.src[r]] = -h.rate_dt[r];
+        if (h.dst[r] >= 0)
+            row[2 * MODEL_MAX_C + 2 + h.dst[r]] = h.rate_dt[r];
+        for (int i = 0; i < MODEL_TAB_STRIDE; ++i) {
+            if (dtype == SSLBM_F32)
+                static_cast<float *>(dst)[r * MODEL_TAB_STRIDE + i] = (float)row[i];
+            else
+                static_cast<double *>(dst)[r * MODEL_TAB_STRIDE + i] = row[i];
+        }
+    }
 }
 
 }  // namespace sslbm
