@@ -109,32 +109,46 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
         for (int ns = 0; ns < NT; ++ns)
             acc[ms][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int t = 0; t < 9; ++t) {
+    // k runs over (tap, 32-channel chunk); the fragments of step k + 1 are
+    // loaded while the MFMAs of step k run (two register sets). Loads are
+    // unconditional: a step past the end reloads the last one.
+    const int nck = (a.cin + 31) / 32;
+    const int steps = 9 * nck;
+    auto load_step = [&](int kk, bf16x8 *A, bf16x8 *B) {
+        kk = kk < steps ? kk : steps - 1;
+        const int t = kk / nck;
+        const int cc = (kk - t * nck) * 32 + 8 * g;
         const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const uint16_t *arow[4];
+        const bool live = cc < a.cin;
 #pragma unroll
         for (int ms = 0; ms < 4; ++ms) {
             const int yy = wrap(py[ms] + dy, a.h), xx = wrap(px[ms] + dx, a.w);
-            arow[ms] = x + (((long long)pn[ms] * a.h + yy) * a.w + xx) * a.x_pitch;
+            const uint16_t *row = x + (((long long)pn[ms] * a.h + yy) * a.w + xx) * a.x_pitch;
+            A[ms] = live ? load8(row + cc) : zero8();
         }
-        for (int c0 = 0; c0 < a.cin; c0 += 32) {
-            const int cc = c0 + 8 * g;
-            const bool live = cc < a.cin;
-            bf16x8 A[4], B[NT];
 #pragma unroll
-            for (int ms = 0; ms < 4; ++ms)
-                A[ms] = live ? load8(arow[ms] + cc) : zero8();
+        for (int ns = 0; ns < NT; ++ns)
+            B[ns] = live ? load8(wt + ((long long)co[ns] * 9 + t) * a.cin + cc) : zero8();
+    };
+    auto mfma_step = [&](const bf16x8 *A, const bf16x8 *B) {
+#pragma unroll
+        for (int ms = 0; ms < 4; ++ms)
 #pragma unroll
             for (int ns = 0; ns < NT; ++ns)
-                B[ns] = live ? load8(wt + ((long long)co[ns] * 9 + t) * a.cin + cc) : zero8();
-#pragma unroll
-            for (int ms = 0; ms < 4; ++ms)
-#pragma unroll
-                for (int ns = 0; ns < NT; ++ns)
-                    acc[ms][ns] =
-                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ms], B[ns], acc[ms][ns], 0, 0, 0);
-        }
+                acc[ms][ns] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ms], B[ns], acc[ms][ns], 0, 0, 0);
+    };
+    bf16x8 A0[4], B0[NT], A1[4], B1[NT];
+    load_step(0, A0, B0);
+    int kk = 0;
+    for (; kk + 1 < steps; kk += 2) {
+        load_step(kk + 1, A1, B1);
+        mfma_step(A0, B0);
+        load_step(kk + 2, A0, B0);
+        mfma_step(A1, B1);
     }
+    if (kk < steps)
+        mfma_step(A0, B0);
 
 #pragma unroll
     for (int ns = 0; ns < NT; ++ns) {
@@ -629,30 +643,31 @@ unsigned blocks_for(long long work) { return (unsigned)((work + THREADS - 1) / T
 
 }  // namespace
 
-hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
+template <int NT>
+static void conv_fwd_nt(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
     const long long P = (long long)a.n * a.h * a.w;
-    const bool two = a.cout > 16;
-    const long long groups = two ? (a.cout + 31) / 32 : 1;
+    const long long groups = (a.cout + 16 * NT - 1) / (16 * NT);
     const long long waves = (P + 63) / 64 * groups;
     const dim3 grid((unsigned)((waves + 3) / 4)), block(THREADS);
-#define SUR_FWD(NT, F, L) hipLaunchKernelGGL((conv_fwd_kernel<NT, F, L>), grid, block, 0, s, a)
-    if (two && f32out && leaky)
-        SUR_FWD(2, true, true);
-    else if (two && f32out)
-        SUR_FWD(2, true, false);
-    else if (two && leaky)
-        SUR_FWD(2, false, true);
-    else if (two)
-        SUR_FWD(2, false, false);
-    else if (f32out && leaky)
-        SUR_FWD(1, true, true);
+    if (f32out && leaky)
+        hipLaunchKernelGGL((conv_fwd_kernel<NT, true, true>), grid, block, 0, s, a);
     else if (f32out)
-        SUR_FWD(1, true, false);
+        hipLaunchKernelGGL((conv_fwd_kernel<NT, true, false>), grid, block, 0, s, a);
     else if (leaky)
-        SUR_FWD(1, false, true);
+        hipLaunchKernelGGL((conv_fwd_kernel<NT, false, true>), grid, block, 0, s, a);
     else
-        SUR_FWD(1, false, false);
-#undef SUR_FWD
+        hipLaunchKernelGGL((conv_fwd_kernel<NT, false, false>), grid, block, 0, s, a);
+}
+
+// A wavefront covers 64 pixels x (16 NT) output channels: the widest tile the
+// output channel count fills.
+hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
+    if (a.cout >= 64)
+        conv_fwd_nt<4>(a, leaky, f32out, s);
+    else if (a.cout > 16)
+        conv_fwd_nt<2>(a, leaky, f32out, s);
+    else
+        conv_fwd_nt<1>(a, leaky, f32out, s);
     return hipGetLastError();
 }
 
