@@ -47,9 +47,8 @@ int ensure_table(sslbm_model *m) {
         return st;
     if (m->table)
         return m->table_device == dev ? SSLBM_OK : SSLBM_E_UNSUPPORTED;
-    const size_t elem = m->dtype == SSLBM_F32 ? 4 : 8;
-    const size_t bytes = (size_t)sslbm::MODEL_MAX_T * sslbm::MODEL_TAB_STRIDE * elem;
-    unsigned char host[sslbm::MODEL_MAX_T * sslbm::MODEL_TAB_STRIDE * 8] = {};
+    const size_t bytes = sslbm::model_table_bytes(m->dtype);
+    alignas(16) unsigned char host[sslbm::model_table_bytes(SSLBM_F64)] = {};
     sslbm::model_table(m->coef, m->dtype, host);
     st = hip_status(m, hipMalloc(&m->table, bytes));
     if (st != SSLBM_OK)

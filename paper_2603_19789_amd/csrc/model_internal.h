@@ -10,9 +10,12 @@ namespace sslbm {
 
 constexpr int MODEL_MAX_C = SSLBM_MAX_COMPARTMENTS;
 constexpr int MODEL_MAX_T = SSLBM_MAX_TRANSITIONS;
-// one transition in the device table: src one-hot, catalyst one-hot, the
-// constant term, the frequency flag, rate dt (delta_dst - delta_src)
-constexpr int MODEL_TAB_STRIDE = 3 * MODEL_MAX_C + 2;
+// device transition table: MODEL_MAX_T int4 records, then MODEL_MAX_T rows
+// of MODEL_MAX_C stoichiometry values
+constexpr size_t model_table_bytes(int dtype) {
+    return (size_t)MODEL_MAX_T * 16 +
+           (size_t)MODEL_MAX_T * MODEL_MAX_C * (dtype == SSLBM_F32 ? 4 : 8);
+}
 
 // Per-step constants passed to the kernel in the arithmetic type: dl =
 // d dt / dx^2 (divided by 6 on D2Q9); counted = bit mask of the compartments
@@ -40,8 +43,7 @@ struct ModelShape {
 ModelShape model_shape(int nx, int ny);
 hipError_t launch_model(int dtype, int lattice, const void *in, void *out, const GridDesc &g,
                         const ModelCoefHost &h, const void *table, hipStream_t s);
-// The device table (MODEL_TAB_STRIDE values per transition, in the
-// arithmetic type) written into host memory dst.
+// The device table (model_table_bytes) written into host memory dst.
 void model_table(const ModelCoefHost &h, int dtype, void *dst);
 
 }  // namespace sslbm

@@ -13,8 +13,9 @@
 // Sources. Transition r moves rate_r dt C[src] (C[cat] if cat >= 0)
 // (/ N if frequency-dependent, 0 where N <= 0) from src to dst (dst < 0:
 // out of the system); N sums the compartments flagged as counted. The table
-// is the same for every node (kernel arguments): its loop is unrolled and
-// every lookup is a select on a scalar condition.
+// is the same for every node and sits in LDS; each lane also keeps its
+// compartment vector and its increments in LDS slots, so a lookup by table
+// index is a single LDS access rather than a select over all compartments.
 //
 // Traversal: the y-march of the single-step kernels (one wavefront per strip
 // of 62 output columns plus one halo column per side, rows in a 4-slot
@@ -30,6 +31,7 @@ namespace sslbm {
 namespace {
 
 constexpr int MHX = 1, MWU = 64 - 2 * MHX;
+constexpr int MODEL_GROUP = 4;  // transitions looked up together (divides MODEL_MAX_T)
 
 template <typename T>
 struct ModelRows {
@@ -58,9 +60,18 @@ __device__ __forceinline__ void fetch_rows(ModelRows<T> &st, const ModelArgs<T> 
             buf_load(row_resource(a.in + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
 }
 
+// A lane's view of its workgroup's LDS: the transition table (shared) and
+// the lane's own compartment and increment slots.
+template <typename T>
+struct LaneLds {
+    const int4 *itab;
+    const T *stoich;
+    T *vals;
+};
+
 template <typename T, int Q, int M, int P>
 __device__ __forceinline__ void model_row(ModelRows<T> &st, const ModelArgs<T> &a,
-                                          const ModelCoef<T> &k, const T *tab, int t) {
+                                          const ModelCoef<T> &k, const LaneLds<T> &lds, int t) {
     constexpr int su = (P + 2) % RING, sm = (P + 3) % RING, sd = P % RING;
     T cen[MODEL_MAX_C], out[MODEL_MAX_C];
     T total = T(0);
@@ -81,21 +92,39 @@ __device__ __forceinline__ void model_row(ModelRows<T> &st, const ModelArgs<T> &
             total += ((k.counted >> c) & 1u) ? cen[c] : T(0);
         }
     }
-    // transitions, from the table in LDS (uniform addresses: broadcasts)
-    for (int r = 0; r < k.ntrans; ++r) {
-        const T *e = tab + r * MODEL_TAB_STRIDE;
-        T src = T(0), cat = e[2 * MODEL_MAX_C];  // the constant term: 1 without catalyst
+    // transitions: each lane keeps its compartment vector and its source
+    // increments in LDS (slot c at element c * 64 + lane), so a lookup by a
+    // table index is one LDS access; slot M of vals holds the constant 1 (no
+    // catalyst), slot M of psi absorbs flows out of the system
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            src = fma(e[c], cen[c], src);
-            cat = fma(e[MODEL_MAX_C + c], cen[c], cat);
+    for (int c = 0; c < M; ++c)
+        lds.vals[c * 64] = cen[c];
+    // 1 / N once per node (0 where N <= 0: no frequency-dependent flow)
+    const T inv_total = total > T(0) ? quotient(T(1), total) : T(0);
+    // MODEL_GROUP transitions at a time: their lookups are issued together,
+    // so a group costs one LDS latency; increments go straight into the
+    // output registers through the stoichiometry rows (rate dt (delta_dst -
+    // delta_src), uniform LDS broadcasts). The table is padded with
+    // zero-rate transitions to a multiple of MODEL_GROUP.
+    for (int r0 = 0; r0 < k.ntrans; r0 += MODEL_GROUP) {
+        int4 d[MODEL_GROUP];
+        T sv[MODEL_GROUP], cv[MODEL_GROUP];
+#pragma unroll
+        for (int j = 0; j < MODEL_GROUP; ++j)
+            d[j] = lds.itab[r0 + j];  // src, catalyst slot, destination, frequency
+#pragma unroll
+        for (int j = 0; j < MODEL_GROUP; ++j) {
+            sv[j] = lds.vals[d[j].x * 64];
+            cv[j] = lds.vals[d[j].y * 64];
         }
-        T flow = src * cat;
-        const T q = quotient(flow, total);
-        flow = e[2 * MODEL_MAX_C + 1] != T(0) ? (total > T(0) ? q : T(0)) : flow;
 #pragma unroll
-        for (int c = 0; c < M; ++c)
-            out[c] = fma(e[2 * MODEL_MAX_C + 2 + c], flow, out[c]);
+        for (int j = 0; j < MODEL_GROUP; ++j) {
+            const T flow = sv[j] * cv[j] * (d[j].w ? inv_total : T(1));
+            const T *row = lds.stoich + (r0 + j) * MODEL_MAX_C;
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                out[c] = fma(row[c], flow, out[c]);
+        }
     }
     if (a.out_col) {
         const long long row = (long long)(a.j0 + t - 1) * a.g.nx;
@@ -107,9 +136,10 @@ __device__ __forceinline__ void model_row(ModelRows<T> &st, const ModelArgs<T> &
 
 template <typename T, int Q, int M, int P>
 __device__ __forceinline__ void model_steady(ModelRows<T> &st, const ModelArgs<T> &a,
-                                             const ModelCoef<T> &k, const T *tab, int t) {
+                                             const ModelCoef<T> &k, const LaneLds<T> &lds,
+                                             int t) {
     fetch_rows<T, M, (P + 1) % RING>(st, a, t + 1);
-    model_row<T, Q, M, P>(st, a, k, tab, t);
+    model_row<T, Q, M, P>(st, a, k, lds, t);
 }
 
 template <typename T, int Q, int M>
@@ -119,10 +149,21 @@ __global__ __launch_bounds__(BLOCK_THREADS) void model_kernel(const T *__restric
                                                               const T *__restrict__ table,
                                                               int strips, int chunks, int rows) {
     // the transition table, copied to LDS by the whole workgroup before any
-    // wavefront may leave
-    __shared__ T tab[MODEL_MAX_T * MODEL_TAB_STRIDE];
-    for (int i = threadIdx.x; i < k.ntrans * MODEL_TAB_STRIDE; i += BLOCK_THREADS)
-        tab[i] = table[i];
+    // wavefront may leave; per-lane slots for the source lookups
+    __shared__ int4 itab[MODEL_MAX_T];
+    __shared__ T stoich[MODEL_MAX_T * MODEL_MAX_C];
+    __shared__ T vals[WAVES_PER_BLOCK][(MODEL_MAX_C + 1) * 64];
+    if (threadIdx.x < (unsigned)MODEL_MAX_T) {
+        const int *row = reinterpret_cast<const int *>(table) + 4 * threadIdx.x;
+        itab[threadIdx.x] = make_int4(row[0], row[1], row[2], row[3]);
+    }
+    if (threadIdx.x < (unsigned)(MODEL_MAX_T * MODEL_MAX_C))
+        stoich[threadIdx.x] = reinterpret_cast<const T *>(reinterpret_cast<const int *>(table) +
+                                                          4 * MODEL_MAX_T)[threadIdx.x];
+    {
+        const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+        vals[w][M * 64 + l] = T(1);
+    }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(
         xcd_tile(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (threadIdx.x >> 6));
@@ -142,6 +183,11 @@ __global__ __launch_bounds__(BLOCK_THREADS) void model_kernel(const T *__restric
     a.out_col = lane >= MHX && lane < MHX + MWU && xl < g.nx;
     a.j0 = y0 - 1;
 
+    LaneLds<T> lds;
+    lds.itab = itab;
+    lds.stoich = stoich;
+    lds.vals = &vals[threadIdx.x >> 6][lane];
+
     ModelRows<T> st;
 #pragma unroll
     for (int s = 0; s < RING; ++s)
@@ -155,17 +201,17 @@ __global__ __launch_bounds__(BLOCK_THREADS) void model_kernel(const T *__restric
     fetch_rows<T, M, 2>(st, a, 2);
     int t = 2;
     for (; t + RING <= tend; t += RING) {
-        model_steady<T, Q, M, 2>(st, a, k, tab, t);
-        model_steady<T, Q, M, 3>(st, a, k, tab, t + 1);
-        model_steady<T, Q, M, 0>(st, a, k, tab, t + 2);
-        model_steady<T, Q, M, 1>(st, a, k, tab, t + 3);
+        model_steady<T, Q, M, 2>(st, a, k, lds, t);
+        model_steady<T, Q, M, 3>(st, a, k, lds, t + 1);
+        model_steady<T, Q, M, 0>(st, a, k, lds, t + 2);
+        model_steady<T, Q, M, 1>(st, a, k, lds, t + 3);
     }
     if (t < tend)
-        model_steady<T, Q, M, 2>(st, a, k, tab, t);
+        model_steady<T, Q, M, 2>(st, a, k, lds, t);
     if (t + 1 < tend)
-        model_steady<T, Q, M, 3>(st, a, k, tab, t + 1);
+        model_steady<T, Q, M, 3>(st, a, k, lds, t + 1);
     if (t + 2 < tend)
-        model_steady<T, Q, M, 0>(st, a, k, tab, t + 2);
+        model_steady<T, Q, M, 0>(st, a, k, lds, t + 2);
 }
 
 template <typename T, int Q, int M>
@@ -232,27 +278,28 @@ hipError_t launch_model(int dtype, int lattice, const void *in, void *out, const
 }
 
 void model_table(const ModelCoefHost &h, int dtype, void *dst) {
-    // per transition: one-hot row of src (MODEL_MAX_C), one-hot row of the
-    // catalyst (MODEL_MAX_C) and the constant 1 when there is none, the
-    // frequency flag, then rate dt (delta_dst - delta_src) per compartment
-    double row[MODEL_TAB_STRIDE];
-    for (int r = 0; r < h.ntrans; ++r) {
-        for (int i = 0; i < MODEL_TAB_STRIDE; ++i)
-            row[i] = 0.0;
-        row[h.src[r]] = 1.0;
-        if (h.cat[r] >= 0)
-            row[MODEL_MAX_C + h.cat[r]] = 1.0;
-        else
-            row[2 * MODEL_MAX_C] = 1.0;
-        row[2 * MODEL_MAX_C + 1] = h.freq[r] ? 1.0 : 0.0;
-        row[2 * MODEL_MAX_C + 2 + h.src[r]] = -h.rate_dt[r];
-        if (h.dst[r] >= 0)
-            row[2 * MODEL_MAX_C + 2 + h.dst[r]] = h.rate_dt[r];
-        for (int i = 0; i < MODEL_TAB_STRIDE; ++i) {
+    // MODEL_MAX_T records {src, catalyst slot (m: the constant 1),
+    // destination, frequency}, then MODEL_MAX_T stoichiometry rows of
+    // MODEL_MAX_C values rate dt (delta_dst - delta_src); records past the
+    // last transition are zero (the kernel reads the table in groups)
+    int *ints = static_cast<int *>(dst);
+    void *rows = ints + 4 * MODEL_MAX_T;
+    for (int r = 0; r < MODEL_MAX_T; ++r) {
+        const bool live = r < h.ntrans;
+        ints[4 * r + 0] = live ? h.src[r] : 0;
+        ints[4 * r + 1] = live && h.cat[r] >= 0 ? h.cat[r] : h.m;
+        ints[4 * r + 2] = live ? h.dst[r] : -1;
+        ints[4 * r + 3] = live ? h.freq[r] : 0;
+        for (int c = 0; c < MODEL_MAX_C; ++c) {
+            double v = 0.0;
+            if (live && c == h.src[r])
+                v = -h.rate_dt[r];
+            if (live && c == h.dst[r])
+                v = h.rate_dt[r];
             if (dtype == SSLBM_F32)
-                static_cast<float *>(dst)[r * MODEL_TAB_STRIDE + i] = (float)row[i];
+                static_cast<float *>(rows)[r * MODEL_MAX_C + c] = (float)v;
             else
-                static_cast<double *>(dst)[r * MODEL_TAB_STRIDE + i] = row[i];
+                static_cast<double *>(rows)[r * MODEL_MAX_C + c] = v;
         }
     }
 }
