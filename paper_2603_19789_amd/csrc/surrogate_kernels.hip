@@ -68,39 +68,85 @@ __device__ __forceinline__ uint4 pack8(const uint16_t *v) {
 }
 
 // ------------------------------------------------------------- forward conv
-// One wavefront: 64 consecutive output pixels x (16 NT) output channels.
-template <int NT, bool F32OUT, bool LEAKY>
+// A workgroup computes (64 WM) consecutive output pixels x (16 NT WN) output
+// channels, WN = 4 / WM, as a grid of WM x WN wavefronts that each own 64
+// pixels x 16 NT channels (4 x NT MFMA tiles). The k loop runs over (tap,
+// 32-channel chunk). Each step's A tile (pixels x 32 channels of the
+// tap-shifted input) and B tile (channels x 32 weights) go through LDS,
+// double-buffered: the global loads of step k + 1 are issued before the
+// MFMAs of step k and written to the other buffer after them, one barrier
+// per step. LDS rows are padded to 40 elements (80 bytes), so the 16 rows a
+// fragment read touches fall into distinct banks.
+constexpr int LDA = 40;
+
+template <int WM, int NT, bool F32OUT, bool LEAKY>
 __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
-    const int wave = blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6);
-    const int groups = (a.cout + 16 * NT - 1) / (16 * NT);
+    constexpr int WN = 4 / WM;
+    constexpr int TP = 64 * WM;       // pixels per workgroup
+    constexpr int TC = 16 * NT * WN;  // output channels per workgroup
+    constexpr int APT = TP * 4 / THREADS;  // 16-byte A pieces per thread
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][TP * LDA];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TC * LDA];
+
+    const int groups = (a.cout + TC - 1) / TC;
     const long long P = (long long)a.n * a.h * a.w;
-    const long long tile = wave / groups;
-    const int cg = wave - (int)(tile * groups);
-    if (tile * 64 >= P)
-        return;
-    const int lane = threadIdx.x & 63;
+    const long long tile = blockIdx.x / groups;
+    const int cg = (int)(blockIdx.x - tile * groups);
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
+    const int wm = wv % WM, wn = wv / WM;
     const uint16_t *x = static_cast<const uint16_t *>(a.x);
     const uint16_t *wt = static_cast<const uint16_t *>(a.wt);
 
-    int pn[4], py[4], px[4];
+    // loader roles: A piece j of this thread is pixel row (tid + 256 j) / 4,
+    // channel chunk (tid + 256 j) % 4; B piece (threads < 4 TC): output
+    // channel row tid / 4, chunk tid % 4
+    int an[APT], ay[APT], ax[APT], arow[APT], ach[APT];
+    const long long hw = (long long)a.h * a.w;
 #pragma unroll
-    for (int ms = 0; ms < 4; ++ms) {
-        long long q = tile * 64 + 16 * ms + m;
+    for (int j = 0; j < APT; ++j) {
+        const int i = tid + THREADS * j;
+        arow[j] = i >> 2;
+        ach[j] = i & 3;
+        long long q = tile * TP + arow[j];
         if (q >= P)
-            q = P - 1;  // a clamped duplicate; its result is never stored
-        const long long hw = (long long)a.h * a.w;
-        pn[ms] = (int)(q / hw);
-        const int r = (int)(q - (long long)pn[ms] * hw);
-        py[ms] = r / a.w;
-        px[ms] = r - py[ms] * a.w;
+            q = P - 1;  // a clamped duplicate; its results are never stored
+        an[j] = (int)(q / hw);
+        const int r = (int)(q - an[j] * hw);
+        ay[j] = r / a.w;
+        ax[j] = r - ay[j] * a.w;
     }
-    int co[NT];
+    const bool bload = tid < 4 * TC;
+    const int brow = tid >> 2, bch = tid & 3;
+    const int bco = min(cg * TC + brow, a.cout - 1);
+
+    const int nck = (a.cin + 31) / 32;
+    const int steps = 9 * nck;
+    uint4 ra[APT], rb = make_uint4(0, 0, 0, 0);
+    auto gload = [&](int st) {
+        st = st < steps ? st : steps - 1;  // past the end: reload the last step
+        const int t = st / nck;
+        const int c0 = (st - t * nck) * 32;
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
 #pragma unroll
-    for (int ns = 0; ns < NT; ++ns) {
-        const int c = cg * 16 * NT + 16 * ns + m;
-        co[ns] = c < a.cout ? c : a.cout - 1;
-    }
+        for (int j = 0; j < APT; ++j) {
+            const int cc = c0 + 8 * ach[j];
+            const int yy = wrap(ay[j] + dy, a.h), xx = wrap(ax[j] + dx, a.w);
+            const uint16_t *src = x + (((long long)an[j] * a.h + yy) * a.w + xx) * a.x_pitch + cc;
+            ra[j] = cc < a.cin ? *reinterpret_cast<const uint4 *>(src) : make_uint4(0, 0, 0, 0);
+        }
+        const int cc = c0 + 8 * bch;
+        if (bload)
+            rb = cc < a.cin ? *reinterpret_cast<const uint4 *>(wt + ((long long)bco * 9 + t) * a.cin + cc)
+                            : make_uint4(0, 0, 0, 0);
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < APT; ++j)
+            *reinterpret_cast<uint4 *>(&As[buf][arow[j] * LDA + 8 * ach[j]]) = ra[j];
+        if (bload)
+            *reinterpret_cast<uint4 *>(&Bs[buf][brow * LDA + 8 * bch]) = rb;
+    };
 
     f32x4 acc[4][NT];
 #pragma unroll
@@ -109,50 +155,35 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
         for (int ns = 0; ns < NT; ++ns)
             acc[ms][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // k runs over (tap, 32-channel chunk); the fragments of step k + 1 are
-    // loaded while the MFMAs of step k run (two register sets). Loads are
-    // unconditional: a step past the end reloads the last one.
-    const int nck = (a.cin + 31) / 32;
-    const int steps = 9 * nck;
-    auto load_step = [&](int kk, bf16x8 *A, bf16x8 *B) {
-        kk = kk < steps ? kk : steps - 1;
-        const int t = kk / nck;
-        const int cc = (kk - t * nck) * 32 + 8 * g;
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const bool live = cc < a.cin;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int st = 0; st < steps; ++st) {
+        const int buf = st & 1;
+        gload(st + 1);
+        bf16x8 A[4], B[NT];
 #pragma unroll
-        for (int ms = 0; ms < 4; ++ms) {
-            const int yy = wrap(py[ms] + dy, a.h), xx = wrap(px[ms] + dx, a.w);
-            const uint16_t *row = x + (((long long)pn[ms] * a.h + yy) * a.w + xx) * a.x_pitch;
-            A[ms] = live ? load8(row + cc) : zero8();
-        }
+        for (int ms = 0; ms < 4; ++ms)
+            A[ms] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4 *>(&As[buf][(wm * 64 + 16 * ms + m) * LDA + 8 * g]));
 #pragma unroll
         for (int ns = 0; ns < NT; ++ns)
-            B[ns] = live ? load8(wt + ((long long)co[ns] * 9 + t) * a.cin + cc) : zero8();
-    };
-    auto mfma_step = [&](const bf16x8 *A, const bf16x8 *B) {
+            B[ns] = __builtin_bit_cast(
+                bf16x8,
+                *reinterpret_cast<const uint4 *>(&Bs[buf][(wn * 16 * NT + 16 * ns + m) * LDA + 8 * g]));
 #pragma unroll
         for (int ms = 0; ms < 4; ++ms)
 #pragma unroll
             for (int ns = 0; ns < NT; ++ns)
                 acc[ms][ns] =
                     __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ms], B[ns], acc[ms][ns], 0, 0, 0);
-    };
-    bf16x8 A0[4], B0[NT], A1[4], B1[NT];
-    load_step(0, A0, B0);
-    int kk = 0;
-    for (; kk + 1 < steps; kk += 2) {
-        load_step(kk + 1, A1, B1);
-        mfma_step(A0, B0);
-        load_step(kk + 2, A0, B0);
-        mfma_step(A1, B1);
+        lstore(buf ^ 1);  // the other buffer was last read before the previous barrier
+        __syncthreads();
     }
-    if (kk < steps)
-        mfma_step(A0, B0);
 
 #pragma unroll
     for (int ns = 0; ns < NT; ++ns) {
-        const int c = cg * 16 * NT + 16 * ns + m;
+        const int c = cg * TC + wn * 16 * NT + 16 * ns + m;
         if (c >= a.cout)
             continue;
         const float b = a.bias ? a.bias[c] : 0.f;
@@ -160,7 +191,7 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
         for (int ms = 0; ms < 4; ++ms)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const long long q = tile * 64 + 16 * ms + 4 * g + i;
+                const long long q = tile * TP + wm * 64 + 16 * ms + 4 * g + i;
                 if (q >= P)
                     continue;
                 float v = acc[ms][ns][i] + b;
@@ -643,31 +674,31 @@ unsigned blocks_for(long long work) { return (unsigned)((work + THREADS - 1) / T
 
 }  // namespace
 
-template <int NT>
-static void conv_fwd_nt(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
+template <int WM, int NT>
+static void conv_fwd_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
+    constexpr int TP = 64 * WM, TC = 16 * NT * (4 / WM);
     const long long P = (long long)a.n * a.h * a.w;
-    const long long groups = (a.cout + 16 * NT - 1) / (16 * NT);
-    const long long waves = (P + 63) / 64 * groups;
-    const dim3 grid((unsigned)((waves + 3) / 4)), block(THREADS);
+    const long long blocks = (P + TP - 1) / TP * ((a.cout + TC - 1) / TC);
+    const dim3 grid((unsigned)blocks), block(THREADS);
     if (f32out && leaky)
-        hipLaunchKernelGGL((conv_fwd_kernel<NT, true, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((conv_fwd_kernel<WM, NT, true, true>), grid, block, 0, s, a);
     else if (f32out)
-        hipLaunchKernelGGL((conv_fwd_kernel<NT, true, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((conv_fwd_kernel<WM, NT, true, false>), grid, block, 0, s, a);
     else if (leaky)
-        hipLaunchKernelGGL((conv_fwd_kernel<NT, false, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((conv_fwd_kernel<WM, NT, false, true>), grid, block, 0, s, a);
     else
-        hipLaunchKernelGGL((conv_fwd_kernel<NT, false, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((conv_fwd_kernel<WM, NT, false, false>), grid, block, 0, s, a);
 }
 
-// A wavefront covers 64 pixels x (16 NT) output channels: the widest tile the
-// output channel count fills.
+// Workgroup tiles: 128 pixels x 64 channels for wide layers, 256 x 32 and
+// 256 x 16 for narrow ones (no channel tile wider than the layer).
 hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
     if (a.cout >= 64)
-        conv_fwd_nt<4>(a, leaky, f32out, s);
+        conv_fwd_cfg<2, 2>(a, leaky, f32out, s);
     else if (a.cout > 16)
-        conv_fwd_nt<2>(a, leaky, f32out, s);
+        conv_fwd_cfg<4, 2>(a, leaky, f32out, s);
     else
-        conv_fwd_nt<1>(a, leaky, f32out, s);
+        conv_fwd_cfg<4, 1>(a, leaky, f32out, s);
     return hipGetLastError();
 }
 
