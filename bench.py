@@ -288,10 +288,11 @@ def run_surrogate(torch, inputs, Solver, train_steps):
     final, rr = roll.run(rho0, T)
     roll_err = S.relative_l2(final, ref)
     # the surrogate alone: every jump accepted (still judged, for the error record)
-    free = S.Rollout(sur, w.params, w.ny, w.nx, tiles=4, tile=64, threshold=1e30, seed=0)
+    free = S.Rollout(sur, w.params, w.ny, w.nx, tiles=4, tile=64, threshold=1e30, seed=0,
+                     backoff=False)
     free_state, fr = free.run(rho0, T)
     free_err = S.relative_l2(free_state, ref)
-    bare = S.Rollout(sur, w.params, w.ny, w.nx, threshold=float("inf"), seed=0)
+    bare = S.Rollout(sur, w.params, w.ny, w.nx, threshold=float("inf"), seed=0, backoff=False)
     _, br = bare.run(rho0, T)
     return {"workload": w.name, "T": T, "jump": sur.jump, "parameters": net.parameters,
             "train": {"steps": rep.steps, "batch": rep.batch, "size": 256, "samples": rep.samples,
@@ -302,6 +303,7 @@ def run_surrogate(torch, inputs, Solver, train_steps):
             "plain_ms": round(plain_ms, 3), "plain_rel_l2_vs_fp64": plain_err,
             "rollout_ms": round(rr.seconds * 1e3, 3), "rollout_rel_l2_vs_fp64": roll_err,
             "accepted_jumps": rr.accepted, "fallback_jumps": rr.fallbacks,
+            "skipped_jumps": rr.skipped,
             "target": 1e-3, "per_jump_threshold": rr.threshold,
             "speedup_at_1e-3": round(plain_ms / (rr.seconds * 1e3), 4),
             "surrogate_only_ms": round(br.seconds * 1e3, 3),
@@ -447,8 +449,8 @@ def main():
         print(f"# surrogate: trained {surrogate_res['train']['steps']} steps in "
               f"{surrogate_res['train']['seconds']:.1f} s (loss {surrogate_res['train']['last_loss']:.2e}); "
               f"time to T plain {surrogate_res['plain_ms']:.1f} ms, rollout "
-              f"{surrogate_res['rollout_ms']:.1f} ms ({surrogate_res['accepted_jumps']} of "
-              f"{surrogate_res['accepted_jumps'] + surrogate_res['fallback_jumps']} jumps accepted), "
+              f"{surrogate_res['rollout_ms']:.1f} ms ({surrogate_res['accepted_jumps']} accepted, "
+              f"{surrogate_res['fallback_jumps']} rejected, {surrogate_res['skipped_jumps']} skipped), "
               f"error {surrogate_res['rollout_rel_l2_vs_fp64']:.2e}",
               file=sys.stderr, flush=True)
 

@@ -477,6 +477,7 @@ class RolloutReport:
     min_check_error: float
     median_check_error: float
     threshold: float
+    skipped: int = 0  # jumps taken by plain SSLBM without trying the surrogate
 
 
 def _rms(t):
@@ -515,12 +516,13 @@ class Rollout:
     (an infinite one runs the surrogate alone, unjudged)."""
 
     def __init__(self, sur: Surrogate, params, h: int, w: int, *, tiles=4, tile=64,
-                 target=1e-3, threshold=None, seed=0):
+                 target=1e-3, threshold=None, seed=0, backoff=True, max_skip=32):
         from .binding import Ensemble, Solver
         torch = _torch()
         self.sur, self.params, self.h, self.w = sur, params, h, w
         self.tiles, self.tile = tiles, tile
         self.target, self.threshold = target, threshold
+        self.backoff, self.max_skip = backoff, max_skip
         self.rng = np.random.default_rng(seed)
         self.solver = Solver(w, h, params, dtype="f32")
         self.scratch = torch.empty((5, h, w), dtype=torch.float32, device="cuda")
@@ -552,30 +554,46 @@ class Rollout:
         return float(torch.max(err))
 
     def run(self, rho0, T: int):
-        """Returns (state at T, RolloutReport); T a multiple of the jump."""
+        """Returns (state at T, RolloutReport); T a multiple of the jump.
+
+        With backoff (the default), a rejected jump makes the next attempt
+        wait: after r rejections in a row the following min(2^r, max_skip)
+        jumps are taken by plain SSLBM in one run, so a surrogate that keeps
+        failing the judge costs a few network passes instead of one per jump."""
         torch = _torch()
         jump = self.sur.jump
         if T % jump:
             raise ValueError(f"T must be a multiple of {jump}")
         state = rho0.clone()
         pred = torch.empty_like(state)
-        accepted = fallbacks = 0
+        accepted = fallbacks = skipped = 0
         errs = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         share = self.threshold if self.threshold is not None else self.target / (T // jump)
         judged = math.isfinite(share)
-        for _ in range(T // jump):
+        jumps, j, streak = T // jump, 0, 0
+        while j < jumps:
             self.sur.predict(state[None], self.planes, out=pred[None])
             err = self._judge(state, pred) if judged else 0.0
             errs.append(err)
             if err <= share:
                 state, pred = pred, state
                 accepted += 1
-            else:
-                self.solver.run(state, jump, self.scratch)
-                fallbacks += 1
+                streak = 0
+                j += 1
+                continue
+            self.solver.run(state, jump, self.scratch)
+            fallbacks += 1
+            j += 1
+            streak += 1
+            if self.backoff:
+                skip = min(2 ** streak, self.max_skip, jumps - j)
+                if skip > 0:
+                    self.solver.run(state, skip * jump, self.scratch)
+                    skipped += skip
+                    j += skip
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
-        return state, RolloutReport(T // jump, accepted, fallbacks, secs, max(errs), min(errs),
-                                    float(np.median(errs)), share)
+        return state, RolloutReport(jumps, accepted, fallbacks, secs, max(errs), min(errs),
+                                    float(np.median(errs)), share, skipped)

@@ -280,9 +280,17 @@ def test_rollout_with_broken_network_falls_back_to_sslbm():
     sur = S.Surrogate(net, 20, [1.0] * 5, [1e-3] * 5)
     prm = inputs.c1_params()
     rho0 = torch.tensor(inputs.c1_workload(64, 64).rho0, dtype=torch.float32).cuda()
-    roll = S.Rollout(sur, prm, 64, 64, tiles=2, tile=16, target=1e-3, seed=2)
+    roll = S.Rollout(sur, prm, 64, 64, tiles=2, tile=16, target=1e-3, seed=2, backoff=False)
     state, rep = roll.run(rho0, 100)
     assert rep.fallbacks == rep.jumps == 5 and rep.accepted == 0
     ref = rho0.clone()
     Solver(64, 64, prm, dtype="f32").run(ref, 100)
+    assert torch.equal(state, ref)
+    # with backoff: attempts at jumps 0, 3 and 8 of 12 (skips of 2 and 4), the
+    # rest plain SSLBM, same bits
+    roll = S.Rollout(sur, prm, 64, 64, tiles=2, tile=16, target=1e-3, seed=2)
+    state, rep = roll.run(rho0, 240)
+    assert (rep.fallbacks, rep.skipped, rep.accepted) == (3, 9, 0)
+    ref = rho0.clone()
+    Solver(64, 64, prm, dtype="f32").run(ref, 240)
     assert torch.equal(state, ref)
