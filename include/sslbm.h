@@ -205,15 +205,17 @@ void sslbm_destroy(sslbm_ctx *c);
  *       and stores the state at steps 0, every, 2 every, ... into
  *       checkpoints, a device buffer of sslbm_checkpoint_count states.
  *   sslbm_adjoint_workspace_bytes: bytes of device workspace the reverse
- *       sweep needs for this context and checkpoint interval (every states
- *       plus 128 bytes per wavefront of the adjoint kernel); 0 for a bad
- *       argument.
+ *       sweep needs for this context and checkpoint interval (about
+ *       every / 2 + 1 states plus 128 bytes per wavefront of the adjoint
+ *       kernels); 0 for a bad argument.
  *   sslbm_adjoint_run: the reverse sweep of a run of nsteps steps recorded
  *       by sslbm_run_checkpointed with the same every and parameters. On
  *       entry lam holds dJ/d rho(T); on return dJ/d rho(0). The run's
  *       parameter gradient is ADDED to grad (device, 9 doubles). Each segment
- *       of `every` steps is recomputed from its checkpoint into the workspace
- *       (never read before it is written; clobbered). Buffers may not overlap.
+ *       of `every` steps is recomputed from its checkpoint, every second state
+ *       into the workspace (never read before it is written; clobbered); the
+ *       reverse steps then go two per pass, the state in between recomputed
+ *       on chip. Buffers may not overlap.
  * Errors: SSLBM_E_ARG (NULL pointer, nsteps < 0, every < 1), SSLBM_E_ALIAS,
  * SSLBM_E_HIP.
  */

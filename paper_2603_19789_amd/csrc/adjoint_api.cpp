@@ -11,6 +11,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <utility>
 
 #include "adjoint_internal.h"
 #include "sslbm.h"
@@ -127,11 +128,18 @@ int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nst
 size_t sslbm_adjoint_workspace_bytes(const sslbm_ctx *c, int every) {
     if (!c || every < 1)
         return 0;
-    // states 1 .. every-1 of a segment, one adjoint field, the partials slots
-    return align256((size_t)every * state_bytes(c)) +
-           align256(partials_bytes(sslbm::adjoint_shape(c->nx, c->ny)));
+    // the states at even offsets 2, 4, .. of a segment, one adjoint field,
+    // the gradient slots of the single-step and the two-step kernels
+    const sslbm::AdjShape s1 = sslbm::adjoint_shape(c->nx, c->ny);
+    const sslbm::AdjShape s2 = sslbm::adjoint2_shape(c->nx, c->ny);
+    const size_t states = (size_t)((every - 1) / 2) + 1;
+    return align256(states * state_bytes(c)) + align256(partials_bytes(s1) + partials_bytes(s2));
 }
 
+// Reverse sweep of one segment of `len` steps from its checkpoint: the
+// states at even offsets are recomputed with two-step passes; the adjoint
+// then runs two steps per pass (the odd state recomputed in registers),
+// with one single step first when len is odd.
 int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, int every,
                       void *lam, double *grad, void *workspace, void *hip_stream) {
     if (!c || !checkpoints || !lam || !grad || !workspace || nsteps < 0 || every < 1)
@@ -149,45 +157,56 @@ int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, i
         return SSLBM_OK;
 
     char *ws = static_cast<char *>(workspace);
-    // segment state i (1 <= i < every) at ws + (i - 1) * bytes; the second
-    // adjoint buffer after them; the partials at the end
-    char *lam_alt = ws + (size_t)(every - 1) * bytes;
-    double *partials = reinterpret_cast<double *>(ws + align256((size_t)every * bytes));
-    const sslbm::AdjShape shape = sslbm::adjoint_shape(c->nx, c->ny);
+    const size_t nstates = (size_t)((every - 1) / 2);  // offsets 2, 4, ..
+    char *lam_alt = ws + nstates * bytes;
+    const sslbm::AdjShape s1 = sslbm::adjoint_shape(c->nx, c->ny);
+    const sslbm::AdjShape s2 = sslbm::adjoint2_shape(c->nx, c->ny);
+    double *part1 = reinterpret_cast<double *>(ws + align256((nstates + 1) * bytes));
+    double *part2 = part1 + s1.slots() * sslbm::ADJ_SLOT;
     const sslbm::GridDesc g = grid_of(c);
     const hipStream_t s = (hipStream_t)hip_stream;
+    int st = hip_status(c, sslbm::launch_zero(part1, (s1.slots() + s2.slots()) * sslbm::ADJ_SLOT,
+                                              s));
+    if (st != SSLBM_OK)
+        return st;
 
     void *cur = lam, *nxt = lam_alt;
-    bool first = true;
     for (long long k = count - 1; k >= 0; --k) {
         const char *cp = static_cast<const char *>(checkpoints) + (size_t)k * bytes;
         const long long len = nsteps - k * every < every ? nsteps - k * every : every;
+        // state at even offset i: the checkpoint, or workspace slot i / 2 - 1
         auto state = [&](long long i) -> const void * {
-            return i == 0 ? (const void *)cp : (const void *)(ws + (size_t)(i - 1) * bytes);
+            return i == 0 ? (const void *)cp : (const void *)(ws + (size_t)(i / 2 - 1) * bytes);
         };
-        for (long long i = 1; i < len; ++i) {
-            const int st = sslbm_step(c, state(i - 1), ws + (size_t)(i - 1) * bytes, hip_stream);
+        for (long long i = 2; i < len; i += 2) {
+            st = sslbm::run_pass(c, state(i - 2), ws + (size_t)(i / 2 - 1) * bytes, 2, s);
             if (st != SSLBM_OK)
                 return st;
         }
-        for (long long i = len - 1; i >= 0; --i) {
-            const int st = hip_status(c, sslbm::launch_adjoint(c->dtype, state(i), cur, nxt, g,
-                                                               c->coef, shape, partials, first, s));
+        long long top = len;
+        if (len % 2) {
+            st = hip_status(c, sslbm::launch_adjoint(c->dtype, state(len - 1), cur, nxt, g, c->coef,
+                                                     s1, part1, false, s));
             if (st != SSLBM_OK)
                 return st;
-            first = false;
-            void *t = cur;
-            cur = nxt;
-            nxt = t;
+            std::swap(cur, nxt);
+            top = len - 1;
+        }
+        for (long long i = top - 2; i >= 0; i -= 2) {
+            st = hip_status(c, sslbm::launch_adjoint2(c->dtype, state(i), cur, nxt, g, c->coef,
+                                                      s2, part2, s));
+            if (st != SSLBM_OK)
+                return st;
+            std::swap(cur, nxt);
         }
     }
     if (cur != lam) {
-        const int st = hip_status(c, hipMemcpyAsync(lam, cur, bytes, hipMemcpyDeviceToDevice, s));
+        st = hip_status(c, hipMemcpyAsync(lam, cur, bytes, hipMemcpyDeviceToDevice, s));
         if (st != SSLBM_OK)
             return st;
     }
-    return hip_status(c, sslbm::launch_adjoint_finish(partials, (int)shape.slots(), factors_of(c),
-                                                      grad, s));
+    return hip_status(c, sslbm::launch_adjoint_finish(part1, (int)(s1.slots() + s2.slots()),
+                                                      factors_of(c), grad, s));
 }
 
 }  // extern "C"

@@ -32,6 +32,14 @@ AdjShape adjoint_shape(int nx, int ny);
 hipError_t launch_adjoint(int dtype, const void *rho, const void *lam, void *out,
                           const GridDesc &g, const StepCoef &k, const AdjShape &s,
                           double *partials, bool first, hipStream_t st);
+// Two reverse steps in one pass (lam(n) from lam(n + 2) and rho(n)), the
+// state of step n + 1 recomputed in registers; the sums of both steps are
+// added to the wavefront slots (zeroed beforehand with launch_zero).
+AdjShape adjoint2_shape(int nx, int ny);
+hipError_t launch_adjoint2(int dtype, const void *rho, const void *lam, void *out,
+                           const GridDesc &g, const StepCoef &k, const AdjShape &s,
+                           double *partials, hipStream_t st);
+hipError_t launch_zero(double *p, long long n, hipStream_t st);
 // grad[0..8] += the scaled sums of all slots.
 hipError_t launch_adjoint_finish(const double *partials, int slots, const AdjFactors &f,
                                  double *grad, hipStream_t st);

@@ -80,14 +80,54 @@ __device__ __forceinline__ void fetch_rho(AdjState<T> &st, const AdjArgs<T> &a, 
             buf_load(row_resource(a.rho + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
 }
 
+// The reverse update of one node: o = A(rho)^T lam at the node, from the
+// adjoint field at the node (lc), its five-point Laplacian (lap) and the
+// state at the node (rho).
+template <typename T, bool DIFFUSE_D>
+__device__ __forceinline__ void adjoint_node(const T lc[5], const T lap[5], const T rho[5],
+                                             const Coef<T> &k, T o[5], T &g, T &de, T &sir) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        o[c] = fma(k.dl[c], lap[c], lc[c]);
+    o[4] = DIFFUSE_D ? fma(k.dl[4], lap[4], lc[4]) : lc[4];
+
+    const T S = rho[0], E = rho[1], I = rho[2], R = rho[3];
+    const T nc = (S + E) + (I + R);
+    const bool live = nc > T(0);
+    const T r = live ? quotient(T(1), nc) : T(0);  // 1 / Nc, or 0 where F = 0
+    sir = (S * I) * r;                             // S I / Nc = F / beta
+    const T qi = k.bdt * (I * r);                  // dt dF/dS + dt F/Nc
+    const T qs = k.bdt * (S * r);                  // dt dF/dI + dt F/Nc
+    const T w = k.bdt * (sir * r);                 // dt F / Nc
+    g = lc[1] - lc[0];                             // F moves S -> E
+    de = lc[2] - lc[1];                            // alpha E moves E -> I
+    o[0] = fma(g, qi - w, o[0]);
+    o[1] = fma(de, k.kE, fma(-g, w, o[1]));
+    o[2] = fma(g, qs - w, o[2]) + (fma(lc[3], k.kR, lc[4] * k.kD) - lc[2] * k.kI);
+    o[3] = fma(-g, w, o[3]);
+}
+
+// The node's contributions to the nine parameter-gradient sums.
+template <typename T>
+__device__ __forceinline__ void adjoint_sums(const T lc[5], const T lap[5], const T rho[5], T g,
+                                             T de, T sir, double acc[ADJ_SUMS]) {
+    acc[0] += (double)(g * sir);
+    acc[1] += (double)(de * rho[1]);
+    acc[2] += (double)(lc[2] * rho[2]);
+    acc[3] += (double)(lc[3] * rho[2]);
+    acc[4] += (double)(lc[4] * rho[2]);
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+        acc[5 + c] += (double)(rho[c] * lap[c]);
+}
+
 // Output row j0 + t - 1 at phase P = t mod 4: lam rows t-2, t-1, t are in
 // slots P-2, P-1, P; rho of the row is in slot P mod 2.
 template <typename T, bool DIFFUSE_D, int P>
 __device__ __forceinline__ void adjoint_row(AdjState<T> &st, const AdjArgs<T> &a, int t,
                                             double acc[ADJ_SUMS]) {
     constexpr int su = (P + 2) % RING, sm = (P + 3) % RING, sd = P % RING, sr = P % 2;
-    const Coef<T> &k = a.k;
-    T lc[5], lap[5], o[5];
+    T lc[5], lap[5], o[5], g, de, sir;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         lc[c] = st.lam[sm][c];
@@ -95,39 +135,13 @@ __device__ __forceinline__ void adjoint_row(AdjState<T> &st, const AdjArgs<T> &a
                      (lane_from_right(lc[c]) + lane_from_left(lc[c]));
         lap[c] = fma(T(-4), lc[c], nb);
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        o[c] = fma(k.dl[c], lap[c], lc[c]);
-    o[4] = DIFFUSE_D ? fma(k.dl[4], lap[4], lc[4]) : lc[4];
-
-    const T S = st.rho[sr][0], E = st.rho[sr][1], I = st.rho[sr][2], R = st.rho[sr][3];
-    const T nc = (S + E) + (I + R);
-    const bool live = nc > T(0);
-    const T r = live ? quotient(T(1), nc) : T(0);  // 1 / Nc, or 0 where F = 0
-    const T sir = (S * I) * r;                     // S I / Nc = F / beta
-    const T qi = k.bdt * (I * r);                  // dt dF/dS + dt F/Nc
-    const T qs = k.bdt * (S * r);                  // dt dF/dI + dt F/Nc
-    const T w = k.bdt * (sir * r);                 // dt F / Nc
-    const T g = lc[1] - lc[0];                     // F moves S -> E
-    const T de = lc[2] - lc[1];                    // alpha E moves E -> I
-    o[0] = fma(g, qi - w, o[0]);
-    o[1] = fma(de, k.kE, fma(-g, w, o[1]));
-    o[2] = fma(g, qs - w, o[2]) + (fma(lc[3], k.kR, lc[4] * k.kD) - lc[2] * k.kI);
-    o[3] = fma(-g, w, o[3]);
-
+    adjoint_node<T, DIFFUSE_D>(lc, lap, st.rho[sr], a.k, o, g, de, sir);
     if (a.out_col) {
         const long long row = (long long)(a.j0 + t - 1) * a.g.nx;
 #pragma unroll
         for (int c = 0; c < 5; ++c)
             buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), a.xo, o[c]);
-        acc[0] += (double)(g * sir);
-        acc[1] += (double)(de * E);
-        acc[2] += (double)(lc[2] * I);
-        acc[3] += (double)(lc[3] * I);
-        acc[4] += (double)(lc[4] * I);
-#pragma unroll
-        for (int c = 0; c < 5; ++c)
-            acc[5 + c] += (double)(st.rho[sr][c] * lap[c]);
+        adjoint_sums(lc, lap, st.rho[sr], g, de, sir, acc);
     }
 }
 
@@ -213,6 +227,183 @@ __global__ __launch_bounds__(BLOCK_THREADS) void adjoint_kernel(
         for (int j = 0; j < ADJ_SUMS; ++j)
             slot[j] = first ? acc[j] : slot[j] + acc[j];
     }
+}
+
+// --------------------------------------------------- two steps per pass
+// lam(n) from lam(n + 2) and the state rho(n): the state of step n + 1 is
+// recomputed in registers by one forward level (the SSLBM update of the
+// pass kernels), the reverse level n + 1 follows it one row behind and the
+// reverse level n one row behind that. Per output row the wavefront reads
+// one row of rho(n) and one of lam(n + 2) and writes one of lam(n): the
+// bytes of one single step for two steps of work. A strip has two halo
+// columns per side (60 output columns); a chunk reads two halo rows above
+// and below.
+constexpr int F_HX = 2, F_WU = 64 - 2 * F_HX;
+
+template <typename T>
+struct Fused2State {
+    T rho0[RING][5];  // rho(n) rows, ring slot = row mod 4
+    T lam2[RING][5];  // lam(n + 2) rows
+    T lam1[RING][5];  // lam(n + 1) rows (computed)
+};
+
+template <typename T>
+struct Fused2Args {
+    const T *__restrict__ rho;
+    const T *__restrict__ lam;
+    T *__restrict__ out;
+    GridDesc g;
+    Coef<T> k;
+    unsigned xoff, xo;
+    bool out_col;
+    int j0;    // first row read: y0 - 2
+    int tend;  // rows read: y1 - y0 + 4
+};
+
+template <typename T, int SL>
+__device__ __forceinline__ void fused_fetch(Fused2State<T> &st, const Fused2Args<T> &a, int t) {
+    const long long row = (long long)map_index(a.j0 + t, a.g.ny, a.g.bc) * a.g.nx;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        st.rho0[SL][c] =
+            buf_load(row_resource(a.rho + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
+        st.lam2[SL][c] =
+            buf_load(row_resource(a.lam + (c * a.g.plane + row), a.g.nx), a.xoff, T(0));
+    }
+}
+
+// Row t at phase P = t mod 4 (rows j0 + t - 2 .. j0 + t are in slots
+// P + 2, P + 3, P): forward level and reverse level n + 1 for row t - 1,
+// then (OUT) reverse level n for row t - 2.
+template <typename T, bool DIFFUSE_D, int P, bool OUT>
+__device__ __forceinline__ void fused_row(Fused2State<T> &st, const Fused2Args<T> &a, int t,
+                                          double acc[ADJ_SUMS]) {
+    constexpr int su = (P + 2) % RING, sm = (P + 3) % RING, sd = P % RING;
+    fused_fetch<T, (P + 1) % RING>(st, a, t + 1);
+    // rho(n + 1) at row t - 1
+    T cen[5], nb[5], r1[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        cen[c] = st.rho0[sm][c];
+        nb[c] = (c < 4 || DIFFUSE_D) ? (st.rho0[su][c] + st.rho0[sd][c]) +
+                                           (lane_from_right(cen[c]) + lane_from_left(cen[c]))
+                                     : T(0);
+    }
+    seird_update<T, DIFFUSE_D>(cen, nb, a.k, r1);
+    // lam(n + 1) at row t - 1
+    {
+        T lc[5], lap[5], o[5], g, de, sir;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            lc[c] = st.lam2[sm][c];
+            const T n2 = (st.lam2[su][c] + st.lam2[sd][c]) +
+                         (lane_from_right(lc[c]) + lane_from_left(lc[c]));
+            lap[c] = fma(T(-4), lc[c], n2);
+        }
+        adjoint_node<T, DIFFUSE_D>(lc, lap, r1, a.k, o, g, de, sir);
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+            st.lam1[sm][c] = o[c];
+        // rows y0 .. y1 - 1 only: the halo rows belong to the neighbouring chunks
+        if (a.out_col && t >= 3 && t < a.tend - 1)
+            adjoint_sums(lc, lap, r1, g, de, sir, acc);
+    }
+    if constexpr (OUT) {
+        // lam(n) at row t - 2, from lam(n + 1) rows t - 3 .. t - 1
+        constexpr int lu = (P + 1) % RING, lm = (P + 2) % RING, ld = (P + 3) % RING;
+        T lc[5], lap[5], o[5], g, de, sir;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            lc[c] = st.lam1[lm][c];
+            const T n1 = (st.lam1[lu][c] + st.lam1[ld][c]) +
+                         (lane_from_right(lc[c]) + lane_from_left(lc[c]));
+            lap[c] = fma(T(-4), lc[c], n1);
+        }
+        adjoint_node<T, DIFFUSE_D>(lc, lap, st.rho0[lm], a.k, o, g, de, sir);
+        if (a.out_col) {
+            const long long row = (long long)(a.j0 + t - 2) * a.g.nx;
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), a.xo, o[c]);
+            adjoint_sums(lc, lap, st.rho0[lm], g, de, sir, acc);
+        }
+    }
+}
+
+template <typename T, bool DIFFUSE_D>
+__global__ __launch_bounds__(BLOCK_THREADS) void adjoint2_kernel(
+    const T *__restrict__ rho, const T *__restrict__ lam, T *__restrict__ out, GridDesc g,
+    Coef<T> k, int strips, int chunks, int rows, double *__restrict__ partials) {
+    const int wave = __builtin_amdgcn_readfirstlane(
+        xcd_tile(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    if (wave >= strips * chunks)
+        return;  // whole wavefront leaves together
+    const int strip = wave / chunks, chunk = wave - strip * chunks;
+    const int y0 = chunk * rows;
+    const int y1 = min(y0 + rows, g.ny);
+    const int lane = threadIdx.x & 63;
+    const int xl = strip * F_WU - F_HX + lane;
+
+    Fused2Args<T> a;
+    a.rho = rho;
+    a.lam = lam;
+    a.out = out;
+    a.g = g;
+    a.k = k;
+    a.xoff = (unsigned)map_index(xl, g.nx, g.bc) * (unsigned)sizeof(T);
+    a.xo = (unsigned)xl * (unsigned)sizeof(T);
+    a.out_col = lane >= F_HX && lane < F_HX + F_WU && xl < g.nx;
+    a.j0 = y0 - 2;
+    a.tend = y1 - y0 + 4;
+
+    Fused2State<T> st;
+#pragma unroll
+    for (int s = 0; s < RING; ++s)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            st.rho0[s][c] = T(0);
+            st.lam2[s][c] = T(0);
+            st.lam1[s][c] = T(0);
+        }
+    double acc[ADJ_SUMS];
+#pragma unroll
+    for (int j = 0; j < ADJ_SUMS; ++j)
+        acc[j] = 0.0;
+
+    fused_fetch<T, 0>(st, a, 0);
+    fused_fetch<T, 1>(st, a, 1);
+    fused_fetch<T, 2>(st, a, 2);
+    fused_row<T, DIFFUSE_D, 2, false>(st, a, 2, acc);
+    fused_row<T, DIFFUSE_D, 3, false>(st, a, 3, acc);
+    int t = 4;
+    for (; t + RING <= a.tend; t += RING) {
+        fused_row<T, DIFFUSE_D, 0, true>(st, a, t, acc);
+        fused_row<T, DIFFUSE_D, 1, true>(st, a, t + 1, acc);
+        fused_row<T, DIFFUSE_D, 2, true>(st, a, t + 2, acc);
+        fused_row<T, DIFFUSE_D, 3, true>(st, a, t + 3, acc);
+    }
+    if (t < a.tend)
+        fused_row<T, DIFFUSE_D, 0, true>(st, a, t, acc);
+    if (t + 1 < a.tend)
+        fused_row<T, DIFFUSE_D, 1, true>(st, a, t + 1, acc);
+    if (t + 2 < a.tend)
+        fused_row<T, DIFFUSE_D, 2, true>(st, a, t + 2, acc);
+
+#pragma unroll
+    for (int j = 0; j < ADJ_SUMS; ++j)
+        acc[j] = wave_sum(acc[j]);
+    if (lane == 0) {
+        double *slot = partials + (long long)wave * ADJ_SLOT;
+#pragma unroll
+        for (int j = 0; j < ADJ_SUMS; ++j)
+            slot[j] += acc[j];
+    }
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(double *__restrict__ p, long long n) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e < n)
+        p[e] = 0.0;
 }
 
 // Sum of the slots in a fixed order (slot-strided per thread, then a fixed
@@ -305,6 +496,55 @@ hipError_t launch_adjoint(int dtype, const void *rho, const void *lam, void *out
                            : launch_t<float, false>(rho, lam, out, g, k, s, partials, first, st);
     return k.diffuse_d ? launch_t<double, true>(rho, lam, out, g, k, s, partials, first, st)
                        : launch_t<double, false>(rho, lam, out, g, k, s, partials, first, st);
+}
+
+AdjShape adjoint2_shape(int nx, int ny) {
+    AdjShape s;
+    s.strips = (nx + F_WU - 1) / F_WU;
+    // as adjoint_shape: one workgroup of four wavefronts per CU, chunks of
+    // at least 8 rows
+    const long long target = 256 * WAVES_PER_BLOCK;
+    long long chunks = target / s.strips;
+    if (chunks < 1)
+        chunks = 1;
+    long long rows = (ny + chunks - 1) / chunks;
+    if (rows < 8)
+        rows = 8;
+    if (rows > ny)
+        rows = ny;
+    s.rows = (int)rows;
+    s.chunks = (int)((ny + rows - 1) / rows);
+    return s;
+}
+
+template <typename T, bool DD>
+static hipError_t launch2_t(const void *rho, const void *lam, void *out, const GridDesc &g,
+                            const StepCoef &k, const AdjShape &s, double *partials,
+                            hipStream_t st) {
+    const int waves = s.strips * s.chunks;
+    const int blocks = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    hipLaunchKernelGGL((adjoint2_kernel<T, DD>), dim3((unsigned)blocks), dim3(BLOCK_THREADS), 0,
+                       st, static_cast<const T *>(rho), static_cast<const T *>(lam),
+                       static_cast<T *>(out), g, cast_coef<T>(k), s.strips, s.chunks, s.rows,
+                       partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint2(int dtype, const void *rho, const void *lam, void *out,
+                           const GridDesc &g, const StepCoef &k, const AdjShape &s,
+                           double *partials, hipStream_t st) {
+    if (dtype == SSLBM_F32)
+        return k.diffuse_d ? launch2_t<float, true>(rho, lam, out, g, k, s, partials, st)
+                           : launch2_t<float, false>(rho, lam, out, g, k, s, partials, st);
+    return k.diffuse_d ? launch2_t<double, true>(rho, lam, out, g, k, s, partials, st)
+                       : launch2_t<double, false>(rho, lam, out, g, k, s, partials, st);
+}
+
+hipError_t launch_zero(double *p, long long n, hipStream_t st) {
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_finish(const double *partials, int slots, const AdjFactors &f,

@@ -101,6 +101,12 @@ sslbm::MarchShape shape_for(const sslbm_ctx *c, int k, const void *in, const voi
 
 namespace sslbm {
 
+// One pass of k steps, in -> out, with the context's pass shape.
+int run_pass(sslbm_ctx *c, const void *in, void *out, int k, hipStream_t s) {
+    return hip_status(c, launch_march(c->dtype, in, out, grid_of(c), c->coef, k,
+                                      shape_for(c, k, in, out), s));
+}
+
 static bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
 // Validation of sslbm_params and the derived per-step constants.

@@ -43,6 +43,10 @@ int derive_coef(const sslbm_params *p, StepCoef *k);
 // whenever nsteps >= 2 (so that ping-pong buffers end where they started).
 std::vector<int> plan_passes(long long nsteps, int K);
 
+// One pass of k steps (1 <= k <= the register limit), in -> out, with the
+// context's pass shape (SSLBM status code).
+int run_pass(sslbm_ctx *c, const void *in, void *out, int k, hipStream_t s);
+
 // ---- launchers (sslbm_kernels.hip) --------------------------------------
 // K steps in one pass: in -> out (no overlap). K in 1..SSLBM_MAX_BLOCKING.
 hipError_t launch_march(int dtype, const void *in, void *out, const GridDesc &g,
