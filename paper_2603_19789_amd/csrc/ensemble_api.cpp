@@ -76,7 +76,7 @@ std::vector<sslbm::EnsTile> make_tiles(const sslbm_ensemble *e, int k, int H, in
     for (int i = 0; i < e->count; ++i)
         for (int y0 = 0; y0 < e->ny[i]; y0 += H)
             for (int x0 = 0; x0 < e->nx[i]; x0 += w)
-                t.push_back({i, x0, y0, std::min(y0 + H, e->ny[i])});
+                t.push_back({i, x0, y0, std::min(y0 + H, e->ny[i]), (y0 / H) & 1});
     return t;
 }
 

@@ -11,9 +11,9 @@
 namespace sslbm {
 
 // One wavefront's work in an ensemble pass: instance, first output column
-// of its strip, output rows [y0, y1).
+// of its strip, output rows [y0, y1), marching up (odd chunks) or down.
 struct EnsTile {
-    int inst, x0, y0, y1;
+    int inst, x0, y0, y1, up;
 };
 
 // One pass of K steps over every tile: in -> out (whole ensemble buffers).

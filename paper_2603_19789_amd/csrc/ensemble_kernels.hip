@@ -33,7 +33,8 @@ void ensemble_march_kernel(const T *__restrict__ in, T *__restrict__ out,
     g.ny = m.ny;
     g.plane = (long long)m.nx * m.ny;
     g.bc = bc;
-    march_tile<T, K, DIFFUSE_D, V>(in + m.offset, out + m.offset, g, m.k, t.x0, t.y0, t.y1);
+    march_tile<T, K, DIFFUSE_D, V>(in + m.offset, out + m.offset, g, m.k, t.x0, t.y0, t.y1,
+                                   t.up != 0);
 }
 
 template <typename T, int K, bool DD, int V>

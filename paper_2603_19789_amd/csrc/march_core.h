@@ -144,18 +144,18 @@ struct MarchArgs {
     bool swap;         // V = 2: the lane's pair lies reversed in memory (mirror image)
     int xl;            // logical column of this lane's first column
     bool out_col[V];   // the column is an output column of the strip
-    int y0;            // first output row of the chunk
-    int j0;            // first level-0 row (y0 - K)
+    int j0;            // first level-0 row (y0 - K marching down, y1 - 1 + K marching up)
+    int dir;           // +1: rows in increasing order, -1: decreasing
     int tend;          // number of level-0 rows
 };
 
 // Level-0 row j0 + t into its ring slot SL. Rows past the chunk are still
 // in range (the index map folds every integer into the grid), so the fetch
 // needs no guard.
-template <typename T, int K, int V, int SL>
+template <typename T, int K, int V, bool SW, int SL>
 __device__ __forceinline__ void fetch_row(MarchState<T, K, V> &st, const MarchArgs<T, V> &a,
                                           int t) {
-    const long long row = (long long)map_index(a.j0 + t, a.g.ny, a.g.bc) * a.g.nx;
+    const long long row = (long long)map_index(a.j0 + a.dir * t, a.g.ny, a.g.bc) * a.g.nx;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         const __amdgpu_buffer_rsrc_t r = row_resource(a.in + (c * a.g.plane + row), a.g.nx);
@@ -163,10 +163,16 @@ __device__ __forceinline__ void fetch_row(MarchState<T, K, V> &st, const MarchAr
             st.ring[0][SL][c][0] = buf_load(r, a.xoff[0], T(0));
         } else {
             // the pair is one aligned vector in memory, possibly mirrored
+            // (only strips with a lane across a no-flux wall take the select)
             T lo, hi;
             buf_load_pair(r, a.xoff[0], lo, hi);
-            st.ring[0][SL][c][0] = a.swap ? hi : lo;
-            st.ring[0][SL][c][1] = a.swap ? lo : hi;
+            if constexpr (SW) {
+                st.ring[0][SL][c][0] = a.swap ? hi : lo;
+                st.ring[0][SL][c][1] = a.swap ? lo : hi;
+            } else {
+                st.ring[0][SL][c][0] = lo;
+                st.ring[0][SL][c][1] = hi;
+            }
         }
     }
 }
@@ -221,7 +227,7 @@ __device__ __forceinline__ void level(MarchState<T, K, V> &st, const MarchArgs<T
             for (int v = 0; v < V; ++v)
                 st.ring[L][s_mid][c][v] = res[c][v];
     } else {
-        const long long row = (long long)(a.j0 + t - K) * a.g.nx;
+        const long long row = (long long)(a.j0 + a.dir * (t - K)) * a.g.nx;
         const unsigned xo = (unsigned)a.xl * (unsigned)sizeof(T);
         if constexpr (V == 1) {
             if (a.out_col[0]) {
@@ -253,31 +259,75 @@ __device__ __forceinline__ void levels(MarchState<T, K, V> &st, const MarchArgs<
 
 // Warm-up rows t = TC < 2K (compile time): fetch row t + 1, then the levels
 // that already have three rows below them (l <= t/2). Nothing is stored yet.
-template <typename T, int K, bool DIFFUSE_D, int V, int TC>
+template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int TC>
 __device__ __forceinline__ void warm_up(MarchState<T, K, V> &st, const MarchArgs<T, V> &a) {
     if constexpr (TC < 2 * K) {
-        fetch_row<T, K, V, (TC + 1) % RING>(st, a, TC + 1);
+        fetch_row<T, K, V, SW, (TC + 1) % RING>(st, a, TC + 1);
         levels<T, K, DIFFUSE_D, V, TC % RING, 1, TC / 2>(st, a, TC);
-        warm_up<T, K, DIFFUSE_D, V, TC + 1>(st, a);
+        warm_up<T, K, DIFFUSE_D, V, SW, TC + 1>(st, a);
     }
 }
 
 // Steady-state row t (phase P): fetch row t + 1, all K levels, one output row.
 // Straight-line code, so the memory counters stay exact and the wait for row
 // t's data lets the row t + 1 loads stay in flight.
-template <typename T, int K, bool DIFFUSE_D, int V, int P>
+template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int P>
 __device__ __forceinline__ void steady_row(MarchState<T, K, V> &st, const MarchArgs<T, V> &a,
                                            int t) {
-    fetch_row<T, K, V, (P + 1) % RING>(st, a, t + 1);
+    fetch_row<T, K, V, SW, (P + 1) % RING>(st, a, t + 1);
     levels<T, K, DIFFUSE_D, V, P, 1, K>(st, a, t);
 }
 
+// The rows of one wavefront's chunk: fill the levels, then one output row
+// per level-0 row. SW: some lane's column pair is mirrored in memory.
+template <typename T, int K, bool DIFFUSE_D, int V, bool SW>
+__device__ __forceinline__ void march_rows(const MarchArgs<T, V> &a) {
+    MarchState<T, K, V> st;
+#pragma unroll
+    for (int l = 0; l < K; ++l)
+#pragma unroll
+        for (int r = 0; r < RING; ++r)
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    st.ring[l][r][c][v] = T(0);
+
+    // rows 0 .. 2K-1: fill the levels; from row 2K on every row yields output
+    fetch_row<T, K, V, SW, 0>(st, a, 0);
+    warm_up<T, K, DIFFUSE_D, V, SW, 0>(st, a);
+    constexpr int P0 = (2 * K) % RING;
+    int t = 2 * K;
+    for (; t + RING <= a.tend; t += RING) {
+        steady_row<T, K, DIFFUSE_D, V, SW, P0>(st, a, t);
+        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 1) % RING>(st, a, t + 1);
+        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 2) % RING>(st, a, t + 2);
+        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 3) % RING>(st, a, t + 3);
+    }
+    // last partial group of rows (only when the chunk height is not a multiple
+    // of 4), nested so that no ring slot's older value stays live through the
+    // loop for a tail row that might read it
+    if (t < a.tend) {
+        steady_row<T, K, DIFFUSE_D, V, SW, P0>(st, a, t);
+        if (t + 1 < a.tend) {
+            steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 1) % RING>(st, a, t + 1);
+            if (t + 2 < a.tend)
+                steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 2) % RING>(st, a, t + 2);
+        }
+    }
+}
+
 // One wavefront: the strip whose first output column is x0, output rows
-// [y0, y1), of the grid g with coefficients k; K steps from in to out.
+// [y0, y1), of the grid g with coefficients k; K steps from in to out,
+// marching down the rows (up = false) or up. The stencil is symmetric in y,
+// so both directions give the same bits. Chunks that meet at a row boundary
+// march towards it (or away from it) together, so the K halo rows on each
+// side of it are read by both wavefronts at about the same time and the
+// second read is served from cache rather than HBM.
 template <typename T, int K, bool DIFFUSE_D, int V>
 __device__ __forceinline__ void march_tile(const T *__restrict__ in, T *__restrict__ out,
                                            const GridDesc &g, const Coef<T> &k, int x0, int y0,
-                                           int y1) {
+                                           int y1, bool up) {
     using Geo = Strip<K, V>;
     const int lane = threadIdx.x & 63;
     MarchArgs<T, V> a;
@@ -285,8 +335,8 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ in, T *__restri
     a.out = out;
     a.g = g;
     a.k = k;
-    a.y0 = y0;
-    a.j0 = y0 - K;
+    a.dir = up ? -1 : 1;
+    a.j0 = up ? y1 - 1 + K : y0 - K;
     a.tend = y1 - y0 + 2 * K;
     a.xl = x0 - Geo::HX + lane * V;
 #pragma unroll
@@ -304,42 +354,24 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ in, T *__restri
             a.xoff[0] = a.xoff[1];
     }
 
-    MarchState<T, K, V> st;
-#pragma unroll
-    for (int l = 0; l < K; ++l)
-#pragma unroll
-        for (int r = 0; r < RING; ++r)
-#pragma unroll
-            for (int c = 0; c < 5; ++c)
-#pragma unroll
-                for (int v = 0; v < V; ++v)
-                    st.ring[l][r][c][v] = T(0);
-
-    // rows 0 .. 2K-1: fill the levels; from row 2K on every row yields output
-    fetch_row<T, K, V, 0>(st, a, 0);
-    warm_up<T, K, DIFFUSE_D, V, 0>(st, a);
-    constexpr int P0 = (2 * K) % RING;
-    int t = 2 * K;
-    for (; t + RING <= a.tend; t += RING) {
-        steady_row<T, K, DIFFUSE_D, V, P0>(st, a, t);
-        steady_row<T, K, DIFFUSE_D, V, (P0 + 1) % RING>(st, a, t + 1);
-        steady_row<T, K, DIFFUSE_D, V, (P0 + 2) % RING>(st, a, t + 2);
-        steady_row<T, K, DIFFUSE_D, V, (P0 + 3) % RING>(st, a, t + 3);
+    // Every strip but the few with a lane across a no-flux wall runs the
+    // loop without the pair select (a wavefront-uniform branch).
+    if constexpr (V == 2) {
+        if (__builtin_amdgcn_ballot_w64(a.swap) != 0) {
+            march_rows<T, K, DIFFUSE_D, V, true>(a);
+            return;
+        }
     }
-    // last partial group of rows (only when the chunk height is not a multiple of 4)
-    if (t < a.tend)
-        steady_row<T, K, DIFFUSE_D, V, P0>(st, a, t);
-    if (t + 1 < a.tend)
-        steady_row<T, K, DIFFUSE_D, V, (P0 + 1) % RING>(st, a, t + 1);
-    if (t + 2 < a.tend)
-        steady_row<T, K, DIFFUSE_D, V, (P0 + 2) % RING>(st, a, t + 2);
+    march_rows<T, K, DIFFUSE_D, V, false>(a);
 }
 
 template <typename T>
 inline Coef<T> cast_coef(const StepCoef &s) {
     Coef<T> k;
-    for (int c = 0; c < 5; ++c)
+    for (int c = 0; c < 5; ++c) {
         k.dl[c] = (T)s.dl[c];
+        k.cl[c] = (T)(1.0 - 4.0 * s.dl[c]);
+    }
     k.bdt = (T)s.bdt;
     k.kE = (T)s.kE;
     k.kI = (T)s.kI;

@@ -23,7 +23,7 @@ void sslbm_march_kernel(
     const int chunk = wave / strips;
     const int y0 = chunk * rows_per_wave;
     march_tile<T, K, DIFFUSE_D, V>(in, out, g, k, strip * Strip<K, V>::WU, y0,
-                                   min(y0 + rows_per_wave, g.ny));
+                                   min(y0 + rows_per_wave, g.ny), (chunk & 1) != 0);
 }
 
 template <typename T, int K, bool DD, int V>
