@@ -275,7 +275,7 @@ void sslbm_ensemble_destroy(sslbm_ensemble *e);
 
 /*
  * Generic compartmental models, Eq. (generic_pde): d_t C = Psi^C + d^C lap C
- * for 1..SSLBM_MAX_COMPARTMENTS compartments, one SSLBM step per launch
+ * for 1..SSLBM_MAX_COMPARTMENTS compartments, SSLBM steps
  * (Eq. (sslbm_final_clean)) on the D2Q5 lattice (lattice = 5) or the D2Q9
  * lattice (lattice = 9: rest weight 4/9, axes 1/9, diagonals 1/36; its
  * symbol is 4/9 + (2/9)(cos kx + cos ky) + (1/9) cos kx cos ky, isotropic
@@ -301,10 +301,18 @@ void sslbm_ensemble_destroy(sslbm_ensemble *e);
  *   sslbm_model_step / sslbm_model_run: as sslbm_step / sslbm_run. The
  *       first call uploads a small transition table to the current device
  *       (synchronous); the model then stays on that device
- *       (SSLBM_E_UNSUPPORTED elsewhere).
+ *       (SSLBM_E_UNSUPPORTED elsewhere). sslbm_model_step takes one step;
+ *       sslbm_model_run takes up to the model's blocking depth of steps per
+ *       pass over device memory.
+ *   sslbm_model_set_blocking: steps per pass of sslbm_model_run, 1 ..
+ *       SSLBM_MODEL_MAX_BLOCKING, or 0 for the automatic choice (else
+ *       SSLBM_E_ARG). Results are bit for bit the same for every depth.
+ *   sslbm_model_get_blocking: the depth sslbm_model_run uses (automatic
+ *       choice resolved) into *steps_per_pass.
  */
 #define SSLBM_MAX_COMPARTMENTS 8
 #define SSLBM_MAX_TRANSITIONS 16
+#define SSLBM_MODEL_MAX_BLOCKING 4
 typedef struct {
     int src, dst, catalyst, frequency;
     double rate;
@@ -315,6 +323,8 @@ int sslbm_model_create(sslbm_model **out, int nx, int ny, int dtype, int bc, int
                        double dt, int ntransitions, const sslbm_transition *transitions);
 int sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hip_stream);
 int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps, void *hip_stream);
+int sslbm_model_set_blocking(sslbm_model *m, int steps_per_pass);
+int sslbm_model_get_blocking(const sslbm_model *m, int *steps_per_pass);
 int sslbm_model_last_hip_error(const sslbm_model *m);
 void sslbm_model_destroy(sslbm_model *m);
 

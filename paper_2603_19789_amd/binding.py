@@ -25,6 +25,7 @@ F32, F64 = 0, 1
 GRAD_COUNT = 9  # dJ/d(beta, alpha, gamma, phi, d[0..4])
 PERIODIC, NOFLUX = 0, 1
 MAX_BLOCKING = 8
+MODEL_MAX_BLOCKING = 4
 _BC = {"periodic": PERIODIC, "noflux": NOFLUX, PERIODIC: PERIODIC, NOFLUX: NOFLUX}
 
 
@@ -110,6 +111,8 @@ def library() -> ctypes.CDLL:
                                    ctypes.POINTER(Transition)],
             "sslbm_model_step": [vp, vp, vp, vp],
             "sslbm_model_run": [vp, vp, vp, ll, vp],
+            "sslbm_model_set_blocking": [vp, i],
+            "sslbm_model_get_blocking": [vp, ctypes.POINTER(i)],
             "sslbm_model_last_hip_error": [vp],
             # surrogate.h
             "sur_conv3x3_forward": [vp, i, i, i, i, i, vp, vp, vp, i, i, i, f, vp],
@@ -573,6 +576,19 @@ class Model:
             raise ValueError(f"{name} must be a contiguous {self.dtype} GPU tensor of shape "
                              f"{self.shape}")
         return ctypes.c_void_p(t.data_ptr())
+
+    def set_blocking(self, steps_per_pass: int = 0):
+        """Steps per pass of run() (0 = automatic); changes speed, never results."""
+        self._check(self.lib.sslbm_model_set_blocking(self.handle, int(steps_per_pass)),
+                    "sslbm_model_set_blocking")
+
+    @property
+    def blocking(self) -> int:
+        """Steps per pass run() uses, automatic choice resolved."""
+        k = ctypes.c_int()
+        self._check(self.lib.sslbm_model_get_blocking(self.handle, ctypes.byref(k)),
+                    "sslbm_model_get_blocking")
+        return k.value
 
     def step(self, rho_in, rho_out=None, stream=None):
         torch = _torch()

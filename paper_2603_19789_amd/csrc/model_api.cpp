@@ -16,6 +16,7 @@ struct sslbm_model {
     int last_hip = 0;
     void *table = nullptr;  // device transition table, uploaded on first use
     int table_device = -1;
+    int blocking = 0;  // steps per pass of sslbm_model_run (0: automatic)
 };
 
 namespace {
@@ -32,6 +33,15 @@ int hip_status(sslbm_model *m, hipError_t e) {
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
     return x < y + nb && y < x + na;
+}
+
+// Steps per pass of sslbm_model_run: the caller's choice, else the deepest
+// pass the kernels are built for. Measured at 4096 x 4096 with the
+// six-compartment model: FP32 71 / 113 / 124 / 128 GLUPS (D2Q5) and
+// 73 / 104 / 113 / 115 (D2Q9) at 1 / 2 / 3 / 4 steps per pass; FP64 peaks
+// at 3 steps (77 and 70 GLUPS), with 4 within 1%.
+int resolved_blocking(const sslbm_model *m) {
+    return m->blocking > 0 ? m->blocking : sslbm::MODEL_MAX_K;
 }
 
 size_t state_bytes(const sslbm_model *m) {
@@ -147,7 +157,7 @@ int sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hi
     if (st != SSLBM_OK)
         return st;
     return hip_status(m, sslbm::launch_model(m->dtype, m->lattice, rho_in, rho_out, grid_of(m),
-                                             m->coef, m->table, (hipStream_t)hip_stream));
+                                             m->coef, m->table, 1, (hipStream_t)hip_stream));
 }
 
 int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
@@ -163,18 +173,35 @@ int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
     if (tst != SSLBM_OK)
         return tst;
     const hipStream_t s = (hipStream_t)hip_stream;
+    const int K = resolved_blocking(m);
     void *src = rho, *dst = scratch;
-    for (long long n = 0; n < nsteps; ++n) {
+    for (long long n = 0; n < nsteps;) {
+        const int k = nsteps - n < K ? (int)(nsteps - n) : K;
         const int st = hip_status(m, sslbm::launch_model(m->dtype, m->lattice, src, dst,
-                                                         grid_of(m), m->coef, m->table, s));
+                                                         grid_of(m), m->coef, m->table, k, s));
         if (st != SSLBM_OK)
             return st;
         void *tmp = src;
         src = dst;
         dst = tmp;
+        n += k;
     }
     if (src != rho)
         return hip_status(m, hipMemcpyAsync(rho, src, bytes, hipMemcpyDeviceToDevice, s));
+    return SSLBM_OK;
+}
+
+int sslbm_model_set_blocking(sslbm_model *m, int steps_per_pass) {
+    if (!m || steps_per_pass < 0 || steps_per_pass > SSLBM_MODEL_MAX_BLOCKING)
+        return SSLBM_E_ARG;
+    m->blocking = steps_per_pass;
+    return SSLBM_OK;
+}
+
+int sslbm_model_get_blocking(const sslbm_model *m, int *steps_per_pass) {
+    if (!m || !steps_per_pass)
+        return SSLBM_E_ARG;
+    *steps_per_pass = resolved_blocking(m);
     return SSLBM_OK;
 }
 

@@ -40,9 +40,22 @@ struct ModelShape {
     int strips, chunks, rows;
 };
 
-ModelShape model_shape(int nx, int ny);
+// Steps per pass the kernels are built for (1..MODEL_MAX_K).
+constexpr int MODEL_MAX_K = SSLBM_MODEL_MAX_BLOCKING;
+
+ModelShape model_shape(int nx, int ny, int K);
+// One pass of K steps, in -> out.
 hipError_t launch_model(int dtype, int lattice, const void *in, void *out, const GridDesc &g,
-                        const ModelCoefHost &h, const void *table, hipStream_t s);
+                        const ModelCoefHost &h, const void *table, int K, hipStream_t s);
+// The kernels of one arithmetic type and lattice (one translation unit each).
+hipError_t launch_model_f32_d2q5(const void *in, void *out, const GridDesc &g,
+                                 const ModelCoefHost &h, const void *table, int K, hipStream_t s);
+hipError_t launch_model_f32_d2q9(const void *in, void *out, const GridDesc &g,
+                                 const ModelCoefHost &h, const void *table, int K, hipStream_t s);
+hipError_t launch_model_f64_d2q5(const void *in, void *out, const GridDesc &g,
+                                 const ModelCoefHost &h, const void *table, int K, hipStream_t s);
+hipError_t launch_model_f64_d2q9(const void *in, void *out, const GridDesc &g,
+                                 const ModelCoefHost &h, const void *table, int K, hipStream_t s);
 // The device table (model_table_bytes) written into host memory dst.
 void model_table(const ModelCoefHost &h, int dtype, void *dst);
 

@@ -3,6 +3,7 @@ declares, and rejects bad arguments on the host before any HIP call."""
 import ctypes
 import math
 import re
+from pathlib import Path
 
 import pytest
 
@@ -282,3 +283,31 @@ def test_generic_model_host_checks(lib):
     assert lib.sslbm_model_create(None, 8, 8, 0, 0, 5, 1, d, counted, 1.0, 0.01, 0,
                                   None) == binding.E_ARG
     assert lib.sslbm_model_step(None, h, h, None) == binding.E_ARG
+
+
+def test_generic_model_blocking_host(lib):
+    """Steps per pass of sslbm_model_run: 0 (automatic) .. the maximum, set
+    and read back on the host."""
+    from paper_2603_19789_amd.binding import Transition
+    header = (Path(__file__).resolve().parents[1] / "include" / "sslbm.h").read_text()
+    assert f"#define SSLBM_MODEL_MAX_BLOCKING {binding.MODEL_MAX_BLOCKING}\n" in header
+    d = (ctypes.c_double * 2)(0.1, 0.1)
+    counted = (ctypes.c_int * 2)(1, 1)
+    tr = (Transition * 1)(Transition(0, 1, -1, 0, 0.5))
+    h = ctypes.c_void_p()
+    assert lib.sslbm_model_create(ctypes.byref(h), 16, 8, binding.F32, binding.PERIODIC, 5, 2,
+                                  d, counted, 1.0, 0.01, 1, tr) == binding.OK
+    try:
+        k = ctypes.c_int()
+        assert lib.sslbm_model_get_blocking(h, ctypes.byref(k)) == binding.OK
+        assert k.value == binding.MODEL_MAX_BLOCKING  # automatic: the deepest pass
+        for want in range(1, binding.MODEL_MAX_BLOCKING + 1):
+            assert lib.sslbm_model_set_blocking(h, want) == binding.OK
+            assert lib.sslbm_model_get_blocking(h, ctypes.byref(k)) == binding.OK
+            assert k.value == want
+        assert lib.sslbm_model_set_blocking(h, binding.MODEL_MAX_BLOCKING + 1) == binding.E_ARG
+        assert lib.sslbm_model_set_blocking(h, -1) == binding.E_ARG
+        assert lib.sslbm_model_get_blocking(h, None) == binding.E_ARG
+        assert lib.sslbm_model_set_blocking(None, 1) == binding.E_ARG
+    finally:
+        lib.sslbm_model_destroy(h)

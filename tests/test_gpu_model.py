@@ -46,6 +46,31 @@ def test_seirvd_steps(orc, nx, ny, lattice, bc, dtype):
     assert err <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("lattice", [5, 9])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (63, 17), (130, 45), (201, 67)])
+def test_blocking_is_bitwise_invisible(nx, ny, lattice, bc, dtype):
+    """Every number of steps per pass (halo columns, warm-up rows, chunks
+    marching up and down) gives the bits of one step per pass."""
+    print(f"model blocking {nx}x{ny} D2Q{lattice} {bc} {dtype}", flush=True)
+    m = inputs.seirvd_model(lattice=lattice, dt=0.05)
+    rng = np.random.default_rng(nx * 5 + ny)
+    rho0 = rng.uniform(0.0, 0.3, size=(6, ny, nx))
+    rho0[0] += 0.5
+    g = Model(nx, ny, m, dtype=dtype, bc=bc)
+    ref = None
+    for k in range(1, 5):
+        g.set_blocking(k)
+        assert g.blocking == k
+        rho = to_gpu(rho0, dtype)
+        g.run(rho, 9)
+        if ref is None:
+            ref = rho
+        else:
+            assert torch.equal(rho, ref), f"{k} steps per pass"
+
+
 def test_seird_as_transitions_matches_the_seird_kernel():
     """SEIRD written as transitions on D2Q5 agrees with the SEIRD pass kernel
     (different rounding order: within the FP64 tolerance)."""
