@@ -303,7 +303,7 @@ def run_surrogate(torch, inputs, Solver, train_steps):
             "plain_ms": round(plain_ms, 3), "plain_rel_l2_vs_fp64": plain_err,
             "rollout_ms": round(rr.seconds * 1e3, 3), "rollout_rel_l2_vs_fp64": roll_err,
             "accepted_jumps": rr.accepted, "fallback_jumps": rr.fallbacks,
-            "skipped_jumps": rr.skipped,
+            "skipped_jumps": rr.skipped, "prefiltered_jumps": rr.prefiltered,
             "target": 1e-3, "per_jump_threshold": rr.threshold,
             "speedup_at_1e-3": round(plain_ms / (rr.seconds * 1e3), 4),
             "surrogate_only_ms": round(br.seconds * 1e3, 3),
@@ -453,7 +453,8 @@ def main():
               f"{surrogate_res['train']['seconds']:.1f} s (loss {surrogate_res['train']['last_loss']:.2e}); "
               f"time to T plain {surrogate_res['plain_ms']:.1f} ms, rollout "
               f"{surrogate_res['rollout_ms']:.1f} ms ({surrogate_res['accepted_jumps']} accepted, "
-              f"{surrogate_res['fallback_jumps']} rejected, {surrogate_res['skipped_jumps']} skipped), "
+              f"{surrogate_res['fallback_jumps']} rejected ({surrogate_res['prefiltered_jumps']} "
+              f"on the judge tiles alone), {surrogate_res['skipped_jumps']} skipped), "
               f"error {surrogate_res['rollout_rel_l2_vs_fp64']:.2e}",
               file=sys.stderr, flush=True)
 

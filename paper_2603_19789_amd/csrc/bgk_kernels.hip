@@ -131,10 +131,8 @@ __global__ __launch_bounds__(BGK_THREADS) void bgk_density_kernel(const T *__res
 template <typename T>
 static BgkCoef<T> bgk_coef(const StepCoef &s) {
     BgkCoef<T> b;
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < 5; ++c)
         b.k.dl[c] = (T)s.dl[c];
-        b.k.cl[c] = (T)(1.0 - 4.0 * s.dl[c]);
-    }
     b.k.bdt = (T)s.bdt;
     b.k.kE = (T)s.kE;
     b.k.kI = (T)s.kI;

@@ -368,10 +368,8 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ in, T *__restri
 template <typename T>
 inline Coef<T> cast_coef(const StepCoef &s) {
     Coef<T> k;
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < 5; ++c)
         k.dl[c] = (T)s.dl[c];
-        k.cl[c] = (T)(1.0 - 4.0 * s.dl[c]);
-    }
     k.bdt = (T)s.bdt;
     k.kE = (T)s.kE;
     k.kI = (T)s.kI;

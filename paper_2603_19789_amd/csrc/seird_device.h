@@ -12,7 +12,6 @@ namespace sslbm {
 template <typename T>
 struct Coef {
     T dl[5];
-    T cl[5];  // 1 - 4 dl, the weight of the centre density in the D2Q5 update
     T bdt, kE, kI, kR, kD;
 };
 
@@ -43,22 +42,30 @@ __device__ __forceinline__ void seird_increments(T S, T E, T I, T R, const Coef<
 //   nb[C] : (north + south) + (east + west) neighbour densities, time t
 // Eq. (sslbm_final_clean) on D2Q5 has rho_f = rho_b = c + (1/6) L c with
 // L c = nb - 4 c, so rho(t+dt) = c + dl L c + Psi dt with dl = (2 tau - 1)/6.
-// It is evaluated as dl nb + ((1 - 4 dl) c + Psi dt): two fused
-// multiply-adds per compartment on top of its source term. The grouping of
-// nb makes the result invariant, bit for bit, under every symmetry of the
-// square lattice. Every kernel uses this function, so every launch shape
-// gives the same bits.
+// The diffusion part is evaluated as c + dl (nb - 4 c): its rounding errors
+// have no preferred sign, so the total population only random-walks. (The
+// cheaper dl nb + (1 - 4 dl) c rounds 1 - 4 dl once per launch, and that
+// error shifts the total the same way every step.) The I balance folds
+// k.kI * I into one fused multiply-add. The grouping of nb makes the result
+// invariant, bit for bit, under every symmetry of the square lattice. Every
+// kernel uses this function, so every launch shape gives the same bits.
 template <typename T, bool DIFFUSE_D>
 __device__ __forceinline__ void seird_update(const T c[5], const T nb[5], const Coef<T> &k,
                                              T out[5]) {
     T fdt, rE, rI;
     seird_increments(c[0], c[1], c[2], c[3], k, fdt, rE, rI);
-    (void)rI;  // the I balance below folds k.kI * I into one fused multiply-add
-    const T src[5] = {-fdt, fdt - rE, fma(-k.kI, c[2], rE), k.kR * c[2], k.kD * c[2]};
+    (void)rI;
+    // nb - 4c with one rounding (4c is exact, so this equals nb - (4c))
+    T diff[5];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        out[q] = fma(k.dl[q], nb[q], fma(k.cl[q], c[q], src[q]));
-    out[4] = DIFFUSE_D ? fma(k.dl[4], nb[4], fma(k.cl[4], c[4], src[4])) : fma(k.kD, c[2], c[4]);
+        diff[q] = fma(k.dl[q], fma(T(-4), c[q], nb[q]), c[q]);
+    diff[4] = DIFFUSE_D ? fma(k.dl[4], fma(T(-4), c[4], nb[4]), c[4]) : c[4];
+    out[0] = diff[0] - fdt;
+    out[1] = diff[1] + (fdt - rE);
+    out[2] = diff[2] + fma(-k.kI, c[2], rE);
+    out[3] = fma(k.kR, c[2], diff[3]);
+    out[4] = fma(k.kD, c[2], diff[4]);
 }
 
 // ---------------------------------------------------------------------------

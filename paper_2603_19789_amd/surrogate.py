@@ -119,6 +119,7 @@ class UNet:
         _check(self.lib.sur_to_bf16(_ptr(self.theta), _ptr(self.theta_bf16), off, None),
                "sur_to_bf16")
         self._shape = None
+        self._sets = {}  # activation and gradient buffers per (batch, h, w)
 
     @property
     def parameters(self) -> int:
@@ -143,8 +144,19 @@ class UNet:
         return list(zip(self.convs, lv))
 
     # ------------------------------------------------------------ buffers --
+    _BUFFER_NAMES = ("x0", "a", "pool", "cat", "e_last", "b", "hdec", "out", "g_cat", "g_l",
+                     "g_l2", "g_pool", "g_e_last", "dout", "wgrad_ws", "flip", "dims")
+
     def _buffers(self, n, h, w):
+        """Make the buffers of batch n at h x w current. Each shape's set is
+        kept, so alternating between shapes (a rollout's whole grid and its
+        judge tiles) allocates nothing after the first use of each."""
         if self._shape == (n, h, w):
+            return
+        if (n, h, w) in self._sets:
+            for name, val in zip(self._BUFFER_NAMES, self._sets[(n, h, w)]):
+                setattr(self, name, val)
+            self._shape = (n, h, w)
             return
         torch = _torch()
         bf = torch.bfloat16
@@ -178,6 +190,7 @@ class UNet:
                                 device="cuda")
         self.dims = dims
         self._shape = (n, h, w)
+        self._sets[(n, h, w)] = tuple(getattr(self, name) for name in self._BUFFER_NAMES)
 
     def e_view(self, l):
         """View of encoder output e_l (inside cat_l, or its own buffer)."""
@@ -478,6 +491,7 @@ class RolloutReport:
     median_check_error: float
     threshold: float
     skipped: int = 0  # jumps taken by plain SSLBM without trying the surrogate
+    prefiltered: int = 0  # fallbacks decided by the network on the judge tiles alone
 
 
 def _rms(t):
@@ -499,6 +513,17 @@ def relative_l2(a, b):
     return worst
 
 
+def receptive_radius(levels: int) -> int:
+    """Pixels (Chebyshev distance) from an output of the U-Net to the
+    farthest input it reads, over every alignment to the pooling grid: a 3x3
+    convolution at level l reaches 2^l, a 2x2 pooling into level l 2^(l-1),
+    and a nearest-neighbour upsampling nothing beyond the block its pooling
+    formed; plus 1 for the last convolution."""
+    convs = sum(2 * 2 ** l for l in range(levels)) + sum(2 * 2 ** l for l in range(levels - 1))
+    pools = sum(2 ** (l - 1) for l in range(1, levels))
+    return convs + pools + 1
+
+
 class Rollout:
     """Advance one grid to step T in jumps of the surrogate, each judged by
     plain SSLBM recomputed on seeded sub-tiles: a tile of side `tile` is
@@ -513,16 +538,30 @@ class Rollout:
     SSLBM from the same state. The budget is `target`, the relative L2 error
     allowed at T; accepted errors can add up, so each of the T / jump jumps
     may spend target / (T / jump). A fixed `threshold` replaces that share
-    (an infinite one runs the surrogate alone, unjudged)."""
+    (an infinite one runs the surrogate alone, unjudged).
+
+    Prefilter: before the network runs on the whole grid, it runs on the
+    judge tiles alone, each cropped with a halo that covers the network's
+    receptive field and aligned to its pooling grid, so that a tile's centre
+    sees the same inputs as in the whole-grid pass (up to the zero padding
+    at the edges of a non-periodic whole grid). A jump whose tile-only
+    error exceeds `prefilter_margin` times its share is redone by plain
+    SSLBM without the whole-grid pass; otherwise the whole-grid prediction
+    is judged as above. The prefilter only ever rejects, so it changes
+    which jumps are tried, never what is accepted."""
 
     def __init__(self, sur: Surrogate, params, h: int, w: int, *, tiles=4, tile=64,
-                 target=1e-3, threshold=None, seed=0, backoff=True, max_skip=32):
+                 target=1e-3, threshold=None, seed=0, backoff=True, max_skip=32,
+                 prefilter=True, prefilter_margin=4.0):
         from .binding import Ensemble, Solver
         torch = _torch()
+        if tile % 16:
+            raise ValueError("tile must be a multiple of 16")
         self.sur, self.params, self.h, self.w = sur, params, h, w
         self.tiles, self.tile = tiles, tile
         self.target, self.threshold = target, threshold
         self.backoff, self.max_skip = backoff, max_skip
+        self.prefilter, self.prefilter_margin = prefilter, prefilter_margin
         self.rng = np.random.default_rng(seed)
         self.solver = Solver(w, h, params, dtype="f32")
         self.scratch = torch.empty((5, h, w), dtype=torch.float32, device="cuda")
@@ -532,26 +571,56 @@ class Rollout:
         self.crop_scratch = self.ens.empty()
         self.pred_crops = torch.empty((tiles, 5, tile, tile), dtype=torch.float32, device="cuda")
         self.planes = param_planes([params])
+        # prefilter tiles: side a multiple of 64 (the network's column
+        # granule), halo >= the receptive field, (side - tile) / 2 a multiple
+        # of 8 (tile corners are multiples of 8: the pooling grid of 4 levels)
+        reach = max(receptive_radius(sur.net.levels), sur.jump)
+        self.pre_side = -(-(tile + 2 * reach) // 64) * 64
+        self.pre_pad = (self.pre_side - tile) // 2
+        self.pre_in = torch.empty((tiles, 5, self.pre_side, self.pre_side), dtype=torch.float32,
+                                  device="cuda")
+        self.pre_out = torch.empty_like(self.pre_in)
+        self.pre_planes = param_planes([params] * tiles)
         self.lib = library()
 
-    def _judge(self, state, pred):
+    def _reference(self, state):
+        """Seeded tile corners (multiples of 8) and plain SSLBM advanced
+        `jump` steps on each tile: (corners, [tiles, 5, tile, tile])."""
         jump, tile = self.sur.jump, self.tile
         side = tile + 2 * jump
         views = self.ens.views(self.crops)
-        corners = [(int(self.rng.integers(0, self.h)), int(self.rng.integers(0, self.w)))
-                   for _ in range(self.tiles)]
-        for (y0, x0), v, pc in zip(corners, views, self.pred_crops):
+        corners = [(int(self.rng.integers(0, self.h)) // 8 * 8,
+                    int(self.rng.integers(0, self.w)) // 8 * 8) for _ in range(self.tiles)]
+        for (y0, x0), v in zip(corners, views):
             _check(self.lib.sur_crop_periodic(_ptr(state), self.h, self.w, y0 - jump, x0 - jump,
                                               side, side, _ptr(v), None), "sur_crop_periodic")
-            _check(self.lib.sur_crop_periodic(_ptr(pred), self.h, self.w, y0, x0, tile, tile,
-                                              _ptr(pc), None), "sur_crop_periodic")
         self.ens.run(self.crops, jump, self.crop_scratch)
         torch = _torch()
         ref = torch.stack([v[:, jump:jump + tile, jump:jump + tile] for v in views])
+        return corners, ref
+
+    def _error(self, state, pred_tiles, ref):
+        torch = _torch()
         scale = torch.maximum(_rms(state), _rms(ref))
-        err = _rms(self.pred_crops - ref) / scale
-        err = torch.where(scale > 0, err, _rms(self.pred_crops - ref))
+        err = _rms(pred_tiles - ref) / scale
+        err = torch.where(scale > 0, err, _rms(pred_tiles - ref))
         return float(torch.max(err))
+
+    def _tile_prediction(self, state, corners):
+        """The network on the judge tiles alone: centres [tiles, 5, tile, tile]."""
+        side, pad, tile = self.pre_side, self.pre_pad, self.tile
+        for (y0, x0), v in zip(corners, self.pre_in):
+            _check(self.lib.sur_crop_periodic(_ptr(state), self.h, self.w, y0 - pad, x0 - pad,
+                                              side, side, _ptr(v), None), "sur_crop_periodic")
+        self.sur.predict(self.pre_in, self.pre_planes, out=self.pre_out)
+        return self.pre_out[:, :, pad:pad + tile, pad:pad + tile]
+
+    def _judge(self, state, pred, corners, ref):
+        tile = self.tile
+        for (y0, x0), pc in zip(corners, self.pred_crops):
+            _check(self.lib.sur_crop_periodic(_ptr(pred), self.h, self.w, y0, x0, tile, tile,
+                                              _ptr(pc), None), "sur_crop_periodic")
+        return self._error(state, self.pred_crops, ref)
 
     def run(self, rho0, T: int):
         """Returns (state at T, RolloutReport); T a multiple of the jump.
@@ -566,7 +635,7 @@ class Rollout:
             raise ValueError(f"T must be a multiple of {jump}")
         state = rho0.clone()
         pred = torch.empty_like(state)
-        accepted = fallbacks = skipped = 0
+        accepted = fallbacks = skipped = prefiltered = 0
         errs = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -574,15 +643,25 @@ class Rollout:
         judged = math.isfinite(share)
         jumps, j, streak = T // jump, 0, 0
         while j < jumps:
-            self.sur.predict(state[None], self.planes, out=pred[None])
-            err = self._judge(state, pred) if judged else 0.0
-            errs.append(err)
-            if err <= share:
-                state, pred = pred, state
-                accepted += 1
-                streak = 0
-                j += 1
-                continue
+            ok = True
+            if judged:
+                corners, ref = self._reference(state)
+                if self.prefilter:
+                    pre = self._error(state, self._tile_prediction(state, corners), ref)
+                    if pre > self.prefilter_margin * share:
+                        errs.append(pre)
+                        prefiltered += 1
+                        ok = False
+            if ok:
+                self.sur.predict(state[None], self.planes, out=pred[None])
+                err = self._judge(state, pred, corners, ref) if judged else 0.0
+                errs.append(err)
+                if err <= share:
+                    state, pred = pred, state
+                    accepted += 1
+                    streak = 0
+                    j += 1
+                    continue
             self.solver.run(state, jump, self.scratch)
             fallbacks += 1
             j += 1
@@ -596,4 +675,6 @@ class Rollout:
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         return state, RolloutReport(jumps, accepted, fallbacks, secs, max(errs), min(errs),
-                                    float(np.median(errs)), share, skipped)
+                                    float(np.median(errs)), share, skipped, prefiltered)
+
+

@@ -7,7 +7,7 @@ import pytest
 
 import generic_pins
 import oracle
-from gpu_util import TOL, max_rel_l2, to_gpu, to_np
+from gpu_util import TOL, _map, max_rel_l2, sample_nodes, to_gpu, to_np
 from paper_2603_19789_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -112,3 +112,39 @@ def test_model_errors():
         g.step(rho, rho)  # in place: the step is out of place
     with pytest.raises(SSLBMError):
         Model(32, 16, inputs.GenericModel(("a",), (100.0,), (), (1,), 5, 1.0, 0.01))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("lattice", [5, 9])
+def test_full_size_4096_sampled(orc, lattice, bc, dtype):
+    """The benchmark's generic workload (six compartments, 4096x4096), run
+    as the benchmark runs it (automatic steps per pass; 9 steps = passes of
+    4, 4 and 1): sampled nodes against the oracle on each node's dependence
+    cone (a periodic window of side 2 n + 3; no-flux walls are the mirror
+    extension of the field), plus the total population (no sinks)."""
+    nsteps, nx, ny = 9, 4096, 4096
+    print(f"model full size D2Q{lattice} {bc} {dtype}", flush=True)
+    m = inputs.seirvd_model(lattice=lattice)
+    rho0 = inputs.seirvd_state(nx, ny)
+    rng = np.random.default_rng(21)
+    rho0[1] += rng.uniform(0, 0.01, size=rho0[1].shape)  # every cell has exposed people
+    g = Model(nx, ny, m, dtype=dtype, bc=bc)
+    assert g.blocking == 4
+    rho = to_gpu(rho0, dtype)
+    g.run(rho, nsteps)
+    torch.cuda.synchronize()
+    nodes = sample_nodes(nx, ny, 48, seed=5)
+    half = nsteps + 1
+    offs = np.arange(-half, half + 1)
+    want = np.empty((len(nodes), 6))
+    for i, (x, y) in enumerate(nodes):
+        win = rho0[:, _map(y + offs, ny, bc)][:, :, _map(x + offs, nx, bc)]
+        want[i] = orc.generic_run(win, m, nsteps, bc="periodic")[:, half, half]
+    xs = torch.tensor([x for x, _ in nodes], device="cuda")
+    ys = torch.tensor([y for _, y in nodes], device="cuda")
+    got = rho[:, ys, xs].T.cpu().double().numpy()
+    err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+    assert np.all(err <= TOL[dtype]), err
+    total = float(rho.double().sum())
+    assert abs(total - rho0.sum()) <= (1e-12 if dtype == "f64" else 1e-5) * rho0.sum()

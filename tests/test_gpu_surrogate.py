@@ -270,6 +270,28 @@ def test_training_learns_and_beats_persistence():
     assert err_net < 0.5 * err_still
 
 
+def test_prefilter_tiles_match_the_whole_grid_pass():
+    """The rollout's prefilter runs the network on the judge tiles alone,
+    each cropped with a halo of the receptive radius and aligned to the
+    pooling grid: for tiles whose receptive field stays inside the grid
+    (away from the zero padding of the whole-grid pass) the tile centres
+    equal the whole-grid prediction bit for bit."""
+    from paper_2603_19789_amd import inputs
+    net = _small_net()
+    sur = S.Surrogate(net, 20, [1.0] * 5, [1e-3] * 5)
+    prm = inputs.c1_params()
+    h = w = 256
+    rng = np.random.default_rng(8)
+    rho = torch.tensor(rng.uniform(0, 1, size=(5, h, w)), dtype=torch.float32).cuda()
+    roll = S.Rollout(sur, prm, h, w, tiles=3, tile=16, target=1e-3, seed=2)
+    assert roll.pre_pad >= S.receptive_radius(net.levels) and roll.pre_pad % 8 == 0
+    corners = [(96, 104), (120, 64), (40, 200)]
+    tiles = roll._tile_prediction(rho, corners).clone()
+    whole = sur.predict(rho[None], S.param_planes([prm]))[0]
+    for (y0, x0), t in zip(corners, tiles):
+        assert torch.equal(t, whole[:, y0:y0 + 16, x0:x0 + 16]), (y0, x0)
+
+
 def test_rollout_with_broken_network_falls_back_to_sslbm():
     """A network with zeroed weights predicts no change; the sub-tile judge
     rejects every jump and the rollout is plain SSLBM, bit for bit."""
@@ -280,15 +302,22 @@ def test_rollout_with_broken_network_falls_back_to_sslbm():
     sur = S.Surrogate(net, 20, [1.0] * 5, [1e-3] * 5)
     prm = inputs.c1_params()
     rho0 = torch.tensor(inputs.c1_workload(64, 64).rho0, dtype=torch.float32).cuda()
-    roll = S.Rollout(sur, prm, 64, 64, tiles=2, tile=16, target=1e-3, seed=2, backoff=False)
+    # judge tiles: four of 32x32 at seed 1, so that every attempt has a tile
+    # within 4 cells of the infected bump (checked on the host from the same
+    # generator); a tile that misses the dynamics cannot see the error
+    roll = S.Rollout(sur, prm, 64, 64, tiles=4, tile=32, target=1e-3, seed=1, backoff=False,
+                     prefilter_margin=1.0)
     state, rep = roll.run(rho0, 100)
     assert rep.fallbacks == rep.jumps == 5 and rep.accepted == 0
+    # a network that predicts no change gives the same tiles in the tile pass
+    # and in the whole-grid pass, so at margin 1 the tile pass decides alone
+    assert rep.prefiltered == 5
     ref = rho0.clone()
     Solver(64, 64, prm, dtype="f32").run(ref, 100)
     assert torch.equal(state, ref)
     # with backoff: attempts at jumps 0, 3 and 8 of 12 (skips of 2 and 4), the
     # rest plain SSLBM, same bits
-    roll = S.Rollout(sur, prm, 64, 64, tiles=2, tile=16, target=1e-3, seed=2)
+    roll = S.Rollout(sur, prm, 64, 64, tiles=4, tile=32, target=1e-3, seed=1)
     state, rep = roll.run(rho0, 240)
     assert (rep.fallbacks, rep.skipped, rep.accepted) == (3, 9, 0)
     ref = rho0.clone()

@@ -206,3 +206,27 @@ def test_unet_storage_hook_changes_only_rounding():
     g16, _ = S.unet_backward(exact, weights, tape16, 0.1, store=S.bf16_round)
     for (a, _), (b, _) in zip(g, g16):
         assert np.linalg.norm(a - b) / np.linalg.norm(a) < 0.2
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 4])
+def test_receptive_radius_brute_force(levels):
+    """The rollout's prefilter pads its tiles by the network's receptive
+    radius: perturbing one input pixel of the oracle U-Net (every alignment
+    to the pooling grid) changes outputs exactly that far away."""
+    from paper_2603_19789_amd.surrogate import receptive_radius
+    spec = S.unet_spec(levels=levels, base=4, cin=2, cout=2)
+    rng = np.random.default_rng(7)
+    weights = [(rng.normal(size=(op[2], 9, op[1])) * 0.5, rng.normal(size=op[2]) * 0.1)
+               for op in spec if op[0] == "conv"]
+    n = 128
+    x = rng.normal(size=(1, n, n, 2))
+    base, _ = S.unet_forward(x, weights, spec, 0.1)
+    reach = 0
+    for off in range(2 ** (levels - 1)):
+        c = n // 2 + off
+        x2 = x.copy()
+        x2[0, c, c, :] += 1.0
+        out, _ = S.unet_forward(x2, weights, spec, 0.1)
+        ys, xs = np.nonzero(np.abs(out - base).max(axis=(0, 3)) > 0)
+        reach = max(reach, int(max(np.abs(ys - c).max(), np.abs(xs - c).max())))
+    assert reach == receptive_radius(levels)
