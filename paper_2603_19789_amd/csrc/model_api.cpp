@@ -35,13 +35,16 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
-// Steps per pass of sslbm_model_run: the caller's choice, else the deepest
-// pass the kernels are built for. Measured at 4096 x 4096 with the
-// six-compartment model: FP32 71 / 113 / 124 / 128 GLUPS (D2Q5) and
-// 73 / 104 / 113 / 115 (D2Q9) at 1 / 2 / 3 / 4 steps per pass; FP64 peaks
-// at 3 steps (77 and 70 GLUPS), with 4 within 1%.
+// Steps per pass of sslbm_model_run: the caller's choice, else 3. Measured
+// at 4096 x 4096 with the six-compartment model, each depth at the
+// wavefronts per SIMD its registers allow: FP32 D2Q5 71 / 140 / 165 / 162
+// GLUPS and D2Q9 73 / 138 / 156 / 153 at 1 / 2 / 3 / 4 steps per pass;
+// FP64 D2Q5 97 and D2Q9 87 at 3 steps, 77 and 69 at 4 (two wavefronts per
+// SIMD).
+constexpr int MODEL_AUTO_K = 3;
+
 int resolved_blocking(const sslbm_model *m) {
-    return m->blocking > 0 ? m->blocking : sslbm::MODEL_MAX_K;
+    return m->blocking > 0 ? m->blocking : MODEL_AUTO_K;
 }
 
 size_t state_bytes(const sslbm_model *m) {

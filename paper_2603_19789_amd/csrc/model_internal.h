@@ -43,7 +43,13 @@ struct ModelShape {
 // Steps per pass the kernels are built for (1..MODEL_MAX_K).
 constexpr int MODEL_MAX_K = SSLBM_MODEL_MAX_BLOCKING;
 
-ModelShape model_shape(int nx, int ny, int K);
+// At most this many wavefronts per SIMD are asked for (the largest count
+// measured to help).
+constexpr int MODEL_MAX_WAVES_PER_SIMD = 4;
+
+// Launch shape of a pass of K steps whose kernel fits resident_per_simd
+// wavefronts per SIMD.
+ModelShape model_shape(int nx, int ny, int K, int resident_per_simd);
 // One pass of K steps, in -> out.
 hipError_t launch_model(int dtype, int lattice, const void *in, void *out, const GridDesc &g,
                         const ModelCoefHost &h, const void *table, int K, hipStream_t s);

@@ -8,16 +8,24 @@
 
 namespace sslbm {
 
-ModelShape model_shape(int nx, int ny, int K) {
-    // two workgroups of four wavefronts per CU (two wavefronts per SIMD hide
-    // each other's LDS and memory waits), chunks of at least 2K and 8 rows;
-    // measured at 4096 x 4096 with six compartments and one step per pass:
-    // 56 GLUPS with one wavefront per SIMD, 73 with two, 66 with four
-    // (shorter chunks, more halo rows)
+ModelShape model_shape(int nx, int ny, int K, int resident_per_simd) {
+    // As many wavefronts per SIMD as fit (so that they hide each other's LDS
+    // and memory waits in one round), at most MODEL_MAX_WAVES_PER_SIMD, on
+    // chunks of at least max(8, 2K) rows. Measured at 4096 x 4096 with six
+    // compartments, FP32, three steps per pass: 124 / 156 / 165 GLUPS at
+    // 2 / 3 / 4 wavefronts per SIMD; with one step per pass 56 / 73 / 66 at
+    // 1 / 2 / 4 (shorter chunks, more halo rows). FP64 with four steps per
+    // pass fits two (196 VGPRs): asking for three drops it from 77 to 65.
     ModelShape s;
     const int wu = 64 - 2 * K;
     s.strips = (nx + wu - 1) / wu;
-    long long chunks = (2 * 256 * WAVES_PER_BLOCK) / s.strips;
+    int per = resident_per_simd < MODEL_MAX_WAVES_PER_SIMD ? resident_per_simd
+                                                           : MODEL_MAX_WAVES_PER_SIMD;
+    if (K == 1 && per > 2)
+        per = 2;
+    if (per < 1)
+        per = 1;
+    long long chunks = ((long long)per * 256 * WAVES_PER_BLOCK) / s.strips;
     if (chunks < 1)
         chunks = 1;
     long long rows = (ny + chunks - 1) / chunks;

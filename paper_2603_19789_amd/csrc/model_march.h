@@ -272,10 +272,35 @@ __global__ __launch_bounds__(BLOCK_THREADS) void model_kernel(const T *__restric
     }
 }
 
+// Wavefronts of model_kernel<T, Q, M, K> that fit on one SIMD at once (512
+// VGPRs per lane, allocated in granules of 8), from the built kernel's
+// register count; queried once per device.
+template <typename T, int Q, int M, int K>
+int resident_waves_per_simd() {
+    static int cached[16] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    if (cached[dev])
+        return cached[dev];
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, (const void *)model_kernel<T, Q, M, K>) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    const int regs = (attr.numRegs + 7) / 8 * 8;
+    int per = regs > 0 ? 512 / regs : 8;
+    per = per < 1 ? 1 : (per > 8 ? 8 : per);
+    cached[dev] = per;
+    return per;
+}
+
 template <typename T, int Q, int M, int K>
 hipError_t launch_mk(const void *in, void *out, const GridDesc &g, const ModelCoef<T> &k,
                      const void *table, hipStream_t s) {
-    const ModelShape sh = model_shape(g.nx, g.ny, K);
+    const ModelShape sh = model_shape(g.nx, g.ny, K, resident_waves_per_simd<T, Q, M, K>());
     const int waves = sh.strips * sh.chunks;
     hipLaunchKernelGGL((model_kernel<T, Q, M, K>), dim3((unsigned)((waves + 3) / 4)),
                        dim3(BLOCK_THREADS), 0, s, static_cast<const T *>(in),

@@ -300,7 +300,7 @@ def test_generic_model_blocking_host(lib):
     try:
         k = ctypes.c_int()
         assert lib.sslbm_model_get_blocking(h, ctypes.byref(k)) == binding.OK
-        assert k.value == binding.MODEL_MAX_BLOCKING  # automatic: the deepest pass
+        assert 1 <= k.value <= binding.MODEL_MAX_BLOCKING  # automatic choice, resolved
         for want in range(1, binding.MODEL_MAX_BLOCKING + 1):
             assert lib.sslbm_model_set_blocking(h, want) == binding.OK
             assert lib.sslbm_model_get_blocking(h, ctypes.byref(k)) == binding.OK
