@@ -326,7 +326,7 @@ def run_generic(torch, inputs, Model, steps):
         m = Model(NX, NY, inputs.seirvd_model(lattice=lattice), dtype="f32")
         rho = rho0.clone()
         scratch = torch.empty_like(rho)
-        m.run(rho, 10, scratch)
+        m.run(rho, steps, scratch)  # warm-up: the same passes as the timed run
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
