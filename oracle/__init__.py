@@ -71,9 +71,10 @@ class Oracle:
         _IP = ctypes.POINTER(ctypes.c_int)
         lib.oracle_generic_step.argtypes = [i, i, i, i, i, _DP, d, d, i, _IP, _IP, _IP, _IP, _DP,
                                             _IP, _DP, _DP]
+        lib.oracle_fd4_rk4_run.argtypes = [i, i, i, _DP, _DP, d, d, _DP, ll]
         for f in ("oracle_sslbm_step", "oracle_sslbm_run", "oracle_bgk_init",
                   "oracle_bgk_density", "oracle_bgk_step", "oracle_bgk_run",
-                  "oracle_sslbm_adjoint_step", "oracle_generic_step"):
+                  "oracle_sslbm_adjoint_step", "oracle_generic_step", "oracle_fd4_rk4_run"):
             getattr(lib, f).restype = ctypes.c_int
         self.lib = lib
 
@@ -108,6 +109,17 @@ class Oracle:
         rc = self.lib.oracle_sslbm_run(nx, ny, _BC[bc], _ptr(rates), _ptr(d), dx, dt,
                                        _ptr(rho), _ptr(work), int(nsteps), threads)
         self._check(rc, "sslbm_run")
+        return rho
+
+    def fd4_rk4_run(self, rho, p, nsteps: int, bc="periodic") -> np.ndarray:
+        """The finite-difference reference of Sec. III: fourth-order centred
+        Laplacian, classic RK4, reactions explicit at every stage."""
+        rho = _f64(rho).copy()
+        _, ny, nx = rho.shape
+        rates, d, dx, dt = self._params(p)
+        rc = self.lib.oracle_fd4_rk4_run(nx, ny, _BC[bc], _ptr(rates), _ptr(d), dx, dt,
+                                         _ptr(rho), int(nsteps))
+        self._check(rc, "fd4_rk4_run")
         return rho
 
     # ------------------------------------------------------------ adjoint --

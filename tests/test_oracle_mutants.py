@@ -6,6 +6,7 @@ strong enough to trust the oracle.
 import pytest
 
 import adjoint_pins
+import fd4_pins
 import generic_pins
 import oracle
 import pins
@@ -75,13 +76,32 @@ MUTANTS = {
                                          "                if (1)\n"),
     "D2Q9 mirror off by one": ("x = 2 * nx - 1 - x;", "x = 2 * nx - 2 - x;"),
     "D2Q9 mirror of y": ("y = -1 - y;", "y = -y;"),
+    "FD4 outer weight sign": ("- u[(size_t)y * nx + fd4_fold(x + 2, nx, bc)];",
+                              "+ u[(size_t)y * nx + fd4_fold(x + 2, nx, bc)];"),
+    "FD4 centre weight in y": ("- 30.0 * here[c]\n                                 + 16.0 * u[(size_t)fd4_fold(y + 1",
+                               "- 28.0 * here[c]\n                                 + 16.0 * u[(size_t)fd4_fold(y + 1"),
+    "FD4 without the 1/12": ("double h2 = 12.0 * dx * dx;", "double h2 = dx * dx;"),
+    "FD4 far neighbour on the wrong side": ("-u[(size_t)y * nx + fd4_fold(x - 2, nx, bc)]",
+                                            "-u[(size_t)y * nx + fd4_fold(x + 2, nx, bc)]"),
+    "FD4 periodic wrap off by one": ("return ((i % n) + n) % n;", "return ((i % n) + n + 1) % n;"),
+    "FD4 reflection about the node": ("return m < n ? m : period - 1 - m;",
+                                      "return m < n ? m : (period - 1 - m + 1) % n;"),
+    "FD4 diffusivity of S for all": ("F[c * plane + cell] = d[c] * (along_x",
+                                     "F[c * plane + cell] = d[0] * (along_x"),
+    "RK4 second stage from k1": ("stage[i] = rho[i] + 0.5 * dt * k2[i];",
+                                 "stage[i] = rho[i] + 0.5 * dt * k1[i];"),
+    "RK4 third stage half step": ("stage[i] = rho[i] + dt * k3[i];",
+                                  "stage[i] = rho[i] + 0.5 * dt * k3[i];"),
+    "RK4 weights": ("(k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i])",
+                    "(k1[i] + 2.0 * k2[i] + k3[i] + 2.0 * k4[i])"),
+    "FD4 reactions left out": ("(along_x + along_y) / h2 + psi[c];", "(along_x + along_y) / h2;"),
 }
 
 
 def _caught(orc) -> list:
     failures = []
     for check in (pins.FAST_SSLBM_CHECKS + pins.FAST_BGK_CHECKS + adjoint_pins.FAST_ADJOINT_CHECKS
-                  + generic_pins.FAST_GENERIC_CHECKS):
+                  + generic_pins.FAST_GENERIC_CHECKS + fd4_pins.FAST_FD4_CHECKS):
         try:
             check(orc)
         except (AssertionError, ValueError, FloatingPointError) as exc:
