@@ -74,6 +74,9 @@ def parse_args():
     ap.add_argument("--generic-steps", type=int, default=200,
                     help="steps of the generic six-compartment model on D2Q5 and D2Q9 "
                          "(0 skips it)")
+    ap.add_argument("--fd4-steps", type=int, default=20,
+                    help="steps of the fourth-order finite-difference / RK4 reference solver "
+                         "on the 4096x4096 workload, FP32 and FP64 (0 skips it)")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the uneven 512-instance ensemble (0 skips it)")
     return ap.parse_args()
@@ -314,6 +317,40 @@ def run_surrogate(torch, inputs, Solver, train_steps):
             "dtype": "bf16 network, f32 state"}
 
 
+def run_fd4(torch, inputs, Solver, steps, sslbm_glups):
+    """The finite-difference reference solver of Sec. III (fourth-order
+    centred Laplacian, classic RK4, four stage launches per step) on the
+    4096 x 4096 R0 = 3 workload, FP32 and FP64, timed with HIP events after
+    one untimed step; the SSLBM's GLUPS on the same workload give the speed
+    ratio the paper's timing table compares. Algorithmic HBM traffic: 16
+    states per step (stage 1 reads u and writes the next stage input and
+    the running sum; stages 2 and 3 read their input, u and the sum and
+    write two; stage 4 reads its input and the sum and writes u)."""
+    w = inputs.c2_workload(r0=3.0)
+    out = []
+    for d in ("f32", "f64"):
+        tdt = torch.float32 if d == "f32" else torch.float64
+        s = Solver(w.nx, w.ny, w.params, dtype=d)
+        rho = torch.tensor(w.rho0, dtype=tdt, device="cuda")
+        work = torch.empty(s.fd4_workspace_bytes(), dtype=torch.uint8, device="cuda")
+        s.fd4_run(rho, 1, work=work)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        s.fd4_run(rho, steps, work=work)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        glups = w.nx * w.ny / (ms * 1e-3) / 1e9
+        elem = 4 if d == "f32" else 8
+        out.append({"dtype": d, "ms_per_step": round(ms, 4), "glups": round(glups, 2),
+                    "algorithmic_gbps": round(16 * 5 * elem * w.nx * w.ny / (ms * 1e-3) / 1e9, 1),
+                    "sslbm_over_fd4": round(sslbm_glups[d] / glups, 2) if d in sslbm_glups
+                    else None})
+    return {"workload": w.name, "steps": steps, "runs": out}
+
+
 def run_generic(torch, inputs, Model, steps):
     """The six-compartment vaccination / waning model (generic transition
     sources) on a 4096 x 4096 periodic grid, D2Q5 and D2Q9, FP32, with the
@@ -438,6 +475,18 @@ def main():
               f"adjoint step {adjoint_res['adjoint_step_gbps']:.0f} GB/s",
               file=sys.stderr, flush=True)
 
+    fd4_res = None
+    if args.fd4_steps > 0:
+        best = {}
+        for r in results:
+            if r.get("scheme") == "sslbm" and r.get("R0") == 3.0:
+                best[r["dtype"]] = r["glups"]
+        fd4_res = run_fd4(torch, inputs, Solver, args.fd4_steps, best)
+        print("# fd4 reference: " + ", ".join(
+            f"{r['dtype']} {r['glups']:.1f} GLUPS ({r['algorithmic_gbps']:.0f} GB/s"
+            + (f", SSLBM {r['sslbm_over_fd4']:.0f}x faster)" if r["sslbm_over_fd4"] else ")")
+            for r in fd4_res["runs"]), file=sys.stderr, flush=True)
+
     generic_res = None
     if args.generic_steps > 0:
         generic_res = run_generic(torch, inputs, Model, args.generic_steps)
@@ -508,6 +557,8 @@ def main():
         line["surrogate"] = surrogate_res
     if generic_res is not None:
         line["generic"] = generic_res
+    if fd4_res is not None:
+        line["fd4"] = fd4_res
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inputs, args.cpu_seconds)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 4)

@@ -172,6 +172,31 @@ int bgk_run(sslbm_ctx *c, void *f, void *rhoD, void *f_scratch, void *rhoD_scrat
 int bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho, void *hip_stream);
 
 /*
+ * The finite-difference reference solver of Sec. III, used to validate the
+ * SSLBM and to time the comparison the paper makes: the PDEs of
+ * Eqs. (EqSEIRD_S)-(EqSEIRD_D) with the Laplacian by fourth-order centred
+ * differences, (-u(-2) + 16 u(-1) - 30 u + 16 u(+1) - u(+2)) / (12 dx^2) per
+ * axis, the classic fourth-order Runge-Kutta method in time, and the
+ * reactions evaluated at every stage. The context's parameters, grid,
+ * arithmetic type and walls apply; a no-flux wall takes ghost values by
+ * even reflection about the boundary face (u(-1) = u(0), u(-2) = u(1)), a
+ * periodic wall wraps. Every context sslbm_init accepts is stable here too
+ * (d_lu <= 1/4 keeps dt d (32/3) / dx^2 inside the RK4 stability interval,
+ * whose real extent is 2.78).
+ *
+ *   sslbm_fd4_workspace_bytes: bytes of the workspace sslbm_fd4_run needs
+ *       (three states), 0 for a null context.
+ *   sslbm_fd4_run: nsteps steps in place in rho (device, layout as
+ *       sslbm_step), work a device buffer of work_bytes >= the workspace
+ *       size, caller-owned and clobbered. SSLBM_E_ARG for null pointers,
+ *       negative nsteps, a short or misaligned buffer; SSLBM_E_ALIAS if rho
+ *       and work overlap. Four launches per step, queued on hip_stream.
+ */
+size_t sslbm_fd4_workspace_bytes(const sslbm_ctx *c);
+int sslbm_fd4_run(sslbm_ctx *c, void *rho, void *work, size_t work_bytes, long long nsteps,
+                  void *hip_stream);
+
+/*
  * Total population per compartment, out_totals[C] = sum_x rho[C](x) in FP64,
  * the quantity conserved by Eq. (mass_conservation) when summed over C.
  * Deterministic (fixed reduction order). Waits for the stream. The first

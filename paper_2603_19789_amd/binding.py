@@ -93,6 +93,7 @@ def library() -> ctypes.CDLL:
             "bgk_run": [vp, vp, vp, vp, vp, ll, vp],
             "bgk_density": [vp, vp, vp, vp, vp],
             "sslbm_total": [vp, vp, ctypes.POINTER(ctypes.c_double), vp],
+            "sslbm_fd4_run": [vp, vp, vp, sz, ll, vp],
             "sslbm_strerror": [i],
             "sslbm_last_hip_error": [vp],
             "sslbm_ensemble_create": [ctypes.POINTER(vp), i, ctypes.POINTER(i),
@@ -149,6 +150,8 @@ def library() -> ctypes.CDLL:
         lib.sslbm_checkpoint_count.restype = ll
         lib.sslbm_adjoint_workspace_bytes.argtypes = [vp, i]
         lib.sslbm_adjoint_workspace_bytes.restype = ctypes.c_size_t
+        lib.sslbm_fd4_workspace_bytes.argtypes = [vp]
+        lib.sslbm_fd4_workspace_bytes.restype = ctypes.c_size_t
         lib.sur_conv3x3_backward_weight_workspace.argtypes = [i, i, i, i, i]
         lib.sur_conv3x3_backward_weight_workspace.restype = ctypes.c_size_t
         _LIB = lib
@@ -287,6 +290,28 @@ class Solver(_Context):
         a = self._tensor(rho, self.shape, "rho")
         self._check(self.lib.sslbm_total(self.handle, a, out, _stream(stream)), "sslbm_total")
         return [out[i] for i in range(5)]
+
+    # ---------------------------------------------- finite-difference reference --
+    def fd4_workspace_bytes(self) -> int:
+        return int(self.lib.sslbm_fd4_workspace_bytes(self.handle))
+
+    def fd4_run(self, rho, nsteps: int, work=None, stream=None):
+        """nsteps steps of the fourth-order finite-difference / RK4 reference
+        solver (Sec. III) in place in rho; work (uint8, at least
+        fd4_workspace_bytes()) is clobbered."""
+        torch = _torch()
+        need = self.fd4_workspace_bytes()
+        if work is None:
+            work = torch.empty(need, dtype=torch.uint8, device="cuda")
+        if (not isinstance(work, torch.Tensor) or work.device.type != "cuda"
+                or not work.is_contiguous()):
+            raise ValueError("work must be a contiguous GPU tensor")
+        nbytes = work.numel() * work.element_size()
+        a = self._tensor(rho, self.shape, "rho")
+        self._check(self.lib.sslbm_fd4_run(self.handle, a, ctypes.c_void_p(work.data_ptr()),
+                                           nbytes, int(nsteps), _stream(stream)),
+                    "sslbm_fd4_run")
+        return rho
 
     # ------------------------------------------------------------ adjoint --
     def _grad(self, grad):

@@ -21,7 +21,8 @@ SOURCES = ["sslbm_api.cpp", "ensemble_api.cpp", "adjoint_api.cpp", "surrogate_ap
            "model_api.cpp", "sslbm_kernels.hip", "ensemble_kernels.hip", "adjoint_kernels.hip",
            "surrogate_kernels.hip", "model_kernels.hip", "model_kernels_f32_d2q5.hip",
            "model_kernels_f32_d2q9.hip", "model_kernels_f64_d2q5.hip",
-           "model_kernels_f64_d2q9.hip", "bgk_kernels.hip", "reduce_kernels.hip"]
+           "model_kernels_f64_d2q9.hip", "bgk_kernels.hip", "reduce_kernels.hip",
+           "fd4_kernels.hip"]
 
 # -ffp-contract=off: only the fma() calls written in the kernels fuse, so every
 # launch shape and blocking depth rounds identically.

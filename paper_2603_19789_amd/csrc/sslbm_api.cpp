@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "fd4_internal.h"
 #include "sslbm.h"
 #include "sslbm_internal.h"
 
@@ -383,6 +384,25 @@ int bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho, void *
         return SSLBM_E_ALIAS;
     return hip_status(c, sslbm::launch_bgk_density(c->dtype, f, rhoD, rho, grid_of(c),
                                                    (hipStream_t)hip_stream));
+}
+
+size_t sslbm_fd4_workspace_bytes(const sslbm_ctx *c) {
+    return c ? 3 * 5 * plane_elems(c) * elem_size(c) : 0;
+}
+
+int sslbm_fd4_run(sslbm_ctx *c, void *rho, void *work, size_t work_bytes, long long nsteps,
+                  void *hip_stream) {
+    if (!c || !rho || !work || nsteps < 0)
+        return SSLBM_E_ARG;
+    const size_t bytes = 5 * plane_elems(c) * elem_size(c);
+    if (work_bytes < 3 * bytes || (uintptr_t)rho % elem_size(c) || (uintptr_t)work % elem_size(c))
+        return SSLBM_E_ARG;
+    if (overlap(rho, bytes, work, 3 * bytes))
+        return SSLBM_E_ALIAS;
+    if (nsteps == 0)
+        return SSLBM_OK;
+    return hip_status(c, sslbm::launch_fd4(c->dtype, rho, work, grid_of(c), c->coef, nsteps,
+                                           (hipStream_t)hip_stream));
 }
 
 int sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_stream) {

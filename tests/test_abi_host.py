@@ -247,6 +247,32 @@ def test_surrogate_header_exports_and_host_checks(lib):
                         None) == binding.E_ARG  # beta1 = 1
 
 
+def test_fd4_host_checks(lib):
+    """The finite-difference reference solver: workspace size and argument
+    errors, all decided on the host."""
+    st, h = _init(lib, 130, 45, binding.F32)
+    assert st == binding.OK
+    state = 5 * 130 * 45 * 4
+    try:
+        assert lib.sslbm_fd4_workspace_bytes(h) == 3 * state
+        assert lib.sslbm_fd4_workspace_bytes(None) == 0
+        vp = ctypes.c_void_p
+        a, w = vp(0x100000000), vp(0x200000000)
+        ws = 3 * state
+        assert lib.sslbm_fd4_run(None, a, w, ws, 1, None) == binding.E_ARG
+        assert lib.sslbm_fd4_run(h, None, w, ws, 1, None) == binding.E_ARG
+        assert lib.sslbm_fd4_run(h, a, None, ws, 1, None) == binding.E_ARG
+        assert lib.sslbm_fd4_run(h, a, w, ws, -1, None) == binding.E_ARG
+        assert lib.sslbm_fd4_run(h, a, w, ws - 1, 1, None) == binding.E_ARG      # short
+        assert lib.sslbm_fd4_run(h, a, vp(w.value + 2), ws, 1, None) == binding.E_ARG  # misaligned
+        assert lib.sslbm_fd4_run(h, a, vp(a.value + state // 2), ws, 1, None) == binding.E_ALIAS
+        assert lib.sslbm_fd4_run(h, vp(w.value + ws - 4), w, ws, 1, None) == binding.E_ALIAS
+        # nothing to do for zero steps: no GPU call is made
+        assert lib.sslbm_fd4_run(h, a, w, ws, 0, None) == binding.OK
+    finally:
+        lib.sslbm_destroy(h)
+
+
 def test_generic_model_host_checks(lib):
     """sslbm_model_create validates the model on the host."""
     from paper_2603_19789_amd.binding import Transition
