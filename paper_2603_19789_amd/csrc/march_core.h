@@ -182,13 +182,14 @@ __device__ __forceinline__ void fetch_row(MarchState<T, K, V> &st, const MarchAr
 // through a DPP wave shift.
 template <typename T, int V, typename Row>
 __device__ __forceinline__ T east_west(const Row &m, int v) {
+    static_assert(V == 1 || V == 2, "one or two columns per lane");
     if constexpr (V == 1) {
-        return lane_from_right(m[0]) + lane_from_left(m[0]);
+        return add_right_to(m[0], lane_from_left(m[0]));
     } else {
         if (v == 0)
-            return m[1] + lane_from_left(m[V - 1]);
+            return add_from_left(m[V - 1]);  // m[1] + the left lane's m[1] (V = 2)
         if (v == V - 1)
-            return lane_from_right(m[0]) + m[V - 2];
+            return add_from_right(m[0]);  // the right lane's m[0] + m[0] (V = 2)
         return m[v + 1] + m[v - 1];
     }
 }

@@ -129,4 +129,40 @@ __device__ __forceinline__ double lane_from_right(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Sums of a value and its neighbour lane's, each one v_add_f32_dpp. This
+// compiler fuses a DPP move into the add that consumes it only part of the
+// time, so these write the fused instruction. The compiler does not see the
+// DPP read inside the asm, so each one starts with s_nop 1: the two wait
+// states gfx9 requires between a VALU write of a register and its DPP read.
+// Lanes without a neighbour read 0 (bound_ctrl), as lane_from_left/right.
+//   x + lane_from_left(x)
+__device__ __forceinline__ float add_from_left(float x) {
+    float r;
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=v"(r)
+        : "v"(x));
+    return r;
+}
+//   lane_from_right(x) + x
+__device__ __forceinline__ float add_from_right(float x) {
+    float r;
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %1 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=v"(r)
+        : "v"(x));
+    return r;
+}
+//   lane_from_right(x) + y
+__device__ __forceinline__ float add_right_to(float x, float y) {
+    float r;
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %1, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=v"(r)
+        : "v"(x), "v"(y));
+    return r;
+}
+__device__ __forceinline__ double add_from_left(double x) { return x + lane_from_left(x); }
+__device__ __forceinline__ double add_from_right(double x) { return lane_from_right(x) + x; }
+__device__ __forceinline__ double add_right_to(double x, double y) {
+    return lane_from_right(x) + y;
+}
+
 }  // namespace sslbm
