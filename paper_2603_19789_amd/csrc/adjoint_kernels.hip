@@ -132,7 +132,7 @@ __device__ __forceinline__ void adjoint_row(AdjState<T> &st, const AdjArgs<T> &a
     for (int c = 0; c < 5; ++c) {
         lc[c] = st.lam[sm][c];
         const T nb = (st.lam[su][c] + st.lam[sd][c]) +
-                     (lane_from_right(lc[c]) + lane_from_left(lc[c]));
+                     add_right_to(lc[c], lane_from_left(lc[c]));
         lap[c] = fma(T(-4), lc[c], nb);
     }
     adjoint_node<T, DIFFUSE_D>(lc, lap, st.rho[sr], a.k, o, g, de, sir);
@@ -286,7 +286,7 @@ __device__ __forceinline__ void fused_row(Fused2State<T> &st, const Fused2Args<T
     for (int c = 0; c < 5; ++c) {
         cen[c] = st.rho0[sm][c];
         nb[c] = (c < 4 || DIFFUSE_D) ? (st.rho0[su][c] + st.rho0[sd][c]) +
-                                           (lane_from_right(cen[c]) + lane_from_left(cen[c]))
+                                           add_right_to(cen[c], lane_from_left(cen[c]))
                                      : T(0);
     }
     seird_update<T, DIFFUSE_D>(cen, nb, a.k, r1);
@@ -297,7 +297,7 @@ __device__ __forceinline__ void fused_row(Fused2State<T> &st, const Fused2Args<T
         for (int c = 0; c < 5; ++c) {
             lc[c] = st.lam2[sm][c];
             const T n2 = (st.lam2[su][c] + st.lam2[sd][c]) +
-                         (lane_from_right(lc[c]) + lane_from_left(lc[c]));
+                         add_right_to(lc[c], lane_from_left(lc[c]));
             lap[c] = fma(T(-4), lc[c], n2);
         }
         adjoint_node<T, DIFFUSE_D>(lc, lap, r1, a.k, o, g, de, sir);
@@ -316,7 +316,7 @@ __device__ __forceinline__ void fused_row(Fused2State<T> &st, const Fused2Args<T
         for (int c = 0; c < 5; ++c) {
             lc[c] = st.lam1[lm][c];
             const T n1 = (st.lam1[lu][c] + st.lam1[ld][c]) +
-                         (lane_from_right(lc[c]) + lane_from_left(lc[c]));
+                         add_right_to(lc[c], lane_from_left(lc[c]));
             lap[c] = fma(T(-4), lc[c], n1);
         }
         adjoint_node<T, DIFFUSE_D>(lc, lap, st.rho0[lm], a.k, o, g, de, sir);

@@ -104,12 +104,12 @@ __device__ __forceinline__ void model_level(ModelRows<T, K> &st, const ModelArgs
         out[c] = T(0);
         if (c < M) {
             const T up = st.ring[L - 1][su][c], dn = st.ring[L - 1][sd][c];
-            const T axis = (up + dn) + (lane_from_right(cen[c]) + lane_from_left(cen[c]));
+            const T axis = (up + dn) + add_right_to(cen[c], lane_from_left(cen[c]));
             if constexpr (Q == 5) {
                 out[c] = fma(k.dl[c], fma(T(-4), cen[c], axis), cen[c]);
             } else {
-                const T diag = (lane_from_right(up) + lane_from_left(up)) +
-                               (lane_from_right(dn) + lane_from_left(dn));
+                const T diag = add_right_to(up, lane_from_left(up)) +
+                               add_right_to(dn, lane_from_left(dn));
                 out[c] = fma(k.dl[c], fma(T(-20), cen[c], fma(T(4), axis, diag)), cen[c]);
             }
             total += ((k.counted >> c) & 1u) ? cen[c] : T(0);
