@@ -256,13 +256,14 @@ struct Fused2Args {
     Coef<T> k;
     unsigned xoff, xo;
     bool out_col;
-    int j0;    // first row read: y0 - 2
+    int j0;    // first row read: y0 - 2 marching down, y1 + 1 marching up
+    int dir;   // +1: rows in increasing order, -1: decreasing
     int tend;  // rows read: y1 - y0 + 4
 };
 
 template <typename T, int SL>
 __device__ __forceinline__ void fused_fetch(Fused2State<T> &st, const Fused2Args<T> &a, int t) {
-    const long long row = (long long)map_index(a.j0 + t, a.g.ny, a.g.bc) * a.g.nx;
+    const long long row = (long long)map_index(a.j0 + a.dir * t, a.g.ny, a.g.bc) * a.g.nx;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         st.rho0[SL][c] =
@@ -321,7 +322,7 @@ __device__ __forceinline__ void fused_row(Fused2State<T> &st, const Fused2Args<T
         }
         adjoint_node<T, DIFFUSE_D>(lc, lap, st.rho0[lm], a.k, o, g, de, sir);
         if (a.out_col) {
-            const long long row = (long long)(a.j0 + t - 2) * a.g.nx;
+            const long long row = (long long)(a.j0 + a.dir * (t - 2)) * a.g.nx;
 #pragma unroll
             for (int c = 0; c < 5; ++c)
                 buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), a.xo, o[c]);
@@ -353,7 +354,12 @@ __global__ __launch_bounds__(BLOCK_THREADS) void adjoint2_kernel(
     a.xoff = (unsigned)map_index(xl, g.nx, g.bc) * (unsigned)sizeof(T);
     a.xo = (unsigned)xl * (unsigned)sizeof(T);
     a.out_col = lane >= F_HX && lane < F_HX + F_WU && xl < g.nx;
-    a.j0 = y0 - 2;
+    // odd chunks march up the rows, so that two chunks meeting at a row
+    // boundary read the halo rows around it at about the same time (the
+    // second read then comes from cache); the stencil is symmetric in y
+    const bool up = (chunk & 1) != 0;
+    a.dir = up ? -1 : 1;
+    a.j0 = up ? y1 + 1 : y0 - 2;
     a.tend = y1 - y0 + 4;
 
     Fused2State<T> st;
@@ -382,12 +388,16 @@ __global__ __launch_bounds__(BLOCK_THREADS) void adjoint2_kernel(
         fused_row<T, DIFFUSE_D, 2, true>(st, a, t + 2, acc);
         fused_row<T, DIFFUSE_D, 3, true>(st, a, t + 3, acc);
     }
-    if (t < a.tend)
+    // tail rows nested, so that no older ring value stays live through the
+    // loop for a tail row that might read it
+    if (t < a.tend) {
         fused_row<T, DIFFUSE_D, 0, true>(st, a, t, acc);
-    if (t + 1 < a.tend)
-        fused_row<T, DIFFUSE_D, 1, true>(st, a, t + 1, acc);
-    if (t + 2 < a.tend)
-        fused_row<T, DIFFUSE_D, 2, true>(st, a, t + 2, acc);
+        if (t + 1 < a.tend) {
+            fused_row<T, DIFFUSE_D, 1, true>(st, a, t + 1, acc);
+            if (t + 2 < a.tend)
+                fused_row<T, DIFFUSE_D, 2, true>(st, a, t + 2, acc);
+        }
+    }
 
 #pragma unroll
     for (int j = 0; j < ADJ_SUMS; ++j)
