@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import TOL, max_rel_l2, sample_nodes, to_gpu, to_np, windowed_oracle
+from gpu_util import TOL, _map, max_rel_l2, sample_nodes, to_gpu, to_np, windowed_oracle
 from paper_2603_19789_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -274,3 +274,36 @@ def test_full_size_4096_sampled(orc, dtype, bc):
     assert np.all(err <= TOL[dtype]), err
     drift = abs(sum(s.total(rho)) - t0) / t0
     assert drift < (1e-12 if dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+def test_bgk_full_size_4096_sampled(orc, dtype, bc):
+    """BGK on the benchmark's 4096x4096 workload (64 foci, R0 = 5), run as the
+    benchmark runs it: sampled nodes against the oracle's BGK on each node's
+    dependence cone (one cell per step). On D2Q5 half-way bounce-back at a
+    wall equals the mirror extension of the field, so no-flux windows are
+    cut from the mirror-extended field and run periodic."""
+    nsteps = 4
+    w = inputs.c2_workload(r0=5.0, nsteps=nsteps)
+    rho0 = w.rho0.copy()
+    rng = np.random.default_rng(23)
+    rho0[1] = rng.uniform(0, 0.02, size=rho0[1].shape)
+    rho0[0] = 1.0 - rho0[1] - rho0[2]
+    b = BGK(w.nx, w.ny, w.params, dtype=dtype, bc=bc)
+    f, rd = b.init(to_gpu(rho0, dtype))
+    b.run(f, rd, nsteps)
+    rho = b.density(f, rd)
+    torch.cuda.synchronize()
+    nodes = sample_nodes(w.nx, w.ny, 60, seed=13)
+    half = nsteps + 1
+    offs = np.arange(-half, half + 1)
+    want = np.empty((len(nodes), 5))
+    for i, (x, y) in enumerate(nodes):
+        win = rho0[:, _map(y + offs, w.ny, bc)][:, :, _map(x + offs, w.nx, bc)]
+        want[i] = orc.bgk_run_density(win, w.params, nsteps, bc="periodic")[:, half, half]
+    xs = torch.tensor([x for x, _ in nodes], device="cuda")
+    ys = torch.tensor([y for _, y in nodes], device="cuda")
+    got = rho[:, ys, xs].T.cpu().double().numpy()
+    err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+    assert np.all(err <= TOL[dtype]), err
