@@ -34,6 +34,14 @@ FLAGS = [
 ]
 
 
+# Per-source additions. The MFMA kernels keep their accumulators in ordinary
+# VGPRs: with the accumulation registers, this compiler copied the running
+# sums of the two-deep convolution pipeline back and forth every step.
+EXTRA_FLAGS = {
+    "surrogate_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def hipcc() -> str:
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     return str(Path(rocm) / "bin" / "hipcc")
@@ -59,7 +67,8 @@ def build(verbose: bool = False) -> Path:
     for name in SOURCES:
         src = CSRC / name
         obj = objdir / (src.stem + ".o")
-        cmds.append([hipcc(), *FLAGS, "-x", "hip", f"-I{INCLUDE}", f"-I{CSRC}", "-c", str(src),
+        cmds.append([hipcc(), *FLAGS, *EXTRA_FLAGS.get(name, []), "-x", "hip", f"-I{INCLUDE}",
+                     f"-I{CSRC}", "-c", str(src),
                      "-o", str(obj)])
         objs.append(str(obj))
     if verbose:

@@ -29,6 +29,12 @@ bool dims_ok(int n, int h, int w) {
            (long long)n * h * w <= (1ll << 34);
 }
 
+// The convolution addresses its input view with 32-bit byte offsets: the
+// view must span less than 2 GiB.
+bool conv_input_fits(int pitch, int n, int h, int w, int c) {
+    return (((long long)n * h * w - 1) * pitch + c) * 2 < (1ll << 31);
+}
+
 bool scales_ok(const float *s) {
     if (!s)
         return false;
@@ -57,7 +63,7 @@ int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin
                         int flags, float slope, void *hip_stream) {
     if (!view_ok(x, x_pitch, cin) || !dims_ok(n, h, w) || !weight || !aligned16(weight) || !y ||
         (flags & ~(SUR_LEAKY | SUR_OUT_F32)) || cout <= 0 || cout > MAX_CHANNELS ||
-        y_pitch < cout || !std::isfinite(slope))
+        y_pitch < cout || !std::isfinite(slope) || !conv_input_fits(x_pitch, n, h, w, cin))
         return SSLBM_E_ARG;
     if (!(flags & SUR_OUT_F32) && !view_ok(y, y_pitch, cout))
         return SSLBM_E_ARG;
@@ -84,7 +90,8 @@ int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w,
                               const void *weight, int cin, void *dx, int dx_pitch,
                               void *flip_scratch, void *hip_stream) {
     if (!view_ok(dz, dz_pitch, cout) || !view_ok(dx, dx_pitch, cin) || !dims_ok(n, h, w) ||
-        !weight || !flip_scratch || !aligned16(flip_scratch))
+        !weight || !flip_scratch || !aligned16(flip_scratch) ||
+        !conv_input_fits(dz_pitch, n, h, w, cout))
         return SSLBM_E_ARG;
     const hipStream_t s = (hipStream_t)hip_stream;
     int st = status(sslbm::launch_flip(weight, cout, cin, flip_scratch, s));

@@ -39,6 +39,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int THREADS = 256;
 
@@ -59,6 +60,17 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
 }
 __device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
 
+// Raw buffer access: the descriptor (base address, byte length) is
+// wavefront-uniform; each lane gives a 32-bit byte offset. Descriptor word 3
+// is the gfx9 raw-buffer format (32-bit data). Offsets at or past the length
+// read zeros. The 16 loaded bytes are taken as one 128-bit integer (taking
+// vector elements one by one lets this compiler narrow the load).
+constexpr int BUF_FORMAT_WORD = 0x00020000;
+__device__ __forceinline__ u32x4 load16(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(
+        u32x4, __builtin_bit_cast(unsigned __int128, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0)));
+}
+
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // Eight BF16 values as one 16-byte vector (element 0 in the low half-word).
@@ -73,10 +85,13 @@ __device__ __forceinline__ uint4 pack8(const uint16_t *v) {
 // pixels x 16 NT channels (4 x NT MFMA tiles). The k loop runs over (tap,
 // 32-channel chunk). Each step's A tile (pixels x 32 channels of the
 // tap-shifted input) and B tile (channels x 32 weights) go through LDS,
-// double-buffered: the global loads of step k + 1 are issued before the
-// MFMAs of step k and written to the other buffer after them, one barrier
-// per step. LDS rows are padded to 40 elements (80 bytes), so the 16 rows a
-// fragment read touches fall into distinct banks.
+// double-buffered, with two steps in flight: while step k is multiplied,
+// step k + 1 (loaded during step k - 1) moves from registers into the other
+// buffer and the loads of step k + 2 are outstanding; one barrier per step.
+// The per-step address work is a few masks and adds: the wrapped rows and
+// columns of the three taps in each direction are computed once per thread.
+// LDS rows are padded to 40 elements (80 bytes), so the 16 rows a fragment
+// read touches fall into distinct banks.
 constexpr int LDA = 40;
 
 template <int WM, int NT, bool F32OUT, bool LEAKY>
@@ -95,13 +110,26 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
     const int wm = wv % WM, wn = wv / WM;
-    const uint16_t *x = static_cast<const uint16_t *>(a.x);
-    const uint16_t *wt = static_cast<const uint16_t *>(a.wt);
+    // Loads go through buffer descriptors over the input view and the
+    // weights (byte offsets are 32-bit; the host checks the sizes). An offset
+    // past the descriptor's range reads zeros: that is how channels past the
+    // end of a layer (cin not a multiple of 32) are filled, with every load
+    // issued unconditionally so that the memory counters stay exact.
+    const long long P_last = P - 1;
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(a.x), (short)0, (int)((P_last * a.x_pitch + a.cin) * 2), BUF_FORMAT_WORD);
+    const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(a.wt), (short)0, a.cout * 9 * a.cin * 2, BUF_FORMAT_WORD);
 
     // loader roles: A piece j of this thread is pixel row (tid + 256 j) / 4,
     // channel chunk (tid + 256 j) % 4; B piece (threads < 4 TC): output
-    // channel row tid / 4, chunk tid % 4
-    int an[APT], ay[APT], ax[APT], arow[APT], ach[APT];
+    // channel row tid / 4, chunk tid % 4. The byte offset of A piece j at tap
+    // (dy, dx) is the offset of the pixel's own row and column plus the
+    // differences to the wrapped rows and columns of the neighbouring taps,
+    // taken through wavefront-uniform bit masks (a select chain on the tap
+    // becomes a lookup table in scratch memory with this compiler).
+    int arow[APT], ach[APT];
+    unsigned ry1[APT], rym[APT], ryp[APT], cx1[APT], cxm[APT], cxp[APT];
     const long long hw = (long long)a.h * a.w;
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
@@ -110,42 +138,65 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
         ach[j] = i & 3;
         long long q = tile * TP + arow[j];
         if (q >= P)
-            q = P - 1;  // a clamped duplicate; its results are never stored
-        an[j] = (int)(q / hw);
-        const int r = (int)(q - an[j] * hw);
-        ay[j] = r / a.w;
-        ax[j] = r - ay[j] * a.w;
+            q = P_last;  // a clamped duplicate; its results are never stored
+        const int n = (int)(q / hw);
+        const int r = (int)(q - n * hw);
+        const int y = r / a.w, xq = r - y * a.w;
+        auto row_off = [&](int d) {
+            return (unsigned)(((long long)n * a.h + wrap(y + d, a.h)) * a.w * a.x_pitch * 2);
+        };
+        auto col_off = [&](int d) {
+            return (unsigned)(wrap(xq + d, a.w) * a.x_pitch * 2 + 16 * ach[j]);
+        };
+        ry1[j] = row_off(0);
+        rym[j] = row_off(-1) - ry1[j];  // modulo 2^32
+        ryp[j] = row_off(1) - ry1[j];
+        cx1[j] = col_off(0);
+        cxm[j] = col_off(-1) - cx1[j];
+        cxp[j] = col_off(1) - cx1[j];
     }
     const bool bload = tid < 4 * TC;
     const int brow = tid >> 2, bch = tid & 3;
     const int bco = min(cg * TC + brow, a.cout - 1);
+    const unsigned boff = (unsigned)((bco * 9 * a.cin + 8 * bch) * 2);
+    constexpr unsigned OUT_OF_RANGE = 0x80000000u;
 
     const int nck = (a.cin + 31) / 32;
     const int steps = 9 * nck;
-    uint4 ra[APT], rb = make_uint4(0, 0, 0, 0);
+    // global loads of step st into registers (past the end: the last step again)
+    struct Stage {
+        u32x4 a[APT];
+        u32x4 b;
+    };
     auto gload = [&](int st) {
-        st = st < steps ? st : steps - 1;  // past the end: reload the last step
+        Stage r;
+        st = st < steps ? st : steps - 1;
         const int t = st / nck;
         const int c0 = (st - t * nck) * 32;
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const int ty = t / 3, tx = t - 3 * ty;  // dy + 1, dx + 1
+        const unsigned my = ty == 0 ? ~0u : 0u, py = ty == 2 ? ~0u : 0u;
+        const unsigned mx = tx == 0 ? ~0u : 0u, px = tx == 2 ? ~0u : 0u;
+        const int left = a.cin - c0;  // channels left in this chunk
 #pragma unroll
         for (int j = 0; j < APT; ++j) {
-            const int cc = c0 + 8 * ach[j];
-            const int yy = wrap(ay[j] + dy, a.h), xx = wrap(ax[j] + dx, a.w);
-            const uint16_t *src = x + (((long long)an[j] * a.h + yy) * a.w + xx) * a.x_pitch + cc;
-            ra[j] = cc < a.cin ? *reinterpret_cast<const uint4 *>(src) : make_uint4(0, 0, 0, 0);
+            const unsigned rr = ry1[j] + (rym[j] & my) + (ryp[j] & py);
+            const unsigned cc = cx1[j] + (cxm[j] & mx) + (cxp[j] & px);
+            const unsigned off = 8 * ach[j] < left ? rr + cc + (unsigned)(2 * c0) : OUT_OF_RANGE;
+            r.a[j] = load16(xr, off);
         }
-        const int cc = c0 + 8 * bch;
-        if (bload)
-            rb = cc < a.cin ? *reinterpret_cast<const uint4 *>(wt + ((long long)bco * 9 + t) * a.cin + cc)
-                            : make_uint4(0, 0, 0, 0);
+        // every thread loads (rows past the tile are clamped duplicates); only
+        // the B-loader threads store
+        const unsigned off =
+            8 * bch < left ? boff + (unsigned)((t * a.cin + c0) * 2) : OUT_OF_RANGE;
+        r.b = load16(wr, off);
+        return r;
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, const Stage &r) {
 #pragma unroll
         for (int j = 0; j < APT; ++j)
-            *reinterpret_cast<uint4 *>(&As[buf][arow[j] * LDA + 8 * ach[j]]) = ra[j];
+            *reinterpret_cast<u32x4 *>(&As[buf][arow[j] * LDA + 8 * ach[j]]) = r.a[j];
         if (bload)
-            *reinterpret_cast<uint4 *>(&Bs[buf][brow * LDA + 8 * bch]) = rb;
+            *reinterpret_cast<u32x4 *>(&Bs[buf][brow * LDA + 8 * bch]) = r.b;
     };
 
     f32x4 acc[4][NT];
@@ -154,13 +205,7 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
 #pragma unroll
         for (int ns = 0; ns < NT; ++ns)
             acc[ms][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int st = 0; st < steps; ++st) {
-        const int buf = st & 1;
-        gload(st + 1);
+    auto compute = [&](int buf) {
         bf16x8 A[4], B[NT];
 #pragma unroll
         for (int ms = 0; ms < 4; ++ms)
@@ -177,9 +222,29 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
             for (int ns = 0; ns < NT; ++ns)
                 acc[ms][ns] =
                     __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ms], B[ns], acc[ms][ns], 0, 0, 0);
-        lstore(buf ^ 1);  // the other buffer was last read before the previous barrier
+    };
+
+    // Two steps in flight: while step st is multiplied out of LDS buffer
+    // st % 2, step st + 1 (loaded during the previous step) goes from
+    // registers into the other buffer and step st + 2 is being loaded. The
+    // loop is unrolled by two so that both register sets are fixed.
+    Stage s0 = gload(0);
+    lstore(0, s0);
+    Stage s1 = gload(1);
+    __syncthreads();
+    int st = 0;
+    for (; st + 1 < steps; st += 2) {
+        s0 = gload(st + 2);
+        compute(0);
+        lstore(1, s1);  // buffer 1 was last read before the previous barrier
+        __syncthreads();
+        s1 = gload(st + 3);
+        compute(1);
+        lstore(0, s0);
         __syncthreads();
     }
+    if (st < steps)
+        compute(0);
 
 #pragma unroll
     for (int ns = 0; ns < NT; ++ns) {

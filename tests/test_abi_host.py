@@ -233,6 +233,11 @@ def test_surrogate_header_exports_and_host_checks(lib):
     assert fwd(a, 16, 1, 8, 8, 12, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG  # cin % 8
     assert fwd(a, 16, 0, 8, 8, 16, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG
     assert fwd(a, 16, 1, 8, 8, 16, b, None, c, 32, 32, 4, 0.1, None) == binding.E_ARG  # flags
+    # the input view must span less than 2 GiB (32-bit byte offsets):
+    # (1 x 8192 x 8192 pixels - 1) x pitch 16 + 16 channels = 2^31 bytes
+    assert fwd(a, 16, 1, 8192, 8192, 16, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG
+    assert lib.sur_conv3x3_backward_data(a, 16, 1, 8192, 8192, 16, b, 8, c, 8, vp(0x400000000),
+                                         None) == binding.E_ARG
     assert lib.sur_conv3x3_backward_weight_workspace(1, 8, 12, 16, 16) == 0  # w % 8
     assert lib.sur_conv3x3_backward_weight_workspace(1, 8, 16, 16, 16) > 0
     ws = lib.sur_conv3x3_backward_weight_workspace(2, 8, 16, 32, 64)
