@@ -82,8 +82,8 @@ __device__ __forceinline__ uint4 pack8(const uint16_t *v) {
 // ------------------------------------------------------------- forward conv
 // A workgroup computes (64 WM) consecutive output pixels x (16 NT WN) output
 // channels, WN = 4 / WM, as a grid of WM x WN wavefronts that each own 64
-// pixels x 16 NT channels (4 x NT MFMA tiles). The k loop runs over (tap,
-// 32-channel chunk). Each step's A tile (pixels x 32 channels of the
+// pixels x 16 NT channels (4 x NT MFMA tiles). The k loop runs over
+// (32-channel chunk, tap). Each step's A tile (pixels x 32 channels of the
 // tap-shifted input) and B tile (channels x 32 weights) go through LDS,
 // double-buffered, with two steps in flight: while step k is multiplied,
 // step k + 1 (loaded during step k - 1) moves from registers into the other
@@ -171,8 +171,9 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
     auto gload = [&](int st) {
         Stage r;
         st = st < steps ? st : steps - 1;
-        const int t = st / nck;
-        const int c0 = (st - t * nck) * 32;
+        const int ck = st / 9;  // k order (chunk, tap), as in the halo kernel
+        const int t = st - 9 * ck;
+        const int c0 = 32 * ck;
         const int ty = t / 3, tx = t - 3 * ty;  // dy + 1, dx + 1
         const unsigned my = ty == 0 ? ~0u : 0u, py = ty == 2 ? ~0u : 0u;
         const unsigned mx = tx == 0 ? ~0u : 0u, px = tx == 2 ? ~0u : 0u;
@@ -267,6 +268,262 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
                 else
                     static_cast<uint16_t *>(a.y)[q * a.y_pitch + c] = to_bf16(v);
             }
+    }
+}
+
+// ------------------------------------------------ forward conv, halo tiles
+// The tiled kernel above reloads the tap-shifted input tile at each of the
+// nine taps: 16-32 KB from L2 per 8 MFMAs per wavefront. Here a workgroup
+// owns an output tile of 8 rows x 32 columns of one image and 16 NT output
+// channels (channel group cg; 4 wavefronts of 2 rows x 32 columns x 16 NT
+// channels) and, per 32-channel chunk, loads the input tile with its
+// one-pixel halo (10 x 34 pixels, periodic wrap) and the weights of all
+// nine taps into LDS once; the nine taps then read shifted fragments of the
+// same halo tile, at offsets known at compile time. The grid holds as many
+// workgroups as are resident at once; workgroup b takes the units (tile,
+// channel group) b, b + G, b + 2G, ... (G the grid size; the groups of a
+// tile are consecutive units, so they run side by side and share the halo
+// through L2), and the loads of its next (unit, chunk) item are in flight
+// while the current one is multiplied. The k order is (chunk, tap), as in
+// the tiled kernel, so both give the same bits. Needs h >= 8 and w >= 32
+// (a halo wraps at most once).
+constexpr int HALO_TH = 8, HALO_TW = 32;
+
+// LDS use (50 KB for 32 channels, 73 KB for 64) allows 3 or 2 workgroups
+// per CU; the register budget is held to the same occupancy.
+template <int NT, bool F32OUT, bool LEAKY>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(NT == 4 ? 2 : 3)))
+void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
+    constexpr int HW2 = HALO_TW + 2, HPIX = (HALO_TH + 2) * HW2;
+    constexpr int HP = HPIX * 4, HPT = (HP + THREADS - 1) / THREADS;  // 16-byte pieces
+    constexpr int TC = 16 * NT;
+    constexpr int BP = 9 * TC * 4, BPT = (BP + THREADS - 1) / THREADS;
+    constexpr unsigned OUT_OF_RANGE = 0x80000000u;
+    __shared__ __attribute__((aligned(16))) uint16_t Hs[HPIX * LDA];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[9 * TC * LDA];
+    __shared__ __attribute__((aligned(16))) float Cs[TC];  // bias of the group
+
+    const int G = gridDim.x;
+    if ((int)blockIdx.x >= units)
+        return;  // whole workgroup, before any barrier
+    const int groups = (a.cout + TC - 1) / TC;
+    const int nck = (a.cin + 31) / 32;
+    const int items = ((units - 1 - (int)blockIdx.x) / G + 1) * nck;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int m = lane & 15, g = lane >> 4;
+    const long long P = (long long)a.n * a.h * a.w;
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(a.x), (short)0, (int)(((P - 1) * a.x_pitch + a.cin) * 2), BUF_FORMAT_WORD);
+    const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void *>(a.wt), (short)0, a.cout * 9 * a.cin * 2, BUF_FORMAT_WORD);
+    // the bias goes through LDS with the weights (no bias: a range of 0 bytes
+    // reads zeros); channels past the layer's read zeros as well
+    const __amdgpu_buffer_rsrc_t br = __builtin_amdgcn_make_buffer_rsrc(
+        a.bias ? const_cast<float *>(a.bias) : const_cast<void *>(a.wt), (short)0,
+        a.bias ? a.cout * 4 : 0, BUF_FORMAT_WORD);
+    const bool cload = tid < TC / 4;
+
+    // weight pieces: row (tap t, channel o of the group) of Bs, 8 channels k
+    // of the chunk; channels past the layer's load its last one (their
+    // results are never stored)
+    unsigned boff[BPT], coff = 0;
+    int bk[BPT], blds[BPT], bt[BPT], bo[BPT];
+    bool bst[BPT];
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+        const int e = tid + THREADS * j;
+        bst[j] = e < BP;
+        const int row = min(e >> 2, 9 * TC - 1), k = e & 3;
+        bt[j] = row / TC;
+        bo[j] = row - bt[j] * TC;
+        bk[j] = 8 * k;
+        blds[j] = row * LDA + 8 * k;
+    }
+    // halo pieces: pixel hp of the halo tile, 8 channels k of the chunk
+    unsigned hoff[HPT];
+    int hk[HPT], hlds[HPT], hy[HPT], hx[HPT];
+    bool hst[HPT];
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int e = tid + THREADS * j;
+        hst[j] = e < HP;
+        const int hp = min(e >> 2, HPIX - 1), k = e & 3;
+        hy[j] = hp / HW2;
+        hx[j] = hp - hy[j] * HW2;
+        hk[j] = 8 * k;
+        hlds[j] = hp * LDA + 8 * k;
+    }
+    auto unit_origin = [&](int unit, int &n, int &y0, int &x0, int &cg) {
+        const int tile = unit / groups;
+        cg = unit - tile * groups;
+        const int per_image = tiles_x * tiles_y;
+        n = tile / per_image;
+        const int r = tile - n * per_image;
+        const int ty = r / tiles_x;
+        y0 = ty * HALO_TH;
+        x0 = (r - ty * tiles_x) * HALO_TW;
+    };
+    auto unit_offsets = [&](int unit) {
+        int n, y0, x0, cg;
+        unit_origin(unit, n, y0, x0, cg);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int y = wrap(y0 - 1 + hy[j], a.h), x = wrap(x0 - 1 + hx[j], a.w);
+            hoff[j] = (unsigned)(((((long long)n * a.h + y) * a.w + x) * a.x_pitch + hk[j]) * 2);
+        }
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const int o = min(cg * TC + bo[j], a.cout - 1);
+            boff[j] = (unsigned)(((o * 9 + bt[j]) * a.cin + bk[j]) * 2);
+        }
+        coff = cload ? (unsigned)((cg * TC + 4 * tid) * 4) : OUT_OF_RANGE;
+    };
+
+    struct Stage {
+        u32x4 h[HPT];
+        u32x4 b[BPT];
+        u32x4 c;
+    };
+    // loads of one chunk (the weights and bias only when they change between
+    // items)
+    auto gload = [&](int chunk, bool weights) {
+        Stage r;
+        const int left = a.cin - 32 * chunk;
+        const unsigned c2 = (unsigned)(64 * chunk);
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+            r.h[j] = load16(xr, hst[j] && hk[j] < left ? hoff[j] + c2 : OUT_OF_RANGE);
+        if (weights) {
+#pragma unroll
+            for (int j = 0; j < BPT; ++j)
+                r.b[j] = load16(wr, bst[j] && bk[j] < left ? boff[j] + c2 : OUT_OF_RANGE);
+            r.c = load16(br, coff);
+        }
+        return r;
+    };
+    auto lstore = [&](const Stage &r, bool weights) {
+#pragma unroll
+        for (int j = 0; j < HPT; ++j)
+            if (hst[j])
+                *reinterpret_cast<u32x4 *>(&Hs[hlds[j]]) = r.h[j];
+        if (weights) {
+#pragma unroll
+            for (int j = 0; j < BPT; ++j)
+                if (bst[j])
+                    *reinterpret_cast<u32x4 *>(&Bs[blds[j]]) = r.b[j];
+            if (cload)
+                *reinterpret_cast<u32x4 *>(&Cs[4 * tid]) = r.c;
+        }
+    };
+    f32x4 acc[4][NT];
+    auto clear = [&]() {
+#pragma unroll
+        for (int ms = 0; ms < 4; ++ms)
+#pragma unroll
+            for (int ns = 0; ns < NT; ++ns)
+                acc[ms][ns] = f32x4{0.f, 0.f, 0.f, 0.f};
+    };
+    // fragment ms of wavefront wv: tile row 2 wv + ms / 2, columns
+    // 16 (ms % 2) .. + 15; at tap (dy, dx) it reads halo pixel
+    // (row + 1 + dy, column + 1 + dx)
+    const uint16_t *ha = &Hs[(2 * wv * HW2 + m) * LDA + 8 * g];
+    const uint16_t *hb = &Bs[m * LDA + 8 * g];
+    auto taps = [&]() {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t % 3;  // shifted by one
+            bf16x8 A[4], B[NT];
+#pragma unroll
+            for (int ms = 0; ms < 4; ++ms)
+                A[ms] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(
+                                ha + ((ms / 2 + dy) * HW2 + 16 * (ms % 2) + dx) * LDA));
+#pragma unroll
+            for (int ns = 0; ns < NT; ++ns)
+                B[ns] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const uint4 *>(hb + (t * TC + 16 * ns) * LDA));
+#pragma unroll
+            for (int ms = 0; ms < 4; ++ms)
+#pragma unroll
+                for (int ns = 0; ns < NT; ++ns)
+                    acc[ms][ns] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ms], B[ns], acc[ms][ns], 0, 0, 0);
+        }
+    };
+    // Output through a buffer descriptor: 32-bit offsets built from the
+    // row's offset (wavefront-uniform) and the lane's column and channel;
+    // pixels past the image's right edge and channels past the layer's get
+    // an offset past the range, and the hardware drops those stores.
+    constexpr int ESZ = F32OUT ? 4 : 2;
+    const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
+        a.y, (short)0, (int)(((P - 1) * a.y_pitch + a.cout) * ESZ), BUF_FORMAT_WORD);
+    const unsigned ypb = (unsigned)(a.y_pitch * ESZ);  // bytes per pixel
+    auto epilogue = [&](int unit) {
+        int n, y0, x0, cg;
+        unit_origin(unit, n, y0, x0, cg);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int y = y0 + 2 * wv + r;
+            if (y >= a.h)
+                continue;  // wavefront-uniform
+            const unsigned row = (unsigned)((((long long)n * a.h + y) * a.w + x0) * ypb);
+#pragma unroll
+            for (int ns = 0; ns < NT; ++ns) {
+                const int c = cg * TC + 16 * ns + m;
+                const float b = Cs[16 * ns + m];
+                const unsigned lane_off = row + (unsigned)(4 * g) * ypb + (unsigned)(c * ESZ);
+#pragma unroll
+                for (int ms = 2 * r; ms < 2 * r + 2; ++ms)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int col = 16 * (ms % 2) + i;  // plus 4 g
+                        const bool ok = c < a.cout && x0 + col + 4 * g < a.w;
+                        const unsigned off = ok ? lane_off + (unsigned)col * ypb : OUT_OF_RANGE;
+                        float v = acc[ms][ns][i] + b;
+                        if (LEAKY)
+                            v = v > 0.f ? v : a.slope * v;
+                        if (F32OUT)
+                            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v),
+                                                                  yr, off, 0, 0);
+                        else
+                            __builtin_amdgcn_raw_buffer_store_b16(
+                                __builtin_bit_cast(unsigned short, (__bf16)v), yr, off, 0, 0);
+                    }
+            }
+        }
+    };
+
+    int unit = blockIdx.x, chunk = 0;
+    unit_offsets(unit);
+    Stage st = gload(0, true);
+    lstore(st, true);
+    __syncthreads();
+    clear();
+    // with one chunk and one channel group the weights stay in LDS
+    const bool reload_b = nck > 1 || groups > 1;
+    for (int it = 0; it < items; ++it) {
+        int nunit = unit, nchunk = chunk + 1;
+        if (nchunk == nck) {
+            nchunk = 0;
+            nunit += G;
+        }
+        const bool more = it + 1 < items;
+        if (more) {
+            if (nunit != unit)
+                unit_offsets(nunit);
+            st = gload(nchunk, reload_b);
+        }
+        taps();
+        if (chunk == nck - 1) {
+            epilogue(unit);
+            clear();
+        }
+        __syncthreads();  // every wavefront is done with the LDS tiles
+        if (more)
+            lstore(st, reload_b);
+        __syncthreads();
+        unit = nunit;
+        chunk = nchunk;
     }
 }
 
@@ -469,7 +726,22 @@ __global__ __launch_bounds__(THREADS) void wgrad_reduce_kernel(const float *__re
 }
 
 // --------------------------------------------------------- elementwise ops
-// Each thread handles 8 channels of one pixel.
+// Each thread handles 8 channels of one pixel as one 16-byte access per
+// operand (views are 16-byte aligned with pitches and channel counts that
+// are multiples of 8).
+__device__ __forceinline__ u32x4 ld8(const uint16_t *p) {
+    return *reinterpret_cast<const u32x4 *>(p);
+}
+__device__ __forceinline__ void st8(uint16_t *p, u32x4 v) { *reinterpret_cast<u32x4 *>(p) = v; }
+// the BF16 values 2k and 2k + 1 of an 8-value vector as floats
+__device__ __forceinline__ float lo_of(unsigned w) { return __builtin_bit_cast(float, w << 16); }
+__device__ __forceinline__ float hi_of(unsigned w) {
+    return __builtin_bit_cast(float, w & 0xffff0000u);
+}
+__device__ __forceinline__ unsigned pack2(float lo, float hi) {
+    return (unsigned)to_bf16(lo) | ((unsigned)to_bf16(hi) << 16);
+}
+
 __global__ __launch_bounds__(THREADS) void leaky_bwd_kernel(const uint16_t *__restrict__ dy,
                                                             int dyp, const uint16_t *__restrict__ y,
                                                             int yp, uint16_t *__restrict__ dz,
@@ -481,12 +753,14 @@ __global__ __launch_bounds__(THREADS) void leaky_bwd_kernel(const uint16_t *__re
         return;
     const long long q = e / c8;
     const int ch = (int)(e - q * c8) * 8;
+    const u32x4 d = ld8(dy + q * dyp + ch), v = ld8(y + q * yp + ch);
+    u32x4 o;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const float d = from_bf16(dy[q * dyp + ch + j]);
-        const float v = from_bf16(y[q * yp + ch + j]);
-        dz[q * dzp + ch + j] = to_bf16(v > 0.f ? d : slope * d);
+    for (int k = 0; k < 4; ++k) {
+        const float d0 = lo_of(d[k]), d1 = hi_of(d[k]);
+        o[k] = pack2(lo_of(v[k]) > 0.f ? d0 : slope * d0, hi_of(v[k]) > 0.f ? d1 : slope * d1);
     }
+    st8(dz + q * dzp + ch, o);
 }
 
 // y (n, h/2, w/2) = mean of 2x2 windows of x (n, h, w)
@@ -503,16 +777,17 @@ __global__ __launch_bounds__(THREADS) void pool2_kernel(const uint16_t *__restri
     const long long r = q / wo;
     const int yo = (int)(r % ho);
     const int nn = (int)(r / ho);
+    const uint16_t *p = x + (((long long)nn * h + 2 * yo) * w + 2 * xo) * xp + ch;
+    const long long down = (long long)w * xp;
+    const u32x4 v00 = ld8(p), v01 = ld8(p + xp), v10 = ld8(p + down), v11 = ld8(p + down + xp);
+    u32x4 o;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        float s = 0.f;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-                s += from_bf16(x[(((long long)nn * h + 2 * yo + a) * w + 2 * xo + b) * xp + ch + j]);
-        y[q * yp + ch + j] = to_bf16(0.25f * s);
+    for (int k = 0; k < 4; ++k) {
+        const float s0 = ((lo_of(v00[k]) + lo_of(v01[k])) + lo_of(v10[k])) + lo_of(v11[k]);
+        const float s1 = ((hi_of(v00[k]) + hi_of(v01[k])) + hi_of(v10[k])) + hi_of(v11[k]);
+        o[k] = pack2(0.25f * s0, 0.25f * s1);
     }
+    st8(y + q * yp + ch, o);
 }
 
 // dx (n, h, w) (+)= dy (n, h/2, w/2) / 4 at the window's four inputs
@@ -531,13 +806,19 @@ __global__ __launch_bounds__(THREADS) void pool2_bwd_kernel(const uint16_t *__re
     const int yy = (int)(r % h);
     const int nn = (int)(r / h);
     const long long qo = ((long long)nn * (h / 2) + yy / 2) * (w / 2) + xx / 2;
+    const u32x4 d = ld8(dy + qo * dyp + ch);
+    u32x4 o;
+    if (accumulate) {
+        const u32x4 v = ld8(dx + q * dxp + ch);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        float v = 0.25f * from_bf16(dy[qo * dyp + ch + j]);
-        if (accumulate)
-            v += from_bf16(dx[q * dxp + ch + j]);
-        dx[q * dxp + ch + j] = to_bf16(v);
+        for (int k = 0; k < 4; ++k)
+            o[k] = pack2(0.25f * lo_of(d[k]) + lo_of(v[k]), 0.25f * hi_of(d[k]) + hi_of(v[k]));
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            o[k] = pack2(0.25f * lo_of(d[k]), 0.25f * hi_of(d[k]));
     }
+    st8(dx + q * dxp + ch, o);
 }
 
 // y (n, 2h, 2w) = x (n, h, w) repeated over 2x2 windows
@@ -555,7 +836,7 @@ __global__ __launch_bounds__(THREADS) void up2_kernel(const uint16_t *__restrict
     const int yy = (int)(r % H);
     const int nn = (int)(r / H);
     const long long qi = ((long long)nn * h + yy / 2) * w + xx / 2;
-    *reinterpret_cast<uint4 *>(y + q * yp + ch) = *reinterpret_cast<const uint4 *>(x + qi * xp + ch);
+    st8(y + q * yp + ch, ld8(x + qi * xp + ch));
 }
 
 // dx (n, h, w) = sum of dy (n, 2h, 2w) over each 2x2 window
@@ -572,17 +853,17 @@ __global__ __launch_bounds__(THREADS) void up2_bwd_kernel(const uint16_t *__rest
     const long long r = q / w;
     const int yy = (int)(r % h);
     const int nn = (int)(r / h);
+    const uint16_t *p = dy + (((long long)nn * 2 * h + 2 * yy) * 2 * w + 2 * xx) * dyp + ch;
+    const long long down = 2LL * w * dyp;
+    const u32x4 v00 = ld8(p), v01 = ld8(p + dyp), v10 = ld8(p + down), v11 = ld8(p + down + dyp);
+    u32x4 o;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        float s = 0.f;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-                s += from_bf16(
-                    dy[(((long long)nn * 2 * h + 2 * yy + a) * 2 * w + 2 * xx + b) * dyp + ch + j]);
-        dx[q * dxp + ch + j] = to_bf16(s);
+    for (int k = 0; k < 4; ++k) {
+        const float s0 = ((lo_of(v00[k]) + lo_of(v01[k])) + lo_of(v10[k])) + lo_of(v11[k]);
+        const float s1 = ((hi_of(v00[k]) + hi_of(v01[k])) + hi_of(v10[k])) + hi_of(v11[k]);
+        o[k] = pack2(s0, s1);
     }
+    st8(dx + q * dxp + ch, o);
 }
 
 // ------------------------------------------------- surrogate input / output
@@ -755,10 +1036,61 @@ static void conv_fwd_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t
         hipLaunchKernelGGL((conv_fwd_kernel<WM, NT, false, false>), grid, block, 0, s, a);
 }
 
-// Workgroup tiles: 128 pixels x 64 channels for wide layers, 256 x 32 and
-// 256 x 16 for narrow ones (no channel tile wider than the layer).
+// Workgroups of kernel f (256 threads) resident on the current device at
+// once, from its register and LDS use; 0 if the runtime cannot say.
+static int resident_workgroups(const void *f) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, THREADS, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return cus * per_cu;
+}
+
+template <int NT>
+static void conv_halo_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
+    const int tiles_x = (a.w + HALO_TW - 1) / HALO_TW, tiles_y = (a.h + HALO_TH - 1) / HALO_TH;
+    const int units = a.n * tiles_x * tiles_y * ((a.cout + 16 * NT - 1) / (16 * NT));
+    const void *f = f32out ? (leaky ? (const void *)conv_halo_kernel<NT, true, true>
+                                    : (const void *)conv_halo_kernel<NT, true, false>)
+                           : (leaky ? (const void *)conv_halo_kernel<NT, false, true>
+                                    : (const void *)conv_halo_kernel<NT, false, false>);
+    const int resident = resident_workgroups(f);
+    const int blocks = resident > 0 && resident < units ? resident : units;
+    const dim3 grid((unsigned)blocks), block(THREADS);
+    if (f32out && leaky)
+        hipLaunchKernelGGL((conv_halo_kernel<NT, true, true>), grid, block, 0, s, a, tiles_x,
+                           tiles_y, units);
+    else if (f32out)
+        hipLaunchKernelGGL((conv_halo_kernel<NT, true, false>), grid, block, 0, s, a, tiles_x,
+                           tiles_y, units);
+    else if (leaky)
+        hipLaunchKernelGGL((conv_halo_kernel<NT, false, true>), grid, block, 0, s, a, tiles_x,
+                           tiles_y, units);
+    else
+        hipLaunchKernelGGL((conv_halo_kernel<NT, false, false>), grid, block, 0, s, a, tiles_x,
+                           tiles_y, units);
+}
+
+// Images of at least 8 x 32 pixels: halo tiles of 16, 32 or 64 output
+// channels. Smaller images: workgroup tiles of 128 pixels x 64 channels for
+// wide layers, 256 x 32 and 256 x 16 for narrow ones (no channel tile wider
+// than the layer).
 hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
-    if (a.cout >= 64)
+    const long long units = (long long)a.n * ((a.h + HALO_TH - 1) / HALO_TH) *
+                            ((a.w + HALO_TW - 1) / HALO_TW) * ((a.cout + 15) / 16);
+    const long long out_bytes =
+        (((long long)a.n * a.h * a.w - 1) * a.y_pitch + a.cout) * (f32out ? 4 : 2);
+    if (a.h >= HALO_TH && a.w >= HALO_TW && units < (1ll << 31) && out_bytes < (1ll << 31)) {
+        if (a.cout > 32)
+            conv_halo_cfg<4>(a, leaky, f32out, s);
+        else if (a.cout > 16)
+            conv_halo_cfg<2>(a, leaky, f32out, s);
+        else
+            conv_halo_cfg<1>(a, leaky, f32out, s);
+    } else if (a.cout >= 64)
         conv_fwd_cfg<2, 2>(a, leaky, f32out, s);
     else if (a.cout > 16)
         conv_fwd_cfg<4, 2>(a, leaky, f32out, s);

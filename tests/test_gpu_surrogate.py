@@ -51,10 +51,20 @@ CONV_CASES = [
     (1, 8, 8, 16, 16), (2, 16, 24, 16, 32), (1, 32, 32, 32, 32), (2, 8, 16, 64, 128),
     (1, 16, 16, 96, 32), (1, 9, 7, 24, 48), (1, 5, 13, 8, 40), (3, 4, 8, 384, 128),
 ]
+# Images of at least 8 x 32 pixels take 8 x 32-pixel halo tiles: whole and
+# ragged tiles, one and several 32-channel chunks (40 = a partial second
+# chunk), channel groups of 16, 32 and 64 (one group, several, a partly
+# used last group), and more (tile, group) units than resident workgroups
+# (each workgroup then takes several, some one more than others).
+HALO_CASES = [
+    (2, 16, 32, 16, 32), (1, 19, 45, 96, 32), (3, 8, 40, 32, 16), (1, 13, 33, 40, 24),
+    (11, 248, 224, 16, 16), (9, 64, 352, 40, 24), (2, 16, 32, 32, 64), (1, 19, 45, 40, 128),
+    (3, 8, 64, 64, 96), (1, 32, 32, 384, 128), (9, 64, 96, 32, 256),
+]
 
 
 @pytest.mark.parametrize("flags", [0, S.LEAKY, S.OUT_F32])
-@pytest.mark.parametrize("n,h,w,cin,cout", CONV_CASES)
+@pytest.mark.parametrize("n,h,w,cin,cout", CONV_CASES + HALO_CASES)
 def test_conv_forward(n, h, w, cin, cout, flags):
     print(f"conv fwd n={n} {h}x{w} {cin}->{cout} flags={flags}", flush=True)
     # input as a channel slice of a wider buffer (pitch > channels, offset 8)
@@ -76,7 +86,25 @@ def test_conv_forward(n, h, w, cin, cout, flags):
     check_close(y.float().cpu().numpy(), want, scale, 1e-6 if f32 else 2 ** -8, "forward")
 
 
-@pytest.mark.parametrize("n,h,w,cin,cout", CONV_CASES[:6])
+@pytest.mark.parametrize("n,h,w,cin,cout", [(1, 9, 7, 24, 48), (2, 16, 40, 40, 24),
+                                             (1, 8, 32, 32, 96)])
+def test_conv_forward_without_bias(n, h, w, cin, cout):
+    """A NULL bias adds nothing (tiled and halo-tile kernels)."""
+    print(f"conv fwd no bias n={n} {h}x{w} {cin}->{cout}", flush=True)
+    x, xv = bf16_array((n, h, w, cin))
+    wt, wv = bf16_array((cout, 9, cin), scale=1.0 / np.sqrt(9 * cin))
+    y = torch.zeros((n, h, w, cout), dtype=torch.float32, device="cuda")
+    st = lib().sur_conv3x3_forward(p(x), cin, n, h, w, cin, p(wt), None, p(y), cout, cout,
+                                   S.OUT_F32, 0.1, None)
+    assert st == binding.OK
+    torch.cuda.synchronize()
+    want = O.conv3x3(xv, wv)
+    check_close(y.cpu().numpy(), want, O.conv3x3(np.abs(xv), np.abs(wv)), 1e-6, "forward")
+
+
+@pytest.mark.parametrize("n,h,w,cin,cout",
+                         CONV_CASES[:6] + [(2, 16, 32, 16, 32), (1, 19, 45, 24, 40),
+                                           (2, 16, 32, 128, 64)])
 def test_conv_backward_data(n, h, w, cin, cout):
     print(f"conv bwd-data n={n} {h}x{w} {cin}->{cout}", flush=True)
     dz, dzv = bf16_array((n, h, w, cout))
