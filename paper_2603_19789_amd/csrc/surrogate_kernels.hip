@@ -31,6 +31,7 @@
 
 #include <cstdint>
 
+#include "seird_device.h"  // xcd_tile
 #include "surrogate_internal.h"
 
 namespace sslbm {
@@ -632,7 +633,9 @@ __global__ __launch_bounds__(THREADS) void bias_sum_kernel(const float *__restri
 // over the pixel range of its split; FP32 partial sums to part[split].
 template <int NI>
 __global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
-    const int wave = blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6);
+    // consecutive waves are the (tap, block) tiles of one pixel range: kept
+    // on one XCD, they read that range from HBM once into its L2
+    const int wave = xcd_tile(blockIdx.x, gridDim.x) * (THREADS / 64) + (threadIdx.x >> 6);
     const int ot = (a.cout + 31) / 32, it = (a.cin + 16 * NI - 1) / (16 * NI);
     const int per_split = ot * it * 9;
     const int split = wave / per_split;
@@ -671,28 +674,62 @@ __global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
     long long k1 = k0 + a.chunk;
     if (k1 > a.Pp)
         k1 = a.Pp;
+    // The lane's 8 pixels q .. q + 7 lie in one row (w % 8 == 0). Its image,
+    // row and column are found once and then advanced with the pixel index,
+    // so the row shift dy (with its periodic wrap) costs no division per
+    // step; padding pixels (q >= P, zero in both planes) are not shifted.
     const long long hw = (long long)a.h * a.w;
-    for (long long q0 = k0; q0 < k1; q0 += 32) {
-        const long long q = q0 + 8 * g;  // 8 pixels of one row (w % 8 == 0)
-        long long qs = q;
-        if (q < a.P) {
-            const long long nn = q / hw;
-            const int rr = (int)(q - nn * hw);
-            const int yy = wrap(rr / a.w + dy, a.h);
-            qs = (nn * a.h + yy) * a.w + (rr - (rr / a.w) * a.w);
+    long long q = k0 + 8 * g;
+    int yy, xx;
+    {
+        const long long nn = q / hw;
+        const int rr = (int)(q - nn * hw);
+        yy = rr / a.w;
+        xx = rr - yy * a.w;
+    }
+    auto shifted = [&]() {
+        long long qs = q + (long long)dy * a.w;
+        if (q >= a.P)
+            qs = q;
+        else if (yy + dy < 0)
+            qs += hw;
+        else if (yy + dy >= a.h)
+            qs -= hw;
+        return qs;
+    };
+    auto advance = [&]() {
+        q += 32;
+        xx += 32;
+        while (xx >= a.w) {
+            xx -= a.w;
+            if (++yy == a.h)
+                yy = 0;
         }
-        bf16x8 A[2], B[NI];
+    };
+    // four k steps of 32 pixels per trip (chunks are multiples of 128): their
+    // loads are issued together, then their MFMAs
+    constexpr int KB = 4;
+    for (long long q0 = k0; q0 < k1; q0 += 32 * KB) {
+        bf16x8 A[KB][2], B[KB][NI];
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-            A[u] = load8(dz + (long long)o[u] * a.Pp + q);
+        for (int kb = 0; kb < KB; ++kb) {
+            const long long qs = shifted();
 #pragma unroll
-        for (int v = 0; v < NI; ++v)
-            B[v] = load8(xs + (long long)i[v] * a.Pp + qs);
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < 2; ++u)
+                A[kb][u] = load8(dz + (long long)o[u] * a.Pp + q);
 #pragma unroll
             for (int v = 0; v < NI; ++v)
-                acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[u], B[v], acc[u][v], 0, 0, 0);
+                B[kb][v] = load8(xs + (long long)i[v] * a.Pp + qs);
+            advance();
+        }
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < NI; ++v)
+                    acc[u][v] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[kb][u], B[kb][v], acc[u][v], 0, 0, 0);
     }
     // result rows (output channels) 4 g + j of subtile u, column m of subtile v
     float *part = a.part + (long long)split * a.cout * 9 * a.cin;
@@ -712,7 +749,26 @@ __global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
         }
 }
 
-// dW = sum over splits (fixed order); db[o] = sum over pixels of dz_t[o][:].
+// dW = sum over splits in a fixed order, in two passes: pass 1 sums each
+// run of RED_RUN consecutive splits (in order) into the run's first slot,
+// pass 2 sums the runs in order. db[o] = sum over pixels of dz_t[o][:].
+constexpr int RED_RUN = 16;
+
+__global__ __launch_bounds__(THREADS) void wgrad_runs_kernel(float *__restrict__ part, int splits,
+                                                             long long count) {
+    const long long t = (long long)blockIdx.x * THREADS + threadIdx.x;
+    const int runs = (splits + RED_RUN - 1) / RED_RUN;
+    if (t >= count * runs)
+        return;
+    const int run = (int)(t / count);
+    const long long e = t - run * count;
+    const int k0 = run * RED_RUN, k1 = min(k0 + RED_RUN, splits);
+    float s = 0.f;
+    for (int k = k0; k < k1; ++k)
+        s += part[k * count + e];
+    part[k0 * count + e] = s;  // only this thread reads or writes these slots
+}
+
 __global__ __launch_bounds__(THREADS) void wgrad_reduce_kernel(const float *__restrict__ part,
                                                                int splits, long long count,
                                                                float *__restrict__ dw) {
@@ -720,7 +776,7 @@ __global__ __launch_bounds__(THREADS) void wgrad_reduce_kernel(const float *__re
     if (e >= count)
         return;
     float s = 0.f;
-    for (int k = 0; k < splits; ++k)
+    for (int k = 0; k < splits; k += RED_RUN)
         s += part[k * count + e];
     dw[e] = s;
 }
@@ -1109,7 +1165,7 @@ hipError_t launch_flip(const void *w, int cout, int cin, void *wf, hipStream_t s
 WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
     WgradPlan p;
     p.P = (long long)n * h * w;
-    p.Pp = (p.P + 31) / 32 * 32;
+    p.Pp = (p.P + 127) / 128 * 128;  // whole trips of four 32-pixel k steps
     p.ni = cin > 16 ? 2 : 1;
     const long long tiles = (long long)((cout + 31) / 32) * ((cin + 16 * p.ni - 1) / (16 * p.ni)) * 9;
     long long splits = 4096 / tiles;  // about 4096 wavefronts in all
@@ -1119,7 +1175,7 @@ WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
     if (splits > max_splits)
         splits = max_splits > 0 ? max_splits : 1;
     long long chunk = (p.Pp + splits - 1) / splits;
-    chunk = (chunk + 31) / 32 * 32;
+    chunk = (chunk + 127) / 128 * 128;
     p.splits = (int)((p.Pp + chunk - 1) / chunk);
     p.chunk = chunk;
     p.waves = tiles * p.splits;
@@ -1169,6 +1225,9 @@ hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, i
     else
         hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(THREADS), 0, s, a);
     const long long count = (long long)cout * 9 * cin;
+    const long long runs = (p.splits + RED_RUN - 1) / RED_RUN;
+    hipLaunchKernelGGL(wgrad_runs_kernel, dim3(blocks_for(count * runs)), dim3(THREADS), 0, s,
+                       part, p.splits, count);
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for(count)), dim3(THREADS), 0, s, part,
                        p.splits, count, dw);
     if (db) {
