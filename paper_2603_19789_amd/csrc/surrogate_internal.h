@@ -30,12 +30,12 @@ struct WgradArgs {
     const uint16_t *dz_t, *xs;
     float *part;
     int n, h, w, cin, cout;
-    long long P, Pp, chunk;
+    long long P, Pr, Pp, chunk;  // pixels; rounded to 128; plane length
     int splits;
 };
 
 struct WgradPlan {
-    long long P, Pp, chunk, waves;
+    long long P, Pr, Pp, chunk, waves;
     int splits, ni;
     size_t dz_t_bytes, xs_bytes, part_bytes;
     size_t bytes() const { return align256(dz_t_bytes) + align256(xs_bytes) + align256(part_bytes); }

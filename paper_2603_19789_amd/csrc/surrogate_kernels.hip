@@ -672,8 +672,8 @@ __global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
 
     const long long k0 = (long long)split * a.chunk;
     long long k1 = k0 + a.chunk;
-    if (k1 > a.Pp)
-        k1 = a.Pp;
+    if (k1 > a.Pr)
+        k1 = a.Pr;
     // The lane's 8 pixels q .. q + 7 lie in one row (w % 8 == 0). Its image,
     // row and column are found once and then advanced with the pixel index,
     // so the row shift dy (with its periodic wrap) costs no division per
@@ -706,7 +706,7 @@ __global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
                 yy = 0;
         }
     };
-    // four k steps of 32 pixels per trip (chunks are multiples of 128): their
+    // four k steps of 32 pixels per trip (ranges are multiples of 128): their
     // loads are issued together, then their MFMAs
     constexpr int KB = 4;
     for (long long q0 = k0; q0 < k1; q0 += 32 * KB) {
@@ -1165,18 +1165,24 @@ hipError_t launch_flip(const void *w, int cout, int cin, void *wf, hipStream_t s
 WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
     WgradPlan p;
     p.P = (long long)n * h * w;
-    p.Pp = (p.P + 127) / 128 * 128;  // whole trips of four 32-pixel k steps
+    // k runs over Pr = P rounded up to whole trips of four 32-pixel k steps.
+    // The planes are 1152 pixels (2304 bytes) longer, so that they are not a
+    // power of two apart: pixel counts here are powers of two, and the 16
+    // planes a fragment load reads at one offset then fell on the same memory
+    // channel and cache set (the weight-gradient GEMM ran 10% slower).
+    p.Pr = (p.P + 127) / 128 * 128;
+    p.Pp = p.Pr + 1152;
     p.ni = cin > 16 ? 2 : 1;
     const long long tiles = (long long)((cout + 31) / 32) * ((cin + 16 * p.ni - 1) / (16 * p.ni)) * 9;
     long long splits = 4096 / tiles;  // about 4096 wavefronts in all
     if (splits < 1)
         splits = 1;
-    const long long max_splits = p.Pp / 256;  // at least 256 pixels each
+    const long long max_splits = p.Pr / 256;  // at least 256 pixels each
     if (splits > max_splits)
         splits = max_splits > 0 ? max_splits : 1;
-    long long chunk = (p.Pp + splits - 1) / splits;
+    long long chunk = (p.Pr + splits - 1) / splits;
     chunk = (chunk + 127) / 128 * 128;
-    p.splits = (int)((p.Pp + chunk - 1) / chunk);
+    p.splits = (int)((p.Pr + chunk - 1) / chunk);
     p.chunk = chunk;
     p.waves = tiles * p.splits;
     // workspace: dz_t (cout x Pp), xs (3 x cin x Pp) BF16, partials FP32
@@ -1216,6 +1222,7 @@ hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, i
     a.cin = cin;
     a.cout = cout;
     a.P = p.P;
+    a.Pr = p.Pr;
     a.Pp = p.Pp;
     a.chunk = p.chunk;
     a.splits = p.splits;
