@@ -45,6 +45,16 @@ int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin
                         const void *weight, const float *bias, void *y, int y_pitch, int cout,
                         int flags, float slope, void *hip_stream);
 
+/* The forward convolution (BF16 output; SUR_OUT_F32 is rejected) followed
+ * by 2 x 2 average pooling of its output: y as sur_conv3x3_forward and
+ * `pooled` (n, h/2, w/2; BF16 view of cout channels) as sur_pool2 of y, bit
+ * for bit, in one pass where the image allows it. h and w even; neither
+ * output may overlap x or each other. */
+int sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, int cin,
+                             const void *weight, const float *bias, void *y, int y_pitch,
+                             int cout, int flags, float slope, void *pooled, int pooled_pitch,
+                             void *hip_stream);
+
 /* dx = d(sum dz * conv(x)) / dx for weight [cout][9][cin]: the convolution
  * of dz with the weights flipped in space and transposed in channels, built
  * in `flip_scratch` (device, >= 18 cout cin bytes). dx is overwritten. */

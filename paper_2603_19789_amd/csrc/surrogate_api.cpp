@@ -58,9 +58,11 @@ sslbm::IoScales make_scales(const float *in, const float *out) {
 
 extern "C" {
 
-int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
-                        const void *weight, const float *bias, void *y, int y_pitch, int cout,
-                        int flags, float slope, void *hip_stream) {
+namespace {
+
+int conv_forward(const void *x, int x_pitch, int n, int h, int w, int cin, const void *weight,
+                 const float *bias, void *y, int y_pitch, int cout, int flags, float slope,
+                 void *pooled, int pooled_pitch, void *hip_stream) {
     if (!view_ok(x, x_pitch, cin) || !dims_ok(n, h, w) || !weight || !aligned16(weight) || !y ||
         (flags & ~(SUR_LEAKY | SUR_OUT_F32)) || cout <= 0 || cout > MAX_CHANNELS ||
         y_pitch < cout || !std::isfinite(slope) || !conv_input_fits(x_pitch, n, h, w, cin))
@@ -82,8 +84,29 @@ int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin
     a.y_pitch = y_pitch;
     a.cout = cout;
     a.slope = slope;
+    a.pool = pooled;
+    a.pool_pitch = pooled_pitch;
     return status(sslbm::launch_conv_fwd(a, flags & SUR_LEAKY, flags & SUR_OUT_F32,
                                          (hipStream_t)hip_stream));
+}
+
+}  // namespace
+
+int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
+                        const void *weight, const float *bias, void *y, int y_pitch, int cout,
+                        int flags, float slope, void *hip_stream) {
+    return conv_forward(x, x_pitch, n, h, w, cin, weight, bias, y, y_pitch, cout, flags, slope,
+                        nullptr, 0, hip_stream);
+}
+
+int sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, int cin,
+                             const void *weight, const float *bias, void *y, int y_pitch,
+                             int cout, int flags, float slope, void *pooled, int pooled_pitch,
+                             void *hip_stream) {
+    if ((flags & SUR_OUT_F32) || h % 2 || w % 2 || !view_ok(pooled, pooled_pitch, cout))
+        return SSLBM_E_ARG;
+    return conv_forward(x, x_pitch, n, h, w, cin, weight, bias, y, y_pitch, cout, flags, slope,
+                        pooled, pooled_pitch, hip_stream);
 }
 
 int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
@@ -110,6 +133,8 @@ int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w,
     a.y_pitch = dx_pitch;
     a.cout = cin;
     a.slope = 0.f;
+    a.pool = nullptr;
+    a.pool_pitch = 0;
     return status(sslbm::launch_conv_fwd(a, false, false, s));
 }
 

@@ -24,6 +24,8 @@ struct ConvArgs {
     int y_pitch;
     int cout;
     float slope;
+    void *pool;  // BF16 NHWC view (n, h/2, w/2) of the 2 x 2 means of y, or null
+    int pool_pitch;
 };
 
 struct WgradArgs {

@@ -291,8 +291,12 @@ __global__ __launch_bounds__(THREADS) void conv_fwd_kernel(ConvArgs a) {
 constexpr int HALO_TH = 8, HALO_TW = 32;
 
 // LDS use (50 KB for 32 channels, 73 KB for 64) allows 3 or 2 workgroups
-// per CU; the register budget is held to the same occupancy.
-template <int NT, bool F32OUT, bool LEAKY>
+// per CU; the register budget is held to the same occupancy. POOL: the
+// epilogue also writes the 2 x 2 means of the BF16 output (a wavefront's two
+// rows start at an even row and a lane's columns 4 g .. 4 g + 3 at an even
+// column, so every window lies in one lane), with the sums of the separate
+// pooling kernel in its order, hence its bits.
+template <int NT, bool F32OUT, bool LEAKY, bool POOL>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(NT == 4 ? 2 : 3)))
 void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     constexpr int HW2 = HALO_TW + 2, HPIX = (HALO_TH + 2) * HW2;
@@ -456,40 +460,72 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     // pixels past the image's right edge and channels past the layer's get
     // an offset past the range, and the hardware drops those stores.
     constexpr int ESZ = F32OUT ? 4 : 2;
-    const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
+    const __amdgpu_buffer_rsrc_t yr_ = __builtin_amdgcn_make_buffer_rsrc(
         a.y, (short)0, (int)(((P - 1) * a.y_pitch + a.cout) * ESZ), BUF_FORMAT_WORD);
     const unsigned ypb = (unsigned)(a.y_pitch * ESZ);  // bytes per pixel
+    const int hp = a.h / 2, wp = a.w / 2;
+    const __amdgpu_buffer_rsrc_t pr = __builtin_amdgcn_make_buffer_rsrc(
+        POOL ? a.pool : a.y, (short)0,
+        POOL ? (int)((((long long)a.n * hp * wp - 1) * a.pool_pitch + a.cout) * 2) : 0,
+        BUF_FORMAT_WORD);
     auto epilogue = [&](int unit) {
         int n, y0, x0, cg;
         unit_origin(unit, n, y0, x0, cg);
+        const int yr = y0 + 2 * wv;  // the wavefront's first row (even)
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int y = y0 + 2 * wv + r;
-            if (y >= a.h)
-                continue;  // wavefront-uniform
-            const unsigned row = (unsigned)((((long long)n * a.h + y) * a.w + x0) * ypb);
+        for (int ns = 0; ns < NT; ++ns) {
+            const int c = cg * TC + 16 * ns + m;
+            const bool c_ok = c < a.cout;
+            const float b = Cs[16 * ns + m];
+            float fv[4][4];  // the stored BF16 values, as floats (POOL only)
 #pragma unroll
-            for (int ns = 0; ns < NT; ++ns) {
-                const int c = cg * TC + 16 * ns + m;
-                const float b = Cs[16 * ns + m];
-                const unsigned lane_off = row + (unsigned)(4 * g) * ypb + (unsigned)(c * ESZ);
+            for (int r = 0; r < 2; ++r) {
+                if (yr + r >= a.h)
+                    continue;  // wavefront-uniform
+                const unsigned lane_off =
+                    (unsigned)((((long long)n * a.h + yr + r) * a.w + x0) * ypb) +
+                    (unsigned)(4 * g) * ypb + (unsigned)(c * ESZ);
 #pragma unroll
                 for (int ms = 2 * r; ms < 2 * r + 2; ++ms)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int col = 16 * (ms % 2) + i;  // plus 4 g
-                        const bool ok = c < a.cout && x0 + col + 4 * g < a.w;
+                        const bool ok = c_ok && x0 + col + 4 * g < a.w;
                         const unsigned off = ok ? lane_off + (unsigned)col * ypb : OUT_OF_RANGE;
                         float v = acc[ms][ns][i] + b;
                         if (LEAKY)
                             v = v > 0.f ? v : a.slope * v;
-                        if (F32OUT)
+                        if (F32OUT) {
                             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v),
-                                                                  yr, off, 0, 0);
-                        else
-                            __builtin_amdgcn_raw_buffer_store_b16(
-                                __builtin_bit_cast(unsigned short, (__bf16)v), yr, off, 0, 0);
+                                                                  yr_, off, 0, 0);
+                        } else {
+                            const unsigned short hv = __builtin_bit_cast(unsigned short, (__bf16)v);
+                            __builtin_amdgcn_raw_buffer_store_b16(hv, yr_, off, 0, 0);
+                            if (POOL)
+                                fv[ms][i] = __builtin_bit_cast(float, (unsigned)hv << 16);
+                        }
                     }
+            }
+            if constexpr (POOL && !F32OUT) {
+                if (yr + 1 < a.h) {  // wavefront-uniform; h is even
+                    const unsigned prow =
+                        (unsigned)(((((long long)n * hp + yr / 2) * wp) * a.pool_pitch + c) * 2);
+                    // window (rows yr, yr + 1; columns x, x + 1), x = x0 + 16 ms + 4 g + i
+#pragma unroll
+                    for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+                        for (int i = 0; i < 4; i += 2) {
+                            const int x = x0 + 16 * ms + 4 * g + i;
+                            const float sum =
+                                ((fv[ms][i] + fv[ms][i + 1]) + fv[ms + 2][i]) + fv[ms + 2][i + 1];
+                            const unsigned off =
+                                c_ok && x < a.w ? prow + (unsigned)(x / 2 * a.pool_pitch * 2)
+                                                : OUT_OF_RANGE;
+                            __builtin_amdgcn_raw_buffer_store_b16(
+                                __builtin_bit_cast(unsigned short, (__bf16)(0.25f * sum)), pr, off,
+                                0, 0);
+                        }
+                }
             }
         }
     };
@@ -1105,29 +1141,33 @@ static int resident_workgroups(const void *f) {
     return cus * per_cu;
 }
 
-template <int NT>
-static void conv_halo_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
+template <int NT, bool F32OUT, bool LEAKY, bool POOL>
+static void conv_halo_go(const ConvArgs &a, hipStream_t s) {
     const int tiles_x = (a.w + HALO_TW - 1) / HALO_TW, tiles_y = (a.h + HALO_TH - 1) / HALO_TH;
     const int units = a.n * tiles_x * tiles_y * ((a.cout + 16 * NT - 1) / (16 * NT));
-    const void *f = f32out ? (leaky ? (const void *)conv_halo_kernel<NT, true, true>
-                                    : (const void *)conv_halo_kernel<NT, true, false>)
-                           : (leaky ? (const void *)conv_halo_kernel<NT, false, true>
-                                    : (const void *)conv_halo_kernel<NT, false, false>);
+    const void *f = (const void *)conv_halo_kernel<NT, F32OUT, LEAKY, POOL>;
     const int resident = resident_workgroups(f);
     const int blocks = resident > 0 && resident < units ? resident : units;
-    const dim3 grid((unsigned)blocks), block(THREADS);
-    if (f32out && leaky)
-        hipLaunchKernelGGL((conv_halo_kernel<NT, true, true>), grid, block, 0, s, a, tiles_x,
-                           tiles_y, units);
-    else if (f32out)
-        hipLaunchKernelGGL((conv_halo_kernel<NT, true, false>), grid, block, 0, s, a, tiles_x,
-                           tiles_y, units);
-    else if (leaky)
-        hipLaunchKernelGGL((conv_halo_kernel<NT, false, true>), grid, block, 0, s, a, tiles_x,
-                           tiles_y, units);
-    else
-        hipLaunchKernelGGL((conv_halo_kernel<NT, false, false>), grid, block, 0, s, a, tiles_x,
-                           tiles_y, units);
+    hipLaunchKernelGGL((conv_halo_kernel<NT, F32OUT, LEAKY, POOL>), dim3((unsigned)blocks),
+                       dim3(THREADS), 0, s, a, tiles_x, tiles_y, units);
+}
+
+template <int NT>
+static void conv_halo_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
+    if (a.pool) {  // BF16 output only
+        if (leaky)
+            conv_halo_go<NT, false, true, true>(a, s);
+        else
+            conv_halo_go<NT, false, false, true>(a, s);
+    } else if (f32out && leaky) {
+        conv_halo_go<NT, true, true, false>(a, s);
+    } else if (f32out) {
+        conv_halo_go<NT, true, false, false>(a, s);
+    } else if (leaky) {
+        conv_halo_go<NT, false, true, false>(a, s);
+    } else {
+        conv_halo_go<NT, false, false, false>(a, s);
+    }
 }
 
 // Images of at least 8 x 32 pixels: halo tiles of 16, 32 or 64 output
@@ -1139,19 +1179,30 @@ hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream
                             ((a.w + HALO_TW - 1) / HALO_TW) * ((a.cout + 15) / 16);
     const long long out_bytes =
         (((long long)a.n * a.h * a.w - 1) * a.y_pitch + a.cout) * (f32out ? 4 : 2);
-    if (a.h >= HALO_TH && a.w >= HALO_TW && units < (1ll << 31) && out_bytes < (1ll << 31)) {
+    const long long pool_bytes =
+        a.pool ? (((long long)a.n * (a.h / 2) * (a.w / 2) - 1) * a.pool_pitch + a.cout) * 2 : 0;
+    if (a.h >= HALO_TH && a.w >= HALO_TW && units < (1ll << 31) && out_bytes < (1ll << 31) &&
+        pool_bytes < (1ll << 31)) {
         if (a.cout > 32)
             conv_halo_cfg<4>(a, leaky, f32out, s);
         else if (a.cout > 16)
             conv_halo_cfg<2>(a, leaky, f32out, s);
         else
             conv_halo_cfg<1>(a, leaky, f32out, s);
-    } else if (a.cout >= 64)
+        return hipGetLastError();
+    }
+    if (a.cout >= 64)
         conv_fwd_cfg<2, 2>(a, leaky, f32out, s);
     else if (a.cout > 16)
         conv_fwd_cfg<4, 2>(a, leaky, f32out, s);
     else
         conv_fwd_cfg<4, 1>(a, leaky, f32out, s);
+    if (a.pool) {  // the tiled kernel has no pooling epilogue
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        return launch_pool2(a.y, a.y_pitch, a.n, a.h, a.w, a.cout, a.pool, a.pool_pitch, s);
+    }
     return hipGetLastError();
 }
 

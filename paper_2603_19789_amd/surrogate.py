@@ -199,17 +199,22 @@ class UNet:
         return _View(self.cat[l], self.ch[l + 1], self.ch[l])
 
     # ------------------------------------------------------------ forward --
-    def _conv(self, k, src: _View, dst, l, f32=False):
+    def _conv(self, k, src: _View, dst, l, f32=False, pooled=None):
+        """Convolution k of level l from src into dst; with `pooled` (a BF16
+        tensor of half the size) also the 2 x 2 means of dst, in one pass."""
         cv = self.convs[k]
         n = self._shape[0]
         hh, ww = self.dims[l]
         flags = (LEAKY if cv.act else 0) | (OUT_F32 if f32 else 0)
         dptr = dst.ptr if isinstance(dst, _View) else _ptr(dst)
         dpitch = dst.pitch if isinstance(dst, _View) else dst.shape[-1]
-        _check(self.lib.sur_conv3x3_forward(
-            src.ptr, src.pitch, n, hh, ww, cv.cin, _ptr(self.theta_bf16, cv.w_off),
-            _ptr(self.theta, cv.b_off), dptr, dpitch, cv.cout, flags, self.slope, None),
-            "sur_conv3x3_forward")
+        args = (src.ptr, src.pitch, n, hh, ww, cv.cin, _ptr(self.theta_bf16, cv.w_off),
+                _ptr(self.theta, cv.b_off), dptr, dpitch, cv.cout, flags, self.slope)
+        if pooled is None:
+            _check(self.lib.sur_conv3x3_forward(*args, None), "sur_conv3x3_forward")
+        else:
+            _check(self.lib.sur_conv3x3_forward_pool(*args, _ptr(pooled), pooled.shape[-1], None),
+                   "sur_conv3x3_forward_pool")
 
     def forward_packed(self):
         """Network pass on self.x0 into self.out (FP32 NHWC, 16 channels)."""
@@ -219,13 +224,10 @@ class UNet:
         for l in range(L):
             src = _View(self.x0, 0, IN_CHANNELS) if l == 0 else _View(self.pool[l], 0, ch[l - 1])
             self._conv(k, src, _View(self.a[l], 0, ch[l]), l)
-            self._conv(k + 1, _View(self.a[l], 0, ch[l]), self.e_view(l), l)
+            # e_l, and (below the last level) its 2 x 2 means: the next input
+            self._conv(k + 1, _View(self.a[l], 0, ch[l]), self.e_view(l), l,
+                       pooled=self.pool[l + 1] if l + 1 < L else None)
             k += 2
-            if l + 1 < L:
-                e = self.e_view(l)
-                hh, ww = self.dims[l]
-                _check(lib.sur_pool2(e.ptr, e.pitch, n, hh, ww, ch[l], _ptr(self.pool[l + 1]),
-                                     ch[l], None), "sur_pool2")
         h_view = self.e_view(L - 1)
         for l in range(L - 2, -1, -1):
             hh, ww = self.dims[l + 1]

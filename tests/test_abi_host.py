@@ -217,6 +217,9 @@ def test_adjoint_host_checks(lib):
     lib.sslbm_destroy(h)
 
 
+S_OUT_F32 = 2  # surrogate.h: SUR_OUT_F32
+
+
 def test_surrogate_header_exports_and_host_checks(lib):
     """surrogate.h: every declared function is exported, and bad arguments
     are rejected on the host (no GPU call is made for them)."""
@@ -238,6 +241,15 @@ def test_surrogate_header_exports_and_host_checks(lib):
     assert fwd(a, 16, 1, 8192, 8192, 16, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG
     assert lib.sur_conv3x3_backward_data(a, 16, 1, 8192, 8192, 16, b, 8, c, 8, vp(0x400000000),
                                          None) == binding.E_ARG
+    # fused pooling: BF16 output only, even sizes, an aligned pooled view
+    d = vp(0x400000000)
+    fp = lib.sur_conv3x3_forward_pool
+    assert fp(a, 16, 1, 8, 8, 16, b, None, c, 32, 32, S_OUT_F32, 0.1, d, 32, None) == binding.E_ARG
+    assert fp(a, 16, 1, 7, 8, 16, b, None, c, 32, 32, 0, 0.1, d, 32, None) == binding.E_ARG
+    assert fp(a, 16, 1, 8, 8, 16, b, None, c, 32, 32, 0, 0.1, None, 32, None) == binding.E_ARG
+    assert fp(a, 16, 1, 8, 8, 16, b, None, c, 32, 32, 0, 0.1, vp(d.value + 2), 32,
+              None) == binding.E_ARG
+    assert fp(a, 16, 1, 8, 8, 16, b, None, c, 32, 32, 0, 0.1, d, 24, None) == binding.E_ARG
     assert lib.sur_conv3x3_backward_weight_workspace(1, 8, 12, 16, 16) == 0  # w % 8
     assert lib.sur_conv3x3_backward_weight_workspace(1, 8, 16, 16, 16) > 0
     ws = lib.sur_conv3x3_backward_weight_workspace(2, 8, 16, 32, 64)

@@ -86,6 +86,36 @@ def test_conv_forward(n, h, w, cin, cout, flags):
     check_close(y.float().cpu().numpy(), want, scale, 1e-6 if f32 else 2 ** -8, "forward")
 
 
+@pytest.mark.parametrize("leaky", [False, True])
+@pytest.mark.parametrize("n,h,w,cin,cout", [
+    (2, 16, 32, 32, 32), (1, 18, 40, 16, 32), (1, 16, 64, 32, 128), (2, 8, 32, 16, 16),
+    (3, 10, 34, 40, 24), (1, 6, 16, 16, 32)])
+def test_conv_forward_pool_equals_conv_then_pool(n, h, w, cin, cout, leaky):
+    """The convolution with its 2 x 2 means written in the same pass (halo
+    tiles: whole and ragged tiles, 16/32/64-channel groups; the last shape
+    takes the tiled kernel and a separate pooling pass) gives both outputs
+    bit for bit as the convolution followed by the pooling kernel."""
+    print(f"conv fwd+pool n={n} {h}x{w} {cin}->{cout} leaky={leaky}", flush=True)
+    x, _ = bf16_array((n, h, w, cin))
+    wt, _ = bf16_array((cout, 9, cin), scale=1.0 / np.sqrt(9 * cin))
+    bias = torch.tensor(RNG.normal(size=cout), dtype=torch.float32).cuda()
+    flags = S.LEAKY if leaky else 0
+    pitch = cout + 8  # output as a channel slice of a wider buffer
+    y1 = torch.zeros((n, h, w, pitch), dtype=BF, device="cuda")
+    y2 = torch.zeros_like(y1)
+    p1 = torch.zeros((n, h // 2, w // 2, cout), dtype=BF, device="cuda")
+    p2 = torch.zeros_like(p1)
+    L = lib()
+    assert L.sur_conv3x3_forward(p(x), cin, n, h, w, cin, p(wt), p(bias), p(y1, 8), pitch, cout,
+                                 flags, 0.1, None) == binding.OK
+    assert L.sur_pool2(p(y1, 8), pitch, n, h, w, cout, p(p1), cout, None) == binding.OK
+    assert L.sur_conv3x3_forward_pool(p(x), cin, n, h, w, cin, p(wt), p(bias), p(y2, 8), pitch,
+                                      cout, flags, 0.1, p(p2), cout, None) == binding.OK
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.int16), y2.view(torch.int16))
+    assert torch.equal(p1.view(torch.int16), p2.view(torch.int16))
+
+
 @pytest.mark.parametrize("n,h,w,cin,cout", [(1, 9, 7, 24, 48), (2, 16, 40, 40, 24),
                                              (1, 8, 32, 32, 96)])
 def test_conv_forward_without_bias(n, h, w, cin, cout):
@@ -236,21 +266,19 @@ def _small_net():
     return S.UNet(levels=3, base=16, slope=0.1, seed=3)
 
 
-def test_unet_forward_backward_against_oracle():
-    """The assembled network (3 levels, base 16, batch 2, 64x64) against the
-    oracle's U-Net with the same BF16 weights, once with the oracle storing
-    activations and gradients in BF16 where the kernels do (close agreement:
-    only FP32-versus-FP64 sums and the roundings they flip differ), and once
-    in plain FP64 (the BF16 storage itself moves the first layers' weight
-    gradients by several per cent; a miswired buffer would leave them
-    uncorrelated, so the direction is checked there). With random weights
-    and data the backward chain amplifies single roundings: the BF16 model
-    itself is 5-15 % from FP64 in the deep layers, and the kernels, whose
-    FP32 sums flip some of its roundings, are within a few per cent of it."""
+def unet_errors(data_seed):
+    """Relative L2 errors of the assembled network (3 levels, base 16, batch
+    2, 64x64) against the oracle's U-Net with the same BF16 weights, on
+    input and output gradient drawn from `data_seed`: the forward output
+    against the oracle storing activations in BF16 where the kernels do and
+    against plain FP64, then per layer (weight gradient, bias gradient)
+    against the BF16 storage model and the cosine of the weight gradient
+    with the FP64 one."""
+    rng = np.random.default_rng(data_seed)
     net = _small_net()
     n, h, w = 2, 64, 64
     net._buffers(n, h, w)
-    x = torch.tensor(RNG.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF).cuda()
+    x = torch.tensor(rng.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF).cuda()
     net.x0.copy_(x)
     out = net.forward_packed().clone()
     weights = net.weights_numpy()
@@ -261,9 +289,7 @@ def test_unet_forward_backward_against_oracle():
     got = out.cpu().numpy()
     err16 = np.linalg.norm(got - want16) / np.linalg.norm(want16)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
-    print(f"U-Net forward rel L2: {err16:.3e} (BF16 storage model), {err:.3e} (FP64)")
-    assert err16 < 5e-3 and err < 2e-2
-    dout = torch.tensor(RNG.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF).cuda()
+    dout = torch.tensor(rng.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF).cuda()
     net.dout.copy_(dout)
     net.backward_packed()
     grads = net.grads_numpy()
@@ -272,12 +298,30 @@ def test_unet_forward_backward_against_oracle():
     want_g, _ = O.unet_backward(dv, weights, tape, 0.1)
     cos = lambda a, b: float(np.sum(a * b) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
     rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-    for k, ((gw, gb), (ww, wb), (fw, fb)) in enumerate(zip(grads, want_g16, want_g)):
-        print(f"  layer {k}: weight gradient rel L2 {rel(gw, ww):.3e} (BF16 model), "
-              f"{rel(gw, fw):.3e} (FP64, cos {cos(gw, fw):.5f}); bias {rel(gb, wb):.3e}, "
-              f"{rel(gb, fb):.3e}")
-        assert rel(gw, ww) < 6e-2 and rel(gb, wb) < 6e-2, k
-        assert cos(gw, fw) > 0.98, k
+    layers = [(rel(gw, ww), rel(gb, wb), cos(gw, fw))
+              for (gw, gb), (ww, wb), (fw, fb) in zip(grads, want_g16, want_g)]
+    return err16, err, layers
+
+
+def test_unet_forward_backward_against_oracle():
+    """The assembled network against the oracle's U-Net (see unet_errors),
+    on its own seeded data: close agreement with the BF16 storage model
+    (only FP32-versus-FP64 sums and the roundings they flip differ), and the
+    direction of every weight gradient against plain FP64 (the BF16 storage
+    itself moves the first layers' weight gradients by several per cent; a
+    miswired buffer would leave them uncorrelated). With random weights and
+    data the backward chain amplifies single roundings: the BF16 model itself
+    is 5-15 % from FP64 in the deep layers, and over eleven data seeds the
+    kernels' worst layer was 2-8 % from it (cosine with FP64 >= 0.991); the
+    bounds leave about twice that."""
+    err16, err, layers = unet_errors(data_seed=21)
+    print(f"U-Net forward rel L2: {err16:.3e} (BF16 storage model), {err:.3e} (FP64)")
+    assert err16 < 5e-3 and err < 2e-2
+    for k, (rw, rb, c) in enumerate(layers):
+        print(f"  layer {k}: weight gradient rel L2 {rw:.3e}, bias {rb:.3e} (BF16 model); "
+              f"cos with FP64 {c:.5f}")
+        assert rw < 1.5e-1 and rb < 1.5e-1, k
+        assert c > 0.98, k
 
 
 def test_training_learns_and_beats_persistence():
