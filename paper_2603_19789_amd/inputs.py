@@ -74,6 +74,17 @@ def gaussian_foci_state(nx: int, ny: int, centres, amplitude: float, width: floa
     return rho
 
 
+def gaussian_foci_factors(nx: int, ny: int, centres, amplitude: float, width: float):
+    """The separable factors of ``gaussian_foci_state``'s infected field before
+    clipping: (gy, gx) of shapes (foci, ny) and (foci, nx), the amplitude
+    folded into gy, so that the field is the sum over the foci of the outer
+    products gy[f] gx[f] (for building many such states on a device)."""
+    gx = np.stack([np.exp(-_min_image_sq(nx, cx) / (2.0 * width * width)) for cx, _ in centres])
+    gy = np.stack([amplitude * np.exp(-_min_image_sq(ny, cy) / (2.0 * width * width))
+                   for _, cy in centres])
+    return gy, gx
+
+
 def seeded_centres(nx: int, ny: int, count: int, seed: int):
     rng = np.random.default_rng(seed)
     xs = rng.integers(0, nx, size=count)

@@ -375,28 +375,60 @@ class Surrogate:
         return out
 
 
-def _ensemble_batch(params_list, h, w, seed, warm, jump):
-    """States (x_t, x_{t+jump}) of a batch of equal grids from 1-8 seeded
-    Gaussian foci after `warm` SSLBM steps, advanced together by the
-    library's ensemble kernel (FP32)."""
+MAX_FOCI = 8
+
+
+def _foci_states(flat, b, h, w, rng):
+    """Fill the ensemble state `flat` (b equal grids) with 1-8 seeded
+    Gaussian foci per grid: `inputs.gaussian_foci_state` fields, assembled
+    on the device from their separable factors (one small upload instead of
+    a full state per grid)."""
     torch = _torch()
-    from .binding import Ensemble
-    from .inputs import gaussian_foci_state
-    rng = np.random.default_rng(seed)
-    ens = Ensemble([(w, h)] * len(params_list), params_list, dtype="f32")
-    flat = ens.empty()
-    states = []
-    for v in ens.views(flat):
-        foci = int(rng.integers(1, 9))
+    from .inputs import gaussian_foci_factors
+    gy = np.zeros((b, MAX_FOCI, h))  # unused foci stay zero
+    gx = np.zeros((b, MAX_FOCI, w))
+    for k in range(b):
+        foci = int(rng.integers(1, MAX_FOCI + 1))
         centres = list(zip(rng.integers(0, w, foci).tolist(), rng.integers(0, h, foci).tolist()))
         amp = float(rng.uniform(0.005, 0.05))
-        v.copy_(torch.tensor(gaussian_foci_state(w, h, centres, amp, float(rng.uniform(3, 8))),
-                             dtype=torch.float32, device="cuda"))
+        gy[k, :foci], gx[k, :foci] = gaussian_foci_factors(w, h, centres, amp,
+                                                           float(rng.uniform(3, 8)))
+    gy_d = torch.tensor(gy.transpose(0, 2, 1).copy(), device="cuda")  # (b, h, foci)
+    gx_d = torch.tensor(gx, device="cuda")                               # (b, foci, w)
+    infected = torch.bmm(gy_d, gx_d).clamp_(max=1.0)
+    x0 = flat.view(b, 5, h, w)  # instance blocks are contiguous (5 h w % 4 == 0)
+    x0.zero_()
+    x0[:, 0] = 1.0 - infected
+    x0[:, 2] = infected
+
+
+def _generator_launch(params_list, h, w, seed):
+    """Pass shape of the data generator's ensemble (b equal grids), tuned
+    once on a seeded batch (`Ensemble.tune`)."""
+    from .binding import Ensemble
+    b = len(params_list)
+    ens = Ensemble([(w, h)] * b, params_list, dtype="f32")
+    flat = ens.empty()
+    _foci_states(flat, b, h, w, np.random.default_rng(seed))
+    return ens.tune(flat, ens.empty())
+
+
+def _ensemble_batch(params_list, h, w, seed, warm, jump, launch=None):
+    """States (x_t, x_{t+jump}) of a batch of equal grids from 1-8 seeded
+    Gaussian foci after `warm` SSLBM steps, advanced together by the
+    library's ensemble kernel (FP32), with pass shape `launch` (a dict as
+    from `_generator_launch`; None: the library's default)."""
+    from .binding import Ensemble
+    b = len(params_list)
+    ens = Ensemble([(w, h)] * b, params_list, dtype="f32")
+    if launch:
+        ens.set_launch(**launch)
+    flat = ens.empty()
+    _foci_states(flat, b, h, w, np.random.default_rng(seed))
     scratch = ens.empty()
     if warm:
         ens.run(flat, warm, scratch)
-    b = len(params_list)
-    x_t = flat.view(b, 5, h, w).clone()  # instance blocks are contiguous (5 h w % 4 == 0)
+    x_t = flat.view(b, 5, h, w).clone()
     ens.run(flat, jump, scratch)
     x_next = flat.view(b, 5, h, w).clone()
     return x_t, x_next
@@ -448,6 +480,8 @@ def train(net: UNet, *, steps=300, batch=16, size=256, jump=50, lr=1e-3, seed=0,
     scale_in = [max(math.sqrt(v), 1e-3) for v in sq_in]
     scale_out = [max(math.sqrt(v), 1e-5) for v in sq_out]
     sur = Surrogate(net, jump, scale_in, scale_out)
+    # the pass shape of the data generator, tuned once for this batch of grids
+    launch = _generator_launch(sample_params(rng, batch), size, size, int(rng.integers(1 << 30)))
     partials = torch.empty(1024, dtype=torch.float64, device="cuda")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     losses = []
@@ -456,7 +490,7 @@ def train(net: UNet, *, steps=300, batch=16, size=256, jump=50, lr=1e-3, seed=0,
     for it in range(steps):
         plist = sample_params(rng, batch)
         x_t, x_n = _ensemble_batch(plist, size, size, int(rng.integers(1 << 30)),
-                                   int(rng.integers(0, max_warm + 1)), jump)
+                                   int(rng.integers(0, max_warm + 1)), jump, launch)
         net._buffers(batch, size, size)
         pl = torch.tensor(param_planes(plist), dtype=torch.float32, device="cuda")
         _check(lib.sur_pack_input(_ptr(x_t), batch, size, size, _ptr(pl), _floats(scale_in),

@@ -230,3 +230,18 @@ def test_receptive_radius_brute_force(levels):
         ys, xs = np.nonzero(np.abs(out - base).max(axis=(0, 3)) > 0)
         reach = max(reach, int(max(np.abs(ys - c).max(), np.abs(xs - c).max())))
     assert reach == receptive_radius(levels)
+
+
+def test_training_initial_states_from_separable_factors():
+    """The surrogate's training data starts from Gaussian-foci states built
+    on the device from their separable factors: the factors' outer-product
+    sum, clipped, is the generator's infected field (periodic wrap included:
+    foci at the grid's edges, a non-square grid)."""
+    from paper_2603_19789_amd.inputs import gaussian_foci_factors, gaussian_foci_state
+    centres = [(3, 199), (100, 7), (255, 128), (0, 0)]
+    gy, gx = gaussian_foci_factors(256, 200, centres, 0.03, 4.5)
+    assert gy.shape == (4, 200) and gx.shape == (4, 256)
+    field = np.minimum(gy.T @ gx, 1.0)
+    want = gaussian_foci_state(256, 200, centres, 0.03, 4.5)
+    assert np.max(np.abs(field - want[2])) < 1e-15
+    assert np.max(np.abs(1.0 - field - want[0])) < 1e-15
