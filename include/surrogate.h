@@ -25,8 +25,9 @@
  * Errors: SSLBM_E_ARG (NULL pointer, size <= 0, a channel count, pitch or
  * pointer not meeting the alignment above, odd h or w where halving is
  * needed, w not a multiple of 8 for the weight gradient, workspace too
- * small, the input view of a convolution spanning 2 GiB or more:
- * ((n h w - 1) pitch + channels) * 2 >= 2^31 bytes), SSLBM_E_HIP.
+ * small, an input view of a convolution or of its gradients (x, dz)
+ * spanning 2 GiB or more: ((n h w - 1) pitch + channels) * 2 >= 2^31
+ * bytes), SSLBM_E_HIP.
  */
 #ifndef SSLBM_SURROGATE_H
 #define SSLBM_SURROGATE_H

@@ -149,7 +149,8 @@ int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int 
                                 int h, int w, int cin, int cout, float *dweight, float *dbias,
                                 void *workspace, size_t workspace_bytes, void *hip_stream) {
     if (!view_ok(x, x_pitch, cin) || !view_ok(dz, dz_pitch, cout) || !dims_ok(n, h, w) ||
-        w % 8 || !dweight || !workspace || !aligned16(workspace))
+        w % 8 || !dweight || !workspace || !aligned16(workspace) ||
+        !conv_input_fits(x_pitch, n, h, w, cin) || !conv_input_fits(dz_pitch, n, h, w, cout))
         return SSLBM_E_ARG;
     if (workspace_bytes < sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout))
         return SSLBM_E_ARG;

@@ -39,6 +39,10 @@ struct WgradArgs {
 struct WgradPlan {
     long long P, Pr, Pp, chunk, waves;
     int splits, ni;
+    // halo-tile path (images of at least 8 x 32 pixels): channel blocks of
+    // 32 x 32, gb workgroups per block
+    bool halo;
+    int nob, nib, gb, tiles, tiles_x, tiles_y;
     size_t dz_t_bytes, xs_bytes, part_bytes;
     size_t bytes() const { return align256(dz_t_bytes) + align256(xs_bytes) + align256(part_bytes); }
 };

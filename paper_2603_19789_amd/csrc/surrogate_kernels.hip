@@ -785,21 +785,214 @@ __global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
         }
 }
 
-// dW = sum over splits in a fixed order, in two passes: pass 1 sums each
-// run of RED_RUN consecutive splits (in order) into the run's first slot,
-// pass 2 sums the runs in order. db[o] = sum over pixels of dz_t[o][:].
-constexpr int RED_RUN = 16;
+// ------------------------------------------ weight gradient, halo tiles
+// dW[o][t][i] = sum over pixels p of dZ[p][o] X[p + shift_t][i], on images of
+// at least 8 x 32 pixels, straight from the NHWC activations: no
+// channel-major copies in HBM. A workgroup owns a block of 32 output x 32
+// input channels and walks pixel tiles of 8 rows x 32 columns. Per tile it
+// transposes into LDS the tile of dZ (channel-major, 32 x 256) and the input
+// tile with its one-pixel halo in three copies shifted by dx = -1, 0, +1
+// (channel-major, 10 rows x 32 columns each), so that every MFMA fragment
+// (8 consecutive pixels of one channel) is one aligned 16-byte LDS read;
+// pixels outside the image carry dZ = 0. Wavefront w takes tile rows 2w and
+// 2w + 1 as its k steps (32 pixels each) and accumulates all nine taps of
+// the 32 x 32 block (each dZ fragment serves nine taps). Each wavefront
+// writes its sums as one split of the fixed-order reduction below. The
+// workgroups of input block 0 also sum the dZ tile per output channel (the
+// bias gradient), thread (o, s) over pixels 32 s .. 32 s + 31 of every tile,
+// and write the eight per-thread sums of a channel, added in order, as
+// their split of the bias.
+constexpr int WH_TH = 8, WH_TW = 32;  // pixel tile
+constexpr int WH_AZ = 264;            // row stride of the dZ tile (elements; bank spread)
+constexpr int WH_BX = 328;            // channel stride of a shifted input copy (elements)
+constexpr int WH_RESIDENT = 512;      // two workgroups per CU on 256 CUs
 
+__device__ __forceinline__ unsigned lo_pair(unsigned a, unsigned b) {
+    return (a & 0xffffu) | (b << 16);
+}
+__device__ __forceinline__ unsigned hi_pair(unsigned a, unsigned b) {
+    return (a >> 16) | (b & 0xffff0000u);
+}
+
+struct WgradHaloArgs {
+    const uint16_t *x, *dz;
+    int xp, dzp, n, h, w, cin, cout;
+    int nob, nib, gb, tiles, tiles_x, tiles_y;
+    float *part;    // [4 gb][cout][9][cin]
+    float *part_b;  // [gb][cout]
+};
+
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_wgrad_halo_kernel(WgradHaloArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t Az[32 * WH_AZ];
+    __shared__ __attribute__((aligned(16))) uint16_t Bx[3 * 32 * WH_BX];
+    constexpr unsigned OUT_OF_RANGE = 0x80000000u;
+    const int blocks = a.nob * a.nib;
+    const int blk = blockIdx.x % blocks, kb = blockIdx.x / blocks;
+    const int ob = blk / a.nib, ib = blk - (blk / a.nib) * a.nib;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int m = lane & 15, g = lane >> 4;
+    const long long P = (long long)a.n * a.h * a.w;
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t *>(a.x), (short)0, (int)(((P - 1) * a.xp + a.cin) * 2), BUF_FORMAT_WORD);
+    const __amdgpu_buffer_rsrc_t dr = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t *>(a.dz), (short)0, (int)(((P - 1) * a.dzp + a.cout) * 2),
+        BUF_FORMAT_WORD);
+    const int oc0 = ob * 32, ic0 = ib * 32;
+
+    f32x4 acc[9][2][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+                acc[t][u][v] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;  // bias: channel tid / 8, pixels 32 (tid % 8) .. + 31 of each tile
+    const bool bias_block = ib == 0;
+
+    for (int tile = kb; tile < a.tiles; tile += a.gb) {
+        const int per_image = a.tiles_x * a.tiles_y;
+        const int n = tile / per_image;
+        const int rt = tile - n * per_image;
+        const int y0 = (rt / a.tiles_x) * WH_TH, x0 = (rt - (rt / a.tiles_x) * a.tiles_x) * WH_TW;
+        // dZ tile: item = (tile row, column pair, group of 8 channels)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int e = tid + THREADS * r;  // < 512
+            const int row = e >> 6, cp = (e >> 2) & 15, j = e & 3;
+            const int y = y0 + row, x = x0 + 2 * cp, oc = oc0 + 8 * j;
+            const bool ok = y < a.h && oc < a.cout;
+            const long long q = ((long long)n * a.h + y) * a.w + x;
+            const u32x4 p0 = load16(dr, ok && x < a.w ? (unsigned)((q * a.dzp + oc) * 2) : OUT_OF_RANGE);
+            const u32x4 p1 =
+                load16(dr, ok && x + 1 < a.w ? (unsigned)(((q + 1) * a.dzp + oc) * 2) : OUT_OF_RANGE);
+            unsigned *dst = reinterpret_cast<unsigned *>(&Az[8 * j * WH_AZ + row * 32 + 2 * cp]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                dst[(2 * k) * (WH_AZ / 2)] = lo_pair(p0[k], p1[k]);
+                dst[(2 * k + 1) * (WH_AZ / 2)] = hi_pair(p0[k], p1[k]);
+            }
+        }
+        // input halo: item = (halo row, column pair, group of 8 channels);
+        // columns c, c + 1 of copy s hold pixels x0 + c + s - 1 and x0 + c + s
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int e = tid + THREADS * r;
+            if (e < 10 * 16 * 4) {
+                const int hr = e >> 6, cp = (e >> 2) & 15, j = e & 3;
+                const int y = wrap(y0 - 1 + hr, a.h), ic = ic0 + 8 * j;
+                const long long rowq = ((long long)n * a.h + y) * a.w;
+                u32x4 px[4];
+#pragma unroll
+                for (int qd = 0; qd < 4; ++qd) {
+                    const int x = wrap(x0 + 2 * cp - 1 + qd, a.w);
+                    px[qd] = load16(xr, ic < a.cin ? (unsigned)(((rowq + x) * a.xp + ic) * 2)
+                                                   : OUT_OF_RANGE);
+                }
+#pragma unroll
+                for (int sh = 0; sh < 3; ++sh) {
+                    unsigned *dst = reinterpret_cast<unsigned *>(
+                        &Bx[(sh * 32 + 8 * j) * WH_BX + hr * 32 + 2 * cp]);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        dst[(2 * k) * (WH_BX / 2)] = lo_pair(px[sh][k], px[sh + 1][k]);
+                        dst[(2 * k + 1) * (WH_BX / 2)] = hi_pair(px[sh][k], px[sh + 1][k]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (bias_block) {
+#pragma unroll
+            for (int k8 = 0; k8 < 4; ++k8) {
+                const u32x4 v = *reinterpret_cast<const u32x4 *>(
+                    &Az[(tid >> 3) * WH_AZ + 32 * (tid & 7) + 8 * k8]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    bsum += __builtin_bit_cast(float, v[k] << 16);
+                    bsum += __builtin_bit_cast(float, v[k] & 0xffff0000u);
+                }
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int row = 2 * wv + kk;  // this k step's 32 pixels: tile row `row`
+            bf16x8 A[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                A[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(
+                                                      &Az[(16 * u + m) * WH_AZ + row * 32 + 8 * g]));
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t % 3;  // shifted by one
+                bf16x8 B[2];
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+                    B[v] = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const uint4 *>(
+                                    &Bx[(dx * 32 + 16 * v + m) * WH_BX + (row + dy) * 32 + 8 * g]));
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v)
+                        acc[t][u][v] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[u], B[v], acc[t][u][v], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    if (bias_block) {
+        // the eight sums of a channel, added in order (the loop's last
+        // barrier has passed: Az is free)
+        float *red = reinterpret_cast<float *>(Az);
+        red[tid] = bsum;
+        __syncthreads();
+        if (tid < 32) {
+            float b = 0.f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                b += red[8 * tid + k];
+            if (oc0 + tid < a.cout)
+                a.part_b[(long long)kb * a.cout + oc0 + tid] = b;
+        }
+    }
+    // this wavefront's split: rows 4 g + jj of subtile u (output channels),
+    // column m of subtile v (input channels)
+    const long long count = (long long)a.cout * 9 * a.cin;
+    float *part = a.part + (long long)(kb * 4 + wv) * count;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int ic = ic0 + 16 * v + m;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int oc = oc0 + 16 * u + 4 * g + jj;
+                if (oc < a.cout && ic < a.cin) {
+#pragma unroll
+                    for (int t = 0; t < 9; ++t)
+                        part[((long long)oc * 9 + t) * a.cin + ic] = acc[t][u][v][jj];
+                }
+            }
+        }
+}
+
+// dW = sum over splits in a fixed order, in two passes: pass 1 sums each
+// run of `run` consecutive splits (in order) into the run's first slot,
+// pass 2 sums the runs in order. With run about sqrt(splits) both passes
+// are short.
 __global__ __launch_bounds__(THREADS) void wgrad_runs_kernel(float *__restrict__ part, int splits,
-                                                             long long count) {
+                                                             long long count, int run) {
     const long long t = (long long)blockIdx.x * THREADS + threadIdx.x;
-    const int runs = (splits + RED_RUN - 1) / RED_RUN;
+    const int runs = (splits + run - 1) / run;
     if (t >= count * runs)
         return;
-    const int run = (int)(t / count);
-    const long long e = t - run * count;
-    const int k0 = run * RED_RUN, k1 = min(k0 + RED_RUN, splits);
+    const int r = (int)(t / count);
+    const long long e = t - r * count;
+    const int k0 = r * run, k1 = min(k0 + run, splits);
     float s = 0.f;
+#pragma unroll 4
     for (int k = k0; k < k1; ++k)
         s += part[k * count + e];
     part[k0 * count + e] = s;  // only this thread reads or writes these slots
@@ -807,15 +1000,17 @@ __global__ __launch_bounds__(THREADS) void wgrad_runs_kernel(float *__restrict__
 
 __global__ __launch_bounds__(THREADS) void wgrad_reduce_kernel(const float *__restrict__ part,
                                                                int splits, long long count,
-                                                               float *__restrict__ dw) {
+                                                               int run, float *__restrict__ dw) {
     const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
     if (e >= count)
         return;
     float s = 0.f;
-    for (int k = 0; k < splits; k += RED_RUN)
+#pragma unroll 4
+    for (int k = 0; k < splits; k += run)
         s += part[k * count + e];
     dw[e] = s;
 }
+
 
 // --------------------------------------------------------- elementwise ops
 // Each thread handles 8 channels of one pixel as one 16-byte access per
@@ -1110,6 +1305,18 @@ __global__ __launch_bounds__(THREADS) void crop_kernel(const float *__restrict__
 
 unsigned blocks_for(long long work) { return (unsigned)((work + THREADS - 1) / THREADS); }
 
+// The two passes over `splits` partial sums of `count` values each.
+static void reduce_splits(float *part, int splits, long long count, float *out, hipStream_t s) {
+    int run = 1;
+    while (run * run < splits)
+        ++run;
+    const long long runs = (splits + run - 1) / run;
+    hipLaunchKernelGGL(wgrad_runs_kernel, dim3(blocks_for(count * runs)), dim3(THREADS), 0, s,
+                       part, splits, count, run);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for(count)), dim3(THREADS), 0, s, part,
+                       splits, count, run, out);
+}
+
 }  // namespace
 
 template <int WM, int NT>
@@ -1216,6 +1423,27 @@ hipError_t launch_flip(const void *w, int cout, int cin, void *wf, hipStream_t s
 WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
     WgradPlan p;
     p.P = (long long)n * h * w;
+    p.tiles_x = (w + WH_TW - 1) / WH_TW;
+    p.tiles_y = (h + WH_TH - 1) / WH_TH;
+    const long long tiles = (long long)n * p.tiles_x * p.tiles_y;
+    p.halo = h >= WH_TH && w >= WH_TW && tiles < (1ll << 31);
+    if (p.halo) {
+        p.tiles = (int)tiles;
+        p.nob = (cout + 31) / 32;
+        p.nib = (cin + 31) / 32;
+        const int blocks = p.nob * p.nib;
+        long long gb = WH_RESIDENT / blocks;
+        gb = gb < 1 ? 1 : (gb > tiles ? tiles : gb);
+        p.gb = (int)gb;
+        p.splits = 4 * p.gb;  // one per wavefront
+        p.Pr = p.Pp = p.chunk = p.waves = 0;
+        p.ni = 0;
+        p.dz_t_bytes = p.xs_bytes = 0;
+        // dW partials, then the bias partials (one per workgroup of a block)
+        p.part_bytes = ((size_t)p.splits * cout * 9 * cin + (size_t)p.gb * cout) * 4;
+        return p;
+    }
+    p.nob = p.nib = p.gb = p.tiles = 0;
     // k runs over Pr = P rounded up to whole trips of four 32-pixel k steps.
     // The planes are 1152 pixels (2304 bytes) longer, so that they are not a
     // power of two apart: pixel counts here are powers of two, and the 16
@@ -1224,8 +1452,8 @@ WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
     p.Pr = (p.P + 127) / 128 * 128;
     p.Pp = p.Pr + 1152;
     p.ni = cin > 16 ? 2 : 1;
-    const long long tiles = (long long)((cout + 31) / 32) * ((cin + 16 * p.ni - 1) / (16 * p.ni)) * 9;
-    long long splits = 4096 / tiles;  // about 4096 wavefronts in all
+    const long long wtiles = (long long)((cout + 31) / 32) * ((cin + 16 * p.ni - 1) / (16 * p.ni)) * 9;
+    long long splits = 4096 / wtiles;  // about 4096 wavefronts in all
     if (splits < 1)
         splits = 1;
     const long long max_splits = p.Pr / 256;  // at least 256 pixels each
@@ -1235,7 +1463,7 @@ WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
     chunk = (chunk + 127) / 128 * 128;
     p.splits = (int)((p.Pr + chunk - 1) / chunk);
     p.chunk = chunk;
-    p.waves = tiles * p.splits;
+    p.waves = wtiles * p.splits;
     // workspace: dz_t (cout x Pp), xs (3 x cin x Pp) BF16, partials FP32
     p.dz_t_bytes = (size_t)cout * p.Pp * 2;
     p.xs_bytes = (size_t)3 * cin * p.Pp * 2;
@@ -1249,6 +1477,34 @@ WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
 hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, int h, int w,
                         int cin, int cout, float *dw, float *db, void *ws, hipStream_t s) {
     const WgradPlan p = wgrad_plan(n, h, w, cin, cout);
+    const long long count = (long long)cout * 9 * cin;
+    if (p.halo) {
+        float *part = static_cast<float *>(ws);
+        WgradHaloArgs a;
+        a.x = static_cast<const uint16_t *>(x);
+        a.dz = static_cast<const uint16_t *>(dz);
+        a.xp = xp;
+        a.dzp = dzp;
+        a.n = n;
+        a.h = h;
+        a.w = w;
+        a.cin = cin;
+        a.cout = cout;
+        a.nob = p.nob;
+        a.nib = p.nib;
+        a.gb = p.gb;
+        a.tiles = p.tiles;
+        a.tiles_x = p.tiles_x;
+        a.tiles_y = p.tiles_y;
+        a.part = part;
+        a.part_b = part + (long long)p.splits * count;
+        hipLaunchKernelGGL(conv_wgrad_halo_kernel, dim3((unsigned)(p.nob * p.nib * p.gb)),
+                           dim3(THREADS), 0, s, a);
+        reduce_splits(part, p.splits, count, dw, s);
+        if (db)
+            reduce_splits(a.part_b, p.gb, cout, db, s);
+        return hipGetLastError();
+    }
     uint16_t *dz_t = static_cast<uint16_t *>(ws);
     uint16_t *xs = reinterpret_cast<uint16_t *>(static_cast<char *>(ws) + align256(p.dz_t_bytes));
     float *part = reinterpret_cast<float *>(static_cast<char *>(ws) + align256(p.dz_t_bytes) +
@@ -1282,12 +1538,7 @@ hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, i
         hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(THREADS), 0, s, a);
     else
         hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(THREADS), 0, s, a);
-    const long long count = (long long)cout * 9 * cin;
-    const long long runs = (p.splits + RED_RUN - 1) / RED_RUN;
-    hipLaunchKernelGGL(wgrad_runs_kernel, dim3(blocks_for(count * runs)), dim3(THREADS), 0, s,
-                       part, p.splits, count);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for(count)), dim3(THREADS), 0, s, part,
-                       p.splits, count, dw);
+    reduce_splits(part, p.splits, count, dw, s);
     if (db) {
         // the bias partials reuse the start of the (already reduced) partials buffer
         hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)cout, BIAS_SLICES), dim3(THREADS), 0,

@@ -150,8 +150,14 @@ def test_conv_backward_data(n, h, w, cin, cout):
     check_close(dx.float().cpu().numpy(), want, scale, 2 ** -8, "backward data")
 
 
+# The first six take channel-major planes (images under 8 x 32 pixels); the
+# rest take halo tiles: whole and ragged tiles, partial and several 32 x 32
+# channel blocks, and more tiles than the workgroups of a block (each then
+# walks several, some one more than others).
 WGRAD_CASES = [(1, 8, 8, 16, 16), (2, 16, 24, 16, 32), (2, 8, 16, 64, 128), (1, 16, 16, 96, 32),
-               (3, 4, 8, 384, 128), (1, 5, 8, 8, 40), (4, 32, 32, 32, 64)]
+               (3, 4, 8, 384, 128), (1, 5, 8, 8, 40), (4, 32, 32, 32, 64), (2, 16, 32, 16, 32),
+               (1, 19, 40, 40, 24), (3, 8, 64, 96, 64), (4, 64, 64, 128, 128),
+               (40, 64, 64, 16, 16)]
 
 
 @pytest.mark.parametrize("n,h,w,cin,cout", WGRAD_CASES)
