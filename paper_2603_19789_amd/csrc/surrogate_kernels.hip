@@ -29,6 +29,7 @@
 //             in a fixed order by a second kernel, so results are deterministic.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 #include "seird_device.h"  // xcd_tile
@@ -1337,23 +1338,37 @@ static void conv_fwd_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t
 
 // Workgroups of kernel f (256 threads) resident on the current device at
 // once, from its register and LDS use; 0 if the runtime cannot say.
-static int resident_workgroups(const void *f) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+// (Queried once per kernel and device: `cache` holds one slot per device.)
+constexpr int MAX_DEVICES = 64;
+static int resident_workgroups(const void *f, std::atomic<int> *cache) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    if (dev >= 0 && dev < MAX_DEVICES) {
+        const int known = cache[dev].load(std::memory_order_relaxed);
+        if (known > 0)
+            return known;
+    }
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, THREADS, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
+    if (dev >= 0 && dev < MAX_DEVICES)
+        cache[dev].store(cus * per_cu, std::memory_order_relaxed);
     return cus * per_cu;
 }
 
 template <int NT, bool F32OUT, bool LEAKY, bool POOL>
 static void conv_halo_go(const ConvArgs &a, hipStream_t s) {
+    static std::atomic<int> cache[MAX_DEVICES];  // zero-initialised (static storage)
     const int tiles_x = (a.w + HALO_TW - 1) / HALO_TW, tiles_y = (a.h + HALO_TH - 1) / HALO_TH;
     const int units = a.n * tiles_x * tiles_y * ((a.cout + 16 * NT - 1) / (16 * NT));
     const void *f = (const void *)conv_halo_kernel<NT, F32OUT, LEAKY, POOL>;
-    const int resident = resident_workgroups(f);
+    const int resident = resident_workgroups(f, cache);
     const int blocks = resident > 0 && resident < units ? resident : units;
     hipLaunchKernelGGL((conv_halo_kernel<NT, F32OUT, LEAKY, POOL>), dim3((unsigned)blocks),
                        dim3(THREADS), 0, s, a, tiles_x, tiles_y, units);
