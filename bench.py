@@ -277,6 +277,7 @@ def run_surrogate(torch, inputs, Solver, train_steps):
     plain = Solver(w.nx, w.ny, w.params, dtype="f32")
     st = rho0.clone()
     scratch = torch.empty_like(st)
+    plain_launch = plain.tune(st, scratch)  # pass shape for this grid size (untimed)
     plain.run(st, T, scratch)  # warm-up
     st = rho0.clone()
     torch.cuda.synchronize()
@@ -287,15 +288,18 @@ def run_surrogate(torch, inputs, Solver, train_steps):
     plain_ms = ev[0].elapsed_time(ev[1])
     plain_err = S.relative_l2(st, ref)
     roll = S.Rollout(sur, w.params, w.ny, w.nx, tiles=4, tile=64, target=1e-3, seed=0)
+    roll.solver.set_launch(**plain_launch)  # its plain SSLBM steps take the same shape
     roll.run(rho0, 100)  # warm-up (buffers, tables)
     final, rr = roll.run(rho0, T)
     roll_err = S.relative_l2(final, ref)
     # the surrogate alone: every jump accepted (still judged, for the error record)
     free = S.Rollout(sur, w.params, w.ny, w.nx, tiles=4, tile=64, threshold=1e30, seed=0,
                      backoff=False)
+    free.solver.set_launch(**plain_launch)
     free_state, fr = free.run(rho0, T)
     free_err = S.relative_l2(free_state, ref)
     bare = S.Rollout(sur, w.params, w.ny, w.nx, threshold=float("inf"), seed=0, backoff=False)
+    bare.solver.set_launch(**plain_launch)
     _, br = bare.run(rho0, T)
     return {"workload": w.name, "T": T, "jump": sur.jump, "parameters": net.parameters,
             "train": {"steps": rep.steps, "batch": rep.batch, "size": 256, "samples": rep.samples,
@@ -303,7 +307,8 @@ def run_surrogate(torch, inputs, Solver, train_steps):
                       "last_loss": rep.last_loss, "tflops": round(rep.conv_tflops, 1)},
             "inference_batch64_256_ms": round(infer_ms, 3),
             "inference_tflops": round(infer_tflops, 1),
-            "plain_ms": round(plain_ms, 3), "plain_rel_l2_vs_fp64": plain_err,
+            "plain_ms": round(plain_ms, 3), "plain_launch": plain_launch,
+            "plain_rel_l2_vs_fp64": plain_err,
             "rollout_ms": round(rr.seconds * 1e3, 3), "rollout_rel_l2_vs_fp64": roll_err,
             "accepted_jumps": rr.accepted, "fallback_jumps": rr.fallbacks,
             "skipped_jumps": rr.skipped, "prefiltered_jumps": rr.prefiltered,

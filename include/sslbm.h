@@ -130,6 +130,22 @@ int sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape);
 int sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape);
 
 /*
+ * Autotuner: times candidate launch shapes of sslbm_run on the caller's
+ * state and keeps the fastest (it becomes the context's shape; *best, if not
+ * NULL, receives it). Candidates: one and (for an even row length and
+ * pair-aligned buffers) two columns per lane; every depth from 1 to the
+ * register limit; rows_per_wave automatic (one round of resident
+ * wavefronts) and 8, 16, 32, 64, 128 where at least twice the depth. Each
+ * candidate runs one untimed and three timed passes rho -> scratch (device
+ * buffers of 5 * nx * ny elements, not overlapping): rho is only read,
+ * scratch is overwritten. Timed with HIP events on hip_stream after
+ * synchronizing it; the call returns when tuning is done. Useful where the
+ * automatic shape is far from the best, chiefly grids too small to give
+ * every resident wavefront a tall chunk.
+ */
+int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream, sslbm_launch *best);
+
+/*
  * One SSLBM time step for all five compartments, Eq. (sslbm_final_clean)
  * with rho_f, rho_b, rho_c of Eqs. (rhof), (rhob), (rhoc) for the mobile
  * compartments, the sources of Eq. (sources) and forward Euler for D,

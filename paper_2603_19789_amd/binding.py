@@ -86,6 +86,7 @@ def library() -> ctypes.CDLL:
             "sslbm_get_blocking": [vp],
             "sslbm_set_launch": [vp, ctypes.POINTER(Launch)],
             "sslbm_get_launch": [vp, ctypes.POINTER(Launch)],
+            "sslbm_tune": [vp, vp, vp, vp, ctypes.POINTER(Launch)],
             "sslbm_step": [vp, vp, vp, vp],
             "sslbm_run": [vp, vp, vp, ll, vp],
             "bgk_init": [vp, vp, vp, vp, vp],
@@ -265,6 +266,18 @@ class Solver(_Context):
         self._check(self.lib.sslbm_get_launch(self.handle, ctypes.byref(shape)),
                     "sslbm_get_launch")
         return shape.as_dict()
+
+    def tune(self, rho, scratch=None, stream=None) -> dict:
+        """Time candidate pass shapes on `rho` (only read; `scratch` is
+        overwritten) and keep the fastest; returns it."""
+        if scratch is None:
+            scratch = self.empty(*self.shape)
+        a = self._tensor(rho, self.shape, "rho")
+        b = self._tensor(scratch, self.shape, "scratch")
+        best = Launch()
+        self._check(self.lib.sslbm_tune(self.handle, a, b, _stream(stream), ctypes.byref(best)),
+                    "sslbm_tune")
+        return best.as_dict()
 
     def step(self, rho_in, rho_out=None, stream=None):
         """One time step rho_in -> rho_out (allocated when not given)."""

@@ -241,6 +241,75 @@ int sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape) {
     return SSLBM_OK;
 }
 
+int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream,
+               sslbm_launch *best) {
+    if (!c || !rho || !scratch)
+        return SSLBM_E_ARG;
+    const size_t bytes = 5 * plane_elems(c) * elem_size(c);
+    if (overlap(rho, bytes, scratch, bytes))
+        return SSLBM_E_ALIAS;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    int st = hip_status(c, hipStreamSynchronize(s));
+    if (st != SSLBM_OK)
+        return st;
+    hipEvent_t t0, t1;
+    st = hip_status(c, hipEventCreate(&t0));
+    if (st != SSLBM_OK)
+        return st;
+    st = hip_status(c, hipEventCreate(&t1));
+    if (st != SSLBM_OK) {
+        (void)hipEventDestroy(t0);
+        return st;
+    }
+    const uintptr_t pair = 2 * elem_size(c);
+    const bool pairs_ok =
+        c->nx % 2 == 0 && (uintptr_t)rho % pair == 0 && (uintptr_t)scratch % pair == 0;
+    const sslbm_launch saved = c->launch;
+    sslbm_launch best_shape = resolve(c);
+    double best_ns = 1e300;
+    for (int V = 1; V <= (pairs_ok ? 2 : 1) && st == SSLBM_OK; ++V) {
+        for (int K = 1; K <= sslbm::march_max_depth(c->dtype, V) && st == SSLBM_OK; ++K) {
+            const int cands[] = {0, 8, 16, 32, 64, 128};
+            for (int H : cands) {
+                if (H != 0 && H < 2 * K)
+                    continue;
+                c->launch = sslbm_launch{K, H, V};
+                // one untimed pass, then three timed ones, all rho -> scratch
+                for (int rep = 0; rep < 4 && st == SSLBM_OK; ++rep) {
+                    if (rep == 1)
+                        st = hip_status(c, hipEventRecord(t0, s));
+                    if (st == SSLBM_OK)
+                        st = sslbm::run_pass(c, rho, scratch, K, s);
+                }
+                if (st == SSLBM_OK)
+                    st = hip_status(c, hipEventRecord(t1, s));
+                if (st == SSLBM_OK)
+                    st = hip_status(c, hipEventSynchronize(t1));
+                float ms = 0.f;
+                if (st == SSLBM_OK)
+                    st = hip_status(c, hipEventElapsedTime(&ms, t0, t1));
+                if (st != SSLBM_OK)
+                    break;
+                const double ns_per_step = 1e6 * ms / (3.0 * K);
+                if (ns_per_step < best_ns) {
+                    best_ns = ns_per_step;
+                    best_shape = resolve(c);
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (st != SSLBM_OK) {
+        c->launch = saved;
+        return st;
+    }
+    c->launch = best_shape;
+    if (best)
+        *best = best_shape;
+    return SSLBM_OK;
+}
+
 int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass) {
     if (!c)
         return SSLBM_E_ARG;

@@ -119,6 +119,9 @@ def test_aliasing_and_argument_errors_before_any_gpu_call(lib):
     assert lib.sslbm_run(h, a, b, 5, None) == binding.E_ALIAS
     assert lib.sslbm_run(h, a, c, -1, None) == binding.E_ARG
     assert lib.sslbm_run(h, a, c, 0, None) == binding.OK   # nothing to do, no HIP call
+    assert lib.sslbm_tune(h, a, b, None, None) == binding.E_ALIAS
+    assert lib.sslbm_tune(h, a, None, None, None) == binding.E_ARG
+    assert lib.sslbm_tune(None, a, c, None, None) == binding.E_ARG
     out = (ctypes.c_double * 5)()
     assert lib.sslbm_total(h, None, out, None) == binding.E_ARG
     assert lib.sslbm_set_blocking(h, -1) == binding.E_ARG

@@ -114,6 +114,28 @@ def test_launch_shape_is_bitwise_invisible(dtype, bc, nx, ny):
     assert tried >= 30
 
 
+@pytest.mark.parametrize("nx,ny", [(256, 256), (131, 45)])
+def test_tune_reads_only_and_keeps_the_bits(nx, ny):
+    """The autotuner only reads the state, leaves the context on a valid shape
+    it reports, and runs afterwards give the same bits as before tuning (odd
+    sizes: one column per lane only)."""
+    p = params_for()
+    rho0 = to_gpu(inputs.random_state(nx, ny, seed=12), "f32")
+    s = Solver(nx, ny, p, dtype="f32")
+    ref = rho0.clone()
+    s.run(ref, 23)
+    x = rho0.clone()
+    best = s.tune(x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, rho0)
+    assert best == s.launch()
+    assert 1 <= best["steps_per_pass"] <= 8 and best["cols_per_lane"] in (1, 2)
+    assert best["rows_per_wave"] >= 1
+    y = rho0.clone()
+    s.run(y, 23)
+    assert torch.equal(y, ref)
+
+
 def test_unaligned_buffers_bitwise():
     """Buffers at any element offset give the same bits (no alignment needs)."""
     nx, ny = 96, 40
