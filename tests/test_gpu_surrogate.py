@@ -39,6 +39,10 @@ def bf16_array(shape, scale=1.0):
 
 
 def check_close(got, want, scale, rtol, what):
+    """|got - want| <= rtol |want| + 1e-5 scale everywhere. For BF16 results
+    rtol = 2^-8 is the rounding bound itself (half an ulp, reached just above
+    a power of two), so worst ratios near 1 are expected; the absolute term,
+    scaled by the sum of absolute products, covers the FP32 accumulation."""
     err = np.abs(got - want)
     bound = rtol * np.abs(want) + 1e-5 * scale + 1e-30
     worst = float(np.max(err / bound))
