@@ -714,3 +714,43 @@ class Rollout:
                                     float(np.median(errs)), share, skipped, prefiltered)
 
 
+
+
+def _main(argv=None):
+    """Time the network's passes (random weights and inputs): forward at
+    one batch size, forward + backward at another, on square images.
+    `python -m paper_2603_19789_amd.surrogate [--forward-batch 64]
+    [--backward-batch 16] [--size 256] [--passes 3]`; prints one line per
+    measurement (for kernel traces of the network's layers)."""
+    import argparse
+    torch = _torch()
+    ap = argparse.ArgumentParser(description=_main.__doc__)
+    ap.add_argument("--forward-batch", type=int, default=64)
+    ap.add_argument("--backward-batch", type=int, default=16)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--passes", type=int, default=3)
+    args = ap.parse_args(argv)
+    net = UNet(levels=4, base=32, seed=0)
+    for batch, backward in ((args.forward_batch, False), (args.backward_batch, True)):
+        net._buffers(batch, args.size, args.size)
+        net.x0.normal_()
+        net.dout.normal_()
+        net.forward_packed()
+        if backward:
+            net.backward_packed()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.passes):
+            net.forward_packed()
+            if backward:
+                net.backward_packed()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.passes * 1e3
+        flops = net.flops(batch, args.size, args.size) * (3.0 if backward else 1.0)
+        what = "forward + backward" if backward else "forward"
+        print(f"{what}, batch {batch} at {args.size}^2: {ms:.3f} ms per pass, "
+              f"{flops / ms / 1e9:.1f} TFLOP/s", flush=True)
+
+
+if __name__ == "__main__":
+    _main()
