@@ -52,7 +52,7 @@ int auto_cols(const sslbm_ctx *c) { return c->dtype == SSLBM_F32 ? 2 : 1; }
 // which all wavefronts of the pass are resident at once (one round, no tail),
 // but at least 2K rows so the halo rows stay a minority. Without a device to
 // query, a fixed estimate of three resident wavefronts per SIMD is used.
-int auto_rows(const sslbm_ctx *c, int K, int V) {
+long long round_rows(const sslbm_ctx *c, int K, int V) {
     const int w = sslbm::strip_width(K, V);
     const long long strips = (c->nx + w - 1) / w;
     long long resident = sslbm::march_resident_waves(c->dtype, K, V, c->coef.diffuse_d);
@@ -61,7 +61,11 @@ int auto_rows(const sslbm_ctx *c, int K, int V) {
     long long chunks = resident / strips;
     if (chunks < 1)
         chunks = 1;
-    long long h = (c->ny + chunks - 1) / chunks;
+    return (c->ny + chunks - 1) / chunks;
+}
+
+int auto_rows(const sslbm_ctx *c, int K, int V) {
+    long long h = round_rows(c, K, V);
     if (h < 2 * K)
         h = 2 * K;
     if (h > 65536)
@@ -74,8 +78,17 @@ sslbm_launch resolve(const sslbm_ctx *c) {
     sslbm_launch r = c->launch;
     if (r.steps_per_pass == 0)
         r.steps_per_pass = auto_depth(c);
-    if (r.cols_per_lane == 0)
+    if (r.cols_per_lane == 0) {
         r.cols_per_lane = auto_cols(c);
+        // A grid too small to give one round of resident two-column strips
+        // chunks of 2K rows takes one column per lane: twice the strips, and
+        // the narrower kernel keeps more wavefronts resident (1024^2 FP32:
+        // 259 -> about 305 GLUPS at six steps per pass).
+        const int K = r.steps_per_pass;
+        if (r.cols_per_lane == 2 && K <= sslbm::march_max_depth(c->dtype, 1) &&
+            round_rows(c, K, 2) < 2 * K)
+            r.cols_per_lane = 1;
+    }
     if (r.rows_per_wave == 0)
         r.rows_per_wave = auto_rows(c, r.steps_per_pass, r.cols_per_lane);
     return r;
