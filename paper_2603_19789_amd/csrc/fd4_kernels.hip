@@ -11,10 +11,12 @@
 // lap u = sum over the axes of -u(-2) + 16 u(-1) - 30 u + 16 u(+1) - u(+2).
 // Each stage is one launch, because every stage reads its input two cells
 // around each node: stage s reads its input y_s with the stencil and writes
-// the next input y_{s+1} = u + c_s k_s (c = 1/2, 1/2, 1) and the running sum
-// w = u + (k1 + 2 k2 + 2 k3) / 6 (pointwise); the last stage writes
-// u' = w + k4 / 6 over u. Buffers: u (the state), two stage inputs used
-// alternately, w.
+// the next input y2 = u + k1/2, y3 = u + k2/2, y4 = u + k3. The stage inputs
+// hold the k's (k1 = 2 (y2 - u), k2 = 2 (y3 - u), k3 = y4 - u), so the last
+// stage needs no running sum: u' = (y2 + 2 y3 + y4 - u) / 3 + k4 / 6, written
+// over u. Buffers: u (the state), y2, y3, y4. Per node and step the four
+// stages move 13 state-sized arrays (stencil reads counted once), against 16
+// with a running sum.
 //
 // A workgroup of 256 threads takes a tile of 64 columns x 16 rows: the tile
 // and its two-cell halo of all five fields are staged in LDS (ghost cells by
@@ -37,8 +39,8 @@ constexpr int ROWS_PER_THREAD = FY * FX / FD4_THREADS;
 
 template <typename T, int STAGE>
 __global__ __launch_bounds__(FD4_THREADS) void fd4_stage_kernel(
-    const T *__restrict__ y_in, const T *__restrict__ u, T *__restrict__ w,
-    T *__restrict__ y_out, GridDesc g, Coef<T> k, int tiles_x, int tiles) {
+    const T *__restrict__ y_in, const T *u, const T *__restrict__ y2,
+    const T *__restrict__ y3, T *out, GridDesc g, Coef<T> k, int tiles_x, int tiles) {
     __shared__ T tile[5][GY][GX];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     if (t >= tiles)
@@ -86,20 +88,16 @@ __global__ __launch_bounds__(FD4_THREADS) void fd4_stage_kernel(
             const T kc = fma(dl12[c], along_x + along_y, src[c]);
             const long long i = c * g.plane + cell;
             if constexpr (STAGE == 1) {
-                // y_in is u
-                w[i] = fma(kc, T(1) / T(6), cen[c]);
-                y_out[i] = fma(kc, T(0.5), cen[c]);
+                out[i] = fma(kc, T(0.5), cen[c]);  // y_in is u
             } else if constexpr (STAGE == 2) {
-                const T uc = u[i];
-                w[i] = fma(kc, T(1) / T(3), w[i]);
-                y_out[i] = fma(kc, T(0.5), uc);
+                out[i] = fma(kc, T(0.5), u[i]);
             } else if constexpr (STAGE == 3) {
-                const T uc = u[i];
-                w[i] = fma(kc, T(1) / T(3), w[i]);
-                y_out[i] = kc + uc;
+                out[i] = kc + u[i];
             } else {
-                // y_out is u: the new state
-                y_out[i] = fma(kc, T(1) / T(6), w[i]);
+                // out is u: the new state (each node read, then written, by
+                // its own thread; the stencil reads y4, not u)
+                const T s = ((y2[i] + T(2) * y3[i]) + cen[c]) - u[i];
+                out[i] = fma(kc, T(1) / T(6), s / T(3));
             }
         }
     }
@@ -109,9 +107,9 @@ template <typename T>
 hipError_t launch_t(void *rho, void *work, const GridDesc &g, const StepCoef &s, long long n,
                     hipStream_t st) {
     T *u = static_cast<T *>(rho);
-    T *a = static_cast<T *>(work);
-    T *b = a + 5 * g.plane;
-    T *w = b + 5 * g.plane;
+    T *y2 = static_cast<T *>(work);
+    T *y3 = y2 + 5 * g.plane;
+    T *y4 = y3 + 5 * g.plane;
     Coef<T> k;
     for (int c = 0; c < 5; ++c)
         k.dl[c] = (T)s.dl[c];
@@ -124,14 +122,14 @@ hipError_t launch_t(void *rho, void *work, const GridDesc &g, const StepCoef &s,
     const int tiles = tiles_x * ((g.ny + FY - 1) / FY);
     const dim3 grid((unsigned)tiles), block(FD4_THREADS);
     for (long long step = 0; step < n; ++step) {
-        hipLaunchKernelGGL((fd4_stage_kernel<T, 1>), grid, block, 0, st, u, u, w, a, g, k, tiles_x,
-                           tiles);
-        hipLaunchKernelGGL((fd4_stage_kernel<T, 2>), grid, block, 0, st, a, u, w, b, g, k, tiles_x,
-                           tiles);
-        hipLaunchKernelGGL((fd4_stage_kernel<T, 3>), grid, block, 0, st, b, u, w, a, g, k, tiles_x,
-                           tiles);
-        hipLaunchKernelGGL((fd4_stage_kernel<T, 4>), grid, block, 0, st, a, u, w, u, g, k, tiles_x,
-                           tiles);
+        hipLaunchKernelGGL((fd4_stage_kernel<T, 1>), grid, block, 0, st, u, u, y2, y3, y2, g, k,
+                           tiles_x, tiles);
+        hipLaunchKernelGGL((fd4_stage_kernel<T, 2>), grid, block, 0, st, y2, u, y2, y3, y3, g, k,
+                           tiles_x, tiles);
+        hipLaunchKernelGGL((fd4_stage_kernel<T, 3>), grid, block, 0, st, y3, u, y2, y3, y4, g, k,
+                           tiles_x, tiles);
+        hipLaunchKernelGGL((fd4_stage_kernel<T, 4>), grid, block, 0, st, y4, u, y2, y3, u, g, k,
+                           tiles_x, tiles);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
