@@ -797,8 +797,9 @@ __global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
 // (8 consecutive pixels of one channel) is one aligned 16-byte LDS read;
 // pixels outside the image carry dZ = 0. Wavefront w takes tile rows 2w and
 // 2w + 1 as its k steps (32 pixels each) and accumulates all nine taps of
-// the 32 x 32 block (each dZ fragment serves nine taps). Each wavefront
-// writes its sums as one split of the fixed-order reduction below. The
+// the 32 x 32 block (each dZ fragment serves nine taps). The four
+// wavefronts' sums are added in LDS and written as the workgroup's split of
+// the fixed-order reduction below. The
 // workgroups of input block 0 also sum the dZ tile per output channel (the
 // bias gradient), thread (o, s) over pixels 32 s .. 32 s + 31 of every tile,
 // and write the eight per-thread sums of a channel, added in order, as
@@ -819,7 +820,7 @@ struct WgradHaloArgs {
     const uint16_t *x, *dz;
     int xp, dzp, n, h, w, cin, cout;
     int nob, nib, gb, tiles, tiles_x, tiles_y;
-    float *part;    // [4 gb][cout][9][cin]
+    float *part;    // [gb][cout][9][cin]
     float *part_b;  // [gb][cout]
 };
 
@@ -958,25 +959,72 @@ void conv_wgrad_halo_kernel(WgradHaloArgs a) {
                 a.part_b[(long long)kb * a.cout + oc0 + tid] = b;
         }
     }
-    // this wavefront's split: rows 4 g + jj of subtile u (output channels),
-    // column m of subtile v (input channels)
+    // The four wavefronts' sums, added in LDS in a fixed order,
+    // (w0 + w2) + (w1 + w3), one wavefront's worth (144 values a lane) at a
+    // time through the input-tile area; the workgroup then writes its split.
+    float *red = reinterpret_cast<float *>(Bx);
+    auto put = [&]() {
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        red[(((t * 2 + u) * 2 + v) * 4 + jj) * 64 + lane] = acc[t][u][v][jj];
+    };
+    auto add = [&]() {
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        acc[t][u][v][jj] += red[(((t * 2 + u) * 2 + v) * 4 + jj) * 64 + lane];
+    };
+    __syncthreads();  // the input tile area is free
+    if (wv == 2)
+        put();
+    __syncthreads();
+    if (wv == 0)
+        add();
+    __syncthreads();
+    if (wv == 3)
+        put();
+    __syncthreads();
+    if (wv == 1)
+        add();
+    __syncthreads();
+    if (wv == 1)
+        put();
+    __syncthreads();
+    if (wv == 0) {
+        add();
+        // the block's sums in LDS as [o][t][i] (32 x 9 x 32), over the
+        // values just read (a wavefront's LDS accesses stay in order)
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        red[((16 * u + 4 * g + jj) * 9 + t) * 32 + 16 * v + m] = acc[t][u][v][jj];
+    }
+    __syncthreads();
+    // the workgroup's split, rows of 32 input channels per (output channel, tap)
     const long long count = (long long)a.cout * 9 * a.cin;
-    float *part = a.part + (long long)(kb * 4 + wv) * count;
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int ic = ic0 + 16 * v + m;
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int oc = oc0 + 16 * u + 4 * g + jj;
-                if (oc < a.cout && ic < a.cin) {
-#pragma unroll
-                    for (int t = 0; t < 9; ++t)
-                        part[((long long)oc * 9 + t) * a.cin + ic] = acc[t][u][v][jj];
-                }
-            }
-        }
+    float *part = a.part + (long long)kb * count;
+    for (int e = tid; e < 32 * 9 * 32; e += THREADS) {
+        const int o = e / 288, r = e - o * 288;
+        const int t = r >> 5, i = r & 31;
+        if (oc0 + o < a.cout && ic0 + i < a.cin)
+            part[((long long)(oc0 + o) * 9 + t) * a.cin + ic0 + i] = red[e];
+    }
 }
 
 // dW = sum over splits in a fixed order, in two passes: pass 1 sums each
@@ -1450,7 +1498,7 @@ WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
         long long gb = WH_RESIDENT / blocks;
         gb = gb < 1 ? 1 : (gb > tiles ? tiles : gb);
         p.gb = (int)gb;
-        p.splits = 4 * p.gb;  // one per wavefront
+        p.splits = p.gb;  // one per workgroup
         p.Pr = p.Pp = p.chunk = p.waves = 0;
         p.ni = 0;
         p.dz_t_bytes = p.xs_bytes = 0;
