@@ -56,6 +56,19 @@ int sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, in
                              int cout, int flags, float slope, void *pooled, int pooled_pitch,
                              void *hip_stream);
 
+/* The forward convolution (BF16 output; flags: SUR_LEAKY only) of the
+ * channel concatenation [up2(xu), x]: input channels [0, cu) are `xu`
+ * (n, h/2, w/2; a BF16 view of cu channels) upsampled 2x by repetition,
+ * channels [cu, cin) are `x` (a view of cin - cu channels), without
+ * materialising the upsampled tensor. Bit for bit sur_up2 into a
+ * concatenation buffer followed by sur_conv3x3_forward. cu a multiple of
+ * 32 and less than cin; h, w even. SSLBM_E_UNSUPPORTED for images under
+ * 8 x 32 pixels (the caller upsamples explicitly there). */
+int sur_conv3x3_forward_up(const void *xu, int xu_pitch, int cu, const void *x, int x_pitch,
+                           int n, int h, int w, int cin, const void *weight, const float *bias,
+                           void *y, int y_pitch, int cout, int flags, float slope,
+                           void *hip_stream);
+
 /* dx = d(sum dz * conv(x)) / dx for weight [cout][9][cin]: the convolution
  * of dz with the weights flipped in space and transposed in channels, built
  * in `flip_scratch` (device, >= 18 cout cin bytes). dx is overwritten. */

@@ -119,6 +119,7 @@ def library() -> ctypes.CDLL:
             # surrogate.h
             "sur_conv3x3_forward": [vp, i, i, i, i, i, vp, vp, vp, i, i, i, f, vp],
             "sur_conv3x3_forward_pool": [vp, i, i, i, i, i, vp, vp, vp, i, i, i, f, vp, i, vp],
+            "sur_conv3x3_forward_up": [vp, i, i, vp, i, i, i, i, i, vp, vp, vp, i, i, i, f, vp],
             "sur_conv3x3_backward_data": [vp, i, i, i, i, i, vp, i, vp, i, vp, vp],
             "sur_conv3x3_backward_weight": [vp, i, vp, i, i, i, i, i, i, vp, vp, vp, sz, vp],
             "sur_leaky_backward": [vp, i, vp, i, vp, i, ll, i, f, vp],

@@ -86,11 +86,47 @@ int conv_forward(const void *x, int x_pitch, int n, int h, int w, int cin, const
     a.slope = slope;
     a.pool = pooled;
     a.pool_pitch = pooled_pitch;
+    a.xu = nullptr;
+    a.xu_pitch = a.cu = 0;
     return status(sslbm::launch_conv_fwd(a, flags & SUR_LEAKY, flags & SUR_OUT_F32,
                                          (hipStream_t)hip_stream));
 }
 
 }  // namespace
+
+int sur_conv3x3_forward_up(const void *xu, int xu_pitch, int cu, const void *x, int x_pitch,
+                           int n, int h, int w, int cin, const void *weight, const float *bias,
+                           void *y, int y_pitch, int cout, int flags, float slope,
+                           void *hip_stream) {
+    if (cu <= 0 || cu % 32 || cin <= cu || !view_ok(xu, xu_pitch, cu) ||
+        !view_ok(x, x_pitch, cin - cu) || !dims_ok(n, h, w) || h % 2 || w % 2 || !weight ||
+        !aligned16(weight) || (flags & ~SUR_LEAKY) || cout <= 0 || cout > MAX_CHANNELS ||
+        cin > MAX_CHANNELS || !view_ok(y, y_pitch, cout) || !std::isfinite(slope) ||
+        !conv_input_fits(x_pitch, n, h, w, cin - cu) ||
+        !conv_input_fits(xu_pitch, n, h / 2, w / 2, cu))
+        return SSLBM_E_ARG;
+    if (h < 8 || w < 32)
+        return SSLBM_E_UNSUPPORTED;  // needs the halo-tile kernel
+    sslbm::ConvArgs a;
+    a.x = x;
+    a.x_pitch = x_pitch;
+    a.n = n;
+    a.h = h;
+    a.w = w;
+    a.cin = cin;
+    a.wt = weight;
+    a.bias = bias;
+    a.y = y;
+    a.y_pitch = y_pitch;
+    a.cout = cout;
+    a.slope = slope;
+    a.pool = nullptr;
+    a.pool_pitch = 0;
+    a.xu = xu;
+    a.xu_pitch = xu_pitch;
+    a.cu = cu;
+    return status(sslbm::launch_conv_fwd(a, flags & SUR_LEAKY, false, (hipStream_t)hip_stream));
+}
 
 int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
                         const void *weight, const float *bias, void *y, int y_pitch, int cout,
@@ -135,6 +171,8 @@ int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w,
     a.slope = 0.f;
     a.pool = nullptr;
     a.pool_pitch = 0;
+    a.xu = nullptr;
+    a.xu_pitch = a.cu = 0;
     return status(sslbm::launch_conv_fwd(a, false, false, s));
 }
 

@@ -26,6 +26,11 @@ struct ConvArgs {
     float slope;
     void *pool;  // BF16 NHWC view (n, h/2, w/2) of the 2 x 2 means of y, or null
     int pool_pitch;
+    // Input channels [0, cu) from xu, a BF16 NHWC view (n, h/2, w/2) read
+    // as its nearest 2x upsampling; channels [cu, cin) from x (its channel
+    // cu is x's channel 0). xu null: all from x.
+    const void *xu;
+    int xu_pitch, cu;
 };
 
 struct WgradArgs {

@@ -297,7 +297,10 @@ constexpr int HALO_TH = 8, HALO_TW = 32;
 // rows start at an even row and a lane's columns 4 g .. 4 g + 3 at an even
 // column, so every window lies in one lane), with the sums of the separate
 // pooling kernel in its order, hence its bits.
-template <int NT, bool F32OUT, bool LEAKY, bool POOL>
+// UP: the first cu input channels are read from a half-resolution view
+// as its nearest 2x upsampling (pixel (y, x) reads (y / 2, x / 2)), so a
+// decoder's upsampled skip concatenation needs no upsampled copy in HBM.
+template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(NT == 4 ? 2 : 3)))
 void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     constexpr int HW2 = HALO_TW + 2, HPIX = (HALO_TH + 2) * HW2;
@@ -318,8 +321,13 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
     const long long P = (long long)a.n * a.h * a.w;
+    const int cx = UP ? a.cin - a.cu : a.cin;  // channels read from x
     const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<void *>(a.x), (short)0, (int)(((P - 1) * a.x_pitch + a.cin) * 2), BUF_FORMAT_WORD);
+        const_cast<void *>(a.x), (short)0, (int)(((P - 1) * a.x_pitch + cx) * 2), BUF_FORMAT_WORD);
+    const int hu = a.h / 2, wu = a.w / 2;
+    const __amdgpu_buffer_rsrc_t xur = __builtin_amdgcn_make_buffer_rsrc(
+        UP ? const_cast<void *>(a.xu) : const_cast<void *>(a.x), (short)0,
+        UP ? (int)((((long long)a.n * hu * wu - 1) * a.xu_pitch + a.cu) * 2) : 0, BUF_FORMAT_WORD);
     const __amdgpu_buffer_rsrc_t wr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<void *>(a.wt), (short)0, a.cout * 9 * a.cin * 2, BUF_FORMAT_WORD);
     // the bias goes through LDS with the weights (no bias: a range of 0 bytes
@@ -346,19 +354,15 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
         blds[j] = row * LDA + 8 * k;
     }
     // halo pieces: pixel hp of the halo tile, 8 channels k of the chunk
-    unsigned hoff[HPT];
-    int hk[HPT], hlds[HPT], hy[HPT], hx[HPT];
-    bool hst[HPT];
-#pragma unroll
-    for (int j = 0; j < HPT; ++j) {
-        const int e = tid + THREADS * j;
-        hst[j] = e < HP;
-        const int hp = min(e >> 2, HPIX - 1), k = e & 3;
-        hy[j] = hp / HW2;
-        hx[j] = hp - hy[j] * HW2;
-        hk[j] = 8 * k;
-        hlds[j] = hp * LDA + 8 * k;
-    }
+    // (hoffu: the same pixel in the half-resolution view)
+    // (piece j of a thread: pixel (tid >> 2) + 64 j, the same 8 channels
+    // hk for every j, LDS slot hlds + 64 j LDA; the pixel's row and column
+    // are recomputed where needed rather than kept in registers)
+    unsigned hoff[HPT], hoffu[HPT];
+    const int hk = 8 * (tid & 3);
+    const int hlds = (tid >> 2) * LDA + hk;
+    auto hpix = [&](int j) { return min((tid >> 2) + 64 * j, HPIX - 1); };
+    auto hst = [&](int j) { return tid + THREADS * j < HP; };
     auto unit_origin = [&](int unit, int &n, int &y0, int &x0, int &cg) {
         const int tile = unit / groups;
         cg = unit - tile * groups;
@@ -374,8 +378,12 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
         unit_origin(unit, n, y0, x0, cg);
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
-            const int y = wrap(y0 - 1 + hy[j], a.h), x = wrap(x0 - 1 + hx[j], a.w);
-            hoff[j] = (unsigned)(((((long long)n * a.h + y) * a.w + x) * a.x_pitch + hk[j]) * 2);
+            const int hp = hpix(j), hy = hp / HW2, hx = hp - hy * HW2;
+            const int y = wrap(y0 - 1 + hy, a.h), x = wrap(x0 - 1 + hx, a.w);
+            hoff[j] = (unsigned)(((((long long)n * a.h + y) * a.w + x) * a.x_pitch + hk) * 2);
+            if constexpr (UP)
+                hoffu[j] = (unsigned)(
+                    ((((long long)n * hu + (y >> 1)) * wu + (x >> 1)) * a.xu_pitch + hk) * 2);
         }
 #pragma unroll
         for (int j = 0; j < BPT; ++j) {
@@ -395,10 +403,22 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     auto gload = [&](int chunk, bool weights) {
         Stage r;
         const int left = a.cin - 32 * chunk;
-        const unsigned c2 = (unsigned)(64 * chunk);
+        if constexpr (UP) {
+            // cu is a multiple of 32: a chunk comes from one view
+            const bool from_up = 32 * chunk < a.cu;
+            const __amdgpu_buffer_rsrc_t src = from_up ? xur : xr;
+            const unsigned c2 = (unsigned)(64 * (from_up ? chunk : chunk - a.cu / 32));
 #pragma unroll
-        for (int j = 0; j < HPT; ++j)
-            r.h[j] = load16(xr, hst[j] && hk[j] < left ? hoff[j] + c2 : OUT_OF_RANGE);
+            for (int j = 0; j < HPT; ++j)
+                r.h[j] = load16(src, hst(j) && hk < left ? (from_up ? hoffu[j] : hoff[j]) + c2
+                                                         : OUT_OF_RANGE);
+        } else {
+            const unsigned c2 = (unsigned)(64 * chunk);
+#pragma unroll
+            for (int j = 0; j < HPT; ++j)
+                r.h[j] = load16(xr, hst(j) && hk < left ? hoff[j] + c2 : OUT_OF_RANGE);
+        }
+        const unsigned c2 = (unsigned)(64 * chunk);
         if (weights) {
 #pragma unroll
             for (int j = 0; j < BPT; ++j)
@@ -410,8 +430,8 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     auto lstore = [&](const Stage &r, bool weights) {
 #pragma unroll
         for (int j = 0; j < HPT; ++j)
-            if (hst[j])
-                *reinterpret_cast<u32x4 *>(&Hs[hlds[j]]) = r.h[j];
+            if (hst(j))
+                *reinterpret_cast<u32x4 *>(&Hs[hlds + 64 * j * LDA]) = r.h[j];
         if (weights) {
 #pragma unroll
             for (int j = 0; j < BPT; ++j)
@@ -1410,21 +1430,26 @@ static int resident_workgroups(const void *f, std::atomic<int> *cache) {
     return cus * per_cu;
 }
 
-template <int NT, bool F32OUT, bool LEAKY, bool POOL>
+template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP = false>
 static void conv_halo_go(const ConvArgs &a, hipStream_t s) {
     static std::atomic<int> cache[MAX_DEVICES];  // zero-initialised (static storage)
     const int tiles_x = (a.w + HALO_TW - 1) / HALO_TW, tiles_y = (a.h + HALO_TH - 1) / HALO_TH;
     const int units = a.n * tiles_x * tiles_y * ((a.cout + 16 * NT - 1) / (16 * NT));
-    const void *f = (const void *)conv_halo_kernel<NT, F32OUT, LEAKY, POOL>;
+    const void *f = (const void *)conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP>;
     const int resident = resident_workgroups(f, cache);
     const int blocks = resident > 0 && resident < units ? resident : units;
-    hipLaunchKernelGGL((conv_halo_kernel<NT, F32OUT, LEAKY, POOL>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP>), dim3((unsigned)blocks),
                        dim3(THREADS), 0, s, a, tiles_x, tiles_y, units);
 }
 
 template <int NT>
 static void conv_halo_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
-    if (a.pool) {  // BF16 output only
+    if (a.xu) {  // BF16 output, no pooling (a decoder's first convolution)
+        if (leaky)
+            conv_halo_go<NT, false, true, false, true>(a, s);
+        else
+            conv_halo_go<NT, false, false, false, true>(a, s);
+    } else if (a.pool) {  // BF16 output only
         if (leaky)
             conv_halo_go<NT, false, true, true>(a, s);
         else
@@ -1451,8 +1476,11 @@ hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream
         (((long long)a.n * a.h * a.w - 1) * a.y_pitch + a.cout) * (f32out ? 4 : 2);
     const long long pool_bytes =
         a.pool ? (((long long)a.n * (a.h / 2) * (a.w / 2) - 1) * a.pool_pitch + a.cout) * 2 : 0;
-    if (a.h >= HALO_TH && a.w >= HALO_TW && units < (1ll << 31) && out_bytes < (1ll << 31) &&
-        pool_bytes < (1ll << 31)) {
+    const bool halo = a.h >= HALO_TH && a.w >= HALO_TW && units < (1ll << 31) &&
+                      out_bytes < (1ll << 31) && pool_bytes < (1ll << 31);
+    if (a.xu && !halo)
+        return hipErrorNotSupported;  // the upsampled input needs halo tiles
+    if (halo) {
         if (a.cout > 32)
             conv_halo_cfg<4>(a, leaky, f32out, s);
         else if (a.cout > 16)

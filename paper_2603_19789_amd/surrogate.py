@@ -151,6 +151,8 @@ class UNet:
         """Make the buffers of batch n at h x w current. Each shape's set is
         kept, so alternating between shapes (a rollout's whole grid and its
         judge tiles) allocates nothing after the first use of each."""
+        if self._shape != (n, h, w):
+            self._backward_ready = False
         if self._shape == (n, h, w):
             return
         if (n, h, w) in self._sets:
@@ -216,10 +218,30 @@ class UNet:
             _check(self.lib.sur_conv3x3_forward_pool(*args, _ptr(pooled), pooled.shape[-1], None),
                    "sur_conv3x3_forward_pool")
 
-    def forward_packed(self):
-        """Network pass on self.x0 into self.out (FP32 NHWC, 16 channels)."""
+    def _conv_up(self, k, low: _View, skip: _View, dst: _View, l):
+        """Convolution k of decoder level l on [up2(low), skip] without the
+        upsampled copy (sur_conv3x3_forward_up); False where the image is
+        too small for it (the caller then upsamples explicitly)."""
+        cv = self.convs[k]
+        n = self._shape[0]
+        hh, ww = self.dims[l]
+        if hh < 8 or ww < 32:
+            return False
+        flags = LEAKY if cv.act else 0
+        _check(self.lib.sur_conv3x3_forward_up(
+            low.ptr, low.pitch, low.c, skip.ptr, skip.pitch, n, hh, ww, cv.cin,
+            _ptr(self.theta_bf16, cv.w_off), _ptr(self.theta, cv.b_off), dst.ptr, dst.pitch,
+            cv.cout, flags, self.slope, None), "sur_conv3x3_forward_up")
+        return True
+
+    def forward_packed(self, fuse_up=False):
+        """Network pass on self.x0 into self.out (FP32 NHWC, 16 channels).
+        fuse_up: decoder convolutions read the upsampled half-resolution
+        tensor directly (same bits; inference only, since the weight
+        gradients read the concatenation buffer it leaves unfilled)."""
         L, ch, lib = self.levels, self.ch, self.lib
         n = self._shape[0]
+        self._backward_ready = not fuse_up
         k = 0
         for l in range(L):
             src = _View(self.x0, 0, IN_CHANNELS) if l == 0 else _View(self.pool[l], 0, ch[l - 1])
@@ -231,9 +253,11 @@ class UNet:
         h_view = self.e_view(L - 1)
         for l in range(L - 2, -1, -1):
             hh, ww = self.dims[l + 1]
-            _check(lib.sur_up2(h_view.ptr, h_view.pitch, n, hh, ww, ch[l + 1], _ptr(self.cat[l]),
-                               self.cat[l].shape[-1], None), "sur_up2")
-            self._conv(k, _View(self.cat[l], 0, ch[l + 1] + ch[l]), _View(self.b[l], 0, ch[l]), l)
+            dst = _View(self.b[l], 0, ch[l])
+            if not (fuse_up and self._conv_up(k, h_view, self.e_view(l), dst, l)):
+                _check(lib.sur_up2(h_view.ptr, h_view.pitch, n, hh, ww, ch[l + 1],
+                                   _ptr(self.cat[l]), self.cat[l].shape[-1], None), "sur_up2")
+                self._conv(k, _View(self.cat[l], 0, ch[l + 1] + ch[l]), dst, l)
             self._conv(k + 1, _View(self.b[l], 0, ch[l]), _View(self.hdec[l], 0, ch[l]), l)
             k += 2
             h_view = _View(self.hdec[l], 0, ch[l])
@@ -264,7 +288,11 @@ class UNet:
 
     def backward_packed(self):
         """Parameter gradients (into self.grad) from self.dout (BF16 NHWC,
-        the loss gradient of self.out)."""
+        the loss gradient of self.out), after forward_packed() without
+        fuse_up."""
+        if not getattr(self, "_backward_ready", False):
+            raise RuntimeError("backward_packed needs a preceding forward_packed() "
+                               "without fuse_up (the concatenation buffers are unfilled)")
         L, ch, lib = self.levels, self.ch, self.lib
         n = self._shape[0]
         k = len(self.convs) - 1
@@ -366,7 +394,7 @@ class Surrogate:
         pl = torch.tensor(planes, dtype=torch.float32, device="cuda").contiguous()
         _check(self.lib.sur_pack_input(_ptr(rho), b, h, w, _ptr(pl), _floats(self.scale_in),
                                        _ptr(self.net.x0), None), "sur_pack_input")
-        self.net.forward_packed()
+        self.net.forward_packed(fuse_up=True)
         if out is None:
             out = torch.empty_like(rho)
         _check(self.lib.sur_apply_output(_ptr(rho), _ptr(self.net.out), b, h, w,
@@ -735,13 +763,14 @@ def _main(argv=None):
         net._buffers(batch, args.size, args.size)
         net.x0.normal_()
         net.dout.normal_()
-        net.forward_packed()
+        # forward alone as inference runs it; with the backward as training does
+        net.forward_packed(fuse_up=not backward)
         if backward:
             net.backward_packed()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.passes):
-            net.forward_packed()
+            net.forward_packed(fuse_up=not backward)
             if backward:
                 net.backward_packed()
         torch.cuda.synchronize()

@@ -253,6 +253,18 @@ def test_surrogate_header_exports_and_host_checks(lib):
     assert fp(a, 16, 1, 8, 8, 16, b, None, c, 32, 32, 0, 0.1, vp(d.value + 2), 32,
               None) == binding.E_ARG
     assert fp(a, 16, 1, 8, 8, 16, b, None, c, 32, 32, 0, 0.1, d, 24, None) == binding.E_ARG
+    # upsampled input: cu a multiple of 32 below cin, even sizes, BF16 output;
+    # images under 8 x 32 pixels are left to the caller
+    fu = lib.sur_conv3x3_forward_up
+    assert fu(a, 16, 16, d, 32, 1, 8, 32, 48, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG
+    assert fu(a, 32, 32, d, 16, 1, 8, 32, 32, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG
+    assert fu(a, 32, 32, d, 16, 1, 9, 32, 48, b, None, c, 32, 32, 0, 0.1, None) == binding.E_ARG
+    assert fu(a, 32, 32, d, 16, 1, 8, 32, 48, b, None, c, 32, 32, S_OUT_F32, 0.1,
+              None) == binding.E_ARG
+    assert fu(a, 32, 32, d, 16, 1, 6, 32, 48, b, None, c, 32, 32, 0, 0.1,
+              None) == binding.E_UNSUPPORTED
+    assert fu(a, 32, 32, d, 16, 1, 8, 16, 48, b, None, c, 32, 32, 0, 0.1,
+              None) == binding.E_UNSUPPORTED
     assert lib.sur_conv3x3_backward_weight_workspace(1, 8, 12, 16, 16) == 0  # w % 8
     assert lib.sur_conv3x3_backward_weight_workspace(1, 8, 16, 16, 16) > 0
     ws = lib.sur_conv3x3_backward_weight_workspace(2, 8, 16, 32, 64)

@@ -120,6 +120,49 @@ def test_conv_forward_pool_equals_conv_then_pool(n, h, w, cin, cout, leaky):
     assert torch.equal(p1.view(torch.int16), p2.view(torch.int16))
 
 
+@pytest.mark.parametrize("n,h,w,cu,cs,cout", [(2, 16, 32, 64, 32, 32), (1, 18, 40, 32, 16, 24),
+                                                (1, 16, 64, 128, 64, 64), (3, 8, 32, 64, 32, 128)])
+def test_conv_forward_up_equals_upsample_then_conv(n, h, w, cu, cs, cout):
+    """The convolution of [up2(low), skip] reading the half-resolution
+    tensor directly gives the bits of sur_up2 into a concatenation buffer
+    followed by the convolution (halo tiles: whole and ragged, 16 to 64
+    channel groups, several chunks from each source)."""
+    print(f"conv fwd up n={n} {h}x{w} up {cu} + {cs} -> {cout}", flush=True)
+    cin = cu + cs
+    low, _ = bf16_array((n, h // 2, w // 2, cu))
+    cat = torch.zeros((n, h, w, cin), dtype=BF, device="cuda")
+    skip, _ = bf16_array((n, h, w, cs))
+    cat[..., cu:] = skip
+    wt, _ = bf16_array((cout, 9, cin), scale=1.0 / np.sqrt(9 * cin))
+    bias = torch.tensor(RNG.normal(size=cout), dtype=torch.float32).cuda()
+    y1 = torch.zeros((n, h, w, cout), dtype=BF, device="cuda")
+    y2 = torch.zeros_like(y1)
+    L = lib()
+    assert L.sur_up2(p(low), cu, n, h // 2, w // 2, cu, p(cat), cin, None) == binding.OK
+    assert L.sur_conv3x3_forward(p(cat), cin, n, h, w, cin, p(wt), p(bias), p(y1), cout, cout,
+                                 S.LEAKY, 0.1, None) == binding.OK
+    # the skip part as a channel slice of the concatenation buffer, as the network lays it out
+    assert L.sur_conv3x3_forward_up(p(low), cu, cu, p(cat, cu), cin, n, h, w, cin, p(wt), p(bias),
+                                    p(y2), cout, cout, S.LEAKY, 0.1, None) == binding.OK
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.int16), y2.view(torch.int16))
+
+
+def test_network_forward_with_fused_upsampling_is_bitwise():
+    """Inference's forward pass (decoder convolutions on the half-resolution
+    tensors) equals the training forward pass bit for bit."""
+    net = _small_net()
+    net._buffers(2, 64, 64)
+    x = torch.tensor(RNG.normal(size=(2, 64, 64, 16)), dtype=torch.float32).to(BF).cuda()
+    net.x0.copy_(x)
+    a = net.forward_packed().clone()
+    b = net.forward_packed(fuse_up=True).clone()
+    assert torch.equal(a, b)
+    # its concatenation buffers are not filled: no backward pass from it
+    with pytest.raises(RuntimeError):
+        net.backward_packed()
+
+
 @pytest.mark.parametrize("n,h,w,cin,cout", [(1, 9, 7, 24, 48), (2, 16, 40, 40, 24),
                                              (1, 8, 32, 32, 96)])
 def test_conv_forward_without_bias(n, h, w, cin, cout):
