@@ -199,6 +199,7 @@ def run_adjoint(torch, inputs, Solver, steps, every=100):
     target = rho0.clone()
     s.run(target, steps)
     s.set_params(w.params)
+    fwd_launch = s.tune(rho0)  # pass shape for this grid size (untimed; same bits)
     count = s.checkpoint_count(steps, every)
     cps = torch.empty((count, 5, w.ny, w.nx), dtype=torch.float64, device="cuda")
     ws = torch.empty(s.adjoint_workspace_bytes(every), dtype=torch.uint8, device="cuda")
@@ -234,7 +235,8 @@ def run_adjoint(torch, inputs, Solver, steps, every=100):
     nodes = w.nx * w.ny
     bytes_per_step = 15 * 8 * nodes  # lam and rho read, new lam written, 5 fields each
     out = {"workload": w.name, "nx": w.nx, "ny": w.ny, "steps": steps, "checkpoint_every": every,
-           "dtype": "f64", "forward_ms": round(fwd_ms, 3), "reverse_ms": round(rev_ms, 3),
+           "dtype": "f64", "forward_launch": fwd_launch,
+           "forward_ms": round(fwd_ms, 3), "reverse_ms": round(rev_ms, 3),
            "gradient_ms": round(fwd_ms + rev_ms, 3),
            "adjoint_step_ms": round(step_ms, 5),
            "adjoint_step_gbps": round(bytes_per_step / (step_ms * 1e-3) / 1e9, 1),
