@@ -135,6 +135,34 @@ def test_adjoint_run_is_deterministic():
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_run_ignores_the_pass_shape(dtype):
+    """The forward run and the reverse sweep's recomputation passes use the
+    context's pass shape (tuned, or set by hand): the checkpoints, the adjoint
+    field and the gradient keep their bits under every shape."""
+    p = rough_params(0.07)
+    s = Solver(150, 90, p, dtype=dtype)
+    rho0 = to_gpu(inputs.random_state(150, 90, seed=8), dtype)
+    lam0 = to_gpu(inputs.random_state(150, 90, seed=12), dtype)
+
+    def gradient():
+        rho = rho0.clone()
+        cps = s.run_checkpointed(rho, 31, 9)
+        lam, grad = s.adjoint_run(cps, 31, 9, lam0.clone())
+        return cps, lam, grad
+
+    want = gradient()
+    shapes = [(3, 5, 1), (2, 16, 2), (1, 1, 1)]
+    for shape in shapes:
+        s.set_launch(*shape)
+        got = gradient()
+        assert all(torch.equal(g, w) for g, w in zip(got, want)), shape
+    s.set_launch()
+    s.tune(rho0)
+    got = gradient()
+    assert all(torch.equal(g, w) for g, w in zip(got, want)), s.launch()
+
+
 def _c4_loss_fn(solver, rho0, target, nsteps):
     """J = 1/2 |I_T - I*|^2 + 1/2 |D_T - D*|^2 from the forward run alone."""
     def loss(params):
