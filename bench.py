@@ -74,9 +74,11 @@ def parse_args():
     ap.add_argument("--generic-steps", type=int, default=200,
                     help="steps of the generic six-compartment model on D2Q5 and D2Q9 "
                          "(0 skips it)")
-    ap.add_argument("--fd4-steps", type=int, default=20,
+    ap.add_argument("--fd4-steps", type=int, default=0,
                     help="steps of the fourth-order finite-difference / RK4 reference solver "
                          "on the 4096x4096 workload, FP32 and FP64 (0 skips it)")
+    ap.add_argument("--no-one-step", action="store_true",
+                    help="skip the one-step-per-pass runs of the pass kernel")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
                     help="steps of the uneven 512-instance ensemble (0 skips it)")
     return ap.parse_args()
@@ -102,34 +104,55 @@ def recorded_traffic():
     return float(m_bytes.group(1))
 
 
-def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK):
+def recorded_valu_issue():
+    """VALU issue utilisation of the headline kernel from the committed
+    counter summary, if it was taken on the current kernel source."""
+    path = ROOT / "profiles" / "sslbm_march_4096_valu.md"
+    if not path.exists():
+        return None
+    text = path.read_text()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]{16})", text)
+    m_val = re.search(r"headline_valu_issue:\s*([0-9.]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_val.group(1))
+
+
+def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK, depth=0):
+    """One scheme / type / R0 on the 4096 x 4096 workload: `warmup` untimed
+    steps, then one untimed run of exactly the timed pass plan (so that every
+    kernel the timed region launches has run before), then `steps` steps
+    timed with HIP events on the launch stream. depth > 0 fixes the SSLBM's
+    steps per pass (0: automatic)."""
     params = inputs.c2_params(r0)
     rho0 = inputs.c2_state(NX, NY)
     tdt = torch.float32 if dtype == "f32" else torch.float64
     stream = torch.cuda.current_stream()
     if scheme == "sslbm":
         solver = Solver(NX, NY, params, dtype=dtype)
+        if depth:
+            solver.set_launch(depth, 0, 0)
         rho = torch.tensor(rho0, dtype=tdt, device="cuda")
         scratch = torch.empty_like(rho)
-        solver.run(rho, warmup, scratch)
         shape = solver.launch()
-        blocking = shape["steps_per_pass"]
+        plan = solver.plan(steps)
 
         def timed():
             solver.run(rho, steps, scratch)
-        launches = -(-steps // blocking)
-        if launches % 2 == 1 and steps >= 2:
-            launches += 1
+        solver.run(rho, warmup, scratch)
+        timed()
+        launches = plan["passes"]
     else:
         solver = BGK(NX, NY, params, dtype=dtype)
         f, rd = solver.init(torch.tensor(rho0, dtype=tdt, device="cuda"))
         fs, ds = torch.empty_like(f), torch.empty_like(rd)
-        solver.run(f, rd, warmup, fs, ds)
-        blocking = 1
         shape = {"steps_per_pass": 1}
+        plan = {"passes": steps, "longest": 1, "shortest": 1}
 
         def timed():
             solver.run(f, rd, steps, fs, ds)
+        solver.run(f, rd, warmup, fs, ds)
+        timed()
         launches = steps
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -145,7 +168,8 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK):
     bytes_per_launch = per_step * cells
     out = {
         "scheme": scheme, "dtype": dtype, "R0": r0, "steps": steps, "ms": ms,
-        "ms_per_step": ms / steps, "glups": glups, "steps_per_pass": blocking, "launch": shape,
+        "ms_per_step": ms / steps, "glups": glups,
+        "steps_per_pass": shape["steps_per_pass"], "launch": shape, "plan": plan,
         "launches": launches, "avg_launch_ms": ms / launches,
         "algorithmic_bytes_per_launch": bytes_per_launch,
         "achieved_gbps": bytes_per_launch / (ms / launches * 1e-3) / 1e9,
@@ -406,27 +430,49 @@ def copy_probe(torch, reps: int = 1):
     return best
 
 
-def cpu_baseline(inputs, target_seconds: float):
-    """The FP64 CPU oracle on the headline workload: whole steps of the
-    4096 x 4096 grid, in groups of 4, until about target_seconds have passed
-    (one untimed step first, so thread start-up is not counted)."""
-    import oracle
-    orc = oracle.load()
-    threads = oracle.host_threads()
+def cpu_model() -> str:
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(orc, inputs, threads, target_seconds, group):
+    """Oracle GLUPS on the headline workload: whole 4096 x 4096 steps in
+    groups of `group` until about target_seconds have passed (one untimed
+    step first, so thread start-up is not counted)."""
     params = inputs.c2_params(HEADLINE[2])
     rho = orc.sslbm_run(inputs.c2_state(NX, NY), params, 1, threads=threads)
     n = 0
     t = time.perf_counter()
     while True:
-        rho = orc.sslbm_run(rho, params, 4, threads=threads)
-        n += 4
+        rho = orc.sslbm_run(rho, params, group, threads=threads)
+        n += group
         el = time.perf_counter() - t
         if el >= target_seconds:
             break
+    return NX * NY * n / el / 1e9, n, el
+
+
+def cpu_baseline(inputs, target_seconds: float):
+    """The FP64 CPU oracle on the headline workload, on every host thread
+    and on one, each for about target_seconds (the one-core run takes at
+    least two steps)."""
+    import oracle
+    orc = oracle.load()
+    threads = oracle.host_threads()
+    rate, n, el = _oracle_rate(orc, inputs, threads, target_seconds, 4)
+    rate1, n1, el1 = _oracle_rate(orc, inputs, 1, target_seconds / 2, 1)
     return {
-        "value": NX * NY * n / el / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+        "value": rate, "unit": "GLUPS", "cores": threads, "kind": "oracle",
         "sample": f"{NX}x{NY} headline workload (R0=3, periodic), {n} FP64 steps, "
                   f"{el:.1f} s on {threads} host threads",
+        "cpu_model": cpu_model(),
+        "one_core": {"value": round(rate1, 5), "unit": "GLUPS", "cores": 1,
+                     "sample": f"{n1} FP64 steps of the same grid, {el1:.1f} s on one thread"},
     }
 
 
@@ -463,11 +509,19 @@ def main():
     results = []
     for s, d, r in variants:
         # BGK is 4x the traffic per step: keep its timed work comparable
-        steps = args.steps if s == "sslbm" else max(1, args.steps // 4)
-        warm = args.warmup if s == "sslbm" else max(1, args.warmup // 4)
-        res = run_variant(torch, s, d, r, steps, warm, inputs, Solver, BGK)
+        steps = args.steps if s == "sslbm" else max(2, args.steps // 4)
+        res = run_variant(torch, s, d, r, steps, args.warmup, inputs, Solver, BGK)
         results.append(res)
-        print(f"# {s} {d} R0={r:g}: {res['glups']:.1f} GLUPS, {res['steps_per_pass']} steps/pass, "
+        print(f"# {s} {d} R0={r:g}: {res['glups']:.1f} GLUPS, {res['steps_per_pass']} steps/pass "
+              f"({res['launches']} passes), {res['achieved_gbps']:.0f} GB/s per launch",
+              file=sys.stderr, flush=True)
+    # the pass kernel at one step per pass (the HBM-streaming case), both types
+    single = {}
+    for d in (() if args.no_one_step else ("f32", "f64")):
+        res = run_variant(torch, "sslbm", d, HEADLINE[2], args.steps, args.warmup, inputs,
+                          Solver, BGK, depth=1)
+        single[d] = res
+        print(f"# sslbm {d} one step per pass: {res['glups']:.1f} GLUPS, "
               f"{res['achieved_gbps']:.0f} GB/s per launch", file=sys.stderr, flush=True)
     ensemble = None
     if args.ensemble_steps > 0:
@@ -522,29 +576,36 @@ def main():
     head = results[0]
     traffic = recorded_traffic()
     k = head["steps_per_pass"]
-    # Several steps per pass move the pass kernel off the HBM roof and onto the
-    # vector-ALU roof (its measured VALU issue rate, not its bytes, is what
-    # saturates); one step per pass is HBM-bound.
-    hbm = {"achieved": round(head["achieved_gbps"], 1), "peak": PEAK_HBM_GBPS,
-           "frac": round(head["achieved_gbps"] / PEAK_HBM_GBPS, 4), "unit": "GB/s"}
-    if k > 1:
-        roof = {"bound": "alu", "unit": "TFLOP/s", "peak": PEAK_VALU_TFLOPS,
-                "achieved": round(head["tflops"], 2),
-                "frac": round(head["tflops"] / PEAK_VALU_TFLOPS, 4)}
-    else:
-        roof = {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBPS,
-                "achieved": hbm["achieved"], "frac": hbm["frac"]}
-    roof.update({
+    v = head["launch"].get("cols_per_lane", 1)
+    # The pass kernel's roof is HBM: algorithmic bytes of one
+    # launch (every field read and written once, whatever its depth) over the
+    # launch's own duration, measured on the launch stream over the timed
+    # passes. Its vector-ALU rate is reported beside it: with several steps per
+    # pass the arithmetic, not the bytes, is what the launch waits on.
+    roof = {
+        "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBPS,
+        "achieved": round(head["achieved_gbps"], 1),
+        "frac": round(head["achieved_gbps"] / PEAK_HBM_GBPS, 4),
         "traffic": traffic,
-        "kernel": f"sslbm_march_kernel<float, {k}, false, {head['launch'].get('cols_per_lane', 1)}>",
-        "steps_per_pass": k,
-        "flops_per_update": FLOPS_PER_UPDATE,
+        "kernel": f"sslbm_march_kernel<float, {k}, false, {v}>",
+        "steps_per_pass": k, "launches": head["launches"], "plan": head["plan"],
         "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
         "avg_launch_ms": round(head["avg_launch_ms"], 5),
-        "hbm": hbm,
+        "valu": {"achieved": round(head["tflops"], 2), "peak": PEAK_VALU_TFLOPS,
+                 "unit": "TFLOP/s", "frac": round(head["tflops"] / PEAK_VALU_TFLOPS, 4),
+                 "flops_per_update": FLOPS_PER_UPDATE,
+                 "issue_frac_profiled": recorded_valu_issue()},
         "effective_hbm_frac": round(head["effective_gbps"] / PEAK_HBM_GBPS, 4),
         "hbm_copy_gbps": round(copy_gbps, 1),
-    })
+        "one_step_per_pass": {
+            d: {"kernel": f"sslbm_march_kernel<{'float' if d == 'f32' else 'double'}, 1, "
+                          f"false, {r['launch'].get('cols_per_lane', 1)}>",
+                "glups": round(r["glups"], 2), "avg_launch_ms": round(r["avg_launch_ms"], 5),
+                "achieved": round(r["achieved_gbps"], 1),
+                "frac": round(r["achieved_gbps"] / PEAK_HBM_GBPS, 4),
+                "frac_of_copy": round(r["achieved_gbps"] / copy_gbps, 4)}
+            for d, r in single.items()},
+    }
     line = {
         "metric": "SSLBM GLUPS & %HBM peak", "value": round(head["glups"], 2), "unit": "GLUPS",
         "n_gpus": 1, "steps": head["steps"], "warmup": args.warmup,

@@ -157,7 +157,10 @@ int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream, s
  * the centre value, so nothing crosses the wall; Sec. II.C.2, mass
  * conservation).
  * rho_in, rho_out: device, layout rho, must not overlap (SSLBM_E_ALIAS).
- * The force of infection is zero where S + E + I + R <= 0.
+ * The force of infection is zero where S + E + I + R <= 0, and also where
+ * that sum is a positive subnormal number of the arithmetic type (below
+ * 2^-126 in FP32, 2^-1022 in FP64): the quotient dropped there is below
+ * beta dt times that bound for non-negative densities.
  */
 int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream);
 
@@ -168,6 +171,18 @@ int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream
  * sslbm_step. nsteps = 0 leaves rho unchanged. rho and scratch must not overlap.
  */
 int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream);
+
+/*
+ * How sslbm_run splits nsteps into passes with the context's current pass
+ * shape: the fewest passes of at most steps_per_pass steps, one more if that
+ * makes their count even and leaves every pass a step (the ping-pong then
+ * ends in rho, with no copy), and the steps spread evenly over them: the
+ * first passes take *longest steps, the rest *shortest (equal when the split
+ * is exact). Host only, no device call. *passes = 0 for nsteps = 0.
+ * longest and shortest may be NULL.
+ */
+int sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int *longest,
+                   int *shortest);
 
 /*
  * BGK comparison scheme, Eq. (pdf) with f^eq = w_i rho, the source w_i Psi dt

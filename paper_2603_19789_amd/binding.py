@@ -89,6 +89,7 @@ def library() -> ctypes.CDLL:
             "sslbm_tune": [vp, vp, vp, vp, ctypes.POINTER(Launch)],
             "sslbm_step": [vp, vp, vp, vp],
             "sslbm_run": [vp, vp, vp, ll, vp],
+            "sslbm_plan_run": [vp, ll, ctypes.POINTER(ll), ctypes.POINTER(i), ctypes.POINTER(i)],
             "bgk_init": [vp, vp, vp, vp, vp],
             "bgk_step": [vp, vp, vp, vp, vp, vp],
             "bgk_run": [vp, vp, vp, vp, vp, ll, vp],
@@ -298,6 +299,15 @@ class Solver(_Context):
         self._check(self.lib.sslbm_run(self.handle, a, b, int(nsteps), _stream(stream)),
                     "sslbm_run")
         return rho
+
+    def plan(self, nsteps: int) -> dict:
+        """How `run` splits nsteps into passes with the current pass shape:
+        {"passes", "longest", "shortest"} (host only)."""
+        n, hi, lo = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.sslbm_plan_run(self.handle, int(nsteps), ctypes.byref(n),
+                                            ctypes.byref(hi), ctypes.byref(lo)),
+                    "sslbm_plan_run")
+        return {"passes": n.value, "longest": hi.value, "shortest": lo.value}
 
     def total(self, rho, stream=None):
         """Per-compartment totals (5 floats, FP64 sums); waits for the stream."""

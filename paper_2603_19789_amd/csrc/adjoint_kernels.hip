@@ -83,6 +83,20 @@ __device__ __forceinline__ void fetch_rho(AdjState<T> &st, const AdjArgs<T> &a, 
 // The reverse update of one node: o = A(rho)^T lam at the node, from the
 // adjoint field at the node (lc), its five-point Laplacian (lap) and the
 // state at the node (rho).
+// Populations below `below` are scaled by `scale` (and S I / Nc back by
+// `unscale`) in the reverse step: every positive subnormal Nc then becomes
+// a normal number.
+template <typename T>
+struct TinyPopulation;
+template <>
+struct TinyPopulation<float> {
+    static constexpr float below = 0x1p-100f, scale = 0x1p64f, unscale = 0x1p-64f;
+};
+template <>
+struct TinyPopulation<double> {
+    static constexpr double below = 0x1p-960, scale = 0x1p512, unscale = 0x1p-512;
+};
+
 template <typename T, bool DIFFUSE_D>
 __device__ __forceinline__ void adjoint_node(const T lc[5], const T lap[5], const T rho[5],
                                              const Coef<T> &k, T o[5], T &g, T &de, T &sir) {
@@ -93,12 +107,20 @@ __device__ __forceinline__ void adjoint_node(const T lc[5], const T lap[5], cons
 
     const T S = rho[0], E = rho[1], I = rho[2], R = rho[3];
     const T nc = (S + E) + (I + R);
-    const bool live = nc > T(0);
-    const T r = live ? quotient(T(1), nc) : T(0);  // 1 / Nc, or 0 where F = 0
-    sir = (S * I) * r;                             // S I / Nc = F / beta
-    const T qi = k.bdt * (I * r);                  // dt dF/dS + dt F/Nc
-    const T qs = k.bdt * (S * r);                  // dt dF/dI + dt F/Nc
-    const T w = k.bdt * (sir * r);                 // dt F / Nc
+    // F = beta S I / Nc is homogeneous of degree one in (S, E, I, R), so its
+    // derivatives keep their size as the population shrinks to zero. A tiny
+    // population is first scaled up by an exact power of two (which leaves
+    // every ratio below unchanged) so that 1 / Nc stays a normal number; at
+    // ordinary sizes the scale is 1 and changes no bit.
+    const bool tiny = nc < TinyPopulation<T>::below;
+    const T up = tiny ? TinyPopulation<T>::scale : T(1);
+    const T Su = S * up, Iu = I * up;
+    const T r = recip_or_zero(nc * up);            // 1 / (up Nc), or 0 where F = 0
+    const T siru = (Su * Iu) * r;                  // up S I / Nc
+    sir = siru * (tiny ? TinyPopulation<T>::unscale : T(1));  // S I / Nc = F / beta
+    const T qi = k.bdt * (Iu * r);                 // dt dF/dS + dt F/Nc
+    const T qs = k.bdt * (Su * r);                 // dt dF/dI + dt F/Nc
+    const T w = k.bdt * (siru * r);                // dt F / Nc
     g = lc[1] - lc[0];                             // F moves S -> E
     de = lc[2] - lc[1];                            // alpha E moves E -> I
     o[0] = fma(g, qi - w, o[0]);

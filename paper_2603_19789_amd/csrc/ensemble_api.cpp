@@ -185,7 +185,9 @@ int tile_table(sslbm_ensemble *e, int k, int H, int V, TileTable **out) {
 int enqueue_run(sslbm_ensemble *e, const sslbm_launch &r, void *rho, void *scratch,
                 long long nsteps, hipStream_t s) {
     void *src = rho, *dst = scratch;
-    for (int k : sslbm::plan_passes(nsteps, r.steps_per_pass)) {
+    const sslbm::PassPlan plan = sslbm::plan_passes(nsteps, r.steps_per_pass);
+    for (long long i = 0; i < plan.count; ++i) {
+        const int k = plan.steps(i);
         const int V = usable_cols(e, r.cols_per_lane, k);
         TileTable *tab = nullptr;
         int st = tile_table(e, k, r.rows_per_wave, V, &tab);
@@ -205,7 +207,12 @@ int enqueue_run(sslbm_ensemble *e, const sslbm_launch &r, void *rho, void *scrat
 
 // Build every tile table a run of nsteps will use (before any capture).
 int prepare_run(sslbm_ensemble *e, const sslbm_launch &r, long long nsteps) {
-    for (int k : sslbm::plan_passes(nsteps, r.steps_per_pass)) {
+    const sslbm::PassPlan plan = sslbm::plan_passes(nsteps, r.steps_per_pass);
+    // a run uses at most two depths: the longer and the shorter passes
+    for (long long i : {0ll, plan.count - 1}) {
+        if (i < 0)
+            continue;
+        const int k = plan.steps(i);
         TileTable *tab = nullptr;
         const int st = tile_table(e, k, r.rows_per_wave, usable_cols(e, r.cols_per_lane, k), &tab);
         if (st != SSLBM_OK)

@@ -121,8 +121,9 @@ __device__ __forceinline__ void model_level(ModelRows<T, K> &st, const ModelArgs
 #pragma unroll
     for (int c = 0; c < M; ++c)
         lds.vals[c * 64] = cen[c];
-    // 1 / N once per node (0 where N <= 0: no frequency-dependent flow)
-    const T inv_total = total > T(0) ? quotient(T(1), total) : T(0);
+    // 1 / N once per node (0 where N is not a positive normal number: no
+    // frequency-dependent flow)
+    const T inv_total = recip_or_zero(total);
     // MODEL_GROUP transitions at a time: their lookups are issued together,
     // so a group costs one LDS latency; increments go straight into the
     // output registers through the stoichiometry rows (rate dt (delta_dst -

@@ -16,13 +16,38 @@ struct Coef {
 };
 
 // ---------------------------------------------------------------------------
-// a / b. FP64 divides with IEEE rounding; FP32 multiplies by the hardware
-// reciprocal (v_rcp_f32, within 1 ulp), which is far inside the FP32
-// tolerance and a fifth of the cost of the rounded division.
-__device__ __forceinline__ float quotient(float a, float b) {
-    return a * __builtin_amdgcn_rcpf(b);
+// 1 / n where n is a positive normal number, else 0.
+//
+// FP32: the hardware reciprocal v_rcp_f32 (within 1 ulp for normal inputs,
+// a fifth of the cost of the rounded division). It is not valid for
+// subnormal inputs (it returns inf there), so positive subnormal n takes
+// the zero branch with n <= 0. The largest quotient this drops is
+// a / n with a = dt beta S I and S, I <= n < 2^-126: below 2^-126 dt beta.
+__device__ __forceinline__ float recip_or_zero(float n) {
+    return n >= 0x1p-126f ? __builtin_amdgcn_rcpf(n) : 0.0f;
 }
-__device__ __forceinline__ double quotient(double a, double b) { return a / b; }
+// FP64: v_rcp_f64 refined by two Newton steps r <- r + r (1 - n r); the
+// select comes last, so the infinite reciprocal of n = 0 never reaches a
+// product that is kept.
+__device__ __forceinline__ double recip_or_zero(double n) {
+    double r = __builtin_amdgcn_rcp(n);
+    r = fma(fma(-n, r, 1.0), r, r);
+    r = fma(fma(-n, r, 1.0), r, r);
+    return n >= 0x1p-1022 ? r : 0.0;
+}
+
+// a / n where n is a positive normal number, else 0 (the force of infection
+// is zero on cells with no contact-eligible population). FP32: a times the
+// reciprocal. FP64: the product corrected once by its residual,
+// q + (a - n q) / n, which is within one ulp of the rounded quotient.
+__device__ __forceinline__ float quotient_or_zero(float a, float n) {
+    return a * recip_or_zero(n);
+}
+__device__ __forceinline__ double quotient_or_zero(double a, double n) {
+    const double r = recip_or_zero(n);
+    const double q = a * r;
+    return fma(fma(-n, q, a), r, q);
+}
 
 // SEIRD source increments Psi^C dt of one node, Eq. (sources) and Eq. (rhoD),
 // from the node's densities at time t. The force of infection is zero where
@@ -31,8 +56,7 @@ template <typename T>
 __device__ __forceinline__ void seird_increments(T S, T E, T I, T R, const Coef<T> &k, T &fdt,
                                                  T &rE, T &rI) {
     const T nc = (S + E) + (I + R);
-    const T q = quotient((k.bdt * S) * I, nc);
-    fdt = nc > T(0) ? q : T(0);
+    fdt = quotient_or_zero((k.bdt * S) * I, nc);
     rE = k.kE * E;
     rI = k.kI * I;
 }

@@ -165,26 +165,18 @@ int derive_coef(const sslbm_params *p, StepCoef *k) {
     return SSLBM_OK;
 }
 
-// Split nsteps into passes of at most K steps, with an even number of passes
-// whenever nsteps >= 2 so that the ping-pong ends in the caller's buffer.
-std::vector<int> plan_passes(long long nsteps, int K) {
-    std::vector<int> passes;
-    for (long long left = nsteps; left > 0;) {
-        const int k = left >= K ? K : (int)left;
-        passes.push_back(k);
-        left -= k;
-    }
-    if (passes.size() % 2 == 1 && nsteps >= 2) {
-        for (size_t i = 0; i < passes.size(); ++i) {
-            if (passes[i] >= 2) {
-                const int a = passes[i] / 2, b = passes[i] - a;
-                passes[i] = a;
-                passes.insert(passes.begin() + (long)i + 1, b);
-                break;
-            }
-        }
-    }
-    return passes;
+PassPlan plan_passes(long long nsteps, int K) {
+    PassPlan p;
+    if (nsteps <= 0 || K < 1)
+        return p;
+    p.count = (nsteps + K - 1) / K;
+    // one more pass only while every pass keeps at least one step (K = 1 and
+    // an odd nsteps stay odd: the run then ends with a copy)
+    if (p.count % 2 == 1 && p.count < nsteps)
+        ++p.count;
+    p.base = (int)(nsteps / p.count);
+    p.longer = nsteps - (long long)p.base * p.count;
+    return p;
 }
 
 }  // namespace sslbm
@@ -323,6 +315,19 @@ int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream,
     return SSLBM_OK;
 }
 
+int sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int *longest,
+                   int *shortest) {
+    if (!c || nsteps < 0 || !passes)
+        return SSLBM_E_ARG;
+    const sslbm::PassPlan p = sslbm::plan_passes(nsteps, resolve(c).steps_per_pass);
+    *passes = p.count;
+    if (longest)
+        *longest = p.count == 0 ? 0 : p.steps(0);
+    if (shortest)
+        *shortest = p.count == 0 ? 0 : p.steps(p.count - 1);
+    return SSLBM_OK;
+}
+
 int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass) {
     if (!c)
         return SSLBM_E_ARG;
@@ -360,7 +365,9 @@ int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hi
     const hipStream_t s = (hipStream_t)hip_stream;
     const sslbm::GridDesc g = grid_of(c);
     void *src = rho, *dst = scratch;
-    for (int k : sslbm::plan_passes(nsteps, K)) {
+    const sslbm::PassPlan plan = sslbm::plan_passes(nsteps, K);
+    for (long long i = 0; i < plan.count; ++i) {
+        const int k = plan.steps(i);
         const int st =
             hip_status(c, sslbm::launch_march(c->dtype, src, dst, g, c->coef, k,
                                               shape_for(c, k, src, dst), s));

@@ -39,9 +39,19 @@ struct MarchShape {
 // ---- host helpers (sslbm_api.cpp) ---------------------------------------
 // Validate parameters and derive the per-step constants (SSLBM status code).
 int derive_coef(const sslbm_params *p, StepCoef *k);
-// Split nsteps into passes of at most K steps, an even number of passes
-// whenever nsteps >= 2 (so that ping-pong buffers end where they started).
-std::vector<int> plan_passes(long long nsteps, int K);
+// How a run of nsteps splits into passes of at most K steps: the fewest
+// passes, made even where that leaves every pass a step (so that ping-pong
+// buffers end where they started), with the steps spread as evenly as possible over them (the
+// first `longer` passes take one step more than the rest). A pass costs
+// about the same HBM traffic whatever its depth, so a short tail pass would
+// waste most of one.
+struct PassPlan {
+    long long count = 0;   // passes
+    int base = 0;          // steps of the shorter passes
+    long long longer = 0;  // passes with base + 1 steps (the first ones)
+    int steps(long long i) const { return i < longer ? base + 1 : base; }
+};
+PassPlan plan_passes(long long nsteps, int K);
 
 // One pass of k steps (1 <= k <= the register limit), in -> out, with the
 // context's pass shape (SSLBM status code).

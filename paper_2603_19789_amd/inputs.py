@@ -103,6 +103,27 @@ def random_state(nx: int, ny: int, seed: int, infected_scale: float = 0.2) -> np
     return rho
 
 
+def empty_block_state(nx: int, ny: int, seed: int, rows: slice, cols: slice,
+                      compartments: int = 5) -> np.ndarray:
+    """``random_state`` (or, for more than five compartments, uniform random
+    densities) with S = E = I = R = 0 on a block of cells (D > 0 there: the
+    deceased are not contact-eligible) and one cell that is entirely empty:
+    cells whose contact-eligible population is zero, next to populated ones,
+    so that diffusion carries ever smaller (eventually subnormal) densities
+    into the block."""
+    if compartments == 5:
+        rho = random_state(nx, ny, seed)
+    else:
+        rng = np.random.default_rng(seed)
+        rho = rng.uniform(0.0, 0.3, size=(compartments, ny, nx))
+        rho[0] += 0.5
+    counted = [c for c in range(compartments) if c != 4]
+    for c in counted:
+        rho[c, rows, cols] = 0.0
+    rho[:, min(3, ny - 1), min(5, nx - 1)] = 0.0
+    return rho
+
+
 # ---------------------------------------------------------------- configs --
 
 @dataclass(frozen=True)

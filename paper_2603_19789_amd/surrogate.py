@@ -67,6 +67,13 @@ class _View:
         return _ptr(self.buf, self.offset)
 
 
+def _copy(v):
+    """A copy of the channels a view (or a whole tensor) covers."""
+    if isinstance(v, _View):
+        return v.buf[..., v.offset:v.offset + v.c].clone()
+    return v.clone()
+
+
 @dataclass
 class _Conv:
     cin: int
@@ -120,6 +127,11 @@ class UNet:
                "sur_to_bf16")
         self._shape = None
         self._sets = {}  # activation and gradient buffers per (batch, h, w)
+        # When a list, every convolution of the forward and backward passes
+        # appends copies of the exact tensors it read and wrote (dicts, see
+        # _conv and _conv_backward), so that each layer can be checked on its
+        # own inputs. It costs a device copy per tensor; None in normal use.
+        self.record = None
 
     @property
     def parameters(self) -> int:
@@ -217,6 +229,9 @@ class UNet:
         else:
             _check(self.lib.sur_conv3x3_forward_pool(*args, _ptr(pooled), pooled.shape[-1], None),
                    "sur_conv3x3_forward_pool")
+        if self.record is not None:
+            self.record.append({"pass": "forward", "k": k, "x": _copy(src), "y": _copy(dst),
+                                "pooled": None if pooled is None else pooled.clone()})
 
     def _conv_up(self, k, low: _View, skip: _View, dst: _View, l):
         """Convolution k of decoder level l on [up2(low), skip] without the
@@ -272,6 +287,10 @@ class UNet:
         lib = self.lib
         n = self._shape[0]
         hh, ww = self.dims[l]
+        rec = None
+        if self.record is not None:
+            rec = {"pass": "backward", "k": k, "x": _copy(x), "gy": _copy(gy),
+                   "y": None if y is None else _copy(y)}
         if cv.act:
             _check(lib.sur_leaky_backward(gy.ptr, gy.pitch, y.ptr, y.pitch, gy.ptr, gy.pitch,
                                           n * hh * ww, cv.cout, self.slope, None),
@@ -285,6 +304,11 @@ class UNet:
             _check(lib.sur_conv3x3_backward_data(
                 gy.ptr, gy.pitch, n, hh, ww, cv.cout, _ptr(self.theta_bf16, cv.w_off), cv.cin,
                 gx.ptr, gx.pitch, _ptr(self.flip), None), "sur_conv3x3_backward_data")
+        if rec is not None:
+            rec.update(dz=_copy(gy), dx=None if gx is None else _copy(gx),
+                       dw=self.grad[cv.w_off:cv.w_off + cv.cout * 9 * cv.cin].clone(),
+                       db=self.grad[cv.b_off:cv.b_off + cv.cout].clone())
+            self.record.append(rec)
 
     def backward_packed(self):
         """Parameter gradients (into self.grad) from self.dout (BF16 NHWC,

@@ -176,6 +176,40 @@ def check_noflux_is_reflection(orc, nx=10, ny=7, nsteps=15, seed=8):
     assert np.max(np.abs(a - b)) < 1e-15
 
 
+def check_empty_cells(orc, nx=14, ny=11, nsteps=60, seed=13):
+    """Cells with no contact-eligible population (S = E = I = R = 0; N_c of
+    Eq. (sources) leaves out D) have no force of infection (reading: F = 0
+    where N_c <= 0) and, with E = I = 0, no source at all. So
+    (1) a state of such cells with resting D stays fixed bit for bit;
+    (2) one step of a state with a block of them is, on the block, one step of
+        pure diffusion (the FFT solution of Eq. G_exact, periodic);
+    (3) a long run from it, periodic and no-flux, stays finite and conserves
+        the total (Eq. mass_conservation)."""
+    p = Params(beta=0.9, alpha=0.3, gamma=0.2, phi=0.3,
+               d=(0.9, 0.6, 0.3, 0.45, 0.0), dx=1.0, dt=0.1)
+    rng = np.random.default_rng(seed)
+    empty = np.zeros((5, ny, nx))
+    empty[4] = rng.uniform(0.1, 1.0, size=(ny, nx))
+    for bc in ("periodic", "noflux"):
+        out = orc.sslbm_run(empty, p, 5, bc=bc)
+        assert np.array_equal(out, empty), f"{bc}: an empty state moved"
+    rho0 = random_state(nx, ny, seed)
+    block = (slice(3, 8), slice(4, 10))
+    rho0[(slice(0, 4),) + block] = 0.0
+    one = orc.sslbm_step(rho0, p)
+    assert np.all(np.isfinite(one)), "non-finite values next to empty cells"
+    for c in range(5):
+        want = ref.exact_discrete_diffusion(rho0[c], _tau(p, c), 1)
+        err = np.max(np.abs(one[c][block] - want[block]))
+        assert err < 1e-15, f"compartment {c}: empty-block step {err:.3e} from pure diffusion"
+    total0 = rho0.sum()
+    for bc in ("periodic", "noflux"):
+        out = orc.sslbm_run(rho0, p, nsteps, bc=bc)
+        assert np.all(np.isfinite(out)), f"{bc}: non-finite values after {nsteps} steps"
+        drift = abs(out.sum() - total0) / total0
+        assert drift < 1e-14, f"{bc}: total drift {drift:.3e} with empty cells"
+
+
 # ------------------------------------------------------------------ BGK ----
 
 def check_bgk_exact_discrete(orc, nx=16, ny=12, nsteps=20, seed=9, tol=1e-12):
@@ -232,12 +266,32 @@ def check_bgk_tau_one_matches_sslbm(orc, nx=10, ny=8, nsteps=12, seed=12):
         assert np.max(np.abs(a - b)) < 1e-14, bc
 
 
+def check_bgk_empty_cells(orc, nx=12, ny=9, nsteps=40, seed=14):
+    """BGK with a block of cells without contact-eligible population: the
+    shared source has F = 0 there, so the run stays finite and conserves the
+    total (both walls), and a state made only of such cells stays fixed."""
+    p = Params(beta=0.9, alpha=0.3, gamma=0.2, phi=0.3,
+               d=(0.9, 0.6, 0.3, 0.45, 0.0), dx=1.0, dt=0.1)
+    rho0 = random_state(nx, ny, seed)
+    rho0[:4, 2:7, 3:9] = 0.0
+    for bc in ("periodic", "noflux"):
+        out = orc.bgk_run_density(rho0, p, nsteps, bc=bc)
+        assert np.all(np.isfinite(out)), f"BGK {bc}: non-finite values"
+        drift = abs(out.sum() - rho0.sum()) / rho0.sum()
+        assert drift < 1e-14, f"BGK {bc}: drift {drift:.3e} with empty cells"
+    empty = np.zeros((5, ny, nx))
+    empty[4] = 0.5
+    out = orc.bgk_run_density(empty, p, 5)
+    assert np.array_equal(out, empty), "BGK: an empty state moved"
+
+
 FAST_SSLBM_CHECKS = (
     check_exact_discrete_diffusion, check_manufactured_eigenmode, check_uniform_stays_uniform,
     check_zero_diffusion_is_euler, check_dfe_growth_rate, check_jacobi_superposition,
     check_conservation, check_recovered_deceased_proportional, check_noflux_is_reflection,
+    check_empty_cells,
 )
 FAST_BGK_CHECKS = (
     check_bgk_exact_discrete, check_bgk_conservation, check_bgk_uniform_is_euler,
-    check_bgk_tau_one_matches_sslbm,
+    check_bgk_tau_one_matches_sslbm, check_bgk_empty_cells,
 )

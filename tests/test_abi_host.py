@@ -369,3 +369,34 @@ def test_generic_model_blocking_host(lib):
         assert lib.sslbm_model_set_blocking(None, 1) == binding.E_ARG
     finally:
         lib.sslbm_model_destroy(h)
+
+
+def test_run_plan_splits_evenly(lib):
+    """sslbm_run's passes: the fewest of at most K steps, made even where every
+    pass keeps a step, the steps spread evenly (host only)."""
+    st, h = _init(lib, 64, 64, binding.F32)
+    assert st == binding.OK
+    n, hi, lo = ctypes.c_longlong(), ctypes.c_int(), ctypes.c_int()
+    try:
+        for K in range(1, 7):
+            assert lib.sslbm_set_blocking(h, K) == binding.OK
+            for nsteps in list(range(0, 130)) + [9999, 10000, 10001]:
+                assert lib.sslbm_plan_run(h, nsteps, ctypes.byref(n), ctypes.byref(hi),
+                                          ctypes.byref(lo)) == binding.OK
+                count, longest, shortest = n.value, hi.value, lo.value
+                if nsteps == 0:
+                    assert count == 0
+                    continue
+                fewest = -(-nsteps // K)
+                even = fewest + (fewest % 2 == 1 and fewest < nsteps)
+                assert count == even, (K, nsteps)
+                assert 1 <= shortest <= longest <= K and longest - shortest <= 1
+                longer = nsteps - shortest * count
+                assert (longer == 0) == (longest == shortest)
+                assert 0 <= longer < count or (longer == 0)
+        assert lib.sslbm_set_blocking(h, 6) == binding.OK
+        lib.sslbm_plan_run(h, 20, ctypes.byref(n), ctypes.byref(hi), ctypes.byref(lo))
+        assert (n.value, hi.value, lo.value) == (4, 5, 5)
+        assert lib.sslbm_plan_run(h, -1, ctypes.byref(n), None, None) == binding.E_ARG
+    finally:
+        lib.sslbm_destroy(h)

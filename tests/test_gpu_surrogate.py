@@ -357,24 +357,135 @@ def unet_errors(data_seed):
 
 
 def test_unet_forward_backward_against_oracle():
-    """The assembled network against the oracle's U-Net (see unet_errors),
-    on its own seeded data: close agreement with the BF16 storage model
-    (only FP32-versus-FP64 sums and the roundings they flip differ), and the
-    direction of every weight gradient against plain FP64 (the BF16 storage
-    itself moves the first layers' weight gradients by several per cent; a
-    miswired buffer would leave them uncorrelated). With random weights and
-    data the backward chain amplifies single roundings: the BF16 model itself
-    is 5-15 % from FP64 in the deep layers, and over eleven data seeds the
-    kernels' worst layer was 2-8 % from it (cosine with FP64 >= 0.991); the
-    bounds leave about twice that."""
+    """Smoke check of the assembled network against the oracle's U-Net (see
+    unet_errors): the forward output close to the BF16 storage model, and
+    every weight gradient pointing the way the FP64 one does. The layer-by-
+    layer bounds are in test_unet_layers_on_their_own_inputs: over a whole
+    backward chain single BF16 roundings are amplified (the BF16 model is
+    itself 5-15 % from FP64 in the deep layers), so no tight bound can be set
+    on the assembled gradients."""
     err16, err, layers = unet_errors(data_seed=21)
     print(f"U-Net forward rel L2: {err16:.3e} (BF16 storage model), {err:.3e} (FP64)")
     assert err16 < 5e-3 and err < 2e-2
     for k, (rw, rb, c) in enumerate(layers):
         print(f"  layer {k}: weight gradient rel L2 {rw:.3e}, bias {rb:.3e} (BF16 model); "
               f"cos with FP64 {c:.5f}")
-        assert rw < 1.5e-1 and rb < 1.5e-1, k
         assert c > 0.98, k
+
+
+def _f64(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def test_unet_layers_on_their_own_inputs():
+    """Every operation of one forward and one backward pass of the assembled
+    network, checked against the oracle on the exact BF16 tensors it read
+    (recorded by UNet.record), to the per-kernel bounds of the tests above:
+      * each convolution's output (2^-8 of the value for BF16 outputs, 1e-6
+        for the FP32 last layer, plus 1e-5 of the sum of |terms|), and the
+        2 x 2 means fused into it;
+      * each backward step: dZ from the activation's adjoint, the weight and
+        bias gradients (1e-6 + 1e-5 of the term sum) and dX (2^-8 + 1e-5);
+      * the wiring between them, walking the oracle's layer list: each
+        convolution reads what the previous operations (pooling, upsampling,
+        concatenation) make of the recorded outputs, and each backward step
+        receives what the adjoints of those operations make of the recorded
+        dX of the step after it (sums rounded to BF16: 2^-8 of the value plus
+        1e-6 of the sum of |terms|).
+    Nothing accumulates from layer to layer: every check starts from the
+    tensors the kernels actually used."""
+    rng = np.random.default_rng(21)
+    net = _small_net()
+    n, h, w = 2, 64, 64
+    net._buffers(n, h, w)
+    net.x0.copy_(torch.tensor(rng.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF))
+    net.record = []
+    net.forward_packed()
+    net.dout.copy_(torch.tensor(rng.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF))
+    net.backward_packed()
+    torch.cuda.synchronize()
+    rec, net.record = net.record, None
+    fwd = {r["k"]: r for r in rec if r["pass"] == "forward"}
+    bwd = {r["k"]: r for r in rec if r["pass"] == "backward"}
+    weights = net.weights_numpy()
+    nconv = len(weights)
+    assert sorted(fwd) == sorted(bwd) == list(range(nconv))
+    slope = net.slope
+    spec = O.unet_spec(levels=3, base=16, cin=16, cout=16)
+
+    for k in range(nconv):
+        W, b = weights[k]
+        act = net.convs[k].act
+        r = fwd[k]
+        x = _f64(r["x"])
+        z = O.conv3x3(x, W, b)
+        want = O.leaky(z, slope) if act else z
+        scale = O.conv3x3(np.abs(x), np.abs(W), np.abs(b))
+        check_close(_f64(r["y"]), want, scale, 2 ** -8 if k < nconv - 1 else 1e-6,
+                    f"forward conv {k}")
+        if r["pooled"] is not None:
+            y = _f64(r["y"])
+            check_close(_f64(r["pooled"]), O.pool2(y), O.pool2(np.abs(y)) * 1e-1, 2 ** -8,
+                        f"pooling fused into conv {k}")
+        rb = bwd[k]
+        gy, dz, xb = _f64(rb["gy"]), _f64(rb["dz"]), _f64(rb["x"])
+        assert np.array_equal(xb, x), f"conv {k}: backward read another input than forward"
+        if act:
+            check_close(dz, O.leaky_bwd(gy, _f64(rb["y"]), slope), np.abs(gy) * 1e-1, 2 ** -8,
+                        f"activation adjoint of conv {k}")
+        else:
+            assert np.array_equal(dz, gy)
+        want_w, want_b = O.conv3x3_bwd_weight(x, dz)
+        scale_w, scale_b = O.conv3x3_bwd_weight(np.abs(x), np.abs(dz))
+        cv = net.convs[k]
+        check_close(rb["dw"].cpu().numpy().reshape(cv.cout, 9, cv.cin), want_w, scale_w, 1e-6,
+                    f"weight gradient of conv {k}")
+        check_close(rb["db"].cpu().numpy(), want_b, scale_b, 1e-6, f"bias gradient of conv {k}")
+        if rb["dx"] is not None:
+            check_close(_f64(rb["dx"]), O.conv3x3_bwd_data(dz, W),
+                        O.conv3x3_bwd_data(np.abs(dz), np.abs(W)), 2 ** -8,
+                        f"backward data of conv {k}")
+        else:
+            assert k == 0
+
+    # forward wiring
+    hcur, saved, k = _f64(net.x0), {}, 0
+    for op in spec:
+        if op[0] == "conv":
+            check_close(_f64(fwd[k]["x"]), hcur, np.abs(hcur) * 1e-4, 2 ** -8,
+                        f"input of conv {k}")
+            hcur = _f64(fwd[k]["y"])
+            k += 1
+        elif op[0] == "pool":
+            hcur = O.bf16_round(O.pool2(hcur))
+        elif op[0] == "up":
+            hcur = O.up2(hcur)
+        elif op[0] == "save":
+            saved[op[1]] = hcur
+        elif op[0] == "cat":
+            hcur = np.concatenate([hcur, saved[op[1]]], axis=3)
+    # backward wiring
+    g, gs, skip, k = _f64(net.dout), None, {}, nconv
+    for op in reversed(spec):
+        if op[0] == "conv":
+            k -= 1
+            check_close(_f64(bwd[k]["gy"]), g, 1e-6 * (gs if gs is not None else np.abs(g)),
+                        2 ** -8, f"output gradient of conv {k}")
+            g = _f64(bwd[k]["dx"]) if bwd[k]["dx"] is not None else None
+            gs = None
+        elif op[0] == "pool":
+            g = O.pool2_bwd(g)
+        elif op[0] == "up":
+            gs = O.up2_bwd(np.abs(g))
+            g = O.up2_bwd(g)
+        elif op[0] == "cat":
+            c_up = g.shape[3] - saved[op[1]].shape[3]
+            skip[op[1]] = g[..., c_up:]
+            g = g[..., :c_up]
+        elif op[0] == "save" and op[1] in skip:
+            gs = np.abs(g) + np.abs(skip[op[1]])
+            g = g + skip.pop(op[1])
+    assert k == 0 and not skip
 
 
 def test_training_learns_and_beats_persistence():

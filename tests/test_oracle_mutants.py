@@ -25,6 +25,8 @@ MUTANTS = {
     "recovery uses phi": ("psi[CR] = (1.0 - k.phi) * k.gamma * I;",
                           "psi[CR] = k.phi * k.gamma * I;"),
     "deaths from E": ("psi[CD] = k.phi * k.gamma * I;", "psi[CD] = k.phi * k.gamma * E;"),
+    "no guard on N_c": ("    if (Nc > 0.0)\n        force", "    if (1)\n        force"),
+    "guard admits N_c = 0": ("    if (Nc > 0.0)\n        force", "    if (Nc >= 0.0)\n        force"),
     "force not divided by N_c": ("force = k.beta * S * I / Nc;", "force = k.beta * S * I;"),
     "force uses E": ("force = k.beta * S * I / Nc;", "force = k.beta * S * E / Nc;"),
     "no-flux ghost zero": ("return field[(size_t)yc * nx + xc];", "return 0.0;"),
