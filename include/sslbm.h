@@ -47,7 +47,8 @@ typedef enum {
     SSLBM_E_UNSUPPORTED = -3, /* valid request this build does not serve (e.g. BGK with d[4] != 0) */
     SSLBM_E_ALIAS = -4,       /* input and output buffers overlap */
     SSLBM_E_HIP = -5,         /* a HIP call or kernel launch failed; see sslbm_last_hip_error */
-    SSLBM_E_NOMEM = -6        /* host allocation of the context failed */
+    SSLBM_E_NOMEM = -6,       /* host allocation of the context failed */
+    SSLBM_E_LIMIT = -7        /* the request needs more than a fixed-size buffer of the library holds */
 } sslbm_status;
 
 typedef enum { SSLBM_F32 = 0, SSLBM_F64 = 1 } sslbm_dtype;     /* storage and arithmetic type */
@@ -278,6 +279,26 @@ void sslbm_destroy(sslbm_ctx *c);
 #define SSLBM_GRAD_COUNT 9
 int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
                        double *grad, void *hip_stream);
+
+/*
+ * sslbm_adjoint_step_noalloc: sslbm_adjoint_step for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same arguments, results and
+ * errors, bit for bit; it calls no hipMalloc, hipFree or other allocating
+ * routine. The step's per-wavefront partial sums go to a fixed device
+ * array of the library (SSLBM_ADJ_NOALLOC_SLOTS slots of 128 bytes,
+ * 512 KiB, held on every GPU the library runs on until the process ends)
+ * instead of a buffer of the context. Every slot the step reads is written
+ * earlier in the same call, so nothing is carried over between calls; but
+ * all calls on one GPU share that array, so calls that overlap in time on
+ * one GPU (two streams, two threads) race and give wrong gradients.
+ * Grids needing more slots than the array holds (one slot per wavefront:
+ * about ceil(nx / 62) x max(1, 1024 / ceil(nx / 62)) wavefronts, so rows of
+ * more than about 250000 cells) return SSLBM_E_LIMIT before any device call.
+ */
+#define SSLBM_ADJ_NOALLOC_SLOTS 4096
+int sslbm_adjoint_step_noalloc(sslbm_ctx *c, const void *rho, const void *lam_next,
+                               void *lam_out, double *grad, void *hip_stream);
 long long sslbm_checkpoint_count(long long nsteps, int every);
 int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, int every,
                            void *checkpoints, void *hip_stream);

@@ -20,7 +20,8 @@ from pathlib import Path
 LIBRARY = Path(__file__).resolve().parent / "libsslbm.so"
 HEADER = Path(__file__).resolve().parent.parent / "include" / "sslbm.h"
 
-OK, E_ARG, E_UNSTABLE, E_UNSUPPORTED, E_ALIAS, E_HIP, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
+OK, E_ARG, E_UNSTABLE, E_UNSUPPORTED, E_ALIAS, E_HIP, E_NOMEM, E_LIMIT = (
+    0, -1, -2, -3, -4, -5, -6, -7)
 F32, F64 = 0, 1
 GRAD_COUNT = 9  # dJ/d(beta, alpha, gamma, phi, d[0..4])
 PERIODIC, NOFLUX = 0, 1
@@ -106,6 +107,7 @@ def library() -> ctypes.CDLL:
             "sslbm_ensemble_run": [vp, vp, vp, ll, i, vp],
             "sslbm_ensemble_last_hip_error": [vp],
             "sslbm_adjoint_step": [vp, vp, vp, vp, vp, vp],
+            "sslbm_adjoint_step_noalloc": [vp, vp, vp, vp, vp, vp],
             "sslbm_run_checkpointed": [vp, vp, vp, ll, i, vp, vp],
             "sslbm_adjoint_run": [vp, vp, ll, i, vp, vp, vp, vp],
             "sslbm_model_create": [ctypes.POINTER(vp), i, i, i, i, i, i,

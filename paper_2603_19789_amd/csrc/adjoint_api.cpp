@@ -8,9 +8,10 @@
 // state is needed by one adjoint step), then runs the segment's adjoint
 // steps backwards. Work: about two forward steps and one adjoint step per
 // step of the run; memory: the checkpoints plus one segment of states.
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <utility>
 
 #include "adjoint_internal.h"
@@ -59,21 +60,94 @@ size_t partials_bytes(const sslbm::AdjShape &s) {
     return (size_t)s.slots() * sslbm::ADJ_SLOT * sizeof(double);
 }
 
-}  // namespace
-
-extern "C" {
-
-int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
-                       double *grad, void *hip_stream) {
+int step_args(const sslbm_ctx *c, const void *rho, const void *lam_next, const void *lam_out,
+              const double *grad) {
     if (!c || !rho || !lam_next || !lam_out || !grad)
         return SSLBM_E_ARG;
     const size_t bytes = state_bytes(c);
     if (overlap(lam_out, bytes, lam_next, bytes) || overlap(lam_out, bytes, rho, bytes) ||
         overlap(grad, 9 * sizeof(double), lam_out, bytes))
         return SSLBM_E_ALIAS;
-    const sslbm::AdjShape shape = sslbm::adjoint_shape(c->nx, c->ny);
+    return SSLBM_OK;
+}
+
+// The reverse step and the sum of its wavefront slots into grad.
+int step_into(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out, double *grad,
+              const sslbm::AdjShape &shape, double *partials, hipStream_t s) {
+    const int st = hip_status(c, sslbm::launch_adjoint(c->dtype, rho, lam_next, lam_out,
+                                                       grid_of(c), c->coef, shape, partials,
+                                                       true, s));
+    if (st != SSLBM_OK)
+        return st;
+    return hip_status(c, sslbm::launch_adjoint_finish(partials, (int)shape.slots(),
+                                                      factors_of(c), grad, s));
+}
+
+}  // namespace
+
+// ---- the allocation-free adjoint step -------------------------------------
+// The wavefront slots of sslbm_adjoint_step_noalloc: a file-scope device
+// array, one copy per GPU. Host code never passes `scratch` itself to a
+// kernel (on the host it only names the symbol): its device address is
+// looked up once per device with that device current, and kept.
+static __device__ __align__(256) double scratch[SSLBM_ADJ_NOALLOC_SLOTS * sslbm::ADJ_SLOT];
+
+namespace {
+
+constexpr long long NOALLOC_SLOTS = SSLBM_ADJ_NOALLOC_SLOTS;
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_lock;
+double *scratch_of_device[MAX_DEVICES] = {};
+
+int scratch_address(sslbm_ctx *c, double **out) {
     int dev = 0;
     int st = hip_status(c, hipGetDevice(&dev));
+    if (st != SSLBM_OK)
+        return st;
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return SSLBM_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> guard(scratch_lock);
+    if (!scratch_of_device[dev]) {
+        void *p = nullptr;
+        st = hip_status(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (st != SSLBM_OK)
+            return st;
+        if (!p)
+            return hip_status(c, hipErrorInvalidSymbol);
+        scratch_of_device[dev] = static_cast<double *>(p);
+    }
+    *out = scratch_of_device[dev];
+    return SSLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sslbm_adjoint_step_noalloc(sslbm_ctx *c, const void *rho, const void *lam_next,
+                               void *lam_out, double *grad, void *hip_stream) {
+    int st = step_args(c, rho, lam_next, lam_out, grad);
+    if (st != SSLBM_OK)
+        return st;
+    const sslbm::AdjShape shape = sslbm::adjoint_shape(c->nx, c->ny);
+    if (shape.slots() > NOALLOC_SLOTS)
+        return SSLBM_E_LIMIT;
+    double *partials = nullptr;
+    st = scratch_address(c, &partials);
+    if (st != SSLBM_OK)
+        return st;
+    return step_into(c, rho, lam_next, lam_out, grad, shape, partials,
+                     (hipStream_t)hip_stream);
+}
+
+int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
+                       double *grad, void *hip_stream) {
+    int st = step_args(c, rho, lam_next, lam_out, grad);
+    if (st != SSLBM_OK)
+        return st;
+    const sslbm::AdjShape shape = sslbm::adjoint_shape(c->nx, c->ny);
+    int dev = 0;
+    st = hip_status(c, hipGetDevice(&dev));
     if (st != SSLBM_OK)
         return st;
     if (!c->adj_partials || c->adj_slots < shape.slots() || c->adj_device != dev) {
@@ -86,13 +160,8 @@ int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void
         c->adj_slots = shape.slots();
         c->adj_device = dev;
     }
-    const hipStream_t s = (hipStream_t)hip_stream;
-    st = hip_status(c, sslbm::launch_adjoint(c->dtype, rho, lam_next, lam_out, grid_of(c),
-                                             c->coef, shape, c->adj_partials, true, s));
-    if (st != SSLBM_OK)
-        return st;
-    return hip_status(c, sslbm::launch_adjoint_finish(c->adj_partials, (int)shape.slots(),
-                                                      factors_of(c), grad, s));
+    return step_into(c, rho, lam_next, lam_out, grad, shape, c->adj_partials,
+                     (hipStream_t)hip_stream);
 }
 
 long long sslbm_checkpoint_count(long long nsteps, int every) {

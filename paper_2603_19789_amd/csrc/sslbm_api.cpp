@@ -544,6 +544,7 @@ const char *sslbm_strerror(int status) {
     case SSLBM_E_ALIAS: return "input and output buffers overlap";
     case SSLBM_E_HIP: return "HIP runtime error";
     case SSLBM_E_NOMEM: return "out of host memory";
+    case SSLBM_E_LIMIT: return "request exceeds a fixed-size buffer of the library";
     default: return "unknown status";
     }
 }

@@ -400,3 +400,19 @@ def test_run_plan_splits_evenly(lib):
         assert lib.sslbm_plan_run(h, -1, ctypes.byref(n), None, None) == binding.E_ARG
     finally:
         lib.sslbm_destroy(h)
+
+
+def test_noalloc_adjoint_step_limit_before_any_device_call(lib):
+    """Rows too long for the fixed slot array are refused on the host."""
+    h = ctypes.c_void_p()
+    params = Params.of(c1_params())
+    assert lib.sslbm_init(ctypes.byref(h), 300000, 1, binding.F64, binding.PERIODIC,
+                          ctypes.byref(params)) == binding.OK
+    try:
+        a, b, c, g = (ctypes.c_void_p(v << 28) for v in (1, 2, 3, 4))
+        assert lib.sslbm_adjoint_step_noalloc(h, a, b, c, g, None) == binding.E_LIMIT
+        assert b"fixed-size" in lib.sslbm_strerror(binding.E_LIMIT)
+        assert lib.sslbm_adjoint_step_noalloc(h, a, b, a, g, None) == binding.E_ALIAS
+        assert lib.sslbm_adjoint_step_noalloc(None, a, b, c, g, None) == binding.E_ARG
+    finally:
+        lib.sslbm_destroy(h)
