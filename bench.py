@@ -185,8 +185,10 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK, de
 
 def run_ensemble(torch, inputs, Ensemble, steps):
     """The uneven ensemble (512 square grids, sides from {64, 128, 256, 512},
-    sampled R0 and diffusivities, FP32): tuned pass shape, then `steps` steps
-    of every instance as one HIP graph launch, timed with HIP events."""
+    sampled R0 and diffusivities, FP32): pass shapes tuned per size class,
+    then `steps` steps of every instance as one HIP graph launch (the classes
+    as parallel branches), timed with HIP events; then every class alone for
+    the same steps, for its own rate."""
     w = inputs.ensemble_workload(nsteps=steps)
     ens = Ensemble(w.sizes, w.params, dtype="f32")
     flat = ens.empty()
@@ -194,21 +196,39 @@ def run_ensemble(torch, inputs, Ensemble, steps):
         v.copy_(torch.tensor(s, dtype=torch.float32, device="cuda"))
     scratch = ens.empty()
     t0 = time.perf_counter()
-    shape = ens.tune(flat, scratch)
+    ens.tune(flat, scratch)
     tune_s = time.perf_counter() - t0
+    start_state = flat.clone()
     ens.run(flat, steps, scratch, graph=True)  # capture and first replay
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    flat.copy_(start_state)
+    ev[0].record(stream)
     ens.run(flat, steps, scratch, graph=True)
-    stop.record(stream)
+    ev[1].record(stream)
     torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
+    ms = ev[0].elapsed_time(ev[1])
     cells = sum(nx * ny for nx, ny in w.sizes)
+    classes = []
+    for c, info in enumerate(ens.classes()):
+        flat.copy_(start_state)
+        ens.run_class(c, flat, steps, scratch)  # warm-up
+        flat.copy_(start_state)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        ens.run_class(c, flat, steps, scratch)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        cms = ev[0].elapsed_time(ev[1])
+        classes.append({"on_chip": info["on_chip"], "max_side": info["max_side"],
+                        "instances": info["instances"], "cells": info["cells"],
+                        "launch": info["launch"], "ms_alone": round(cms, 3),
+                        "glups_alone": round(info["cells"] * steps / (cms * 1e-3) / 1e9, 2)})
     return {"workload": w.name, "instances": len(w.sizes), "cells": cells, "steps": steps,
             "ms": round(ms, 3), "glups": round(cells * steps / (ms * 1e-3) / 1e9, 2),
-            "launch": shape, "tune_s": round(tune_s, 3), "graph": True, "dtype": "f32"}
+            "launch": ens.launch(), "classes": classes, "tune_s": round(tune_s, 3),
+            "graph": True, "dtype": "f32"}
 
 
 def run_adjoint(torch, inputs, Solver, steps, every=100):
@@ -526,8 +546,11 @@ def main():
     ensemble = None
     if args.ensemble_steps > 0:
         ensemble = run_ensemble(torch, inputs, Ensemble, args.ensemble_steps)
-        print(f"# ensemble: {ensemble['glups']:.1f} GLUPS over {ensemble['instances']} grids, "
-              f"shape {ensemble['launch']}", file=sys.stderr, flush=True)
+        print(f"# ensemble: {ensemble['glups']:.1f} GLUPS over {ensemble['instances']} grids; "
+              + "; ".join(f"{'on chip' if c['on_chip'] else 'up to %d' % c['max_side']}: "
+                          f"{c['instances']} grids, {c['glups_alone']:.1f} GLUPS alone, "
+                          f"shape {c['launch']}" for c in ensemble["classes"]),
+              file=sys.stderr, flush=True)
 
     adjoint_res = None
     if args.adjoint_steps > 0:

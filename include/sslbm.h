@@ -308,8 +308,8 @@ int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, i
 
 /*
  * Ensembles: many independent SSLBM grids of different sizes and parameters
- * advanced together, one launch per pass covering every instance (each
- * instance gets exactly the bits sslbm_run would give it alone).
+ * advanced together (each instance gets exactly the bits sslbm_run would
+ * give it alone).
  *
  * State layout: one device buffer holds all instances; instance i is a
  * [5][ny_i][nx_i] block at element offset sslbm_ensemble_offset(e, i)
@@ -317,36 +317,73 @@ int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, i
  * their contents after a run are unspecified).
  * sslbm_ensemble_elements(e) is the buffer length in elements.
  *
+ * Size classes. Instances whose five fields fit in 80 KiB (64 x 64 in
+ * FP32) form the on-chip class: one launch holds each of them in the LDS
+ * of one workgroup for every step of a run, reading and writing its fields
+ * once. The others are grouped by the power-of-two bucket of their longest
+ * side (up to 128, 256, 512, ...); each such march class takes passes of
+ * several steps (as sslbm_run) with a pass shape of its own. During a run the
+ * classes advance side by side, each on its own stream or graph branch.
+ *
  *   sslbm_ensemble_create: count >= 1 instances; nx, ny: host arrays of
  *       count grid sizes (1 .. 65536 each); params: host array of count
  *       parameter sets (each validated as in sslbm_init); dtype and bc as in
  *       sslbm_init, shared by all instances. Host memory only; device tables
  *       are built on first use. Errors: SSLBM_E_ARG, SSLBM_E_UNSTABLE (with
  *       the failing instance index in *bad_instance if not NULL).
- *   sslbm_ensemble_set_launch / get_launch: pass shape shared by all
- *       instances, as sslbm_set_launch (zero = automatic).
- *   sslbm_ensemble_tune: times candidate pass shapes on the current state
- *       (reads rho, writes only scratch), keeps the fastest, reports it in
- *       *best if not NULL. Waits for the stream.
+ *   sslbm_ensemble_class_count: number of size classes (>= 1).
+ *   sslbm_ensemble_instance_class: the class of an instance.
+ *   sslbm_ensemble_class_info: what a class holds and, for a march class,
+ *       its resolved pass shape (zeros for the on-chip class). Host only.
+ *   sslbm_ensemble_set_class_launch: pass shape of one march class, as
+ *       sslbm_set_launch (zero fields automatic; SSLBM_E_UNSUPPORTED for the
+ *       on-chip class). sslbm_ensemble_set_launch sets it for every march
+ *       class; sslbm_ensemble_get_launch reports the shape of the march
+ *       class with the most cells (zeros if there is none).
+ *   sslbm_ensemble_tune: times rounds of one pass of every march class side
+ *       by side on the current state (reads rho, writes only scratch) and
+ *       keeps the shapes with the highest joint rate (cell-updates per
+ *       second): first one shape for all march classes, then each class in
+ *       turn, largest first, tries its own candidates while the others keep
+ *       theirs. Candidates: every depth and column count within the register
+ *       budget, rows per wavefront automatic or 8, 16, 32, 64, 128. Reports
+ *       the largest class's shape in *best if not NULL. Waits for the stream.
  *   sslbm_ensemble_run: nsteps steps of every instance, result in rho,
- *       scratch clobbered. With SSLBM_RUN_GRAPH in flags the passes are
- *       captured once into a HIP graph (cached for the same nsteps, buffers
- *       and shape) and replayed as one launch; the graph runs on a stream of
- *       the ensemble that is ordered after, and before, hip_stream. The first
- *       call with a new shape uploads tables (synchronous).
+ *       scratch clobbered. With SSLBM_RUN_GRAPH in flags the work of all
+ *       classes is captured once into one HIP graph (one branch per class;
+ *       cached for the same nsteps and buffers until a shape changes) and
+ *       replayed as one launch; the graph runs on a stream of the ensemble
+ *       that is ordered after, and before, hip_stream. Without the flag the
+ *       classes fork from and join back to hip_stream. The first call with a
+ *       new shape uploads tables (synchronous).
+ *   sslbm_ensemble_run_class: nsteps steps of the instances of one class
+ *       only, on hip_stream (the other instances are left as they are).
  */
 #define SSLBM_RUN_GRAPH 1
 typedef struct sslbm_ensemble sslbm_ensemble;
+typedef struct {
+    int on_chip;          /* 1: the instances stay in LDS for a whole run */
+    int instances;        /* instances in the class */
+    long long cells;      /* sum of nx * ny over them */
+    int max_side;         /* their longest side */
+    sslbm_launch launch;  /* pass shape of a march class, resolved; zeros on chip */
+} sslbm_ensemble_class;
 int sslbm_ensemble_create(sslbm_ensemble **out, int count, const int *nx, const int *ny,
                           int dtype, int bc, const sslbm_params *params, int *bad_instance);
 long long sslbm_ensemble_offset(const sslbm_ensemble *e, int instance);
 long long sslbm_ensemble_elements(const sslbm_ensemble *e);
+int sslbm_ensemble_class_count(const sslbm_ensemble *e);
+int sslbm_ensemble_instance_class(const sslbm_ensemble *e, int instance);
+int sslbm_ensemble_class_info(const sslbm_ensemble *e, int cls, sslbm_ensemble_class *info);
+int sslbm_ensemble_set_class_launch(sslbm_ensemble *e, int cls, const sslbm_launch *shape);
 int sslbm_ensemble_set_launch(sslbm_ensemble *e, const sslbm_launch *shape);
 int sslbm_ensemble_get_launch(const sslbm_ensemble *e, sslbm_launch *shape);
 int sslbm_ensemble_tune(sslbm_ensemble *e, const void *rho, void *scratch, void *hip_stream,
                         sslbm_launch *best);
 int sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps, int flags,
                        void *hip_stream);
+int sslbm_ensemble_run_class(sslbm_ensemble *e, int cls, void *rho, void *scratch,
+                             long long nsteps, void *hip_stream);
 int sslbm_ensemble_last_hip_error(const sslbm_ensemble *e);
 void sslbm_ensemble_destroy(sslbm_ensemble *e);
 

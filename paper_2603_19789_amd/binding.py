@@ -65,6 +65,16 @@ class Launch(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class EnsembleClass(ctypes.Structure):
+    """One size class of an ensemble (sslbm_ensemble_class)."""
+    _fields_ = [("on_chip", ctypes.c_int), ("instances", ctypes.c_int),
+                ("cells", ctypes.c_longlong), ("max_side", ctypes.c_int), ("launch", Launch)]
+
+    def as_dict(self):
+        return {"on_chip": bool(self.on_chip), "instances": self.instances, "cells": self.cells,
+                "max_side": self.max_side, "launch": self.launch.as_dict()}
+
+
 _LIB = None
 
 
@@ -105,6 +115,11 @@ def library() -> ctypes.CDLL:
             "sslbm_ensemble_get_launch": [vp, ctypes.POINTER(Launch)],
             "sslbm_ensemble_tune": [vp, vp, vp, vp, ctypes.POINTER(Launch)],
             "sslbm_ensemble_run": [vp, vp, vp, ll, i, vp],
+            "sslbm_ensemble_run_class": [vp, i, vp, vp, ll, vp],
+            "sslbm_ensemble_class_count": [vp],
+            "sslbm_ensemble_instance_class": [vp, i],
+            "sslbm_ensemble_class_info": [vp, i, ctypes.POINTER(EnsembleClass)],
+            "sslbm_ensemble_set_class_launch": [vp, i, ctypes.POINTER(Launch)],
             "sslbm_ensemble_last_hip_error": [vp],
             "sslbm_adjoint_step": [vp, vp, vp, vp, vp, vp],
             "sslbm_adjoint_step_noalloc": [vp, vp, vp, vp, vp, vp],
@@ -484,7 +499,9 @@ RUN_GRAPH = 1
 
 class Ensemble:
     """Many independent SSLBM grids of different sizes and parameters,
-    advanced together (one launch per pass, optionally one HIP graph per run).
+    advanced together: size classes side by side (instances of at most 80 KiB
+    held in LDS for the whole run, the others in passes with a shape per
+    class), optionally captured as one HIP graph per run.
 
     The state is one flat tensor of ``elements`` values; ``views(state)``
     gives the (5, ny_i, nx_i) block of every instance."""
@@ -558,7 +575,8 @@ class Ensemble:
         return shape.as_dict()
 
     def tune(self, state, scratch=None, stream=None) -> dict:
-        """Time candidate pass shapes on `state` (unchanged), keep the fastest."""
+        """Time candidate pass shapes of every march class on `state`
+        (unchanged), keep the fastest per class; returns the largest class's."""
         if scratch is None:
             scratch = self.empty()
         best = Launch()
@@ -566,6 +584,39 @@ class Ensemble:
                                                  self._flat(scratch, "scratch"), _stream(stream),
                                                  ctypes.byref(best)), "sslbm_ensemble_tune")
         return best.as_dict()
+
+    def classes(self) -> list:
+        """Every size class: on_chip, instances, cells, max_side, launch."""
+        out = []
+        for c in range(self.lib.sslbm_ensemble_class_count(self.handle)):
+            info = EnsembleClass()
+            self._check(self.lib.sslbm_ensemble_class_info(self.handle, c, ctypes.byref(info)),
+                        "sslbm_ensemble_class_info")
+            out.append(info.as_dict())
+        return out
+
+    def instance_class(self, instance: int) -> int:
+        c = self.lib.sslbm_ensemble_instance_class(self.handle, int(instance))
+        if c < 0:
+            raise SSLBMError(c, "sslbm_ensemble_instance_class")
+        return c
+
+    def set_class_launch(self, cls, steps_per_pass=0, rows_per_wave=0, cols_per_lane=0):
+        shape = Launch(int(steps_per_pass), int(rows_per_wave), int(cols_per_lane))
+        self._check(self.lib.sslbm_ensemble_set_class_launch(self.handle, int(cls),
+                                                             ctypes.byref(shape)),
+                    "sslbm_ensemble_set_class_launch")
+
+    def run_class(self, cls, state, nsteps: int, scratch=None, stream=None):
+        """nsteps steps of the instances of class `cls` only."""
+        if scratch is None:
+            scratch = self.empty()
+        self._check(self.lib.sslbm_ensemble_run_class(self.handle, int(cls),
+                                                      self._flat(state, "state"),
+                                                      self._flat(scratch, "scratch"),
+                                                      int(nsteps), _stream(stream)),
+                    "sslbm_ensemble_run_class")
+        return state
 
     def run(self, state, nsteps: int, scratch=None, graph: bool = False, stream=None):
         if scratch is None:

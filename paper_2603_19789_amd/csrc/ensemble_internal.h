@@ -21,6 +21,14 @@ struct EnsTile {
 hipError_t launch_ensemble(int dtype, const void *in, void *out, const EnsTile *tiles,
                            int ntiles, const void *insts, int bc, int K, int V, bool diffuse_d,
                            hipStream_t s);
+// Instances whose five fields fit ENS_LDS_BYTES of LDS (64 x 64 in FP32)
+// run all nsteps steps on chip, one workgroup each: lds_inst is a device
+// array of `count` instance indices; lds_bytes (the largest such instance,
+// 5 nx ny elements) is the dynamic LDS of each workgroup. In place in state.
+constexpr int ENS_LDS_BYTES = 81920;
+hipError_t launch_ensemble_lds(int dtype, void *state, const int *lds_inst, int count,
+                               const void *insts, int bc, long long nsteps, bool diffuse_d,
+                               size_t lds_bytes, hipStream_t s);
 // Size of one packed instance record for dtype, and packing of one record.
 size_t ensemble_instance_bytes(int dtype);
 void ensemble_pack_instance(int dtype, void *dst, long long offset, int nx, int ny,

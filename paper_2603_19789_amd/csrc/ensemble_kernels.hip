@@ -87,6 +87,113 @@ hipError_t launch_ensemble(int dtype, const void *in, void *out, const EnsTile *
                      : dispatch_ek<double, false, 1>(in, out, tiles, ntiles, insts, bc, K, s);
 }
 
+// ---------------------------------------------------------------------------
+// Instances small enough for the LDS of one workgroup (5 nx ny elements in
+// ENS_LDS_BYTES: 64 x 64 in FP32) stay on chip for the whole run: one
+// workgroup per instance reads it once, takes every step in LDS and writes it
+// back once. A step: each thread forms the updates of its cells (cells
+// tid, tid + 512, ...) into registers from the LDS values of the previous
+// step, then, after a barrier, writes them over them. The neighbour sum is
+// (north + south) + (east + west) and the update is seird_update, as in the
+// pass kernels, so results are those of sslbm_run bit for bit.
+constexpr int ENS_LDS_THREADS = 512;
+
+template <typename T>
+constexpr int lds_cells_per_thread() {
+    return ENS_LDS_BYTES / (5 * (int)sizeof(T)) / ENS_LDS_THREADS;
+}
+
+// Eight wavefronts per workgroup, at most 256 VGPRs each (the updates of a
+// thread's eight cells wait in registers for the barrier): one instance per
+// CU at a time, which leaves the other half of the CU's LDS and most of its
+// registers to other kernels.
+template <typename T, bool DIFFUSE_D>
+__global__ __launch_bounds__(ENS_LDS_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+void ensemble_lds_kernel(
+    T *__restrict__ state, const int *__restrict__ lds_inst,
+    const EnsInstance<T> *__restrict__ insts, int bc, long long nsteps) {
+    extern __shared__ __align__(16) unsigned char lds_bytes[];
+    T *s = reinterpret_cast<T *>(lds_bytes);
+    const EnsInstance<T> m = insts[lds_inst[blockIdx.x]];
+    const int nx = m.nx, ny = m.ny, n = nx * ny;
+    T *g = state + m.offset;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 5 * n; i += ENS_LDS_THREADS)
+        s[i] = g[i];
+
+    constexpr int CPT = lds_cells_per_thread<T>();
+    int nbr[CPT][4];  // north, south, east, west cell indices
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int cell = tid + j * ENS_LDS_THREADS;
+        const int x = cell < n ? cell % nx : 0, y = cell < n ? cell / nx : 0;
+        nbr[j][0] = map_index(y - 1, ny, bc) * nx + x;
+        nbr[j][1] = map_index(y + 1, ny, bc) * nx + x;
+        nbr[j][2] = y * nx + map_index(x + 1, nx, bc);
+        nbr[j][3] = y * nx + map_index(x - 1, nx, bc);
+    }
+    __syncthreads();
+    for (long long t = 0; t < nsteps; ++t) {
+        T out[CPT][5];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int cell = tid + j * ENS_LDS_THREADS;
+            if (cell < n) {
+                T cen[5], nb[5];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const T *f = s + c * n;
+                    cen[c] = f[cell];
+                    nb[c] = (c < 4 || DIFFUSE_D)
+                                ? (f[nbr[j][0]] + f[nbr[j][1]]) + (f[nbr[j][2]] + f[nbr[j][3]])
+                                : T(0);
+                }
+                seird_update<T, DIFFUSE_D>(cen, nb, m.k, out[j]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int cell = tid + j * ENS_LDS_THREADS;
+            if (cell < n) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c)
+                    s[c * n + cell] = out[j][c];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < 5 * n; i += ENS_LDS_THREADS)
+        g[i] = s[i];
+}
+
+template <typename T, bool DD>
+static hipError_t launch_lds_t(void *state, const int *lds_inst, int count, const void *insts,
+                               int bc, long long nsteps, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL((ensemble_lds_kernel<T, DD>), dim3((unsigned)count),
+                       dim3(ENS_LDS_THREADS), lds_bytes, st, static_cast<T *>(state), lds_inst,
+                       static_cast<const EnsInstance<T> *>(insts), bc, nsteps);
+    return hipGetLastError();
+}
+
+hipError_t launch_ensemble_lds(int dtype, void *state, const int *lds_inst, int count,
+                               const void *insts, int bc, long long nsteps, bool diffuse_d,
+                               size_t lds_bytes, hipStream_t s) {
+    if (count <= 0 || nsteps <= 0)
+        return hipSuccess;
+    if (lds_bytes > (size_t)ENS_LDS_BYTES)
+        return hipErrorInvalidValue;
+    if (dtype == SSLBM_F32)
+        return diffuse_d ? launch_lds_t<float, true>(state, lds_inst, count, insts, bc, nsteps,
+                                                     lds_bytes, s)
+                         : launch_lds_t<float, false>(state, lds_inst, count, insts, bc, nsteps,
+                                                      lds_bytes, s);
+    return diffuse_d ? launch_lds_t<double, true>(state, lds_inst, count, insts, bc, nsteps,
+                                                  lds_bytes, s)
+                     : launch_lds_t<double, false>(state, lds_inst, count, insts, bc, nsteps,
+                                                   lds_bytes, s);
+}
+
 size_t ensemble_instance_bytes(int dtype) {
     return dtype == SSLBM_F32 ? sizeof(EnsInstance<float>) : sizeof(EnsInstance<double>);
 }

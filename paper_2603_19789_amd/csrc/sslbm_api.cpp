@@ -66,6 +66,11 @@ long long round_rows(const sslbm_ctx *c, int K, int V) {
 
 int auto_rows(const sslbm_ctx *c, int K, int V) {
     long long h = round_rows(c, K, V);
+    // One step per pass: a wavefront's work is so short that several rounds
+    // of 8-row chunks stream better than one round of taller ones (4096^2:
+    // FP32 4.44 -> 4.68 TB/s, FP64 4.54 -> 4.71 TB/s).
+    if (K == 1 && h > 8)
+        h = 8;
     if (h < 2 * K)
         h = 2 * K;
     if (h > 65536)

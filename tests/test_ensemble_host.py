@@ -75,7 +75,7 @@ def test_launch_shape_and_run_arguments(lib):
 
 
 def test_odd_rows_use_one_column_per_lane(lib):
-    st, h, _ = _create(lib, [(64, 64), (65, 64)], [c1_params()] * 2)
+    st, h, _ = _create(lib, [(200, 64), (201, 64)], [c1_params()] * 2)
     got = Launch()
     assert lib.sslbm_ensemble_get_launch(h, ctypes.byref(got)) == binding.OK
     assert got.cols_per_lane == 1
@@ -90,3 +90,38 @@ def test_uneven_workload_recipe():
         assert 1.5 <= p.beta / p.gamma <= 5.0
     e = binding.Ensemble(w.sizes, w.params)
     assert e.elements >= sum(5 * nx * ny for nx, ny in w.sizes)
+
+
+def test_size_classes():
+    """Instances of at most 80 KiB go on chip; the others are grouped by the
+    power-of-two bucket of their longest side, each with a shape of its own."""
+    sizes = [(64, 64), (3, 5), (130, 71), (128, 128), (256, 64), (65, 64), (512, 512), (1, 1)]
+    e = binding.Ensemble(sizes, [c1_params()] * len(sizes), dtype="f32")
+    cls = e.classes()
+    on_chip = [c for c in cls if c["on_chip"]]
+    assert len(on_chip) == 1 and on_chip[0]["instances"] == 3
+    assert on_chip[0]["cells"] == 64 * 64 + 15 + 1 and on_chip[0]["launch"]["steps_per_pass"] == 0
+    # (65, 64) and (128, 128) share the bucket up to 128; (130, 71) and (256, 64) up to 256
+    march = {c["max_side"]: c for c in cls if not c["on_chip"]}
+    assert sorted(march) == [128, 256, 512]
+    assert march[128]["instances"] == 2 and march[256]["instances"] == 2
+    for i, (nx, ny) in enumerate(sizes):
+        c = cls[e.instance_class(i)]
+        assert c["on_chip"] == (5 * nx * ny * 4 <= 81920)
+    for c in march.values():
+        assert c["launch"]["steps_per_pass"] == 6 and c["launch"]["rows_per_wave"] >= 12
+    # a shape for one class leaves the others automatic
+    k512 = next(i for i, c in enumerate(cls) if c["max_side"] == 512 and not c["on_chip"])
+    e.set_class_launch(k512, 3, 40, 1)
+    after = e.classes()
+    assert after[k512]["launch"] == {"steps_per_pass": 3, "rows_per_wave": 40, "cols_per_lane": 1}
+    assert e.launch() == after[k512]["launch"]  # the class with the most cells
+    k_chip = next(i for i, c in enumerate(cls) if c["on_chip"])
+    with pytest.raises(binding.SSLBMError):
+        e.set_class_launch(k_chip, 3, 0, 1)
+    with pytest.raises(binding.SSLBMError):
+        e.set_class_launch(len(cls), 3, 0, 1)
+    # FP64: 64 x 64 is 160 KiB, too large for the on-chip class
+    e64 = binding.Ensemble([(64, 64), (40, 40)], [c1_params()] * 2, dtype="f64")
+    c64 = e64.classes()
+    assert [c["on_chip"] for c in c64] == [False, True]
