@@ -48,7 +48,7 @@ HEADLINE = ("sslbm", "f32", 3.0)
 KERNEL_SOURCES = ["paper_2603_19789_amd/csrc/sslbm_kernels.hip",
                   "paper_2603_19789_amd/csrc/march_core.h",
                   "paper_2603_19789_amd/csrc/seird_device.h"]
-TRAFFIC_FILE = ROOT / "profiles" / "sslbm_march_f32_4096_traffic.md"
+TRAFFIC_FILE = ROOT / "profiles" / "sslbm_march_4096_traffic.md"
 
 # algorithmic HBM bytes per node and step at one step per pass
 SSLBM_BYTES = {"f32": 40, "f64": 80}      # 5 fields read + 5 written
@@ -77,6 +77,8 @@ def parse_args():
     ap.add_argument("--fd4-steps", type=int, default=0,
                     help="steps of the fourth-order finite-difference / RK4 reference solver "
                          "on the 4096x4096 workload, FP32 and FP64 (0 skips it)")
+    ap.add_argument("--drift-steps", type=int, default=10000,
+                    help="steps of the FP32-versus-FP64 drift run at R0 = 5 (0 skips it)")
     ap.add_argument("--no-one-step", action="store_true",
                     help="skip the one-step-per-pass runs of the pass kernel")
     ap.add_argument("--ensemble-steps", type=int, default=2000,
@@ -91,31 +93,35 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the headline kernel, from the committed counter
-    summary, if it was taken on the current kernel source."""
-    if not TRAFFIC_FILE.exists():
-        return None
-    text = TRAFFIC_FILE.read_text()
-    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]{16})", text)
-    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
-        return None
-    return float(m_bytes.group(1))
-
-
-def recorded_valu_issue():
-    """VALU issue utilisation of the headline kernel from the committed
-    counter summary, if it was taken on the current kernel source."""
-    path = ROOT / "profiles" / "sslbm_march_4096_valu.md"
+def _recorded(path, key, kernel):
+    """A per-kernel figure from a committed counter summary: the line
+    `key: <kernel> = <value>`, if the summary was taken on the current
+    kernel source (its kernel_source_sha256_16 line)."""
     if not path.exists():
         return None
     text = path.read_text()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]{16})", text)
-    m_val = re.search(r"headline_valu_issue:\s*([0-9.]+)", text)
-    if not m_hash or not m_val or m_hash.group(1) != kernel_hash():
+    if not m_hash or m_hash.group(1) != kernel_hash():
         return None
-    return float(m_val.group(1))
+    for m in re.finditer(rf"{key}:\s*(.+?)\s*=\s*([0-9.eE+-]+)\s*$", text, re.M):
+        if m.group(1) == kernel:
+            return float(m.group(2))
+    return None
+
+
+def recorded_traffic(kernel="sslbm_march_kernel<float, 5, false, 2>"):
+    """HBM bytes per launch of `kernel` on the 4096 x 4096 workload."""
+    return _recorded(TRAFFIC_FILE, "hbm_bytes_per_launch", kernel)
+
+
+def recorded_valu_issue(kernel="sslbm_march_kernel<float, 5, false, 2>"):
+    """VALU issue utilisation of `kernel` on the 4096 x 4096 workload."""
+    return _recorded(ROOT / "profiles" / "sslbm_march_4096_valu.md", "valu_issue", kernel)
+
+
+def march_kernel(dtype, k, cols_per_lane):
+    t = "float" if dtype == "f32" else "double"
+    return f"sslbm_march_kernel<{t}, {k}, false, {cols_per_lane}>"
 
 
 def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK, depth=0):
@@ -181,6 +187,23 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK, de
         out["total_population"] = sum(tot)
     del solver
     return out
+
+
+def run_drift(torch, inputs, Solver, steps):
+    """FP32 against FP64 on the 4096 x 4096 workload at R0 = 5 over `steps`
+    steps (both on the GPU): per-compartment relative L2 difference."""
+    w = inputs.c2_workload(r0=5.0, nsteps=steps)
+    out = {}
+    for d, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        s = Solver(w.nx, w.ny, w.params, dtype=d)
+        rho = torch.tensor(w.rho0, dtype=tdt, device="cuda")
+        s.run(rho, steps)
+        out[d] = rho.double()
+        del s
+    rel = [float(torch.linalg.vector_norm(out["f32"][c] - out["f64"][c])
+                 / torch.linalg.vector_norm(out["f64"][c])) for c in range(5)]
+    return {"workload": w.name, "steps": steps, "rel_l2_by_compartment": rel,
+            "max": max(rel)}
 
 
 def run_ensemble(torch, inputs, Ensemble, steps):
@@ -543,6 +566,11 @@ def main():
         single[d] = res
         print(f"# sslbm {d} one step per pass: {res['glups']:.1f} GLUPS, "
               f"{res['achieved_gbps']:.0f} GB/s per launch", file=sys.stderr, flush=True)
+    drift = None
+    if args.drift_steps > 0:
+        drift = run_drift(torch, inputs, Solver, args.drift_steps)
+        print(f"# FP32 vs FP64 over {drift['steps']} steps at R0=5: max relative L2 "
+              f"{drift['max']:.2e}", file=sys.stderr, flush=True)
     ensemble = None
     if args.ensemble_steps > 0:
         ensemble = run_ensemble(torch, inputs, Ensemble, args.ensemble_steps)
@@ -597,32 +625,28 @@ def main():
     copy_gbps = copy_probe(torch, 1 if args.copy_probe else 5)
 
     head = results[0]
-    traffic = recorded_traffic()
-    k = head["steps_per_pass"]
+    # the kernel the timed passes launch (the even split may shorten every pass)
+    k = head["plan"]["longest"]
     v = head["launch"].get("cols_per_lane", 1)
-    # The pass kernel's roof is HBM: algorithmic bytes of one
-    # launch (every field read and written once, whatever its depth) over the
-    # launch's own duration, measured on the launch stream over the timed
-    # passes. Its vector-ALU rate is reported beside it: with several steps per
-    # pass the arithmetic, not the bytes, is what the launch waits on.
+    kernel = march_kernel("f32", k, v)
+    traffic = recorded_traffic(kernel)
     roof = {
         "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBPS,
         "achieved": round(head["achieved_gbps"], 1),
         "frac": round(head["achieved_gbps"] / PEAK_HBM_GBPS, 4),
         "traffic": traffic,
-        "kernel": f"sslbm_march_kernel<float, {k}, false, {v}>",
+        "kernel": kernel,
         "steps_per_pass": k, "launches": head["launches"], "plan": head["plan"],
         "algorithmic_bytes_per_launch": head["algorithmic_bytes_per_launch"],
         "avg_launch_ms": round(head["avg_launch_ms"], 5),
         "valu": {"achieved": round(head["tflops"], 2), "peak": PEAK_VALU_TFLOPS,
                  "unit": "TFLOP/s", "frac": round(head["tflops"] / PEAK_VALU_TFLOPS, 4),
                  "flops_per_update": FLOPS_PER_UPDATE,
-                 "issue_frac_profiled": recorded_valu_issue()},
+                 "issue_frac_profiled": recorded_valu_issue(kernel)},
         "effective_hbm_frac": round(head["effective_gbps"] / PEAK_HBM_GBPS, 4),
         "hbm_copy_gbps": round(copy_gbps, 1),
         "one_step_per_pass": {
-            d: {"kernel": f"sslbm_march_kernel<{'float' if d == 'f32' else 'double'}, 1, "
-                          f"false, {r['launch'].get('cols_per_lane', 1)}>",
+            d: {"kernel": march_kernel(d, 1, r["launch"].get("cols_per_lane", 1)),
                 "glups": round(r["glups"], 2), "avg_launch_ms": round(r["avg_launch_ms"], 5),
                 "achieved": round(r["achieved_gbps"], 1),
                 "frac": round(r["achieved_gbps"] / PEAK_HBM_GBPS, 4),
@@ -641,6 +665,8 @@ def main():
         "variants": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                      for r in results],
     }
+    if drift is not None:
+        line["fp32_drift"] = drift
     if ensemble is not None:
         line["ensemble"] = ensemble
     if adjoint_res is not None:

@@ -35,7 +35,7 @@ def _map(i, n, bc):
     return np.where(m < n, m, 2 * n - 1 - m)
 
 
-def windowed_oracle(orc, rho0, params, nsteps, bc, samples):
+def windowed_oracle(orc, rho0, params, nsteps, bc, samples, threads=1):
     """Oracle values after nsteps at the sampled (x, y) nodes. Each node depends
     only on nodes within nsteps cells, so the oracle runs on a periodic window
     of side 2 nsteps + 3 around it; no-flux walls are the mirror-image
@@ -48,7 +48,7 @@ def windowed_oracle(orc, rho0, params, nsteps, bc, samples):
         ys = _map(y + offs, ny, bc)
         xs = _map(x + offs, nx, bc)
         win = rho0[:, ys][:, :, xs]
-        res = orc.sslbm_run(win, params, nsteps, bc="periodic")
+        res = orc.sslbm_run(win, params, nsteps, bc="periodic", threads=threads)
         out[s] = res[:, half, half]
     return out
 

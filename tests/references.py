@@ -12,6 +12,9 @@ different statement in the paper or from mathematics that fixes the answer:
 * ``euler_ode`` / ``rk4_ode`` -- textbook integrators of the local SEIRD ODE
 * ``dfe_eigenvalues``      -- Eq. (eigenvalues) for the E-I block at the DFE
 * ``heat_kernel_gaussian`` -- continuum solution of pure diffusion from a Gaussian
+* ``bgk_fp32_model``       -- the BGK scheme (Eq. pdf) evaluated in plain NumPy
+                              float32, to measure what FP32 storage and
+                              arithmetic alone cost (not a pin of the oracle)
 """
 from __future__ import annotations
 
@@ -177,3 +180,37 @@ def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
 
 def rel_l2_per_compartment(a: np.ndarray, b: np.ndarray):
     return [rel_l2(a[c], b[c]) for c in range(a.shape[0])]
+
+
+# ------------------------------------------------------- FP32 rounding floor --
+
+def bgk_fp32_model(rho0: np.ndarray, p, nsteps: int) -> np.ndarray:
+    """The BGK scheme of Eq. (pdf) with f^eq = w_i rho and the source
+    w_i Psi dt (Eq. sources, Eq. rhoD by forward Euler for D), equilibrium
+    start, periodic push streaming, every value stored and every operation
+    rounded in float32 by NumPy. Returns the densities in float64. It is not
+    a reference for the scheme (the FP64 oracle is), only for how far FP32
+    rounding alone moves it."""
+    f32 = np.float32
+    w = WEIGHTS.astype(f32)
+    rho = np.asarray(rho0, dtype=f32)
+    f = np.stack([w[i] * rho[:4] for i in range(5)], axis=1)
+    dead = rho[4].copy()
+    dl = np.array([lattice_diffusivity(p, c) for c in range(4)])
+    omega = (1.0 / (0.5 + 3.0 * dl)).astype(f32)
+    bdt, ke, ki = f32(p.beta * p.dt), f32(p.alpha * p.dt), f32(p.gamma * p.dt)
+    kr, kd = f32((1 - p.phi) * p.gamma * p.dt), f32(p.phi * p.gamma * p.dt)
+    for _ in range(nsteps):
+        r = f.sum(axis=1, dtype=f32)
+        S, E, I, R = r
+        nc = (S + E) + (I + R)
+        force = np.where(nc > 0, bdt * S * I / np.where(nc > 0, nc, f32(1)), f32(0))
+        src = np.stack([-force, force - ke * E, ke * E - ki * I, kr * I])
+        new = np.empty_like(f)
+        for c in range(4):
+            for i in range(5):
+                post = f[c, i] + (w[i] * r[c] - f[c, i]) * omega[c] + w[i] * src[c]
+                new[c, i] = np.roll(post, (CY[i], CX[i]), axis=(0, 1))
+        dead = dead + kd * I
+        f = new
+    return np.concatenate([f.sum(axis=1, dtype=f32), dead[None]]).astype(np.float64)

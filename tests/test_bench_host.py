@@ -18,8 +18,11 @@ def test_more_than_one_gpu_is_refused():
 def test_recorded_traffic_matches_the_kernel_source():
     sys.path.insert(0, str(ROOT))
     import bench
-    traffic = bench.recorded_traffic()
-    assert traffic is not None, "profiles/ summary was taken on another version of the kernel"
-    # the headline pass moves its algorithmic bytes plus a few per cent of halo
-    algorithmic = 40 * 4096 * 4096
-    assert algorithmic <= traffic < 1.2 * algorithmic
+    for kernel in ("sslbm_march_kernel<float, 5, false, 2>",
+                   "sslbm_march_kernel<float, 6, false, 2>"):
+        traffic = bench.recorded_traffic(kernel)
+        assert traffic is not None, f"no counter summary of {kernel} on the current source"
+        # a pass moves its algorithmic bytes plus a few per cent of halo
+        algorithmic = 40 * 4096 * 4096
+        assert algorithmic <= traffic < 1.2 * algorithmic
+        assert 0.0 < bench.recorded_valu_issue(kernel) < 1.0
