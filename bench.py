@@ -371,10 +371,44 @@ def run_surrogate(torch, inputs, Solver, train_steps):
     bare = S.Rollout(sur, w.params, w.ny, w.nx, threshold=float("inf"), seed=0, backoff=False)
     bare.solver.set_launch(**plain_launch)
     _, br = bare.run(rho0, T)
+    # time to T against the error target, for the trained 50-step network and
+    # one trained the same way for 200-step jumps: plain SSLBM reaches every
+    # target (its error is plain_err), so each row compares time at that
+    # target's error budget
+    curve = []
+    nets = [(sur.jump, sur)]
+    net200 = S.UNet(levels=4, base=32, seed=0)
+    sur200, rep200 = S.train(net200, steps=train_steps, batch=16, size=256, jump=200, lr=1e-3,
+                             seed=1)
+    nets.append((200, sur200))
+    net_pass_ms = {}
+    for jump, model in nets:
+        unjudged = S.Rollout(model, w.params, w.ny, w.nx, threshold=float("inf"), seed=0,
+                             backoff=False)
+        unjudged.solver.set_launch(**plain_launch)
+        unjudged.run(rho0, T)  # warm-up
+        alone, ar = unjudged.run(rho0, T)
+        net_pass_ms[jump] = ar.seconds * 1e3 / ar.jumps
+        curve.append({"jump": jump, "target": None, "ms": round(ar.seconds * 1e3, 3),
+                      "rel_l2_vs_fp64": S.relative_l2(alone, ref), "accepted": ar.jumps,
+                      "jumps": ar.jumps, "speedup": round(plain_ms / (ar.seconds * 1e3), 4)})
+        for target in (1e-3, 1e-2, 3e-2):
+            rl = S.Rollout(model, w.params, w.ny, w.nx, tiles=4, tile=64, target=target, seed=0)
+            rl.solver.set_launch(**plain_launch)
+            rl.run(rho0, 4 * jump)  # warm-up
+            st_t, rt = rl.run(rho0, T)
+            e = S.relative_l2(st_t, ref)
+            curve.append({"jump": jump, "target": target, "ms": round(rt.seconds * 1e3, 3),
+                          "rel_l2_vs_fp64": e, "meets_target": e <= target,
+                          "accepted": rt.accepted, "jumps": rt.jumps,
+                          "speedup": round(plain_ms / (rt.seconds * 1e3), 4)})
+    plain_step_ms = plain_ms / T
     return {"workload": w.name, "T": T, "jump": sur.jump, "parameters": net.parameters,
             "train": {"steps": rep.steps, "batch": rep.batch, "size": 256, "samples": rep.samples,
                       "seconds": round(rep.seconds, 2), "first_loss": rep.first_loss,
                       "last_loss": rep.last_loss, "tflops": round(rep.conv_tflops, 1)},
+            "train_jump200": {"seconds": round(rep200.seconds, 2), "first_loss": rep200.first_loss,
+                              "last_loss": rep200.last_loss},
             "inference_batch64_256_ms": round(infer_ms, 3),
             "inference_tflops": round(infer_tflops, 1),
             "plain_ms": round(plain_ms, 3), "plain_launch": plain_launch,
@@ -389,6 +423,13 @@ def run_surrogate(torch, inputs, Solver, train_steps):
             "surrogate_only_speedup": round(plain_ms / (br.seconds * 1e3), 4),
             "jump_error_estimate": {"min": fr.min_check_error, "median": fr.median_check_error,
                                     "max": fr.max_check_error},
+            "time_to_T": curve,
+            # one network pass on the whole grid against plain SSLBM per step:
+            # a jump shorter than this many steps cannot win even if every
+            # jump were accepted without any judging
+            "network_pass_ms": {str(j): round(v, 4) for j, v in net_pass_ms.items()},
+            "plain_step_ms": round(plain_step_ms, 5),
+            "break_even_jump_steps": round(net_pass_ms[nets[0][0]] / plain_step_ms, 1),
             "dtype": "bf16 network, f32 state"}
 
 
@@ -611,6 +652,14 @@ def main():
     surrogate_res = None
     if args.surrogate_steps > 0:
         surrogate_res = run_surrogate(torch, inputs, Solver, args.surrogate_steps)
+        for row in surrogate_res["time_to_T"]:
+            print(f"#   jump {row['jump']}, target {row['target']}: {row['ms']:.1f} ms "
+                  f"({row['speedup']:.3f}x plain), error {row['rel_l2_vs_fp64']:.2e}, "
+                  f"{row['accepted']}/{row['jumps']} jumps by the network", file=sys.stderr,
+                  flush=True)
+        print(f"#   break-even jump {surrogate_res['break_even_jump_steps']} steps "
+              f"(network pass {surrogate_res['network_pass_ms']} ms, plain step "
+              f"{surrogate_res['plain_step_ms']} ms)", file=sys.stderr, flush=True)
         print(f"# surrogate: trained {surrogate_res['train']['steps']} steps in "
               f"{surrogate_res['train']['seconds']:.1f} s (loss {surrogate_res['train']['last_loss']:.2e}); "
               f"time to T plain {surrogate_res['plain_ms']:.1f} ms, rollout "

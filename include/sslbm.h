@@ -158,10 +158,9 @@ int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream, s
  * the centre value, so nothing crosses the wall; Sec. II.C.2, mass
  * conservation).
  * rho_in, rho_out: device, layout rho, must not overlap (SSLBM_E_ALIAS).
- * The force of infection is zero where S + E + I + R <= 0, and also where
- * that sum is a positive subnormal number of the arithmetic type (below
- * 2^-126 in FP32, 2^-1022 in FP64): the quotient dropped there is below
- * beta dt times that bound for non-negative densities.
+ * The force of infection is zero where S + E + I + R <= 0, and in FP32 also
+ * where that sum is a positive subnormal number (below 2^-126): the quotient
+ * dropped there is below 2^-126 beta dt for non-negative densities.
  */
 int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream);
 

@@ -7,9 +7,8 @@
 // Design. One wavefront owns a strip of 64 V consecutive columns (V = 1 or
 // 2 adjacent columns per lane) and walks down a chunk of rows. For every
 // level l = 0..K-1 it keeps the recent rows of that level in registers;
-// level 0 is read from HBM one or two rows ahead of use (prefetch_rows
-// below), levels 1..K are computed from the rows of the level below, and
-// level K is written to HBM. East and
+// level 0 is read from HBM one row ahead of use, levels 1..K are computed
+// from the rows of the level below, and level K is written to HBM. East and
 // west neighbours come from the neighbouring register of the lane or, across
 // lanes, from DPP wave shifts; north and south neighbours are the lane's own
 // rows. No LDS and no barrier is needed: wavefronts are independent. A
@@ -259,53 +258,25 @@ __device__ __forceinline__ void levels(MarchState<T, K, V> &st, const MarchArgs<
     }
 }
 
-// How far ahead level-0 rows are fetched. Level 1 of row t reads level-0
-// rows t-2, t-1, t and is the last reader of row t-2, so once it is done
-// row t+2 can be fetched into that slot ((t+2) mod 4 = (t-2) mod 4): the
-// ring of 4 then holds two rows in use and two in flight, and every load
-// has the rest of its own row's levels plus all of the next row's to arrive.
-// The cost is the registers of the second row in flight, which levels 2..K
-// could otherwise reuse. FP64 gains (4096^2, five steps per pass: 333 ->
-// 318 us per pass, its arithmetic is the shorter wait); FP32 at six steps
-// per pass would spill and measured 2% slower, so it fetches one row ahead:
-// row t+1 at the start of row t.
-template <typename T>
-constexpr int prefetch_rows() {
-    return sizeof(T) == 8 ? 2 : 1;
-}
-
-// Warm-up rows t = TC < 2K (compile time): the levels that already have
-// three rows below them (l <= t/2) and the fetch of the row prefetch_rows
-// ahead (after level 1 when two ahead). Nothing is stored yet.
+// Warm-up rows t = TC < 2K (compile time): fetch row t + 1, then the levels
+// that already have three rows below them (l <= t/2). Nothing is stored yet.
 template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int TC>
 __device__ __forceinline__ void warm_up(MarchState<T, K, V> &st, const MarchArgs<T, V> &a) {
     if constexpr (TC < 2 * K) {
-        if constexpr (prefetch_rows<T>() == 2) {
-            levels<T, K, DIFFUSE_D, V, TC % RING, 1, (TC / 2 < 1 ? TC / 2 : 1)>(st, a, TC);
-            fetch_row<T, K, V, SW, (TC + 2) % RING>(st, a, TC + 2);
-            levels<T, K, DIFFUSE_D, V, TC % RING, 2, TC / 2>(st, a, TC);
-        } else {
-            fetch_row<T, K, V, SW, (TC + 1) % RING>(st, a, TC + 1);
-            levels<T, K, DIFFUSE_D, V, TC % RING, 1, TC / 2>(st, a, TC);
-        }
+        fetch_row<T, K, V, SW, (TC + 1) % RING>(st, a, TC + 1);
+        levels<T, K, DIFFUSE_D, V, TC % RING, 1, TC / 2>(st, a, TC);
         warm_up<T, K, DIFFUSE_D, V, SW, TC + 1>(st, a);
     }
 }
 
-// Steady-state row t (phase P): the fetch of row t + prefetch_rows, all K
-// levels, one output row. Straight-line code, so the memory counters stay
-// exact: the wait for row t's data leaves the later rows' loads in flight.
+// Steady-state row t (phase P): fetch row t + 1, all K levels, one output row.
+// Straight-line code, so the memory counters stay exact and the wait for row
+// t's data lets the row t + 1 loads stay in flight.
 template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int P>
 __device__ __forceinline__ void steady_row(MarchState<T, K, V> &st, const MarchArgs<T, V> &a,
                                            int t) {
-    if constexpr (prefetch_rows<T>() == 2) {
-        levels<T, K, DIFFUSE_D, V, P, 1, 1>(st, a, t);
-        fetch_row<T, K, V, SW, (P + 2) % RING>(st, a, t + 2);
-        levels<T, K, DIFFUSE_D, V, P, 2, K>(st, a, t);
-    } else {
-        fetch_row<T, K, V, SW, (P + 1) % RING>(st, a, t + 1);
-        levels<T, K, DIFFUSE_D, V, P, 1, K>(st, a, t);
-    }
+    fetch_row<T, K, V, SW, (P + 1) % RING>(st, a, t + 1);
+    levels<T, K, DIFFUSE_D, V, P, 1, K>(st, a, t);
 }
 
 // The rows of one wavefront's chunk: fill the levels, then one output row
@@ -325,8 +296,6 @@ __device__ __forceinline__ void march_rows(const MarchArgs<T, V> &a) {
 
     // rows 0 .. 2K-1: fill the levels; from row 2K on every row yields output
     fetch_row<T, K, V, SW, 0>(st, a, 0);
-    if constexpr (prefetch_rows<T>() == 2)
-        fetch_row<T, K, V, SW, 1>(st, a, 1);
     warm_up<T, K, DIFFUSE_D, V, SW, 0>(st, a);
     constexpr int P0 = (2 * K) % RING;
     int t = 2 * K;

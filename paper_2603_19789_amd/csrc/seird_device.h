@@ -21,32 +21,30 @@ struct Coef {
 // FP32: the hardware reciprocal v_rcp_f32 (within 1 ulp for normal inputs,
 // a fifth of the cost of the rounded division). It is not valid for
 // subnormal inputs (it returns inf there), so positive subnormal n takes
-// the zero branch with n <= 0. The largest quotient this drops is
-// a / n with a = dt beta S I and S, I <= n < 2^-126: below 2^-126 dt beta.
+// the zero branch with n <= 0.
+// FP64: the rounded division, taken unconditionally and then selected (a
+// division under the select measured slower: the compiler branches around
+// it); 1 / n overflows for the smallest subnormal n, hence the same
+// normal-number condition.
 __device__ __forceinline__ float recip_or_zero(float n) {
     return n >= 0x1p-126f ? __builtin_amdgcn_rcpf(n) : 0.0f;
 }
-// FP64: v_rcp_f64 refined by two Newton steps r <- r + r (1 - n r); the
-// select comes last, so the infinite reciprocal of n = 0 never reaches a
-// product that is kept.
 __device__ __forceinline__ double recip_or_zero(double n) {
-    double r = __builtin_amdgcn_rcp(n);
-    r = fma(fma(-n, r, 1.0), r, r);
-    r = fma(fma(-n, r, 1.0), r, r);
+    const double r = 1.0 / n;
     return n >= 0x1p-1022 ? r : 0.0;
 }
 
-// a / n where n is a positive normal number, else 0 (the force of infection
-// is zero on cells with no contact-eligible population). FP32: a times the
-// reciprocal. FP64: the product corrected once by its residual,
-// q + (a - n q) / n, which is within one ulp of the rounded quotient.
+// a / n where n > 0, else 0 (the force of infection is zero on cells with
+// no contact-eligible population). FP32: a times the reciprocal, so a
+// positive subnormal n also gives 0; the quotient dropped there is below
+// 2^-126 beta dt, since a = dt beta S I with S, I <= n. FP64: the rounded
+// quotient, exact for subnormal n too.
 __device__ __forceinline__ float quotient_or_zero(float a, float n) {
     return a * recip_or_zero(n);
 }
 __device__ __forceinline__ double quotient_or_zero(double a, double n) {
-    const double r = recip_or_zero(n);
-    const double q = a * r;
-    return fma(fma(-n, q, a), r, q);
+    const double q = a / n;
+    return n > 0.0 ? q : 0.0;
 }
 
 // SEIRD source increments Psi^C dt of one node, Eq. (sources) and Eq. (rhoD),
