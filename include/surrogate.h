@@ -76,6 +76,28 @@ int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w,
                               const void *weight, int cin, void *dx, int dx_pitch,
                               void *flip_scratch, void *hip_stream);
 
+/* The backward-data weights of several layers in one launch: for each
+ * layer l < layers (at most 32), weight[l] ([cout[l]][9][cin[l]], BF16)
+ * flipped in space and transposed in channels into flipped[l]
+ * ([cin[l]][9][cout[l]], 18 cout cin bytes, 16-byte aligned):
+ * flipped[i][8 - tap][o] = weight[o][tap][i]. Host arrays of device
+ * pointers; no flipped buffer may overlap a weight or another flipped one.
+ * Exact (a permutation). */
+int sur_flip_weights(int layers, const void *const *weight, const int *cout, const int *cin,
+                     void *const *flipped, void *hip_stream);
+
+/* sur_conv3x3_backward_data on weights flipped by sur_flip_weights, and,
+ * when act is not NULL, through the adjoint of the leaky activation whose
+ * output act is: act is a BF16 view of cin channels at dx's pixels, and
+ * each stored value v becomes BF16(act > 0 ? v : slope v). Bit for bit
+ * sur_conv3x3_backward_data followed by sur_leaky_backward in place (the
+ * chain rule through an activation that feeds this convolution's input,
+ * without a separate pass). dx may not overlap dz or act. */
+int sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int n, int h, int w,
+                                      int cout, const void *flipped, int cin, void *dx,
+                                      int dx_pitch, const void *act, int act_pitch, float slope,
+                                      void *hip_stream);
+
 /* Workspace bytes of sur_conv3x3_backward_weight for these sizes (0 if invalid). */
 size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int cout);
 
@@ -85,6 +107,18 @@ size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int c
 int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int dz_pitch, int n,
                                 int h, int w, int cin, int cout, float *dweight, float *dbias,
                                 void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* sur_conv3x3_backward_weight of the convolution that sur_conv3x3_forward_up
+ * computes: its input's channels [0, cu) are xu (n, h/2, w/2) upsampled 2x
+ * by repetition and channels [cu, cin) are x, read without the upsampled
+ * copy. Bit for bit sur_up2 into a concatenation buffer followed by
+ * sur_conv3x3_backward_weight; the same workspace size. cu a multiple of 32
+ * and less than cin; h even, w a multiple of 8. SSLBM_E_UNSUPPORTED for
+ * images under 8 x 32 pixels. */
+int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const void *x,
+                                   int x_pitch, const void *dz, int dz_pitch, int n, int h, int w,
+                                   int cin, int cout, float *dweight, float *dbias,
+                                   void *workspace, size_t workspace_bytes, void *hip_stream);
 
 /* dz = y > 0 ? dy : slope dy over `pixels` pixels of c channels (y is the
  * activation's output). dz may alias dy. */
@@ -98,6 +132,12 @@ int sur_pool2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, i
               void *hip_stream);
 int sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
                        int dx_pitch, int accumulate, void *hip_stream);
+/* sur_pool2_backward, then the activation adjoint of sur_leaky_backward on
+ * the stored result, with act (a BF16 view of c channels at dx's pixels,
+ * not NULL) the activation's output: bit for bit the two calls in a row. */
+int sur_pool2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                           int dx_pitch, int accumulate, const void *act, int act_pitch,
+                           float slope, void *hip_stream);
 
 /* 2x nearest-neighbour upsampling of x (n, h, w, c) into y (n, 2h, 2w, c),
  * and its adjoint: dx (n, h, w) = sum of dy over each 2x2 window. */
@@ -105,6 +145,12 @@ int sur_up2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int
             void *hip_stream);
 int sur_up2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
                      int dx_pitch, void *hip_stream);
+/* sur_up2_backward, then the activation adjoint as in
+ * sur_pool2_backward_act (act a BF16 view of c channels at dx's pixels,
+ * not NULL): bit for bit the two calls in a row. */
+int sur_up2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                         int dx_pitch, const void *act, int act_pitch, float slope,
+                         void *hip_stream);
 
 /* Network input from densities: x (BF16 NHWC, 16 channels, pitch 16) holds
  * rho_c / scale_in[c] for c < 5, then planes[b][0..8] (FP32 device

@@ -140,11 +140,18 @@ def library() -> ctypes.CDLL:
             "sur_conv3x3_forward_up": [vp, i, i, vp, i, i, i, i, i, vp, vp, vp, i, i, i, f, vp],
             "sur_conv3x3_backward_data": [vp, i, i, i, i, i, vp, i, vp, i, vp, vp],
             "sur_conv3x3_backward_weight": [vp, i, vp, i, i, i, i, i, i, vp, vp, vp, sz, vp],
+            "sur_conv3x3_backward_weight_up": [vp, i, i, vp, i, vp, i, i, i, i, i, i, vp, vp, vp,
+                                               sz, vp],
+            "sur_conv3x3_backward_data_flipped": [vp, i, i, i, i, i, vp, i, vp, i, vp, i, f, vp],
+            "sur_flip_weights": [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(i),
+                                 ctypes.POINTER(vp), vp],
             "sur_leaky_backward": [vp, i, vp, i, vp, i, ll, i, f, vp],
             "sur_pool2": [vp, i, i, i, i, i, vp, i, vp],
             "sur_pool2_backward": [vp, i, i, i, i, i, vp, i, i, vp],
+            "sur_pool2_backward_act": [vp, i, i, i, i, i, vp, i, i, vp, i, f, vp],
             "sur_up2": [vp, i, i, i, i, i, vp, i, vp],
             "sur_up2_backward": [vp, i, i, i, i, i, vp, i, vp],
+            "sur_up2_backward_act": [vp, i, i, i, i, i, vp, i, vp, i, f, vp],
             "sur_pack_input": [vp, i, i, i, vp, fp, vp, vp],
             "sur_apply_output": [vp, vp, i, i, i, fp, vp, vp],
             "sur_mse_loss": [vp, vp, vp, i, i, i, fp, vp, vp, vp, vp],

@@ -145,17 +145,13 @@ int sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, in
                         pooled, pooled_pitch, hip_stream);
 }
 
-int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
-                              const void *weight, int cin, void *dx, int dx_pitch,
-                              void *flip_scratch, void *hip_stream) {
-    if (!view_ok(dz, dz_pitch, cout) || !view_ok(dx, dx_pitch, cin) || !dims_ok(n, h, w) ||
-        !weight || !flip_scratch || !aligned16(flip_scratch) ||
-        !conv_input_fits(dz_pitch, n, h, w, cout))
-        return SSLBM_E_ARG;
-    const hipStream_t s = (hipStream_t)hip_stream;
-    int st = status(sslbm::launch_flip(weight, cout, cin, flip_scratch, s));
-    if (st != SSLBM_OK)
-        return st;
+namespace {
+
+// The backward-data convolution with weights already flipped (after the
+// arguments were checked), optionally through the activation adjoint.
+int backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
+                  const void *flipped, int cin, void *dx, int dx_pitch, const void *act,
+                  int act_pitch, float slope, hipStream_t s) {
     sslbm::ConvArgs a;
     a.x = dz;
     a.x_pitch = dz_pitch;
@@ -163,17 +159,79 @@ int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w,
     a.h = h;
     a.w = w;
     a.cin = cout;
-    a.wt = flip_scratch;
+    a.wt = flipped;
     a.bias = nullptr;
     a.y = dx;
     a.y_pitch = dx_pitch;
     a.cout = cin;
-    a.slope = 0.f;
+    a.slope = slope;
     a.pool = nullptr;
     a.pool_pitch = 0;
     a.xu = nullptr;
     a.xu_pitch = a.cu = 0;
+    a.mask = act;
+    a.mask_pitch = act ? act_pitch : 0;
     return status(sslbm::launch_conv_fwd(a, false, false, s));
+}
+
+bool backward_data_args_ok(const void *dz, int dz_pitch, int n, int h, int w, int cout,
+                           const void *weight, int cin, const void *dx, int dx_pitch) {
+    return view_ok(dz, dz_pitch, cout) && view_ok(dx, dx_pitch, cin) && dims_ok(n, h, w) &&
+           weight && conv_input_fits(dz_pitch, n, h, w, cout);
+}
+
+// An activation view for the adjoint: null (none), or a BF16 view of c
+// channels with a finite slope.
+bool act_ok(const void *act, int act_pitch, int c, float slope) {
+    return !act || (view_ok(act, act_pitch, c) && std::isfinite(slope));
+}
+
+}  // namespace
+
+int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
+                              const void *weight, int cin, void *dx, int dx_pitch,
+                              void *flip_scratch, void *hip_stream) {
+    if (!backward_data_args_ok(dz, dz_pitch, n, h, w, cout, weight, cin, dx, dx_pitch) ||
+        !flip_scratch || !aligned16(flip_scratch))
+        return SSLBM_E_ARG;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    int st = status(sslbm::launch_flip(weight, cout, cin, flip_scratch, s));
+    if (st != SSLBM_OK)
+        return st;
+    return backward_data(dz, dz_pitch, n, h, w, cout, flip_scratch, cin, dx, dx_pitch, nullptr, 0,
+                         0.f, s);
+}
+
+int sur_flip_weights(int layers, const void *const *weight, const int *cout, const int *cin,
+                     void *const *flipped, void *hip_stream) {
+    if (layers < 1 || layers > sslbm::SUR_MAX_FLIP_LAYERS || !weight || !cout || !cin || !flipped)
+        return SSLBM_E_ARG;
+    sslbm::FlipTable t{};
+    t.layers = layers;
+    t.start[0] = 0;
+    for (int l = 0; l < layers; ++l) {
+        if (!weight[l] || !flipped[l] || !aligned16(flipped[l]) || cout[l] <= 0 ||
+            cout[l] > MAX_CHANNELS || cin[l] <= 0 || cin[l] > MAX_CHANNELS)
+            return SSLBM_E_ARG;
+        t.w[l] = weight[l];
+        t.wf[l] = flipped[l];
+        t.cout[l] = cout[l];
+        t.cin[l] = cin[l];
+        t.start[l + 1] = t.start[l] + (long long)cout[l] * 9 * cin[l];
+    }
+    return status(sslbm::launch_flip_multi(t, (hipStream_t)hip_stream));
+}
+
+int sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int n, int h, int w,
+                                      int cout, const void *flipped, int cin, void *dx,
+                                      int dx_pitch, const void *act, int act_pitch, float slope,
+                                      void *hip_stream) {
+    if (!backward_data_args_ok(dz, dz_pitch, n, h, w, cout, flipped, cin, dx, dx_pitch) ||
+        !aligned16(flipped) || !act_ok(act, act_pitch, cin, slope) ||
+        (act && !conv_input_fits(act_pitch, n, h, w, cin)))
+        return SSLBM_E_ARG;
+    return backward_data(dz, dz_pitch, n, h, w, cout, flipped, cin, dx, dx_pitch, act, act_pitch,
+                         slope, (hipStream_t)hip_stream);
 }
 
 size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int cout) {
@@ -192,8 +250,27 @@ int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int 
         return SSLBM_E_ARG;
     if (workspace_bytes < sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout))
         return SSLBM_E_ARG;
-    return status(sslbm::launch_wgrad(x, x_pitch, dz, dz_pitch, n, h, w, cin, cout, dweight,
-                                      dbias, workspace, (hipStream_t)hip_stream));
+    return status(sslbm::launch_wgrad(x, x_pitch, nullptr, 0, 0, dz, dz_pitch, n, h, w, cin, cout,
+                                      dweight, dbias, workspace, (hipStream_t)hip_stream));
+}
+
+int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const void *x,
+                                   int x_pitch, const void *dz, int dz_pitch, int n, int h, int w,
+                                   int cin, int cout, float *dweight, float *dbias,
+                                   void *workspace, size_t workspace_bytes, void *hip_stream) {
+    if (cu <= 0 || cu % 32 || cin <= cu || cin > MAX_CHANNELS || !view_ok(xu, xu_pitch, cu) ||
+        !view_ok(x, x_pitch, cin - cu) || !view_ok(dz, dz_pitch, cout) || !dims_ok(n, h, w) ||
+        h % 2 || w % 8 || !dweight || !workspace || !aligned16(workspace) ||
+        !conv_input_fits(x_pitch, n, h, w, cin - cu) ||
+        !conv_input_fits(xu_pitch, n, h / 2, w / 2, cu) ||
+        !conv_input_fits(dz_pitch, n, h, w, cout))
+        return SSLBM_E_ARG;
+    if (workspace_bytes < sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout))
+        return SSLBM_E_ARG;
+    if (h < 8 || w < 32)
+        return SSLBM_E_UNSUPPORTED;  // needs the halo-tile kernel
+    return status(sslbm::launch_wgrad(x, x_pitch, xu, xu_pitch, cu, dz, dz_pitch, n, h, w, cin,
+                                      cout, dweight, dbias, workspace, (hipStream_t)hip_stream));
 }
 
 int sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,
@@ -218,7 +295,17 @@ int sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c,
         w % 2)
         return SSLBM_E_ARG;
     return status(sslbm::launch_pool2_bwd(dy, dy_pitch, n, h, w, c, dx, dx_pitch, accumulate != 0,
-                                          (hipStream_t)hip_stream));
+                                          nullptr, 0, 0.f, (hipStream_t)hip_stream));
+}
+
+int sur_pool2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                           int dx_pitch, int accumulate, const void *act, int act_pitch,
+                           float slope, void *hip_stream) {
+    if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, h, w) || h % 2 ||
+        w % 2 || !act || !act_ok(act, act_pitch, c, slope))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_pool2_bwd(dy, dy_pitch, n, h, w, c, dx, dx_pitch, accumulate != 0,
+                                          act, act_pitch, slope, (hipStream_t)hip_stream));
 }
 
 int sur_up2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
@@ -232,8 +319,18 @@ int sur_up2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, v
                      int dx_pitch, void *hip_stream) {
     if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, 2 * h, 2 * w))
         return SSLBM_E_ARG;
-    return status(
-        sslbm::launch_up2_bwd(dy, dy_pitch, n, h, w, c, dx, dx_pitch, (hipStream_t)hip_stream));
+    return status(sslbm::launch_up2_bwd(dy, dy_pitch, n, h, w, c, dx, dx_pitch, nullptr, 0, 0.f,
+                                        (hipStream_t)hip_stream));
+}
+
+int sur_up2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                         int dx_pitch, const void *act, int act_pitch, float slope,
+                         void *hip_stream) {
+    if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, 2 * h, 2 * w) ||
+        !act || !act_ok(act, act_pitch, c, slope))
+        return SSLBM_E_ARG;
+    return status(sslbm::launch_up2_bwd(dy, dy_pitch, n, h, w, c, dx, dx_pitch, act, act_pitch,
+                                        slope, (hipStream_t)hip_stream));
 }
 
 int sur_pack_input(const float *rho, int batch, int h, int w, const float *planes,

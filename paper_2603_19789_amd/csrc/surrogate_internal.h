@@ -31,6 +31,11 @@ struct ConvArgs {
     // cu is x's channel 0). xu null: all from x.
     const void *xu;
     int xu_pitch, cu;
+    // Activation adjoint in the epilogue: each stored BF16 value v becomes
+    // BF16(m > 0 ? v : slope v), m the element of this BF16 NHWC view (cout
+    // channels, the pixels of y) at the same pixel and channel. Null: none.
+    const void *mask = nullptr;
+    int mask_pitch = 0;
 };
 
 struct WgradArgs {
@@ -52,6 +57,19 @@ struct WgradPlan {
     size_t bytes() const { return align256(dz_t_bytes) + align256(xs_bytes) + align256(part_bytes); }
 };
 
+// Weights of several layers for one flip launch (the backward-data kernels
+// of a whole network): layer l's [cout][9][cin] weights w[l] become
+// [cin][9][cout] flipped in space at wf[l]; start[l] is the prefix sum of
+// the layers' element counts.
+constexpr int SUR_MAX_FLIP_LAYERS = 32;
+struct FlipTable {
+    int layers;
+    const void *w[SUR_MAX_FLIP_LAYERS];
+    void *wf[SUR_MAX_FLIP_LAYERS];
+    int cout[SUR_MAX_FLIP_LAYERS], cin[SUR_MAX_FLIP_LAYERS];
+    long long start[SUR_MAX_FLIP_LAYERS + 1];
+};
+
 struct IoScales {
     float inv_in[5];   // input density channel = rho / scale_in
     float out[5];      // increment = scale_out * network output
@@ -64,19 +82,24 @@ struct AdamArgs {
 
 hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s);
 hipError_t launch_flip(const void *w, int cout, int cin, void *wf, hipStream_t s);
+hipError_t launch_flip_multi(const FlipTable &t, hipStream_t s);
 WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout);
-hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, int h, int w,
-                        int cin, int cout, float *dw, float *db, void *ws, hipStream_t s);
+// xu: null, or the half-resolution view of input channels [0, cu) (images
+// of at least 8 x 32 pixels; hipErrorNotSupported otherwise)
+hipError_t launch_wgrad(const void *x, int xp, const void *xu, int xup, int cu, const void *dz,
+                        int dzp, int n, int h, int w, int cin, int cout, float *dw, float *db,
+                        void *ws, hipStream_t s);
 hipError_t launch_leaky_bwd(const void *dy, int dyp, const void *y, int yp, void *dz, int dzp,
                             long long pixels, int c, float slope, hipStream_t s);
 hipError_t launch_pool2(const void *x, int xp, int n, int h, int w, int c, void *y, int yp,
                         hipStream_t s);
 hipError_t launch_pool2_bwd(const void *dy, int dyp, int n, int h, int w, int c, void *dx,
-                            int dxp, bool accumulate, hipStream_t s);
+                            int dxp, bool accumulate, const void *mask, int mp, float slope,
+                            hipStream_t s);
 hipError_t launch_up2(const void *x, int xp, int n, int h, int w, int c, void *y, int yp,
                       hipStream_t s);
 hipError_t launch_up2_bwd(const void *dy, int dyp, int n, int h, int w, int c, void *dx, int dxp,
-                          hipStream_t s);
+                          const void *mask, int mp, float slope, hipStream_t s);
 hipError_t launch_pack_input(const float *rho, int batch, int h, int w, const float *planes,
                              const IoScales &sc, void *x, hipStream_t s);
 hipError_t launch_apply_output(const float *rho, const float *out, int batch, int h, int w,

@@ -300,9 +300,14 @@ constexpr int HALO_TH = 8, HALO_TW = 32;
 // UP: the first cu input channels are read from a half-resolution view
 // as its nearest 2x upsampling (pixel (y, x) reads (y / 2, x / 2)), so a
 // decoder's upsampled skip concatenation needs no upsampled copy in HBM.
-template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP>
+// MASK (BF16 output, no pooling; the backward-data pass): the epilogue also
+// applies the adjoint of the activation that produced the pass's output
+// tensor, reading that activation from a.mask (see ConvArgs), with the
+// roundings of a separate sur_leaky_backward over the stored values.
+template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP, bool MASK>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(NT == 4 ? 2 : 3)))
 void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
+    static_assert(!MASK || (!F32OUT && !POOL), "the mask applies to plain BF16 outputs");
     constexpr int HW2 = HALO_TW + 2, HPIX = (HALO_TH + 2) * HW2;
     constexpr int HP = HPIX * 4, HPT = (HP + THREADS - 1) / THREADS;  // 16-byte pieces
     constexpr int TC = 16 * NT;
@@ -489,6 +494,10 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
         POOL ? a.pool : a.y, (short)0,
         POOL ? (int)((((long long)a.n * hp * wp - 1) * a.pool_pitch + a.cout) * 2) : 0,
         BUF_FORMAT_WORD);
+    const __amdgpu_buffer_rsrc_t mr = __builtin_amdgcn_make_buffer_rsrc(
+        MASK ? const_cast<void *>(a.mask) : a.y, (short)0,
+        MASK ? (int)(((P - 1) * a.mask_pitch + a.cout) * 2) : 0, BUF_FORMAT_WORD);
+    const unsigned mpb = (unsigned)(a.mask_pitch * 2);
     auto epilogue = [&](int unit) {
         int n, y0, x0, cg;
         unit_origin(unit, n, y0, x0, cg);
@@ -503,6 +512,23 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
             for (int r = 0; r < 2; ++r) {
                 if (yr + r >= a.h)
                     continue;  // wavefront-uniform
+                // the activation's outputs at the row's 8 values of this lane
+                // (MASK only), all requested before the first is used
+                unsigned short mk[4][4];
+                if constexpr (MASK) {
+                    const unsigned mrow =
+                        (unsigned)((((long long)n * a.h + yr + r) * a.w + x0) * mpb) +
+                        (unsigned)(4 * g) * mpb + (unsigned)(c * 2);
+#pragma unroll
+                    for (int ms = 2 * r; ms < 2 * r + 2; ++ms)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int col = 16 * (ms % 2) + i;
+                            const bool ok = c_ok && x0 + col + 4 * g < a.w;
+                            mk[ms][i] = __builtin_amdgcn_raw_buffer_load_b16(
+                                mr, ok ? mrow + (unsigned)col * mpb : OUT_OF_RANGE, 0, 0);
+                        }
+                }
                 const unsigned lane_off =
                     (unsigned)((((long long)n * a.h + yr + r) * a.w + x0) * ypb) +
                     (unsigned)(4 * g) * ypb + (unsigned)(c * ESZ);
@@ -520,7 +546,13 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
                             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v),
                                                                   yr_, off, 0, 0);
                         } else {
-                            const unsigned short hv = __builtin_bit_cast(unsigned short, (__bf16)v);
+                            unsigned short hv = __builtin_bit_cast(unsigned short, (__bf16)v);
+                            if constexpr (MASK) {
+                                const float d = __builtin_bit_cast(float, (unsigned)hv << 16);
+                                const float mv =
+                                    __builtin_bit_cast(float, (unsigned)mk[ms][i] << 16);
+                                hv = to_bf16(mv > 0.f ? d : a.slope * d);
+                            }
                             __builtin_amdgcn_raw_buffer_store_b16(hv, yr_, off, 0, 0);
                             if (POOL)
                                 fv[ms][i] = __builtin_bit_cast(float, (unsigned)hv << 16);
@@ -596,6 +628,24 @@ __global__ __launch_bounds__(THREADS) void flip_kernel(const uint16_t *__restric
     const int t = (int)((e / cin) % 9);
     const int o = (int)(e / (9ll * cin));
     wf[((long long)i * 9 + (8 - t)) * cout + o] = w[e];
+}
+
+// The same for several layers in one launch: thread e flips element
+// e - start[l] of layer l, start[l] <= e < start[l + 1].
+__global__ __launch_bounds__(THREADS) void flip_multi_kernel(FlipTable t) {
+    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
+    if (e >= t.start[t.layers])
+        return;
+    int l = 0;
+    while (e >= t.start[l + 1])
+        ++l;
+    const long long k = e - t.start[l];
+    const int cin = t.cin[l], cout = t.cout[l];
+    const int i = (int)(k % cin);
+    const int tap = (int)((k / cin) % 9);
+    const int o = (int)(k / (9ll * cin));
+    static_cast<uint16_t *>(t.wf[l])[((long long)i * 9 + (8 - tap)) * cout + o] =
+        static_cast<const uint16_t *>(t.w[l])[k];
 }
 
 // ------------------------------------------------------- backward weights
@@ -808,37 +858,60 @@ __global__ __launch_bounds__(THREADS) void conv_wgrad_kernel(WgradArgs a) {
 
 // ------------------------------------------ weight gradient, halo tiles
 // dW[o][t][i] = sum over pixels p of dZ[p][o] X[p + shift_t][i], on images of
-// at least 8 x 32 pixels, straight from the NHWC activations: no
-// channel-major copies in HBM. A workgroup owns a block of 32 output x 32
-// input channels and walks pixel tiles of 8 rows x 32 columns. Per tile it
-// transposes into LDS the tile of dZ (channel-major, 32 x 256) and the input
-// tile with its one-pixel halo in three copies shifted by dx = -1, 0, +1
-// (channel-major, 10 rows x 32 columns each), so that every MFMA fragment
-// (8 consecutive pixels of one channel) is one aligned 16-byte LDS read;
-// pixels outside the image carry dZ = 0. Wavefront w takes tile rows 2w and
-// 2w + 1 as its k steps (32 pixels each) and accumulates all nine taps of
-// the 32 x 32 block (each dZ fragment serves nine taps). The four
+// at least 8 x 32 pixels, straight from the NHWC activations. A workgroup
+// owns a block of 32 output x 32 input channels and walks pixel tiles of 8
+// rows x 32 columns. Per tile, LDS holds the dZ tile (256 pixels) and the
+// input tile with its one-pixel halo (10 x 34 pixels, periodic wrap) in
+// their natural pixel-major layout, one 16-byte store per 8 channels; pixels
+// outside the image carry dZ = 0. The MFMA fragments need the opposite
+// order (8 consecutive pixels of one channel per lane): they are read with
+// the LDS transpose load, which hands lane i of each 16-lane group element
+// j of the 8-byte piece addressed by lane 4 j + i / 4, at element i % 4.
+// When lane 4 q + r of a group addresses pixel k0 + q, channels c0 + 4 r ..
+// + 3, lane i receives channel c0 + i of pixels k0 .. k0 + 3; two such loads
+// (k0 and k0 + 4) make a fragment. A tap's horizontal shift is a shift of
+// the pixel rows, so one copy of the input tile serves all nine taps.
+// Wavefront w takes tile rows 2w and 2w + 1 as its k steps (32 pixels
+// each). For each horizontal shift it reads the four halo rows those steps
+// touch once and uses each for every vertical shift it serves (12 MFMAs per
+// pair of fragments); the next tile's loads are in flight meanwhile. The four
 // wavefronts' sums are added in LDS and written as the workgroup's split of
-// the fixed-order reduction below. The
-// workgroups of input block 0 also sum the dZ tile per output channel (the
-// bias gradient), thread (o, s) over pixels 32 s .. 32 s + 31 of every tile,
-// and write the eight per-thread sums of a channel, added in order, as
-// their split of the bias.
-constexpr int WH_TH = 8, WH_TW = 32;  // pixel tile
-constexpr int WH_AZ = 264;            // row stride of the dZ tile (elements; bank spread)
-constexpr int WH_BX = 328;            // channel stride of a shifted input copy (elements)
-constexpr int WH_RESIDENT = 512;      // two workgroups per CU on 256 CUs
+// the fixed-order reduction below. The workgroups of input block 0 also sum
+// the dZ tile per output channel (the bias gradient): thread (pixel group
+// s, channels 8 j .. 8 j + 7) over pixels s, s + 64, s + 128, s + 192 of
+// every tile; the 64 sums of a channel are then added in order.
+constexpr int WH_TH = 8, WH_TW = 32;     // pixel tile
+constexpr int WH_HW = WH_TW + 2;         // halo tile columns
+constexpr int WH_HPIX = (WH_TH + 2) * WH_HW;
+constexpr int WH_PZ = 40;  // LDS row pitch (elements) of a dZ pixel: 16-byte stores
+constexpr int WH_PX = 40;  // and of an input pixel
+constexpr int WH_ZP = WH_TH * WH_TW * 4 / THREADS;           // 16-byte pieces a thread loads
+constexpr int WH_XP = (WH_HPIX * 4 + THREADS - 1) / THREADS;
+constexpr int WH_RESIDENT = 512;         // two workgroups per CU on 256 CUs
+constexpr int WH_LDS = WH_TH * WH_TW * WH_PZ + WH_HPIX * WH_PX;  // elements
+static_assert(WH_LDS * 2 >= 9 * 2 * 2 * 4 * 64 * 4, "the cross-wavefront sums reuse the tiles");
 
-__device__ __forceinline__ unsigned lo_pair(unsigned a, unsigned b) {
-    return (a & 0xffffu) | (b << 16);
-}
-__device__ __forceinline__ unsigned hi_pair(unsigned a, unsigned b) {
-    return (a >> 16) | (b & 0xffff0000u);
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// One MFMA fragment from a pixel-major LDS tile: the element pointers p0 and
+// p1 (8-byte aligned) are this lane's addresses for pixels k0 + q and
+// k0 + 4 + q as described above.
+__device__ __forceinline__ bf16x8 tr_fragment(const uint16_t *p0, const uint16_t *p1) {
+    typedef __attribute__((address_space(3))) v4s *lds_v4s;
+    const v4s lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(p0));
+    const v4s hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s)(p1));
+    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
 struct WgradHaloArgs {
     const uint16_t *x, *dz;
     int xp, dzp, n, h, w, cin, cout;
+    // input channels [0, cu) from xu (n, h/2, w/2) as its nearest 2x
+    // upsampling, [cu, cin) from x (x's channel 0 is input channel cu);
+    // xu null: all from x (cu = 0). cu is a multiple of 32, so a block of
+    // 32 input channels comes from one view.
+    const uint16_t *xu;
+    int xup, cu;
     int nob, nib, gb, tiles, tiles_x, tiles_y;
     float *part;    // [gb][cout][9][cin]
     float *part_b;  // [gb][cout]
@@ -846,8 +919,9 @@ struct WgradHaloArgs {
 
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 void conv_wgrad_halo_kernel(WgradHaloArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t Az[32 * WH_AZ];
-    __shared__ __attribute__((aligned(16))) uint16_t Bx[3 * 32 * WH_BX];
+    __shared__ __attribute__((aligned(16))) uint16_t lds[WH_LDS];
+    uint16_t *const Zs = lds;
+    uint16_t *const Xs = lds + WH_TH * WH_TW * WH_PZ;
     constexpr unsigned OUT_OF_RANGE = 0x80000000u;
     const int blocks = a.nob * a.nib;
     const int blk = blockIdx.x % blocks, kb = blockIdx.x / blocks;
@@ -855,12 +929,67 @@ void conv_wgrad_halo_kernel(WgradHaloArgs a) {
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
     const long long P = (long long)a.n * a.h * a.w;
-    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint16_t *>(a.x), (short)0, (int)(((P - 1) * a.xp + a.cin) * 2), BUF_FORMAT_WORD);
+    const int oc0 = ob * 32, ic0 = ib * 32;
+    const bool from_up = ic0 < a.cu;  // workgroup-uniform
+    const int hu = a.h / 2, wu = a.w / 2;
+    const __amdgpu_buffer_rsrc_t xr =
+        from_up ? __builtin_amdgcn_make_buffer_rsrc(
+                      const_cast<uint16_t *>(a.xu), (short)0,
+                      (int)((((long long)a.n * hu * wu - 1) * a.xup + a.cu) * 2), BUF_FORMAT_WORD)
+                : __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(a.x), (short)0,
+                                                    (int)(((P - 1) * a.xp + a.cin - a.cu) * 2),
+                                                    BUF_FORMAT_WORD);
     const __amdgpu_buffer_rsrc_t dr = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint16_t *>(a.dz), (short)0, (int)(((P - 1) * a.dzp + a.cout) * 2),
         BUF_FORMAT_WORD);
-    const int oc0 = ob * 32, ic0 = ib * 32;
+
+    // the 16-byte pieces of a tile: dZ piece e = tid + 256 r is pixel e / 4
+    // (tile row e / 128, column (e / 4) % 32), channels 8 (e % 4) ..; input
+    // piece e (e < 1360) is halo pixel e / 4, channels 8 (e % 4) ..
+    const int j8 = 8 * (tid & 3);
+    struct Stage {
+        u32x4 z[WH_ZP], x[WH_XP];
+    };
+    auto gload = [&](int tile) {
+        Stage st;
+        const int per_image = a.tiles_x * a.tiles_y;
+        const int n = tile / per_image;
+        const int rt = tile - n * per_image;
+        const int y0 = (rt / a.tiles_x) * WH_TH, x0 = (rt - (rt / a.tiles_x) * a.tiles_x) * WH_TW;
+        const int oc = oc0 + j8;
+#pragma unroll
+        for (int r = 0; r < WH_ZP; ++r) {
+            const int px = (tid >> 2) + 64 * r;
+            const int y = y0 + (px >> 5), x = x0 + (px & 31);
+            const bool ok = y < a.h && x < a.w && oc < a.cout;
+            const long long q = ((long long)n * a.h + y) * a.w + x;
+            st.z[r] = load16(dr, ok ? (unsigned)((q * a.dzp + oc) * 2) : OUT_OF_RANGE);
+        }
+        const int ic = ic0 + j8;
+#pragma unroll
+        for (int r = 0; r < WH_XP; ++r) {
+            const int hp = min((tid >> 2) + 64 * r, WH_HPIX - 1);
+            const int hr = hp / WH_HW, hc = hp - (hp / WH_HW) * WH_HW;
+            const int y = wrap(y0 - 1 + hr, a.h), x = wrap(x0 - 1 + hc, a.w);
+            unsigned off;
+            if (from_up)
+                off = (unsigned)(((((long long)n * hu + (y >> 1)) * wu + (x >> 1)) * a.xup + ic) * 2);
+            else
+                off = ic < a.cin ? (unsigned)(((((long long)n * a.h + y) * a.w + x) * a.xp + ic - a.cu) * 2)
+                                 : OUT_OF_RANGE;
+            st.x[r] = load16(xr, off);
+        }
+        return st;
+    };
+    auto lstore = [&](const Stage &st) {
+#pragma unroll
+        for (int r = 0; r < WH_ZP; ++r)
+            *reinterpret_cast<u32x4 *>(&Zs[((tid >> 2) + 64 * r) * WH_PZ + j8]) = st.z[r];
+#pragma unroll
+        for (int r = 0; r < WH_XP; ++r)
+            if ((tid >> 2) + 64 * r < WH_HPIX)
+                *reinterpret_cast<u32x4 *>(&Xs[((tid >> 2) + 64 * r) * WH_PX + j8]) = st.x[r];
+    };
 
     f32x4 acc[9][2][2];
 #pragma unroll
@@ -870,119 +999,92 @@ void conv_wgrad_halo_kernel(WgradHaloArgs a) {
 #pragma unroll
             for (int v = 0; v < 2; ++v)
                 acc[t][u][v] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;  // bias: channel tid / 8, pixels 32 (tid % 8) .. + 31 of each tile
     const bool bias_block = ib == 0;
+    float bsum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // channels 8 (tid % 4) ..
 
-    for (int tile = kb; tile < a.tiles; tile += a.gb) {
-        const int per_image = a.tiles_x * a.tiles_y;
-        const int n = tile / per_image;
-        const int rt = tile - n * per_image;
-        const int y0 = (rt / a.tiles_x) * WH_TH, x0 = (rt - (rt / a.tiles_x) * a.tiles_x) * WH_TW;
-        // dZ tile: item = (tile row, column pair, group of 8 channels)
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int e = tid + THREADS * r;  // < 512
-            const int row = e >> 6, cp = (e >> 2) & 15, j = e & 3;
-            const int y = y0 + row, x = x0 + 2 * cp, oc = oc0 + 8 * j;
-            const bool ok = y < a.h && oc < a.cout;
-            const long long q = ((long long)n * a.h + y) * a.w + x;
-            const u32x4 p0 = load16(dr, ok && x < a.w ? (unsigned)((q * a.dzp + oc) * 2) : OUT_OF_RANGE);
-            const u32x4 p1 =
-                load16(dr, ok && x + 1 < a.w ? (unsigned)(((q + 1) * a.dzp + oc) * 2) : OUT_OF_RANGE);
-            unsigned *dst = reinterpret_cast<unsigned *>(&Az[8 * j * WH_AZ + row * 32 + 2 * cp]);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                dst[(2 * k) * (WH_AZ / 2)] = lo_pair(p0[k], p1[k]);
-                dst[(2 * k + 1) * (WH_AZ / 2)] = hi_pair(p0[k], p1[k]);
-            }
-        }
-        // input halo: item = (halo row, column pair, group of 8 channels);
-        // columns c, c + 1 of copy s hold pixels x0 + c + s - 1 and x0 + c + s
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int e = tid + THREADS * r;
-            if (e < 10 * 16 * 4) {
-                const int hr = e >> 6, cp = (e >> 2) & 15, j = e & 3;
-                const int y = wrap(y0 - 1 + hr, a.h), ic = ic0 + 8 * j;
-                const long long rowq = ((long long)n * a.h + y) * a.w;
-                u32x4 px[4];
-#pragma unroll
-                for (int qd = 0; qd < 4; ++qd) {
-                    const int x = wrap(x0 + 2 * cp - 1 + qd, a.w);
-                    px[qd] = load16(xr, ic < a.cin ? (unsigned)(((rowq + x) * a.xp + ic) * 2)
-                                                   : OUT_OF_RANGE);
-                }
-#pragma unroll
-                for (int sh = 0; sh < 3; ++sh) {
-                    unsigned *dst = reinterpret_cast<unsigned *>(
-                        &Bx[(sh * 32 + 8 * j) * WH_BX + hr * 32 + 2 * cp]);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        dst[(2 * k) * (WH_BX / 2)] = lo_pair(px[sh][k], px[sh + 1][k]);
-                        dst[(2 * k + 1) * (WH_BX / 2)] = hi_pair(px[sh][k], px[sh + 1][k]);
-                    }
-                }
-            }
-        }
-        __syncthreads();
+    // this lane's transpose-load addresses (elements): pixel row offset q
+    // within a group of four, channel offset 4 r
+    const int tq = 8 * g + (m >> 2), tc = 4 * (m & 3);
+    const uint16_t *za = Zs + (2 * wv * WH_TW + tq) * WH_PZ + tc;
+    const uint16_t *xa = Xs + (2 * wv * WH_HW + tq) * WH_PX + tc;
+
+    int tile = kb;
+    if (tile < a.tiles)
+        lstore(gload(tile));
+    __syncthreads();
+    for (; tile < a.tiles; tile += a.gb) {
+        const bool more = tile + a.gb < a.tiles;
+        Stage next;
+        if (more)
+            next = gload(tile + a.gb);
         if (bias_block) {
 #pragma unroll
-            for (int k8 = 0; k8 < 4; ++k8) {
+            for (int r = 0; r < 4; ++r) {
                 const u32x4 v = *reinterpret_cast<const u32x4 *>(
-                    &Az[(tid >> 3) * WH_AZ + 32 * (tid & 7) + 8 * k8]);
+                    &Zs[((tid >> 2) + 64 * r) * WH_PZ + j8]);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    bsum += __builtin_bit_cast(float, v[k] << 16);
-                    bsum += __builtin_bit_cast(float, v[k] & 0xffff0000u);
+                    bsum[2 * k] += __builtin_bit_cast(float, v[k] << 16);
+                    bsum[2 * k + 1] += __builtin_bit_cast(float, v[k] & 0xffff0000u);
                 }
             }
         }
+        // dZ fragments of both k steps (rows 2 wv + kk), both 16-channel halves
+        bf16x8 A[2][2];
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-            const int row = 2 * wv + kk;  // this k step's 32 pixels: tile row `row`
-            bf16x8 A[2];
+        for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
-                A[u] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(
-                                                      &Az[(16 * u + m) * WH_AZ + row * 32 + 8 * g]));
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int dy = t / 3, dx = t % 3;  // shifted by one
-                bf16x8 B[2];
-#pragma unroll
-                for (int v = 0; v < 2; ++v)
-                    B[v] = __builtin_bit_cast(
-                        bf16x8, *reinterpret_cast<const uint4 *>(
-                                    &Bx[(dx * 32 + 16 * v + m) * WH_BX + (row + dy) * 32 + 8 * g]));
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int v = 0; v < 2; ++v)
-                        acc[t][u][v] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[u], B[v], acc[t][u][v], 0, 0, 0);
+            for (int u = 0; u < 2; ++u) {
+                const uint16_t *p = za + (kk * WH_TW) * WH_PZ + 16 * u;
+                A[kk][u] = tr_fragment(p, p + 4 * WH_PZ);
             }
-        }
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                // halo rows 2 wv + rr, rr = kk + dy
+                bf16x8 B[4];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const uint16_t *p = xa + (rr * WH_HW + dx) * WH_PX + 16 * v;
+                    B[rr] = tr_fragment(p, p + 4 * WH_PX);
+                }
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+                            acc[3 * dy + dx][u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                A[kk][u], B[kk + dy], acc[3 * dy + dx][u][v], 0, 0, 0);
+            }
+        __syncthreads();  // every wavefront is done with the tiles
+        if (more)
+            lstore(next);
         __syncthreads();
     }
     if (bias_block) {
-        // the eight sums of a channel, added in order (the loop's last
-        // barrier has passed: Az is free)
-        float *red = reinterpret_cast<float *>(Az);
-        red[tid] = bsum;
+        // channel 8 (t % 4) + k of thread t: the 64 sums of a channel (the
+        // threads t with the same t % 4), added in thread order
+        float *red = reinterpret_cast<float *>(lds);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            red[k * THREADS + tid] = bsum[k];
         __syncthreads();
         if (tid < 32) {
+            const int k = tid & 7, c4 = tid >> 3;  // channel 8 c4 + k
             float b = 0.f;
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                b += red[8 * tid + k];
+            for (int s = 0; s < 64; ++s)
+                b += red[k * THREADS + 4 * s + c4];
             if (oc0 + tid < a.cout)
                 a.part_b[(long long)kb * a.cout + oc0 + tid] = b;
         }
+        __syncthreads();
     }
     // The four wavefronts' sums, added in LDS in a fixed order,
     // (w0 + w2) + (w1 + w3), one wavefront's worth (144 values a lane) at a
-    // time through the input-tile area; the workgroup then writes its split.
-    float *red = reinterpret_cast<float *>(Bx);
+    // time; the workgroup then writes its split.
+    float *red = reinterpret_cast<float *>(lds);
     auto put = [&]() {
 #pragma unroll
         for (int t = 0; t < 9; ++t)
@@ -1005,7 +1107,7 @@ void conv_wgrad_halo_kernel(WgradHaloArgs a) {
                     for (int jj = 0; jj < 4; ++jj)
                         acc[t][u][v][jj] += red[(((t * 2 + u) * 2 + v) * 4 + jj) * 64 + lane];
     };
-    __syncthreads();  // the input tile area is free
+    __syncthreads();  // the tile area is free
     if (wv == 2)
         put();
     __syncthreads();
@@ -1047,37 +1149,50 @@ void conv_wgrad_halo_kernel(WgradHaloArgs a) {
     }
 }
 
-// dW = sum over splits in a fixed order, in two passes: pass 1 sums each
-// run of `run` consecutive splits (in order) into the run's first slot,
-// pass 2 sums the runs in order. With run about sqrt(splits) both passes
-// are short.
-__global__ __launch_bounds__(THREADS) void wgrad_runs_kernel(float *__restrict__ part, int splits,
-                                                             long long count, int run) {
-    const long long t = (long long)blockIdx.x * THREADS + threadIdx.x;
-    const int runs = (splits + run - 1) / run;
-    if (t >= count * runs)
-        return;
-    const int r = (int)(t / count);
-    const long long e = t - r * count;
-    const int k0 = r * run, k1 = min(k0 + run, splits);
-    float s = 0.f;
-#pragma unroll 4
-    for (int k = k0; k < k1; ++k)
-        s += part[k * count + e];
-    part[k0 * count + e] = s;  // only this thread reads or writes these slots
-}
-
-__global__ __launch_bounds__(THREADS) void wgrad_reduce_kernel(const float *__restrict__ part,
-                                                               int splits, long long count,
-                                                               int run, float *__restrict__ dw) {
-    const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
-    if (e >= count)
-        return;
-    float s = 0.f;
-#pragma unroll 4
-    for (int k = 0; k < splits; k += run)
-        s += part[k * count + e];
-    dw[e] = s;
+// dW (and the bias gradient) = the sum of the splits' partials in a fixed
+// order, in one launch. A workgroup owns C = 256 / R consecutive outputs
+// (the dW values, then the bias values) and R groups of consecutive splits:
+// thread (group r, output j) adds the splits of group r in order, and the
+// R group sums of an output are then added in group order. Lanes of a
+// wavefront read consecutive outputs of one split (coalesced rows).
+__global__ __launch_bounds__(THREADS) void splits_sum_kernel(const float *__restrict__ part,
+                                                             long long count, float *__restrict__ dw,
+                                                             const float *__restrict__ part_b,
+                                                             int nb, float *__restrict__ db,
+                                                             int splits, int R) {
+    __shared__ float red[THREADS];
+    const int C = THREADS / R;
+    const int tid = threadIdx.x, j = tid % C, r = tid / C;
+    const long long e = (long long)blockIdx.x * C + j;
+    const long long total = count + (db ? nb : 0);
+    const float *src = nullptr;
+    long long stride = 0;
+    if (e < count) {
+        src = part + e;
+        stride = count;
+    } else if (e < total) {
+        src = part_b + (e - count);
+        stride = nb;
+    }
+    const int per = (splits + R - 1) / R;
+    const int k0 = r * per, k1 = min(k0 + per, splits);
+    float sum = 0.f;
+    if (src) {
+#pragma unroll 8
+        for (int k = k0; k < k1; ++k)
+            sum += src[(long long)k * stride];
+    }
+    red[tid] = sum;
+    __syncthreads();
+    if (r == 0 && src) {
+        float t = red[j];
+        for (int q = 1; q < R; ++q)
+            t += red[q * C + j];
+        if (e < count)
+            dw[e] = t;
+        else
+            db[e - count] = t;
+    }
 }
 
 
@@ -1097,6 +1212,17 @@ __device__ __forceinline__ float hi_of(unsigned w) {
 __device__ __forceinline__ unsigned pack2(float lo, float hi) {
     return (unsigned)to_bf16(lo) | ((unsigned)to_bf16(hi) << 16);
 }
+// The activation adjoint on eight stored BF16 gradients d: m > 0 ? d :
+// slope d, m the activation's outputs at the same elements, rounded to BF16.
+__device__ __forceinline__ u32x4 leaky_adjoint(u32x4 d, u32x4 m, float slope) {
+    u32x4 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float d0 = lo_of(d[k]), d1 = hi_of(d[k]);
+        o[k] = pack2(lo_of(m[k]) > 0.f ? d0 : slope * d0, hi_of(m[k]) > 0.f ? d1 : slope * d1);
+    }
+    return o;
+}
 
 __global__ __launch_bounds__(THREADS) void leaky_bwd_kernel(const uint16_t *__restrict__ dy,
                                                             int dyp, const uint16_t *__restrict__ y,
@@ -1109,14 +1235,7 @@ __global__ __launch_bounds__(THREADS) void leaky_bwd_kernel(const uint16_t *__re
         return;
     const long long q = e / c8;
     const int ch = (int)(e - q * c8) * 8;
-    const u32x4 d = ld8(dy + q * dyp + ch), v = ld8(y + q * yp + ch);
-    u32x4 o;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float d0 = lo_of(d[k]), d1 = hi_of(d[k]);
-        o[k] = pack2(lo_of(v[k]) > 0.f ? d0 : slope * d0, hi_of(v[k]) > 0.f ? d1 : slope * d1);
-    }
-    st8(dz + q * dzp + ch, o);
+    st8(dz + q * dzp + ch, leaky_adjoint(ld8(dy + q * dyp + ch), ld8(y + q * yp + ch), slope));
 }
 
 // y (n, h/2, w/2) = mean of 2x2 windows of x (n, h, w)
@@ -1146,11 +1265,15 @@ __global__ __launch_bounds__(THREADS) void pool2_kernel(const uint16_t *__restri
     st8(y + q * yp + ch, o);
 }
 
-// dx (n, h, w) (+)= dy (n, h/2, w/2) / 4 at the window's four inputs
+// dx (n, h, w) (+)= dy (n, h/2, w/2) / 4 at the window's four inputs; with
+// a mask (a BF16 view of the activation output at dx's pixels), the stored
+// sum then goes through the activation's adjoint (leaky_adjoint).
 __global__ __launch_bounds__(THREADS) void pool2_bwd_kernel(const uint16_t *__restrict__ dy,
                                                             int dyp, int n, int h, int w, int c,
                                                             uint16_t *__restrict__ dx, int dxp,
-                                                            int accumulate) {
+                                                            int accumulate,
+                                                            const uint16_t *__restrict__ mask,
+                                                            int mp, float slope) {
     const int c8 = c / 8;
     const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
     if (e >= (long long)n * h * w * c8)
@@ -1174,6 +1297,8 @@ __global__ __launch_bounds__(THREADS) void pool2_bwd_kernel(const uint16_t *__re
         for (int k = 0; k < 4; ++k)
             o[k] = pack2(0.25f * lo_of(d[k]), 0.25f * hi_of(d[k]));
     }
+    if (mask)
+        o = leaky_adjoint(o, ld8(mask + q * mp + ch), slope);
     st8(dx + q * dxp + ch, o);
 }
 
@@ -1195,10 +1320,14 @@ __global__ __launch_bounds__(THREADS) void up2_kernel(const uint16_t *__restrict
     st8(y + q * yp + ch, ld8(x + qi * xp + ch));
 }
 
-// dx (n, h, w) = sum of dy (n, 2h, 2w) over each 2x2 window
+// dx (n, h, w) = sum of dy (n, 2h, 2w) over each 2x2 window; with a mask
+// (a BF16 view of the activation output at dx's pixels), the stored sum
+// then goes through the activation's adjoint (leaky_adjoint).
 __global__ __launch_bounds__(THREADS) void up2_bwd_kernel(const uint16_t *__restrict__ dy,
                                                           int dyp, int n, int h, int w, int c,
-                                                          uint16_t *__restrict__ dx, int dxp) {
+                                                          uint16_t *__restrict__ dx, int dxp,
+                                                          const uint16_t *__restrict__ mask,
+                                                          int mp, float slope) {
     const int c8 = c / 8;
     const long long e = (long long)blockIdx.x * THREADS + threadIdx.x;
     if (e >= (long long)n * h * w * c8)
@@ -1219,6 +1348,8 @@ __global__ __launch_bounds__(THREADS) void up2_bwd_kernel(const uint16_t *__rest
         const float s1 = ((hi_of(v00[k]) + hi_of(v01[k])) + hi_of(v10[k])) + hi_of(v11[k]);
         o[k] = pack2(s0, s1);
     }
+    if (mask)
+        o = leaky_adjoint(o, ld8(mask + q * mp + ch), slope);
     st8(dx + q * dxp + ch, o);
 }
 
@@ -1374,16 +1505,19 @@ __global__ __launch_bounds__(THREADS) void crop_kernel(const float *__restrict__
 
 unsigned blocks_for(long long work) { return (unsigned)((work + THREADS - 1) / THREADS); }
 
-// The two passes over `splits` partial sums of `count` values each.
-static void reduce_splits(float *part, int splits, long long count, float *out, hipStream_t s) {
-    int run = 1;
-    while (run * run < splits)
-        ++run;
-    const long long runs = (splits + run - 1) / run;
-    hipLaunchKernelGGL(wgrad_runs_kernel, dim3(blocks_for(count * runs)), dim3(THREADS), 0, s,
-                       part, splits, count, run);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for(count)), dim3(THREADS), 0, s, part,
-                       splits, count, run, out);
+// The sums over `splits` partials of `count` dW values each (rows of
+// `count`), and of `nb` bias values each when db is not null (rows of nb
+// at part_b), in one launch: R groups of splits per output, R a power of
+// two up to 16 with about four or more splits a group.
+static void reduce_splits(const float *part, int splits, long long count, float *dw,
+                          const float *part_b, int nb, float *db, hipStream_t s) {
+    int R = 1;
+    while (R < 16 && 4 * (2 * R) <= splits)
+        R *= 2;
+    const int C = THREADS / R;
+    const long long total = count + (db ? nb : 0);
+    hipLaunchKernelGGL(splits_sum_kernel, dim3((unsigned)((total + C - 1) / C)), dim3(THREADS), 0,
+                       s, part, count, dw, part_b, nb, db, splits, R);
 }
 
 }  // namespace
@@ -1430,21 +1564,23 @@ static int resident_workgroups(const void *f, std::atomic<int> *cache) {
     return cus * per_cu;
 }
 
-template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP = false>
+template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP = false, bool MASK = false>
 static void conv_halo_go(const ConvArgs &a, hipStream_t s) {
     static std::atomic<int> cache[MAX_DEVICES];  // zero-initialised (static storage)
     const int tiles_x = (a.w + HALO_TW - 1) / HALO_TW, tiles_y = (a.h + HALO_TH - 1) / HALO_TH;
     const int units = a.n * tiles_x * tiles_y * ((a.cout + 16 * NT - 1) / (16 * NT));
-    const void *f = (const void *)conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP>;
+    const void *f = (const void *)conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP, MASK>;
     const int resident = resident_workgroups(f, cache);
     const int blocks = resident > 0 && resident < units ? resident : units;
-    hipLaunchKernelGGL((conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP, MASK>), dim3((unsigned)blocks),
                        dim3(THREADS), 0, s, a, tiles_x, tiles_y, units);
 }
 
 template <int NT>
 static void conv_halo_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
-    if (a.xu) {  // BF16 output, no pooling (a decoder's first convolution)
+    if (a.mask) {  // the backward-data pass: BF16 output, no bias or activation
+        conv_halo_go<NT, false, false, false, false, true>(a, s);
+    } else if (a.xu) {  // BF16 output, no pooling (a decoder's first convolution)
         if (leaky)
             conv_halo_go<NT, false, true, false, true>(a, s);
         else
@@ -1476,8 +1612,13 @@ hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream
         (((long long)a.n * a.h * a.w - 1) * a.y_pitch + a.cout) * (f32out ? 4 : 2);
     const long long pool_bytes =
         a.pool ? (((long long)a.n * (a.h / 2) * (a.w / 2) - 1) * a.pool_pitch + a.cout) * 2 : 0;
+    const long long mask_bytes =
+        a.mask ? (((long long)a.n * a.h * a.w - 1) * a.mask_pitch + a.cout) * 2 : 0;
+    if (a.mask && (leaky || f32out || a.pool || a.xu))
+        return hipErrorInvalidValue;  // the mask goes with plain BF16 outputs only
     const bool halo = a.h >= HALO_TH && a.w >= HALO_TW && units < (1ll << 31) &&
-                      out_bytes < (1ll << 31) && pool_bytes < (1ll << 31);
+                      out_bytes < (1ll << 31) && pool_bytes < (1ll << 31) &&
+                      mask_bytes < (1ll << 31);
     if (a.xu && !halo)
         return hipErrorNotSupported;  // the upsampled input needs halo tiles
     if (halo) {
@@ -1501,6 +1642,13 @@ hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream
             return e;
         return launch_pool2(a.y, a.y_pitch, a.n, a.h, a.w, a.cout, a.pool, a.pool_pitch, s);
     }
+    if (a.mask) {  // nor a mask epilogue: the activation adjoint in place
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        return launch_leaky_bwd(a.y, a.y_pitch, a.mask, a.mask_pitch, a.y, a.y_pitch,
+                                (long long)a.n * a.h * a.w, a.cout, a.slope, s);
+    }
     return hipGetLastError();
 }
 
@@ -1508,6 +1656,12 @@ hipError_t launch_flip(const void *w, int cout, int cin, void *wf, hipStream_t s
     hipLaunchKernelGGL(flip_kernel, dim3(blocks_for((long long)cout * 9 * cin)), dim3(THREADS), 0,
                        s, static_cast<const uint16_t *>(w), cout, cin,
                        static_cast<uint16_t *>(wf));
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_multi(const FlipTable &t, hipStream_t s) {
+    hipLaunchKernelGGL(flip_multi_kernel, dim3(blocks_for(t.start[t.layers])), dim3(THREADS), 0, s,
+                       t);
     return hipGetLastError();
 }
 
@@ -1565,10 +1719,13 @@ WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
     return p;
 }
 
-hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, int h, int w,
-                        int cin, int cout, float *dw, float *db, void *ws, hipStream_t s) {
+hipError_t launch_wgrad(const void *x, int xp, const void *xu, int xup, int cu, const void *dz,
+                        int dzp, int n, int h, int w, int cin, int cout, float *dw, float *db,
+                        void *ws, hipStream_t s) {
     const WgradPlan p = wgrad_plan(n, h, w, cin, cout);
     const long long count = (long long)cout * 9 * cin;
+    if (xu && !p.halo)
+        return hipErrorNotSupported;  // the upsampled input needs halo tiles
     if (p.halo) {
         float *part = static_cast<float *>(ws);
         WgradHaloArgs a;
@@ -1589,11 +1746,12 @@ hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, i
         a.tiles_y = p.tiles_y;
         a.part = part;
         a.part_b = part + (long long)p.splits * count;
+        a.xu = static_cast<const uint16_t *>(xu);
+        a.xup = xu ? xup : 0;
+        a.cu = xu ? cu : 0;
         hipLaunchKernelGGL(conv_wgrad_halo_kernel, dim3((unsigned)(p.nob * p.nib * p.gb)),
                            dim3(THREADS), 0, s, a);
-        reduce_splits(part, p.splits, count, dw, s);
-        if (db)
-            reduce_splits(a.part_b, p.gb, cout, db, s);
+        reduce_splits(part, p.splits, count, dw, a.part_b, cout, db, s);
         return hipGetLastError();
     }
     uint16_t *dz_t = static_cast<uint16_t *>(ws);
@@ -1629,7 +1787,7 @@ hipError_t launch_wgrad(const void *x, int xp, const void *dz, int dzp, int n, i
         hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(THREADS), 0, s, a);
     else
         hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(THREADS), 0, s, a);
-    reduce_splits(part, p.splits, count, dw, s);
+    reduce_splits(part, p.splits, count, dw, nullptr, 0, nullptr, s);
     if (db) {
         // the bias partials reuse the start of the (already reduced) partials buffer
         hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)cout, BIAS_SLICES), dim3(THREADS), 0,
@@ -1657,10 +1815,12 @@ hipError_t launch_pool2(const void *x, int xp, int n, int h, int w, int c, void 
 }
 
 hipError_t launch_pool2_bwd(const void *dy, int dyp, int n, int h, int w, int c, void *dx,
-                            int dxp, bool accumulate, hipStream_t s) {
+                            int dxp, bool accumulate, const void *mask, int mp, float slope,
+                            hipStream_t s) {
     hipLaunchKernelGGL(pool2_bwd_kernel, dim3(blocks_for((long long)n * h * w * (c / 8))),
                        dim3(THREADS), 0, s, static_cast<const uint16_t *>(dy), dyp, n, h, w, c,
-                       static_cast<uint16_t *>(dx), dxp, accumulate ? 1 : 0);
+                       static_cast<uint16_t *>(dx), dxp, accumulate ? 1 : 0,
+                       static_cast<const uint16_t *>(mask), mp, slope);
     return hipGetLastError();
 }
 
@@ -1673,10 +1833,11 @@ hipError_t launch_up2(const void *x, int xp, int n, int h, int w, int c, void *y
 }
 
 hipError_t launch_up2_bwd(const void *dy, int dyp, int n, int h, int w, int c, void *dx, int dxp,
-                          hipStream_t s) {
+                          const void *mask, int mp, float slope, hipStream_t s) {
     hipLaunchKernelGGL(up2_bwd_kernel, dim3(blocks_for((long long)n * h * w * (c / 8))),
                        dim3(THREADS), 0, s, static_cast<const uint16_t *>(dy), dyp, n, h, w, c,
-                       static_cast<uint16_t *>(dx), dxp);
+                       static_cast<uint16_t *>(dx), dxp, static_cast<const uint16_t *>(mask), mp,
+                       slope);
     return hipGetLastError();
 }
 

@@ -74,6 +74,14 @@ def _copy(v):
     return v.clone()
 
 
+def _up_cat_copy(low, skip):
+    """The concatenation [up2(low), skip] that a decoder convolution reads
+    without materialising it, as one tensor (for records)."""
+    torch = _torch()
+    up = _copy(low).repeat_interleave(2, dim=1).repeat_interleave(2, dim=2)
+    return torch.cat([up, _copy(skip)], dim=3)
+
+
 @dataclass
 class _Conv:
     cin: int
@@ -81,6 +89,7 @@ class _Conv:
     act: bool
     w_off: int = 0  # offset of W [cout][9][cin] in the flat parameter vector
     b_off: int = 0  # offset of b [cout]
+    f_off: int = 0  # offset of the flipped W [cin][9][cout] in UNet.flipped
 
 
 class UNet:
@@ -109,6 +118,12 @@ class UNet:
             cv.b_off = off
             off += (cv.cout + 7) // 8 * 8
         self.convs, self.count = convs, off
+        # the backward-data weights ([cin][9][cout], flipped in space), one
+        # block per convolution, rebuilt from theta_bf16 by each backward pass
+        foff = 0
+        for cv in convs:
+            cv.f_off = foff
+            foff += (cv.cout * 9 * cv.cin + 7) // 8 * 8
         # He initialisation for the activated layers; a small last layer, so
         # the untrained network predicts increments near zero
         rng = np.random.default_rng(seed)
@@ -119,6 +134,7 @@ class UNet:
                 0.0, std, cv.cout * 9 * cv.cin)
         self.theta = torch.tensor(theta, device="cuda")
         self.theta_bf16 = torch.empty(off, dtype=torch.bfloat16, device="cuda")
+        self.flipped = torch.empty(foff, dtype=torch.bfloat16, device="cuda")
         self.grad = torch.zeros_like(self.theta)
         self.m = torch.zeros_like(self.theta)
         self.v = torch.zeros_like(self.theta)
@@ -157,14 +173,14 @@ class UNet:
 
     # ------------------------------------------------------------ buffers --
     _BUFFER_NAMES = ("x0", "a", "pool", "cat", "e_last", "b", "hdec", "out", "g_cat", "g_l",
-                     "g_l2", "g_pool", "g_e_last", "dout", "wgrad_ws", "flip", "dims")
+                     "g_l2", "g_pool", "g_e_last", "dout", "wgrad_ws", "dims")
 
     def _buffers(self, n, h, w):
         """Make the buffers of batch n at h x w current. Each shape's set is
         kept, so alternating between shapes (a rollout's whole grid and its
         judge tiles) allocates nothing after the first use of each."""
         if self._shape != (n, h, w):
-            self._backward_ready = False
+            self._fused_up = None  # no forward pass on this shape yet
         if self._shape == (n, h, w):
             return
         if (n, h, w) in self._sets:
@@ -200,8 +216,6 @@ class UNet:
             ws = max(ws, self.lib.sur_conv3x3_backward_weight_workspace(
                 n, dims[l][0], dims[l][1], cv.cin, cv.cout))
         self.wgrad_ws = torch.empty(ws, dtype=torch.uint8, device="cuda")
-        self.flip = torch.empty(max(cv.cout * 9 * cv.cin for cv in self.convs) + 64, dtype=bf,
-                                device="cuda")
         self.dims = dims
         self._shape = (n, h, w)
         self._sets[(n, h, w)] = tuple(getattr(self, name) for name in self._BUFFER_NAMES)
@@ -240,23 +254,32 @@ class UNet:
         cv = self.convs[k]
         n = self._shape[0]
         hh, ww = self.dims[l]
-        if hh < 8 or ww < 32:
+        if hh < 8 or ww < 32 or low.c % 32:
             return False
         flags = LEAKY if cv.act else 0
         _check(self.lib.sur_conv3x3_forward_up(
             low.ptr, low.pitch, low.c, skip.ptr, skip.pitch, n, hh, ww, cv.cin,
             _ptr(self.theta_bf16, cv.w_off), _ptr(self.theta, cv.b_off), dst.ptr, dst.pitch,
             cv.cout, flags, self.slope, None), "sur_conv3x3_forward_up")
+        if self.record is not None:
+            self.record.append({"pass": "forward", "k": k, "x": _up_cat_copy(low, skip),
+                                "y": _copy(dst), "pooled": None})
         return True
 
-    def forward_packed(self, fuse_up=False):
+    def _low_view(self, l):
+        """The half-resolution input of decoder level l's upsampling: the
+        decoder output of level l + 1, or the bottleneck's encoder output."""
+        L = self.levels
+        return self.e_view(L - 1) if l + 1 == L - 1 else _View(self.hdec[l + 1], 0, self.ch[l + 1])
+
+    def forward_packed(self, fuse_up=True):
         """Network pass on self.x0 into self.out (FP32 NHWC, 16 channels).
         fuse_up: decoder convolutions read the upsampled half-resolution
-        tensor directly (same bits; inference only, since the weight
-        gradients read the concatenation buffer it leaves unfilled)."""
+        tensor directly, where the image allows (same bits as the explicit
+        upsampled copy; the backward pass reads the same views)."""
         L, ch, lib = self.levels, self.ch, self.lib
         n = self._shape[0]
-        self._backward_ready = not fuse_up
+        self._fused_up = [False] * max(L - 1, 0)
         k = 0
         for l in range(L):
             src = _View(self.x0, 0, IN_CHANNELS) if l == 0 else _View(self.pool[l], 0, ch[l - 1])
@@ -265,99 +288,127 @@ class UNet:
             self._conv(k + 1, _View(self.a[l], 0, ch[l]), self.e_view(l), l,
                        pooled=self.pool[l + 1] if l + 1 < L else None)
             k += 2
-        h_view = self.e_view(L - 1)
         for l in range(L - 2, -1, -1):
             hh, ww = self.dims[l + 1]
+            low = self._low_view(l)
             dst = _View(self.b[l], 0, ch[l])
-            if not (fuse_up and self._conv_up(k, h_view, self.e_view(l), dst, l)):
-                _check(lib.sur_up2(h_view.ptr, h_view.pitch, n, hh, ww, ch[l + 1],
+            self._fused_up[l] = fuse_up and self._conv_up(k, low, self.e_view(l), dst, l)
+            if not self._fused_up[l]:
+                _check(lib.sur_up2(low.ptr, low.pitch, n, hh, ww, ch[l + 1],
                                    _ptr(self.cat[l]), self.cat[l].shape[-1], None), "sur_up2")
                 self._conv(k, _View(self.cat[l], 0, ch[l + 1] + ch[l]), dst, l)
             self._conv(k + 1, _View(self.b[l], 0, ch[l]), _View(self.hdec[l], 0, ch[l]), l)
             k += 2
-            h_view = _View(self.hdec[l], 0, ch[l])
+        h_view = _View(self.hdec[0], 0, ch[0]) if L > 1 else self.e_view(0)
         self._conv(k, h_view, self.out, 0, f32=True)
         return self.out
 
     # ----------------------------------------------------------- backward --
-    def _conv_backward(self, k, x: _View, y: _View, gy: _View, gx, l):
-        """Gradients of conv k (input x, output y, output gradient gy, which
-        is turned into dZ in place); dX into view gx unless gx is None."""
+    def _flip_weights(self):
+        """The backward-data weights of every convolution from theta_bf16,
+        in one launch per 32 convolutions."""
+        vp = ctypes.c_void_p
+        for k0 in range(0, len(self.convs), 32):
+            cvs = self.convs[k0:k0 + 32]
+            m = len(cvs)
+            w = (vp * m)(*[_ptr(self.theta_bf16, cv.w_off) for cv in cvs])
+            f = (vp * m)(*[_ptr(self.flipped, cv.f_off) for cv in cvs])
+            co = (ctypes.c_int * m)(*[cv.cout for cv in cvs])
+            ci = (ctypes.c_int * m)(*[cv.cin for cv in cvs])
+            _check(self.lib.sur_flip_weights(m, w, co, ci, f, None), "sur_flip_weights")
+
+    def _conv_backward(self, k, x, dz: _View, gx, act, l):
+        """Gradients of conv k from dz (the gradient of its pre-activation
+        output): weight and bias gradients into self.grad, and dX into view
+        gx unless gx is None, through the adjoint of the activation whose
+        output is `act` (the convolution's own input) when act is not None.
+        x: the input view, or (low, skip) for a decoder convolution that
+        read its upsampled input directly."""
         cv = self.convs[k]
         lib = self.lib
         n = self._shape[0]
         hh, ww = self.dims[l]
-        rec = None
-        if self.record is not None:
-            rec = {"pass": "backward", "k": k, "x": _copy(x), "gy": _copy(gy),
-                   "y": None if y is None else _copy(y)}
-        if cv.act:
-            _check(lib.sur_leaky_backward(gy.ptr, gy.pitch, y.ptr, y.pitch, gy.ptr, gy.pitch,
-                                          n * hh * ww, cv.cout, self.slope, None),
-                   "sur_leaky_backward")
         ws = self.wgrad_ws
-        _check(lib.sur_conv3x3_backward_weight(
-            x.ptr, x.pitch, gy.ptr, gy.pitch, n, hh, ww, cv.cin, cv.cout,
-            _ptr(self.grad, cv.w_off), _ptr(self.grad, cv.b_off), _ptr(ws), ws.numel(), None),
-            "sur_conv3x3_backward_weight")
+        dw, db = _ptr(self.grad, cv.w_off), _ptr(self.grad, cv.b_off)
+        if isinstance(x, tuple):
+            low, skip = x
+            _check(lib.sur_conv3x3_backward_weight_up(
+                low.ptr, low.pitch, low.c, skip.ptr, skip.pitch, dz.ptr, dz.pitch, n, hh, ww,
+                cv.cin, cv.cout, dw, db, _ptr(ws), ws.numel(), None),
+                "sur_conv3x3_backward_weight_up")
+        else:
+            _check(lib.sur_conv3x3_backward_weight(
+                x.ptr, x.pitch, dz.ptr, dz.pitch, n, hh, ww, cv.cin, cv.cout, dw, db, _ptr(ws),
+                ws.numel(), None), "sur_conv3x3_backward_weight")
         if gx is not None:
-            _check(lib.sur_conv3x3_backward_data(
-                gy.ptr, gy.pitch, n, hh, ww, cv.cout, _ptr(self.theta_bf16, cv.w_off), cv.cin,
-                gx.ptr, gx.pitch, _ptr(self.flip), None), "sur_conv3x3_backward_data")
-        if rec is not None:
-            rec.update(dz=_copy(gy), dx=None if gx is None else _copy(gx),
-                       dw=self.grad[cv.w_off:cv.w_off + cv.cout * 9 * cv.cin].clone(),
-                       db=self.grad[cv.b_off:cv.b_off + cv.cout].clone())
-            self.record.append(rec)
+            _check(lib.sur_conv3x3_backward_data_flipped(
+                dz.ptr, dz.pitch, n, hh, ww, cv.cout, _ptr(self.flipped, cv.f_off), cv.cin,
+                gx.ptr, gx.pitch, None if act is None else act.ptr,
+                0 if act is None else act.pitch, self.slope, None),
+                "sur_conv3x3_backward_data_flipped")
+        if self.record is not None:
+            self.record.append({
+                "pass": "backward", "k": k,
+                "x": _up_cat_copy(*x) if isinstance(x, tuple) else _copy(x),
+                "dz": _copy(dz), "dx": None if gx is None else _copy(gx),
+                "act": None if act is None else _copy(act),
+                "dw": self.grad[cv.w_off:cv.w_off + cv.cout * 9 * cv.cin].clone(),
+                "db": self.grad[cv.b_off:cv.b_off + cv.cout].clone()})
 
     def backward_packed(self):
         """Parameter gradients (into self.grad) from self.dout (BF16 NHWC,
-        the loss gradient of self.out), after forward_packed() without
-        fuse_up."""
-        if not getattr(self, "_backward_ready", False):
-            raise RuntimeError("backward_packed needs a preceding forward_packed() "
-                               "without fuse_up (the concatenation buffers are unfilled)")
+        the loss gradient of self.out), after forward_packed(). Every
+        gradient tensor a convolution reads is already its pre-activation
+        gradient: the activation adjoints run inside the kernels that
+        produce them (backward data, the upsampling and pooling adjoints)."""
+        if getattr(self, "_fused_up", None) is None:
+            raise RuntimeError("backward_packed needs a preceding forward_packed() on this shape")
         L, ch, lib = self.levels, self.ch, self.lib
         n = self._shape[0]
+        self._flip_weights()
         k = len(self.convs) - 1
+        # output layer (no activation: dZ = dout); its input is the last
+        # activation's output
         h_in = _View(self.hdec[0], 0, ch[0]) if L > 1 else self.e_view(0)
-        g_h = _View(self.g_l[0], 0, ch[0])
-        # output layer (no activation: dZ = dout)
-        self._conv_backward(k, h_in, None, _View(self.dout, 0, OUT_CHANNELS), g_h, 0)
-        k -= 1
+        self._conv_backward(k, h_in, _View(self.dout, 0, OUT_CHANNELS),
+                            _View(self.g_l[0], 0, ch[0]), h_in, 0)
         # decoder, from the top level down
         for l in range(0, L - 1):
             k_first = len(self.convs) - 1 - 2 * (l + 1)
             b = _View(self.b[l], 0, ch[l])
-            hdec = _View(self.hdec[l], 0, ch[l])
             g_b = _View(self.g_l2[l], 0, ch[l])
-            self._conv_backward(k_first + 1, b, hdec, _View(self.g_l[l], 0, ch[l]), g_b, l)
-            cat = _View(self.cat[l], 0, ch[l + 1] + ch[l])
-            g_cat = _View(self.g_cat[l], 0, ch[l + 1] + ch[l])
-            self._conv_backward(k_first, cat, b, g_b, g_cat, l)
-            # gradient of the upsampled input -> the level below's output
+            self._conv_backward(k_first + 1, b, _View(self.g_l[l], 0, ch[l]), g_b, b, l)
+            low = self._low_view(l)
+            x = ((low, self.e_view(l)) if self._fused_up[l]
+                 else _View(self.cat[l], 0, ch[l + 1] + ch[l]))
+            self._conv_backward(k_first, x, g_b, _View(self.g_cat[l], 0, ch[l + 1] + ch[l]),
+                                None, l)
+            # the upsampled part's gradient -> the pre-activation gradient of
+            # the level below's output
             below = (_View(self.g_l[l + 1], 0, ch[l + 1]) if l + 1 < L - 1
                      else _View(self.g_e_last, 0, ch[L - 1]))
             hh, ww = self.dims[l + 1]
-            _check(lib.sur_up2_backward(_ptr(self.g_cat[l]), self.g_cat[l].shape[-1], n, hh, ww,
-                                        ch[l + 1], below.ptr, below.pitch, None),
-                   "sur_up2_backward")
+            _check(lib.sur_up2_backward_act(_ptr(self.g_cat[l]), self.g_cat[l].shape[-1], n, hh,
+                                            ww, ch[l + 1], below.ptr, below.pitch, low.ptr,
+                                            low.pitch, self.slope, None), "sur_up2_backward_act")
         # encoder, from the bottleneck up
         for l in range(L - 1, -1, -1):
             k1 = 2 * l
+            e = self.e_view(l)
             if l == L - 1:
                 g_e = _View(self.g_e_last, 0, ch[l])
             else:
                 g_e = _View(self.g_cat[l], ch[l + 1], ch[l])  # skip gradient already there
                 hh, ww = self.dims[l]
-                _check(lib.sur_pool2_backward(_ptr(self.g_pool[l + 1]), ch[l], n, hh, ww, ch[l],
-                                              g_e.ptr, g_e.pitch, 1, None), "sur_pool2_backward")
+                _check(lib.sur_pool2_backward_act(_ptr(self.g_pool[l + 1]), ch[l], n, hh, ww,
+                                                  ch[l], g_e.ptr, g_e.pitch, 1, e.ptr, e.pitch,
+                                                  self.slope, None), "sur_pool2_backward_act")
             a = _View(self.a[l], 0, ch[l])
             g_a = _View(self.g_l2[l], 0, ch[l])
-            self._conv_backward(k1 + 1, a, self.e_view(l), g_e, g_a, l)
+            self._conv_backward(k1 + 1, a, g_e, g_a, a, l)
             src = _View(self.x0, 0, IN_CHANNELS) if l == 0 else _View(self.pool[l], 0, ch[l - 1])
             g_src = None if l == 0 else _View(self.g_pool[l], 0, ch[l - 1])
-            self._conv_backward(k1, src, a, g_a, g_src, l)
+            self._conv_backward(k1, src, g_a, g_src, None, l)
 
     def adam(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
         self.step_count += 1
@@ -788,13 +839,13 @@ def _main(argv=None):
         net.x0.normal_()
         net.dout.normal_()
         # forward alone as inference runs it; with the backward as training does
-        net.forward_packed(fuse_up=not backward)
+        net.forward_packed()
         if backward:
             net.backward_packed()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.passes):
-            net.forward_packed(fuse_up=not backward)
+            net.forward_packed()
             if backward:
                 net.backward_packed()
         torch.cuda.synchronize()

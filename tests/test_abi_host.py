@@ -277,6 +277,49 @@ def test_surrogate_header_exports_and_host_checks(lib):
                         None) == binding.E_ARG  # step 0
     assert lib.sur_adam(a, None, b, c, vp(0x500000000), 10, 1, 1e-3, 1.0, 0.999, 1e-8,
                         None) == binding.E_ARG  # beta1 = 1
+    # several layers' backward-data weights: 1..32 layers, valid shapes,
+    # 16-byte aligned outputs
+    ptrs = (vp * 33)(*([b] * 33))
+    outs = (vp * 33)(*([c] * 33))
+    ints = (ctypes.c_int * 33)(*([16] * 33))
+    flip = lib.sur_flip_weights
+    assert flip(0, ptrs, ints, ints, outs, None) == binding.E_ARG
+    assert flip(33, ptrs, ints, ints, outs, None) == binding.E_ARG
+    assert flip(2, ptrs, ints, ints, None, None) == binding.E_ARG
+    assert flip(1, ptrs, (ctypes.c_int * 1)(0), ints, outs, None) == binding.E_ARG
+    assert flip(1, ptrs, ints, ints, (vp * 1)(vp(c.value + 2)), None) == binding.E_ARG
+    # backward data on pre-flipped weights through an activation: the
+    # activation view's channels and alignment, a finite slope
+    bdf = lib.sur_conv3x3_backward_data_flipped
+    assert bdf(a, 16, 1, 8, 8, 16, b, 8, c, 8, d, 4, 0.1, None) == binding.E_ARG  # pitch < cin
+    assert bdf(a, 16, 1, 8, 8, 16, b, 8, c, 8, vp(d.value + 2), 8, 0.1, None) == binding.E_ARG
+    assert bdf(a, 16, 1, 8, 8, 16, b, 8, c, 8, d, 8, float("nan"), None) == binding.E_ARG
+    assert bdf(a, 16, 1, 8, 8, 16, vp(b.value + 2), 8, c, 8, None, 0, 0.1, None) == binding.E_ARG
+    assert bdf(a, 16, 1, 8192, 8192, 16, b, 8, c, 8, None, 0, 0.1, None) == binding.E_ARG
+    # the pooling and upsampling adjoints through an activation need one
+    assert lib.sur_pool2_backward_act(a, 16, 1, 8, 8, 16, b, 16, 1, None, 16, 0.1,
+                                      None) == binding.E_ARG
+    assert lib.sur_pool2_backward_act(a, 16, 1, 8, 8, 16, b, 16, 1, d, 16, float("inf"),
+                                      None) == binding.E_ARG
+    assert lib.sur_up2_backward_act(a, 16, 1, 4, 4, 16, b, 16, None, 16, 0.1,
+                                    None) == binding.E_ARG
+    assert lib.sur_up2_backward_act(a, 16, 1, 4, 4, 16, b, 16, d, 8, 0.1, None) == binding.E_ARG
+    # weight gradient of an upsampled input: as the forward's checks, plus
+    # the workspace; images under 8 x 32 pixels are left to the caller
+    wu = lib.sur_conv3x3_backward_weight_up
+    ws = lib.sur_conv3x3_backward_weight_workspace(1, 8, 32, 48, 32)
+    wsp = vp(0x500000000)
+    assert wu(a, 16, 16, d, 32, b, 32, 1, 8, 32, 48, 32, c, None, wsp, ws, None) == binding.E_ARG
+    assert wu(a, 32, 32, d, 16, b, 32, 1, 8, 32, 32, 32, c, None, wsp, ws, None) == binding.E_ARG
+    assert wu(a, 32, 32, d, 16, b, 32, 1, 9, 32, 48, 32, c, None, wsp, ws, None) == binding.E_ARG
+    assert wu(a, 32, 32, d, 16, b, 32, 1, 8, 32, 48, 32, c, None, wsp, ws - 1,
+              None) == binding.E_ARG
+    ws6 = lib.sur_conv3x3_backward_weight_workspace(1, 6, 32, 48, 32)
+    assert wu(a, 32, 32, d, 16, b, 32, 1, 6, 32, 48, 32, c, None, wsp, ws6,
+              None) == binding.E_UNSUPPORTED
+    ws16 = lib.sur_conv3x3_backward_weight_workspace(1, 8, 16, 48, 32)
+    assert wu(a, 32, 32, d, 16, b, 32, 1, 8, 16, 48, 32, c, None, wsp, ws16,
+              None) == binding.E_UNSUPPORTED
 
 
 def test_fd4_host_checks(lib):

@@ -148,19 +148,25 @@ def test_conv_forward_up_equals_upsample_then_conv(n, h, w, cu, cs, cout):
     assert torch.equal(y1.view(torch.int16), y2.view(torch.int16))
 
 
-def test_network_forward_with_fused_upsampling_is_bitwise():
-    """Inference's forward pass (decoder convolutions on the half-resolution
-    tensors) equals the training forward pass bit for bit."""
+def test_network_fused_upsampling_is_bitwise():
+    """Decoder convolutions that read the upsampled half-resolution tensor
+    directly (the forward convolution and the weight gradient) give the bits
+    of the explicit upsampled copy: the network's output and every
+    parameter gradient are equal."""
     net = _small_net()
     net._buffers(2, 64, 64)
     x = torch.tensor(RNG.normal(size=(2, 64, 64, 16)), dtype=torch.float32).to(BF).cuda()
     net.x0.copy_(x)
-    a = net.forward_packed().clone()
+    net.dout.copy_(torch.tensor(RNG.normal(size=(2, 64, 64, 16)), dtype=torch.float32).to(BF))
+    a = net.forward_packed(fuse_up=False).clone()
+    assert not any(net._fused_up)
+    net.backward_packed()
+    ga = net.grad.clone()
     b = net.forward_packed(fuse_up=True).clone()
+    assert all(net._fused_up)
+    net.backward_packed()
     assert torch.equal(a, b)
-    # its concatenation buffers are not filled: no backward pass from it
-    with pytest.raises(RuntimeError):
-        net.backward_packed()
+    assert torch.equal(ga, net.grad)
 
 
 @pytest.mark.parametrize("n,h,w,cin,cout", [(1, 9, 7, 24, 48), (2, 16, 40, 40, 24),
@@ -195,6 +201,184 @@ def test_conv_backward_data(n, h, w, cin, cout):
     want = O.conv3x3_bwd_data(dzv, wv)
     scale = O.conv3x3_bwd_data(np.abs(dzv), np.abs(wv))
     check_close(dx.float().cpu().numpy(), want, scale, 2 ** -8, "backward data")
+
+
+def test_flip_weights_of_several_layers():
+    """sur_flip_weights on layers of different shapes in one launch: a
+    permutation, so exact: flipped[i][8 - tap][o] = weight[o][tap][i]."""
+    shapes = [(16, 16), (32, 16), (24, 40), (128, 384), (16, 32)]
+    ws, wvs, fs = [], [], []
+    for cout, cin in shapes:
+        t, v = bf16_array((cout, 9, cin))
+        ws.append(t)
+        wvs.append(v)
+        fs.append(torch.empty((cin, 9, cout), dtype=BF, device="cuda"))
+    m = len(shapes)
+    vp = ctypes.c_void_p
+    st = lib().sur_flip_weights(m, (vp * m)(*[p(t) for t in ws]),
+                                (ctypes.c_int * m)(*[c for c, _ in shapes]),
+                                (ctypes.c_int * m)(*[c for _, c in shapes]),
+                                (vp * m)(*[p(t) for t in fs]), None)
+    assert st == binding.OK
+    torch.cuda.synchronize()
+    for v, f in zip(wvs, fs):
+        want = np.transpose(v[:, ::-1, :], (2, 1, 0))
+        assert np.array_equal(_f64(f), want)
+
+
+# Halo tiles (whole and ragged, one and several channel groups and chunks)
+# and the tiled kernel of small images, which applies the activation's
+# adjoint in a second pass.
+ACT_CASES = [(2, 16, 32, 16, 32), (1, 19, 45, 40, 24), (3, 8, 40, 32, 16), (2, 16, 32, 128, 64),
+             (1, 9, 7, 24, 48), (2, 8, 16, 64, 16)]
+
+
+@pytest.mark.parametrize("n,h,w,cin,cout", ACT_CASES)
+def test_conv_backward_data_through_activation(n, h, w, cin, cout):
+    """sur_conv3x3_backward_data_flipped: without an activation, bit for bit
+    sur_conv3x3_backward_data; with one, bit for bit that followed by
+    sur_leaky_backward, and against the oracle's bwd_data times the
+    activation's derivative. Two BF16 roundings (dX, then slope dX): at most
+    2 u + u^2 of the value, u = 2^-8, where the single rounding of the plain
+    pass is held to u."""
+    print(f"conv bwd-data + activation n={n} {h}x{w} {cin}->{cout}", flush=True)
+    slope = 0.1
+    dz, dzv = bf16_array((n, h, w, cout))
+    wt, wv = bf16_array((cout, 9, cin), scale=1.0 / np.sqrt(9 * cin))
+    pitch = cin + 8
+    act, actv = bf16_array((n, h, w, pitch))  # a channel slice of a wider buffer
+    act_view = p(act, 8)
+    L = lib()
+    flip = torch.empty(cout * 9 * cin + 64, dtype=BF, device="cuda")
+    ref = torch.empty((n, h, w, cin), dtype=BF, device="cuda")
+    assert L.sur_conv3x3_backward_data(p(dz), cout, n, h, w, cout, p(wt), cin, p(ref), cin,
+                                       p(flip), None) == binding.OK
+    ref_plain = ref.clone()
+    vp = ctypes.c_void_p
+    one = ctypes.c_int * 1
+    flipped = torch.empty((cin, 9, cout), dtype=BF, device="cuda")
+    assert L.sur_flip_weights(1, (vp * 1)(p(wt)), one(cout), one(cin), (vp * 1)(p(flipped)),
+                              None) == binding.OK
+    plain = torch.empty_like(ref)
+    assert L.sur_conv3x3_backward_data_flipped(p(dz), cout, n, h, w, cout, p(flipped), cin,
+                                               p(plain), cin, None, 0, 0.0, None) == binding.OK
+    fused = torch.empty((n, h, w, cin + 16), dtype=BF, device="cuda")  # strided output view
+    assert L.sur_conv3x3_backward_data_flipped(p(dz), cout, n, h, w, cout, p(flipped), cin,
+                                               p(fused), cin + 16, act_view, pitch, slope,
+                                               None) == binding.OK
+    assert L.sur_leaky_backward(p(ref), cin, act_view, pitch, p(ref), cin, n * h * w, cin, slope,
+                                None) == binding.OK
+    torch.cuda.synchronize()
+    assert torch.equal(plain, ref_plain)
+    got = fused[..., :cin]
+    assert torch.equal(got, ref), "fused activation adjoint differs from the two calls"
+    a = actv[..., 8:8 + cin]
+    factor = np.where(a > 0, 1.0, slope)
+    want = O.conv3x3_bwd_data(dzv, wv)
+    scale = O.conv3x3_bwd_data(np.abs(dzv), np.abs(wv))
+    check_close(_f64(plain), want, scale, 2 ** -8, "backward data, pre-flipped weights")
+    u = 2.0 ** -8
+    check_close(_f64(got), factor * want, factor * scale * (1 + u) ** 2, 2 * u + u * u,
+                "backward data through the activation")
+
+
+def test_conv_backward_data_flipped_matches_scratch_flip():
+    """Without an activation the pre-flipped entry point gives the bits of
+    sur_conv3x3_backward_data (which flips into its scratch)."""
+    n, h, w, cin, cout = 2, 16, 64, 40, 72
+    dz, _ = bf16_array((n, h, w, cout))
+    wt, _ = bf16_array((cout, 9, cin), scale=0.05)
+    L = lib()
+    flip = torch.empty(cout * 9 * cin + 64, dtype=BF, device="cuda")
+    ref = torch.empty((n, h, w, cin), dtype=BF, device="cuda")
+    assert L.sur_conv3x3_backward_data(p(dz), cout, n, h, w, cout, p(wt), cin, p(ref), cin,
+                                       p(flip), None) == binding.OK
+    vp = ctypes.c_void_p
+    one = ctypes.c_int * 1
+    flipped = torch.empty((cin, 9, cout), dtype=BF, device="cuda")
+    assert L.sur_flip_weights(1, (vp * 1)(p(wt)), one(cout), one(cin), (vp * 1)(p(flipped)),
+                              None) == binding.OK
+    got = torch.empty_like(ref)
+    assert L.sur_conv3x3_backward_data_flipped(p(dz), cout, n, h, w, cout, p(flipped), cin,
+                                               p(got), cin, None, 0, 0.0, None) == binding.OK
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+
+
+def test_pool_up_backward_through_activation():
+    """sur_pool2_backward_act and sur_up2_backward_act: bit for bit the plain
+    adjoint followed by sur_leaky_backward, and against the oracle (two BF16
+    roundings: 2 u + u^2 of the value; FP32 sums: 1e-6 of |terms|)."""
+    n, h, w, c, slope = 2, 8, 12, 24, 0.1
+    u = 2.0 ** -8
+    L = lib()
+    act, actv = bf16_array((n, h, w, c))
+    factor = np.where(actv > 0, 1.0, slope)
+    # pooling adjoint, accumulating into dx
+    dy, dyv = bf16_array((n, h // 2, w // 2, c))
+    dx0, dx0v = bf16_array((n, h, w, c))
+    two = dx0.clone()
+    assert L.sur_pool2_backward(p(dy), c, n, h, w, c, p(two), c, 1, None) == binding.OK
+    assert L.sur_leaky_backward(p(two), c, p(act), c, p(two), c, n * h * w, c, slope,
+                                None) == binding.OK
+    one = dx0.clone()
+    assert L.sur_pool2_backward_act(p(dy), c, n, h, w, c, p(one), c, 1, p(act), c, slope,
+                                    None) == binding.OK
+    torch.cuda.synchronize()
+    assert torch.equal(one, two)
+    want = factor * (dx0v + O.pool2_bwd(dyv))
+    check_close(_f64(one), want, factor * (np.abs(dx0v) + O.pool2_bwd(np.abs(dyv))) * 1e-1,
+                2 * u + u * u, "pooling adjoint through the activation")
+    # upsampling adjoint
+    du, duv = bf16_array((n, 2 * h, 2 * w, c))
+    two = torch.empty((n, h, w, c), dtype=BF, device="cuda")
+    assert L.sur_up2_backward(p(du), c, n, h, w, c, p(two), c, None) == binding.OK
+    assert L.sur_leaky_backward(p(two), c, p(act), c, p(two), c, n * h * w, c, slope,
+                                None) == binding.OK
+    one = torch.empty_like(two)
+    assert L.sur_up2_backward_act(p(du), c, n, h, w, c, p(one), c, p(act), c, slope,
+                                  None) == binding.OK
+    torch.cuda.synchronize()
+    assert torch.equal(one, two)
+    check_close(_f64(one), factor * O.up2_bwd(duv), factor * O.up2_bwd(np.abs(duv)) * 1e-1,
+                2 * u + u * u, "upsampling adjoint through the activation")
+
+
+@pytest.mark.parametrize("n,h,w,cu,cs,cout", [(2, 16, 32, 32, 16, 32), (1, 18, 40, 64, 24, 40),
+                                              (3, 8, 64, 96, 32, 64), (2, 32, 32, 32, 32, 16)])
+def test_conv_backward_weight_up(n, h, w, cu, cs, cout):
+    """sur_conv3x3_backward_weight_up reads [up2(xu), x] without the copy:
+    bit for bit the weight gradient of the materialised concatenation, and
+    against the oracle on it."""
+    print(f"conv bwd-weight up n={n} {h}x{w} {cu}+{cs}->{cout}", flush=True)
+    cin = cu + cs
+    L = lib()
+    lowp = cu + 8
+    low, lowv = bf16_array((n, h // 2, w // 2, lowp))
+    skp = cs + 16
+    skip, skipv = bf16_array((n, h, w, skp))
+    dz, dzv = bf16_array((n, h, w, cout))
+    cat = torch.empty((n, h, w, cin), dtype=BF, device="cuda")
+    assert L.sur_up2(p(low), lowp, n, h // 2, w // 2, cu, p(cat), cin, None) == binding.OK
+    cat[..., cu:] = skip[..., 8:8 + cs]
+    ws_bytes = L.sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    dw_ref = torch.empty((cout, 9, cin), dtype=torch.float32, device="cuda")
+    db_ref = torch.empty(cout, dtype=torch.float32, device="cuda")
+    assert L.sur_conv3x3_backward_weight(p(cat), cin, p(dz), cout, n, h, w, cin, cout, p(dw_ref),
+                                         p(db_ref), p(ws), ws_bytes, None) == binding.OK
+    dw = torch.empty_like(dw_ref)
+    db = torch.empty_like(db_ref)
+    assert L.sur_conv3x3_backward_weight_up(p(low), lowp, cu, p(skip, 8), skp, p(dz), cout, n, h,
+                                            w, cin, cout, p(dw), p(db), p(ws), ws_bytes,
+                                            None) == binding.OK
+    torch.cuda.synchronize()
+    assert torch.equal(dw, dw_ref) and torch.equal(db, db_ref)
+    xv = np.concatenate([O.up2(lowv[..., :cu]), skipv[..., 8:8 + cs]], axis=3)
+    want_w, want_b = O.conv3x3_bwd_weight(xv, dzv)
+    scale_w, scale_b = O.conv3x3_bwd_weight(np.abs(xv), np.abs(dzv))
+    check_close(dw.cpu().numpy(), want_w, scale_w, 1e-6, "backward weight, upsampled input")
+    check_close(db.cpu().numpy(), want_b, scale_b, 1e-6, "bias gradient, upsampled input")
 
 
 # The first six take channel-major planes (images under 8 x 32 pixels); the
@@ -384,14 +568,19 @@ def test_unet_layers_on_their_own_inputs():
       * each convolution's output (2^-8 of the value for BF16 outputs, 1e-6
         for the FP32 last layer, plus 1e-5 of the sum of |terms|), and the
         2 x 2 means fused into it;
-      * each backward step: dZ from the activation's adjoint, the weight and
-        bias gradients (1e-6 + 1e-5 of the term sum) and dX (2^-8 + 1e-5);
+      * each backward step: the weight and bias gradients (1e-6 + 1e-5 of
+        the term sum) and dX (2^-8 + 1e-5), or, where dX is written through
+        the adjoint of the activation that produced the convolution's input,
+        the activation's derivative times dX (two BF16 roundings: 2 u + u^2,
+        u = 2^-8);
       * the wiring between them, walking the oracle's layer list: each
         convolution reads what the previous operations (pooling, upsampling,
         concatenation) make of the recorded outputs, and each backward step
-        receives what the adjoints of those operations make of the recorded
-        dX of the step after it (sums rounded to BF16: 2^-8 of the value plus
-        1e-6 of the sum of |terms|).
+        reads either the very tensor the step after it wrote through the
+        activation's adjoint, or what the adjoints of pooling, upsampling
+        and concatenation make of the recorded dX of the steps after it,
+        times the activation's derivative (sums in FP32, two BF16 roundings:
+        2 u + u^2 of the value plus 1e-6 of the sum of |terms|).
     Nothing accumulates from layer to layer: every check starts from the
     tensors the kernels actually used."""
     rng = np.random.default_rng(21)
@@ -401,6 +590,7 @@ def test_unet_layers_on_their_own_inputs():
     net.x0.copy_(torch.tensor(rng.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF))
     net.record = []
     net.forward_packed()
+    assert all(net._fused_up)  # the decoders read their upsampled inputs directly
     net.dout.copy_(torch.tensor(rng.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF))
     net.backward_packed()
     torch.cuda.synchronize()
@@ -411,6 +601,7 @@ def test_unet_layers_on_their_own_inputs():
     nconv = len(weights)
     assert sorted(fwd) == sorted(bwd) == list(range(nconv))
     slope = net.slope
+    u = 2.0 ** -8
     spec = O.unet_spec(levels=3, base=16, cin=16, cout=16)
 
     for k in range(nconv):
@@ -428,25 +619,27 @@ def test_unet_layers_on_their_own_inputs():
             check_close(_f64(r["pooled"]), O.pool2(y), O.pool2(np.abs(y)) * 1e-1, 2 ** -8,
                         f"pooling fused into conv {k}")
         rb = bwd[k]
-        gy, dz, xb = _f64(rb["gy"]), _f64(rb["dz"]), _f64(rb["x"])
+        dz, xb = _f64(rb["dz"]), _f64(rb["x"])
         assert np.array_equal(xb, x), f"conv {k}: backward read another input than forward"
-        if act:
-            check_close(dz, O.leaky_bwd(gy, _f64(rb["y"]), slope), np.abs(gy) * 1e-1, 2 ** -8,
-                        f"activation adjoint of conv {k}")
-        else:
-            assert np.array_equal(dz, gy)
         want_w, want_b = O.conv3x3_bwd_weight(x, dz)
         scale_w, scale_b = O.conv3x3_bwd_weight(np.abs(x), np.abs(dz))
         cv = net.convs[k]
         check_close(rb["dw"].cpu().numpy().reshape(cv.cout, 9, cv.cin), want_w, scale_w, 1e-6,
                     f"weight gradient of conv {k}")
         check_close(rb["db"].cpu().numpy(), want_b, scale_b, 1e-6, f"bias gradient of conv {k}")
-        if rb["dx"] is not None:
-            check_close(_f64(rb["dx"]), O.conv3x3_bwd_data(dz, W),
-                        O.conv3x3_bwd_data(np.abs(dz), np.abs(W)), 2 ** -8,
-                        f"backward data of conv {k}")
-        else:
+        if rb["dx"] is None:
             assert k == 0
+            continue
+        want_x = O.conv3x3_bwd_data(dz, W)
+        scale_x = O.conv3x3_bwd_data(np.abs(dz), np.abs(W))
+        if rb["act"] is None:
+            check_close(_f64(rb["dx"]), want_x, scale_x, 2 ** -8, f"backward data of conv {k}")
+        else:
+            # the activation is the one that produced this convolution's input
+            assert np.array_equal(_f64(rb["act"]), x) and net.convs[k - 1].act
+            f = np.where(x > 0, 1.0, slope)
+            check_close(_f64(rb["dx"]), f * want_x, f * scale_x * (1 + u) ** 2, 2 * u + u * u,
+                        f"backward data of conv {k} through the activation")
 
     # forward wiring
     hcur, saved, k = _f64(net.x0), {}, 0
@@ -464,27 +657,36 @@ def test_unet_layers_on_their_own_inputs():
             saved[op[1]] = hcur
         elif op[0] == "cat":
             hcur = np.concatenate([hcur, saved[op[1]]], axis=3)
-    # backward wiring
-    g, gs, skip, k = _f64(net.dout), None, {}, nconv
+    # backward wiring; `direct`: g is a tensor a kernel wrote through the
+    # activation's adjoint, which the next convolution must read as it is
+    g, gs, direct, skip, k = _f64(net.dout), None, True, {}, nconv
     for op in reversed(spec):
         if op[0] == "conv":
             k -= 1
-            check_close(_f64(bwd[k]["gy"]), g, 1e-6 * (gs if gs is not None else np.abs(g)),
-                        2 ** -8, f"output gradient of conv {k}")
+            dz = _f64(bwd[k]["dz"])
+            if direct:
+                assert np.array_equal(dz, g), f"conv {k} read another dZ than was written"
+            else:
+                assert net.convs[k].act
+                f = np.where(_f64(fwd[k]["y"]) > 0, 1.0, slope)
+                check_close(dz, f * g, f * 1e-6 * gs, 2 * u + u * u,
+                            f"output gradient of conv {k}")
             g = _f64(bwd[k]["dx"]) if bwd[k]["dx"] is not None else None
-            gs = None
+            direct, gs = bwd[k]["act"] is not None, None
         elif op[0] == "pool":
-            g = O.pool2_bwd(g)
+            gs, g, direct = O.pool2_bwd(np.abs(g)), O.pool2_bwd(g), False
         elif op[0] == "up":
-            gs = O.up2_bwd(np.abs(g))
-            g = O.up2_bwd(g)
+            gs, g, direct = O.up2_bwd(np.abs(g)), O.up2_bwd(g), False
         elif op[0] == "cat":
+            assert not direct
             c_up = g.shape[3] - saved[op[1]].shape[3]
             skip[op[1]] = g[..., c_up:]
             g = g[..., :c_up]
+            gs = None if gs is None else gs[..., :c_up]
         elif op[0] == "save" and op[1] in skip:
-            gs = np.abs(g) + np.abs(skip[op[1]])
+            gs = (np.abs(g) if gs is None else gs) + np.abs(skip[op[1]])
             g = g + skip.pop(op[1])
+            direct = False
     assert k == 0 and not skip
 
 
