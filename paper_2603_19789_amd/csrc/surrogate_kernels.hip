@@ -320,9 +320,14 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     const int G = gridDim.x;
     if ((int)blockIdx.x >= units)
         return;  // whole workgroup, before any barrier
+    // Workgroup b runs on XCD b % 8, each with its own L2: consecutive units
+    // (the channel groups of a tile, then neighbouring tiles, which share
+    // halo pixels) are given to the workgroups of one XCD.
+    const int vb = G % 8 == 0 && G <= units ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8)
+                                            : (int)blockIdx.x;
     const int groups = (a.cout + TC - 1) / TC;
     const int nck = (a.cin + 31) / 32;
-    const int items = ((units - 1 - (int)blockIdx.x) / G + 1) * nck;
+    const int items = ((units - 1 - vb) / G + 1) * nck;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
     const long long P = (long long)a.n * a.h * a.w;
@@ -583,7 +588,7 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
         }
     };
 
-    int unit = blockIdx.x, chunk = 0;
+    int unit = vb, chunk = 0;
     unit_offsets(unit);
     Stage st = gload(0, true);
     lstore(st, true);
@@ -924,7 +929,13 @@ void conv_wgrad_halo_kernel(WgradHaloArgs a) {
     uint16_t *const Xs = lds + WH_TH * WH_TW * WH_PZ;
     constexpr unsigned OUT_OF_RANGE = 0x80000000u;
     const int blocks = a.nob * a.nib;
-    const int blk = blockIdx.x % blocks, kb = blockIdx.x / blocks;
+    // Workgroup b runs on XCD b % 8, each with its own L2: the channel
+    // blocks of one split (which read the same tiles) are given to the
+    // workgroups of one XCD.
+    const int nwg = gridDim.x;
+    const int vb = nwg % 8 == 0 ? (int)(blockIdx.x % 8) * (nwg / 8) + (int)(blockIdx.x / 8)
+                                : (int)blockIdx.x;
+    const int blk = vb % blocks, kb = vb / blocks;
     const int ob = blk / a.nib, ib = blk - (blk / a.nib) * a.nib;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
