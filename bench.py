@@ -592,8 +592,10 @@ def main():
 
     results = []
     for s, d, r in variants:
-        # BGK is 4x the traffic per step: keep its timed work comparable
-        steps = args.steps if s == "sslbm" else max(2, args.steps // 4)
+        # BGK is 4x the traffic per step: keep its timed work comparable, and
+        # even (bgk_run works in place: an odd count ends with a copy of the
+        # whole distribution state back into the caller's buffer)
+        steps = args.steps if s == "sslbm" else 2 * max(1, (args.steps + 7) // 8)
         res = run_variant(torch, s, d, r, steps, args.warmup, inputs, Solver, BGK)
         results.append(res)
         print(f"# {s} {d} R0={r:g}: {res['glups']:.1f} GLUPS, {res['steps_per_pass']} steps/pass "

@@ -192,7 +192,9 @@ int sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int 
  * call returns SSLBM_E_UNSUPPORTED when d[4] != 0.
  *   bgk_init:    f_i = w_i rho (equilibrium start), rhoD = rho[D].
  *   bgk_step:    one step, f_in/rhoD_in -> f_out/rhoD_out (no overlap).
- *   bgk_run:     nsteps steps in place in f/rhoD, using same-size scratch.
+ *   bgk_run:     nsteps steps in place in f/rhoD, using same-size scratch
+ *                (the steps alternate between the two; an odd nsteps ends
+ *                with a copy of the state from the scratch into f/rhoD).
  *   bgk_density: rho[C] = sum_i f_i for S, E, I, R and rho[D] = rhoD.
  */
 int bgk_init(sslbm_ctx *c, const void *rho, void *f, void *rhoD, void *hip_stream);
