@@ -120,6 +120,22 @@ int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const v
                                    int cin, int cout, float *dweight, float *dbias,
                                    void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* The weight gradient of sur_conv3x3_backward_weight (xu NULL, cu 0) or of
+ * sur_conv3x3_backward_weight_up (xu not NULL), in two stream-ordered parts
+ * so that the second overlaps the caller's later work: the per-split
+ * partial sums are computed on hip_stream into the workspace; then `event`
+ * (a hipEvent_t as void*, created by the caller) is recorded on hip_stream,
+ * sum_stream waits for it, and the fixed-order sums over the splits that
+ * write dweight and dbias run on sum_stream. The same bits as the one-stream
+ * call. dweight, dbias and the workspace belong to the call until the
+ * caller has waited for sum_stream; each call in flight needs its own
+ * workspace. sum_stream may equal hip_stream (then event may be NULL). */
+int sur_conv3x3_backward_weight_overlap(const void *xu, int xu_pitch, int cu, const void *x,
+                                        int x_pitch, const void *dz, int dz_pitch, int n, int h,
+                                        int w, int cin, int cout, float *dweight, float *dbias,
+                                        void *workspace, size_t workspace_bytes,
+                                        void *hip_stream, void *sum_stream, void *event);
+
 /* dz = y > 0 ? dy : slope dy over `pixels` pixels of c channels (y is the
  * activation's output). dz may alias dy. */
 int sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,

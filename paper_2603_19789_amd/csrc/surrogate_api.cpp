@@ -251,7 +251,33 @@ int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int 
     if (workspace_bytes < sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout))
         return SSLBM_E_ARG;
     return status(sslbm::launch_wgrad(x, x_pitch, nullptr, 0, 0, dz, dz_pitch, n, h, w, cin, cout,
-                                      dweight, dbias, workspace, (hipStream_t)hip_stream));
+                                      dweight, dbias, workspace, (hipStream_t)hip_stream,
+                                      (hipStream_t)hip_stream, nullptr));
+}
+
+int sur_conv3x3_backward_weight_overlap(const void *xu, int xu_pitch, int cu, const void *x,
+                                        int x_pitch, const void *dz, int dz_pitch, int n, int h,
+                                        int w, int cin, int cout, float *dweight, float *dbias,
+                                        void *workspace, size_t workspace_bytes,
+                                        void *hip_stream, void *sum_stream, void *event) {
+    const int cx = xu ? cin - cu : cin;  // channels read from x
+    if (!view_ok(x, x_pitch, cx) || !view_ok(dz, dz_pitch, cout) || !dims_ok(n, h, w) ||
+        w % 8 || !dweight || !workspace || !aligned16(workspace) || cin > MAX_CHANNELS ||
+        !conv_input_fits(x_pitch, n, h, w, cx) || !conv_input_fits(dz_pitch, n, h, w, cout) ||
+        (sum_stream != hip_stream && !event))
+        return SSLBM_E_ARG;
+    if (xu && (cu <= 0 || cu % 32 || cin <= cu || !view_ok(xu, xu_pitch, cu) || h % 2 ||
+               !conv_input_fits(xu_pitch, n, h / 2, w / 2, cu)))
+        return SSLBM_E_ARG;
+    if (!xu && cu != 0)
+        return SSLBM_E_ARG;
+    if (workspace_bytes < sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout))
+        return SSLBM_E_ARG;
+    if (xu && (h < 8 || w < 32))
+        return SSLBM_E_UNSUPPORTED;  // needs the halo-tile kernel
+    return status(sslbm::launch_wgrad(x, x_pitch, xu, xu_pitch, cu, dz, dz_pitch, n, h, w, cin,
+                                      cout, dweight, dbias, workspace, (hipStream_t)hip_stream,
+                                      (hipStream_t)sum_stream, (hipEvent_t)event));
 }
 
 int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const void *x,
@@ -270,7 +296,8 @@ int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const v
     if (h < 8 || w < 32)
         return SSLBM_E_UNSUPPORTED;  // needs the halo-tile kernel
     return status(sslbm::launch_wgrad(x, x_pitch, xu, xu_pitch, cu, dz, dz_pitch, n, h, w, cin,
-                                      cout, dweight, dbias, workspace, (hipStream_t)hip_stream));
+                                      cout, dweight, dbias, workspace, (hipStream_t)hip_stream,
+                                      (hipStream_t)hip_stream, nullptr));
 }
 
 int sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,

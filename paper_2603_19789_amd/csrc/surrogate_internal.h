@@ -85,10 +85,12 @@ hipError_t launch_flip(const void *w, int cout, int cin, void *wf, hipStream_t s
 hipError_t launch_flip_multi(const FlipTable &t, hipStream_t s);
 WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout);
 // xu: null, or the half-resolution view of input channels [0, cu) (images
-// of at least 8 x 32 pixels; hipErrorNotSupported otherwise)
+// of at least 8 x 32 pixels; hipErrorNotSupported otherwise). The partial
+// sums are computed on s; the sums over the splits run on sum_s, after s
+// reaches them (ev recorded on s; unused when sum_s is s).
 hipError_t launch_wgrad(const void *x, int xp, const void *xu, int xup, int cu, const void *dz,
                         int dzp, int n, int h, int w, int cin, int cout, float *dw, float *db,
-                        void *ws, hipStream_t s);
+                        void *ws, hipStream_t s, hipStream_t sum_s, hipEvent_t ev);
 hipError_t launch_leaky_bwd(const void *dy, int dyp, const void *y, int yp, void *dz, int dzp,
                             long long pixels, int c, float slope, hipStream_t s);
 hipError_t launch_pool2(const void *x, int xp, int n, int h, int w, int c, void *y, int yp,

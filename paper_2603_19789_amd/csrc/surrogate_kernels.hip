@@ -1732,9 +1732,18 @@ WgradPlan wgrad_plan(int n, int h, int w, int cin, int cout) {
 
 hipError_t launch_wgrad(const void *x, int xp, const void *xu, int xup, int cu, const void *dz,
                         int dzp, int n, int h, int w, int cin, int cout, float *dw, float *db,
-                        void *ws, hipStream_t s) {
+                        void *ws, hipStream_t s, hipStream_t sum_s, hipEvent_t ev) {
     const WgradPlan p = wgrad_plan(n, h, w, cin, cout);
     const long long count = (long long)cout * 9 * cin;
+    // the sums of the splits go on sum_s once the partials on s are written
+    auto hand_over = [&]() -> hipError_t {
+        if (sum_s == s)
+            return hipSuccess;
+        hipError_t e = hipEventRecord(ev, s);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(sum_s, ev, 0);
+        return e;
+    };
     if (xu && !p.halo)
         return hipErrorNotSupported;  // the upsampled input needs halo tiles
     if (p.halo) {
@@ -1762,7 +1771,10 @@ hipError_t launch_wgrad(const void *x, int xp, const void *xu, int xup, int cu, 
         a.cu = xu ? cu : 0;
         hipLaunchKernelGGL(conv_wgrad_halo_kernel, dim3((unsigned)(p.nob * p.nib * p.gb)),
                            dim3(THREADS), 0, s, a);
-        reduce_splits(part, p.splits, count, dw, a.part_b, cout, db, s);
+        const hipError_t e = hand_over();
+        if (e != hipSuccess)
+            return e;
+        reduce_splits(part, p.splits, count, dw, a.part_b, cout, db, sum_s);
         return hipGetLastError();
     }
     uint16_t *dz_t = static_cast<uint16_t *>(ws);
@@ -1798,13 +1810,16 @@ hipError_t launch_wgrad(const void *x, int xp, const void *xu, int xup, int cu, 
         hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(THREADS), 0, s, a);
     else
         hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(THREADS), 0, s, a);
-    reduce_splits(part, p.splits, count, dw, nullptr, 0, nullptr, s);
+    const hipError_t e = hand_over();
+    if (e != hipSuccess)
+        return e;
+    reduce_splits(part, p.splits, count, dw, nullptr, 0, nullptr, sum_s);
     if (db) {
         // the bias partials reuse the start of the (already reduced) partials buffer
         hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)cout, BIAS_SLICES), dim3(THREADS), 0,
-                           s, dz_t, p.Pp, part);
+                           sum_s, dz_t, p.Pp, part);
         hipLaunchKernelGGL(bias_sum_kernel, dim3((unsigned)((cout + THREADS - 1) / THREADS)),
-                           dim3(THREADS), 0, s, part, cout, db);
+                           dim3(THREADS), 0, sum_s, part, cout, db);
     }
     return hipGetLastError();
 }

@@ -96,10 +96,14 @@ class UNet:
     """The surrogate network: parameters (FP32 master, BF16 copy), Adam
     state, and the forward and backward passes over a batch."""
 
-    def __init__(self, levels: int = 4, base: int = 32, slope: float = 0.1, seed: int = 0):
+    def __init__(self, levels: int = 4, base: int = 32, slope: float = 0.1, seed: int = 0,
+                 overlap_sums: bool = True):
         torch = _torch()
         self.lib = library()
         self.levels, self.base, self.slope = levels, base, slope
+        # the weight gradients' split sums on a second stream (True), or on
+        # the pass's own stream (False); the same bits either way
+        self.overlap_sums = overlap_sums
         self.ch = [base * 2 ** l for l in range(levels)]
         convs = []
         c = IN_CHANNELS
@@ -174,6 +178,9 @@ class UNet:
     # ------------------------------------------------------------ buffers --
     _BUFFER_NAMES = ("x0", "a", "pool", "cat", "e_last", "b", "hdec", "out", "g_cat", "g_l",
                      "g_l2", "g_pool", "g_e_last", "dout", "wgrad_ws", "dims")
+    # The backward pass runs the sums of each weight gradient's splits on a
+    # second stream (default priority), overlapped with the rest of the
+    # pass: every convolution has its own workspace and event for that.
 
     def _buffers(self, n, h, w):
         """Make the buffers of batch n at h x w current. Each shape's set is
@@ -211,11 +218,7 @@ class UNet:
         self.g_pool = [None] + [mk(l, ch[l - 1]) for l in range(1, L)]
         self.g_e_last = mk(L - 1, ch[L - 1])
         self.dout = torch.empty((n, h, w, OUT_CHANNELS), dtype=bf, device="cuda")
-        ws = 0
-        for cv, l in self._levels_of_convs():
-            ws = max(ws, self.lib.sur_conv3x3_backward_weight_workspace(
-                n, dims[l][0], dims[l][1], cv.cin, cv.cout))
-        self.wgrad_ws = torch.empty(ws, dtype=torch.uint8, device="cuda")
+        self.wgrad_ws = None  # per-convolution workspaces, made by the first backward pass
         self.dims = dims
         self._shape = (n, h, w)
         self._sets[(n, h, w)] = tuple(getattr(self, name) for name in self._BUFFER_NAMES)
@@ -306,7 +309,7 @@ class UNet:
     # ----------------------------------------------------------- backward --
     def _flip_weights(self):
         """The backward-data weights of every convolution from theta_bf16,
-        in one launch per 32 convolutions."""
+        in one launch per 32 convolutions, on the side stream."""
         vp = ctypes.c_void_p
         for k0 in range(0, len(self.convs), 32):
             cvs = self.convs[k0:k0 + 32]
@@ -315,31 +318,50 @@ class UNet:
             f = (vp * m)(*[_ptr(self.flipped, cv.f_off) for cv in cvs])
             co = (ctypes.c_int * m)(*[cv.cout for cv in cvs])
             ci = (ctypes.c_int * m)(*[cv.cin for cv in cvs])
-            _check(self.lib.sur_flip_weights(m, w, co, ci, f, None), "sur_flip_weights")
+            _check(self.lib.sur_flip_weights(m, w, co, ci, f, vp(self._side.cuda_stream)),
+                   "sur_flip_weights")
+
+    def _backward_setup(self):
+        """The per-convolution weight-gradient workspaces of the current
+        shape, the side stream and the events (created on first use)."""
+        torch = _torch()
+        if getattr(self, "_side", None) is None:
+            self._side = torch.cuda.Stream()
+            self._events = [torch.cuda.Event() for _ in self.convs]
+            self._flip_done = torch.cuda.Event()
+            for ev in self._events + [self._flip_done]:
+                ev.record(torch.cuda.default_stream())  # creates the event
+        if self.wgrad_ws is None:
+            n = self._shape[0]
+            self.wgrad_ws = [
+                torch.empty(self.lib.sur_conv3x3_backward_weight_workspace(
+                    n, self.dims[l][0], self.dims[l][1], cv.cin, cv.cout),
+                    dtype=torch.uint8, device="cuda")
+                for cv, l in self._levels_of_convs()]
+            self._sets[self._shape] = tuple(getattr(self, name) for name in self._BUFFER_NAMES)
 
     def _conv_backward(self, k, x, dz: _View, gx, act, l):
         """Gradients of conv k from dz (the gradient of its pre-activation
-        output): weight and bias gradients into self.grad, and dX into view
-        gx unless gx is None, through the adjoint of the activation whose
-        output is `act` (the convolution's own input) when act is not None.
-        x: the input view, or (low, skip) for a decoder convolution that
-        read its upsampled input directly."""
+        output): weight and bias gradients into self.grad (their split sums
+        on the side stream), and dX into view gx unless gx is None, through
+        the adjoint of the activation whose output is `act` (the
+        convolution's own input) when act is not None. x: the input view,
+        or (low, skip) for a decoder convolution that read its upsampled
+        input directly."""
         cv = self.convs[k]
         lib = self.lib
         n = self._shape[0]
         hh, ww = self.dims[l]
-        ws = self.wgrad_ws
+        ws = self.wgrad_ws[k]
         dw, db = _ptr(self.grad, cv.w_off), _ptr(self.grad, cv.b_off)
-        if isinstance(x, tuple):
-            low, skip = x
-            _check(lib.sur_conv3x3_backward_weight_up(
-                low.ptr, low.pitch, low.c, skip.ptr, skip.pitch, dz.ptr, dz.pitch, n, hh, ww,
-                cv.cin, cv.cout, dw, db, _ptr(ws), ws.numel(), None),
-                "sur_conv3x3_backward_weight_up")
-        else:
-            _check(lib.sur_conv3x3_backward_weight(
-                x.ptr, x.pitch, dz.ptr, dz.pitch, n, hh, ww, cv.cin, cv.cout, dw, db, _ptr(ws),
-                ws.numel(), None), "sur_conv3x3_backward_weight")
+        low, skip = x if isinstance(x, tuple) else (None, x)
+        vp = ctypes.c_void_p
+        _check(lib.sur_conv3x3_backward_weight_overlap(
+            None if low is None else low.ptr, 0 if low is None else low.pitch,
+            0 if low is None else low.c, skip.ptr, skip.pitch, dz.ptr, dz.pitch, n, hh, ww,
+            cv.cin, cv.cout, dw, db, _ptr(ws), ws.numel(), None,
+            vp(self._side.cuda_stream) if self.overlap_sums else None,
+            vp(self._events[k].cuda_event)), "sur_conv3x3_backward_weight_overlap")
         if gx is not None:
             _check(lib.sur_conv3x3_backward_data_flipped(
                 dz.ptr, dz.pitch, n, hh, ww, cv.cout, _ptr(self.flipped, cv.f_off), cv.cin,
@@ -347,6 +369,7 @@ class UNet:
                 0 if act is None else act.pitch, self.slope, None),
                 "sur_conv3x3_backward_data_flipped")
         if self.record is not None:
+            _torch().cuda.default_stream().wait_stream(self._side)  # dW, db written
             self.record.append({
                 "pass": "backward", "k": k,
                 "x": _up_cat_copy(*x) if isinstance(x, tuple) else _copy(x),
@@ -365,7 +388,15 @@ class UNet:
             raise RuntimeError("backward_packed needs a preceding forward_packed() on this shape")
         L, ch, lib = self.levels, self.ch, self.lib
         n = self._shape[0]
+        torch = _torch()
+        main = torch.cuda.default_stream()  # the stream of every library call here
+        self._backward_setup()
+        # the side stream starts after everything before (theta_bf16 from
+        # the last Adam step); the first backward-data waits for the flip
+        self._side.wait_stream(main)
         self._flip_weights()
+        self._flip_done.record(self._side)
+        main.wait_event(self._flip_done)
         k = len(self.convs) - 1
         # output layer (no activation: dZ = dout); its input is the last
         # activation's output
@@ -409,6 +440,7 @@ class UNet:
             src = _View(self.x0, 0, IN_CHANNELS) if l == 0 else _View(self.pool[l], 0, ch[l - 1])
             g_src = None if l == 0 else _View(self.g_pool[l], 0, ch[l - 1])
             self._conv_backward(k1, src, g_a, g_src, None, l)
+        main.wait_stream(self._side)  # self.grad complete; workspaces free
 
     def adam(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
         self.step_count += 1

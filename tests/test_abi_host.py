@@ -320,6 +320,17 @@ def test_surrogate_header_exports_and_host_checks(lib):
     ws16 = lib.sur_conv3x3_backward_weight_workspace(1, 8, 16, 48, 32)
     assert wu(a, 32, 32, d, 16, b, 32, 1, 8, 16, 48, 32, c, None, wsp, ws16,
               None) == binding.E_UNSUPPORTED
+    # the split sums on another stream need an event; cu goes with xu
+    wo = lib.sur_conv3x3_backward_weight_overlap
+    st2 = vp(0x700000000)
+    assert wo(None, 0, 0, d, 48, b, 32, 1, 8, 32, 48, 32, c, None, wsp, ws, None, st2,
+              None) == binding.E_ARG
+    assert wo(None, 0, 32, d, 48, b, 32, 1, 8, 32, 48, 32, c, None, wsp, ws, None, None,
+              None) == binding.E_ARG
+    assert wo(a, 32, 16, d, 32, b, 32, 1, 8, 32, 48, 32, c, None, wsp, ws, None, None,
+              None) == binding.E_ARG
+    assert wo(a, 32, 32, d, 16, b, 32, 1, 6, 32, 48, 32, c, None, wsp, ws6, None, None,
+              None) == binding.E_UNSUPPORTED
 
 
 def test_fd4_host_checks(lib):

@@ -344,6 +344,28 @@ def test_pool_up_backward_through_activation():
                 2 * u + u * u, "upsampling adjoint through the activation")
 
 
+def test_network_gradients_with_overlapped_split_sums_are_bitwise():
+    """The weight gradients' split sums on a second stream (the default) give
+    the network's parameter gradients bit for bit as on one stream, over two
+    passes in a row (the workspaces and events are reused)."""
+    net = _small_net()
+    net._buffers(2, 64, 64)
+    for rep in range(2):
+        x = torch.tensor(RNG.normal(size=(2, 64, 64, 16)), dtype=torch.float32).to(BF)
+        g = torch.tensor(RNG.normal(size=(2, 64, 64, 16)), dtype=torch.float32).to(BF)
+        grads = []
+        for overlap in (True, False):
+            net.overlap_sums = overlap
+            net.x0.copy_(x)
+            net.dout.copy_(g)
+            net.grad.fill_(12345.0)  # padding between blocks keeps it in both
+            net.forward_packed()
+            net.backward_packed()
+            grads.append(net.grad.clone())
+        torch.cuda.synchronize()
+        assert torch.equal(grads[0], grads[1]), rep
+
+
 @pytest.mark.parametrize("n,h,w,cu,cs,cout", [(2, 16, 32, 32, 16, 32), (1, 18, 40, 64, 24, 40),
                                               (3, 8, 64, 96, 32, 64), (2, 32, 32, 32, 32, 16)])
 def test_conv_backward_weight_up(n, h, w, cu, cs, cout):
@@ -416,6 +438,45 @@ def test_conv_backward_weight(n, h, w, cin, cout):
     lib().sur_conv3x3_backward_weight(p(buf), pitch, p(dz), cout, n, h, w, cin, cout, p(dw2),
                                       None, p(ws), ws_bytes, None)
     assert torch.equal(dw, dw2)
+
+
+@pytest.mark.parametrize("n,h,w,cin,cout,cu", [(2, 16, 32, 16, 32, 0), (1, 19, 40, 40, 24, 0),
+                                                (2, 8, 16, 64, 128, 0), (2, 16, 32, 48, 32, 32)])
+def test_conv_backward_weight_overlap_on_a_second_stream(n, h, w, cin, cout, cu):
+    """sur_conv3x3_backward_weight_overlap with the split sums on another
+    stream gives the bits of the one-stream call (halo tiles, the
+    channel-major path of small images, and an upsampled input)."""
+    print(f"conv bwd-weight overlap n={n} {h}x{w} {cin}->{cout} cu={cu}", flush=True)
+    L = lib()
+    dz, _ = bf16_array((n, h, w, cout))
+    ws_bytes = L.sur_conv3x3_backward_weight_workspace(n, h, w, cin, cout)
+    ws1 = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    ws2 = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    dw1 = torch.empty((cout, 9, cin), dtype=torch.float32, device="cuda")
+    db1 = torch.empty(cout, dtype=torch.float32, device="cuda")
+    dw2, db2 = torch.full_like(dw1, float("nan")), torch.full_like(db1, float("nan"))
+    side = torch.cuda.Stream()
+    ev = torch.cuda.Event()
+    ev.record(torch.cuda.default_stream())
+    vp = ctypes.c_void_p
+    if cu:
+        low, _ = bf16_array((n, h // 2, w // 2, cu))
+        skip, _ = bf16_array((n, h, w, cin - cu))
+        assert L.sur_conv3x3_backward_weight_up(p(low), cu, cu, p(skip), cin - cu, p(dz), cout, n,
+                                                h, w, cin, cout, p(dw1), p(db1), p(ws1),
+                                                ws_bytes, None) == binding.OK
+        args = (p(low), cu, cu, p(skip), cin - cu)
+    else:
+        x, _ = bf16_array((n, h, w, cin))
+        assert L.sur_conv3x3_backward_weight(p(x), cin, p(dz), cout, n, h, w, cin, cout, p(dw1),
+                                             p(db1), p(ws1), ws_bytes, None) == binding.OK
+        args = (None, 0, 0, p(x), cin)
+    assert L.sur_conv3x3_backward_weight_overlap(*args, p(dz), cout, n, h, w, cin, cout, p(dw2),
+                                                 p(db2), p(ws2), ws_bytes, None,
+                                                 vp(side.cuda_stream), vp(ev.cuda_event)) == binding.OK
+    torch.cuda.default_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert torch.equal(dw1, dw2) and torch.equal(db1, db2)
 
 
 def test_pool_up_leaky():
