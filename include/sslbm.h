@@ -99,6 +99,32 @@ int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_p
 int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p);
 
 /*
+ * The parameter struct from rates stated as (beta, sigma, gamma, mu): beta
+ * contact rate, sigma = 1 / incubation period, gamma recovery rate, mu
+ * death rate. The paper's Eq. (sources) has alpha = sigma, a removal rate
+ * gamma_paper = gamma + mu and a fatality ratio phi = mu / (gamma + mu).
+ * d, dx, dt are copied as given. Host only. SSLBM_E_ARG: out or d null, a
+ * rate negative or not finite, or gamma + mu not > 0. The result still goes
+ * through sslbm_init's validation.
+ */
+int sslbm_params_from_rates(double beta, double sigma, double gamma, double mu, const double d[5],
+                            double dx, double dt, sslbm_params *out);
+
+/*
+ * Gradients with respect to (beta, sigma, gamma, mu) from those with
+ * respect to (beta, alpha, gamma_paper, phi), the first four of the nine
+ * that sslbm_adjoint_run returns, by the chain rule of the mapping above at
+ * the given gamma and mu:
+ *   dL/dsigma = dL/dalpha,
+ *   dL/dgamma = dL/dgamma_paper - dL/dphi mu / (gamma + mu)^2,
+ *   dL/dmu    = dL/dgamma_paper + dL/dphi gamma / (gamma + mu)^2.
+ * grad_rates may alias grad_params. Host only. SSLBM_E_ARG: a null pointer,
+ * gamma or mu negative or not finite, or gamma + mu not > 0.
+ */
+int sslbm_rate_gradients(const double grad_params[4], double gamma, double mu,
+                         double grad_rates[4]);
+
+/*
  * Blocking depth: the number of time steps sslbm_run advances per pass over
  * HBM (each pass reads and writes the five fields once). 0 restores the
  * automatic choice. Allowed range 0..SSLBM_MAX_BLOCKING; results are bit for

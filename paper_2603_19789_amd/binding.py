@@ -165,6 +165,12 @@ def library() -> ctypes.CDLL:
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.sslbm_params_from_rates.argtypes = [ctypes.c_double] * 4 + [dp, ctypes.c_double,
+                                                                        ctypes.c_double, pp]
+        lib.sslbm_params_from_rates.restype = ctypes.c_int
+        lib.sslbm_rate_gradients.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
+        lib.sslbm_rate_gradients.restype = ctypes.c_int
         lib.sslbm_strerror.restype = ctypes.c_char_p
         lib.sslbm_destroy.argtypes = [vp]
         lib.sslbm_destroy.restype = None

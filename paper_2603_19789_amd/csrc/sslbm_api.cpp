@@ -215,6 +215,45 @@ int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_p
     return SSLBM_OK;
 }
 
+int sslbm_params_from_rates(double beta, double sigma, double gamma, double mu, const double d[5],
+                            double dx, double dt, sslbm_params *out) {
+    const double rates[4] = {beta, sigma, gamma, mu};
+    if (!out || !d)
+        return SSLBM_E_ARG;
+    for (double r : rates)
+        if (!std::isfinite(r) || r < 0.0)
+            return SSLBM_E_ARG;
+    const double removal = gamma + mu;
+    if (!(removal > 0.0))
+        return SSLBM_E_ARG;
+    sslbm_params p;
+    p.beta = beta;
+    p.alpha = sigma;
+    p.gamma = removal;
+    p.phi = mu / removal;
+    for (int c = 0; c < 5; ++c)
+        p.d[c] = d[c];
+    p.dx = dx;
+    p.dt = dt;
+    *out = p;
+    return SSLBM_OK;
+}
+
+int sslbm_rate_gradients(const double grad_params[4], double gamma, double mu,
+                         double grad_rates[4]) {
+    if (!grad_params || !grad_rates || !std::isfinite(gamma) || !std::isfinite(mu) ||
+        gamma < 0.0 || mu < 0.0 || !(gamma + mu > 0.0))
+        return SSLBM_E_ARG;
+    const double removal = gamma + mu, r2 = removal * removal;
+    const double g_beta = grad_params[0], g_alpha = grad_params[1];
+    const double g_removal = grad_params[2], g_phi = grad_params[3];
+    grad_rates[0] = g_beta;
+    grad_rates[1] = g_alpha;
+    grad_rates[2] = g_removal - g_phi * (mu / r2);
+    grad_rates[3] = g_removal + g_phi * (gamma / r2);
+    return SSLBM_OK;
+}
+
 int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p) {
     if (!c)
         return SSLBM_E_ARG;

@@ -5,6 +5,7 @@ import math
 import re
 from pathlib import Path
 
+import numpy as np
 import pytest
 
 from paper_2603_19789_amd import binding
@@ -470,3 +471,51 @@ def test_noalloc_adjoint_step_limit_before_any_device_call(lib):
         assert lib.sslbm_adjoint_step_noalloc(None, a, b, c, g, None) == binding.E_ARG
     finally:
         lib.sslbm_destroy(h)
+
+
+def test_rate_notation_helpers(lib):
+    """sslbm_params_from_rates builds the paper's (beta, alpha, gamma, phi)
+    from (beta, sigma, gamma, mu) as inputs.from_sigma_mu does, and
+    sslbm_rate_gradients is the chain rule of that map: checked against
+    central differences of a linear functional of the mapped parameters."""
+    from paper_2603_19789_amd import inputs
+    dp = ctypes.POINTER(ctypes.c_double)
+    d = (ctypes.c_double * 5)(1e-3, 2e-3, 3e-3, 4e-3, 0.0)
+    out = binding.Params()
+    rates = (0.55, 0.2, 0.1, 0.01)
+    assert lib.sslbm_params_from_rates(*rates, d, 1.0, 0.01, ctypes.byref(out)) == binding.OK
+    ref = inputs.from_sigma_mu(*rates, (0.0,) * 5)
+    assert (out.beta, out.alpha, out.gamma) == (ref.beta, ref.alpha, ref.gamma)
+    assert out.phi == pytest.approx(ref.phi, rel=1e-15)
+    assert list(out.d) == list(d) and (out.dx, out.dt) == (1.0, 0.01)
+    for bad in ((-0.1, 0.2, 0.1, 0.01), (0.5, float("nan"), 0.1, 0.01), (0.5, 0.2, 0.0, 0.0)):
+        assert lib.sslbm_params_from_rates(*bad, d, 1.0, 0.01, ctypes.byref(out)) == binding.E_ARG
+    assert lib.sslbm_params_from_rates(*rates, None, 1.0, 0.01, ctypes.byref(out)) == binding.E_ARG
+
+    def mapped(b, s, g, m):
+        p = binding.Params()
+        assert lib.sslbm_params_from_rates(b, s, g, m, d, 1.0, 0.01, ctypes.byref(p)) == 0
+        return np.array([p.beta, p.alpha, p.gamma, p.phi])
+
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        r = rng.uniform(0.05, 0.6, 4)
+        gp = rng.normal(size=4)
+        fd = np.empty(4)
+        for i in range(4):
+            h = 1e-6 * r[i]
+            up, dn = r.copy(), r.copy()
+            up[i] += h
+            dn[i] -= h
+            fd[i] = (gp @ mapped(*up) - gp @ mapped(*dn)) / (2 * h)
+        gin = (ctypes.c_double * 4)(*gp)
+        gout = (ctypes.c_double * 4)()
+        assert lib.sslbm_rate_gradients(gin, r[2], r[3], gout) == binding.OK
+        assert np.allclose(list(gout), fd, rtol=1e-7, atol=1e-9)
+        # in place
+        assert lib.sslbm_rate_gradients(gin, r[2], r[3], gin) == binding.OK
+        assert list(gin) == list(gout)
+    gin = (ctypes.c_double * 4)(1, 2, 3, 4)
+    assert lib.sslbm_rate_gradients(gin, -1.0, 0.1, gin) == binding.E_ARG
+    assert lib.sslbm_rate_gradients(gin, 0.0, 0.0, gin) == binding.E_ARG
+    assert lib.sslbm_rate_gradients(None, 0.1, 0.1, gin) == binding.E_ARG
