@@ -259,7 +259,9 @@ def run_adjoint(torch, inputs, Solver, steps, every=100):
     compartments diffusing, J = 1/2 |I_T - I*|^2 + 1/2 |D_T - D*|^2 against a
     target made with perturbed rates): the checkpointed forward run, then the
     reverse sweep (segment recomputation + adjoint steps), timed with HIP
-    events; plus the adjoint step alone, for its bandwidth."""
+    events, at a checkpoint every `every` steps and again with a checkpoint
+    every 2 steps (every state the reverse sweep reads stored in HBM: no
+    recomputation); plus the adjoint step alone, for its bandwidth."""
     w = inputs.c4_workload(nsteps=steps)
     s = Solver(w.nx, w.ny, inputs.c4_target_params(), dtype="f64")
     rho0 = torch.tensor(w.rho0, dtype=torch.float64, device="cuda")
@@ -267,25 +269,33 @@ def run_adjoint(torch, inputs, Solver, steps, every=100):
     s.run(target, steps)
     s.set_params(w.params)
     fwd_launch = s.tune(rho0)  # pass shape for this grid size (untimed; same bits)
-    count = s.checkpoint_count(steps, every)
-    cps = torch.empty((count, 5, w.ny, w.nx), dtype=torch.float64, device="cuda")
-    ws = torch.empty(s.adjoint_workspace_bytes(every), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    for rep in range(2):  # the first pass warms up; the second is timed
-        rho = rho0.clone()
-        lam = torch.zeros_like(rho)
-        grad = torch.zeros(9, dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        ev[0].record(stream)
-        s.run_checkpointed(rho, steps, every, checkpoints=cps)
-        ev[1].record(stream)
-        lam[2] = rho[2] - target[2]
-        lam[4] = rho[4] - target[4]
-        s.adjoint_run(cps, steps, every, lam, grad=grad, workspace=ws)
-        ev[2].record(stream)
-        torch.cuda.synchronize()
-    fwd_ms, rev_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+
+    def gradient(ev_every):
+        count = s.checkpoint_count(steps, ev_every)
+        cps = torch.empty((count, 5, w.ny, w.nx), dtype=torch.float64, device="cuda")
+        ws = torch.empty(s.adjoint_workspace_bytes(ev_every), dtype=torch.uint8, device="cuda")
+        for rep in range(2):  # the first pass warms up; the second is timed
+            rho = rho0.clone()
+            lam = torch.zeros_like(rho)
+            grad = torch.zeros(9, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            s.run_checkpointed(rho, steps, ev_every, checkpoints=cps)
+            ev[1].record(stream)
+            lam[2] = rho[2] - target[2]
+            lam[4] = rho[4] - target[4]
+            s.adjoint_run(cps, steps, ev_every, lam, grad=grad, workspace=ws)
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+        fwd, rev = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+        stored_gb = (cps.numel() * 8 + ws.numel()) / 1e9
+        del cps, ws
+        return fwd, rev, grad, lam, stored_gb
+
+    fwd_ms, rev_ms, grad, lam, gb = gradient(every)
+    fwd2, rev2, grad2, _, gb2 = gradient(2)
     # the adjoint step alone (adjoint kernel + the one-block gradient sum)
     reps = 200
     a, b = lam.clone(), torch.empty_like(lam)
@@ -304,7 +314,10 @@ def run_adjoint(torch, inputs, Solver, steps, every=100):
     out = {"workload": w.name, "nx": w.nx, "ny": w.ny, "steps": steps, "checkpoint_every": every,
            "dtype": "f64", "forward_launch": fwd_launch,
            "forward_ms": round(fwd_ms, 3), "reverse_ms": round(rev_ms, 3),
-           "gradient_ms": round(fwd_ms + rev_ms, 3),
+           "gradient_ms": round(fwd_ms + rev_ms, 3), "stored_gb": round(gb, 2),
+           "every_2": {"forward_ms": round(fwd2, 3), "reverse_ms": round(rev2, 3),
+                       "gradient_ms": round(fwd2 + rev2, 3), "stored_gb": round(gb2, 2),
+                       "same_gradient": bool(torch.equal(grad, grad2))},
            "adjoint_step_ms": round(step_ms, 5),
            "adjoint_step_gbps": round(bytes_per_step / (step_ms * 1e-3) / 1e9, 1),
            "adjoint_bytes_per_node": 120,
@@ -628,7 +641,10 @@ def main():
         adjoint_res = run_adjoint(torch, inputs, Solver, args.adjoint_steps)
         print(f"# adjoint: gradient in {adjoint_res['gradient_ms']:.1f} ms "
               f"(forward {adjoint_res['forward_ms']:.1f}, reverse {adjoint_res['reverse_ms']:.1f}); "
-              f"adjoint step {adjoint_res['adjoint_step_gbps']:.0f} GB/s",
+              f"adjoint step {adjoint_res['adjoint_step_gbps']:.0f} GB/s; every 2 steps stored: "
+              f"{adjoint_res['every_2']['gradient_ms']:.1f} ms "
+              f"({adjoint_res['every_2']['stored_gb']:.0f} GB, same gradient: "
+              f"{adjoint_res['every_2']['same_gradient']})",
               file=sys.stderr, flush=True)
 
     fd4_res = None

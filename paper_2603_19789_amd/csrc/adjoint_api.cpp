@@ -181,6 +181,25 @@ int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nst
         overlap(rho, bytes, scratch, bytes))
         return SSLBM_E_ALIAS;
     const hipStream_t s = (hipStream_t)hip_stream;
+    if (count == 0)
+        return SSLBM_OK;
+    if (every <= sslbm::march_max_depth(c->dtype, 1)) {
+        // One pass per segment, written straight into the next checkpoint
+        // (the last one into rho): one copy in all, no ping-pong through
+        // scratch. The pass kernel gives the same bits at every depth.
+        char *cp = static_cast<char *>(checkpoints);
+        int st = hip_status(c, hipMemcpyAsync(cp, rho, bytes, hipMemcpyDeviceToDevice, s));
+        if (st != SSLBM_OK)
+            return st;
+        for (long long k = 0; k < count; ++k) {
+            const long long n = nsteps - k * every < every ? nsteps - k * every : every;
+            void *out = k + 1 < count ? static_cast<void *>(cp + (size_t)(k + 1) * bytes) : rho;
+            st = sslbm::run_pass(c, cp + (size_t)k * bytes, out, (int)n, s);
+            if (st != SSLBM_OK)
+                return st;
+        }
+        return SSLBM_OK;
+    }
     for (long long k = 0; k < count; ++k) {
         char *slot = static_cast<char *>(checkpoints) + (size_t)k * bytes;
         int st = hip_status(c, hipMemcpyAsync(slot, rho, bytes, hipMemcpyDeviceToDevice, s));

@@ -104,21 +104,43 @@ def test_adjoint_run_matches_oracle(orc, bc, nsteps, every):
     assert gerr <= GRAD_TOL["f64"]
 
 
-def test_checkpoints_are_the_states():
+@pytest.mark.parametrize("every", [10, 2, 3, 8])
+def test_checkpoints_are_the_states(every):
     """run_checkpointed ends where run ends, and checkpoint k is the state
-    after k * every steps, bit for bit."""
+    after k * every steps, bit for bit (copies between runs for long
+    intervals; one pass per segment written into the next checkpoint for
+    intervals up to the deepest pass, with a ragged last segment)."""
     p = inputs.c1_params()
     rho0 = inputs.random_state(96, 80, seed=5)
     s = Solver(96, 80, p, dtype="f32")
     a = to_gpu(rho0, "f32")
-    cps = s.run_checkpointed(a, 53, 10)
+    cps = s.run_checkpointed(a, 53, every)
     b = to_gpu(rho0, "f32")
     s.run(b, 53)
     assert torch.equal(a, b)
-    for k in range(6):
+    assert cps.shape[0] == (53 + every - 1) // every
+    for k in range(cps.shape[0]):
         c = to_gpu(rho0, "f32")
-        s.run(c, 10 * k)
+        s.run(c, every * k)
         assert torch.equal(cps[k], c), k
+
+
+def test_gradient_with_every_state_stored_is_bitwise():
+    """Checkpoints every 2 steps (the reverse sweep recomputes nothing) give
+    the adjoint field and parameter gradient of checkpoints every 20 steps
+    bit for bit: stored and recomputed states have the same bits, and the
+    reverse steps run in the same passes."""
+    p = rough_params(0.07)
+    s = Solver(120, 88, p, dtype="f64")
+    rho0 = to_gpu(inputs.random_state(120, 88, seed=3), "f64")
+    lam0 = torch.randn(5, 88, 120, dtype=torch.float64, device="cuda",
+                       generator=torch.Generator("cuda").manual_seed(2))
+    outs = []
+    for every in (20, 2):
+        rho = rho0.clone()
+        cps = s.run_checkpointed(rho, 60, every)
+        outs.append(s.adjoint_run(cps, 60, every, lam0.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
 def test_adjoint_run_is_deterministic():
