@@ -363,6 +363,9 @@ class UNet:
             vp(self._side.cuda_stream) if self.overlap_sums else None,
             vp(self._events[k].cuda_event)), "sur_conv3x3_backward_weight_overlap")
         if gx is not None:
+            if self._flip_pending:  # the flipped weights, from the side stream
+                _torch().cuda.default_stream().wait_event(self._flip_done)
+                self._flip_pending = False
             _check(lib.sur_conv3x3_backward_data_flipped(
                 dz.ptr, dz.pitch, n, hh, ww, cv.cout, _ptr(self.flipped, cv.f_off), cv.cin,
                 gx.ptr, gx.pitch, None if act is None else act.ptr,
@@ -392,11 +395,12 @@ class UNet:
         main = torch.cuda.default_stream()  # the stream of every library call here
         self._backward_setup()
         # the side stream starts after everything before (theta_bf16 from
-        # the last Adam step); the first backward-data waits for the flip
+        # the last Adam step); the flip there overlaps the first weight
+        # gradient, and the first backward-data waits for it
         self._side.wait_stream(main)
         self._flip_weights()
         self._flip_done.record(self._side)
-        main.wait_event(self._flip_done)
+        self._flip_pending = True  # the first backward-data waits for it
         k = len(self.convs) - 1
         # output layer (no activation: dZ = dout); its input is the last
         # activation's output
