@@ -290,9 +290,9 @@ void sslbm_destroy(sslbm_ctx *c);
  *       checkpoints, a device buffer of sslbm_checkpoint_count states. For
  *       every up to the deepest single pass of the dtype (5 in FP64, 8 in
  *       FP32) each segment is one pass written straight into the next
- *       checkpoint (scratch unused); with every = 2 the
- *       reverse sweep then recomputes nothing, at the cost of nsteps / 2
- *       stored states (1024^2 FP64 x 2000 steps: 42 GB).
+ *       checkpoint (scratch unused), two segments per pass when every
+ *       = 2; the reverse sweep then recomputes nothing, at the cost of
+ *       nsteps / 2 stored states (1024^2 FP64 x 2000 steps: 42 GB).
  *   sslbm_adjoint_workspace_bytes: bytes of device workspace the reverse
  *       sweep needs for this context and checkpoint interval (about
  *       every / 2 + 1 states plus 128 bytes per wavefront of the adjoint

@@ -186,15 +186,26 @@ int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nst
     if (every <= sslbm::march_max_depth(c->dtype, 1)) {
         // One pass per segment, written straight into the next checkpoint
         // (the last one into rho): one copy in all, no ping-pong through
-        // scratch. The pass kernel gives the same bits at every depth.
+        // scratch; checkpoints every 2 steps take two segments per pass. The
+        // pass kernel gives the same bits at every depth.
         char *cp = static_cast<char *>(checkpoints);
         int st = hip_status(c, hipMemcpyAsync(cp, rho, bytes, hipMemcpyDeviceToDevice, s));
         if (st != SSLBM_OK)
             return st;
-        for (long long k = 0; k < count; ++k) {
+        auto slot = [&](long long k) -> void * {
+            return k < count ? static_cast<void *>(cp + (size_t)k * bytes) : rho;
+        };
+        for (long long k = 0; k < count;) {
             const long long n = nsteps - k * every < every ? nsteps - k * every : every;
-            void *out = k + 1 < count ? static_cast<void *>(cp + (size_t)(k + 1) * bytes) : rho;
-            st = sslbm::run_pass(c, cp + (size_t)k * bytes, out, (int)n, s);
+            if (every == 2 && n == 2 && k + 1 < count && nsteps - (k + 1) * every >= 2) {
+                // two segments in one pass of 4 steps, the state after 2
+                // steps written on the way
+                st = sslbm::run_pass_mid2(c, slot(k), slot(k + 1), slot(k + 2), s);
+                k += 2;
+            } else {
+                st = sslbm::run_pass(c, slot(k), slot(k + 1), (int)n, s);
+                k += 1;
+            }
             if (st != SSLBM_OK)
                 return st;
         }

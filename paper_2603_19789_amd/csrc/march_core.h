@@ -138,6 +138,7 @@ template <typename T, int V>
 struct MarchArgs {
     const T *__restrict__ in;
     T *__restrict__ out;
+    T *__restrict__ mid_out;  // the state after MID steps (MID > 0 only)
     GridDesc g;
     Coef<T> k;
     unsigned xoff[V];  // byte offsets of this lane's memory columns within a row
@@ -197,7 +198,35 @@ __device__ __forceinline__ T east_west(const Row &m, int v) {
 // Level l (1..K) at phase P: the row j - l from rows j-l-1, j-l, j-l+1 of
 // level l-1 (slots (P-l-1), (P-l), (P-l+1) mod RING); the result goes to slot
 // (P-l) mod RING of level l, or to HBM for l = K (output row j - K).
-template <typename T, int K, bool DIFFUSE_D, int V, int P, int L>
+// Row r (counted from j0 in the marching direction) of the five results of
+// this lane into dst, at the strip's output columns.
+template <typename T, int V>
+__device__ __forceinline__ void store_row(T *__restrict__ dst, const MarchArgs<T, V> &a, int r,
+                                          const T (&res)[5][V]) {
+    const long long row = (long long)(a.j0 + a.dir * r) * a.g.nx;
+    const unsigned xo = (unsigned)a.xl * (unsigned)sizeof(T);
+    if constexpr (V == 1) {
+        if (a.out_col[0]) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                buf_store(row_resource(dst + (c * a.g.plane + row), a.g.nx), xo, res[c][0]);
+        }
+    } else {
+        // strips start at even columns and nx is even, so a pair is either
+        // entirely output or entirely halo
+        if (a.out_col[0]) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+                buf_store_pair(row_resource(dst + (c * a.g.plane + row), a.g.nx), xo, res[c][0],
+                               res[c][1]);
+        }
+    }
+}
+
+// MID > 0: level MID's rows that are output rows of the chunk also go to
+// a.mid_out, the state after MID steps (the same bits as a pass of MID
+// steps: the output rows and columns hold exact values at every level).
+template <typename T, int K, bool DIFFUSE_D, int V, int P, int L, int MID = 0>
 __device__ __forceinline__ void level(MarchState<T, K, V> &st, const MarchArgs<T, V> &a, int t) {
     constexpr int s_up = ((P - L - 1) % RING + RING) % RING;
     constexpr int s_mid = ((P - L) % RING + RING) % RING;
@@ -227,61 +256,49 @@ __device__ __forceinline__ void level(MarchState<T, K, V> &st, const MarchArgs<T
 #pragma unroll
             for (int v = 0; v < V; ++v)
                 st.ring[L][s_mid][c][v] = res[c][v];
-    } else {
-        const long long row = (long long)(a.j0 + a.dir * (t - K)) * a.g.nx;
-        const unsigned xo = (unsigned)a.xl * (unsigned)sizeof(T);
-        if constexpr (V == 1) {
-            if (a.out_col[0]) {
-#pragma unroll
-                for (int c = 0; c < 5; ++c)
-                    buf_store(row_resource(a.out + (c * a.g.plane + row), a.g.nx), xo, res[c][0]);
-            }
-        } else {
-            // strips start at even columns and nx is even, so a pair is either
-            // entirely output or entirely halo
-            if (a.out_col[0]) {
-#pragma unroll
-                for (int c = 0; c < 5; ++c)
-                    buf_store_pair(row_resource(a.out + (c * a.g.plane + row), a.g.nx), xo,
-                                   res[c][0], res[c][1]);
-            }
+        if constexpr (L == MID) {
+            // the level's row t - L is an output row for t - L in [K, tend - K)
+            if (t - L >= K && t - L < a.tend - K)
+                store_row<T, V>(a.mid_out, a, t - L, res);
         }
+    } else {
+        store_row<T, V>(a.out, a, t - K, res);
     }
 }
 
 // Levels L..LMAX at phase P.
-template <typename T, int K, bool DIFFUSE_D, int V, int P, int L, int LMAX>
+template <typename T, int K, bool DIFFUSE_D, int V, int P, int L, int LMAX, int MID = 0>
 __device__ __forceinline__ void levels(MarchState<T, K, V> &st, const MarchArgs<T, V> &a, int t) {
     if constexpr (L <= LMAX) {
-        level<T, K, DIFFUSE_D, V, P, L>(st, a, t);
-        levels<T, K, DIFFUSE_D, V, P, L + 1, LMAX>(st, a, t);
+        level<T, K, DIFFUSE_D, V, P, L, MID>(st, a, t);
+        levels<T, K, DIFFUSE_D, V, P, L + 1, LMAX, MID>(st, a, t);
     }
 }
 
 // Warm-up rows t = TC < 2K (compile time): fetch row t + 1, then the levels
 // that already have three rows below them (l <= t/2). Nothing is stored yet.
-template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int TC>
+template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int TC, int MID = 0>
 __device__ __forceinline__ void warm_up(MarchState<T, K, V> &st, const MarchArgs<T, V> &a) {
     if constexpr (TC < 2 * K) {
         fetch_row<T, K, V, SW, (TC + 1) % RING>(st, a, TC + 1);
-        levels<T, K, DIFFUSE_D, V, TC % RING, 1, TC / 2>(st, a, TC);
-        warm_up<T, K, DIFFUSE_D, V, SW, TC + 1>(st, a);
+        levels<T, K, DIFFUSE_D, V, TC % RING, 1, TC / 2, MID>(st, a, TC);
+        warm_up<T, K, DIFFUSE_D, V, SW, TC + 1, MID>(st, a);
     }
 }
 
 // Steady-state row t (phase P): fetch row t + 1, all K levels, one output row.
 // Straight-line code, so the memory counters stay exact and the wait for row
 // t's data lets the row t + 1 loads stay in flight.
-template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int P>
+template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int P, int MID = 0>
 __device__ __forceinline__ void steady_row(MarchState<T, K, V> &st, const MarchArgs<T, V> &a,
                                            int t) {
     fetch_row<T, K, V, SW, (P + 1) % RING>(st, a, t + 1);
-    levels<T, K, DIFFUSE_D, V, P, 1, K>(st, a, t);
+    levels<T, K, DIFFUSE_D, V, P, 1, K, MID>(st, a, t);
 }
 
 // The rows of one wavefront's chunk: fill the levels, then one output row
 // per level-0 row. SW: some lane's column pair is mirrored in memory.
-template <typename T, int K, bool DIFFUSE_D, int V, bool SW>
+template <typename T, int K, bool DIFFUSE_D, int V, bool SW, int MID = 0>
 __device__ __forceinline__ void march_rows(const MarchArgs<T, V> &a) {
     MarchState<T, K, V> st;
 #pragma unroll
@@ -296,24 +313,24 @@ __device__ __forceinline__ void march_rows(const MarchArgs<T, V> &a) {
 
     // rows 0 .. 2K-1: fill the levels; from row 2K on every row yields output
     fetch_row<T, K, V, SW, 0>(st, a, 0);
-    warm_up<T, K, DIFFUSE_D, V, SW, 0>(st, a);
+    warm_up<T, K, DIFFUSE_D, V, SW, 0, MID>(st, a);
     constexpr int P0 = (2 * K) % RING;
     int t = 2 * K;
     for (; t + RING <= a.tend; t += RING) {
-        steady_row<T, K, DIFFUSE_D, V, SW, P0>(st, a, t);
-        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 1) % RING>(st, a, t + 1);
-        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 2) % RING>(st, a, t + 2);
-        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 3) % RING>(st, a, t + 3);
+        steady_row<T, K, DIFFUSE_D, V, SW, P0, MID>(st, a, t);
+        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 1) % RING, MID>(st, a, t + 1);
+        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 2) % RING, MID>(st, a, t + 2);
+        steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 3) % RING, MID>(st, a, t + 3);
     }
     // last partial group of rows (only when the chunk height is not a multiple
     // of 4), nested so that no ring slot's older value stays live through the
     // loop for a tail row that might read it
     if (t < a.tend) {
-        steady_row<T, K, DIFFUSE_D, V, SW, P0>(st, a, t);
+        steady_row<T, K, DIFFUSE_D, V, SW, P0, MID>(st, a, t);
         if (t + 1 < a.tend) {
-            steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 1) % RING>(st, a, t + 1);
+            steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 1) % RING, MID>(st, a, t + 1);
             if (t + 2 < a.tend)
-                steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 2) % RING>(st, a, t + 2);
+                steady_row<T, K, DIFFUSE_D, V, SW, (P0 + 2) % RING, MID>(st, a, t + 2);
         }
     }
 }
@@ -325,15 +342,17 @@ __device__ __forceinline__ void march_rows(const MarchArgs<T, V> &a) {
 // march towards it (or away from it) together, so the K halo rows on each
 // side of it are read by both wavefronts at about the same time and the
 // second read is served from cache rather than HBM.
-template <typename T, int K, bool DIFFUSE_D, int V>
+template <typename T, int K, bool DIFFUSE_D, int V, int MID = 0>
 __device__ __forceinline__ void march_tile(const T *__restrict__ in, T *__restrict__ out,
                                            const GridDesc &g, const Coef<T> &k, int x0, int y0,
-                                           int y1, bool up) {
+                                           int y1, bool up, T *__restrict__ mid_out = nullptr) {
+    static_assert(MID >= 0 && MID < K, "the middle state is one of levels 1 .. K-1");
     using Geo = Strip<K, V>;
     const int lane = threadIdx.x & 63;
     MarchArgs<T, V> a;
     a.in = in;
     a.out = out;
+    a.mid_out = mid_out;
     a.g = g;
     a.k = k;
     a.dir = up ? -1 : 1;
@@ -359,11 +378,11 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ in, T *__restri
     // loop without the pair select (a wavefront-uniform branch).
     if constexpr (V == 2) {
         if (__builtin_amdgcn_ballot_w64(a.swap) != 0) {
-            march_rows<T, K, DIFFUSE_D, V, true>(a);
+            march_rows<T, K, DIFFUSE_D, V, true, MID>(a);
             return;
         }
     }
-    march_rows<T, K, DIFFUSE_D, V, false>(a);
+    march_rows<T, K, DIFFUSE_D, V, false, MID>(a);
 }
 
 template <typename T>

@@ -126,6 +126,15 @@ int run_pass(sslbm_ctx *c, const void *in, void *out, int k, hipStream_t s) {
                                       shape_for(c, k, in, out), s));
 }
 
+int run_pass_mid2(sslbm_ctx *c, const void *in, void *mid, void *out, hipStream_t s) {
+    // both outputs pair-aligned for two columns per lane
+    MarchShape shape = shape_for(c, 4, in, out);
+    if ((uintptr_t)mid % (2 * elem_size(c)) != 0)
+        shape.cols_per_lane = 1;
+    return hip_status(c, launch_march_mid(c->dtype, in, mid, out, grid_of(c), c->coef, 4, 2,
+                                          shape, s));
+}
+
 static bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
 // Validation of sslbm_params and the derived per-step constants.

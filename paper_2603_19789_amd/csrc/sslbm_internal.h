@@ -56,6 +56,8 @@ PassPlan plan_passes(long long nsteps, int K);
 // One pass of k steps (1 <= k <= the register limit), in -> out, with the
 // context's pass shape (SSLBM status code).
 int run_pass(sslbm_ctx *c, const void *in, void *out, int k, hipStream_t s);
+// One pass of 4 steps in -> out writing the state after 2 steps to mid.
+int run_pass_mid2(sslbm_ctx *c, const void *in, void *mid, void *out, hipStream_t s);
 
 // ---- launchers (sslbm_kernels.hip) --------------------------------------
 // K steps in one pass: in -> out (no overlap). K in 1..SSLBM_MAX_BLOCKING.
@@ -63,6 +65,12 @@ hipError_t launch_march(int dtype, const void *in, void *out, const GridDesc &g,
                         const StepCoef &k, int K, const MarchShape &shape, hipStream_t s);
 // Largest steps-per-pass whose kernel fits the register budget.
 int march_max_depth(int dtype, int cols_per_lane);
+// A pass of K steps in -> out that also writes the state after MID steps to
+// mid (no overlap among the three); K = 4, MID = 2 only (else
+// hipErrorNotSupported).
+hipError_t launch_march_mid(int dtype, const void *in, void *mid, void *out, const GridDesc &g,
+                            const StepCoef &k, int K, int MID, const MarchShape &shape,
+                            hipStream_t s);
 // Output columns of one wavefront strip at K steps per pass.
 int strip_width(int K, int cols_per_lane);
 // Wavefronts of the K-step pass kernel resident on the current device at

@@ -26,6 +26,24 @@ void sslbm_march_kernel(
                                    min(y0 + rows_per_wave, g.ny), (chunk & 1) != 0);
 }
 
+// The same pass, writing the state after MID steps to `mid` as well: the
+// checkpoints of a recorded run, two per pass over HBM.
+template <typename T, int K, bool DIFFUSE_D, int V, int MID>
+__global__ __launch_bounds__(BLOCK_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+void sslbm_march_mid_kernel(
+    const T *__restrict__ in, T *__restrict__ mid, T *__restrict__ out, GridDesc g, Coef<T> k,
+    int rows_per_wave, int strips, int total_waves) {
+    const int wave = __builtin_amdgcn_readfirstlane(
+        xcd_tile(blockIdx.x, gridDim.x) * WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    if (wave >= total_waves)
+        return;  // whole wavefront leaves together
+    const int strip = wave % strips;
+    const int chunk = wave / strips;
+    const int y0 = chunk * rows_per_wave;
+    march_tile<T, K, DIFFUSE_D, V, MID>(in, out, g, k, strip * Strip<K, V>::WU, y0,
+                                        min(y0 + rows_per_wave, g.ny), (chunk & 1) != 0, mid);
+}
+
 template <typename T, int K, bool DD, int V>
 static hipError_t launch_k(const void *in, void *out, const GridDesc &g, const StepCoef &s,
                            const MarchShape &shape, hipStream_t st) {
@@ -78,6 +96,48 @@ hipError_t launch_march(int dtype, const void *in, void *out, const GridDesc &g,
                            : dispatch_v<float, false>(in, out, g, k, K, shape, s);
     return k.diffuse_d ? dispatch_v<double, true>(in, out, g, k, K, shape, s)
                        : dispatch_v<double, false>(in, out, g, k, K, shape, s);
+}
+
+template <typename T, bool DD, int V>
+static hipError_t launch_mid_t(const void *in, void *mid, void *out, const GridDesc &g,
+                               const StepCoef &s, const MarchShape &shape, hipStream_t st) {
+    constexpr int K = 4, MID = 2;
+    if constexpr (!march_fits<T, K, V>()) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int WU = Strip<K, V>::WU;
+        const int strips = (g.nx + WU - 1) / WU;
+        const int chunks = (g.ny + shape.rows_per_wave - 1) / shape.rows_per_wave;
+        const long long waves = (long long)strips * chunks;
+        const long long blocks = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+        if (waves > 0x7fffffffll)
+            return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL((sslbm_march_mid_kernel<T, K, DD, V, MID>), dim3((unsigned)blocks),
+                           dim3(BLOCK_THREADS), 0, st, static_cast<const T *>(in),
+                           static_cast<T *>(mid), static_cast<T *>(out), g, cast_coef<T>(s),
+                           shape.rows_per_wave, strips, (int)waves);
+        return hipGetLastError();
+    }
+}
+
+hipError_t launch_march_mid(int dtype, const void *in, void *mid, void *out, const GridDesc &g,
+                            const StepCoef &k, int K, int MID, const MarchShape &shape,
+                            hipStream_t s) {
+    if (K != 4 || MID != 2)
+        return hipErrorNotSupported;
+    const bool v2 = shape.cols_per_lane == 2;
+    if (dtype == SSLBM_F32) {
+        if (k.diffuse_d)
+            return v2 ? launch_mid_t<float, true, 2>(in, mid, out, g, k, shape, s)
+                      : launch_mid_t<float, true, 1>(in, mid, out, g, k, shape, s);
+        return v2 ? launch_mid_t<float, false, 2>(in, mid, out, g, k, shape, s)
+                  : launch_mid_t<float, false, 1>(in, mid, out, g, k, shape, s);
+    }
+    if (k.diffuse_d)
+        return v2 ? launch_mid_t<double, true, 2>(in, mid, out, g, k, shape, s)
+                  : launch_mid_t<double, true, 1>(in, mid, out, g, k, shape, s);
+    return v2 ? launch_mid_t<double, false, 2>(in, mid, out, g, k, shape, s)
+              : launch_mid_t<double, false, 1>(in, mid, out, g, k, shape, s);
 }
 
 int strip_width(int K, int cols_per_lane) {
