@@ -9,7 +9,9 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * - Every function returns an int status (sslbm_status); SSLBM_OK is 0.
+ * - Every entry point returns an sslbm_status (an int-sized enum; SSLBM_OK
+ *   is 0), except the few that return a count, a depth or a HIP error
+ *   code, which say so and return int.
  * - Arguments are validated on the host before any HIP call: a rejected call
  *   enqueues nothing, touches no device memory and works without a GPU.
  * - Device buffers are plain device pointers allocated and owned by the
@@ -78,7 +80,9 @@ typedef struct sslbm_ctx sslbm_ctx;
 /*
  * Create a context for an nx-by-ny grid.
  * dtype: SSLBM_F32 or SSLBM_F64 (element type of every buffer, and the
- *        arithmetic precision). bc: SSLBM_PERIODIC or SSLBM_NOFLUX.
+ *        arithmetic precision). bc: SSLBM_PERIODIC or SSLBM_NOFLUX. Both
+ *        are passed as int so that any other value is rejected (an enum
+ *        parameter could not hold one in C++).
  * Validation (no GPU needed):
  *   SSLBM_E_ARG      out or p null; nx, ny < 1 or above 1<<20; unknown dtype or
  *                    bc; any rate or d negative or not finite; phi > 1;
@@ -93,10 +97,11 @@ typedef struct sslbm_ctx sslbm_ctx;
  *                    with growing amplitude.
  * On success *out owns host memory released by sslbm_destroy.
  */
-int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_params *p);
+sslbm_status sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc,
+                        const sslbm_params *p);
 
 /* Replace the parameters (same validation as sslbm_init); grid, dtype and bc stay. */
-int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p);
+sslbm_status sslbm_set_params(sslbm_ctx *c, const sslbm_params *p);
 
 /*
  * The parameter struct from rates stated as (beta, sigma, gamma, mu): beta
@@ -107,8 +112,8 @@ int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p);
  * rate negative or not finite, or gamma + mu not > 0. The result still goes
  * through sslbm_init's validation.
  */
-int sslbm_params_from_rates(double beta, double sigma, double gamma, double mu, const double d[5],
-                            double dx, double dt, sslbm_params *out);
+sslbm_status sslbm_params_from_rates(double beta, double sigma, double gamma, double mu,
+                                     const double d[5], double dx, double dt, sslbm_params *out);
 
 /*
  * Gradients with respect to (beta, sigma, gamma, mu) from those with
@@ -121,8 +126,8 @@ int sslbm_params_from_rates(double beta, double sigma, double gamma, double mu, 
  * grad_rates may alias grad_params. Host only. SSLBM_E_ARG: a null pointer,
  * gamma or mu negative or not finite, or gamma + mu not > 0.
  */
-int sslbm_rate_gradients(const double grad_params[4], double gamma, double mu,
-                         double grad_rates[4]);
+sslbm_status sslbm_rate_gradients(const double grad_params[4], double gamma, double mu,
+                                  double grad_rates[4]);
 
 /*
  * Blocking depth: the number of time steps sslbm_run advances per pass over
@@ -132,7 +137,7 @@ int sslbm_rate_gradients(const double grad_params[4], double gamma, double mu,
  * sslbm_set_launch below.
  */
 #define SSLBM_MAX_BLOCKING 8
-int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass);
+sslbm_status sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass);
 int sslbm_get_blocking(const sslbm_ctx *c);
 
 /*
@@ -153,8 +158,8 @@ typedef struct {
     int rows_per_wave;
     int cols_per_lane;
 } sslbm_launch;
-int sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape);
-int sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape);
+sslbm_status sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape);
+sslbm_status sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape);
 
 /*
  * Autotuner: times candidate launch shapes of sslbm_run on the caller's
@@ -170,7 +175,8 @@ int sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape);
  * automatic shape is far from the best, chiefly grids too small to give
  * every resident wavefront a tall chunk.
  */
-int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream, sslbm_launch *best);
+sslbm_status sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream,
+                        sslbm_launch *best);
 
 /*
  * One SSLBM time step for all five compartments, Eq. (sslbm_final_clean)
@@ -188,7 +194,7 @@ int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream, s
  * where that sum is a positive subnormal number (below 2^-126): the quotient
  * dropped there is below 2^-126 beta dt for non-negative densities.
  */
-int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream);
+sslbm_status sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream);
 
 /*
  * nsteps SSLBM steps, several per HBM pass (see sslbm_set_blocking). The
@@ -196,7 +202,7 @@ int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream
  * contents are undefined afterwards. Bit for bit equal to nsteps calls of
  * sslbm_step. nsteps = 0 leaves rho unchanged. rho and scratch must not overlap.
  */
-int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream);
+sslbm_status sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream);
 
 /*
  * How sslbm_run splits nsteps into passes with the context's current pass
@@ -207,8 +213,8 @@ int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hi
  * is exact). Host only, no device call. *passes = 0 for nsteps = 0.
  * longest and shortest may be NULL.
  */
-int sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int *longest,
-                   int *shortest);
+sslbm_status sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int *longest,
+                            int *shortest);
 
 /*
  * BGK comparison scheme, Eq. (pdf) with f^eq = w_i rho, the source w_i Psi dt
@@ -223,12 +229,13 @@ int sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int 
  *                with a copy of the state from the scratch into f/rhoD).
  *   bgk_density: rho[C] = sum_i f_i for S, E, I, R and rho[D] = rhoD.
  */
-int bgk_init(sslbm_ctx *c, const void *rho, void *f, void *rhoD, void *hip_stream);
-int bgk_step(sslbm_ctx *c, const void *f_in, const void *rhoD_in, void *f_out, void *rhoD_out,
-             void *hip_stream);
-int bgk_run(sslbm_ctx *c, void *f, void *rhoD, void *f_scratch, void *rhoD_scratch,
-            long long nsteps, void *hip_stream);
-int bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho, void *hip_stream);
+sslbm_status bgk_init(sslbm_ctx *c, const void *rho, void *f, void *rhoD, void *hip_stream);
+sslbm_status bgk_step(sslbm_ctx *c, const void *f_in, const void *rhoD_in, void *f_out,
+                      void *rhoD_out, void *hip_stream);
+sslbm_status bgk_run(sslbm_ctx *c, void *f, void *rhoD, void *f_scratch, void *rhoD_scratch,
+                     long long nsteps, void *hip_stream);
+sslbm_status bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho,
+                         void *hip_stream);
 
 /*
  * The finite-difference reference solver of Sec. III, used to validate the
@@ -252,8 +259,8 @@ int bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho, void *
  *       and work overlap. Four launches per step, queued on hip_stream.
  */
 size_t sslbm_fd4_workspace_bytes(const sslbm_ctx *c);
-int sslbm_fd4_run(sslbm_ctx *c, void *rho, void *work, size_t work_bytes, long long nsteps,
-                  void *hip_stream);
+sslbm_status sslbm_fd4_run(sslbm_ctx *c, void *rho, void *work, size_t work_bytes, long long nsteps,
+                           void *hip_stream);
 
 /*
  * Total population per compartment, out_totals[C] = sum_x rho[C](x) in FP64,
@@ -262,7 +269,7 @@ int sslbm_fd4_run(sslbm_ctx *c, void *rho, void *work, size_t work_bytes, long l
  * call allocates a small device buffer (5 doubles per block) kept by the
  * context until sslbm_destroy.
  */
-int sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_stream);
+sslbm_status sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_stream);
 
 /* Release a context (NULL is allowed). */
 void sslbm_destroy(sslbm_ctx *c);
@@ -309,8 +316,8 @@ void sslbm_destroy(sslbm_ctx *c);
  * SSLBM_E_HIP.
  */
 #define SSLBM_GRAD_COUNT 9
-int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
-                       double *grad, void *hip_stream);
+sslbm_status sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
+                                double *grad, void *hip_stream);
 
 /*
  * sslbm_adjoint_step_noalloc: sslbm_adjoint_step for callers that cannot
@@ -329,14 +336,14 @@ int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void
  * more than about 250000 cells) return SSLBM_E_LIMIT before any device call.
  */
 #define SSLBM_ADJ_NOALLOC_SLOTS 4096
-int sslbm_adjoint_step_noalloc(sslbm_ctx *c, const void *rho, const void *lam_next,
-                               void *lam_out, double *grad, void *hip_stream);
+sslbm_status sslbm_adjoint_step_noalloc(sslbm_ctx *c, const void *rho, const void *lam_next,
+                                        void *lam_out, double *grad, void *hip_stream);
 long long sslbm_checkpoint_count(long long nsteps, int every);
-int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, int every,
-                           void *checkpoints, void *hip_stream);
+sslbm_status sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nsteps,
+                                    int every, void *checkpoints, void *hip_stream);
 size_t sslbm_adjoint_workspace_bytes(const sslbm_ctx *c, int every);
-int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, int every,
-                      void *lam, double *grad, void *workspace, void *hip_stream);
+sslbm_status sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, int every,
+                               void *lam, double *grad, void *workspace, void *hip_stream);
 
 /*
  * Ensembles: many independent SSLBM grids of different sizes and parameters
@@ -400,22 +407,24 @@ typedef struct {
     int max_side;         /* their longest side */
     sslbm_launch launch;  /* pass shape of a march class, resolved; zeros on chip */
 } sslbm_ensemble_class;
-int sslbm_ensemble_create(sslbm_ensemble **out, int count, const int *nx, const int *ny,
-                          int dtype, int bc, const sslbm_params *params, int *bad_instance);
+sslbm_status sslbm_ensemble_create(sslbm_ensemble **out, int count, const int *nx, const int *ny,
+                                   int dtype, int bc, const sslbm_params *params,
+                                   int *bad_instance);
 long long sslbm_ensemble_offset(const sslbm_ensemble *e, int instance);
 long long sslbm_ensemble_elements(const sslbm_ensemble *e);
 int sslbm_ensemble_class_count(const sslbm_ensemble *e);
 int sslbm_ensemble_instance_class(const sslbm_ensemble *e, int instance);
-int sslbm_ensemble_class_info(const sslbm_ensemble *e, int cls, sslbm_ensemble_class *info);
-int sslbm_ensemble_set_class_launch(sslbm_ensemble *e, int cls, const sslbm_launch *shape);
-int sslbm_ensemble_set_launch(sslbm_ensemble *e, const sslbm_launch *shape);
-int sslbm_ensemble_get_launch(const sslbm_ensemble *e, sslbm_launch *shape);
-int sslbm_ensemble_tune(sslbm_ensemble *e, const void *rho, void *scratch, void *hip_stream,
-                        sslbm_launch *best);
-int sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps, int flags,
-                       void *hip_stream);
-int sslbm_ensemble_run_class(sslbm_ensemble *e, int cls, void *rho, void *scratch,
-                             long long nsteps, void *hip_stream);
+sslbm_status sslbm_ensemble_class_info(const sslbm_ensemble *e, int cls,
+                                       sslbm_ensemble_class *info);
+sslbm_status sslbm_ensemble_set_class_launch(sslbm_ensemble *e, int cls, const sslbm_launch *shape);
+sslbm_status sslbm_ensemble_set_launch(sslbm_ensemble *e, const sslbm_launch *shape);
+sslbm_status sslbm_ensemble_get_launch(const sslbm_ensemble *e, sslbm_launch *shape);
+sslbm_status sslbm_ensemble_tune(sslbm_ensemble *e, const void *rho, void *scratch,
+                                 void *hip_stream, sslbm_launch *best);
+sslbm_status sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps,
+                                int flags, void *hip_stream);
+sslbm_status sslbm_ensemble_run_class(sslbm_ensemble *e, int cls, void *rho, void *scratch,
+                                      long long nsteps, void *hip_stream);
 int sslbm_ensemble_last_hip_error(const sslbm_ensemble *e);
 void sslbm_ensemble_destroy(sslbm_ensemble *e);
 
@@ -464,13 +473,15 @@ typedef struct {
     double rate;
 } sslbm_transition;
 typedef struct sslbm_model sslbm_model;
-int sslbm_model_create(sslbm_model **out, int nx, int ny, int dtype, int bc, int lattice,
-                       int compartments, const double *d, const int *counted, double dx,
-                       double dt, int ntransitions, const sslbm_transition *transitions);
-int sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hip_stream);
-int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps, void *hip_stream);
-int sslbm_model_set_blocking(sslbm_model *m, int steps_per_pass);
-int sslbm_model_get_blocking(const sslbm_model *m, int *steps_per_pass);
+sslbm_status sslbm_model_create(sslbm_model **out, int nx, int ny, int dtype, int bc,
+                                int lattice, int compartments, const double *d, const int *counted,
+                                double dx, double dt, int ntransitions,
+                                const sslbm_transition *transitions);
+sslbm_status sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hip_stream);
+sslbm_status sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
+                             void *hip_stream);
+sslbm_status sslbm_model_set_blocking(sslbm_model *m, int steps_per_pass);
+sslbm_status sslbm_model_get_blocking(const sslbm_model *m, int *steps_per_pass);
 int sslbm_model_last_hip_error(const sslbm_model *m);
 void sslbm_model_destroy(sslbm_model *m);
 

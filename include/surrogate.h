@@ -6,7 +6,7 @@
  * no surrogate; these are standard deep-learning operations, on BF16 MFMA
  * with FP32 accumulation.
  *
- * Conventions (as sslbm.h): int status codes from sslbm.h, host-side
+ * Conventions (as sslbm.h): sslbm_status codes from sslbm.h, host-side
  * validation before any HIP call, caller-owned device buffers, work enqueued
  * on hip_stream (a hipStream_t as void*, NULL = default stream).
  *
@@ -42,19 +42,19 @@ extern "C" {
 #define SUR_OUT_F32 2 /* write the output view in FP32 instead of BF16 */
 
 /* Forward convolution (see above); y may not overlap x. */
-int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
-                        const void *weight, const float *bias, void *y, int y_pitch, int cout,
-                        int flags, float slope, void *hip_stream);
+sslbm_status sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
+                                 const void *weight, const float *bias, void *y, int y_pitch,
+                                 int cout, int flags, float slope, void *hip_stream);
 
 /* The forward convolution (BF16 output; SUR_OUT_F32 is rejected) followed
  * by 2 x 2 average pooling of its output: y as sur_conv3x3_forward and
  * `pooled` (n, h/2, w/2; BF16 view of cout channels) as sur_pool2 of y, bit
  * for bit, in one pass where the image allows it. h and w even; neither
  * output may overlap x or each other. */
-int sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, int cin,
-                             const void *weight, const float *bias, void *y, int y_pitch,
-                             int cout, int flags, float slope, void *pooled, int pooled_pitch,
-                             void *hip_stream);
+sslbm_status sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, int cin,
+                                      const void *weight, const float *bias, void *y, int y_pitch,
+                                      int cout, int flags, float slope, void *pooled,
+                                      int pooled_pitch, void *hip_stream);
 
 /* The forward convolution (BF16 output; flags: SUR_LEAKY only) of the
  * channel concatenation [up2(xu), x]: input channels [0, cu) are `xu`
@@ -64,17 +64,17 @@ int sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, in
  * concatenation buffer followed by sur_conv3x3_forward. cu a multiple of
  * 32 and less than cin; h, w even. SSLBM_E_UNSUPPORTED for images under
  * 8 x 32 pixels (the caller upsamples explicitly there). */
-int sur_conv3x3_forward_up(const void *xu, int xu_pitch, int cu, const void *x, int x_pitch,
-                           int n, int h, int w, int cin, const void *weight, const float *bias,
-                           void *y, int y_pitch, int cout, int flags, float slope,
-                           void *hip_stream);
+sslbm_status sur_conv3x3_forward_up(const void *xu, int xu_pitch, int cu, const void *x,
+                                    int x_pitch, int n, int h, int w, int cin, const void *weight,
+                                    const float *bias, void *y, int y_pitch, int cout, int flags,
+                                    float slope, void *hip_stream);
 
 /* dx = d(sum dz * conv(x)) / dx for weight [cout][9][cin]: the convolution
  * of dz with the weights flipped in space and transposed in channels, built
  * in `flip_scratch` (device, >= 18 cout cin bytes). dx is overwritten. */
-int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
-                              const void *weight, int cin, void *dx, int dx_pitch,
-                              void *flip_scratch, void *hip_stream);
+sslbm_status sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
+                                       const void *weight, int cin, void *dx, int dx_pitch,
+                                       void *flip_scratch, void *hip_stream);
 
 /* The backward-data weights of several layers in one launch: for each
  * layer l < layers (at most 32), weight[l] ([cout[l]][9][cin[l]], BF16)
@@ -83,8 +83,8 @@ int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w,
  * flipped[i][8 - tap][o] = weight[o][tap][i]. Host arrays of device
  * pointers; no flipped buffer may overlap a weight or another flipped one.
  * Exact (a permutation). */
-int sur_flip_weights(int layers, const void *const *weight, const int *cout, const int *cin,
-                     void *const *flipped, void *hip_stream);
+sslbm_status sur_flip_weights(int layers, const void *const *weight, const int *cout,
+                              const int *cin, void *const *flipped, void *hip_stream);
 
 /* sur_conv3x3_backward_data on weights flipped by sur_flip_weights, and,
  * when act is not NULL, through the adjoint of the leaky activation whose
@@ -93,10 +93,10 @@ int sur_flip_weights(int layers, const void *const *weight, const int *cout, con
  * sur_conv3x3_backward_data followed by sur_leaky_backward in place (the
  * chain rule through an activation that feeds this convolution's input,
  * without a separate pass). dx may not overlap dz or act. */
-int sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int n, int h, int w,
-                                      int cout, const void *flipped, int cin, void *dx,
-                                      int dx_pitch, const void *act, int act_pitch, float slope,
-                                      void *hip_stream);
+sslbm_status sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int n, int h, int w,
+                                               int cout, const void *flipped, int cin, void *dx,
+                                               int dx_pitch, const void *act, int act_pitch,
+                                               float slope, void *hip_stream);
 
 /* Workspace bytes of sur_conv3x3_backward_weight for these sizes (0 if invalid). */
 size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int cout);
@@ -104,9 +104,10 @@ size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int c
 /* dweight[o][tap][i] = sum_{n,y,x} dz[n,y,x,o] x[n,y+dy,x+dx,i] and
  * dbias[o] = sum dz[..., o] (FP32, overwritten; dbias may be NULL).
  * Deterministic: FP32 partial sums over pixel ranges added in a fixed order. */
-int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int dz_pitch, int n,
-                                int h, int w, int cin, int cout, float *dweight, float *dbias,
-                                void *workspace, size_t workspace_bytes, void *hip_stream);
+sslbm_status sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int dz_pitch,
+                                         int n, int h, int w, int cin, int cout, float *dweight,
+                                         float *dbias, void *workspace, size_t workspace_bytes,
+                                         void *hip_stream);
 
 /* sur_conv3x3_backward_weight of the convolution that sur_conv3x3_forward_up
  * computes: its input's channels [0, cu) are xu (n, h/2, w/2) upsampled 2x
@@ -115,10 +116,11 @@ int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int 
  * sur_conv3x3_backward_weight; the same workspace size. cu a multiple of 32
  * and less than cin; h even, w a multiple of 8. SSLBM_E_UNSUPPORTED for
  * images under 8 x 32 pixels. */
-int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const void *x,
-                                   int x_pitch, const void *dz, int dz_pitch, int n, int h, int w,
-                                   int cin, int cout, float *dweight, float *dbias,
-                                   void *workspace, size_t workspace_bytes, void *hip_stream);
+sslbm_status sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const void *x,
+                                            int x_pitch, const void *dz, int dz_pitch, int n, int h,
+                                            int w, int cin, int cout, float *dweight, float *dbias,
+                                            void *workspace, size_t workspace_bytes,
+                                            void *hip_stream);
 
 /* The weight gradient of sur_conv3x3_backward_weight (xu NULL, cu 0) or of
  * sur_conv3x3_backward_weight_up (xu not NULL), in two stream-ordered parts
@@ -130,79 +132,81 @@ int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const v
  * call. dweight, dbias and the workspace belong to the call until the
  * caller has waited for sum_stream; each call in flight needs its own
  * workspace. sum_stream may equal hip_stream (then event may be NULL). */
-int sur_conv3x3_backward_weight_overlap(const void *xu, int xu_pitch, int cu, const void *x,
-                                        int x_pitch, const void *dz, int dz_pitch, int n, int h,
-                                        int w, int cin, int cout, float *dweight, float *dbias,
-                                        void *workspace, size_t workspace_bytes,
-                                        void *hip_stream, void *sum_stream, void *event);
+sslbm_status sur_conv3x3_backward_weight_overlap(const void *xu, int xu_pitch, int cu,
+                                                 const void *x, int x_pitch, const void *dz,
+                                                 int dz_pitch, int n, int h, int w, int cin,
+                                                 int cout, float *dweight, float *dbias,
+                                                 void *workspace, size_t workspace_bytes,
+                                                 void *hip_stream, void *sum_stream, void *event);
 
 /* dz = y > 0 ? dy : slope dy over `pixels` pixels of c channels (y is the
  * activation's output). dz may alias dy. */
-int sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,
-                       int dz_pitch, long long pixels, int c, float slope, void *hip_stream);
+sslbm_status sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,
+                                int dz_pitch, long long pixels, int c, float slope,
+                                void *hip_stream);
 
 /* 2x2 average pooling of x (n, h, w, c) into y (n, h/2, w/2, c), and its
  * adjoint: dx (n, h, w) = dy / 4 broadcast over each window, added to dx
  * when accumulate != 0. */
-int sur_pool2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
-              void *hip_stream);
-int sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
-                       int dx_pitch, int accumulate, void *hip_stream);
+sslbm_status sur_pool2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
+                       void *hip_stream);
+sslbm_status sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                                int dx_pitch, int accumulate, void *hip_stream);
 /* sur_pool2_backward, then the activation adjoint of sur_leaky_backward on
  * the stored result, with act (a BF16 view of c channels at dx's pixels,
  * not NULL) the activation's output: bit for bit the two calls in a row. */
-int sur_pool2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
-                           int dx_pitch, int accumulate, const void *act, int act_pitch,
-                           float slope, void *hip_stream);
+sslbm_status sur_pool2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c,
+                                    void *dx, int dx_pitch, int accumulate, const void *act,
+                                    int act_pitch, float slope, void *hip_stream);
 
 /* 2x nearest-neighbour upsampling of x (n, h, w, c) into y (n, 2h, 2w, c),
  * and its adjoint: dx (n, h, w) = sum of dy over each 2x2 window. */
-int sur_up2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
-            void *hip_stream);
-int sur_up2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
-                     int dx_pitch, void *hip_stream);
+sslbm_status sur_up2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
+                     void *hip_stream);
+sslbm_status sur_up2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                              int dx_pitch, void *hip_stream);
 /* sur_up2_backward, then the activation adjoint as in
  * sur_pool2_backward_act (act a BF16 view of c channels at dx's pixels,
  * not NULL): bit for bit the two calls in a row. */
-int sur_up2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
-                         int dx_pitch, const void *act, int act_pitch, float slope,
-                         void *hip_stream);
+sslbm_status sur_up2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c,
+                                  void *dx, int dx_pitch, const void *act, int act_pitch,
+                                  float slope, void *hip_stream);
 
 /* Network input from densities: x (BF16 NHWC, 16 channels, pitch 16) holds
  * rho_c / scale_in[c] for c < 5, then planes[b][0..8] (FP32 device
  * [batch][9], the normalised rates and diffusivities) on every pixel, then
  * two zero channels. scale_in: host array of 5 positive floats. */
-int sur_pack_input(const float *rho, int batch, int h, int w, const float *planes,
-                   const float *scale_in, void *x, void *hip_stream);
+sslbm_status sur_pack_input(const float *rho, int batch, int h, int w, const float *planes,
+                            const float *scale_in, void *x, void *hip_stream);
 
 /* rho_next = rho + scale_out[c] * out[..., c] for c < 5; out is FP32 NHWC
  * with 16 channels (the network's last layer). rho_next may alias rho. */
-int sur_apply_output(const float *rho, const float *out, int batch, int h, int w,
-                     const float *scale_out, float *rho_next, void *hip_stream);
+sslbm_status sur_apply_output(const float *rho, const float *out, int batch, int h, int w,
+                              const float *scale_out, float *rho_next, void *hip_stream);
 
 /* Training loss: the mean over (b, y, x, c < 5) of
  * (out[..., c] - (target - rho)_c / scale_out[c])^2 into *loss (device
  * double), and its gradient dout (BF16 NHWC, 16 channels, zero for c >= 5).
  * partials: device scratch of 1024 doubles. */
-int sur_mse_loss(const float *out, const float *rho, const float *target, int batch, int h,
-                 int w, const float *scale_out, void *dout, double *partials, double *loss,
-                 void *hip_stream);
+sslbm_status sur_mse_loss(const float *out, const float *rho, const float *target, int batch, int h,
+                          int w, const float *scale_out, void *dout, double *partials, double *loss,
+                          void *hip_stream);
 
 /* One Adam step (Kingma and Ba, 2015) over count FP32 parameters; step
  * counts from 1. theta_bf16 (may be NULL) receives the rounded parameters. */
-int sur_adam(float *theta, void *theta_bf16, const float *grad, float *m, float *v,
-             long long count, int step, float lr, float beta1, float beta2, float eps,
-             void *hip_stream);
+sslbm_status sur_adam(float *theta, void *theta_bf16, const float *grad, float *m, float *v,
+                      long long count, int step, float lr, float beta1, float beta2, float eps,
+                      void *hip_stream);
 
 /* Periodic crop of a density state: dst[c][j][i] = rho[c][(y0 + j) mod h]
  * [(x0 + i) mod w] for the 5 compartments, j < ch, i < cw (FP32; any integer
  * y0, x0). Used to recompute SSLBM steps on sub-tiles when judging the
  * surrogate. */
-int sur_crop_periodic(const float *rho, int h, int w, int y0, int x0, int ch, int cw, float *dst,
-                      void *hip_stream);
+sslbm_status sur_crop_periodic(const float *rho, int h, int w, int y0, int x0, int ch, int cw,
+                               float *dst, void *hip_stream);
 
 /* dst = round-to-nearest-even BF16 of src (count values). */
-int sur_to_bf16(const float *src, void *dst, long long count, void *hip_stream);
+sslbm_status sur_to_bf16(const float *src, void *dst, long long count, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,7 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     return na && nb && x < y + nb && y < x + na;
 }
 
-int hip_status(sslbm_ctx *c, hipError_t e) {
+sslbm_status hip_status(sslbm_ctx *c, hipError_t e) {
     if (e == hipSuccess)
         return SSLBM_OK;
     c->last_hip = (int)e;
@@ -60,8 +60,8 @@ size_t partials_bytes(const sslbm::AdjShape &s) {
     return (size_t)s.slots() * sslbm::ADJ_SLOT * sizeof(double);
 }
 
-int step_args(const sslbm_ctx *c, const void *rho, const void *lam_next, const void *lam_out,
-              const double *grad) {
+sslbm_status step_args(const sslbm_ctx *c, const void *rho, const void *lam_next,
+                       const void *lam_out, const double *grad) {
     if (!c || !rho || !lam_next || !lam_out || !grad)
         return SSLBM_E_ARG;
     const size_t bytes = state_bytes(c);
@@ -72,9 +72,10 @@ int step_args(const sslbm_ctx *c, const void *rho, const void *lam_next, const v
 }
 
 // The reverse step and the sum of its wavefront slots into grad.
-int step_into(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out, double *grad,
-              const sslbm::AdjShape &shape, double *partials, hipStream_t s) {
-    const int st = hip_status(c, sslbm::launch_adjoint(c->dtype, rho, lam_next, lam_out,
+sslbm_status step_into(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
+                       double *grad, const sslbm::AdjShape &shape, double *partials,
+                       hipStream_t s) {
+    const sslbm_status st = hip_status(c, sslbm::launch_adjoint(c->dtype, rho, lam_next, lam_out,
                                                        grid_of(c), c->coef, shape, partials,
                                                        true, s));
     if (st != SSLBM_OK)
@@ -99,9 +100,9 @@ constexpr int MAX_DEVICES = 64;
 std::mutex scratch_lock;
 double *scratch_of_device[MAX_DEVICES] = {};
 
-int scratch_address(sslbm_ctx *c, double **out) {
+sslbm_status scratch_address(sslbm_ctx *c, double **out) {
     int dev = 0;
-    int st = hip_status(c, hipGetDevice(&dev));
+    sslbm_status st = hip_status(c, hipGetDevice(&dev));
     if (st != SSLBM_OK)
         return st;
     if (dev < 0 || dev >= MAX_DEVICES)
@@ -124,9 +125,9 @@ int scratch_address(sslbm_ctx *c, double **out) {
 
 extern "C" {
 
-int sslbm_adjoint_step_noalloc(sslbm_ctx *c, const void *rho, const void *lam_next,
-                               void *lam_out, double *grad, void *hip_stream) {
-    int st = step_args(c, rho, lam_next, lam_out, grad);
+sslbm_status sslbm_adjoint_step_noalloc(sslbm_ctx *c, const void *rho, const void *lam_next,
+                                        void *lam_out, double *grad, void *hip_stream) {
+    sslbm_status st = step_args(c, rho, lam_next, lam_out, grad);
     if (st != SSLBM_OK)
         return st;
     const sslbm::AdjShape shape = sslbm::adjoint_shape(c->nx, c->ny);
@@ -140,9 +141,9 @@ int sslbm_adjoint_step_noalloc(sslbm_ctx *c, const void *rho, const void *lam_ne
                      (hipStream_t)hip_stream);
 }
 
-int sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
-                       double *grad, void *hip_stream) {
-    int st = step_args(c, rho, lam_next, lam_out, grad);
+sslbm_status sslbm_adjoint_step(sslbm_ctx *c, const void *rho, const void *lam_next, void *lam_out,
+                                double *grad, void *hip_stream) {
+    sslbm_status st = step_args(c, rho, lam_next, lam_out, grad);
     if (st != SSLBM_OK)
         return st;
     const sslbm::AdjShape shape = sslbm::adjoint_shape(c->nx, c->ny);
@@ -170,8 +171,8 @@ long long sslbm_checkpoint_count(long long nsteps, int every) {
     return (nsteps + every - 1) / every;
 }
 
-int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, int every,
-                           void *checkpoints, void *hip_stream) {
+sslbm_status sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nsteps,
+                                    int every, void *checkpoints, void *hip_stream) {
     if (!c || !rho || !scratch || !checkpoints || nsteps < 0 || every < 1)
         return SSLBM_E_ARG;
     const size_t bytes = state_bytes(c);
@@ -189,7 +190,7 @@ int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nst
         // scratch; checkpoints every 2 steps take two segments per pass. The
         // pass kernel gives the same bits at every depth.
         char *cp = static_cast<char *>(checkpoints);
-        int st = hip_status(c, hipMemcpyAsync(cp, rho, bytes, hipMemcpyDeviceToDevice, s));
+        sslbm_status st = hip_status(c, hipMemcpyAsync(cp, rho, bytes, hipMemcpyDeviceToDevice, s));
         if (st != SSLBM_OK)
             return st;
         auto slot = [&](long long k) -> void * {
@@ -213,7 +214,8 @@ int sslbm_run_checkpointed(sslbm_ctx *c, void *rho, void *scratch, long long nst
     }
     for (long long k = 0; k < count; ++k) {
         char *slot = static_cast<char *>(checkpoints) + (size_t)k * bytes;
-        int st = hip_status(c, hipMemcpyAsync(slot, rho, bytes, hipMemcpyDeviceToDevice, s));
+        sslbm_status st =
+            hip_status(c, hipMemcpyAsync(slot, rho, bytes, hipMemcpyDeviceToDevice, s));
         if (st != SSLBM_OK)
             return st;
         const long long n = nsteps - k * every < every ? nsteps - k * every : every;
@@ -239,8 +241,8 @@ size_t sslbm_adjoint_workspace_bytes(const sslbm_ctx *c, int every) {
 // states at even offsets are recomputed with two-step passes; the adjoint
 // then runs two steps per pass (the odd state recomputed in registers),
 // with one single step first when len is odd.
-int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, int every,
-                      void *lam, double *grad, void *workspace, void *hip_stream) {
+sslbm_status sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, int every,
+                               void *lam, double *grad, void *workspace, void *hip_stream) {
     if (!c || !checkpoints || !lam || !grad || !workspace || nsteps < 0 || every < 1)
         return SSLBM_E_ARG;
     const size_t bytes = state_bytes(c);
@@ -264,8 +266,8 @@ int sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long nsteps, i
     double *part2 = part1 + s1.slots() * sslbm::ADJ_SLOT;
     const sslbm::GridDesc g = grid_of(c);
     const hipStream_t s = (hipStream_t)hip_stream;
-    int st = hip_status(c, sslbm::launch_zero(part1, (s1.slots() + s2.slots()) * sslbm::ADJ_SLOT,
-                                              s));
+    sslbm_status st = hip_status(
+        c, sslbm::launch_zero(part1, (s1.slots() + s2.slots()) * sslbm::ADJ_SLOT, s));
     if (st != SSLBM_OK)
         return st;
 

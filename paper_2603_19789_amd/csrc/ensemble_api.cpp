@@ -86,7 +86,7 @@ struct sslbm_ensemble {
 
 namespace {
 
-int hip_status(sslbm_ensemble *e, hipError_t err) {
+sslbm_status hip_status(sslbm_ensemble *e, hipError_t err) {
     if (err == hipSuccess)
         return SSLBM_OK;
     e->last_hip = (int)err;
@@ -179,9 +179,9 @@ void drop_graphs(sslbm_ensemble *e) {
     e->graphs.clear();
 }
 
-int ensure_device_tables(sslbm_ensemble *e) {
+sslbm_status ensure_device_tables(sslbm_ensemble *e) {
     int dev = 0;
-    int st = hip_status(e, hipGetDevice(&dev));
+    sslbm_status st = hip_status(e, hipGetDevice(&dev));
     if (st != SSLBM_OK)
         return st;
     if (e->insts && e->device == dev)
@@ -229,14 +229,15 @@ int ensure_device_tables(sslbm_ensemble *e) {
     return SSLBM_OK;
 }
 
-int tile_table(sslbm_ensemble *e, int c, int k, int H, int V, TileTable **out) {
+sslbm_status tile_table(sslbm_ensemble *e, int c, int k, int H, int V, TileTable **out) {
     auto key = std::make_tuple(c, k, H, V);
     auto it = e->tiles.find(key);
     if (it == e->tiles.end()) {
         const std::vector<sslbm::EnsTile> t = make_tiles(e, c, k, H, V);
         TileTable tab;
         tab.count = (int)t.size();
-        int st = hip_status(e, hipMalloc((void **)&tab.dev, sizeof(sslbm::EnsTile) * t.size()));
+        sslbm_status st =
+            hip_status(e, hipMalloc((void **)&tab.dev, sizeof(sslbm::EnsTile) * t.size()));
         if (st != SSLBM_OK)
             return st;
         st = hip_status(e, hipMemcpy(tab.dev, t.data(), sizeof(sslbm::EnsTile) * t.size(),
@@ -252,8 +253,8 @@ int tile_table(sslbm_ensemble *e, int c, int k, int H, int V, TileTable **out) {
 }
 
 // Enqueue nsteps steps of class c on stream s (tables must exist).
-int enqueue_class(sslbm_ensemble *e, int c, void *rho, void *scratch, long long nsteps,
-                  bool pairs_ok, hipStream_t s) {
+sslbm_status enqueue_class(sslbm_ensemble *e, int c, void *rho, void *scratch, long long nsteps,
+                           bool pairs_ok, hipStream_t s) {
     const EnsClass &cl = e->classes[c];
     if (cl.on_chip)
         return hip_status(e, sslbm::launch_ensemble_lds(
@@ -266,7 +267,7 @@ int enqueue_class(sslbm_ensemble *e, int c, void *rho, void *scratch, long long 
         const int k = plan.steps(i);
         const int V = usable_cols(e, c, r.cols_per_lane, k, pairs_ok);
         TileTable *tab = nullptr;
-        int st = tile_table(e, c, k, r.rows_per_wave, V, &tab);
+        sslbm_status st = tile_table(e, c, k, r.rows_per_wave, V, &tab);
         if (st != SSLBM_OK)
             return st;
         st = hip_status(e, sslbm::launch_ensemble(e->dtype, src, dst, tab->dev, tab->count,
@@ -279,7 +280,7 @@ int enqueue_class(sslbm_ensemble *e, int c, void *rho, void *scratch, long long 
         const size_t eb = elem_bytes(e);
         for (int i : cl.insts) {
             const size_t off = (size_t)e->offset[i] * eb;
-            const int st = hip_status(
+            const sslbm_status st = hip_status(
                 e, hipMemcpyAsync(static_cast<char *>(rho) + off, static_cast<char *>(src) + off,
                                   5 * (size_t)e->nx[i] * e->ny[i] * eb, hipMemcpyDeviceToDevice,
                                   s));
@@ -291,11 +292,11 @@ int enqueue_class(sslbm_ensemble *e, int c, void *rho, void *scratch, long long 
 }
 
 // Every class on its own stream, forked from and joined back to s.
-int enqueue_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps, bool pairs_ok,
-                hipStream_t s) {
+sslbm_status enqueue_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps,
+                         bool pairs_ok, hipStream_t s) {
     if (e->classes.size() == 1)
         return enqueue_class(e, 0, rho, scratch, nsteps, pairs_ok, s);
-    int st = hip_status(e, hipEventRecord(e->ev_fork, s));
+    sslbm_status st = hip_status(e, hipEventRecord(e->ev_fork, s));
     for (size_t c = 0; c < e->classes.size() && st == SSLBM_OK; ++c) {
         EnsClass &cl = e->classes[c];
         st = hip_status(e, hipStreamWaitEvent(cl.stream, e->ev_fork, 0));
@@ -311,7 +312,7 @@ int enqueue_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps, b
 
 // Build every tile table a run of nsteps will use (before any capture): a
 // class's run uses at most two depths, the longer and the shorter passes.
-int prepare_run(sslbm_ensemble *e, long long nsteps, bool pairs_ok) {
+sslbm_status prepare_run(sslbm_ensemble *e, long long nsteps, bool pairs_ok) {
     for (int c = 0; c < (int)e->classes.size(); ++c) {
         if (e->classes[c].on_chip)
             continue;
@@ -322,7 +323,7 @@ int prepare_run(sslbm_ensemble *e, long long nsteps, bool pairs_ok) {
                 continue;
             const int k = plan.steps(i);
             TileTable *tab = nullptr;
-            const int st = tile_table(e, c, k, r.rows_per_wave,
+            const sslbm_status st = tile_table(e, c, k, r.rows_per_wave,
                                       usable_cols(e, c, r.cols_per_lane, k, pairs_ok), &tab);
             if (st != SSLBM_OK)
                 return st;
@@ -341,7 +342,7 @@ bool pairs_aligned(const sslbm_ensemble *e, const void *rho, const void *scratch
     return !((uintptr_t)rho % pair) && !((uintptr_t)scratch % pair);
 }
 
-int check_shape(const sslbm_ensemble *e, const sslbm_launch &r) {
+sslbm_status check_shape(const sslbm_ensemble *e, const sslbm_launch &r) {
     if (r.steps_per_pass < 0 || r.steps_per_pass > SSLBM_MAX_BLOCKING || r.rows_per_wave < 0 ||
         r.rows_per_wave > 65536 || r.cols_per_lane < 0 || r.cols_per_lane > 2)
         return SSLBM_E_ARG;
@@ -357,8 +358,8 @@ int check_shape(const sslbm_ensemble *e, const sslbm_launch &r) {
 // the classes' current shapes: one untimed round, then three timed ones.
 // Returns the joint rate in cell-updates per nanosecond (0 on error).
 double joint_rate(sslbm_ensemble *e, const void *rho, void *scratch, bool pairs_ok,
-                  hipEvent_t t0, hipEvent_t t1, int *status) {
-    int st = SSLBM_OK;
+                  hipEvent_t t0, hipEvent_t t1, sslbm_status *status) {
+    sslbm_status st = SSLBM_OK;
     double work = 0.0;  // cell-updates of one round
     for (int rep = 0; rep < 4 && st == SSLBM_OK; ++rep) {
         if (rep == 1)
@@ -414,8 +415,8 @@ std::vector<sslbm_launch> candidates(const sslbm_ensemble *e, int c, bool pairs_
 // The tuner: first one shape for every march class (the best joint rate),
 // then each class in turn, largest first, tries its candidates while the
 // others keep theirs, and keeps whichever raises the joint rate.
-int tune_classes(sslbm_ensemble *e, const void *rho, void *scratch, bool pairs_ok,
-                 hipEvent_t t0, hipEvent_t t1) {
+sslbm_status tune_classes(sslbm_ensemble *e, const void *rho, void *scratch, bool pairs_ok,
+                          hipEvent_t t0, hipEvent_t t1) {
     std::vector<int> march;
     for (int c = 0; c < (int)e->classes.size(); ++c)
         if (!e->classes[c].on_chip)
@@ -424,7 +425,7 @@ int tune_classes(sslbm_ensemble *e, const void *rho, void *scratch, bool pairs_o
         return SSLBM_OK;
     std::sort(march.begin(), march.end(),
               [&](int a, int b) { return e->classes[a].cells > e->classes[b].cells; });
-    int st = SSLBM_OK;
+    sslbm_status st = SSLBM_OK;
     double best = -1.0;
     sslbm_launch common{};
     for (const sslbm_launch &cand : candidates(e, march[0], pairs_ok)) {
@@ -463,8 +464,9 @@ int tune_classes(sslbm_ensemble *e, const void *rho, void *scratch, bool pairs_o
 
 extern "C" {
 
-int sslbm_ensemble_create(sslbm_ensemble **out, int count, const int *nx, const int *ny,
-                          int dtype, int bc, const sslbm_params *params, int *bad_instance) {
+sslbm_status sslbm_ensemble_create(sslbm_ensemble **out, int count, const int *nx, const int *ny,
+                                   int dtype, int bc, const sslbm_params *params,
+                                   int *bad_instance) {
     if (bad_instance)
         *bad_instance = -1;
     if (!out || !nx || !ny || !params || count < 1 || count > MAX_INSTANCES)
@@ -483,7 +485,7 @@ int sslbm_ensemble_create(sslbm_ensemble **out, int count, const int *nx, const 
     long long off = 0;
     for (int i = 0; i < count; ++i) {
         sslbm::StepCoef k;
-        int st = SSLBM_OK;
+        sslbm_status st = SSLBM_OK;
         if (nx[i] < 1 || ny[i] < 1 || nx[i] > MAX_ENS_SIDE || ny[i] > MAX_ENS_SIDE)
             st = SSLBM_E_ARG;
         else
@@ -574,7 +576,8 @@ int sslbm_ensemble_instance_class(const sslbm_ensemble *e, int instance) {
     return e->class_of[instance];
 }
 
-int sslbm_ensemble_class_info(const sslbm_ensemble *e, int cls, sslbm_ensemble_class *info) {
+sslbm_status sslbm_ensemble_class_info(const sslbm_ensemble *e, int cls,
+                                       sslbm_ensemble_class *info) {
     if (!e || !info || !valid_class(e, cls))
         return SSLBM_E_ARG;
     const EnsClass &cl = e->classes[cls];
@@ -586,10 +589,11 @@ int sslbm_ensemble_class_info(const sslbm_ensemble *e, int cls, sslbm_ensemble_c
     return SSLBM_OK;
 }
 
-int sslbm_ensemble_set_class_launch(sslbm_ensemble *e, int cls, const sslbm_launch *shape) {
+sslbm_status sslbm_ensemble_set_class_launch(sslbm_ensemble *e, int cls,
+                                             const sslbm_launch *shape) {
     if (!e || !shape || !valid_class(e, cls))
         return SSLBM_E_ARG;
-    const int st = check_shape(e, *shape);
+    const sslbm_status st = check_shape(e, *shape);
     if (st != SSLBM_OK)
         return st;
     if (e->classes[cls].on_chip)
@@ -599,10 +603,10 @@ int sslbm_ensemble_set_class_launch(sslbm_ensemble *e, int cls, const sslbm_laun
     return SSLBM_OK;
 }
 
-int sslbm_ensemble_set_launch(sslbm_ensemble *e, const sslbm_launch *shape) {
+sslbm_status sslbm_ensemble_set_launch(sslbm_ensemble *e, const sslbm_launch *shape) {
     if (!e || !shape)
         return SSLBM_E_ARG;
-    const int st = check_shape(e, *shape);
+    const sslbm_status st = check_shape(e, *shape);
     if (st != SSLBM_OK)
         return st;
     for (EnsClass &cl : e->classes)
@@ -612,7 +616,7 @@ int sslbm_ensemble_set_launch(sslbm_ensemble *e, const sslbm_launch *shape) {
     return SSLBM_OK;
 }
 
-int sslbm_ensemble_get_launch(const sslbm_ensemble *e, sslbm_launch *shape) {
+sslbm_status sslbm_ensemble_get_launch(const sslbm_ensemble *e, sslbm_launch *shape) {
     if (!e || !shape)
         return SSLBM_E_ARG;
     const int c = main_class(e);
@@ -620,7 +624,7 @@ int sslbm_ensemble_get_launch(const sslbm_ensemble *e, sslbm_launch *shape) {
     return SSLBM_OK;
 }
 
-static int run_checks(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps) {
+static sslbm_status run_checks(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps) {
     if (!e || !rho || !scratch || nsteps < 0)
         return SSLBM_E_ARG;
     const size_t bytes = elem_bytes(e) * e->elements;
@@ -629,9 +633,9 @@ static int run_checks(sslbm_ensemble *e, void *rho, void *scratch, long long nst
     return SSLBM_OK;
 }
 
-int sslbm_ensemble_run_class(sslbm_ensemble *e, int cls, void *rho, void *scratch,
-                             long long nsteps, void *hip_stream) {
-    int st = run_checks(e, rho, scratch, nsteps);
+sslbm_status sslbm_ensemble_run_class(sslbm_ensemble *e, int cls, void *rho, void *scratch,
+                                      long long nsteps, void *hip_stream) {
+    sslbm_status st = run_checks(e, rho, scratch, nsteps);
     if (st != SSLBM_OK)
         return st;
     if (!valid_class(e, cls))
@@ -647,9 +651,9 @@ int sslbm_ensemble_run_class(sslbm_ensemble *e, int cls, void *rho, void *scratc
     return enqueue_class(e, cls, rho, scratch, nsteps, pairs_ok, (hipStream_t)hip_stream);
 }
 
-int sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps, int flags,
-                       void *hip_stream) {
-    int st = run_checks(e, rho, scratch, nsteps);
+sslbm_status sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long nsteps,
+                                int flags, void *hip_stream) {
+    sslbm_status st = run_checks(e, rho, scratch, nsteps);
     if (st != SSLBM_OK)
         return st;
     if (flags & ~SSLBM_RUN_GRAPH)
@@ -673,7 +677,7 @@ int sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long ns
         st = hip_status(e, hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
         if (st != SSLBM_OK)
             return st;
-        const int run_st = enqueue_run(e, rho, scratch, nsteps, pairs_ok, e->stream);
+        const sslbm_status run_st = enqueue_run(e, rho, scratch, nsteps, pairs_ok, e->stream);
         hipGraph_t graph = nullptr;
         const hipError_t end = hipStreamEndCapture(e->stream, &graph);
         if (run_st != SSLBM_OK) {
@@ -705,14 +709,14 @@ int sslbm_ensemble_run(sslbm_ensemble *e, void *rho, void *scratch, long long ns
     return st;
 }
 
-int sslbm_ensemble_tune(sslbm_ensemble *e, const void *rho, void *scratch, void *hip_stream,
-                        sslbm_launch *best) {
+sslbm_status sslbm_ensemble_tune(sslbm_ensemble *e, const void *rho, void *scratch,
+                                 void *hip_stream, sslbm_launch *best) {
     if (!e || !rho || !scratch)
         return SSLBM_E_ARG;
     const size_t bytes = elem_bytes(e) * e->elements;
     if (overlap(rho, bytes, scratch, bytes))
         return SSLBM_E_ALIAS;
-    int st = ensure_device_tables(e);
+    sslbm_status st = ensure_device_tables(e);
     if (st != SSLBM_OK)
         return st;
     st = hip_status(e, hipStreamSynchronize((hipStream_t)hip_stream));

@@ -23,7 +23,7 @@ namespace {
 
 constexpr int MAX_SIDE = 1 << 20;
 
-int hip_status(sslbm_model *m, hipError_t e) {
+sslbm_status hip_status(sslbm_model *m, hipError_t e) {
     if (e == hipSuccess)
         return SSLBM_OK;
     m->last_hip = (int)e;
@@ -53,9 +53,9 @@ size_t state_bytes(const sslbm_model *m) {
 
 // The device transition table on the current device (uploaded once; a
 // model stays on the device it first ran on).
-int ensure_table(sslbm_model *m) {
+sslbm_status ensure_table(sslbm_model *m) {
     int dev = 0;
-    int st = hip_status(m, hipGetDevice(&dev));
+    sslbm_status st = hip_status(m, hipGetDevice(&dev));
     if (st != SSLBM_OK)
         return st;
     if (m->table)
@@ -89,9 +89,9 @@ sslbm::GridDesc grid_of(const sslbm_model *m) {
 
 extern "C" {
 
-int sslbm_model_create(sslbm_model **out, int nx, int ny, int dtype, int bc, int lattice,
-                       int compartments, const double *d, const int *counted, double dx,
-                       double dt, int ntransitions, const sslbm_transition *t) {
+sslbm_status sslbm_model_create(sslbm_model **out, int nx, int ny, int dtype, int bc,
+                                int lattice, int compartments, const double *d, const int *counted,
+                                double dx, double dt, int ntransitions, const sslbm_transition *t) {
     if (!out)
         return SSLBM_E_ARG;
     *out = nullptr;
@@ -150,21 +150,21 @@ int sslbm_model_create(sslbm_model **out, int nx, int ny, int dtype, int bc, int
     return SSLBM_OK;
 }
 
-int sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hip_stream) {
+sslbm_status sslbm_model_step(sslbm_model *m, const void *rho_in, void *rho_out, void *hip_stream) {
     if (!m || !rho_in || !rho_out)
         return SSLBM_E_ARG;
     const size_t bytes = state_bytes(m);
     if (overlap(rho_in, bytes, rho_out, bytes))
         return SSLBM_E_ALIAS;
-    const int st = ensure_table(m);
+    const sslbm_status st = ensure_table(m);
     if (st != SSLBM_OK)
         return st;
     return hip_status(m, sslbm::launch_model(m->dtype, m->lattice, rho_in, rho_out, grid_of(m),
                                              m->coef, m->table, 1, (hipStream_t)hip_stream));
 }
 
-int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
-                    void *hip_stream) {
+sslbm_status sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
+                             void *hip_stream) {
     if (!m || !rho || !scratch || nsteps < 0)
         return SSLBM_E_ARG;
     const size_t bytes = state_bytes(m);
@@ -172,7 +172,7 @@ int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
         return SSLBM_E_ALIAS;
     if (nsteps == 0)
         return SSLBM_OK;
-    const int tst = ensure_table(m);
+    const sslbm_status tst = ensure_table(m);
     if (tst != SSLBM_OK)
         return tst;
     const hipStream_t s = (hipStream_t)hip_stream;
@@ -180,7 +180,7 @@ int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
     void *src = rho, *dst = scratch;
     for (long long n = 0; n < nsteps;) {
         const int k = nsteps - n < K ? (int)(nsteps - n) : K;
-        const int st = hip_status(m, sslbm::launch_model(m->dtype, m->lattice, src, dst,
+        const sslbm_status st = hip_status(m, sslbm::launch_model(m->dtype, m->lattice, src, dst,
                                                          grid_of(m), m->coef, m->table, k, s));
         if (st != SSLBM_OK)
             return st;
@@ -194,14 +194,14 @@ int sslbm_model_run(sslbm_model *m, void *rho, void *scratch, long long nsteps,
     return SSLBM_OK;
 }
 
-int sslbm_model_set_blocking(sslbm_model *m, int steps_per_pass) {
+sslbm_status sslbm_model_set_blocking(sslbm_model *m, int steps_per_pass) {
     if (!m || steps_per_pass < 0 || steps_per_pass > SSLBM_MODEL_MAX_BLOCKING)
         return SSLBM_E_ARG;
     m->blocking = steps_per_pass;
     return SSLBM_OK;
 }
 
-int sslbm_model_get_blocking(const sslbm_model *m, int *steps_per_pass) {
+sslbm_status sslbm_model_get_blocking(const sslbm_model *m, int *steps_per_pass) {
     if (!m || !steps_per_pass)
         return SSLBM_E_ARG;
     *steps_per_pass = resolved_blocking(m);

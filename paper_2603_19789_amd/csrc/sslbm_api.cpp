@@ -35,7 +35,7 @@ sslbm::GridDesc grid_of(const sslbm_ctx *c) {
     return g;
 }
 
-int hip_status(sslbm_ctx *c, hipError_t e) {
+sslbm_status hip_status(sslbm_ctx *c, hipError_t e) {
     if (e == hipSuccess)
         return SSLBM_OK;
     c->last_hip = (int)e;
@@ -121,12 +121,12 @@ sslbm::MarchShape shape_for(const sslbm_ctx *c, int k, const void *in, const voi
 namespace sslbm {
 
 // One pass of k steps, in -> out, with the context's pass shape.
-int run_pass(sslbm_ctx *c, const void *in, void *out, int k, hipStream_t s) {
+sslbm_status run_pass(sslbm_ctx *c, const void *in, void *out, int k, hipStream_t s) {
     return hip_status(c, launch_march(c->dtype, in, out, grid_of(c), c->coef, k,
                                       shape_for(c, k, in, out), s));
 }
 
-int run_pass_mid2(sslbm_ctx *c, const void *in, void *mid, void *out, hipStream_t s) {
+sslbm_status run_pass_mid2(sslbm_ctx *c, const void *in, void *mid, void *out, hipStream_t s) {
     // both outputs pair-aligned for two columns per lane
     MarchShape shape = shape_for(c, 4, in, out);
     if ((uintptr_t)mid % (2 * elem_size(c)) != 0)
@@ -138,7 +138,7 @@ int run_pass_mid2(sslbm_ctx *c, const void *in, void *mid, void *out, hipStream_
 static bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
 // Validation of sslbm_params and the derived per-step constants.
-int derive_coef(const sslbm_params *p, StepCoef *k) {
+sslbm_status derive_coef(const sslbm_params *p, StepCoef *k) {
     if (!p)
         return SSLBM_E_ARG;
     if (!finite_nonneg(p->beta) || !finite_nonneg(p->alpha) || !finite_nonneg(p->gamma) ||
@@ -197,7 +197,8 @@ PassPlan plan_passes(long long nsteps, int K) {
 
 extern "C" {
 
-int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_params *p) {
+sslbm_status sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc,
+                        const sslbm_params *p) {
     if (!out || !p)
         return SSLBM_E_ARG;
     *out = nullptr;
@@ -208,7 +209,7 @@ int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_p
     if (bc != SSLBM_PERIODIC && bc != SSLBM_NOFLUX)
         return SSLBM_E_ARG;
     sslbm::StepCoef k;
-    const int st = sslbm::derive_coef(p, &k);
+    const sslbm_status st = sslbm::derive_coef(p, &k);
     if (st != SSLBM_OK)
         return st;
     sslbm_ctx *c = new (std::nothrow) sslbm_ctx();
@@ -224,8 +225,8 @@ int sslbm_init(sslbm_ctx **out, int nx, int ny, int dtype, int bc, const sslbm_p
     return SSLBM_OK;
 }
 
-int sslbm_params_from_rates(double beta, double sigma, double gamma, double mu, const double d[5],
-                            double dx, double dt, sslbm_params *out) {
+sslbm_status sslbm_params_from_rates(double beta, double sigma, double gamma, double mu,
+                                     const double d[5], double dx, double dt, sslbm_params *out) {
     const double rates[4] = {beta, sigma, gamma, mu};
     if (!out || !d)
         return SSLBM_E_ARG;
@@ -248,8 +249,8 @@ int sslbm_params_from_rates(double beta, double sigma, double gamma, double mu, 
     return SSLBM_OK;
 }
 
-int sslbm_rate_gradients(const double grad_params[4], double gamma, double mu,
-                         double grad_rates[4]) {
+sslbm_status sslbm_rate_gradients(const double grad_params[4], double gamma, double mu,
+                                  double grad_rates[4]) {
     if (!grad_params || !grad_rates || !std::isfinite(gamma) || !std::isfinite(mu) ||
         gamma < 0.0 || mu < 0.0 || !(gamma + mu > 0.0))
         return SSLBM_E_ARG;
@@ -263,11 +264,11 @@ int sslbm_rate_gradients(const double grad_params[4], double gamma, double mu,
     return SSLBM_OK;
 }
 
-int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p) {
+sslbm_status sslbm_set_params(sslbm_ctx *c, const sslbm_params *p) {
     if (!c)
         return SSLBM_E_ARG;
     sslbm::StepCoef k;
-    const int st = sslbm::derive_coef(p, &k);
+    const sslbm_status st = sslbm::derive_coef(p, &k);
     if (st != SSLBM_OK)
         return st;
     c->p = *p;
@@ -275,7 +276,7 @@ int sslbm_set_params(sslbm_ctx *c, const sslbm_params *p) {
     return SSLBM_OK;
 }
 
-int sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape) {
+sslbm_status sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape) {
     if (!c || !shape)
         return SSLBM_E_ARG;
     const sslbm_launch &r = *shape;
@@ -292,22 +293,22 @@ int sslbm_set_launch(sslbm_ctx *c, const sslbm_launch *shape) {
     return SSLBM_OK;
 }
 
-int sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape) {
+sslbm_status sslbm_get_launch(const sslbm_ctx *c, sslbm_launch *shape) {
     if (!c || !shape)
         return SSLBM_E_ARG;
     *shape = resolve(c);
     return SSLBM_OK;
 }
 
-int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream,
-               sslbm_launch *best) {
+sslbm_status sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream,
+                        sslbm_launch *best) {
     if (!c || !rho || !scratch)
         return SSLBM_E_ARG;
     const size_t bytes = 5 * plane_elems(c) * elem_size(c);
     if (overlap(rho, bytes, scratch, bytes))
         return SSLBM_E_ALIAS;
     const hipStream_t s = (hipStream_t)hip_stream;
-    int st = hip_status(c, hipStreamSynchronize(s));
+    sslbm_status st = hip_status(c, hipStreamSynchronize(s));
     if (st != SSLBM_OK)
         return st;
     hipEvent_t t0, t1;
@@ -368,8 +369,8 @@ int sslbm_tune(sslbm_ctx *c, const void *rho, void *scratch, void *hip_stream,
     return SSLBM_OK;
 }
 
-int sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int *longest,
-                   int *shortest) {
+sslbm_status sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int *longest,
+                            int *shortest) {
     if (!c || nsteps < 0 || !passes)
         return SSLBM_E_ARG;
     const sslbm::PassPlan p = sslbm::plan_passes(nsteps, resolve(c).steps_per_pass);
@@ -381,7 +382,7 @@ int sslbm_plan_run(const sslbm_ctx *c, long long nsteps, long long *passes, int 
     return SSLBM_OK;
 }
 
-int sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass) {
+sslbm_status sslbm_set_blocking(sslbm_ctx *c, int steps_per_pass) {
     if (!c)
         return SSLBM_E_ARG;
     sslbm_launch r = c->launch;
@@ -395,7 +396,7 @@ int sslbm_get_blocking(const sslbm_ctx *c) {
     return resolve(c).steps_per_pass;
 }
 
-int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream) {
+sslbm_status sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream) {
     if (!c || !rho_in || !rho_out)
         return SSLBM_E_ARG;
     const size_t bytes = 5 * plane_elems(c) * elem_size(c);
@@ -406,7 +407,7 @@ int sslbm_step(sslbm_ctx *c, const void *rho_in, void *rho_out, void *hip_stream
                                              (hipStream_t)hip_stream));
 }
 
-int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream) {
+sslbm_status sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hip_stream) {
     if (!c || !rho || !scratch || nsteps < 0)
         return SSLBM_E_ARG;
     const size_t bytes = 5 * plane_elems(c) * elem_size(c);
@@ -421,7 +422,7 @@ int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hi
     const sslbm::PassPlan plan = sslbm::plan_passes(nsteps, K);
     for (long long i = 0; i < plan.count; ++i) {
         const int k = plan.steps(i);
-        const int st =
+        const sslbm_status st =
             hip_status(c, sslbm::launch_march(c->dtype, src, dst, g, c->coef, k,
                                               shape_for(c, k, src, dst), s));
         if (st != SSLBM_OK)
@@ -435,7 +436,7 @@ int sslbm_run(sslbm_ctx *c, void *rho, void *scratch, long long nsteps, void *hi
     return SSLBM_OK;
 }
 
-static int bgk_check(const sslbm_ctx *c) {
+static sslbm_status bgk_check(const sslbm_ctx *c) {
     if (!c)
         return SSLBM_E_ARG;
     if (c->p.d[4] != 0.0)
@@ -443,8 +444,8 @@ static int bgk_check(const sslbm_ctx *c) {
     return SSLBM_OK;
 }
 
-int bgk_init(sslbm_ctx *c, const void *rho, void *f, void *rhoD, void *hip_stream) {
-    int st = bgk_check(c);
+sslbm_status bgk_init(sslbm_ctx *c, const void *rho, void *f, void *rhoD, void *hip_stream) {
+    sslbm_status st = bgk_check(c);
     if (st != SSLBM_OK)
         return st;
     if (!rho || !f || !rhoD)
@@ -457,9 +458,9 @@ int bgk_init(sslbm_ctx *c, const void *rho, void *f, void *rhoD, void *hip_strea
                                                 (hipStream_t)hip_stream));
 }
 
-int bgk_step(sslbm_ctx *c, const void *f_in, const void *rhoD_in, void *f_out, void *rhoD_out,
-             void *hip_stream) {
-    int st = bgk_check(c);
+sslbm_status bgk_step(sslbm_ctx *c, const void *f_in, const void *rhoD_in, void *f_out,
+                      void *rhoD_out, void *hip_stream) {
+    sslbm_status st = bgk_check(c);
     if (st != SSLBM_OK)
         return st;
     if (!f_in || !rhoD_in || !f_out || !rhoD_out)
@@ -478,9 +479,9 @@ int bgk_step(sslbm_ctx *c, const void *f_in, const void *rhoD_in, void *f_out, v
                                                 grid_of(c), c->coef, (hipStream_t)hip_stream));
 }
 
-int bgk_run(sslbm_ctx *c, void *f, void *rhoD, void *f_scratch, void *rhoD_scratch,
-            long long nsteps, void *hip_stream) {
-    int st = bgk_check(c);
+sslbm_status bgk_run(sslbm_ctx *c, void *f, void *rhoD, void *f_scratch, void *rhoD_scratch,
+                     long long nsteps, void *hip_stream) {
+    sslbm_status st = bgk_check(c);
     if (st != SSLBM_OK)
         return st;
     if (!f || !rhoD || !f_scratch || !rhoD_scratch || nsteps < 0)
@@ -515,8 +516,9 @@ int bgk_run(sslbm_ctx *c, void *f, void *rhoD, void *f_scratch, void *rhoD_scrat
     return SSLBM_OK;
 }
 
-int bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho, void *hip_stream) {
-    int st = bgk_check(c);
+sslbm_status bgk_density(sslbm_ctx *c, const void *f, const void *rhoD, void *rho,
+                         void *hip_stream) {
+    sslbm_status st = bgk_check(c);
     if (st != SSLBM_OK)
         return st;
     if (!f || !rhoD || !rho)
@@ -532,8 +534,8 @@ size_t sslbm_fd4_workspace_bytes(const sslbm_ctx *c) {
     return c ? 3 * 5 * plane_elems(c) * elem_size(c) : 0;
 }
 
-int sslbm_fd4_run(sslbm_ctx *c, void *rho, void *work, size_t work_bytes, long long nsteps,
-                  void *hip_stream) {
+sslbm_status sslbm_fd4_run(sslbm_ctx *c, void *rho, void *work, size_t work_bytes, long long nsteps,
+                           void *hip_stream) {
     if (!c || !rho || !work || nsteps < 0)
         return SSLBM_E_ARG;
     const size_t bytes = 5 * plane_elems(c) * elem_size(c);
@@ -547,13 +549,13 @@ int sslbm_fd4_run(sslbm_ctx *c, void *rho, void *work, size_t work_bytes, long l
                                            (hipStream_t)hip_stream));
 }
 
-int sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_stream) {
+sslbm_status sslbm_total(sslbm_ctx *c, const void *rho, double out_totals[5], void *hip_stream) {
     if (!c || !rho || !out_totals)
         return SSLBM_E_ARG;
     const sslbm::GridDesc g = grid_of(c);
     const int blocks = sslbm::total_blocks(g);
     int dev = 0;
-    int st = hip_status(c, hipGetDevice(&dev));
+    sslbm_status st = hip_status(c, hipGetDevice(&dev));
     if (st != SSLBM_OK)
         return st;
     if (!c->partials || c->partial_blocks < blocks || c->partial_device != dev) {

@@ -38,7 +38,7 @@ struct MarchShape {
 
 // ---- host helpers (sslbm_api.cpp) ---------------------------------------
 // Validate parameters and derive the per-step constants (SSLBM status code).
-int derive_coef(const sslbm_params *p, StepCoef *k);
+sslbm_status derive_coef(const sslbm_params *p, StepCoef *k);
 // How a run of nsteps splits into passes of at most K steps: the fewest
 // passes, made even where that leaves every pass a step (so that ping-pong
 // buffers end where they started), with the steps spread as evenly as possible over them (the
@@ -55,9 +55,9 @@ PassPlan plan_passes(long long nsteps, int K);
 
 // One pass of k steps (1 <= k <= the register limit), in -> out, with the
 // context's pass shape (SSLBM status code).
-int run_pass(sslbm_ctx *c, const void *in, void *out, int k, hipStream_t s);
+sslbm_status run_pass(sslbm_ctx *c, const void *in, void *out, int k, hipStream_t s);
 // One pass of 4 steps in -> out writing the state after 2 steps to mid.
-int run_pass_mid2(sslbm_ctx *c, const void *in, void *mid, void *out, hipStream_t s);
+sslbm_status run_pass_mid2(sslbm_ctx *c, const void *in, void *mid, void *out, hipStream_t s);
 
 // ---- launchers (sslbm_kernels.hip) --------------------------------------
 // K steps in one pass: in -> out (no overlap). K in 1..SSLBM_MAX_BLOCKING.

@@ -14,7 +14,7 @@ namespace {
 constexpr int MAX_SIDE = 1 << 16;
 constexpr int MAX_CHANNELS = 4096;
 
-int status(hipError_t e) { return e == hipSuccess ? SSLBM_OK : SSLBM_E_HIP; }
+sslbm_status status(hipError_t e) { return e == hipSuccess ? SSLBM_OK : SSLBM_E_HIP; }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -60,9 +60,10 @@ extern "C" {
 
 namespace {
 
-int conv_forward(const void *x, int x_pitch, int n, int h, int w, int cin, const void *weight,
-                 const float *bias, void *y, int y_pitch, int cout, int flags, float slope,
-                 void *pooled, int pooled_pitch, void *hip_stream) {
+sslbm_status conv_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
+                          const void *weight, const float *bias, void *y, int y_pitch, int cout,
+                          int flags, float slope, void *pooled, int pooled_pitch,
+                          void *hip_stream) {
     if (!view_ok(x, x_pitch, cin) || !dims_ok(n, h, w) || !weight || !aligned16(weight) || !y ||
         (flags & ~(SUR_LEAKY | SUR_OUT_F32)) || cout <= 0 || cout > MAX_CHANNELS ||
         y_pitch < cout || !std::isfinite(slope) || !conv_input_fits(x_pitch, n, h, w, cin))
@@ -94,10 +95,10 @@ int conv_forward(const void *x, int x_pitch, int n, int h, int w, int cin, const
 
 }  // namespace
 
-int sur_conv3x3_forward_up(const void *xu, int xu_pitch, int cu, const void *x, int x_pitch,
-                           int n, int h, int w, int cin, const void *weight, const float *bias,
-                           void *y, int y_pitch, int cout, int flags, float slope,
-                           void *hip_stream) {
+sslbm_status sur_conv3x3_forward_up(const void *xu, int xu_pitch, int cu, const void *x,
+                                    int x_pitch, int n, int h, int w, int cin, const void *weight,
+                                    const float *bias, void *y, int y_pitch, int cout, int flags,
+                                    float slope, void *hip_stream) {
     if (cu <= 0 || cu % 32 || cin <= cu || !view_ok(xu, xu_pitch, cu) ||
         !view_ok(x, x_pitch, cin - cu) || !dims_ok(n, h, w) || h % 2 || w % 2 || !weight ||
         !aligned16(weight) || (flags & ~SUR_LEAKY) || cout <= 0 || cout > MAX_CHANNELS ||
@@ -128,17 +129,17 @@ int sur_conv3x3_forward_up(const void *xu, int xu_pitch, int cu, const void *x, 
     return status(sslbm::launch_conv_fwd(a, flags & SUR_LEAKY, false, (hipStream_t)hip_stream));
 }
 
-int sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
-                        const void *weight, const float *bias, void *y, int y_pitch, int cout,
-                        int flags, float slope, void *hip_stream) {
+sslbm_status sur_conv3x3_forward(const void *x, int x_pitch, int n, int h, int w, int cin,
+                                 const void *weight, const float *bias, void *y, int y_pitch,
+                                 int cout, int flags, float slope, void *hip_stream) {
     return conv_forward(x, x_pitch, n, h, w, cin, weight, bias, y, y_pitch, cout, flags, slope,
                         nullptr, 0, hip_stream);
 }
 
-int sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, int cin,
-                             const void *weight, const float *bias, void *y, int y_pitch,
-                             int cout, int flags, float slope, void *pooled, int pooled_pitch,
-                             void *hip_stream) {
+sslbm_status sur_conv3x3_forward_pool(const void *x, int x_pitch, int n, int h, int w, int cin,
+                                      const void *weight, const float *bias, void *y, int y_pitch,
+                                      int cout, int flags, float slope, void *pooled,
+                                      int pooled_pitch, void *hip_stream) {
     if ((flags & SUR_OUT_F32) || h % 2 || w % 2 || !view_ok(pooled, pooled_pitch, cout))
         return SSLBM_E_ARG;
     return conv_forward(x, x_pitch, n, h, w, cin, weight, bias, y, y_pitch, cout, flags, slope,
@@ -149,9 +150,9 @@ namespace {
 
 // The backward-data convolution with weights already flipped (after the
 // arguments were checked), optionally through the activation adjoint.
-int backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
-                  const void *flipped, int cin, void *dx, int dx_pitch, const void *act,
-                  int act_pitch, float slope, hipStream_t s) {
+sslbm_status backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
+                           const void *flipped, int cin, void *dx, int dx_pitch, const void *act,
+                           int act_pitch, float slope, hipStream_t s) {
     sslbm::ConvArgs a;
     a.x = dz;
     a.x_pitch = dz_pitch;
@@ -188,22 +189,22 @@ bool act_ok(const void *act, int act_pitch, int c, float slope) {
 
 }  // namespace
 
-int sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
-                              const void *weight, int cin, void *dx, int dx_pitch,
-                              void *flip_scratch, void *hip_stream) {
+sslbm_status sur_conv3x3_backward_data(const void *dz, int dz_pitch, int n, int h, int w, int cout,
+                                       const void *weight, int cin, void *dx, int dx_pitch,
+                                       void *flip_scratch, void *hip_stream) {
     if (!backward_data_args_ok(dz, dz_pitch, n, h, w, cout, weight, cin, dx, dx_pitch) ||
         !flip_scratch || !aligned16(flip_scratch))
         return SSLBM_E_ARG;
     const hipStream_t s = (hipStream_t)hip_stream;
-    int st = status(sslbm::launch_flip(weight, cout, cin, flip_scratch, s));
+    sslbm_status st = status(sslbm::launch_flip(weight, cout, cin, flip_scratch, s));
     if (st != SSLBM_OK)
         return st;
     return backward_data(dz, dz_pitch, n, h, w, cout, flip_scratch, cin, dx, dx_pitch, nullptr, 0,
                          0.f, s);
 }
 
-int sur_flip_weights(int layers, const void *const *weight, const int *cout, const int *cin,
-                     void *const *flipped, void *hip_stream) {
+sslbm_status sur_flip_weights(int layers, const void *const *weight, const int *cout,
+                              const int *cin, void *const *flipped, void *hip_stream) {
     if (layers < 1 || layers > sslbm::SUR_MAX_FLIP_LAYERS || !weight || !cout || !cin || !flipped)
         return SSLBM_E_ARG;
     sslbm::FlipTable t{};
@@ -222,10 +223,10 @@ int sur_flip_weights(int layers, const void *const *weight, const int *cout, con
     return status(sslbm::launch_flip_multi(t, (hipStream_t)hip_stream));
 }
 
-int sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int n, int h, int w,
-                                      int cout, const void *flipped, int cin, void *dx,
-                                      int dx_pitch, const void *act, int act_pitch, float slope,
-                                      void *hip_stream) {
+sslbm_status sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int n, int h, int w,
+                                               int cout, const void *flipped, int cin, void *dx,
+                                               int dx_pitch, const void *act, int act_pitch,
+                                               float slope, void *hip_stream) {
     if (!backward_data_args_ok(dz, dz_pitch, n, h, w, cout, flipped, cin, dx, dx_pitch) ||
         !aligned16(flipped) || !act_ok(act, act_pitch, cin, slope) ||
         (act && !conv_input_fits(act_pitch, n, h, w, cin)))
@@ -241,9 +242,10 @@ size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int c
     return sslbm::wgrad_plan(n, h, w, cin, cout).bytes();
 }
 
-int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int dz_pitch, int n,
-                                int h, int w, int cin, int cout, float *dweight, float *dbias,
-                                void *workspace, size_t workspace_bytes, void *hip_stream) {
+sslbm_status sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int dz_pitch,
+                                         int n, int h, int w, int cin, int cout, float *dweight,
+                                         float *dbias, void *workspace, size_t workspace_bytes,
+                                         void *hip_stream) {
     if (!view_ok(x, x_pitch, cin) || !view_ok(dz, dz_pitch, cout) || !dims_ok(n, h, w) ||
         w % 8 || !dweight || !workspace || !aligned16(workspace) ||
         !conv_input_fits(x_pitch, n, h, w, cin) || !conv_input_fits(dz_pitch, n, h, w, cout))
@@ -255,11 +257,12 @@ int sur_conv3x3_backward_weight(const void *x, int x_pitch, const void *dz, int 
                                       (hipStream_t)hip_stream, nullptr));
 }
 
-int sur_conv3x3_backward_weight_overlap(const void *xu, int xu_pitch, int cu, const void *x,
-                                        int x_pitch, const void *dz, int dz_pitch, int n, int h,
-                                        int w, int cin, int cout, float *dweight, float *dbias,
-                                        void *workspace, size_t workspace_bytes,
-                                        void *hip_stream, void *sum_stream, void *event) {
+sslbm_status sur_conv3x3_backward_weight_overlap(const void *xu, int xu_pitch, int cu,
+                                                 const void *x, int x_pitch, const void *dz,
+                                                 int dz_pitch, int n, int h, int w, int cin,
+                                                 int cout, float *dweight, float *dbias,
+                                                 void *workspace, size_t workspace_bytes,
+                                                 void *hip_stream, void *sum_stream, void *event) {
     const int cx = xu ? cin - cu : cin;  // channels read from x
     if (!view_ok(x, x_pitch, cx) || !view_ok(dz, dz_pitch, cout) || !dims_ok(n, h, w) ||
         w % 8 || !dweight || !workspace || !aligned16(workspace) || cin > MAX_CHANNELS ||
@@ -280,10 +283,11 @@ int sur_conv3x3_backward_weight_overlap(const void *xu, int xu_pitch, int cu, co
                                       (hipStream_t)sum_stream, (hipEvent_t)event));
 }
 
-int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const void *x,
-                                   int x_pitch, const void *dz, int dz_pitch, int n, int h, int w,
-                                   int cin, int cout, float *dweight, float *dbias,
-                                   void *workspace, size_t workspace_bytes, void *hip_stream) {
+sslbm_status sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const void *x,
+                                            int x_pitch, const void *dz, int dz_pitch, int n, int h,
+                                            int w, int cin, int cout, float *dweight, float *dbias,
+                                            void *workspace, size_t workspace_bytes,
+                                            void *hip_stream) {
     if (cu <= 0 || cu % 32 || cin <= cu || cin > MAX_CHANNELS || !view_ok(xu, xu_pitch, cu) ||
         !view_ok(x, x_pitch, cin - cu) || !view_ok(dz, dz_pitch, cout) || !dims_ok(n, h, w) ||
         h % 2 || w % 8 || !dweight || !workspace || !aligned16(workspace) ||
@@ -300,8 +304,9 @@ int sur_conv3x3_backward_weight_up(const void *xu, int xu_pitch, int cu, const v
                                       (hipStream_t)hip_stream, nullptr));
 }
 
-int sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,
-                       int dz_pitch, long long pixels, int c, float slope, void *hip_stream) {
+sslbm_status sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch, void *dz,
+                                int dz_pitch, long long pixels, int c, float slope,
+                                void *hip_stream) {
     if (!view_ok(dy, dy_pitch, c) || !view_ok(y, y_pitch, c) || !view_ok(dz, dz_pitch, c) ||
         pixels <= 0 || !std::isfinite(slope))
         return SSLBM_E_ARG;
@@ -309,15 +314,15 @@ int sur_leaky_backward(const void *dy, int dy_pitch, const void *y, int y_pitch,
                                           (hipStream_t)hip_stream));
 }
 
-int sur_pool2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
-              void *hip_stream) {
+sslbm_status sur_pool2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
+                       void *hip_stream) {
     if (!view_ok(x, x_pitch, c) || !view_ok(y, y_pitch, c) || !dims_ok(n, h, w) || h % 2 || w % 2)
         return SSLBM_E_ARG;
     return status(sslbm::launch_pool2(x, x_pitch, n, h, w, c, y, y_pitch, (hipStream_t)hip_stream));
 }
 
-int sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
-                       int dx_pitch, int accumulate, void *hip_stream) {
+sslbm_status sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                                int dx_pitch, int accumulate, void *hip_stream) {
     if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, h, w) || h % 2 ||
         w % 2)
         return SSLBM_E_ARG;
@@ -325,9 +330,9 @@ int sur_pool2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c,
                                           nullptr, 0, 0.f, (hipStream_t)hip_stream));
 }
 
-int sur_pool2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
-                           int dx_pitch, int accumulate, const void *act, int act_pitch,
-                           float slope, void *hip_stream) {
+sslbm_status sur_pool2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c,
+                                    void *dx, int dx_pitch, int accumulate, const void *act,
+                                    int act_pitch, float slope, void *hip_stream) {
     if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, h, w) || h % 2 ||
         w % 2 || !act || !act_ok(act, act_pitch, c, slope))
         return SSLBM_E_ARG;
@@ -335,24 +340,24 @@ int sur_pool2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, in
                                           act, act_pitch, slope, (hipStream_t)hip_stream));
 }
 
-int sur_up2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
-            void *hip_stream) {
+sslbm_status sur_up2(const void *x, int x_pitch, int n, int h, int w, int c, void *y, int y_pitch,
+                     void *hip_stream) {
     if (!view_ok(x, x_pitch, c) || !view_ok(y, y_pitch, c) || !dims_ok(n, 2 * h, 2 * w))
         return SSLBM_E_ARG;
     return status(sslbm::launch_up2(x, x_pitch, n, h, w, c, y, y_pitch, (hipStream_t)hip_stream));
 }
 
-int sur_up2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
-                     int dx_pitch, void *hip_stream) {
+sslbm_status sur_up2_backward(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
+                              int dx_pitch, void *hip_stream) {
     if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, 2 * h, 2 * w))
         return SSLBM_E_ARG;
     return status(sslbm::launch_up2_bwd(dy, dy_pitch, n, h, w, c, dx, dx_pitch, nullptr, 0, 0.f,
                                         (hipStream_t)hip_stream));
 }
 
-int sur_up2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c, void *dx,
-                         int dx_pitch, const void *act, int act_pitch, float slope,
-                         void *hip_stream) {
+sslbm_status sur_up2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int c,
+                                  void *dx, int dx_pitch, const void *act, int act_pitch,
+                                  float slope, void *hip_stream) {
     if (!view_ok(dy, dy_pitch, c) || !view_ok(dx, dx_pitch, c) || !dims_ok(n, 2 * h, 2 * w) ||
         !act || !act_ok(act, act_pitch, c, slope))
         return SSLBM_E_ARG;
@@ -360,25 +365,25 @@ int sur_up2_backward_act(const void *dy, int dy_pitch, int n, int h, int w, int 
                                         slope, (hipStream_t)hip_stream));
 }
 
-int sur_pack_input(const float *rho, int batch, int h, int w, const float *planes,
-                   const float *scale_in, void *x, void *hip_stream) {
+sslbm_status sur_pack_input(const float *rho, int batch, int h, int w, const float *planes,
+                            const float *scale_in, void *x, void *hip_stream) {
     if (!rho || !planes || !x || !aligned16(x) || !dims_ok(batch, h, w) || !scales_ok(scale_in))
         return SSLBM_E_ARG;
     return status(sslbm::launch_pack_input(rho, batch, h, w, planes, make_scales(scale_in, nullptr),
                                            x, (hipStream_t)hip_stream));
 }
 
-int sur_apply_output(const float *rho, const float *out, int batch, int h, int w,
-                     const float *scale_out, float *rho_next, void *hip_stream) {
+sslbm_status sur_apply_output(const float *rho, const float *out, int batch, int h, int w,
+                              const float *scale_out, float *rho_next, void *hip_stream) {
     if (!rho || !out || !rho_next || !dims_ok(batch, h, w) || !scales_ok(scale_out))
         return SSLBM_E_ARG;
     return status(sslbm::launch_apply_output(rho, out, batch, h, w, make_scales(nullptr, scale_out),
                                              rho_next, (hipStream_t)hip_stream));
 }
 
-int sur_mse_loss(const float *out, const float *rho, const float *target, int batch, int h,
-                 int w, const float *scale_out, void *dout, double *partials, double *loss,
-                 void *hip_stream) {
+sslbm_status sur_mse_loss(const float *out, const float *rho, const float *target, int batch, int h,
+                          int w, const float *scale_out, void *dout, double *partials, double *loss,
+                          void *hip_stream) {
     if (!out || !rho || !target || !dout || !aligned16(dout) || !partials || !loss ||
         !dims_ok(batch, h, w) || !scales_ok(scale_out))
         return SSLBM_E_ARG;
@@ -386,9 +391,9 @@ int sur_mse_loss(const float *out, const float *rho, const float *target, int ba
                                     dout, partials, loss, (hipStream_t)hip_stream));
 }
 
-int sur_adam(float *theta, void *theta_bf16, const float *grad, float *m, float *v,
-             long long count, int step, float lr, float beta1, float beta2, float eps,
-             void *hip_stream) {
+sslbm_status sur_adam(float *theta, void *theta_bf16, const float *grad, float *m, float *v,
+                      long long count, int step, float lr, float beta1, float beta2, float eps,
+                      void *hip_stream) {
     if (!theta || !grad || !m || !v || count <= 0 || step < 1 || !(lr >= 0.f) ||
         !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
         return SSLBM_E_ARG;
@@ -403,14 +408,14 @@ int sur_adam(float *theta, void *theta_bf16, const float *grad, float *m, float 
                                      (hipStream_t)hip_stream));
 }
 
-int sur_crop_periodic(const float *rho, int h, int w, int y0, int x0, int ch, int cw, float *dst,
-                      void *hip_stream) {
+sslbm_status sur_crop_periodic(const float *rho, int h, int w, int y0, int x0, int ch, int cw,
+                               float *dst, void *hip_stream) {
     if (!rho || !dst || !dims_ok(1, h, w) || !dims_ok(1, ch, cw))
         return SSLBM_E_ARG;
     return status(sslbm::launch_crop(rho, h, w, y0, x0, ch, cw, dst, (hipStream_t)hip_stream));
 }
 
-int sur_to_bf16(const float *src, void *dst, long long count, void *hip_stream) {
+sslbm_status sur_to_bf16(const float *src, void *dst, long long count, void *hip_stream) {
     if (!src || !dst || count <= 0)
         return SSLBM_E_ARG;
     return status(sslbm::launch_to_bf16(src, dst, count, (hipStream_t)hip_stream));

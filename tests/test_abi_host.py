@@ -12,7 +12,7 @@ from paper_2603_19789_amd import binding
 from paper_2603_19789_amd.binding import Params
 from paper_2603_19789_amd.inputs import c1_params
 
-SIG_RE = re.compile(r"^\s*(?:int|void|long\s+long|size_t|const\s+char\s*\*)\s*\**\s*(\w+)\s*\(",
+SIG_RE = re.compile(r"^\s*(?:sslbm_status|int|void|long\s+long|size_t|const\s+char\s*\*)\s*\**\s*(\w+)\s*\(",
                     re.M)
 
 
