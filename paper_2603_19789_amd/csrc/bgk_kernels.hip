@@ -3,8 +3,10 @@
 // collide with f^eq = w_i rho and the source w_i Psi dt, and push each
 // post-collision population to x + c_i (periodic wrap, or half-way
 // bounce-back at a no-flux wall). One thread per node, rows of the grid on
-// blockIdx.y, so every population plane is read and written in coalesced
-// 256-node row segments (the pushed ones shifted by one node). Stores keep
+// blockIdx.y (grids taller than the 65535 rows a launch can span take rows
+// y, y + 65535, ... in one workgroup), so every population plane is read and
+// written in coalesced 256-node row segments (the pushed ones shifted by one
+// node). Stores keep
 // the default cache policy: the pushed rows are shifted by one node, and L2
 // merges the partial lines (non-temporal stores measured 5% slower).
 #include <hip/hip_runtime.h>
@@ -28,16 +30,14 @@ __device__ __forceinline__ T weight(int i) {
     return i == 0 ? T(1) / T(3) : T(1) / T(6);
 }
 
+// Most rows a launch spans (the grid's y dimension).
+constexpr int BGK_MAX_GRID_ROWS = 65535;
+
+// One node (x, y): collide and push.
 template <typename T>
-__global__ __launch_bounds__(BGK_THREADS) void bgk_step_kernel(const T *__restrict__ f_in,
-                                                               const T *__restrict__ d_in,
-                                                               T *__restrict__ f_out,
-                                                               T *__restrict__ d_out, GridDesc g,
-                                                               BgkCoef<T> k) {
-    const int x = blockIdx.x * BGK_THREADS + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= g.nx)
-        return;
+__device__ __forceinline__ void bgk_node(const T *__restrict__ f_in, const T *__restrict__ d_in,
+                                         T *__restrict__ f_out, T *__restrict__ d_out,
+                                         const GridDesc &g, const BgkCoef<T> &k, int x, int y) {
     const long long plane = g.plane;
     const long long cell = (long long)y * g.nx + x;
 
@@ -92,40 +92,55 @@ __global__ __launch_bounds__(BGK_THREADS) void bgk_step_kernel(const T *__restri
 }
 
 template <typename T>
+__global__ __launch_bounds__(BGK_THREADS) void bgk_step_kernel(const T *__restrict__ f_in,
+                                                               const T *__restrict__ d_in,
+                                                               T *__restrict__ f_out,
+                                                               T *__restrict__ d_out, GridDesc g,
+                                                               BgkCoef<T> k) {
+    const int x = blockIdx.x * BGK_THREADS + threadIdx.x;
+    if (x >= g.nx)
+        return;
+    for (int y = blockIdx.y; y < g.ny; y += gridDim.y)
+        bgk_node(f_in, d_in, f_out, d_out, g, k, x, y);
+}
+
+template <typename T>
 __global__ __launch_bounds__(BGK_THREADS) void bgk_init_kernel(const T *__restrict__ rho,
                                                                T *__restrict__ f,
                                                                T *__restrict__ rhoD, GridDesc g) {
-    const long long cell = (long long)blockIdx.x * BGK_THREADS + threadIdx.x;
-    if (cell >= g.plane)
-        return;
     const long long plane = g.plane;
+    const long long stride = (long long)gridDim.x * BGK_THREADS;
+    for (long long cell = (long long)blockIdx.x * BGK_THREADS + threadIdx.x; cell < plane;
+         cell += stride) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const T r = rho[c * plane + cell];
+        for (int c = 0; c < 4; ++c) {
+            const T r = rho[c * plane + cell];
 #pragma unroll
-        for (int i = 0; i < 5; ++i)
-            f[(c * 5 + i) * plane + cell] = weight<T>(i) * r;
+            for (int i = 0; i < 5; ++i)
+                f[(c * 5 + i) * plane + cell] = weight<T>(i) * r;
+        }
+        rhoD[cell] = rho[4 * plane + cell];
     }
-    rhoD[cell] = rho[4 * plane + cell];
 }
 
 template <typename T>
 __global__ __launch_bounds__(BGK_THREADS) void bgk_density_kernel(const T *__restrict__ f,
                                                                   const T *__restrict__ rhoD,
                                                                   T *__restrict__ rho, GridDesc g) {
-    const long long cell = (long long)blockIdx.x * BGK_THREADS + threadIdx.x;
-    if (cell >= g.plane)
-        return;
     const long long plane = g.plane;
+    const long long stride = (long long)gridDim.x * BGK_THREADS;
+    for (long long cell = (long long)blockIdx.x * BGK_THREADS + threadIdx.x; cell < plane;
+         cell += stride) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        T s = T(0);
+        for (int c = 0; c < 4; ++c) {
+            T s = T(0);
 #pragma unroll
-        for (int i = 0; i < 5; ++i)
-            s += f[(c * 5 + i) * plane + cell];
-        rho[c * plane + cell] = s;
+            for (int i = 0; i < 5; ++i)
+                s += f[(c * 5 + i) * plane + cell];
+            rho[c * plane + cell] = s;
+        }
+        rho[4 * plane + cell] = rhoD[cell];
     }
-    rho[4 * plane + cell] = rhoD[cell];
 }
 
 template <typename T>
@@ -143,13 +158,17 @@ static BgkCoef<T> bgk_coef(const StepCoef &s) {
     return b;
 }
 
+// One thread per cell, at most 2^22 workgroups (2^30 work-items, within a
+// launch's 32-bit work-item count); larger planes loop.
 static dim3 plane_grid(const GridDesc &g) {
-    return dim3((unsigned)((g.plane + BGK_THREADS - 1) / BGK_THREADS));
+    const long long blocks = (g.plane + BGK_THREADS - 1) / BGK_THREADS;
+    return dim3((unsigned)(blocks < (1ll << 22) ? blocks : (1ll << 22)));
 }
 
 hipError_t launch_bgk_step(int dtype, const void *f_in, const void *rhoD_in, void *f_out,
                            void *rhoD_out, const GridDesc &g, const StepCoef &k, hipStream_t s) {
-    const dim3 grid((g.nx + BGK_THREADS - 1) / BGK_THREADS, g.ny);
+    const dim3 grid((g.nx + BGK_THREADS - 1) / BGK_THREADS,
+                    g.ny < BGK_MAX_GRID_ROWS ? g.ny : BGK_MAX_GRID_ROWS);
     if (dtype == SSLBM_F32)
         hipLaunchKernelGGL(bgk_step_kernel<float>, grid, dim3(BGK_THREADS), 0, s,
                            (const float *)f_in, (const float *)rhoD_in, (float *)f_out,
