@@ -98,6 +98,26 @@ sslbm_status sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int
                                                int dx_pitch, const void *act, int act_pitch,
                                                float slope, void *hip_stream);
 
+/* The backward-data pass of a decoder's first convolution, whose first cu
+ * input channels were the 2x nearest upsampling of a half-resolution
+ * tensor u (the upsampled-input convolution sur_conv3x3_forward_up):
+ * sur_conv3x3_backward_data_flipped into dx for channels [cu, cin) (dx's
+ * channels [0, cu) are undefined afterwards), and the gradient of u into du
+ * (n, h/2, w/2, cu channels): each 2x2 window of the upsampled channels'
+ * BF16-rounded gradient summed, rounded to BF16 and, when du_act is not
+ * NULL, passed through the leaky activation's adjoint with du_act (a BF16
+ * view of cu channels at du's pixels, the activation's output). Bit for
+ * bit sur_conv3x3_backward_data_flipped into dx followed by
+ * sur_up2_backward_act (or sur_up2_backward) from dx's first cu channels
+ * into du, in one pass on images of at least 8 x 32 pixels and as those
+ * two passes on smaller ones. cu: a multiple of 16, at most cin; h and w
+ * even. du may not overlap dz, dx or du_act. */
+sslbm_status sur_conv3x3_backward_data_up(const void *dz, int dz_pitch, int n, int h, int w,
+                                          int cout, const void *flipped, int cin, int cu,
+                                          void *dx, int dx_pitch, void *du, int du_pitch,
+                                          const void *du_act, int du_act_pitch, float slope,
+                                          void *hip_stream);
+
 /* Workspace bytes of sur_conv3x3_backward_weight for these sizes (0 if invalid). */
 size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int cout);
 

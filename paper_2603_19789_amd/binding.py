@@ -143,6 +143,8 @@ def library() -> ctypes.CDLL:
             "sur_conv3x3_backward_weight_up": [vp, i, i, vp, i, vp, i, i, i, i, i, i, vp, vp, vp,
                                                sz, vp],
             "sur_conv3x3_backward_data_flipped": [vp, i, i, i, i, i, vp, i, vp, i, vp, i, f, vp],
+            "sur_conv3x3_backward_data_up": [vp, i, i, i, i, i, vp, i, i, vp, i, vp, i, vp, i, f,
+                                             vp],
             "sur_conv3x3_backward_weight_overlap": [vp, i, i, vp, i, vp, i, i, i, i, i, i, vp, vp,
                                                     vp, sz, vp, vp, vp],
             "sur_flip_weights": [i, ctypes.POINTER(vp), ctypes.POINTER(i), ctypes.POINTER(i),

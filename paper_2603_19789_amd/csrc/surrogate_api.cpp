@@ -235,6 +235,52 @@ sslbm_status sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int
                          slope, (hipStream_t)hip_stream);
 }
 
+sslbm_status sur_conv3x3_backward_data_up(const void *dz, int dz_pitch, int n, int h, int w,
+                                          int cout, const void *flipped, int cin, int cu,
+                                          void *dx, int dx_pitch, void *du, int du_pitch,
+                                          const void *du_act, int du_act_pitch, float slope,
+                                          void *hip_stream) {
+    if (!backward_data_args_ok(dz, dz_pitch, n, h, w, cout, flipped, cin, dx, dx_pitch) ||
+        !aligned16(flipped) || cu <= 0 || cu % 16 || cu > cin || h % 2 || w % 2 ||
+        !view_ok(du, du_pitch, cu) || !act_ok(du_act, du_act_pitch, cu, slope) ||
+        (du_act && !conv_input_fits(du_act_pitch, n, h / 2, w / 2, cu)) ||
+        !conv_input_fits(du_pitch, n, h / 2, w / 2, cu))
+        return SSLBM_E_ARG;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    sslbm::ConvArgs a;
+    a.x = dz;
+    a.x_pitch = dz_pitch;
+    a.n = n;
+    a.h = h;
+    a.w = w;
+    a.cin = cout;
+    a.wt = flipped;
+    a.bias = nullptr;
+    a.y = dx;
+    a.y_pitch = dx_pitch;
+    a.cout = cin;
+    a.slope = slope;
+    a.pool = nullptr;
+    a.pool_pitch = 0;
+    a.xu = nullptr;
+    a.xu_pitch = a.cu = 0;
+    a.du = du;
+    a.du_pitch = du_pitch;
+    a.cd = cu;
+    a.du_mask = du_act;
+    a.du_mask_pitch = du_act ? du_act_pitch : 0;
+    const hipError_t e = sslbm::launch_conv_fwd(a, false, false, s);
+    if (e != hipErrorNotSupported)
+        return status(e);
+    // images too small for halo tiles: the two passes
+    sslbm_status st =
+        backward_data(dz, dz_pitch, n, h, w, cout, flipped, cin, dx, dx_pitch, nullptr, 0, 0.f, s);
+    if (st != SSLBM_OK)
+        return st;
+    return status(sslbm::launch_up2_bwd(dx, dx_pitch, n, h / 2, w / 2, cu, du, du_pitch, du_act,
+                                        du_act ? du_act_pitch : 0, slope, s));
+}
+
 size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int cout) {
     if (!dims_ok(n, h, w) || cin <= 0 || cin % 8 || cout <= 0 || cout % 8 ||
         cin > MAX_CHANNELS || cout > MAX_CHANNELS || w % 8)

@@ -304,10 +304,19 @@ constexpr int HALO_TH = 8, HALO_TW = 32;
 // applies the adjoint of the activation that produced the pass's output
 // tensor, reading that activation from a.mask (see ConvArgs), with the
 // roundings of a separate sur_leaky_backward over the stored values.
-template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP, bool MASK>
+// UPB (BF16 output; the backward-data pass of a decoder's first convolution,
+// whose first a.cd input channels were a 2x upsampling): output channels
+// below a.cd are kept in registers instead of stored; each 2 x 2 window of
+// their BF16-rounded values (all in one lane, as for POOL) is summed in the
+// order of the separate upsampling adjoint, rounded, passed through the
+// activation adjoint with a.du_mask when given, and written to the
+// half-resolution view a.du: the bits of the two separate passes.
+template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP, bool MASK, bool UPB>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(NT == 4 ? 2 : 3)))
 void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     static_assert(!MASK || (!F32OUT && !POOL), "the mask applies to plain BF16 outputs");
+    static_assert(!UPB || (!F32OUT && !LEAKY && !POOL && !UP && !MASK),
+                  "the upsampling adjoint goes with plain BF16 outputs");
     constexpr int HW2 = HALO_TW + 2, HPIX = (HALO_TH + 2) * HW2;
     constexpr int HP = HPIX * 4, HPT = (HP + THREADS - 1) / THREADS;  // 16-byte pieces
     constexpr int TC = 16 * NT;
@@ -503,6 +512,15 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
         MASK ? const_cast<void *>(a.mask) : a.y, (short)0,
         MASK ? (int)(((P - 1) * a.mask_pitch + a.cout) * 2) : 0, BUF_FORMAT_WORD);
     const unsigned mpb = (unsigned)(a.mask_pitch * 2);
+    const __amdgpu_buffer_rsrc_t ur = __builtin_amdgcn_make_buffer_rsrc(
+        UPB ? a.du : a.y, (short)0,
+        UPB ? (int)((((long long)a.n * hp * wp - 1) * a.du_pitch + a.cd) * 2) : 0,
+        BUF_FORMAT_WORD);
+    const bool umask = UPB && a.du_mask;
+    const __amdgpu_buffer_rsrc_t umr = __builtin_amdgcn_make_buffer_rsrc(
+        umask ? const_cast<void *>(a.du_mask) : a.y, (short)0,
+        umask ? (int)((((long long)a.n * hp * wp - 1) * a.du_mask_pitch + a.cd) * 2) : 0,
+        BUF_FORMAT_WORD);
     auto epilogue = [&](int unit) {
         int n, y0, x0, cg;
         unit_origin(unit, n, y0, x0, cg);
@@ -512,7 +530,10 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
             const int c = cg * TC + 16 * ns + m;
             const bool c_ok = c < a.cout;
             const float b = Cs[16 * ns + m];
-            float fv[4][4];  // the stored BF16 values, as floats (POOL only)
+            // UPB: this 16-channel block belongs to the upsampled input
+            // (wavefront-uniform; cd is a multiple of 16)
+            const bool up_block = UPB && cg * TC + 16 * ns < a.cd;
+            float fv[4][4];  // the stored BF16 values, as floats (POOL, UPB)
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 if (yr + r >= a.h)
@@ -558,11 +579,51 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
                                     __builtin_bit_cast(float, (unsigned)mk[ms][i] << 16);
                                 hv = to_bf16(mv > 0.f ? d : a.slope * d);
                             }
-                            __builtin_amdgcn_raw_buffer_store_b16(hv, yr_, off, 0, 0);
-                            if (POOL)
+                            if (!up_block)
+                                __builtin_amdgcn_raw_buffer_store_b16(hv, yr_, off, 0, 0);
+                            if (POOL || UPB)
                                 fv[ms][i] = __builtin_bit_cast(float, (unsigned)hv << 16);
                         }
                     }
+            }
+            if constexpr (UPB) {
+                if (up_block && yr + 1 < a.h) {  // wavefront-uniform; h is even
+                    const long long lrow = ((long long)n * hp + yr / 2) * wp;
+                    const unsigned urow = (unsigned)((lrow * a.du_pitch + c) * 2);
+                    const unsigned mrow = (unsigned)((lrow * a.du_mask_pitch + c) * 2);
+                    // window (rows yr, yr + 1; columns x, x + 1), x = x0 + 16 ms + 4 g + i
+                    unsigned off[2][2];
+                    unsigned short um[2][2];
+#pragma unroll
+                    for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            const int x = x0 + 16 * ms + 4 * g + 2 * j;
+                            const bool ok = c_ok && x < a.w;
+                            off[ms][j] = ok ? urow + (unsigned)(x / 2 * a.du_pitch * 2)
+                                            : OUT_OF_RANGE;
+                            if (umask)
+                                um[ms][j] = __builtin_amdgcn_raw_buffer_load_b16(
+                                    umr, ok ? mrow + (unsigned)(x / 2 * a.du_mask_pitch * 2)
+                                            : OUT_OF_RANGE,
+                                    0, 0);
+                        }
+#pragma unroll
+                    for (int ms = 0; ms < 2; ++ms)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            const int i = 2 * j;
+                            const float sum =
+                                ((fv[ms][i] + fv[ms][i + 1]) + fv[ms + 2][i]) + fv[ms + 2][i + 1];
+                            unsigned short hs = to_bf16(sum);
+                            if (umask) {
+                                const float d = __builtin_bit_cast(float, (unsigned)hs << 16);
+                                const float mv = __builtin_bit_cast(float, (unsigned)um[ms][j] << 16);
+                                hs = to_bf16(mv > 0.f ? d : a.slope * d);
+                            }
+                            __builtin_amdgcn_raw_buffer_store_b16(hs, ur, off[ms][j], 0, 0);
+                        }
+                }
             }
             if constexpr (POOL && !F32OUT) {
                 if (yr + 1 < a.h) {  // wavefront-uniform; h is even
@@ -1575,21 +1636,24 @@ static int resident_workgroups(const void *f, std::atomic<int> *cache) {
     return cus * per_cu;
 }
 
-template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP = false, bool MASK = false>
+template <int NT, bool F32OUT, bool LEAKY, bool POOL, bool UP = false, bool MASK = false,
+          bool UPB = false>
 static void conv_halo_go(const ConvArgs &a, hipStream_t s) {
     static std::atomic<int> cache[MAX_DEVICES];  // zero-initialised (static storage)
     const int tiles_x = (a.w + HALO_TW - 1) / HALO_TW, tiles_y = (a.h + HALO_TH - 1) / HALO_TH;
     const int units = a.n * tiles_x * tiles_y * ((a.cout + 16 * NT - 1) / (16 * NT));
-    const void *f = (const void *)conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP, MASK>;
+    const void *f = (const void *)conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP, MASK, UPB>;
     const int resident = resident_workgroups(f, cache);
     const int blocks = resident > 0 && resident < units ? resident : units;
-    hipLaunchKernelGGL((conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP, MASK>), dim3((unsigned)blocks),
-                       dim3(THREADS), 0, s, a, tiles_x, tiles_y, units);
+    hipLaunchKernelGGL((conv_halo_kernel<NT, F32OUT, LEAKY, POOL, UP, MASK, UPB>),
+                       dim3((unsigned)blocks), dim3(THREADS), 0, s, a, tiles_x, tiles_y, units);
 }
 
 template <int NT>
 static void conv_halo_cfg(const ConvArgs &a, bool leaky, bool f32out, hipStream_t s) {
-    if (a.mask) {  // the backward-data pass: BF16 output, no bias or activation
+    if (a.du) {  // backward-data with the upsampling adjoint: BF16, no bias
+        conv_halo_go<NT, false, false, false, false, false, true>(a, s);
+    } else if (a.mask) {  // the backward-data pass: BF16 output, no bias or activation
         conv_halo_go<NT, false, false, false, false, true>(a, s);
     } else if (a.xu) {  // BF16 output, no pooling (a decoder's first convolution)
         if (leaky)
@@ -1627,11 +1691,18 @@ hipError_t launch_conv_fwd(const ConvArgs &a, bool leaky, bool f32out, hipStream
         a.mask ? (((long long)a.n * a.h * a.w - 1) * a.mask_pitch + a.cout) * 2 : 0;
     if (a.mask && (leaky || f32out || a.pool || a.xu))
         return hipErrorInvalidValue;  // the mask goes with plain BF16 outputs only
+    if (a.du && (leaky || f32out || a.pool || a.xu || a.mask || a.cd <= 0 || a.cd % 16 ||
+                 a.cd > a.cout || a.h % 2 || a.w % 2))
+        return hipErrorInvalidValue;  // the upsampling adjoint: plain BF16, even sizes
+    const long long half = (long long)a.n * (a.h / 2) * (a.w / 2);
+    const long long du_bytes = a.du ? ((half - 1) * a.du_pitch + a.cd) * 2 : 0;
+    const long long du_mask_bytes = a.du_mask ? ((half - 1) * a.du_mask_pitch + a.cd) * 2 : 0;
     const bool halo = a.h >= HALO_TH && a.w >= HALO_TW && units < (1ll << 31) &&
                       out_bytes < (1ll << 31) && pool_bytes < (1ll << 31) &&
-                      mask_bytes < (1ll << 31);
-    if (a.xu && !halo)
-        return hipErrorNotSupported;  // the upsampled input needs halo tiles
+                      mask_bytes < (1ll << 31) && du_bytes < (1ll << 31) &&
+                      du_mask_bytes < (1ll << 31);
+    if ((a.xu || a.du) && !halo)
+        return hipErrorNotSupported;  // the upsampled input and its adjoint need halo tiles
     if (halo) {
         if (a.cout > 32)
             conv_halo_cfg<4>(a, leaky, f32out, s);

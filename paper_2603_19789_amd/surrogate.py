@@ -97,13 +97,16 @@ class UNet:
     state, and the forward and backward passes over a batch."""
 
     def __init__(self, levels: int = 4, base: int = 32, slope: float = 0.1, seed: int = 0,
-                 overlap_sums: bool = True):
+                 overlap_sums: bool = True, fuse_up_bwd: bool = True):
         torch = _torch()
         self.lib = library()
         self.levels, self.base, self.slope = levels, base, slope
         # the weight gradients' split sums on a second stream (True), or on
         # the pass's own stream (False); the same bits either way
         self.overlap_sums = overlap_sums
+        # a decoder's upsampling adjoint inside its first convolution's
+        # backward-data pass (True), or as a pass of its own; the same bits
+        self.fuse_up_bwd = fuse_up_bwd
         self.ch = [base * 2 ** l for l in range(levels)]
         convs = []
         c = IN_CHANNELS
@@ -340,14 +343,17 @@ class UNet:
                 for cv, l in self._levels_of_convs()]
             self._sets[self._shape] = tuple(getattr(self, name) for name in self._BUFFER_NAMES)
 
-    def _conv_backward(self, k, x, dz: _View, gx, act, l):
+    def _conv_backward(self, k, x, dz: _View, gx, act, l, up=None):
         """Gradients of conv k from dz (the gradient of its pre-activation
         output): weight and bias gradients into self.grad (their split sums
         on the side stream), and dX into view gx unless gx is None, through
         the adjoint of the activation whose output is `act` (the
         convolution's own input) when act is not None. x: the input view,
         or (low, skip) for a decoder convolution that read its upsampled
-        input directly."""
+        input directly. up = (below, low): the upsampled channels' gradient
+        goes, through the upsampling adjoint and the adjoint of the
+        activation whose output is `low`, to the half-resolution view
+        `below` instead of gx (whose first low.c channels are left undefined)."""
         cv = self.convs[k]
         lib = self.lib
         n = self._shape[0]
@@ -366,11 +372,18 @@ class UNet:
             if self._flip_pending:  # the flipped weights, from the side stream
                 _torch().cuda.default_stream().wait_event(self._flip_done)
                 self._flip_pending = False
-            _check(lib.sur_conv3x3_backward_data_flipped(
-                dz.ptr, dz.pitch, n, hh, ww, cv.cout, _ptr(self.flipped, cv.f_off), cv.cin,
-                gx.ptr, gx.pitch, None if act is None else act.ptr,
-                0 if act is None else act.pitch, self.slope, None),
-                "sur_conv3x3_backward_data_flipped")
+            if up is not None:
+                below, lo = up
+                _check(lib.sur_conv3x3_backward_data_up(
+                    dz.ptr, dz.pitch, n, hh, ww, cv.cout, _ptr(self.flipped, cv.f_off), cv.cin,
+                    lo.c, gx.ptr, gx.pitch, below.ptr, below.pitch, lo.ptr, lo.pitch,
+                    self.slope, None), "sur_conv3x3_backward_data_up")
+            else:
+                _check(lib.sur_conv3x3_backward_data_flipped(
+                    dz.ptr, dz.pitch, n, hh, ww, cv.cout, _ptr(self.flipped, cv.f_off), cv.cin,
+                    gx.ptr, gx.pitch, None if act is None else act.ptr,
+                    0 if act is None else act.pitch, self.slope, None),
+                    "sur_conv3x3_backward_data_flipped")
         if self.record is not None:
             _torch().cuda.default_stream().wait_stream(self._side)  # dW, db written
             self.record.append({
@@ -416,16 +429,21 @@ class UNet:
             low = self._low_view(l)
             x = ((low, self.e_view(l)) if self._fused_up[l]
                  else _View(self.cat[l], 0, ch[l + 1] + ch[l]))
-            self._conv_backward(k_first, x, g_b, _View(self.g_cat[l], 0, ch[l + 1] + ch[l]),
-                                None, l)
             # the upsampled part's gradient -> the pre-activation gradient of
             # the level below's output
             below = (_View(self.g_l[l + 1], 0, ch[l + 1]) if l + 1 < L - 1
                      else _View(self.g_e_last, 0, ch[L - 1]))
-            hh, ww = self.dims[l + 1]
-            _check(lib.sur_up2_backward_act(_ptr(self.g_cat[l]), self.g_cat[l].shape[-1], n, hh,
-                                            ww, ch[l + 1], below.ptr, below.pitch, low.ptr,
-                                            low.pitch, self.slope, None), "sur_up2_backward_act")
+            g_cat = _View(self.g_cat[l], 0, ch[l + 1] + ch[l])
+            # (a recording pass keeps the full-resolution gradient for its checks)
+            if self.fuse_up_bwd and self.record is None:
+                self._conv_backward(k_first, x, g_b, g_cat, None, l, up=(below, low))
+            else:
+                self._conv_backward(k_first, x, g_b, g_cat, None, l)
+                hh, ww = self.dims[l + 1]
+                _check(lib.sur_up2_backward_act(
+                    _ptr(self.g_cat[l]), self.g_cat[l].shape[-1], n, hh, ww, ch[l + 1],
+                    below.ptr, below.pitch, low.ptr, low.pitch, self.slope, None),
+                    "sur_up2_backward_act")
         # encoder, from the bottleneck up
         for l in range(L - 1, -1, -1):
             k1 = 2 * l

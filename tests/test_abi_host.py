@@ -297,6 +297,25 @@ def test_surrogate_header_exports_and_host_checks(lib):
     assert bdf(a, 16, 1, 8, 8, 16, b, 8, c, 8, d, 8, float("nan"), None) == binding.E_ARG
     assert bdf(a, 16, 1, 8, 8, 16, vp(b.value + 2), 8, c, 8, None, 0, 0.1, None) == binding.E_ARG
     assert bdf(a, 16, 1, 8192, 8192, 16, b, 8, c, 8, None, 0, 0.1, None) == binding.E_ARG
+    # backward data with the upsampling adjoint: cu a multiple of 16 up to
+    # cin, even sizes, aligned half-resolution views, a finite slope
+    bdu = lib.sur_conv3x3_backward_data_up
+    e = vp(0x500000000)
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 0, c, 48, d, 32, e, 32, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 24, c, 48, d, 24, e, 24, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 64, c, 48, d, 64, e, 64, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 9, 32, 16, b, 48, 32, c, 48, d, 32, e, 32, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 31, 16, b, 48, 32, c, 48, d, 32, e, 32, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 32, c, 48, None, 32, e, 32, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 32, c, 48, d, 16, e, 32, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 32, c, 48, vp(d.value + 2), 32, e, 32, 0.1,
+               None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 32, c, 48, d, 32, vp(e.value + 2), 32, 0.1,
+               None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 32, c, 48, d, 32, e, 32, float("inf"),
+               None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, vp(b.value + 2), 48, 32, c, 48, d, 32, e, 32, 0.1,
+               None) == binding.E_ARG
     # the pooling and upsampling adjoints through an activation need one
     assert lib.sur_pool2_backward_act(a, 16, 1, 8, 8, 16, b, 16, 1, None, 16, 0.1,
                                       None) == binding.E_ARG

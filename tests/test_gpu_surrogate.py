@@ -344,6 +344,79 @@ def test_pool_up_backward_through_activation():
                 2 * u + u * u, "upsampling adjoint through the activation")
 
 
+@pytest.mark.parametrize("n,h,w,cout,cin,cu,act,du_pad", [
+    (2, 16, 64, 32, 96, 64, True, 0),    # 64-channel groups: one upsampled, one skip
+    (1, 18, 40, 24, 48, 32, True, 16),   # a group split between the two; du a wider buffer
+    (3, 8, 32, 16, 32, 16, False, 0),    # 32-channel groups, no activation
+    (2, 24, 96, 64, 192, 128, True, 0),  # two upsampled groups, ragged tiles
+    (1, 8, 32, 16, 32, 32, True, 0),     # every channel upsampled: dx untouched
+    (1, 6, 16, 16, 48, 16, True, 0),     # too small for halo tiles: the two passes
+])
+def test_conv_backward_data_up_equals_two_passes(n, h, w, cout, cin, cu, act, du_pad):
+    """sur_conv3x3_backward_data_up: dx's channels [cu, cin) and the
+    half-resolution gradient du bit for bit those of
+    sur_conv3x3_backward_data_flipped followed by sur_up2_backward_act (or
+    sur_up2_backward); on halo tiles dx's first cu channels are not written
+    (smaller images run the two passes, which write them)."""
+    slope = 0.1
+    L = lib()
+    dz, _ = bf16_array((n, h, w, cout))
+    wt, _ = bf16_array((cout, 9, cin), scale=0.05)
+    a, _ = bf16_array((n, h // 2, w // 2, cu))
+    vp = ctypes.c_void_p
+    one = ctypes.c_int * 1
+    flipped = torch.empty((cin, 9, cout), dtype=BF, device="cuda")
+    assert L.sur_flip_weights(1, (vp * 1)(p(wt)), one(cout), one(cin), (vp * 1)(p(flipped)),
+                              None) == binding.OK
+    full = torch.empty((n, h, w, cin), dtype=BF, device="cuda")
+    assert L.sur_conv3x3_backward_data_flipped(p(dz), cout, n, h, w, cout, p(flipped), cin,
+                                               p(full), cin, None, 0, 0.0, None) == binding.OK
+    ref = torch.empty((n, h // 2, w // 2, cu), dtype=BF, device="cuda")
+    if act:
+        assert L.sur_up2_backward_act(p(full), cin, n, h // 2, w // 2, cu, p(ref), cu, p(a), cu,
+                                      slope, None) == binding.OK
+    else:
+        assert L.sur_up2_backward(p(full), cin, n, h // 2, w // 2, cu, p(ref), cu,
+                                  None) == binding.OK
+    dx = torch.full((n, h, w, cin), 12345.0, dtype=BF, device="cuda")
+    sentinel = dx[..., :cu].clone()
+    du_buf = torch.full((n, h // 2, w // 2, cu + du_pad), -7.0, dtype=BF, device="cuda")
+    du_off = du_pad // 2 // 8 * 8
+    assert L.sur_conv3x3_backward_data_up(
+        p(dz), cout, n, h, w, cout, p(flipped), cin, cu, p(dx), cin, p(du_buf, du_off),
+        cu + du_pad, p(a) if act else None, cu, slope, None) == binding.OK
+    torch.cuda.synchronize()
+    assert torch.equal(dx[..., cu:], full[..., cu:])
+    if h >= 8 and w >= 32:
+        assert torch.equal(dx[..., :cu], sentinel)
+    assert torch.equal(du_buf[..., du_off:du_off + cu], ref)
+    rest = torch.cat([du_buf[..., :du_off], du_buf[..., du_off + cu:]], dim=-1)
+    assert bool((rest == -7.0).all())
+
+
+def test_network_fused_upsampling_adjoint_is_bitwise():
+    """The decoders' upsampling adjoints inside the backward-data passes (the
+    default) give the network's parameter gradients bit for bit as the
+    separate passes, on 64 x 64 images (every decoder level on halo tiles)
+    and 32 x 32 (the lower level too small for them: two passes)."""
+    net = _small_net()
+    for n, h, w in ((2, 64, 64), (2, 32, 32)):
+        net._buffers(n, h, w)
+        x = torch.tensor(RNG.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF)
+        g = torch.tensor(RNG.normal(size=(n, h, w, 16)), dtype=torch.float32).to(BF)
+        grads = []
+        for fuse in (True, False):
+            net.fuse_up_bwd = fuse
+            net.x0.copy_(x)
+            net.dout.copy_(g)
+            net.grad.fill_(12345.0)  # padding between blocks keeps it in both
+            net.forward_packed()
+            net.backward_packed()
+            grads.append(net.grad.clone())
+        torch.cuda.synchronize()
+        assert torch.equal(grads[0], grads[1]), (n, h, w)
+
+
 def test_network_gradients_with_overlapped_split_sums_are_bitwise():
     """The weight gradients' split sums on a second stream (the default) give
     the network's parameter gradients bit for bit as on one stream, over two
