@@ -104,23 +104,35 @@ def test_adjoint_run_matches_oracle(orc, bc, nsteps, every):
     assert gerr <= GRAD_TOL["f64"]
 
 
-@pytest.mark.parametrize("every", [10, 2, 3, 8])
-def test_checkpoints_are_the_states(every):
+CHECKPOINT_CASES = (
+    [("f32", "periodic", 96, 80, 0.0, e) for e in (10, 2, 3, 8)]
+    + [(d, bc, nx, ny, dd, e)
+       for d in ("f32", "f64") for bc in ("periodic", "noflux")
+       for nx, ny, dd in ((97, 61, 0.0), (130, 7, 0.07), (64, 90, 0.07))
+       for e in (2, 5)])
+
+
+@pytest.mark.parametrize("dtype,bc,nx,ny,d_dead,every", CHECKPOINT_CASES)
+def test_checkpoints_are_the_states(dtype, bc, nx, ny, d_dead, every):
     """run_checkpointed ends where run ends, and checkpoint k is the state
-    after k * every steps, bit for bit (copies between runs for long
+    after k * every steps, bit for bit: copies between runs for long
     intervals; one pass per segment written into the next checkpoint for
-    intervals up to the deepest pass, with a ragged last segment)."""
-    p = inputs.c1_params()
-    rho0 = inputs.random_state(96, 80, seed=5)
-    s = Solver(96, 80, p, dtype="f32")
-    a = to_gpu(rho0, "f32")
+    intervals up to the deepest pass, with a ragged last segment; at an
+    interval of 2, four-step passes that also write the state after two
+    steps. Both types and walls, an odd width (one column per lane), a grid
+    shorter than a chunk, and a diffusing D compartment."""
+    p = inputs.c1_params() if d_dead == 0.0 else rough_params(d_dead)
+    print(f"checkpoints {dtype} {bc} {nx}x{ny} dD={d_dead} every={every}", flush=True)
+    rho0 = inputs.random_state(nx, ny, seed=5)
+    s = Solver(nx, ny, p, dtype=dtype, bc=bc)
+    a = to_gpu(rho0, dtype)
     cps = s.run_checkpointed(a, 53, every)
-    b = to_gpu(rho0, "f32")
+    b = to_gpu(rho0, dtype)
     s.run(b, 53)
     assert torch.equal(a, b)
     assert cps.shape[0] == (53 + every - 1) // every
     for k in range(cps.shape[0]):
-        c = to_gpu(rho0, "f32")
+        c = to_gpu(rho0, dtype)
         s.run(c, every * k)
         assert torch.equal(cps[k], c), k
 
