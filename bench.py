@@ -18,7 +18,8 @@ Prints one JSON line (rank 0, N = 1 only):
                             and the measured 1 GiB copy rate as the practical
                             ceiling
   steady_state              the headline run over 120 steps (passes of the
-                            deepest blocking, as long runs take them)
+                            deepest blocking, as long runs take them), the
+                            median of three timed runs
   cpu_baseline              the FP64 CPU oracle on a bounded sample of the same
                             workload, on the host cores
 """
@@ -129,11 +130,13 @@ def march_kernel(dtype, k, cols_per_lane):
     return f"sslbm_march_kernel<{t}, {k}, false, {cols_per_lane}>"
 
 
-def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK, depth=0):
+def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK, depth=0,
+                repeats=1):
     """One scheme / type / R0 on the 4096 x 4096 workload: `warmup` untimed
     steps, then one untimed run of exactly the timed pass plan (so that every
     kernel the timed region launches has run before), then `steps` steps
-    timed with HIP events on the launch stream. depth > 0 fixes the SSLBM's
+    timed with HIP events on the launch stream (`repeats` times, the median
+    reported, the others under `ms_runs`). depth > 0 fixes the SSLBM's
     steps per pass (0: automatic)."""
     params = inputs.c2_params(r0)
     rho0 = inputs.c2_state(NX, NY)
@@ -165,13 +168,16 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK, de
         solver.run(f, rd, warmup, fs, ds)
         timed()
         launches = steps
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    timed()
-    stop.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
+    runs = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        timed()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        runs.append(start.elapsed_time(stop))
+    ms = sorted(runs)[len(runs) // 2]
     cells = NX * NY
     glups = cells * steps / (ms * 1e-3) / 1e9
     per_step = SSLBM_BYTES[dtype] if scheme == "sslbm" else BGK_BYTES[dtype]
@@ -179,6 +185,7 @@ def run_variant(torch, scheme, dtype, r0, steps, warmup, inputs, Solver, BGK, de
     bytes_per_launch = per_step * cells
     out = {
         "scheme": scheme, "dtype": dtype, "R0": r0, "steps": steps, "ms": ms,
+        "ms_runs": [round(v, 5) for v in runs],
         "ms_per_step": ms / steps, "glups": glups,
         "steps_per_pass": shape["steps_per_pass"], "launch": shape, "plan": plan,
         "launches": launches, "avg_launch_ms": ms / launches,
@@ -629,9 +636,10 @@ def main():
     steady = None
     if head["scheme"] == "sslbm" and head["dtype"] == "f32":
         sr = run_variant(torch, "sslbm", "f32", head["R0"], STEADY_STEPS, args.warmup, inputs,
-                         Solver, BGK)
+                         Solver, BGK, repeats=3)
         kk = sr["plan"]["longest"]
-        steady = {"steps": STEADY_STEPS, "glups": round(sr["glups"], 2),
+        steady = {"steps": STEADY_STEPS, "repeats": 3, "glups": round(sr["glups"], 2),
+                  "ms_runs": [round(v, 4) for v in sr["ms_runs"]],
                   "ms_per_step": round(sr["ms_per_step"], 5), "plan": sr["plan"],
                   "kernel": march_kernel("f32", kk, sr["launch"].get("cols_per_lane", 1)),
                   "avg_launch_ms": round(sr["avg_launch_ms"], 5),
