@@ -279,7 +279,17 @@ sslbm_status sslbm_adjoint_run(sslbm_ctx *c, const void *checkpoints, long long 
         auto state = [&](long long i) -> const void * {
             return i == 0 ? (const void *)cp : (const void *)(ws + (size_t)(i / 2 - 1) * bytes);
         };
-        for (long long i = 2; i < len; i += 2) {
+        // every second state of the segment from its checkpoint: four-step
+        // passes that also write the state after two steps (the bits of two
+        // two-step passes), one two-step pass for an odd count
+        long long i = 2;
+        for (; i + 2 < len; i += 4) {
+            st = sslbm::run_pass_mid2(c, state(i - 2), ws + (size_t)(i / 2 - 1) * bytes,
+                                      ws + (size_t)(i / 2) * bytes, s);
+            if (st != SSLBM_OK)
+                return st;
+        }
+        for (; i < len; i += 2) {
             st = sslbm::run_pass(c, state(i - 2), ws + (size_t)(i / 2 - 1) * bytes, 2, s);
             if (st != SSLBM_OK)
                 return st;
