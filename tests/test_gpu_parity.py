@@ -79,6 +79,42 @@ def test_diffusing_deceased(orc, dtype, bc):
     assert max_rel_l2(to_np(rho), orc.sslbm_run(rho0, p, 20, bc=bc)) <= TOL[dtype]
 
 
+# Degenerate parameter sets of the method, with dx = 1 and dt = 1/4 so that
+# a diffusivity of 1 is d_lu = 1/4 exactly (the largest the step accepts: the
+# centre weight 1 - 4 d_lu vanishes and the checkerboard mode has G = -1).
+DEGENERATE = {
+    "stability_limit": dict(beta=0.4, alpha=0.3, gamma=0.2, phi=0.1,
+                            d=(1.0, 0.6, 0.6, 1.0, 1.0)),
+    "no_diffusion": dict(beta=0.9, alpha=0.5, gamma=0.3, phi=0.2, d=(0.0,) * 5),
+    "no_reactions": dict(beta=0.0, alpha=0.0, gamma=0.0, phi=0.0,
+                         d=(0.2, 0.4, 0.6, 0.8, 0.3)),
+    "all_removed_die": dict(beta=0.6, alpha=0.4, gamma=0.5, phi=1.0,
+                            d=(0.3, 0.2, 0.1, 0.2, 0.0)),
+    "none_die": dict(beta=0.6, alpha=0.4, gamma=0.5, phi=0.0,
+                     d=(0.3, 0.2, 0.1, 0.2, 0.0)),
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("case", sorted(DEGENERATE))
+def test_degenerate_parameters(orc, case, bc, dtype):
+    """The diffusivity at the stability limit, no diffusion (the per-cell
+    ODE by forward Euler), no reactions (pure diffusion), and the two ends
+    of the death fraction: blocked runs and single steps against the
+    oracle."""
+    p = inputs.Params(dx=1.0, dt=0.25, **DEGENERATE[case])
+    rho0 = inputs.random_state(70, 45, seed=len(case))
+    s = Solver(70, 45, p, dtype=dtype, bc=bc)
+    one = to_np(s.step(to_gpu(rho0, dtype)))
+    assert max_rel_l2(one, orc.sslbm_step(rho0, p, bc=bc)) <= TOL[dtype]
+    rho = to_gpu(rho0, dtype)
+    s.run(rho, 30)
+    got = to_np(rho)
+    assert np.all(np.isfinite(got))
+    assert max_rel_l2(got, orc.sslbm_run(rho0, p, 30, bc=bc)) <= TOL[dtype]
+
+
 def _reference_steps(s, rho0, n):
     ref_t = rho0.clone()
     tmp = torch.empty_like(ref_t)
