@@ -282,6 +282,30 @@ def test_bgk_against_oracle(orc, nx, ny, bc, dtype):
     assert max_rel_l2(got, orc.bgk_run_density(rho0, p, 15, bc=bc)) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["periodic", "noflux"])
+@pytest.mark.parametrize("case", ["stability_limit", "no_diffusion", "no_reactions",
+                                  "all_removed_die"])
+def test_bgk_degenerate_parameters(orc, case, bc, dtype):
+    """BGK on the degenerate sets (D not diffusing, which BGK requires): at
+    d_lu = 1/4 tau = 5/4; with no diffusion 1 / tau = 2, the edge of
+    over-relaxation. One step and a 16-step run against the oracle."""
+    kw = dict(DEGENERATE[case])
+    kw["d"] = tuple(kw["d"][:4]) + (0.0,)
+    p = inputs.Params(dx=1.0, dt=0.25, **kw)
+    rho0 = inputs.random_state(46, 31, seed=7 + len(case))
+    b = BGK(46, 31, p, dtype=dtype, bc=bc)
+    f, rd = b.init(to_gpu(rho0, dtype))
+    fo, do = orc.bgk_init(rho0)
+    f1, _ = b.step(f, rd)
+    fo1, _ = orc.bgk_step(fo, do, p, bc=bc)
+    assert max_rel_l2(to_np(f1).reshape(20, 31, 46), fo1.reshape(20, 31, 46)) <= TOL[dtype]
+    b.run(f, rd, 16)
+    got = to_np(b.density(f, rd))
+    assert np.all(np.isfinite(got))
+    assert max_rel_l2(got, orc.bgk_run_density(rho0, p, 16, bc=bc)) <= TOL[dtype]
+
+
 def test_bgk_c1_1000_steps(orc):
     w = inputs.c1_workload()
     b = BGK(w.nx, w.ny, w.params, dtype="f64")
