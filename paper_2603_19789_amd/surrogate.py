@@ -179,7 +179,8 @@ class UNet:
         return list(zip(self.convs, lv))
 
     # ------------------------------------------------------------ buffers --
-    _BUFFER_NAMES = ("x0", "a", "pool", "cat", "e_last", "b", "hdec", "out", "g_cat", "g_l",
+    _BUFFER_NAMES = ("x0", "a", "pool", "cat", "e_dense", "e_last", "b", "hdec", "out", "g_cat",
+                     "g_l",
                      "g_l2", "g_pool", "g_e_last", "dout", "wgrad_ws", "dims")
     # The backward pass runs the sums of each weight gradient's splits on a
     # second stream (default priority), overlapped with the rest of the
@@ -210,6 +211,11 @@ class UNet:
         self.a = [mk(l, ch[l]) for l in range(L)]
         self.pool = [None] + [mk(l, ch[l - 1]) for l in range(1, L)]
         self.cat = [mk(l, ch[l + 1] + ch[l]) for l in range(L - 1)]
+        # e_l on its own, for the levels whose decoder reads the upsampled
+        # tensor directly: a channel slice of cat_l shares every pixel's
+        # cache lines with the upsampled channels, which that decoder never
+        # reads, so reading and writing the slice moves about twice its bytes
+        self.e_dense = [mk(l, ch[l]) for l in range(L - 1)]
         self.e_last = mk(L - 1, ch[L - 1])
         self.b = [mk(l, ch[l]) for l in range(L - 1)]
         self.hdec = [mk(l, ch[l]) for l in range(L - 1)]
@@ -227,10 +233,21 @@ class UNet:
         self._sets[(n, h, w)] = tuple(getattr(self, name) for name in self._BUFFER_NAMES)
 
     def e_view(self, l):
-        """View of encoder output e_l (inside cat_l, or its own buffer)."""
+        """View of encoder output e_l: its own buffer at the bottleneck and
+        where the decoder reads the upsampled tensor directly (this pass),
+        else inside cat_l next to the upsampled copy."""
         if l == self.levels - 1:
             return _View(self.e_last, 0, self.ch[l])
+        if self._fused_up is not None and self._fused_up[l]:
+            return _View(self.e_dense[l], 0, self.ch[l])
         return _View(self.cat[l], self.ch[l + 1], self.ch[l])
+
+    def _up_fits(self, l):
+        """Decoder level l can read its upsampled input directly (the image
+        holds halo tiles and the upsampled channels come in 32-channel
+        chunks)."""
+        hh, ww = self.dims[l]
+        return hh >= 8 and ww >= 32 and self.ch[l + 1] % 32 == 0
 
     # ------------------------------------------------------------ forward --
     def _conv(self, k, src: _View, dst, l, f32=False, pooled=None):
@@ -260,7 +277,7 @@ class UNet:
         cv = self.convs[k]
         n = self._shape[0]
         hh, ww = self.dims[l]
-        if hh < 8 or ww < 32 or low.c % 32:
+        if not self._up_fits(l) or low.c != self.ch[l + 1]:
             return False
         flags = LEAKY if cv.act else 0
         _check(self.lib.sur_conv3x3_forward_up(
@@ -285,7 +302,9 @@ class UNet:
         upsampled copy; the backward pass reads the same views)."""
         L, ch, lib = self.levels, self.ch, self.lib
         n = self._shape[0]
-        self._fused_up = [False] * max(L - 1, 0)
+        # decided before the encoder runs: it writes e_l where the decoder
+        # will read it
+        self._fused_up = [fuse_up and self._up_fits(l) for l in range(max(L - 1, 0))]
         k = 0
         for l in range(L):
             src = _View(self.x0, 0, IN_CHANNELS) if l == 0 else _View(self.pool[l], 0, ch[l - 1])
@@ -298,8 +317,10 @@ class UNet:
             hh, ww = self.dims[l + 1]
             low = self._low_view(l)
             dst = _View(self.b[l], 0, ch[l])
-            self._fused_up[l] = fuse_up and self._conv_up(k, low, self.e_view(l), dst, l)
-            if not self._fused_up[l]:
+            if self._fused_up[l]:
+                if not self._conv_up(k, low, self.e_view(l), dst, l):
+                    raise RuntimeError("decoder level cannot read its upsampled input directly")
+            else:
                 _check(lib.sur_up2(low.ptr, low.pitch, n, hh, ww, ch[l + 1],
                                    _ptr(self.cat[l]), self.cat[l].shape[-1], None), "sur_up2")
                 self._conv(k, _View(self.cat[l], 0, ch[l + 1] + ch[l]), dst, l)
