@@ -100,18 +100,18 @@ sslbm_status sur_conv3x3_backward_data_flipped(const void *dz, int dz_pitch, int
 
 /* The backward-data pass of a decoder's first convolution, whose first cu
  * input channels were the 2x nearest upsampling of a half-resolution
- * tensor u (the upsampled-input convolution sur_conv3x3_forward_up):
- * sur_conv3x3_backward_data_flipped into dx for channels [cu, cin) (dx's
- * channels [0, cu) are undefined afterwards), and the gradient of u into du
- * (n, h/2, w/2, cu channels): each 2x2 window of the upsampled channels'
- * BF16-rounded gradient summed, rounded to BF16 and, when du_act is not
- * NULL, passed through the leaky activation's adjoint with du_act (a BF16
- * view of cu channels at du's pixels, the activation's output). Bit for
- * bit sur_conv3x3_backward_data_flipped into dx followed by
- * sur_up2_backward_act (or sur_up2_backward) from dx's first cu channels
- * into du, in one pass on images of at least 8 x 32 pixels and as those
- * two passes on smaller ones. cu: a multiple of 16, at most cin; h and w
- * even. du may not overlap dz, dx or du_act. */
+ * tensor u (the upsampled-input convolution sur_conv3x3_forward_up), in one
+ * pass. dx, a view of cin - cu channels, receives the gradient of input
+ * channels [cu, cin) (channel c at dx's channel c - cu). du (n, h/2, w/2, cu
+ * channels) receives the gradient of u: each 2x2 window of the upsampled
+ * channels' BF16-rounded gradient summed, rounded to BF16 and, when du_act
+ * is not NULL, passed through the leaky activation's adjoint with du_act (a
+ * BF16 view of cu channels at du's pixels, the activation's output). Bit
+ * for bit sur_conv3x3_backward_data_flipped into a cin-channel buffer,
+ * followed by sur_up2_backward_act (or sur_up2_backward) from its first cu
+ * channels into du. cu: a multiple of 16, below cin; h and w even. Images
+ * under 8 x 32 pixels return SSLBM_E_UNSUPPORTED (run the two calls above
+ * instead). dx and du may not overlap dz, each other or du_act. */
 sslbm_status sur_conv3x3_backward_data_up(const void *dz, int dz_pitch, int n, int h, int w,
                                           int cout, const void *flipped, int cin, int cu,
                                           void *dx, int dx_pitch, void *du, int du_pitch,

@@ -240,8 +240,9 @@ sslbm_status sur_conv3x3_backward_data_up(const void *dz, int dz_pitch, int n, i
                                           void *dx, int dx_pitch, void *du, int du_pitch,
                                           const void *du_act, int du_act_pitch, float slope,
                                           void *hip_stream) {
-    if (!backward_data_args_ok(dz, dz_pitch, n, h, w, cout, flipped, cin, dx, dx_pitch) ||
-        !aligned16(flipped) || cu <= 0 || cu % 16 || cu > cin || h % 2 || w % 2 ||
+    if (!view_ok(dz, dz_pitch, cout) || !dims_ok(n, h, w) || !flipped || !aligned16(flipped) ||
+        !conv_input_fits(dz_pitch, n, h, w, cout) || cin <= 0 || cin > MAX_CHANNELS ||
+        cu <= 0 || cu % 16 || cu >= cin || h % 2 || w % 2 || !view_ok(dx, dx_pitch, cin - cu) ||
         !view_ok(du, du_pitch, cu) || !act_ok(du_act, du_act_pitch, cu, slope) ||
         (du_act && !conv_input_fits(du_act_pitch, n, h / 2, w / 2, cu)) ||
         !conv_input_fits(du_pitch, n, h / 2, w / 2, cu))
@@ -269,16 +270,10 @@ sslbm_status sur_conv3x3_backward_data_up(const void *dz, int dz_pitch, int n, i
     a.cd = cu;
     a.du_mask = du_act;
     a.du_mask_pitch = du_act ? du_act_pitch : 0;
+    // images too small for halo tiles (or views too large for their 32-bit
+    // offsets) are the caller's to run as the two separate passes
     const hipError_t e = sslbm::launch_conv_fwd(a, false, false, s);
-    if (e != hipErrorNotSupported)
-        return status(e);
-    // images too small for halo tiles: the two passes
-    sslbm_status st =
-        backward_data(dz, dz_pitch, n, h, w, cout, flipped, cin, dx, dx_pitch, nullptr, 0, 0.f, s);
-    if (st != SSLBM_OK)
-        return st;
-    return status(sslbm::launch_up2_bwd(dx, dx_pitch, n, h / 2, w / 2, cu, du, du_pitch, du_act,
-                                        du_act ? du_act_pitch : 0, slope, s));
+    return e == hipErrorNotSupported ? SSLBM_E_UNSUPPORTED : status(e);
 }
 
 size_t sur_conv3x3_backward_weight_workspace(int n, int h, int w, int cin, int cout) {

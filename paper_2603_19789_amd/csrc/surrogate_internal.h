@@ -37,12 +37,13 @@ struct ConvArgs {
     const void *mask = nullptr;
     int mask_pitch = 0;
     // Adjoint of a 2x nearest upsampling in the epilogue (backward-data of a
-    // decoder's first convolution): output channels [0, cd) are not stored
-    // in y; the sum of each 2 x 2 window of their BF16-rounded values,
-    // rounded to BF16 and passed through the activation adjoint with du_mask
-    // (a BF16 NHWC view at du's pixels; null: none), goes to du, a BF16 NHWC
-    // view (n, h/2, w/2) of cd channels. cd is a multiple of 16; h and w are
-    // even. Null du: none.
+    // decoder's first convolution): y is a view of cout - cd channels that
+    // receives output channels [cd, cout) (channel c at column c - cd).
+    // Channels [0, cd) go elsewhere: the sum of each 2 x 2 window of their
+    // BF16-rounded values, rounded to BF16 and passed through the activation
+    // adjoint with du_mask (a BF16 NHWC view at du's pixels; null: none), to
+    // du, a BF16 NHWC view (n, h/2, w/2) of cd channels. cd is a multiple of
+    // 16; h and w are even. Null du: none.
     void *du = nullptr;
     int du_pitch = 0, cd = 0;
     const void *du_mask = nullptr;

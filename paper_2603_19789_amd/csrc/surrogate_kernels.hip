@@ -306,7 +306,8 @@ constexpr int HALO_TH = 8, HALO_TW = 32;
 // roundings of a separate sur_leaky_backward over the stored values.
 // UPB (BF16 output; the backward-data pass of a decoder's first convolution,
 // whose first a.cd input channels were a 2x upsampling): output channels
-// below a.cd are kept in registers instead of stored; each 2 x 2 window of
+// from a.cd on go to y, a view of a.cout - a.cd channels (channel c at
+// column c - a.cd); those below a.cd are kept in registers; each 2 x 2 window of
 // their BF16-rounded values (all in one lane, as for POOL) is summed in the
 // order of the separate upsampling adjoint, rounded, passed through the
 // activation adjoint with a.du_mask when given, and written to the
@@ -500,8 +501,10 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
     // pixels past the image's right edge and channels past the layer's get
     // an offset past the range, and the hardware drops those stores.
     constexpr int ESZ = F32OUT ? 4 : 2;
+    // UPB: y holds only the channels from a.cd on (channel c at column c - cd)
+    const int yc0 = UPB ? a.cd : 0;
     const __amdgpu_buffer_rsrc_t yr_ = __builtin_amdgcn_make_buffer_rsrc(
-        a.y, (short)0, (int)(((P - 1) * a.y_pitch + a.cout) * ESZ), BUF_FORMAT_WORD);
+        a.y, (short)0, (int)(((P - 1) * a.y_pitch + a.cout - yc0) * ESZ), BUF_FORMAT_WORD);
     const unsigned ypb = (unsigned)(a.y_pitch * ESZ);  // bytes per pixel
     const int hp = a.h / 2, wp = a.w / 2;
     const __amdgpu_buffer_rsrc_t pr = __builtin_amdgcn_make_buffer_rsrc(
@@ -557,7 +560,7 @@ void conv_halo_kernel(ConvArgs a, int tiles_x, int tiles_y, int units) {
                 }
                 const unsigned lane_off =
                     (unsigned)((((long long)n * a.h + yr + r) * a.w + x0) * ypb) +
-                    (unsigned)(4 * g) * ypb + (unsigned)(c * ESZ);
+                    (unsigned)(4 * g) * ypb + (unsigned)((c - yc0) * ESZ);
 #pragma unroll
                 for (int ms = 2 * r; ms < 2 * r + 2; ++ms)
 #pragma unroll

@@ -180,7 +180,7 @@ class UNet:
 
     # ------------------------------------------------------------ buffers --
     _BUFFER_NAMES = ("x0", "a", "pool", "cat", "e_dense", "e_last", "b", "hdec", "out", "g_cat",
-                     "g_l",
+                     "g_e_dense", "g_l",
                      "g_l2", "g_pool", "g_e_last", "dout", "wgrad_ws", "dims")
     # The backward pass runs the sums of each weight gradient's splits on a
     # second stream (default priority), overlapped with the rest of the
@@ -222,6 +222,9 @@ class UNet:
         self.out = torch.empty((n, h, w, OUT_CHANNELS), dtype=torch.float32, device="cuda")
         # gradients
         self.g_cat = [mk(l, ch[l + 1] + ch[l]) for l in range(L - 1)]
+        # the gradient of e_l on its own where the upsampling adjoint runs
+        # inside the backward-data pass (as e_dense, for the same reason)
+        self.g_e_dense = [mk(l, ch[l]) for l in range(L - 1)]
         self.g_l = [mk(l, ch[l]) for l in range(L)]      # gradient of a level's C_l tensors
         self.g_l2 = [mk(l, ch[l]) for l in range(L)]
         self.g_pool = [None] + [mk(l, ch[l - 1]) for l in range(1, L)]
@@ -374,7 +377,7 @@ class UNet:
         input directly. up = (below, low): the upsampled channels' gradient
         goes, through the upsampling adjoint and the adjoint of the
         activation whose output is `low`, to the half-resolution view
-        `below` instead of gx (whose first low.c channels are left undefined)."""
+        `below`, and gx is a view of the remaining (skip) channels only."""
         cv = self.convs[k]
         lib = self.lib
         n = self._shape[0]
@@ -435,6 +438,7 @@ class UNet:
         self._flip_weights()
         self._flip_done.record(self._side)
         self._flip_pending = True  # the first backward-data waits for it
+        self._bwd_fused = [False] * max(L - 1, 0)
         k = len(self.convs) - 1
         # output layer (no activation: dZ = dout); its input is the last
         # activation's output
@@ -455,9 +459,13 @@ class UNet:
             below = (_View(self.g_l[l + 1], 0, ch[l + 1]) if l + 1 < L - 1
                      else _View(self.g_e_last, 0, ch[L - 1]))
             g_cat = _View(self.g_cat[l], 0, ch[l + 1] + ch[l])
+            # where the forward read the upsampled tensor directly, one pass
+            # gives the skip gradient (on its own) and the half-resolution one
             # (a recording pass keeps the full-resolution gradient for its checks)
-            if self.fuse_up_bwd and self.record is None:
-                self._conv_backward(k_first, x, g_b, g_cat, None, l, up=(below, low))
+            self._bwd_fused[l] = self.fuse_up_bwd and self._fused_up[l] and self.record is None
+            if self._bwd_fused[l]:
+                self._conv_backward(k_first, x, g_b, _View(self.g_e_dense[l], 0, ch[l]), None, l,
+                                    up=(below, low))
             else:
                 self._conv_backward(k_first, x, g_b, g_cat, None, l)
                 hh, ww = self.dims[l + 1]
@@ -472,7 +480,10 @@ class UNet:
             if l == L - 1:
                 g_e = _View(self.g_e_last, 0, ch[l])
             else:
-                g_e = _View(self.g_cat[l], ch[l + 1], ch[l])  # skip gradient already there
+                # the skip gradient is already there; the pooled path's
+                # gradient adds to it, through the activation adjoint
+                g_e = (_View(self.g_e_dense[l], 0, ch[l]) if self._bwd_fused[l]
+                       else _View(self.g_cat[l], ch[l + 1], ch[l]))
                 hh, ww = self.dims[l]
                 _check(lib.sur_pool2_backward_act(_ptr(self.g_pool[l + 1]), ch[l], n, hh, ww,
                                                   ch[l], g_e.ptr, g_e.pitch, 1, e.ptr, e.pitch,

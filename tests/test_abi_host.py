@@ -304,6 +304,8 @@ def test_surrogate_header_exports_and_host_checks(lib):
     assert bdu(a, 16, 1, 8, 32, 16, b, 48, 0, c, 48, d, 32, e, 32, 0.1, None) == binding.E_ARG
     assert bdu(a, 16, 1, 8, 32, 16, b, 48, 24, c, 48, d, 24, e, 24, 0.1, None) == binding.E_ARG
     assert bdu(a, 16, 1, 8, 32, 16, b, 48, 64, c, 48, d, 64, e, 64, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 48, c, 48, d, 48, e, 48, 0.1, None) == binding.E_ARG
+    assert bdu(a, 16, 1, 8, 32, 16, b, 48, 32, c, 8, d, 32, e, 32, 0.1, None) == binding.E_ARG
     assert bdu(a, 16, 1, 9, 32, 16, b, 48, 32, c, 48, d, 32, e, 32, 0.1, None) == binding.E_ARG
     assert bdu(a, 16, 1, 8, 31, 16, b, 48, 32, c, 48, d, 32, e, 32, 0.1, None) == binding.E_ARG
     assert bdu(a, 16, 1, 8, 32, 16, b, 48, 32, c, 48, None, 32, e, 32, 0.1, None) == binding.E_ARG

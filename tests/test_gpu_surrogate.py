@@ -344,20 +344,18 @@ def test_pool_up_backward_through_activation():
                 2 * u + u * u, "upsampling adjoint through the activation")
 
 
-@pytest.mark.parametrize("n,h,w,cout,cin,cu,act,du_pad", [
+@pytest.mark.parametrize("n,h,w,cout,cin,cu,act,pad", [
     (2, 16, 64, 32, 96, 64, True, 0),    # 64-channel groups: one upsampled, one skip
-    (1, 18, 40, 24, 48, 32, True, 16),   # a group split between the two; du a wider buffer
+    (1, 18, 40, 24, 48, 32, True, 16),   # a group split between the two; views in wider buffers
     (3, 8, 32, 16, 32, 16, False, 0),    # 32-channel groups, no activation
-    (2, 24, 96, 64, 192, 128, True, 0),  # two upsampled groups, ragged tiles
-    (1, 8, 32, 16, 32, 32, True, 0),     # every channel upsampled: dx untouched
-    (1, 6, 16, 16, 48, 16, True, 0),     # too small for halo tiles: the two passes
+    (2, 24, 96, 64, 192, 128, True, 8),  # two upsampled groups, ragged tiles
 ])
-def test_conv_backward_data_up_equals_two_passes(n, h, w, cout, cin, cu, act, du_pad):
-    """sur_conv3x3_backward_data_up: dx's channels [cu, cin) and the
+def test_conv_backward_data_up_equals_two_passes(n, h, w, cout, cin, cu, act, pad):
+    """sur_conv3x3_backward_data_up: dx (the cin - cu skip channels) and the
     half-resolution gradient du bit for bit those of
-    sur_conv3x3_backward_data_flipped followed by sur_up2_backward_act (or
-    sur_up2_backward); on halo tiles dx's first cu channels are not written
-    (smaller images run the two passes, which write them)."""
+    sur_conv3x3_backward_data_flipped into a cin-channel buffer followed by
+    sur_up2_backward_act (or sur_up2_backward) from its first cu channels;
+    nothing written outside the two views."""
     slope = 0.1
     L = lib()
     dz, _ = bf16_array((n, h, w, cout))
@@ -378,20 +376,34 @@ def test_conv_backward_data_up_equals_two_passes(n, h, w, cout, cin, cu, act, du
     else:
         assert L.sur_up2_backward(p(full), cin, n, h // 2, w // 2, cu, p(ref), cu,
                                   None) == binding.OK
-    dx = torch.full((n, h, w, cin), 12345.0, dtype=BF, device="cuda")
-    sentinel = dx[..., :cu].clone()
-    du_buf = torch.full((n, h // 2, w // 2, cu + du_pad), -7.0, dtype=BF, device="cuda")
-    du_off = du_pad // 2 // 8 * 8
+    off = pad // 2 // 8 * 8  # each view starts inside its (wider) buffer
+    dx_buf = torch.full((n, h, w, cin - cu + pad), 12345.0, dtype=BF, device="cuda")
+    du_buf = torch.full((n, h // 2, w // 2, cu + pad), -7.0, dtype=BF, device="cuda")
     assert L.sur_conv3x3_backward_data_up(
-        p(dz), cout, n, h, w, cout, p(flipped), cin, cu, p(dx), cin, p(du_buf, du_off),
-        cu + du_pad, p(a) if act else None, cu, slope, None) == binding.OK
+        p(dz), cout, n, h, w, cout, p(flipped), cin, cu, p(dx_buf, off), cin - cu + pad,
+        p(du_buf, off), cu + pad, p(a) if act else None, cu, slope, None) == binding.OK
     torch.cuda.synchronize()
-    assert torch.equal(dx[..., cu:], full[..., cu:])
-    if h >= 8 and w >= 32:
-        assert torch.equal(dx[..., :cu], sentinel)
-    assert torch.equal(du_buf[..., du_off:du_off + cu], ref)
-    rest = torch.cat([du_buf[..., :du_off], du_buf[..., du_off + cu:]], dim=-1)
-    assert bool((rest == -7.0).all())
+    assert torch.equal(dx_buf[..., off:off + cin - cu], full[..., cu:])
+    assert torch.equal(du_buf[..., off:off + cu], ref)
+    for buf, c, fill in ((dx_buf, cin - cu, 12345.0), (du_buf, cu, -7.0)):
+        rest = torch.cat([buf[..., :off], buf[..., off + c:]], dim=-1)
+        assert bool((rest == torch.tensor(fill, dtype=BF)).all())
+
+
+def test_conv_backward_data_up_leaves_small_images_to_the_caller():
+    """Images under 8 x 32 pixels are not run (SSLBM_E_UNSUPPORTED) and
+    nothing is written."""
+    n, h, w, cout, cin, cu = 1, 6, 16, 16, 48, 16
+    L = lib()
+    dz, _ = bf16_array((n, h, w, cout))
+    flipped = torch.zeros((cin, 9, cout), dtype=BF, device="cuda")
+    dx = torch.full((n, h, w, cin - cu), 3.0, dtype=BF, device="cuda")
+    du = torch.full((n, h // 2, w // 2, cu), 3.0, dtype=BF, device="cuda")
+    assert L.sur_conv3x3_backward_data_up(p(dz), cout, n, h, w, cout, p(flipped), cin, cu, p(dx),
+                                          cin - cu, p(du), cu, None, 0, 0.1,
+                                          None) == binding.E_UNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool((dx == 3.0).all()) and bool((du == 3.0).all())
 
 
 def test_network_fused_upsampling_adjoint_is_bitwise():
