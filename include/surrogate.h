@@ -8,7 +8,11 @@
  *
  * Conventions (as sslbm.h): sslbm_status codes from sslbm.h, host-side
  * validation before any HIP call, caller-owned device buffers, work enqueued
- * on hip_stream (a hipStream_t as void*, NULL = default stream).
+ * on hip_stream (a hipStream_t as void*, NULL = default stream). One
+ * difference: where an entry below says that views may not overlap, that is
+ * not checked (no SSLBM_E_ALIAS here). Views are often channel slices of
+ * one wider buffer, whose byte ranges interleave without sharing an
+ * element; overlapping views give undefined results.
  *
  * Tensors
  * -------
