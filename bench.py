@@ -22,6 +22,15 @@ Prints one JSON line (rank 0, N = 1 only):
                             median of three timed runs
   cpu_baseline              the FP64 CPU oracle on a bounded sample of the same
                             workload, on the host cores
+  fp32_drift, ensemble,     further legs, each skipped when its step count is
+  adjoint, generic,         0: FP32 against FP64 over the workload's run length;
+  surrogate, fd4            512 uneven grids by size class; the 1024^2 FP64
+                            gradient; the D2Q5 / D2Q9 compartmental models; the
+                            U-Net's training, inference and judged rollout; the
+                            finite-difference reference (off by default)
+
+--steps defaults to 10 000, the workload's run length (passes of six steps);
+--steps 20 gives the short run (four passes of five).
 """
 from __future__ import annotations
 
