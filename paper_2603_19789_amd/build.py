@@ -19,10 +19,17 @@ ARCH = "gfx950"
 
 SOURCES = ["sslbm_api.cpp", "ensemble_api.cpp", "adjoint_api.cpp", "surrogate_api.cpp",
            "model_api.cpp", "sslbm_kernels.hip", "ensemble_kernels.hip", "adjoint_kernels.hip",
-           "surrogate_kernels.hip", "model_kernels.hip", "model_kernels_f32_d2q5.hip",
-           "model_kernels_f32_d2q9.hip", "model_kernels_f64_d2q5.hip",
-           "model_kernels_f64_d2q9.hip", "bgk_kernels.hip", "reduce_kernels.hip",
-           "fd4_kernels.hip"]
+           "surrogate_kernels.hip", "model_kernels.hip", "bgk_kernels.hip",
+           "reduce_kernels.hip", "fd4_kernels.hip"]
+
+# Sources compiled more than once, one object per set of definitions: the
+# generic-model kernels per arithmetic type and lattice (four objects that
+# compile in parallel instead of one long serial unit).
+INSTANCES = [
+    ("model_kernels_inst.hip", f"model_kernels_{t}_d2q{q}",
+     [f"-DMODEL_FP64={int(t == 'f64')}", f"-DMODEL_Q={q}"])
+    for t in ("f32", "f64") for q in (5, 9)
+]
 
 # -ffp-contract=off: only the fma() calls written in the kernels fuse, so every
 # launch shape and blocking depth rounds identically.
@@ -64,11 +71,12 @@ def build(verbose: bool = False) -> Path:
     objdir = PKG / "_build"
     objdir.mkdir(exist_ok=True)
     cmds, objs = [], []
-    for name in SOURCES:
+    units = [(name, Path(name).stem, []) for name in SOURCES] + INSTANCES
+    for name, stem, defines in units:
         src = CSRC / name
-        obj = objdir / (src.stem + ".o")
-        cmds.append([hipcc(), *FLAGS, *EXTRA_FLAGS.get(name, []), "-x", "hip", f"-I{INCLUDE}",
-                     f"-I{CSRC}", "-c", str(src),
+        obj = objdir / (stem + ".o")
+        cmds.append([hipcc(), *FLAGS, *EXTRA_FLAGS.get(name, []), *defines, "-x", "hip",
+                     f"-I{INCLUDE}", f"-I{CSRC}", "-c", str(src),
                      "-o", str(obj)])
         objs.append(str(obj))
     if verbose:
