@@ -91,7 +91,11 @@ sys.exit(pytest.main(["-q", "-x", "-p", "no:cacheprovider", "{root}/tests/test_a
 
 
 def test_library_host_side_under_sanitizers(tmp_path):
-    kernels = [OBJ / f"{p.stem}.o" for p in CSRC.glob("*.hip")]
+    from paper_2603_19789_amd import build as hip_build
+    # the device-code objects of the normal build: one per kernel source,
+    # plus one per instantiation of a source compiled more than once
+    kernels = [OBJ / f"{Path(n).stem}.o" for n in hip_build.SOURCES if n.endswith(".hip")]
+    kernels += [OBJ / f"{stem}.o" for _, stem, _ in hip_build.INSTANCES]
     if not all(k.exists() for k in kernels):
         pytest.skip("kernel objects of the normal build are missing (run the build first)")
     runtimes = glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
